@@ -1,0 +1,485 @@
+/*
+ * ej_oracle.c -- plain, slow CPU oracle for EmbedJoin (Zhang & Zhang,
+ * "EmbedJoin: Efficient Edit Similarity Joins via Embeddings").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header or table with the
+ * GPU path.
+ *
+ * Everything is computed the direct way, one string and one table at a time,
+ * in the order the paper states it:
+ *   - Algorithm 1 (CGK embedding) materialises every one of the L output
+ *     symbols of the walk, then the LSH coordinates are read from it;
+ *   - Section 4 "two-level hashing": a signature u in {1..|S|+1}^m is hashed
+ *     to <u, v> mod P with 128-bit intermediates;
+ *   - Algorithm 3 (EmbedJoin) keeps one chained hash table per (seed, LSH
+ *     function), visits the strings in length order, probes, applies the
+ *     length test / eviction, inserts, and de-duplicates the pairs found in
+ *     each iteration;
+ *   - Section 3.3 (Ukkonen): threshold edit distance on the 2K+1 diagonals
+ *     with an early exit once a whole row of the band exceeds K.
+ *
+ * Randomness (the paper only says "random string" and "random hash
+ * function"): every random word is W(key, c) = Mix64(key + (c+1)*GAMMA),
+ * i.e. the (c+1)-th output of a SplitMix64 generator seeded with `key`
+ * (Steele, Lea, Flood, OOPSLA 2014).  Stream keys are W(seed, tag<<32|idx)
+ * with tag 0 = the CGK random string R of seed l (idx = l), tag 1 = LSH
+ * coordinates of table (l, j) (idx = l*z + j), tag 2 = the second-level hash
+ * vector of table (l, j).
+ *   R bit b          = bit (b mod 64) of W(key_R, b / 64)
+ *   coordinate k     = floor(W(key_POS, k) * L / 2^64)       (with replacement)
+ *   v_k              = (W(key_V, k) >> 3) mod P,   P = 2^61 - 1
+ * Symbol codes: the alphabet is the sorted set of distinct input bytes, code
+ * of the k-th smallest byte is k-1, and the padding symbol (bottom) is |S|.
+ * A sampled symbol c maps to u = c + 1, so bottom maps to |S| + 1.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EJO_P ((1ULL << 61) - 1ULL)
+#define EJO_GAMMA 0x9E3779B97F4A7C15ULL
+
+/* ---------------------------------------------------------------- RNG -- */
+
+uint64_t ejo_mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Plain sequential SplitMix64: the state advances by GAMMA per draw. */
+void ejo_splitmix64_stream(uint64_t seed, uint64_t count, uint64_t *out) {
+    uint64_t s = seed;
+    for (uint64_t i = 0; i < count; i++) {
+        s += EJO_GAMMA;
+        out[i] = ejo_mix64(s);
+    }
+}
+
+/* The c-th word (0-based) of the stream seeded with `key`.  The generator's
+ * state after c+1 draws is key + (c+1)*GAMMA (a Weyl sequence), so the word
+ * is the output function applied to that state. */
+uint64_t ejo_word(uint64_t key, uint64_t c) {
+    return ejo_mix64(key + (c + 1ULL) * EJO_GAMMA);
+}
+
+uint64_t ejo_stream_key(uint64_t seed, uint32_t tag, uint32_t idx) {
+    return ejo_word(seed, ((uint64_t)tag << 32) | (uint64_t)idx);
+}
+
+/* Draws the randomness of one run.
+ *   Rbits[l][b]  for b < L*sigma : the first L*|S| bits of R^l as 0/1 bytes
+ *   pos[l][j][k] in [0, L)        : coordinate k of LSH function f_j^l
+ *   v[l][j][k]   in [0, P)        : second-level vector of table (l, j)     */
+void ejo_draw(uint64_t seed, uint32_t r, uint32_t z, uint32_t m, uint32_t L,
+              uint32_t sigma, uint8_t *Rbits, uint32_t *pos, uint64_t *v) {
+    uint64_t nbits = (uint64_t)L * sigma;
+    for (uint32_t l = 0; l < r; l++) {
+        uint64_t key = ejo_stream_key(seed, 0, l);
+        uint64_t nwords = (nbits + 63) / 64;
+        uint64_t *words = (uint64_t *)malloc(sizeof(uint64_t) * (nwords ? nwords : 1));
+        ejo_splitmix64_stream(key, nwords, words);
+        for (uint64_t b = 0; b < nbits; b++)
+            Rbits[l * nbits + b] = (uint8_t)((words[b / 64] >> (b % 64)) & 1ULL);
+        free(words);
+    }
+    for (uint32_t l = 0; l < r; l++) {
+        for (uint32_t j = 0; j < z; j++) {
+            uint64_t kp = ejo_stream_key(seed, 1, l * z + j);
+            uint64_t kv = ejo_stream_key(seed, 2, l * z + j);
+            uint64_t *wp = (uint64_t *)malloc(sizeof(uint64_t) * m);
+            uint64_t *wv = (uint64_t *)malloc(sizeof(uint64_t) * m);
+            ejo_splitmix64_stream(kp, m, wp);
+            ejo_splitmix64_stream(kv, m, wv);
+            for (uint32_t k = 0; k < m; k++) {
+                unsigned __int128 prod = (unsigned __int128)wp[k] * (unsigned __int128)L;
+                pos[((uint64_t)l * z + j) * m + k] = (uint32_t)(prod >> 64);
+                v[((uint64_t)l * z + j) * m + k] = (wv[k] >> 3) % EJO_P;
+            }
+            free(wp);
+            free(wv);
+        }
+    }
+}
+
+/* ----------------------------------------------------------- alphabet -- */
+
+/* Sorted distinct bytes; lut[b] = code or -1.  Returns |S|. */
+int ejo_alphabet(const uint8_t *chars, uint64_t total, int32_t *lut) {
+    int present[256];
+    memset(present, 0, sizeof(present));
+    for (uint64_t i = 0; i < total; i++) present[chars[i]] = 1;
+    int sigma = 0;
+    for (int b = 0; b < 256; b++) lut[b] = present[b] ? sigma++ : -1;
+    return sigma;
+}
+
+/* ------------------------------------------------- Algorithm 1 (CGK) -- */
+
+/* Embeds x (symbol codes, length len) with random bits Rbits (0/1 bytes,
+ * pi_j(sigma_k) = Rbits[(j-1)*sigma + (k-1)] in the paper's 1-based terms)
+ * into out[0..L).  Pointer i starts at the first character; at every step
+ * the current character is emitted and i moves on iff pi_j(x[i]) = 1; once i
+ * is past the end the padding symbol `sigma` is emitted. */
+void ejo_cgk_embed(const uint8_t *x, uint32_t len, const uint8_t *Rbits,
+                   uint32_t sigma, uint32_t L, uint8_t *out) {
+    uint64_t i = 0;
+    for (uint64_t j = 0; j < L; j++) {
+        if (i < len) {
+            out[j] = x[i];
+            i += Rbits[j * sigma + x[i]];
+        } else {
+            out[j] = (uint8_t)sigma;
+        }
+    }
+}
+
+/* Section 4, two-level hashing: <u, v> mod P with u_k = t[pos_k] + 1. */
+uint64_t ejo_key(const uint8_t *t, const uint32_t *pos, const uint64_t *v, uint32_t m) {
+    unsigned __int128 acc = 0;
+    for (uint32_t k = 0; k < m; k++) {
+        uint64_t u = (uint64_t)t[pos[k]] + 1ULL;
+        acc += (unsigned __int128)u * (unsigned __int128)v[k];
+        acc %= EJO_P;
+    }
+    return (uint64_t)acc;
+}
+
+/* ------------------------------------------------ edit distance (3.3) -- */
+
+/* Textbook Wagner-Fischer, full table, two rows. */
+uint32_t ejo_ed_full(const uint8_t *x, uint32_t lx, const uint8_t *y, uint32_t ly) {
+    uint32_t *prev = (uint32_t *)malloc(sizeof(uint32_t) * (ly + 1));
+    uint32_t *cur = (uint32_t *)malloc(sizeof(uint32_t) * (ly + 1));
+    for (uint32_t j = 0; j <= ly; j++) prev[j] = j;
+    for (uint32_t i = 1; i <= lx; i++) {
+        cur[0] = i;
+        for (uint32_t j = 1; j <= ly; j++) {
+            uint32_t best = prev[j - 1] + (x[i - 1] != y[j - 1]);
+            if (prev[j] + 1 < best) best = prev[j] + 1;
+            if (cur[j - 1] + 1 < best) best = cur[j - 1] + 1;
+            cur[j] = best;
+        }
+        uint32_t *t = prev; prev = cur; cur = t;
+    }
+    uint32_t d = prev[ly];
+    free(prev);
+    free(cur);
+    return d;
+}
+
+/* Ukkonen's threshold algorithm: only cells with |i - j| <= K are filled
+ * (cells outside the band count as infinite); a row whose band cells all
+ * exceed K ends the computation.  Returns ED(x, y) if it is <= K, else K+1. */
+uint32_t ejo_ed_banded(const uint8_t *x, uint32_t lx, const uint8_t *y, uint32_t ly,
+                       uint32_t K) {
+    const uint32_t INF = 0xFFFFFFF0u;
+    uint32_t diff = lx > ly ? lx - ly : ly - lx;
+    if (diff > K) return K + 1;
+    uint32_t *prev = (uint32_t *)malloc(sizeof(uint32_t) * (ly + 1));
+    uint32_t *cur = (uint32_t *)malloc(sizeof(uint32_t) * (ly + 1));
+    for (uint32_t j = 0; j <= ly; j++) prev[j] = (j <= K) ? j : INF;
+    uint32_t result = K + 1;
+    int done = 0;
+    for (uint32_t i = 1; i <= lx && !done; i++) {
+        uint32_t jlo = (i > K) ? i - K : 0;
+        uint32_t jhi = (i + K < ly) ? i + K : ly;
+        /* the cells just outside the band are infinite */
+        if (jlo >= 1) cur[jlo - 1] = INF;
+        if (jhi + 1 <= ly) cur[jhi + 1] = INF;
+        uint32_t rowmin = INF;
+        for (uint32_t j = jlo; j <= jhi; j++) {
+            uint32_t best;
+            if (j == 0) {
+                best = i;
+            } else {
+                best = prev[j - 1] + (x[i - 1] != y[j - 1]);
+                if (prev[j] != INF && prev[j] + 1 < best) best = prev[j] + 1;
+                if (cur[j - 1] != INF && cur[j - 1] + 1 < best) best = cur[j - 1] + 1;
+            }
+            if (best > INF) best = INF;
+            cur[j] = best;
+            if (best < rowmin) rowmin = best;
+        }
+        if (rowmin > K) done = 1;
+        uint32_t *t = prev; prev = cur; cur = t;
+    }
+    if (!done && prev[ly] <= K) result = prev[ly];
+    free(prev);
+    free(cur);
+    return result;
+}
+
+/* -------------------------------------------------- Algorithm 2 + 3 ----- */
+
+typedef struct {
+    uint64_t key;
+    uint32_t *ids;
+    uint32_t count, cap;
+    int used;
+} ejo_bucket;
+
+typedef struct {
+    ejo_bucket *slots;
+    uint64_t nslots; /* power of two */
+} ejo_table;
+
+static void table_init(ejo_table *t, uint64_t nslots) {
+    t->nslots = nslots;
+    t->slots = (ejo_bucket *)calloc(nslots, sizeof(ejo_bucket));
+}
+
+static void table_free(ejo_table *t) {
+    for (uint64_t s = 0; s < t->nslots; s++) free(t->slots[s].ids);
+    free(t->slots);
+}
+
+/* Linear probing on the key; returns the bucket holding `key`, creating it. */
+static ejo_bucket *table_bucket(ejo_table *t, uint64_t key) {
+    uint64_t h = ejo_mix64(key) & (t->nslots - 1);
+    while (t->slots[h].used && t->slots[h].key != key) h = (h + 1) & (t->nslots - 1);
+    if (!t->slots[h].used) {
+        t->slots[h].used = 1;
+        t->slots[h].key = key;
+    }
+    return &t->slots[h];
+}
+
+static void bucket_push(ejo_bucket *b, uint32_t id) {
+    if (b->count == b->cap) {
+        b->cap = b->cap ? 2 * b->cap : 4;
+        b->ids = (uint32_t *)realloc(b->ids, sizeof(uint32_t) * b->cap);
+    }
+    b->ids[b->count++] = id;
+}
+
+/* Sort order of Algorithm 2: length, then bytes, then original position. */
+static const uint8_t *g_chars;
+static const uint64_t *g_offsets;
+static int cmp_len_alpha(const void *pa, const void *pb) {
+    uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+    uint64_t la = g_offsets[a + 1] - g_offsets[a], lb = g_offsets[b + 1] - g_offsets[b];
+    if (la != lb) return la < lb ? -1 : 1;
+    int c = memcmp(g_chars + g_offsets[a], g_chars + g_offsets[b], la);
+    if (c) return c < 0 ? -1 : 1;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+static int cmp_u64(const void *pa, const void *pb) {
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Result of one join.  All indices are positions in the input.  Arrays are
+ * malloc'ed here and released with ejo_result_free. */
+typedef struct {
+    uint32_t sigma, L;
+    uint64_t n_cand;
+    uint64_t *cand;      /* (i << 32) | j, i < j, sorted */
+    uint32_t *cand_dist; /* min(ED, K+1) per candidate */
+    uint64_t n_out;
+    uint64_t *out;       /* (i << 32) | j, i < j, ED <= K, sorted */
+    uint32_t *out_dist;
+    uint64_t *keys;      /* [r*z][n], table-major, input order */
+    uint8_t *sig;        /* [n][r][z][m] sampled symbols (codes), input order */
+} ejo_result;
+
+void ejo_result_free(ejo_result *res) {
+    free(res->cand);
+    free(res->cand_dist);
+    free(res->out);
+    free(res->out_dist);
+    free(res->keys);
+    free(res->sig);
+    memset(res, 0, sizeof(*res));
+}
+
+/* Truncation length actually used: L_req, or ceil(average length) when 0,
+ * never more than 3N (the full output length of Algorithm 1) and at least 1. */
+uint32_t ejo_effective_L(const uint64_t *offsets, uint32_t n, uint32_t L_req) {
+    uint64_t total = n ? offsets[n] - offsets[0] : 0, N = 0;
+    for (uint32_t i = 0; i < n; i++) {
+        uint64_t li = offsets[i + 1] - offsets[i];
+        if (li > N) N = li;
+    }
+    uint64_t L = L_req;
+    if (L == 0) L = n ? (total + n - 1) / n : 1;
+    if (L > 3 * N) L = 3 * N;
+    if (L == 0) L = 1;
+    return (uint32_t)L;
+}
+
+/* EmbedJoin (Algorithm 3 with Algorithm 2 as preprocessing).
+ * explicit_R (r * L * sigma 0/1 bytes), explicit_pos and explicit_v replace
+ * the drawn randomness when non-NULL (used to replay the paper's running
+ * example).  Returns 0 on success. */
+int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+             uint32_t r, uint32_t z, uint32_t m, uint32_t L_req, uint64_t seed,
+             const uint8_t *explicit_R, const uint32_t *explicit_pos,
+             const uint64_t *explicit_v, ejo_result *res) {
+    memset(res, 0, sizeof(*res));
+    if (r == 0 || z == 0 || m == 0) return -1;
+    uint64_t total = n ? offsets[n] - offsets[0] : 0;
+    int32_t lut[256];
+    int sigma = ejo_alphabet(chars + (n ? offsets[0] : 0), total, lut);
+    uint32_t L = ejo_effective_L(offsets, n, L_req);
+    res->sigma = (uint32_t)sigma;
+    res->L = L;
+    uint32_t T = r * z;
+
+    /* symbol codes of every string */
+    uint8_t *codes = (uint8_t *)malloc(total ? total : 1);
+    for (uint64_t i = 0; i < total; i++) codes[i] = (uint8_t)lut[chars[offsets[0] + i]];
+
+    /* randomness */
+    uint64_t rb = (uint64_t)L * (uint64_t)sigma;
+    uint8_t *Rbits = (uint8_t *)malloc(r * rb + 1);
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * T * m);
+    uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * T * m);
+    ejo_draw(seed, r, z, m, L, (uint32_t)sigma, Rbits, pos, v);
+    if (explicit_R) memcpy(Rbits, explicit_R, r * rb);
+    if (explicit_pos) memcpy(pos, explicit_pos, sizeof(uint32_t) * T * m);
+    if (explicit_v) memcpy(v, explicit_v, sizeof(uint64_t) * T * m);
+
+    /* Algorithm 2: sort, then embed every string r times; keep only the
+     * sampled symbols (Section 4) and the resulting bucket keys. */
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    for (uint32_t i = 0; i < n; i++) order[i] = i;
+    g_chars = chars;
+    g_offsets = offsets;
+    qsort(order, n, sizeof(uint32_t), cmp_len_alpha);
+
+    res->keys = (uint64_t *)malloc(sizeof(uint64_t) * T * (n ? n : 1));
+    res->sig = (uint8_t *)malloc((uint64_t)n * T * m + 1);
+    uint8_t *t = (uint8_t *)malloc(L);
+    uint8_t *u = (uint8_t *)malloc(m);
+    for (uint32_t l = 0; l < r; l++) {
+        for (uint32_t oi = 0; oi < n; oi++) {
+            uint32_t i = order[oi];
+            uint32_t len = (uint32_t)(offsets[i + 1] - offsets[i]);
+            ejo_cgk_embed(codes + (offsets[i] - offsets[0]), len, Rbits + l * rb,
+                          (uint32_t)sigma, L, t);
+            for (uint32_t j = 0; j < z; j++) {
+                const uint32_t *pj = pos + ((uint64_t)l * z + j) * m;
+                const uint64_t *vj = v + ((uint64_t)l * z + j) * m;
+                for (uint32_t k = 0; k < m; k++) u[k] = t[pj[k]];
+                memcpy(res->sig + (((uint64_t)i * r + l) * z + j) * m, u, m);
+                res->keys[((uint64_t)l * z + j) * n + i] = ejo_key(t, pj, vj, m);
+            }
+        }
+    }
+    free(t);
+    free(u);
+
+    /* Algorithm 3: one hash table per (l, j); strings in sorted order. */
+    ejo_table *tables = (ejo_table *)malloc(sizeof(ejo_table) * T);
+    uint64_t nslots = 16;
+    while (nslots < 2ULL * n) nslots <<= 1;
+    for (uint32_t q = 0; q < T; q++) table_init(&tables[q], nslots);
+    uint64_t cap = 1024, cnt = 0;
+    uint64_t *cand = (uint64_t *)malloc(sizeof(uint64_t) * cap);
+    uint64_t icap = 64;
+    uint64_t *iter_pairs = (uint64_t *)malloc(sizeof(uint64_t) * icap);
+    for (uint32_t oi = 0; oi < n; oi++) {
+        uint32_t si = order[oi];
+        uint64_t len_i = offsets[si + 1] - offsets[si];
+        uint64_t icnt = 0;
+        for (uint32_t l = 0; l < r; l++) {
+            for (uint32_t j = 0; j < z; j++) {
+                uint32_t q = l * z + j;
+                ejo_bucket *b = table_bucket(&tables[q], res->keys[(uint64_t)q * n + si]);
+                uint32_t keep = 0;
+                for (uint32_t e = 0; e < b->count; e++) {
+                    uint32_t s = b->ids[e];
+                    uint64_t len_s = offsets[s + 1] - offsets[s];
+                    if (len_i - len_s <= K) {
+                        uint32_t a = s < si ? s : si, c = s < si ? si : s;
+                        if (icnt == icap) {
+                            icap *= 2;
+                            iter_pairs = (uint64_t *)realloc(iter_pairs, sizeof(uint64_t) * icap);
+                        }
+                        iter_pairs[icnt++] = ((uint64_t)a << 32) | c;
+                        b->ids[keep++] = s;
+                    }
+                    /* else: evicted (not kept) */
+                }
+                b->count = keep;
+                bucket_push(b, si);
+            }
+        }
+        /* remove duplicate pairs found in this iteration; pairs from
+         * different iterations differ in their later element */
+        qsort(iter_pairs, icnt, sizeof(uint64_t), cmp_u64);
+        for (uint64_t e = 0; e < icnt; e++) {
+            if (e > 0 && iter_pairs[e] == iter_pairs[e - 1]) continue;
+            if (cnt == cap) {
+                cap *= 2;
+                cand = (uint64_t *)realloc(cand, sizeof(uint64_t) * cap);
+            }
+            cand[cnt++] = iter_pairs[e];
+        }
+    }
+    free(iter_pairs);
+    for (uint32_t q = 0; q < T; q++) table_free(&tables[q]);
+    free(tables);
+    qsort(cand, cnt, sizeof(uint64_t), cmp_u64);
+
+    /* verification */
+    res->n_cand = cnt;
+    res->cand = cand;
+    res->cand_dist = (uint32_t *)malloc(sizeof(uint32_t) * (cnt ? cnt : 1));
+    res->out = (uint64_t *)malloc(sizeof(uint64_t) * (cnt ? cnt : 1));
+    res->out_dist = (uint32_t *)malloc(sizeof(uint32_t) * (cnt ? cnt : 1));
+    uint64_t nout = 0;
+    for (uint64_t e = 0; e < cnt; e++) {
+        uint32_t a = (uint32_t)(cand[e] >> 32), c = (uint32_t)(cand[e] & 0xFFFFFFFFu);
+        uint32_t d = ejo_ed_banded(chars + offsets[a], (uint32_t)(offsets[a + 1] - offsets[a]),
+                                   chars + offsets[c], (uint32_t)(offsets[c + 1] - offsets[c]), K);
+        res->cand_dist[e] = d;
+        if (d <= K) {
+            res->out[nout] = cand[e];
+            res->out_dist[nout] = d;
+            nout++;
+        }
+    }
+    res->n_out = nout;
+    free(order);
+    free(codes);
+    free(Rbits);
+    free(pos);
+    free(v);
+    return 0;
+}
+
+/* Verification only: min(ED, K+1) for each pair (a_k, b_k). */
+void ejo_verify_pairs(const uint8_t *chars, const uint64_t *offsets, const uint64_t *pairs,
+                      uint64_t count, uint32_t K, uint32_t *dist) {
+    for (uint64_t e = 0; e < count; e++) {
+        uint32_t a = (uint32_t)(pairs[e] >> 32), c = (uint32_t)(pairs[e] & 0xFFFFFFFFu);
+        dist[e] = ejo_ed_banded(chars + offsets[a], (uint32_t)(offsets[a + 1] - offsets[a]),
+                                chars + offsets[c], (uint32_t)(offsets[c + 1] - offsets[c]), K);
+    }
+}
+
+/* Exact join by brute force: every pair, full Wagner-Fischer.  Writes at
+ * most `cap` pairs, returns the total count. */
+uint64_t ejo_brute_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+                        uint64_t *out, uint32_t *dist, uint64_t cap) {
+    uint64_t cnt = 0;
+    for (uint32_t a = 0; a < n; a++) {
+        for (uint32_t c = a + 1; c < n; c++) {
+            uint32_t d = ejo_ed_full(chars + offsets[a], (uint32_t)(offsets[a + 1] - offsets[a]),
+                                     chars + offsets[c], (uint32_t)(offsets[c + 1] - offsets[c]));
+            if (d <= K) {
+                if (cnt < cap) {
+                    out[cnt] = ((uint64_t)a << 32) | c;
+                    dist[cnt] = d;
+                }
+                cnt++;
+            }
+        }
+    }
+    return cnt;
+}

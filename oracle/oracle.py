@@ -1,0 +1,258 @@
+"""ctypes front-end of the plain C oracle (``ej_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, by the smoke check and by the
+CPU-baseline leg of the benchmark.  The product package never imports it.
+
+``build()`` compiles ``ej_oracle.c`` with gcc into ``liboracle.so`` next to
+this file; every other function loads that library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "ej_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+P61 = (1 << 61) - 1
+GAMMA = 0x9E3779B97F4A7C15
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+                               "-Wno-unused-function", SRC, "-o", tmp])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [
+        ("sigma", ctypes.c_uint32), ("L", ctypes.c_uint32),
+        ("n_cand", ctypes.c_uint64), ("cand", ctypes.POINTER(ctypes.c_uint64)),
+        ("cand_dist", ctypes.POINTER(ctypes.c_uint32)),
+        ("n_out", ctypes.c_uint64), ("out", ctypes.POINTER(ctypes.c_uint64)),
+        ("out_dist", ctypes.POINTER(ctypes.c_uint32)),
+        ("keys", ctypes.POINTER(ctypes.c_uint64)),
+        ("sig", ctypes.POINTER(ctypes.c_uint8)),
+    ]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=False)
+        L = ctypes.CDLL(LIB)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.ejo_mix64.restype = ctypes.c_uint64
+        L.ejo_mix64.argtypes = [ctypes.c_uint64]
+        L.ejo_word.restype = ctypes.c_uint64
+        L.ejo_word.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.ejo_stream_key.restype = ctypes.c_uint64
+        L.ejo_stream_key.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32]
+        L.ejo_splitmix64_stream.restype = None
+        L.ejo_splitmix64_stream.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p]
+        L.ejo_draw.restype = None
+        L.ejo_draw.argtypes = [ctypes.c_uint64] + [ctypes.c_uint32] * 5 + [u8p, u32p, u64p]
+        L.ejo_alphabet.restype = ctypes.c_int
+        L.ejo_alphabet.argtypes = [u8p, ctypes.c_uint64, i32p]
+        L.ejo_cgk_embed.restype = None
+        L.ejo_cgk_embed.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32,
+                                    ctypes.c_uint32, u8p]
+        L.ejo_key.restype = ctypes.c_uint64
+        L.ejo_key.argtypes = [u8p, u32p, u64p, ctypes.c_uint32]
+        L.ejo_ed_full.restype = ctypes.c_uint32
+        L.ejo_ed_full.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32]
+        L.ejo_ed_banded.restype = ctypes.c_uint32
+        L.ejo_ed_banded.argtypes = [u8p, ctypes.c_uint32, u8p, ctypes.c_uint32, ctypes.c_uint32]
+        L.ejo_effective_L.restype = ctypes.c_uint32
+        L.ejo_effective_L.argtypes = [u64p, ctypes.c_uint32, ctypes.c_uint32]
+        L.ejo_join.restype = ctypes.c_int
+        L.ejo_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                               ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                               ctypes.c_uint64, u8p, u32p, u64p, ctypes.POINTER(_Result)]
+        L.ejo_result_free.restype = None
+        L.ejo_result_free.argtypes = [ctypes.POINTER(_Result)]
+        L.ejo_verify_pairs.restype = None
+        L.ejo_verify_pairs.argtypes = [u8p, u64p, u64p, ctypes.c_uint64, ctypes.c_uint32, u32p]
+        L.ejo_brute_join.restype = ctypes.c_uint64
+        L.ejo_brute_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
+                                     u64p, u32p, ctypes.c_uint64]
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _u8(b) -> np.ndarray:
+    if isinstance(b, (bytes, bytearray)):
+        return np.frombuffer(bytes(b) + b"\0", dtype=np.uint8)[:len(b)].copy()
+    return np.ascontiguousarray(b, dtype=np.uint8)
+
+
+# ------------------------------------------------------------------- RNG --
+
+def mix64(z: int) -> int:
+    return int(lib().ejo_mix64(z))
+
+
+def word(key: int, c: int) -> int:
+    return int(lib().ejo_word(key, c))
+
+
+def stream_key(seed: int, tag: int, idx: int) -> int:
+    return int(lib().ejo_stream_key(seed, tag, idx))
+
+
+def splitmix64(seed: int, count: int) -> np.ndarray:
+    out = np.zeros(max(count, 1), dtype=np.uint64)
+    lib().ejo_splitmix64_stream(seed, count, _ptr(out, ctypes.c_uint64))
+    return out[:count]
+
+
+def draw(seed: int, r: int, z: int, m: int, L: int, sigma: int):
+    """Returns (Rbits[r, L*sigma] 0/1, pos[r, z, m], v[r, z, m])."""
+    Rb = np.zeros(max(r * L * sigma, 1), dtype=np.uint8)
+    pos = np.zeros(r * z * m, dtype=np.uint32)
+    v = np.zeros(r * z * m, dtype=np.uint64)
+    lib().ejo_draw(seed, r, z, m, L, sigma, _ptr(Rb, ctypes.c_uint8),
+                   _ptr(pos, ctypes.c_uint32), _ptr(v, ctypes.c_uint64))
+    return Rb[:r * L * sigma].reshape(r, L * sigma), pos.reshape(r, z, m), v.reshape(r, z, m)
+
+
+# ----------------------------------------------------------- primitives --
+
+def alphabet(chars) -> tuple[int, np.ndarray]:
+    c = _u8(chars)
+    lut = np.zeros(256, dtype=np.int32)
+    s = lib().ejo_alphabet(_ptr(c, ctypes.c_uint8), c.shape[0], _ptr(lut, ctypes.c_int32))
+    return int(s), lut
+
+
+def cgk_embed(codes, Rbits_l, sigma: int, L: int) -> np.ndarray:
+    x = _u8(codes)
+    R = np.ascontiguousarray(Rbits_l, dtype=np.uint8)
+    out = np.zeros(max(L, 1), dtype=np.uint8)
+    lib().ejo_cgk_embed(_ptr(x, ctypes.c_uint8), x.shape[0], _ptr(R, ctypes.c_uint8),
+                        sigma, L, _ptr(out, ctypes.c_uint8))
+    return out[:L]
+
+
+def key(t, pos, v) -> int:
+    t = _u8(t)
+    pos = np.ascontiguousarray(pos, dtype=np.uint32)
+    v = np.ascontiguousarray(v, dtype=np.uint64)
+    return int(lib().ejo_key(_ptr(t, ctypes.c_uint8), _ptr(pos, ctypes.c_uint32),
+                             _ptr(v, ctypes.c_uint64), pos.shape[0]))
+
+
+def ed_full(x, y) -> int:
+    x, y = _u8(x), _u8(y)
+    return int(lib().ejo_ed_full(_ptr(x, ctypes.c_uint8), x.shape[0],
+                                 _ptr(y, ctypes.c_uint8), y.shape[0]))
+
+
+def ed_banded(x, y, K: int) -> int:
+    x, y = _u8(x), _u8(y)
+    return int(lib().ejo_ed_banded(_ptr(x, ctypes.c_uint8), x.shape[0],
+                                   _ptr(y, ctypes.c_uint8), y.shape[0], K))
+
+
+def effective_L(offsets, L_req: int) -> int:
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    return int(lib().ejo_effective_L(_ptr(off, ctypes.c_uint64), off.shape[0] - 1, L_req))
+
+
+# -------------------------------------------------------------- the join --
+
+class JoinResult:
+    def __init__(self, res: _Result, n: int, r: int, z: int, m: int):
+        self.sigma = int(res.sigma)
+        self.L = int(res.L)
+        nc, no = int(res.n_cand), int(res.n_out)
+        self.cand = np.ctypeslib.as_array(res.cand, (max(nc, 1),))[:nc].copy()
+        self.cand_dist = np.ctypeslib.as_array(res.cand_dist, (max(nc, 1),))[:nc].copy()
+        self.out = np.ctypeslib.as_array(res.out, (max(no, 1),))[:no].copy()
+        self.out_dist = np.ctypeslib.as_array(res.out_dist, (max(no, 1),))[:no].copy()
+        T = r * z
+        self.keys = np.ctypeslib.as_array(res.keys, (max(T * n, 1),))[:T * n].copy().reshape(T, n)
+        self.sig = np.ctypeslib.as_array(res.sig, (max(n * T * m, 1),))[:n * T * m].copy() \
+            .reshape(n, r, z, m)
+
+    @staticmethod
+    def pairs(codes: np.ndarray) -> np.ndarray:
+        codes = np.asarray(codes, dtype=np.uint64)
+        return np.stack([(codes >> np.uint64(32)).astype(np.int64),
+                         (codes & np.uint64(0xFFFFFFFF)).astype(np.int64)], 1)
+
+    @property
+    def cand_pairs(self):
+        return self.pairs(self.cand)
+
+    @property
+    def out_pairs(self):
+        return self.pairs(self.out)
+
+
+def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
+         explicit_R=None, explicit_pos=None, explicit_v=None) -> JoinResult:
+    c = _u8(chars)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.shape[0] - 1
+    res = _Result()
+    eR = None if explicit_R is None else np.ascontiguousarray(explicit_R, dtype=np.uint8)
+    eP = None if explicit_pos is None else np.ascontiguousarray(explicit_pos, dtype=np.uint32)
+    eV = None if explicit_v is None else np.ascontiguousarray(explicit_v, dtype=np.uint64)
+    rc = lib().ejo_join(_ptr(c, ctypes.c_uint8) if c.size else None,
+                        _ptr(off, ctypes.c_uint64), n, K, r, z, m, L, seed,
+                        None if eR is None else _ptr(eR, ctypes.c_uint8),
+                        None if eP is None else _ptr(eP, ctypes.c_uint32),
+                        None if eV is None else _ptr(eV, ctypes.c_uint64),
+                        ctypes.byref(res))
+    if rc != 0:
+        raise ValueError(f"oracle join rejected its arguments (rc={rc})")
+    try:
+        return JoinResult(res, n, r, z, m)
+    finally:
+        lib().ejo_result_free(ctypes.byref(res))
+
+
+def verify_pairs(chars, offsets, pairs, K: int) -> np.ndarray:
+    c = _u8(chars)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    p = np.ascontiguousarray(pairs, dtype=np.uint64)
+    d = np.zeros(max(p.shape[0], 1), dtype=np.uint32)
+    lib().ejo_verify_pairs(_ptr(c, ctypes.c_uint8) if c.size else None,
+                           _ptr(off, ctypes.c_uint64), _ptr(p, ctypes.c_uint64),
+                           p.shape[0], K, _ptr(d, ctypes.c_uint32))
+    return d[:p.shape[0]]
+
+
+def brute_join(chars, offsets, K: int):
+    """Exact join: (pairs[i<j] as uint64 codes, dist)."""
+    c = _u8(chars)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.shape[0] - 1
+    cap = 1 << 16
+    while True:
+        out = np.zeros(cap, dtype=np.uint64)
+        d = np.zeros(cap, dtype=np.uint32)
+        cnt = int(lib().ejo_brute_join(_ptr(c, ctypes.c_uint8) if c.size else None,
+                                       _ptr(off, ctypes.c_uint64), n, K,
+                                       _ptr(out, ctypes.c_uint64), _ptr(d, ctypes.c_uint32), cap))
+        if cnt <= cap:
+            return out[:cnt], d[:cnt]
+        cap = cnt

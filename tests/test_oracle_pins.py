@@ -1,0 +1,373 @@
+"""Pins of the CPU oracle against facts outside itself: the paper's worked
+examples, published RNG test vectors, the definition of edit distance checked
+by exhaustive search, closed forms of the LSH collision probability, and
+brute force on tiny inputs."""
+import itertools
+import json
+import os
+from collections import deque
+
+import numpy as np
+import pytest
+
+import synthdata as sd
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------------------ RNG --
+
+def test_splitmix64_published_vector(oracle_lib):
+    g = _load("splitmix64.json")
+    got = oracle_lib.splitmix64(g["seed"], len(g["outputs"]))
+    assert [int(x) for x in got] == [int(x) for x in g["outputs"]]
+
+
+def test_counter_word_is_stream_draw(oracle_lib):
+    # W(key, c) is the (c+1)-th draw of the sequential generator seeded with key
+    for key in (0, 1, 1234567, 0xDEADBEEFCAFEBABE):
+        seq = oracle_lib.splitmix64(key, 40)
+        assert [oracle_lib.word(key, c) for c in range(40)] == [int(x) for x in seq]
+
+
+def test_random_string_bits_balanced(oracle_lib):
+    R, pos, v = oracle_lib.draw(7, 3, 4, 8, 4000, 4)
+    frac = R.mean()
+    # 48000 fair bits: 6 sigma is ~0.014
+    assert abs(frac - 0.5) < 0.014
+    assert (pos < 4000).all()
+    assert (v < oracle_lib.P61).all()
+
+
+def test_coordinates_uniform(oracle_lib):
+    L = 64
+    _, pos, _ = oracle_lib.draw(3, 4, 16, 64, L, 4)
+    counts = np.bincount(pos.ravel(), minlength=L)
+    exp = pos.size / L
+    chi2 = ((counts - exp) ** 2 / exp).sum()
+    # 63 degrees of freedom: 99.99th percentile is ~ 118
+    assert chi2 < 118
+
+
+# -------------------------------------------------- running example ----
+
+def _running_example_randomness(g):
+    sig = g["alphabet"]
+    L, r, z, m = g["L"], g["r"], g["z"], g["m"]
+    R = np.zeros((r, L * len(sig)), dtype=np.uint8)
+    for l, name in enumerate(["R1", "R2"]):
+        for k, ch in enumerate(sig):
+            for j, bit in enumerate(g["pi"][name][ch]):
+                R[l, j * len(sig) + k] = bit
+    coords = g["lsh_coordinates_1based"]
+    pos = np.zeros((r, z, m), dtype=np.uint32)
+    for l in range(r):
+        for j in range(z):
+            pos[l, j] = np.array(coords[f"f{j + 1}^{l + 1}"]) - 1
+    return R, pos
+
+
+def test_running_example_embeddings(oracle_lib):
+    g = _load("running_example.json")
+    R, _ = _running_example_randomness(g)
+    sigma, lut = oracle_lib.alphabet(b"".join(s.encode() for s in g["strings"]))
+    assert sigma == 4
+    letters = np.array([ord(c) for c in g["alphabet"]])
+    for i, s in enumerate(g["strings"]):
+        codes = lut[np.frombuffer(s.encode(), dtype=np.uint8)].astype(np.uint8)
+        for l in range(2):
+            t = oracle_lib.cgk_embed(codes, R[l], sigma, g["L"])
+            got = "".join(chr(letters[c]) for c in t)
+            assert got == g["embeddings_prefix"][f"t{i + 1}^{l + 1}"], (i, l)
+
+
+def test_running_example_join(oracle_lib):
+    g = _load("running_example.json")
+    R, pos = _running_example_randomness(g)
+    col = sd.from_strings([s.encode() for s in g["strings"]])
+    res = oracle_lib.join(col.chars, col.offsets, g["K"], g["r"], g["z"], g["m"],
+                          seed=0, L=g["L"], explicit_R=R, explicit_pos=pos)
+    letters = g["alphabet"]
+    for i in range(4):
+        sigs = ["".join(letters[c] for c in res.sig[i, l, j]) for l in range(2) for j in range(2)]
+        assert sigs == g["signatures"][str(i + 1)], i
+    assert (res.cand_pairs + 1).tolist() == g["candidates_1based"]
+    assert (res.out_pairs + 1).tolist() == g["output_1based"]
+    assert res.out_dist.tolist() == [2, 3]
+
+
+# ---------------------------------------------------- intro example ----
+
+def test_intro_example_brute_force(oracle_lib):
+    g = _load("intro_example.json")
+    col = sd.from_strings([s.encode() for s in g["strings"]])
+    codes, d = oracle_lib.brute_join(col.chars, col.offsets, g["K"])
+    S = g["strings"]
+    got = sorted(tuple(sorted((S[int(c) >> 32], S[int(c) & 0xFFFFFFFF]))) for c in codes)
+    assert got == sorted(tuple(sorted(p)) for p in g["output"])
+    # threshold is inclusive: at K=3 four more pairs (distance exactly 3) join
+    codes3, d3 = oracle_lib.brute_join(col.chars, col.offsets, 3)
+    assert len(codes3) == 7 and sorted(d3.tolist()) == [2, 2, 2, 3, 3, 3, 3]
+
+
+def test_intro_example_embedjoin_fixed_seed(oracle_lib):
+    g = _load("intro_example.json")
+    col = sd.from_strings([s.encode() for s in g["strings"]])
+    res = oracle_lib.join(col.chars, col.offsets, g["K"], r=7, z=7, m=1, seed=0, L=5)
+    S = g["strings"]
+    got = sorted(tuple(sorted((S[a], S[b]))) for a, b in res.out_pairs)
+    assert got == sorted(tuple(sorted(p)) for p in g["output"])
+
+
+# ------------------------------------------------------ edit distance ----
+
+def _ed_by_search(x: bytes, y: bytes, alphabet: bytes) -> int:
+    """Edit distance by its definition: breadth-first search over strings,
+    one insertion / deletion / substitution per edge."""
+    if x == y:
+        return 0
+    maxlen = max(len(x), len(y)) + 1
+    seen = {x}
+    q = deque([(x, 0)])
+    while q:
+        s, d = q.popleft()
+        nbrs = set()
+        for i in range(len(s)):
+            nbrs.add(s[:i] + s[i + 1:])
+            for a in alphabet:
+                nbrs.add(s[:i] + bytes([a]) + s[i + 1:])
+        if len(s) < maxlen:
+            for i in range(len(s) + 1):
+                for a in alphabet:
+                    nbrs.add(s[:i] + bytes([a]) + s[i:])
+        for t in nbrs:
+            if t == y:
+                return d + 1
+            if t not in seen:
+                seen.add(t)
+                q.append((t, d + 1))
+    raise AssertionError("unreachable")
+
+
+def test_edit_distance_matches_definition(oracle_lib):
+    rng = np.random.default_rng(11)
+    alpha = b"ab"
+    for _ in range(120):
+        lx, ly = rng.integers(0, 6, size=2)
+        x = bytes(rng.choice(list(alpha), size=lx).tolist())
+        y = bytes(rng.choice(list(alpha), size=ly).tolist())
+        truth = _ed_by_search(x, y, alpha)
+        assert oracle_lib.ed_full(x, y) == truth, (x, y)
+        for K in range(0, 6):
+            assert oracle_lib.ed_banded(x, y, K) == min(truth, K + 1), (x, y, K)
+
+
+def test_edit_distance_textbook_values(oracle_lib):
+    assert oracle_lib.ed_full(b"kitten", b"sitting") == 3
+    assert oracle_lib.ed_full(b"", b"abc") == 3
+    assert oracle_lib.ed_full(b"flaw", b"lawn") == 2
+    assert oracle_lib.ed_banded(b"kitten", b"sitting", 2) == 3
+    assert oracle_lib.ed_banded(b"", b"", 0) == 0
+
+
+def test_banded_matches_full_on_longer_strings(oracle_lib):
+    col = sd.clusters(5, 6, lambda r, b: 4, lambda r: r.integers(150, 260),
+                      lambda r, L: r.poisson(15))
+    S = col.strings()
+    rng = np.random.default_rng(2)
+    for a, b in itertools.combinations(range(len(S)), 2):
+        full = oracle_lib.ed_full(S[a], S[b])
+        for K in (0, 5, int(rng.integers(0, 60)), 120):
+            assert oracle_lib.ed_banded(S[a], S[b], K) == min(full, K + 1)
+
+
+def test_edit_distance_metric_properties(oracle_lib):
+    col = sd.random_strings(9, 12, 0, 40, letters=b"ACG")
+    S = col.strings()
+    for a, b in itertools.combinations(range(len(S)), 2):
+        d = oracle_lib.ed_full(S[a], S[b])
+        assert d == oracle_lib.ed_full(S[b], S[a])
+        assert abs(len(S[a]) - len(S[b])) <= d <= max(len(S[a]), len(S[b]))
+        if len(S[a]) == len(S[b]):
+            assert d <= sum(p != q for p, q in zip(S[a], S[b]))
+    for a, b, c in itertools.combinations(range(len(S)), 3):
+        assert oracle_lib.ed_full(S[a], S[c]) <= oracle_lib.ed_full(S[a], S[b]) + \
+            oracle_lib.ed_full(S[b], S[c])
+
+
+# --------------------------------------------------------- embedding ----
+
+def _codes(oracle_lib, strings):
+    sigma, lut = oracle_lib.alphabet(b"".join(strings))
+    return sigma, [lut[np.frombuffer(s, dtype=np.uint8)].astype(np.uint8) for s in strings]
+
+
+def test_ed_at_most_hamming_when_walks_finish(oracle_lib):
+    """Footnote of the introduction: with bottom padding, ED(x,y) <= Ham of the
+    embeddings whenever both walks have consumed their strings."""
+    col = sd.clusters(21, 30, lambda r, b: 3, lambda r: r.integers(20, 60),
+                      lambda r, L: r.poisson(4))
+    S = col.strings()
+    sigma, C = _codes(oracle_lib, S)
+    L = 3 * max(len(s) for s in S)
+    R, _, _ = oracle_lib.draw(4, 6, 1, 1, L, sigma)
+    checked = 0
+    for l in range(6):
+        E = [oracle_lib.cgk_embed(c, R[l], sigma, L) for c in C]
+        done = [bool(e[-1] == sigma) or len(s) == 0 for e, s in zip(E, S)]
+        for a, b in itertools.combinations(range(len(S)), 2):
+            if done[a] and done[b]:
+                ham = int((E[a] != E[b]).sum())
+                assert oracle_lib.ed_full(S[a], S[b]) <= ham
+                checked += 1
+    assert checked > 1000
+
+
+def test_embedding_is_prefix_stable_and_deterministic(oracle_lib):
+    S = sd.random_strings(3, 10, 0, 80).strings()
+    sigma, C = _codes(oracle_lib, S)
+    R, _, _ = oracle_lib.draw(1, 1, 1, 1, 300, sigma)
+    for c in C:
+        full = oracle_lib.cgk_embed(c, R[0], sigma, 300)
+        assert (oracle_lib.cgk_embed(c, R[0], sigma, 100) == full[:100]).all()
+        # the walk never skips a character: the embedding, with padding and
+        # repeats removed step by step, spells the string
+        steps = [int(s) for s in full if s != sigma]
+        assert len(steps) >= len(c)
+
+
+def test_walk_length_about_twice_string_length(oracle_lib):
+    """Section 4.1: the number of embedding steps concentrates around 2|x|."""
+    S = sd.random_strings(5, 60, 800, 1200).strings()
+    sigma, C = _codes(oracle_lib, S)
+    L = 3 * max(len(s) for s in S)
+    R, _, _ = oracle_lib.draw(9, 2, 1, 1, L, sigma)
+    ratios = []
+    for l in range(2):
+        for c in C:
+            t = oracle_lib.cgk_embed(c, R[l], sigma, L)
+            end = int(np.argmax(t == sigma)) if (t == sigma).any() else L
+            ratios.append(end / len(c))
+    assert 1.9 < float(np.mean(ratios)) < 2.1
+
+
+# ---------------------------------------------------------------- LSH ----
+
+def test_key_is_linear_in_the_signature(oracle_lib):
+    """<u, v> mod P: raising one coordinate symbol by one adds v_k mod P."""
+    rng = np.random.default_rng(4)
+    _, _, v = oracle_lib.draw(2, 1, 1, 24, 100, 5)
+    v = v[0, 0]
+    pos = np.arange(24, dtype=np.uint32)
+    for _ in range(50):
+        t = rng.integers(0, 5, size=24).astype(np.uint8)
+        k = int(rng.integers(0, 24))
+        t2 = t.copy()
+        t2[k] += 1
+        d = (oracle_lib.key(t2, pos, v) - oracle_lib.key(t, pos, v)) % oracle_lib.P61
+        assert d == int(v[k])
+    # all-zero codes: u = 1 everywhere, key = sum(v) mod P
+    t = np.zeros(24, dtype=np.uint8)
+    assert oracle_lib.key(t, pos, v) == sum(int(x) for x in v) % oracle_lib.P61
+
+
+def test_bit_sampling_collision_probability(oracle_lib):
+    """Bit-sampling theorem + AND construction: for embeddings at Hamming
+    distance H over L coordinates, a table with m coordinates drawn with
+    replacement collides with probability (1 - H/L)^m."""
+    rng = np.random.default_rng(8)
+    L, m = 40, 3
+    a = rng.integers(0, 4, size=L).astype(np.uint8)
+    b = a.copy()
+    H = 10
+    flip = rng.choice(L, size=H, replace=False)
+    b[flip] = (b[flip] + 1) % 4
+    trials = 0
+    hits = 0
+    for seed in range(40):
+        _, pos, v = oracle_lib.draw(seed, 1, 100, m, L, 4)
+        for j in range(100):
+            trials += 1
+            hits += oracle_lib.key(a, pos[0, j], v[0, j]) == oracle_lib.key(b, pos[0, j], v[0, j])
+    p = (1 - H / L) ** m
+    sd_ = np.sqrt(p * (1 - p) / trials)
+    assert abs(hits / trials - p) < 5 * sd_
+
+
+# -------------------------------------------------------- whole join ----
+
+def _brute_candidates(col, keys, K):
+    n = col.n
+    lens = col.lengths()
+    out = set()
+    for a in range(n):
+        for b in range(a + 1, n):
+            if abs(lens[a] - lens[b]) <= K and (keys[:, a] == keys[:, b]).any():
+                out.add((a, b))
+    return out
+
+
+@pytest.mark.parametrize("seed,K,r,z,m,L", [(0, 12, 3, 4, 2, 0), (1, 30, 2, 5, 3, 40),
+                                             (2, 5, 4, 3, 1, 20), (3, 0, 3, 3, 2, 0)])
+def test_candidates_equal_definition(oracle_lib, seed, K, r, z, m, L):
+    """The hash-table loop with eviction yields exactly the pairs that share a
+    bucket in some table and differ in length by at most K."""
+    col = sd.clusters(seed, 15, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(5, 70),
+                      lambda rr, LL: rr.poisson(3))
+    res = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
+    assert set(map(tuple, res.cand_pairs.tolist())) == _brute_candidates(col, res.keys, K)
+
+
+def test_buckets_by_key_equal_buckets_by_signature(oracle_lib):
+    col = sd.clusters(6, 20, lambda rr, b: 3, lambda rr: rr.integers(10, 30),
+                      lambda rr, L: rr.poisson(2))
+    r, z, m = 2, 3, 4
+    res = oracle_lib.join(col.chars, col.offsets, 5, r, z, m, seed=6, L=16)
+    for l in range(r):
+        for j in range(z):
+            sig = [bytes(res.sig[i, l, j]) for i in range(col.n)]
+            key = res.keys[l * z + j]
+            for a, b in itertools.combinations(range(col.n), 2):
+                assert (sig[a] == sig[b]) == (key[a] == key[b])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_output_is_exact_subset_and_precision_one(oracle_lib, seed):
+    col = sd.clusters(seed, 25, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(30, 90),
+                      lambda rr, L: rr.poisson(4))
+    K = 8
+    truth_codes, truth_d = oracle_lib.brute_join(col.chars, col.offsets, K)
+    truth = dict(zip(truth_codes.tolist(), truth_d.tolist()))
+    res = oracle_lib.join(col.chars, col.offsets, K, 4, 6, 3, seed=seed, L=0)
+    for c, d in zip(res.out.tolist(), res.out_dist.tolist()):
+        assert truth[c] == d
+    # every candidate that is a true pair is reported
+    cand_true = [c for c in res.cand.tolist() if c in truth]
+    assert sorted(cand_true) == res.out.tolist()
+
+
+def test_identical_strings_always_join(oracle_lib):
+    S = [b"ACGTTGCA" * 5, b"ACGTTGCA" * 5, b"", b"", b"TTTT", b"TTTT"]
+    col = sd.from_strings(S)
+    res = oracle_lib.join(col.chars, col.offsets, 0, 1, 1, 4, seed=3, L=0)
+    assert res.out_pairs.tolist() == [[0, 1], [2, 3], [4, 5]]
+    assert res.out_dist.tolist() == [0, 0, 0]
+
+
+def test_empty_and_degenerate_inputs(oracle_lib):
+    col = sd.from_strings([])
+    res = oracle_lib.join(col.chars, col.offsets, 3, 2, 2, 2)
+    assert res.out.size == 0 and res.cand.size == 0
+    col = sd.from_strings([b"", b"", b""])
+    res = oracle_lib.join(col.chars, col.offsets, 0, 2, 2, 2)
+    assert res.out_pairs.tolist() == [[0, 1], [0, 2], [1, 2]]
+    col = sd.from_strings([b"A"])
+    res = oracle_lib.join(col.chars, col.offsets, 3, 2, 2, 2)
+    assert res.out.size == 0
+    with pytest.raises(ValueError):
+        oracle_lib.join(col.chars, col.offsets, 3, 0, 2, 2)
