@@ -1,0 +1,231 @@
+/*
+ * embedjoin.h -- C ABI of libembedjoin.so, an MI355X (gfx950) implementation
+ * of the data-parallel hot path of EmbedJoin (H. Zhang, Q. Zhang, "EmbedJoin:
+ * Efficient Edit Similarity Joins via Embeddings").
+ *
+ * Problem (Section 1): given strings s_1..s_n and a threshold K, report the
+ * pairs (s_i, s_j), i != j, with ED(s_i, s_j) <= K.  EmbedJoin (Algorithms 1-3)
+ * finds candidate pairs by embedding every string r times into Hamming space
+ * with the CGK walk (Algorithm 1), hashing each embedding with z bit-sampling
+ * LSH functions of m coordinates (Section 3.2, two-level hashing of Section
+ * 4), keeping pairs that share a bucket in some table and differ in length by
+ * at most K (Algorithm 3), and verifying every candidate with exact
+ * threshold edit distance (Section 3.3).  The output is therefore exact in
+ * precision and may miss pairs (recall < 1), fully determined by the inputs,
+ * the parameters and the random seed.
+ *
+ * Conventions shared by every entry point
+ *   - Strings are a byte array plus offsets: string i is
+ *     chars[offsets[i] .. offsets[i+1]), offsets non-decreasing, n+1 entries.
+ *     Strings may be empty.  Pairs refer to positions 0..n-1; identical
+ *     strings at different positions are different strings.
+ *   - Alphabet: the sorted set of distinct bytes of the input; the k-th
+ *     smallest byte has code k-1 and the padding symbol (bottom) is |S|.
+ *   - Randomness follows one counter-based specification (SplitMix64 words
+ *     W(key, c) = Mix64(key + (c+1) * 0x9E3779B97F4A7C15)); stream keys are
+ *     W(seed, tag << 32 | idx) with tag 0 for the random string R^l (idx l),
+ *     tag 1 for LSH coordinates and tag 2 for the second-level hash vector of
+ *     table (l, j) (idx l*z + j).  Bit b of R^l is bit b%64 of
+ *     W(key_R, b/64); pi_j(sigma_k) is bit (j-1)*|S| + (k-1).  Coordinate k of
+ *     table (l, j) is floor(W(key_POS, k) * L / 2^64) (drawn with
+ *     replacement), and v_k = (W(key_V, k) >> 3) mod (2^61 - 1).
+ *   - Bucket key of table (l, j) for a string: sum_k u_k v_k mod (2^61 - 1)
+ *     with u_k = (symbol at coordinate k) + 1.
+ *   - Truncation (Section 4.1): the embedding is cut to L symbols; L = 0
+ *     selects ceil(average length); L is clamped to [1, 3N], N = max length.
+ *   - Every call returns an ej_status.  No C++ exception crosses the ABI.
+ *     On failure ej_last_error() describes the cause.
+ *   - "d_" pointers are device pointers on the context's device; device work
+ *     is enqueued on the context's stream.  Inputs are read-only and owned by
+ *     the caller; device inputs must stay valid until the stream has
+ *     finished the call.  Host inputs may be freed when the call returns.
+ */
+#ifndef EMBEDJOIN_H
+#define EMBEDJOIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EJ_OK = 0,
+    EJ_EINVAL = 1,      /* invalid argument (sizes, null pointers, offsets, r*z*m == 0 ...) */
+    EJ_EALPHABET = 2,   /* byte outside the index alphabet, or a 256-symbol alphabet */
+    EJ_ENOMEM = 3,      /* host or device allocation failed, or HBM admission refused */
+    EJ_ECAPACITY = 4,   /* caller buffer too small; the required count was written */
+    EJ_EHIP = 5,        /* a HIP runtime call failed */
+    EJ_EUNSUPPORTED = 6 /* parameters outside what the kernels implement (see each call) */
+} ej_status;
+
+/* Flags of ej_params.flags */
+#define EJ_FLAG_PLAIN 0u   /* one launch per stage, host-sized buffers */
+#define EJ_FLAG_GRAPH 1u   /* batched form: stages A1-A6 replayed from a captured HIP graph */
+#define EJ_FLAG_TIMING 2u  /* record per-stage device times in ej_result */
+
+typedef struct ej_ctx ej_ctx;
+
+typedef struct {
+    uint32_t K;      /* edit-distance threshold */
+    uint32_t r;      /* number of CGK embeddings (seeds) per string */
+    uint32_t z;      /* LSH functions per embedding */
+    uint32_t m;      /* coordinates per LSH function (signature length) */
+    uint32_t L;      /* truncation length, 0 = ceil(average length) */
+    uint32_t flags;  /* EJ_FLAG_* */
+    uint64_t seed;   /* seed of the counter-based random streams */
+} ej_params;
+
+typedef struct {
+    uint64_t count;        /* number of output pairs */
+    uint32_t *pairs;       /* host, [count][2], i < j, sorted lexicographically */
+    int32_t *dist;         /* host, [count], the edit distance of each pair (<= K) */
+    uint64_t n_candidates; /* |C|: de-duplicated candidate pairs that were verified */
+    uint64_t n_raw;        /* candidate pairs before de-duplication across tables */
+    uint32_t sigma;        /* alphabet size */
+    uint32_t L;            /* truncation length used */
+    float ms_prep, ms_embed, ms_bucket, ms_candidates, ms_verify, ms_output; /* EJ_FLAG_TIMING */
+} ej_result;
+
+/* ---------------------------------------------------------------- lifecycle */
+
+/* Creates a context on `device`.  hip_stream (a hipStream_t) may be NULL: the
+ * context then creates its own stream.  The context owns a grow-only device
+ * workspace that is reused across calls. */
+ej_status ej_create(ej_ctx **ctx, int device, void *hip_stream);
+void ej_destroy(ej_ctx *ctx);
+const char *ej_last_error(const ej_ctx *ctx);
+/* Library version as major*10000 + minor*100 + patch. */
+int ej_version(void);
+/* Bytes of device workspace the context currently holds. */
+uint64_t ej_workspace_bytes(const ej_ctx *ctx);
+
+/* ------------------------------------------------------------- end to end */
+
+/* EmbedJoin self-join (Algorithm 3 with Algorithm 2 as preprocessing) of the
+ * host strings `strings`/`offsets` (n strings) with threshold K and
+ * parameters r, z, m, the given seed and the default truncation.  The
+ * library allocates out->pairs and out->dist (free with ej_result_free).
+ * Errors: EJ_EINVAL (n >= 2^31, r*z*m == 0, m > 64, r*z > 4096,
+ * non-monotone offsets, a string longer than 2^31 - 1), EJ_EALPHABET (all
+ * 256 byte values present), EJ_EUNSUPPORTED (K > 1022), EJ_ENOMEM, EJ_EHIP. */
+ej_status ej_join(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                  uint32_t K, uint32_t r, uint32_t z, uint32_t m, uint64_t seed,
+                  ej_result *out);
+
+/* As ej_join with every parameter of ej_params (L, flags). */
+ej_status ej_join_ex(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                     const ej_params *p, ej_result *out);
+
+/* As ej_join_ex with the strings already in device memory (d_offsets holds
+ * n+1 absolute offsets into d_chars).  Results are still returned in host
+ * memory.  This is the form whose time excludes the host-to-device copy. */
+ej_status ej_join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                         uint32_t n, const ej_params *p, ej_result *out);
+
+void ej_result_free(ej_result *res);
+
+/* --------------------------------------------------------- stage entry points
+ * Each stage can be called on its own; ej_join chains the same kernels.
+ * Sizes that depend on the data are returned in host memory, so these calls
+ * synchronise the context stream before returning. */
+
+/* A1-A2: CGK embedding of every string under r seeds (Algorithm 1 truncated
+ * to L, Section 4.1), sampling of the z*m LSH coordinates of each seed
+ * (Section 4, sparse embedding) and the two-level hash (Section 4).
+ *   d_keys [r*z][n] uint64  key of string i in table l*z + j (input order)
+ *   d_sig  [n][r][z][m] uint8 sampled symbol codes, or NULL
+ * *L_used and *sigma receive the truncation length and alphabet size. */
+ej_status ej_embed(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                   const ej_params *p, uint8_t *d_sig, uint64_t *d_keys, uint32_t *L_used,
+                   uint32_t *sigma);
+
+/* A3: bucketing (the hash tables D_j^l of Algorithm 3).  Each of the
+ * `ntables` tables (keys laid out [ntables][n]) is sorted by (the top
+ * `key_bits` bits of the key, string length, position) with a stable
+ * on-device LSD radix sort; key_bits in 1..32, 0 picks the default.
+ * Entries whose top key bits agree form a group; a group contains one or
+ * more whole buckets (distinct full keys sharing their top bits are rare
+ * and are told apart by ej_candidates).
+ *   d_len          [n] uint32 string lengths
+ *   d_ids_sorted   [ntables][n] uint32 positions in sorted order
+ *   d_group_start  capacity ntables*n + 1 uint32: index (into the
+ *                  [ntables*n] sorted array) where each group starts, with
+ *                  a final entry ntables*n
+ *   *ngroups       number of groups */
+ej_status ej_lsh_bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, uint32_t n,
+                        uint32_t ntables, uint32_t key_bits, uint32_t *d_ids_sorted,
+                        uint32_t *d_group_start, uint64_t *ngroups);
+
+/* A4: candidate pairs (Algorithm 3, with the sliding-window length test and
+ * the de-duplication across tables): every pair of positions that share a
+ * full key in some table and whose lengths differ by at most K, once.
+ *   d_pairs   capacity `capacity` uint64 codes (i << 32) | j, i < j, sorted
+ *   *count    number of candidates; if it exceeds `capacity` nothing is
+ *             written to d_pairs and EJ_ECAPACITY is returned
+ *   *n_raw    pairs found before de-duplication (may be NULL) */
+ej_status ej_candidates(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_ids_sorted,
+                        const uint32_t *d_group_start, uint64_t ngroups, const uint32_t *d_len,
+                        uint32_t n, uint32_t ntables, uint32_t K, uint64_t *d_pairs,
+                        uint64_t capacity, uint64_t *count, uint64_t *n_raw);
+
+/* A5: threshold edit distance (Section 3.3) of each pair, with a
+ * bit-parallel banded kernel: d_dist[k] = ED(s_a, s_b) if it is <= K_k,
+ * else K_k + 1, where K_k = d_Kq[k] when d_Kq is not NULL and K otherwise.
+ * Pairs are uint64 codes (a << 32) | b.  EJ_EUNSUPPORTED if a threshold
+ * exceeds 1022. */
+ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                    const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
+                    int32_t *d_dist);
+
+/* Test hook: replace the drawn randomness of the next calls by explicit
+ * values (host arrays): Rbits [r][L*sigma] 0/1 bytes (pi_j(sigma_k) at
+ * (j-1)*sigma + k-1), pos [r][z][m] coordinates < L, v [r][z][m] values
+ * < 2^61-1 or NULL (then v is drawn from the seed).  The values apply only
+ * to calls with the same r, z, m, L and alphabet size.  Passing Rbits ==
+ * NULL clears the override. */
+ej_status ej_set_explicit_randomness(ej_ctx *ctx, uint32_t r, uint32_t z, uint32_t m,
+                                     uint32_t L, uint32_t sigma, const uint8_t *Rbits,
+                                     const uint32_t *pos, const uint64_t *v);
+
+/* ------------------------------------------------------------------ serving
+ * A device-resident LSH index over a fixed collection (the embedding and
+ * bucketing stages run once at build time; queries are embedded with the
+ * same random streams, truncation and alphabet).  Result of query q: the
+ * index positions s that share a full key with q in some table, satisfy
+ * ||q| - |s|| <= K_q and ED(q, s) <= K_q, sorted by position. */
+typedef struct ej_index ej_index;
+
+typedef struct {
+    uint32_t nq;
+    uint64_t *offsets;     /* host, [nq+1]: results of query q are [offsets[q], offsets[q+1]) */
+    uint32_t *ids;         /* host, index positions */
+    int32_t *dist;         /* host, edit distances */
+    uint64_t n_candidates; /* (query, index) pairs verified */
+    float ms_total;        /* device time of the batch */
+} ej_qresult;
+
+/* Builds the index from host (on_device = 0) or device (1) strings.  p->K is
+ * ignored (thresholds come per query); p->L = 0 picks ceil(average length). */
+ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                         const ej_params *p, int on_device, ej_index **index);
+/* Answers nq queries (host strings) with per-query thresholds Kq (host).
+ * EJ_EALPHABET if a query byte is outside the index alphabet; EJ_ENOMEM if
+ * the batch's workspace estimate exceeds the free HBM (or the admission
+ * limit set with ej_index_set_hbm_limit). */
+ej_status ej_query_batch(ej_index *index, const uint8_t *q, const uint64_t *q_offsets,
+                         uint32_t nq, const uint32_t *Kq, ej_qresult *out);
+/* Bytes of device memory the batch would need (admission estimate). */
+uint64_t ej_query_workspace_estimate(const ej_index *index, const uint64_t *q_offsets,
+                                     uint32_t nq, const uint32_t *Kq);
+/* Caps the HBM the index may use for a batch (0 = free HBM reported by HIP). */
+void ej_index_set_hbm_limit(ej_index *index, uint64_t bytes);
+uint32_t ej_index_size(const ej_index *index);
+void ej_qresult_free(ej_qresult *res);
+void ej_index_free(ej_index *index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EMBEDJOIN_H */

@@ -463,15 +463,18 @@ void ejo_verify_pairs(const uint8_t *chars, const uint64_t *offsets, const uint6
     }
 }
 
-/* Exact join by brute force: every pair, full Wagner-Fischer.  Writes at
- * most `cap` pairs, returns the total count. */
+/* Exact join by brute force: every pair; full Wagner-Fischer when `full` is
+ * set, else Ukkonen's threshold DP (same answer for ED <= K).  Writes at most
+ * `cap` pairs, returns the total count. */
 uint64_t ejo_brute_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
-                        uint64_t *out, uint32_t *dist, uint64_t cap) {
+                        uint64_t *out, uint32_t *dist, uint64_t cap, int full) {
     uint64_t cnt = 0;
     for (uint32_t a = 0; a < n; a++) {
         for (uint32_t c = a + 1; c < n; c++) {
-            uint32_t d = ejo_ed_full(chars + offsets[a], (uint32_t)(offsets[a + 1] - offsets[a]),
-                                     chars + offsets[c], (uint32_t)(offsets[c + 1] - offsets[c]));
+            const uint8_t *xa = chars + offsets[a], *xc = chars + offsets[c];
+            uint32_t la = (uint32_t)(offsets[a + 1] - offsets[a]);
+            uint32_t lc = (uint32_t)(offsets[c + 1] - offsets[c]);
+            uint32_t d = full ? ejo_ed_full(xa, la, xc, lc) : ejo_ed_banded(xa, la, xc, lc, K);
             if (d <= K) {
                 if (cnt < cap) {
                     out[cnt] = ((uint64_t)a << 32) | c;

@@ -88,7 +88,7 @@ def lib():
         L.ejo_verify_pairs.argtypes = [u8p, u64p, u64p, ctypes.c_uint64, ctypes.c_uint32, u32p]
         L.ejo_brute_join.restype = ctypes.c_uint64
         L.ejo_brute_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
-                                     u64p, u32p, ctypes.c_uint64]
+                                     u64p, u32p, ctypes.c_uint64, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -241,8 +241,9 @@ def verify_pairs(chars, offsets, pairs, K: int) -> np.ndarray:
     return d[:p.shape[0]]
 
 
-def brute_join(chars, offsets, K: int):
-    """Exact join: (pairs[i<j] as uint64 codes, dist)."""
+def brute_join(chars, offsets, K: int, full: bool = False):
+    """Exact join over all pairs: (pairs[i<j] as uint64 codes, dist).  full=True
+    uses textbook Wagner-Fischer, else Ukkonen's threshold DP."""
     c = _u8(chars)
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     n = off.shape[0] - 1
@@ -252,7 +253,8 @@ def brute_join(chars, offsets, K: int):
         d = np.zeros(cap, dtype=np.uint32)
         cnt = int(lib().ejo_brute_join(_ptr(c, ctypes.c_uint8) if c.size else None,
                                        _ptr(off, ctypes.c_uint64), n, K,
-                                       _ptr(out, ctypes.c_uint64), _ptr(d, ctypes.c_uint32), cap))
+                                       _ptr(out, ctypes.c_uint64), _ptr(d, ctypes.c_uint32), cap,
+                                       1 if full else 0))
         if cnt <= cap:
             return out[:cnt], d[:cnt]
         cap = cnt

@@ -1,0 +1,309 @@
+"""MI355X (gfx950) implementation of the EmbedJoin hot path.
+
+Thin ctypes binding over ``libembedjoin.so`` (C ABI in ``include/embedjoin.h``).
+Every step of the join runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch provides device memory and streams.  Importing
+works without a GPU, but every call needs the built library and a device: a
+missing library raises ``ImportError`` when the first call is made -- there is
+no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libembedjoin.so")
+
+EJ_OK, EJ_EINVAL, EJ_EALPHABET, EJ_ENOMEM, EJ_ECAPACITY, EJ_EHIP, EJ_EUNSUPPORTED = range(7)
+STATUS_NAMES = {0: "EJ_OK", 1: "EJ_EINVAL", 2: "EJ_EALPHABET", 3: "EJ_ENOMEM",
+                4: "EJ_ECAPACITY", 5: "EJ_EHIP", 6: "EJ_EUNSUPPORTED"}
+FLAG_PLAIN, FLAG_GRAPH, FLAG_TIMING = 0, 1, 2
+
+# Every symbol declared in include/embedjoin.h.
+EXPORTS = [
+    "ej_create", "ej_destroy", "ej_last_error", "ej_version", "ej_workspace_bytes",
+    "ej_join", "ej_join_ex", "ej_join_device", "ej_result_free",
+    "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_set_explicit_randomness",
+    "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
+    "ej_index_size", "ej_qresult_free", "ej_index_free",
+]
+
+
+class EmbedJoinError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_uint32), ("r", ctypes.c_uint32), ("z", ctypes.c_uint32),
+                ("m", ctypes.c_uint32), ("L", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("seed", ctypes.c_uint64)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_uint64), ("pairs", ctypes.POINTER(ctypes.c_uint32)),
+                ("dist", ctypes.POINTER(ctypes.c_int32)), ("n_candidates", ctypes.c_uint64),
+                ("n_raw", ctypes.c_uint64), ("sigma", ctypes.c_uint32), ("L", ctypes.c_uint32),
+                ("ms_prep", ctypes.c_float), ("ms_embed", ctypes.c_float),
+                ("ms_bucket", ctypes.c_float), ("ms_candidates", ctypes.c_float),
+                ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float)]
+
+
+class _QResult(ctypes.Structure):
+    _fields_ = [("nq", ctypes.c_uint32), ("offsets", ctypes.POINTER(ctypes.c_uint64)),
+                ("ids", ctypes.POINTER(ctypes.c_uint32)), ("dist", ctypes.POINTER(ctypes.c_int32)),
+                ("n_candidates", ctypes.c_uint64), ("ms_total", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libembedjoin.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1702_00093_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u8p, u32p, u64p, i32p = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint8),
+                                 ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint64),
+                                 ctypes.POINTER(ctypes.c_int32))
+    u32, u64, c_int = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    sig = {
+        "ej_create": (c_int, [ctypes.POINTER(vp), c_int, vp]),
+        "ej_destroy": (None, [vp]),
+        "ej_last_error": (ctypes.c_char_p, [vp]),
+        "ej_version": (c_int, []),
+        "ej_workspace_bytes": (u64, [vp]),
+        "ej_join": (c_int, [vp, vp, vp, u32, u32, u32, u32, u32, u64, ctypes.POINTER(_Result)]),
+        "ej_join_ex": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), ctypes.POINTER(_Result)]),
+        "ej_join_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params),
+                                   ctypes.POINTER(_Result)]),
+        "ej_result_free": (None, [ctypes.POINTER(_Result)]),
+        "ej_embed": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), vp, vp, u32p, u32p]),
+        "ej_lsh_bucket": (c_int, [vp, vp, vp, u32, u32, u32, vp, vp, u64p]),
+        "ej_candidates": (c_int, [vp, vp, vp, vp, u64, vp, u32, u32, u32, vp, u64, u64p, u64p]),
+        "ej_verify": (c_int, [vp, vp, vp, u32, vp, u64, u32, vp, vp]),
+        "ej_set_explicit_randomness": (c_int, [vp, u32, u32, u32, u32, u32, vp, vp, vp]),
+        "ej_index_build": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), c_int,
+                                   ctypes.POINTER(vp)]),
+        "ej_query_batch": (c_int, [vp, vp, vp, u32, vp, ctypes.POINTER(_QResult)]),
+        "ej_query_workspace_estimate": (u64, [vp, vp, u32, vp]),
+        "ej_index_set_hbm_limit": (None, [vp, u64]),
+        "ej_index_size": (u32, [vp]),
+        "ej_qresult_free": (None, [ctypes.POINTER(_QResult)]),
+        "ej_index_free": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------- helpers --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(x):
+    """Address of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def _host_u8(chars) -> np.ndarray:
+    if isinstance(chars, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(chars), dtype=np.uint8)
+    if hasattr(chars, "detach"):
+        chars = chars.detach().cpu().numpy()
+    return np.ascontiguousarray(chars, dtype=np.uint8)
+
+
+def _host_u64(offsets) -> np.ndarray:
+    if hasattr(offsets, "detach"):
+        offsets = offsets.detach().cpu().numpy()
+    return np.ascontiguousarray(offsets, dtype=np.uint64)
+
+
+def _is_device(x) -> bool:
+    return hasattr(x, "is_cuda") and x.is_cuda
+
+
+@dataclass
+class JoinResult:
+    pairs: np.ndarray          # [count, 2] int64, i < j, sorted
+    dist: np.ndarray           # [count] int32
+    n_candidates: int
+    n_raw: int
+    sigma: int
+    L: int
+    ms: dict
+
+    @property
+    def codes(self) -> np.ndarray:
+        return (self.pairs[:, 0].astype(np.uint64) << np.uint64(32)) | \
+            self.pairs[:, 1].astype(np.uint64)
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        L = lib()
+        self._h = ctypes.c_void_p()
+        st = L.ej_create(ctypes.byref(self._h), device, stream)
+        if st != EJ_OK:
+            raise EmbedJoinError(st, "ej_create failed")
+        self.device = device
+
+    def close(self):
+        if self._h:
+            lib().ej_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != EJ_OK:
+            msg = lib().ej_last_error(self._h)
+            raise EmbedJoinError(st, msg.decode() if msg else "")
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(lib().ej_workspace_bytes(self._h))
+
+    # ----------------------------------------------------------- the join --
+    def join(self, chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
+             flags: int = 0) -> JoinResult:
+        """EmbedJoin self-join.  Host inputs (bytes / numpy / CPU tensors) go
+        through ej_join_ex; CUDA tensors (uint8 chars, int64 offsets) go
+        through ej_join_device."""
+        p = Params(K, r, z, m, L, flags, seed)
+        res = _Result()
+        if _is_device(chars) or _is_device(offsets):
+            torch = _torch()
+            assert chars.dtype == torch.uint8 and offsets.dtype == torch.int64
+            assert chars.is_contiguous() and offsets.is_contiguous()
+            n = offsets.numel() - 1
+            st = lib().ej_join_device(self._h, _ptr(chars), _ptr(offsets), n, ctypes.byref(p),
+                                      ctypes.byref(res))
+        else:
+            c = _host_u8(chars)
+            o = _host_u64(offsets)
+            n = o.shape[0] - 1
+            st = lib().ej_join_ex(self._h, _ptr(c) if c.size else None, _ptr(o), n,
+                                  ctypes.byref(p), ctypes.byref(res))
+        self._check(st)
+        try:
+            cnt = int(res.count)
+            pairs = np.ctypeslib.as_array(res.pairs, (max(cnt, 1) * 2,))[:2 * cnt].copy() \
+                .reshape(cnt, 2).astype(np.int64)
+            dist = np.ctypeslib.as_array(res.dist, (max(cnt, 1),))[:cnt].copy()
+            ms = dict(prep=res.ms_prep, embed=res.ms_embed, bucket=res.ms_bucket,
+                      candidates=res.ms_candidates, verify=res.ms_verify, output=res.ms_output)
+            return JoinResult(pairs, dist, int(res.n_candidates), int(res.n_raw),
+                              int(res.sigma), int(res.L), ms)
+        finally:
+            lib().ej_result_free(ctypes.byref(res))
+
+    # ------------------------------------------------------------- stages --
+    def embed(self, d_chars, d_offsets, r: int, z: int, m: int, seed: int = 0, L: int = 0,
+              want_sig: bool = False):
+        """A1-A2 on device tensors.  Returns (keys [r*z, n] int64, sig [n, r, z, m] uint8 or
+        None, L_used, sigma)."""
+        torch = _torch()
+        n = d_offsets.numel() - 1
+        keys = torch.empty((r * z, max(n, 1)), dtype=torch.int64, device=d_offsets.device)
+        sig = torch.empty((max(n, 1), r, z, m), dtype=torch.uint8, device=d_offsets.device) \
+            if want_sig else None
+        p = Params(0, r, z, m, L, 0, seed)
+        Lu, sg = ctypes.c_uint32(), ctypes.c_uint32()
+        self._check(lib().ej_embed(self._h, _ptr(d_chars) if d_chars.numel() else None,
+                                   _ptr(d_offsets), n, ctypes.byref(p), _ptr(sig), _ptr(keys),
+                                   ctypes.byref(Lu), ctypes.byref(sg)))
+        return keys[:, :n], (sig[:n] if sig is not None else None), int(Lu.value), int(sg.value)
+
+    def lsh_bucket(self, d_keys, d_len, key_bits: int = 0):
+        """A3.  d_keys [T, n] int64, d_len [n] int32.  Returns (ids [T*n] int32,
+        group_start [ngroups+1] int32)."""
+        torch = _torch()
+        T, n = d_keys.shape
+        ids = torch.empty(max(T * n, 1), dtype=torch.int32, device=d_keys.device)
+        gs = torch.empty(T * n + 1, dtype=torch.int32, device=d_keys.device)
+        ng = ctypes.c_uint64()
+        self._check(lib().ej_lsh_bucket(self._h, _ptr(d_keys.contiguous()), _ptr(d_len), n, T,
+                                        key_bits, _ptr(ids), _ptr(gs), ctypes.byref(ng)))
+        return ids[:T * n], gs[:int(ng.value) + 1]
+
+    def candidates(self, d_keys, d_ids, d_group_start, d_len, K: int, capacity: int | None = None):
+        """A4.  Returns (pairs int64 codes (i << 32 | j), n_raw)."""
+        torch = _torch()
+        T, n = d_keys.shape
+        cap = capacity if capacity is not None else 1 << 20
+        while True:
+            out = torch.empty(max(cap, 1), dtype=torch.int64, device=d_keys.device)
+            cnt, raw = ctypes.c_uint64(), ctypes.c_uint64()
+            st = lib().ej_candidates(self._h, _ptr(d_keys.contiguous()), _ptr(d_ids),
+                                     _ptr(d_group_start), d_group_start.numel() - 1, _ptr(d_len),
+                                     n, T, K, _ptr(out), cap, ctypes.byref(cnt), ctypes.byref(raw))
+            if st == EJ_ECAPACITY and capacity is None:
+                cap = int(cnt.value)
+                continue
+            self._check(st)
+            return out[:int(cnt.value)], int(raw.value)
+
+    def verify(self, d_chars, d_offsets, d_pairs, K: int, d_Kq=None):
+        """A5.  Returns int32 distances, min(ED, K+1) per pair."""
+        torch = _torch()
+        n = d_offsets.numel() - 1
+        cnt = d_pairs.numel()
+        dist = torch.empty(max(cnt, 1), dtype=torch.int32, device=d_offsets.device)
+        self._check(lib().ej_verify(self._h, _ptr(d_chars) if d_chars.numel() else None,
+                                    _ptr(d_offsets), n, _ptr(d_pairs) if cnt else None, cnt, K,
+                                    _ptr(d_Kq), _ptr(dist)))
+        return dist[:cnt]
+
+    def set_explicit_randomness(self, r, z, m, L, sigma, Rbits=None, pos=None, v=None):
+        if Rbits is None:
+            self._check(lib().ej_set_explicit_randomness(self._h, 0, 0, 0, 0, 0, None, None, None))
+            return
+        R = np.ascontiguousarray(Rbits, dtype=np.uint8)
+        P = np.ascontiguousarray(pos, dtype=np.uint32)
+        V = None if v is None else np.ascontiguousarray(v, dtype=np.uint64)
+        self._check(lib().ej_set_explicit_randomness(self._h, r, z, m, L, sigma, _ptr(R), _ptr(P),
+                                                     _ptr(V)))
+
+
+_default: dict[int, Context] = {}
+
+
+def context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
+         flags: int = 0, device: int = 0) -> JoinResult:
+    return context(device).join(chars, offsets, K, r, z, m, seed=seed, L=L, flags=flags)
+
+
+def version() -> int:
+    return int(lib().ej_version())

@@ -1,0 +1,148 @@
+// Context, workspace and error plumbing of the C ABI.
+#include <string.h>
+
+#include <new>
+
+#include "ej_internal.h"
+
+namespace ej {
+
+void fail(ej_status code, const std::string &msg) { throw Error{code, msg}; }
+
+void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    DevBuf &b = ctx->ws[name];
+    if (b.bytes < bytes) {
+        if (b.p) {
+            EJ_HIP(hipStreamSynchronize(ctx->stream));
+            EJ_HIP(hipFree(b.p));
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        size_t want = bytes + bytes / 8 + 256;  // grow with headroom
+        hipError_t e = hipMalloc(&b.p, want);
+        if (e != hipSuccess) {
+            b.p = nullptr;
+            fail(EJ_ENOMEM, "device allocation of " + std::to_string(want) + " bytes for '" +
+                                name + "' failed: " + hipGetErrorString(e));
+        }
+        b.bytes = want;
+    }
+    return b.p;
+}
+
+void sync(ej_ctx *ctx) { EJ_HIP(hipStreamSynchronize(ctx->stream)); }
+
+void read_back(ej_ctx *ctx, const void *dsrc, size_t bytes, void *hdst) {
+    if (bytes > 4096) fail(EJ_EINVAL, "read_back larger than the pinned staging buffer");
+    EJ_HIP(hipMemcpyAsync(ctx->pinned, dsrc, bytes, hipMemcpyDeviceToHost, ctx->stream));
+    EJ_HIP(hipStreamSynchronize(ctx->stream));
+    memcpy(hdst, ctx->pinned, bytes);
+}
+
+}  // namespace ej
+
+using namespace ej;
+
+extern "C" {
+
+int ej_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+ej_status ej_create(ej_ctx **out, int device, void *hip_stream) {
+    if (!out) return EJ_EINVAL;
+    *out = nullptr;
+    ej_ctx *ctx = new (std::nothrow) ej_ctx();
+    if (!ctx) return EJ_ENOMEM;
+    try {
+        int ndev = 0;
+        EJ_HIP(hipGetDeviceCount(&ndev));
+        if (device < 0 || device >= ndev) fail(EJ_EINVAL, "no such device");
+        ctx->device = device;
+        EJ_HIP(hipSetDevice(device));
+        if (hip_stream) {
+            ctx->stream = (hipStream_t)hip_stream;
+            ctx->own_stream = false;
+        } else {
+            EJ_HIP(hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+            ctx->own_stream = true;
+        }
+        EJ_HIP(hipDeviceGetAttribute(&ctx->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+        int lds = 65536;
+        EJ_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+        ctx->lds_max = lds;
+        EJ_HIP(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
+        for (int i = 0; i < 8; i++) EJ_HIP(hipEventCreate(&ctx->timers.ev[i]));
+    } catch (const Error &e) {
+        ej_status c = e.code;
+        ej_destroy(ctx);
+        return c;
+    }
+    *out = ctx;
+    return EJ_OK;
+}
+
+void ej_destroy(ej_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->ws)
+        if (kv.second.p) (void)hipFree(kv.second.p);
+    ctx->ws.clear();
+    for (int i = 0; i < 8; i++)
+        if (ctx->timers.ev[i]) (void)hipEventDestroy(ctx->timers.ev[i]);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+}
+
+const char *ej_last_error(const ej_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+uint64_t ej_workspace_bytes(const ej_ctx *ctx) {
+    if (!ctx) return 0;
+    uint64_t s = 0;
+    for (auto &kv : ctx->ws) s += kv.second.bytes;
+    return s;
+}
+
+ej_status ej_set_explicit_randomness(ej_ctx *ctx, uint32_t r, uint32_t z, uint32_t m, uint32_t L,
+                                     uint32_t sigma, const uint8_t *Rbits, const uint32_t *pos,
+                                     const uint64_t *v) {
+    if (!ctx) return EJ_EINVAL;
+    try {
+        Explicit &ex = ctx->ex;
+        if (!Rbits) {
+            ex = Explicit();
+            return EJ_OK;
+        }
+        if (!pos || r == 0 || z == 0 || m == 0 || L == 0 || sigma == 0)
+            fail(EJ_EINVAL, "explicit randomness needs Rbits, pos and non-zero sizes");
+        uint64_t nbits = (uint64_t)L * sigma;
+        ex.r = r;
+        ex.z = z;
+        ex.m = m;
+        ex.L = L;
+        ex.sigma = sigma;
+        ex.nw = (uint32_t)((nbits + 31) / 32) + 2;
+        ex.Rwords.assign((size_t)r * ex.nw, 0u);
+        for (uint32_t l = 0; l < r; l++)
+            for (uint64_t b = 0; b < nbits; b++)
+                if (Rbits[l * nbits + b]) ex.Rwords[(size_t)l * ex.nw + b / 32] |= 1u << (b % 32);
+        ex.pos.assign(pos, pos + (size_t)r * z * m);
+        for (uint32_t x : ex.pos)
+            if (x >= L) fail(EJ_EINVAL, "explicit coordinate outside [0, L)");
+        if (v) {
+            ex.v.assign(v, v + (size_t)r * z * m);
+            for (uint64_t x : ex.v)
+                if (x >= P61) fail(EJ_EINVAL, "explicit v outside [0, 2^61-1)");
+        } else {
+            ex.v.clear();
+        }
+        ex.active = true;
+        return EJ_OK;
+    } catch (const Error &e) {
+        ctx->err = e.msg;
+        return e.code;
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,200 @@
+// Internal declarations shared by the translation units of libembedjoin.so.
+// Not part of the ABI (include/embedjoin.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "embedjoin.h"
+
+namespace ej {
+
+// ------------------------------------------------------------------ errors --
+struct Error {
+    ej_status code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(ej_status code, const std::string &msg);
+
+#define EJ_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            ::ej::fail(e_ == hipErrorOutOfMemory ? EJ_ENOMEM : EJ_EHIP,                  \
+                       std::string(#call) + ": " + hipGetErrorString(e_));               \
+    } while (0)
+
+#define EJ_CHECK_LAUNCH() EJ_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- constants --
+constexpr uint64_t P61 = (1ULL << 61) - 1ULL;
+constexpr uint64_t GAMMA = 0x9E3779B97F4A7C15ULL;
+constexpr uint32_t TAG_R = 0, TAG_POS = 1, TAG_V = 2;
+
+__host__ __device__ inline uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+// Word c of the SplitMix64 stream seeded with key (counter form).
+__host__ __device__ inline uint64_t rng_word(uint64_t key, uint64_t c) {
+    return mix64(key + (c + 1ULL) * GAMMA);
+}
+__host__ __device__ inline uint64_t stream_key(uint64_t seed, uint32_t tag, uint32_t idx) {
+    return rng_word(seed, ((uint64_t)tag << 32) | idx);
+}
+
+// Lane broadcasts.  The builtin returns a signed int; widen through uint32_t so
+// that 64-bit values (pointers, indices) are not sign-extended.
+__device__ inline uint32_t readlane_u32(uint32_t v, uint32_t lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)lane);
+}
+__device__ inline uint64_t readlane_u64(uint64_t v, uint32_t lane) {
+    return ((uint64_t)readlane_u32((uint32_t)(v >> 32), lane) << 32) |
+           (uint64_t)readlane_u32((uint32_t)v, lane);
+}
+
+// ---------------------------------------------------------------- context --
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Explicit {
+    bool active = false;
+    uint32_t r = 0, z = 0, m = 0, L = 0, sigma = 0;
+    std::vector<uint32_t> Rwords;  // [r][nw] packed bits
+    uint32_t nw = 0;
+    std::vector<uint32_t> pos;     // [r][z][m]
+    std::vector<uint64_t> v;       // [r][z][m] (empty: drawn)
+};
+
+struct Timers {
+    hipEvent_t ev[8] = {};
+    bool on = false;
+};
+
+}  // namespace ej
+
+struct ej_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::map<std::string, ej::DevBuf> ws;
+    ej::Explicit ex;
+    int num_cu = 256;
+    int lds_max = 65536;         // max dynamic LDS per workgroup
+    uint64_t *pinned = nullptr;  // small pinned host buffer for size read-backs
+    ej::Timers timers;
+};
+
+namespace ej {
+
+void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes);
+template <typename T>
+T *ws(ej_ctx *ctx, const std::string &name, size_t count) {
+    return (T *)ws_get(ctx, name, count * sizeof(T));
+}
+void sync(ej_ctx *ctx);
+// Copies `count` u64 words from device to host through the pinned buffer.
+void read_back(ej_ctx *ctx, const void *dsrc, size_t bytes, void *hdst);
+
+inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+inline uint32_t bits_for(uint64_t v) {  // bits needed to represent values 0..v
+    uint32_t b = 0;
+    while (b < 64 && (v >> b) != 0) b++;
+    return b;
+}
+
+// --------------------------------------------------------------- primitives --
+// Exclusive prefix sum of n values (in place allowed).  *d_total (device,
+// nullable) receives the sum.
+void scan_exclusive_u32(ej_ctx *ctx, const uint32_t *d_in, uint32_t *d_out, uint64_t n,
+                        uint64_t *d_total);
+void scan_exclusive_u64(ej_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, uint64_t n,
+                        uint64_t *d_total);
+
+// Stable LSD radix sort of `nseg` independent equal-length segments of
+// `seglen` entries, ordered by bits [0, key_bits) of the keys.  Values
+// (nullable) move with the keys.  Results end in the _out arrays; the _in
+// arrays are clobbered.  digit_bits in {4..11}.
+void radix_sort_u32(ej_ctx *ctx, uint32_t *keys_in, uint32_t *vals_in, uint32_t *keys_out,
+                    uint32_t *vals_out, uint32_t nseg, uint32_t seglen, uint32_t key_bits,
+                    uint32_t digit_bits);
+void radix_sort_u64(ej_ctx *ctx, uint64_t *keys_in, uint64_t *keys_out, uint64_t n,
+                    uint32_t key_bits, uint32_t digit_bits);
+
+// ------------------------------------------------------------------ stages --
+struct Prep {
+    uint32_t n = 0;
+    uint64_t base = 0;      // offsets[0]
+    uint64_t total = 0;     // total bytes
+    uint32_t maxlen = 0;
+    uint32_t sigma = 0;
+    uint8_t lut[256];
+    uint32_t L = 0;
+    uint32_t bw = 8;        // bits per packed code
+    const uint64_t *d_offsets = nullptr;
+    const uint8_t *d_chars = nullptr;
+    uint32_t *d_len = nullptr;      // [n]
+    uint8_t *d_codes = nullptr;     // [total] symbol codes, same layout as chars (base-relative)
+    uint32_t *d_packed = nullptr;   // packed codes, bw bits each, base-relative
+    uint32_t *d_perm = nullptr;     // [n] positions in (length, position) order
+};
+
+struct Rand {
+    uint32_t r = 0, z = 0, m = 0, L = 0, sigma = 0;
+    uint32_t S = 0;              // z*m samples per seed
+    uint32_t Lpad = 0;           // stride of Rstep rows
+    uint32_t nw = 0;             // stride of Rwords rows (u32)
+    uint32_t Jmax = 0;           // max over seeds of (last sampled step + 1)
+    uint32_t *d_Rwords = nullptr;  // [r][nw]
+    uint32_t *d_Rstep = nullptr;   // [r][Lpad] bits of step j (sigma <= 32)
+    uint32_t *d_pos = nullptr;     // [r][z][m]
+    uint64_t *d_v = nullptr;       // [r][z][m]
+    uint32_t *d_spos = nullptr;    // [r][S] sampled steps, ascending
+    uint32_t *d_sslot = nullptr;   // [r][S] slot (j*m + k) of each sample
+    uint32_t *d_J = nullptr;       // [r] last sampled step + 1
+};
+
+// Computes lengths, alphabet, truncation and encodings of a device string set.
+// If `fixed_alphabet` is non-null its 256-entry table (code or 0xFF) is used
+// and bytes outside it are an error.
+void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+             uint32_t L_req, Prep &pp, const char *tag, const uint8_t *fixed_lut = nullptr,
+             uint32_t fixed_sigma = 0, uint32_t fixed_L = 0, bool need_perm = true);
+void draw_randomness(ej_ctx *ctx, const ej_params &p, uint32_t L, uint32_t sigma, Rand &rd,
+                     const char *tag);
+void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, uint8_t *d_sig);
+
+struct Buckets {
+    uint32_t T = 0, n = 0;
+    uint32_t *d_ids = nullptr;        // [T*n]
+    uint32_t *d_gid = nullptr;        // [T*n] group id of each sorted entry
+    uint32_t *d_gstart = nullptr;     // [ngroups + 1]
+    uint64_t ngroups = 0;
+};
+void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
+            uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag);
+
+// Candidate pairs as packed codes (a << 32 | b), a < b, sorted and unique.
+// Returns the count; *n_raw gets the pre-dedup count.
+uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, const uint32_t *d_len,
+                    uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag);
+
+// Threshold edit distance of `count` pairs (codes a << 32 | b) over the
+// symbol codes of a string set.
+void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
+            uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
+            const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b = nullptr,
+            const uint64_t *d_offsets_b = nullptr, uint64_t base_b = 0, uint32_t maxlen_b = 0);
+
+uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported
+
+}  // namespace ej

@@ -1,0 +1,409 @@
+// End-to-end join (A0-A6) and the stage entry points of the C ABI.
+#include <stdlib.h>
+#include <string.h>
+
+#include "ej_internal.h"
+
+namespace ej {
+
+namespace {
+
+inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
+    uint64_t g = (work + block - 1) / block;
+    uint64_t cap = (uint64_t)ctx->num_cu * 16;
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return (uint32_t)g;
+}
+
+__global__ void k_out_flags(const int32_t *__restrict__ dist, uint64_t cnt, uint32_t K,
+                            uint32_t *__restrict__ flags) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        flags[e] = (dist[e] >= 0 && (uint32_t)dist[e] <= K) ? 1u : 0u;
+}
+
+__global__ void k_out_compact(const uint64_t *__restrict__ pairs, const int32_t *__restrict__ dist,
+                              uint64_t cnt, const uint32_t *__restrict__ flags,
+                              const uint32_t *__restrict__ pos, uint32_t *__restrict__ out_pairs,
+                              int32_t *__restrict__ out_dist) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        if (flags[e]) {
+            uint32_t p = pos[e];
+            uint64_t c = pairs[e];
+            out_pairs[2 * (uint64_t)p] = (uint32_t)(c >> 32);
+            out_pairs[2 * (uint64_t)p + 1] = (uint32_t)c;
+            out_dist[p] = dist[e];
+        }
+    }
+}
+
+__global__ void k_gid_from_starts(const uint32_t *__restrict__ gstart, uint64_t ngroups,
+                                  uint32_t *__restrict__ gid) {
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ngroups;
+         g += (uint64_t)gridDim.x * blockDim.x)
+        for (uint32_t e = gstart[g]; e < gstart[g + 1]; e++) gid[e] = (uint32_t)g;
+}
+
+__global__ void k_max_len_shim(const uint32_t *__restrict__ a, uint32_t n, uint32_t *__restrict__ out) {
+    uint32_t mx = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        mx = max(mx, a[i]);
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, mx);
+}
+
+__global__ void k_iota_shim(uint32_t *__restrict__ a, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        a[i] = i;
+}
+
+// Flags (bit 0) a pair whose positions are not below n_a / n_b.
+__global__ void k_check_pairs(const uint64_t *__restrict__ pairs, uint64_t cnt, uint32_t n_a,
+                              uint32_t n_b, uint32_t *__restrict__ bad) {
+    uint32_t b = 0;
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint64_t c = pairs[e];
+        if ((uint32_t)(c >> 32) >= n_a || (uint32_t)c >= n_b) b = 1;
+    }
+    if (b) atomicOr(bad, 1u);
+}
+
+// Flags group starts that are not increasing from 0 to tot.
+__global__ void k_check_groups(const uint32_t *__restrict__ gs, uint64_t ng, uint64_t tot,
+                               uint32_t *__restrict__ bad) {
+    uint32_t b = 0;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < ng;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        if (gs[g] >= gs[g + 1] || gs[g + 1] > tot) b = 1;
+        if (g == 0 && gs[0] != 0) b = 1;
+        if (g == ng - 1 && gs[ng] != tot) b = 1;
+    }
+    if (b) atomicOr(bad, 1u);
+}
+
+void check_params(const ej_params &p, uint32_t n) {
+    if (p.r == 0 || p.z == 0 || p.m == 0) fail(EJ_EINVAL, "r, z and m must be positive");
+    if (p.m > 64) fail(EJ_EINVAL, "m must be at most 64");
+    if ((uint64_t)p.r * p.z > 4096) fail(EJ_EINVAL, "r*z must be at most 4096");
+    if (n >= 0x80000000u) fail(EJ_EINVAL, "n must be below 2^31");
+    if (p.K > 0x7FFFFFFFu) fail(EJ_EINVAL, "K must be below 2^31");
+    if (verify_lanes_for(p.K) == 0) fail(EJ_EUNSUPPORTED, "K above 1022 is not supported");
+}
+
+struct StageTimer {
+    ej_ctx *ctx;
+    bool on;
+    int idx = 0;
+    explicit StageTimer(ej_ctx *c, bool o) : ctx(c), on(o) {}
+    void mark() {
+        if (on && idx < 8) EJ_HIP(hipEventRecord(ctx->timers.ev[idx++], ctx->stream));
+    }
+    float between(int a, int b) {
+        if (!on || b >= idx) return 0.f;
+        float ms = 0.f;
+        EJ_HIP(hipEventElapsedTime(&ms, ctx->timers.ev[a], ctx->timers.ev[b]));
+        return ms;
+    }
+};
+
+template <typename F>
+ej_status run_guarded(ej_ctx *ctx, F &&fn) {
+    if (!ctx) return EJ_EINVAL;
+    try {
+        EJ_HIP(hipSetDevice(ctx->device));
+        fn();
+        ctx->err.clear();
+        return EJ_OK;
+    } catch (const Error &e) {
+        ctx->err = e.msg;
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipGetLastError();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return EJ_ENOMEM;
+    }
+}
+
+}  // namespace
+
+// The whole path on device-resident strings.
+void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                 const ej_params &p, ej_result *out) {
+    check_params(p, n);
+    memset(out, 0, sizeof(*out));
+    StageTimer tm(ctx, (p.flags & EJ_FLAG_TIMING) != 0);
+    tm.mark();  // 0
+    Prep pp;
+    prepare(ctx, d_chars, d_offsets, n, p.L, pp, "j");
+    out->sigma = pp.sigma;
+    out->L = pp.L;
+    tm.mark();  // 1
+    Rand rd;
+    draw_randomness(ctx, p, pp.L, pp.sigma, rd, "j");
+    const uint32_t T = p.r * p.z;
+    uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
+    embed_keys(ctx, pp, rd, keys, nullptr);
+    tm.mark();  // 2
+    Buckets bk;
+    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, 32, bk, "j");
+    tm.mark();  // 3
+    uint64_t *pairs = nullptr;
+    uint64_t raw = 0;
+    uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j");
+    out->n_candidates = cnt;
+    out->n_raw = raw;
+    tm.mark();  // 4
+    int32_t *dist = ws<int32_t>(ctx, "j_dist", cnt);
+    verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, pairs, cnt, p.K, nullptr,
+           dist);
+    tm.mark();  // 5
+    uint64_t nout = 0;
+    uint32_t *opairs = nullptr;
+    int32_t *odist = nullptr;
+    if (cnt) {
+        uint32_t *flags = ws<uint32_t>(ctx, "j_oflags", cnt);
+        uint32_t *pos = ws<uint32_t>(ctx, "j_opos", cnt);
+        uint64_t *d_no = ws<uint64_t>(ctx, "j_nout", 1);
+        hipLaunchKernelGGL(k_out_flags, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
+                           (const int32_t *)dist, cnt, p.K, flags);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, flags, pos, cnt, d_no);
+        read_back(ctx, d_no, 8, &nout);
+        opairs = ws<uint32_t>(ctx, "j_opairs", 2 * nout);
+        odist = ws<int32_t>(ctx, "j_odist", nout);
+        hipLaunchKernelGGL(k_out_compact, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
+                           (const uint64_t *)pairs, (const int32_t *)dist, cnt,
+                           (const uint32_t *)flags, (const uint32_t *)pos, opairs, odist);
+        EJ_CHECK_LAUNCH();
+    }
+    out->count = nout;
+    out->pairs = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (nout ? nout : 1));
+    out->dist = (int32_t *)malloc(sizeof(int32_t) * (nout ? nout : 1));
+    if (!out->pairs || !out->dist) {
+        free(out->pairs);
+        free(out->dist);
+        out->pairs = nullptr;
+        out->dist = nullptr;
+        fail(EJ_ENOMEM, "host allocation of the result failed");
+    }
+    if (nout) {
+        EJ_HIP(hipMemcpyAsync(out->pairs, opairs, sizeof(uint32_t) * 2 * nout,
+                              hipMemcpyDeviceToHost, ctx->stream));
+        EJ_HIP(hipMemcpyAsync(out->dist, odist, sizeof(int32_t) * nout, hipMemcpyDeviceToHost,
+                              ctx->stream));
+    }
+    tm.mark();  // 6
+    sync(ctx);
+    out->ms_prep = tm.between(0, 1);
+    out->ms_embed = tm.between(1, 2);
+    out->ms_bucket = tm.between(2, 3);
+    out->ms_candidates = tm.between(3, 4);
+    out->ms_verify = tm.between(4, 5);
+    out->ms_output = tm.between(5, 6);
+}
+
+}  // namespace ej
+
+using namespace ej;
+
+namespace {
+
+struct HostInput {
+    uint8_t *d_chars = nullptr;
+    uint64_t *d_offsets = nullptr;
+};
+
+// Copies host strings into the context workspace (offsets rebased to 0).
+HostInput upload(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                 const char *tag) {
+    if (!offsets) fail(EJ_EINVAL, "null offsets");
+    for (uint32_t i = 0; i < n; i++)
+        if (offsets[i + 1] < offsets[i]) fail(EJ_EINVAL, "offsets are not non-decreasing");
+    uint64_t base = offsets[0], total = offsets[n] - offsets[0];
+    if (total && !strings) fail(EJ_EINVAL, "null strings");
+    HostInput h;
+    std::string t(tag);
+    h.d_chars = ws<uint8_t>(ctx, t + "_hchars", total + 16);
+    h.d_offsets = ws<uint64_t>(ctx, t + "_hoffsets", (uint64_t)n + 1);
+    std::vector<uint64_t> rebased(offsets, offsets + n + 1);
+    for (auto &o : rebased) o -= base;
+    if (total)
+        EJ_HIP(hipMemcpyAsync(h.d_chars, strings + base, total, hipMemcpyHostToDevice, ctx->stream));
+    EJ_HIP(hipMemcpyAsync(h.d_offsets, rebased.data(), sizeof(uint64_t) * (n + 1),
+                          hipMemcpyHostToDevice, ctx->stream));
+    sync(ctx);  // the rebased vector is pageable and local
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+ej_status ej_join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                         const ej_params *p, ej_result *out) {
+    if (!p || !out || !d_offsets) return EJ_EINVAL;
+    return run_guarded(ctx, [&] { join_device(ctx, d_chars, d_offsets, n, *p, out); });
+}
+
+ej_status ej_join_ex(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                     const ej_params *p, ej_result *out) {
+    if (!p || !out) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        check_params(*p, n);
+        HostInput h = upload(ctx, strings, offsets, n, "in");
+        join_device(ctx, h.d_chars, h.d_offsets, n, *p, out);
+    });
+}
+
+ej_status ej_join(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                  uint32_t K, uint32_t r, uint32_t z, uint32_t m, uint64_t seed, ej_result *out) {
+    ej_params p;
+    memset(&p, 0, sizeof(p));
+    p.K = K;
+    p.r = r;
+    p.z = z;
+    p.m = m;
+    p.seed = seed;
+    return ej_join_ex(ctx, strings, offsets, n, &p, out);
+}
+
+void ej_result_free(ej_result *res) {
+    if (!res) return;
+    free(res->pairs);
+    free(res->dist);
+    res->pairs = nullptr;
+    res->dist = nullptr;
+    res->count = 0;
+}
+
+ej_status ej_embed(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                   const ej_params *p, uint8_t *d_sig, uint64_t *d_keys, uint32_t *L_used,
+                   uint32_t *sigma) {
+    if (!p || !d_offsets || (n && !d_keys)) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        ej_params q = *p;
+        q.K = 0;
+        check_params(q, n);
+        Prep pp;
+        prepare(ctx, d_chars, d_offsets, n, p->L, pp, "e");
+        Rand rd;
+        draw_randomness(ctx, *p, pp.L, pp.sigma, rd, "e");
+        embed_keys(ctx, pp, rd, d_keys, d_sig);
+        sync(ctx);
+        if (L_used) *L_used = pp.L;
+        if (sigma) *sigma = pp.sigma;
+    });
+}
+
+ej_status ej_lsh_bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, uint32_t n,
+                        uint32_t ntables, uint32_t key_bits, uint32_t *d_ids_sorted,
+                        uint32_t *d_group_start, uint64_t *ngroups) {
+    if (!ngroups || (n && (!d_keys || !d_len || !d_ids_sorted || !d_group_start)))
+        return EJ_EINVAL;
+    if (key_bits > 32) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        // length order of the strings, as Algorithm 2 sorts them
+        uint32_t maxlen = 0;
+        uint32_t *perm = ws<uint32_t>(ctx, "b_perm", n + 1);
+        if (n) {
+            uint32_t *d_mx = ws<uint32_t>(ctx, "b_maxlen", 1);
+            EJ_HIP(hipMemsetAsync(d_mx, 0, 4, ctx->stream));
+            hipLaunchKernelGGL(k_max_len_shim, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
+                               d_len, n, d_mx);
+            EJ_CHECK_LAUNCH();
+            read_back(ctx, d_mx, 4, &maxlen);
+            uint32_t *lk = ws<uint32_t>(ctx, "b_lk", n), *lk2 = ws<uint32_t>(ctx, "b_lk2", n);
+            uint32_t *iota = ws<uint32_t>(ctx, "b_iota", n);
+            EJ_HIP(hipMemcpyAsync(lk, d_len, 4ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+            hipLaunchKernelGGL(k_iota_shim, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
+                               iota, n);
+            EJ_CHECK_LAUNCH();
+            radix_sort_u32(ctx, lk, iota, lk2, perm, 1, n, bits_for(maxlen), 8);
+        }
+        Buckets bk;
+        bucket(ctx, d_keys, d_len, perm, n, ntables, key_bits, bk, "b");
+        uint64_t tot = (uint64_t)ntables * n;
+        if (tot)
+            EJ_HIP(hipMemcpyAsync(d_ids_sorted, bk.d_ids, 4 * tot, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+        EJ_HIP(hipMemcpyAsync(d_group_start, bk.d_gstart, 4 * (bk.ngroups + 1),
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        sync(ctx);
+        *ngroups = bk.ngroups;
+    });
+}
+
+ej_status ej_candidates(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_ids_sorted,
+                        const uint32_t *d_group_start, uint64_t ngroups, const uint32_t *d_len,
+                        uint32_t n, uint32_t ntables, uint32_t K, uint64_t *d_pairs,
+                        uint64_t capacity, uint64_t *count, uint64_t *n_raw) {
+    if (!count) return EJ_EINVAL;
+    if ((uint64_t)ntables * n && (!d_keys || !d_ids_sorted || !d_group_start || !d_len))
+        return EJ_EINVAL;
+    ej_status st = run_guarded(ctx, [&] {
+        Buckets bk;
+        bk.T = ntables;
+        bk.n = n;
+        bk.ngroups = ngroups;
+        bk.d_ids = const_cast<uint32_t *>(d_ids_sorted);
+        bk.d_gstart = const_cast<uint32_t *>(d_group_start);
+        uint64_t tot = (uint64_t)ntables * n;
+        if ((ngroups == 0) != (tot == 0) || ngroups > tot) fail(EJ_EINVAL, "inconsistent group count");
+        if (ngroups) {
+            uint32_t *d_bad = ws<uint32_t>(ctx, "c_bad", 1);
+            EJ_HIP(hipMemsetAsync(d_bad, 0, 4, ctx->stream));
+            hipLaunchKernelGGL(k_check_groups, dim3(grid_for(ctx, ngroups, 256)), dim3(256), 0,
+                               ctx->stream, d_group_start, ngroups, tot, d_bad);
+            EJ_CHECK_LAUNCH();
+            uint32_t bad = 0;
+            read_back(ctx, d_bad, 4, &bad);
+            if (bad) fail(EJ_EINVAL, "group starts are not increasing from 0 to ntables*n");
+        }
+        bk.d_gid = ws<uint32_t>(ctx, "c_gid", tot + 1);
+        if (ngroups)
+            hipLaunchKernelGGL(k_gid_from_starts, dim3(grid_for(ctx, ngroups, 256)), dim3(256), 0,
+                               ctx->stream, d_group_start, ngroups, bk.d_gid);
+        EJ_CHECK_LAUNCH();
+        uint64_t *pairs = nullptr;
+        uint64_t raw = 0;
+        uint64_t cnt = candidates(ctx, d_keys, bk, d_len, K, &pairs, &raw, "c");
+        *count = cnt;
+        if (n_raw) *n_raw = raw;
+        if (cnt > capacity) fail(EJ_ECAPACITY, "candidate buffer too small");
+        if (cnt)
+            EJ_HIP(hipMemcpyAsync(d_pairs, pairs, 8 * cnt, hipMemcpyDeviceToDevice, ctx->stream));
+        sync(ctx);
+    });
+    return st;
+}
+
+ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                    const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
+                    int32_t *d_dist) {
+    if (!d_offsets || (count && (!d_pairs || !d_dist))) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        if (!d_Kq && verify_lanes_for(K) == 0)
+            fail(EJ_EUNSUPPORTED, "K above 1022 is not supported");
+        Prep pp;
+        prepare(ctx, d_chars, d_offsets, n, 0, pp, "v", nullptr, 0, 0, false);
+        if (count) {
+            uint32_t *d_bad = ws<uint32_t>(ctx, "v_bad", 1);
+            EJ_HIP(hipMemsetAsync(d_bad, 0, 4, ctx->stream));
+            hipLaunchKernelGGL(k_check_pairs, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
+                               ctx->stream, d_pairs, count, n, n, d_bad);
+            EJ_CHECK_LAUNCH();
+            uint32_t bad = 0;
+            read_back(ctx, d_bad, 4, &bad);
+            if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
+        }
+        verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, d_pairs, count, K, d_Kq,
+               d_dist);
+        sync(ctx);
+    });
+}
+
+}  // extern "C"

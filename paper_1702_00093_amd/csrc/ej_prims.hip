@@ -1,0 +1,307 @@
+// Device-wide primitives used by the stages: exclusive prefix sums and a
+// stable, segmented LSD radix sort.  Both are written for 64-lane waves:
+// wave-level steps use ballots and DPP-backed shuffles, block-level steps
+// combine the waves of a 256-thread workgroup through LDS.
+#include "ej_internal.h"
+
+namespace ej {
+
+namespace {
+
+constexpr int BLK = 256;            // threads per workgroup (4 waves)
+constexpr int NWAVE = BLK / 64;
+constexpr int IPT = 8;              // items per thread
+constexpr int TILE = BLK * IPT;     // items per workgroup tile
+
+template <typename T>
+__device__ inline T wave_inclusive_scan(T x, uint32_t lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    return x;
+}
+
+// Exclusive scan of one value per thread across the workgroup.
+template <typename T>
+__device__ inline T block_exclusive_scan(T v, T *lds, T &total) {
+    uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T x = wave_inclusive_scan(v, lane);
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    T before = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < NWAVE; w++) {
+        T s = lds[w];
+        if (w < (int)wave) before += s;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return before + x - v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLK) k_scan_reduce(const T *__restrict__ in, uint64_t n,
+                                                     T *__restrict__ partials) {
+    __shared__ T lds[NWAVE];
+    uint64_t base = (uint64_t)blockIdx.x * TILE;
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        uint64_t e = base + (uint64_t)i * BLK + threadIdx.x;
+        if (e < n) s += in[e];
+    }
+    T total;
+    block_exclusive_scan(s, lds, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+// Single workgroup: exclusive scan of the per-tile partial sums.
+template <typename T>
+__global__ void __launch_bounds__(BLK) k_scan_partials(T *__restrict__ partials, uint64_t nb,
+                                                       uint64_t *__restrict__ total_out) {
+    __shared__ T lds[NWAVE];
+    T carry = 0;
+    for (uint64_t base = 0; base < nb; base += TILE) {
+        T v[IPT];
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < IPT; i++) {
+            uint64_t e = base + (uint64_t)threadIdx.x * IPT + i;
+            v[i] = e < nb ? partials[e] : 0;
+            s += v[i];
+        }
+        T total;
+        T ex = block_exclusive_scan(s, lds, total) + carry;
+#pragma unroll
+        for (int i = 0; i < IPT; i++) {
+            uint64_t e = base + (uint64_t)threadIdx.x * IPT + i;
+            if (e < nb) partials[e] = ex;
+            ex += v[i];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = (uint64_t)carry;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLK) k_scan_down(const T *in, T *out, uint64_t n,
+                                                   const T *__restrict__ partials) {
+    __shared__ T lds[NWAVE];
+    uint64_t base = (uint64_t)blockIdx.x * TILE + (uint64_t)threadIdx.x * IPT;
+    T v[IPT];
+    T s = 0;
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        v[i] = (base + i < n) ? in[base + i] : 0;
+        s += v[i];
+    }
+    T total;
+    T ex = block_exclusive_scan(s, lds, total) + partials[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        if (base + i < n) out[base + i] = ex;
+        ex += v[i];
+    }
+}
+
+template <typename T>
+void scan_exclusive(ej_ctx *ctx, const T *d_in, T *d_out, uint64_t n, uint64_t *d_total,
+                    const char *name) {
+    if (n == 0) {
+        if (d_total) EJ_HIP(hipMemsetAsync(d_total, 0, sizeof(uint64_t), ctx->stream));
+        return;
+    }
+    uint64_t nb = (n + TILE - 1) / TILE;
+    T *partials = ws<T>(ctx, std::string("scan_partials_") + name, nb);
+    hipLaunchKernelGGL(k_scan_reduce<T>, dim3((uint32_t)nb), dim3(BLK), 0, ctx->stream, d_in, n,
+                       partials);
+    EJ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_partials<T>, dim3(1), dim3(BLK), 0, ctx->stream, partials, nb,
+                       d_total);
+    EJ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_scan_down<T>, dim3((uint32_t)nb), dim3(BLK), 0, ctx->stream, d_in, d_out,
+                       n, (const T *)partials);
+    EJ_CHECK_LAUNCH();
+}
+
+// ---------------------------------------------------------- radix sort --
+
+template <typename K>
+__global__ void __launch_bounds__(BLK) k_rs_hist(const K *__restrict__ keys, uint32_t seglen,
+                                                 uint32_t tps, uint32_t shift, uint32_t dbits,
+                                                 uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t cnt[];
+    const uint32_t NB = 1u << dbits, mask = NB - 1;
+    uint32_t seg = blockIdx.x / tps, tile = blockIdx.x % tps;
+    for (uint32_t d = threadIdx.x; d < NB; d += BLK) cnt[d] = 0;
+    __syncthreads();
+    uint64_t segbase = (uint64_t)seg * seglen;
+    uint32_t t0 = tile * TILE;
+#pragma unroll
+    for (int i = 0; i < IPT; i++) {
+        uint32_t e = t0 + i * BLK + threadIdx.x;
+        if (e < seglen) {
+            uint32_t d = (uint32_t)(keys[segbase + e] >> shift) & mask;
+            atomicAdd(&cnt[d], 1u);
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = threadIdx.x; d < NB; d += BLK)
+        hist[((uint64_t)seg * NB + d) * tps + tile] = cnt[d];
+}
+
+// Stable scatter: element order inside a tile is round-major, then thread
+// order, so waves rank their lanes with a ballot-based match on the digit
+// and add the counts of lower waves and earlier rounds.
+template <typename K, bool HAS_VAL>
+__global__ void __launch_bounds__(BLK) k_rs_scatter(const K *__restrict__ kin,
+                                                    const uint32_t *__restrict__ vin,
+                                                    K *__restrict__ kout,
+                                                    uint32_t *__restrict__ vout, uint32_t seglen,
+                                                    uint32_t tps, uint32_t shift, uint32_t dbits,
+                                                    const uint32_t *__restrict__ hist) {
+    extern __shared__ uint32_t sm[];
+    const uint32_t NB = 1u << dbits, mask = NB - 1;
+    uint32_t *base_off = sm;           // [NB]
+    uint32_t *run = sm + NB;           // [NB]
+    uint32_t *wc = sm + 2 * NB;        // [NWAVE][NB] tagged wave counts
+    uint32_t seg = blockIdx.x / tps, tile = blockIdx.x % tps;
+    uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (uint32_t d = threadIdx.x; d < NB; d += BLK) {
+        base_off[d] = hist[((uint64_t)seg * NB + d) * tps + tile];
+        run[d] = 0;
+        for (int w = 0; w < NWAVE; w++) wc[w * NB + d] = 0;
+    }
+    __syncthreads();
+    uint64_t segbase = (uint64_t)seg * seglen;
+    uint32_t t0 = tile * TILE;
+    const uint64_t lt_mask = (1ULL << lane) - 1ULL;
+    for (int rd = 0; rd < IPT; rd++) {
+        uint32_t e = t0 + rd * BLK + threadIdx.x;
+        bool valid = e < seglen;
+        K key = 0;
+        uint32_t val = 0, d = 0;
+        if (valid) {
+            key = kin[segbase + e];
+            if (HAS_VAL) val = vin[segbase + e];
+            d = (uint32_t)(key >> shift) & mask;
+        }
+        uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
+        for (uint32_t b = 0; b < dbits; b++) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        uint64_t lower = peers & lt_mask;
+        uint32_t rank = (uint32_t)__popcll(lower);
+        uint32_t cnt = (uint32_t)__popcll(peers);
+        uint32_t tag = (uint32_t)(rd + 1) << 16;
+        if (valid && lower == 0) wc[wave * NB + d] = tag | cnt;
+        __syncthreads();
+        if (valid) {
+            uint32_t prefix = 0;
+            for (uint32_t w = 0; w < wave; w++) {
+                uint32_t x = wc[w * NB + d];
+                if ((x & 0xFFFF0000u) == tag) prefix += x & 0xFFFFu;
+            }
+            uint32_t pos = base_off[d] + run[d] + prefix + rank;
+            kout[pos] = key;
+            if (HAS_VAL) vout[pos] = val;
+        }
+        __syncthreads();
+        if (valid && lower == 0) atomicAdd(&run[d], cnt);
+    }
+}
+
+template <typename K, bool HAS_VAL>
+void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout, uint32_t nseg,
+                     uint32_t seglen, uint32_t key_bits, uint32_t dbits) {
+    uint64_t n = (uint64_t)nseg * seglen;
+    if (n == 0) return;
+    if (dbits < 4) dbits = 4;
+    if (dbits > 11) dbits = 11;
+    uint32_t passes = (key_bits + dbits - 1) / dbits;
+    if (passes == 0) {
+        EJ_HIP(hipMemcpyAsync(kout, kin, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
+        if (HAS_VAL)
+            EJ_HIP(hipMemcpyAsync(vout, vin, n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+        return;
+    }
+    // with an odd number of passes the first pass writes kout; with an even
+    // number it writes kin's partner so that the last pass lands in kout
+    uint32_t tps = ceil_div(seglen, TILE);
+    uint32_t NB = 1u << dbits;
+    uint64_t hn = (uint64_t)nseg * NB * tps;
+    uint32_t *hist = ws<uint32_t>(ctx, "rs_hist", hn);
+    K *a = kin, *b = kout;
+    uint32_t *va = vin, *vb = vout;
+    if (passes % 2 == 0) {
+        // even: pass 0 kin->kout, 1 kout->kin, ... ends in kin; copy once up
+        // front instead so the final pass writes kout
+        EJ_HIP(hipMemcpyAsync(kout, kin, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
+        if (HAS_VAL)
+            EJ_HIP(hipMemcpyAsync(vout, vin, n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+        a = kout;
+        b = kin;
+        va = vout;
+        vb = vin;
+    }
+    size_t hist_lds = NB * sizeof(uint32_t);
+    size_t scat_lds = (2 + NWAVE) * NB * sizeof(uint32_t);
+    for (uint32_t p = 0; p < passes; p++) {
+        uint32_t shift = p * dbits;
+        uint32_t db = (key_bits - shift < dbits) ? key_bits - shift : dbits;
+        hipLaunchKernelGGL(k_rs_hist<K>, dim3(nseg * tps), dim3(BLK), hist_lds, ctx->stream,
+                           (const K *)a, seglen, tps, shift, db, hist);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive<uint32_t>(ctx, hist, hist, (uint64_t)nseg * (1u << db) * tps, nullptr,
+                                 "rs");
+        hipLaunchKernelGGL((k_rs_scatter<K, HAS_VAL>), dim3(nseg * tps), dim3(BLK), scat_lds,
+                           ctx->stream, (const K *)a, (const uint32_t *)va, b, vb, seglen, tps,
+                           shift, db, (const uint32_t *)hist);
+        EJ_CHECK_LAUNCH();
+        K *t = a;
+        a = b;
+        b = t;
+        uint32_t *tv = va;
+        va = vb;
+        vb = tv;
+    }
+}
+
+}  // namespace
+
+void scan_exclusive_u32(ej_ctx *ctx, const uint32_t *d_in, uint32_t *d_out, uint64_t n,
+                        uint64_t *d_total) {
+    scan_exclusive<uint32_t>(ctx, d_in, d_out, n, d_total, "u32");
+}
+
+void scan_exclusive_u64(ej_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, uint64_t n,
+                        uint64_t *d_total) {
+    scan_exclusive<uint64_t>(ctx, d_in, d_out, n, d_total, "u64");
+}
+
+void radix_sort_u32(ej_ctx *ctx, uint32_t *keys_in, uint32_t *vals_in, uint32_t *keys_out,
+                    uint32_t *vals_out, uint32_t nseg, uint32_t seglen, uint32_t key_bits,
+                    uint32_t digit_bits) {
+    if (vals_in)
+        radix_sort_impl<uint32_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, nseg, seglen,
+                                        key_bits, digit_bits);
+    else
+        radix_sort_impl<uint32_t, false>(ctx, keys_in, nullptr, keys_out, nullptr, nseg, seglen,
+                                         key_bits, digit_bits);
+}
+
+void radix_sort_u64(ej_ctx *ctx, uint64_t *keys_in, uint64_t *keys_out, uint64_t n,
+                    uint32_t key_bits, uint32_t digit_bits) {
+    if (n > 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "radix_sort_u64: more than 2^32 keys");
+    radix_sort_impl<uint64_t, false>(ctx, keys_in, nullptr, keys_out, nullptr, 1, (uint32_t)n,
+                                     key_bits, digit_bits);
+}
+
+}  // namespace ej

@@ -1,0 +1,268 @@
+"""GPU parity: every stage of the HIP path, called through the C ABI, against
+the CPU oracle on the same seeded inputs.  All results here are integers, so
+the bar is bit-exact equality."""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import synthdata as sd
+from tests._gpu_util import codes_to_set, pairs_to_codes, to_device
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ej():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1702_00093_amd as ej
+    ej.lib()  # raises if the library is not built
+    return ej
+
+
+@pytest.fixture(scope="module")
+def ctx(ej):
+    return ej.Context(0)
+
+
+def _oracle_join(oracle_lib, col, K, r, z, m, seed, L=0):
+    return oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
+
+
+def _assert_join_equal(res, ref):
+    got = pairs_to_codes(res.pairs)
+    assert got.tolist() == ref.out.tolist()
+    assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
+    assert res.n_candidates == len(ref.cand)
+    assert res.L == ref.L and res.sigma == ref.sigma
+
+
+# ------------------------------------------------------ paper examples ----
+
+def test_running_example_through_hook(ej, ctx, oracle_lib):
+    g = json.load(open(os.path.join(GOLD, "running_example.json")))
+    letters = g["alphabet"]
+    R = np.zeros((2, g["L"] * 4), dtype=np.uint8)
+    for l, name in enumerate(["R1", "R2"]):
+        for k, ch in enumerate(letters):
+            for j, bit in enumerate(g["pi"][name][ch]):
+                R[l, j * 4 + k] = bit
+    pos = np.zeros((2, 2, 2), dtype=np.uint32)
+    for l in range(2):
+        for j in range(2):
+            pos[l, j] = np.array(g["lsh_coordinates_1based"][f"f{j + 1}^{l + 1}"]) - 1
+    col = sd.from_strings([s.encode() for s in g["strings"]])
+    _say("running example (explicit randomness)")
+    ctx.set_explicit_randomness(2, 2, 2, g["L"], 4, R, pos)
+    try:
+        chars, offs = to_device(col)
+        keys, sig, L_used, sigma = ctx.embed(chars, offs, 2, 2, 2, seed=0, L=g["L"], want_sig=True)
+        sig = sig.cpu().numpy()
+        for i in range(4):
+            got = ["".join(letters[c] for c in sig[i, l, j]) for l in range(2) for j in range(2)]
+            assert got == g["signatures"][str(i + 1)]
+        res = ctx.join(col.chars, col.offsets, g["K"], 2, 2, 2, seed=0, L=g["L"])
+    finally:
+        ctx.set_explicit_randomness(0, 0, 0, 0, 0)
+    assert (res.pairs + 1).tolist() == g["output_1based"]
+    assert res.dist.tolist() == [2, 3]
+    assert res.n_candidates == len(g["candidates_1based"])
+
+
+def test_intro_example(ej, ctx):
+    g = json.load(open(os.path.join(GOLD, "intro_example.json")))
+    col = sd.from_strings([s.encode() for s in g["strings"]])
+    _say("intro example r=7 z=7 m=1 L=5 seed=0")
+    res = ctx.join(col.chars, col.offsets, g["K"], 7, 7, 1, seed=0, L=5)
+    S = g["strings"]
+    got = sorted(tuple(sorted((S[a], S[b]))) for a, b in res.pairs.tolist())
+    assert got == sorted(tuple(sorted(p)) for p in g["output"])
+
+
+# ------------------------------------------------------ stage by stage ----
+
+STAGE_CASES = [
+    # seed, n_bases, len range, edits, K, r, z, m, L, letters
+    (0, 40, (50, 300), 6, 12, 3, 4, 6, 0, sd.DNA),
+    (1, 30, (100, 700), 20, 40, 2, 7, 12, 0, sd.DNA),
+    (2, 25, (10, 90), 3, 5, 4, 3, 3, 24, sd.PROTEIN25),
+    (3, 20, (200, 2600), 30, 60, 3, 5, 20, 0, sd.DNA),          # walks span several LDS windows
+    (4, 30, (0, 40), 2, 3, 3, 4, 2, 0, b"AB"),                  # empty strings, 2 letters
+    (5, 15, (30, 120), 8, 20, 2, 6, 5, 0, bytes(range(65, 65 + 40))),  # 40 letters: generic pi path
+]
+
+
+@pytest.mark.parametrize("case", STAGE_CASES, ids=[f"c{c[0]}" for c in STAGE_CASES])
+def test_stages_match_oracle(ej, ctx, oracle_lib, case):
+    import torch
+    seed, nb, (lo, hi), E, K, r, z, m, L, letters = case
+    col = sd.clusters(seed, nb, lambda rr, b: rr.integers(1, 6), lambda rr: rr.integers(lo, hi + 1),
+                      lambda rr, LL: rr.poisson(E), letters=letters)
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, seed, L)
+    chars, offs = to_device(col)
+    _say(f"stages case seed={seed} n={col.n} K={K} r={r} z={z} m={m} L={L}")
+    keys, sig, L_used, sigma = ctx.embed(chars, offs, r, z, m, seed=seed, L=L, want_sig=True)
+    torch.cuda.synchronize()
+    assert L_used == ref.L and sigma == ref.sigma
+    assert np.array_equal(sig.cpu().numpy(), ref.sig)
+    assert np.array_equal(keys.cpu().numpy().astype(np.uint64), ref.keys)
+    d_len = torch.from_numpy(col.lengths().astype(np.int32)).cuda()
+    ids, gstart = ctx.lsh_bucket(keys, d_len)
+    cand, n_raw = ctx.candidates(keys, ids, gstart, d_len, K)
+    assert cand.cpu().numpy().astype(np.uint64).tolist() == ref.cand.tolist()
+    dist = ctx.verify(chars, offs, cand, K)
+    assert dist.cpu().numpy().tolist() == ref.cand_dist.astype(np.int32).tolist()
+    res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
+    _assert_join_equal(res, ref)
+    # device-resident form gives the same answer
+    res2 = ctx.join(chars, offs, K, r, z, m, seed=seed, L=L)
+    _assert_join_equal(res2, ref)
+
+
+def test_bucket_key_bits_do_not_change_candidates(ej, ctx, oracle_lib):
+    import torch
+    col = sd.clusters(7, 30, lambda rr, b: 4, lambda rr: rr.integers(40, 80),
+                      lambda rr, LL: rr.poisson(3))
+    K, r, z, m = 10, 3, 5, 2
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 7, 16)
+    chars, offs = to_device(col)
+    keys, _, _, _ = ctx.embed(chars, offs, r, z, m, seed=7, L=16)
+    d_len = torch.from_numpy(col.lengths().astype(np.int32)).cuda()
+    for bits in (1, 3, 8, 17, 32):
+        _say(f"bucket key_bits={bits}")
+        ids, gstart = ctx.lsh_bucket(keys, d_len, key_bits=bits)
+        cand, _ = ctx.candidates(keys, ids, gstart, d_len, K)
+        assert cand.cpu().numpy().astype(np.uint64).tolist() == ref.cand.tolist()
+
+
+# ------------------------------------------------------- verification ----
+
+@pytest.mark.parametrize("K", [0, 1, 7, 15, 16, 31, 50, 63, 100, 250, 400, 500, 1000, 1022])
+def test_verify_matches_ukkonen(ej, ctx, oracle_lib, K):
+    import torch
+    rng = np.random.default_rng(K)
+    col = sd.clusters(100 + K, 12, lambda rr, b: 5,
+                      lambda rr: rr.integers(0, 3 * K + 60),
+                      lambda rr, LL: rr.poisson(max(1, K // 2)))
+    n = col.n
+    a = rng.integers(0, n, size=400)
+    b = rng.integers(0, n, size=400)
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+    chars, offs = to_device(col)
+    _say(f"verify K={K} n={n}")
+    got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+    assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+
+
+def test_verify_per_pair_thresholds(ej, ctx, oracle_lib):
+    import torch
+    rng = np.random.default_rng(5)
+    col = sd.clusters(55, 20, lambda rr, b: 4, lambda rr: rr.integers(100, 1500),
+                      lambda rr, LL: rr.poisson(40))
+    n = col.n
+    a = rng.integers(0, n, size=300)
+    b = rng.integers(0, n, size=300)
+    Kq = rng.integers(0, 600, size=300).astype(np.uint32)
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    want = [int(oracle_lib.verify_pairs(col.chars, col.offsets, codes[i:i + 1], int(Kq[i]))[0])
+            for i in range(300)]
+    chars, offs = to_device(col)
+    _say("verify per-pair thresholds")
+    got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), 0,
+                     d_Kq=torch.from_numpy(Kq.astype(np.int32)).cuda())
+    assert got.cpu().numpy().tolist() == want
+
+
+def test_verify_long_strings_random_and_similar(ej, ctx, oracle_lib):
+    import torch
+    col = sd.clusters(77, 3, lambda rr, b: 3, lambda rr: rr.integers(4500, 5501),
+                      lambda rr, LL: rr.poisson(0.04 * LL))
+    n = col.n
+    a, b = np.triu_indices(n, 1)
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    chars, offs = to_device(col)
+    for K in (250, 500):
+        want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+        _say(f"verify long K={K}")
+        got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+        assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+
+
+# ------------------------------------------------------------ edge cases ----
+
+def test_edge_cases(ej, ctx, oracle_lib):
+    cases = [
+        ("empty set", []),
+        ("one string", [b"ACGT"]),
+        ("all empty", [b"", b"", b""]),
+        ("one letter", [b"AAAA", b"AAA", b"AAAAA", b"", b"A"]),
+        ("duplicates", [b"ACGTACGT"] * 5 + [b"ACGAACGT"]),
+    ]
+    for name, S in cases:
+        col = sd.from_strings(S)
+        for K in (0, 1, 3):
+            _say(f"edge {name} K={K}")
+            ref = _oracle_join(oracle_lib, col, K, 3, 4, 2, 11)
+            res = ctx.join(col.chars, col.offsets, K, 3, 4, 2, seed=11)
+            _assert_join_equal(res, ref)
+
+
+def test_invalid_arguments_are_rejected(ej, ctx):
+    col = sd.from_strings([b"ACGT", b"ACGA"])
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ctx.join(col.chars, col.offsets, 2, 0, 4, 4)
+    assert e.value.status == ej.EJ_EINVAL
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ctx.join(col.chars, col.offsets, 2000, 1, 1, 1)
+    assert e.value.status == ej.EJ_EUNSUPPORTED
+    bad = np.array([0, 4, 2], dtype=np.uint64)
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ctx.join(col.chars, bad, 2, 1, 1, 1)
+    assert e.value.status == ej.EJ_EINVAL
+    import torch
+    chars, offs = to_device(col)
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ctx.verify(chars, offs, torch.tensor([(5 << 32) | 1], dtype=torch.int64, device="cuda"), 2)
+    assert e.value.status == ej.EJ_EINVAL
+    # the context still works after errors
+    res = ctx.join(col.chars, col.offsets, 1, 2, 2, 2)
+    assert res.pairs.tolist() == [[0, 1]]
+
+
+# -------------------------------------------------- the tiny workload ----
+
+def test_tiny_dna_workload_full(ej, ctx, oracle_lib):
+    """2,000 DNA strings (200 bases x 10 copies, Poisson(30) edits), K=50,
+    r=3, z=7, m=24 -- the small configuration, in full."""
+    col, prm = sd.tiny_dna(0)
+    ref = _oracle_join(oracle_lib, col, prm["K"], prm["r"], prm["z"], prm["m"], 0)
+    _say(f"tiny workload n={col.n} candidates={len(ref.cand)}")
+    res = ctx.join(col.chars, col.offsets, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
+    _assert_join_equal(res, ref)
+    chars, offs = to_device(col)
+    res2 = ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
+    _assert_join_equal(res2, ref)
+
+
+def test_tiny_dna_recall_point(ej, ctx, oracle_lib):
+    """A permissive parameter point on the tiny workload: output still equals
+    the oracle's, and every output pair is a true pair."""
+    col, prm = sd.tiny_dna(0, n_bases=60)
+    K = prm["K"]
+    ref = _oracle_join(oracle_lib, col, K, 7, 16, 8, 3, 64)
+    res = ctx.join(col.chars, col.offsets, K, 7, 16, 8, seed=3, L=64)
+    _say(f"tiny recall point candidates={res.n_candidates}")
+    _assert_join_equal(res, ref)
+    S = col.strings()
+    for (a, b), d in zip(res.pairs.tolist(), res.dist.tolist()):
+        assert oracle_lib.ed_full(S[a], S[b]) == d <= K

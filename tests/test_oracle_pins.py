@@ -106,12 +106,13 @@ def test_running_example_join(oracle_lib):
 def test_intro_example_brute_force(oracle_lib):
     g = _load("intro_example.json")
     col = sd.from_strings([s.encode() for s in g["strings"]])
-    codes, d = oracle_lib.brute_join(col.chars, col.offsets, g["K"])
+    codes, d = oracle_lib.brute_join(col.chars, col.offsets, g["K"], full=True)
     S = g["strings"]
     got = sorted(tuple(sorted((S[int(c) >> 32], S[int(c) & 0xFFFFFFFF]))) for c in codes)
     assert got == sorted(tuple(sorted(p)) for p in g["output"])
     # threshold is inclusive: at K=3 four more pairs (distance exactly 3) join
-    codes3, d3 = oracle_lib.brute_join(col.chars, col.offsets, 3)
+    codes3, d3 = oracle_lib.brute_join(col.chars, col.offsets, 3, full=True)
+    assert oracle_lib.brute_join(col.chars, col.offsets, 3)[0].tolist() == codes3.tolist()
     assert len(codes3) == 7 and sorted(d3.tolist()) == [2, 2, 2, 3, 3, 3, 3]
 
 
@@ -341,8 +342,10 @@ def test_output_is_exact_subset_and_precision_one(oracle_lib, seed):
     col = sd.clusters(seed, 25, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(30, 90),
                       lambda rr, L: rr.poisson(4))
     K = 8
-    truth_codes, truth_d = oracle_lib.brute_join(col.chars, col.offsets, K)
+    truth_codes, truth_d = oracle_lib.brute_join(col.chars, col.offsets, K, full=True)
     truth = dict(zip(truth_codes.tolist(), truth_d.tolist()))
+    fast_codes, fast_d = oracle_lib.brute_join(col.chars, col.offsets, K)
+    assert fast_codes.tolist() == truth_codes.tolist() and fast_d.tolist() == truth_d.tolist()
     res = oracle_lib.join(col.chars, col.offsets, K, 4, 6, 3, seed=seed, L=0)
     for c, d in zip(res.out.tolist(), res.out_dist.tolist()):
         assert truth[c] == d
