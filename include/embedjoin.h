@@ -85,7 +85,16 @@ typedef struct {
     uint64_t n_raw;        /* candidate pairs before de-duplication across tables */
     uint32_t sigma;        /* alphabet size */
     uint32_t L;            /* truncation length used */
-    float ms_prep, ms_embed, ms_bucket, ms_candidates, ms_verify, ms_output; /* EJ_FLAG_TIMING */
+    /* EJ_FLAG_TIMING: device time of each stage, from events on the context
+     * stream: prep = A0 and the random streams, embed = the walk kernel (A1-A2),
+     * bucket = A3, candidates = A4, verify = the verification kernel (A5),
+     * output = compaction and copy-out (A6). */
+    float ms_prep, ms_embed, ms_bucket, ms_candidates, ms_verify, ms_output;
+    /* EJ_FLAG_TIMING: work done, for rooflines.  walk_steps = CGK steps taken
+     * (each walk stops after its seed's last sampled step); verify_columns =
+     * text columns evaluated over all candidates (a pair stops early once its
+     * distance provably exceeds K). */
+    uint64_t walk_steps, verify_columns;
 } ej_result;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -101,6 +110,18 @@ int ej_version(void);
 /* Bytes of device workspace the context currently holds. */
 uint64_t ej_workspace_bytes(const ej_ctx *ctx);
 
+/* Launch-shape knobs of the context.  None of them changes any result:
+ *   "verify_lds_budget"     LDS bytes per wave of the verification kernel
+ *   "verify_pass1_cols"     columns of verification pass 1 (multiple of 32;
+ *                           0 = a single pass)
+ *   "verify_blocks_per_cu"  workgroups per CU of the verification grid
+ *   "embed_lds_budget"      LDS bytes per wave of the walk kernel
+ *   "radix_bits"            digit width of the radix sorts (4..11)
+ *   "bucket_key_bits"       key bits sorted when bucketing (1..32)
+ * EJ_EINVAL for an unknown name or a value out of range. */
+ej_status ej_tune_set(ej_ctx *ctx, const char *name, uint32_t value);
+ej_status ej_tune_get(const ej_ctx *ctx, const char *name, uint32_t *value);
+
 /* ------------------------------------------------------------- end to end */
 
 /* EmbedJoin self-join (Algorithm 3 with Algorithm 2 as preprocessing) of the
@@ -109,7 +130,7 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  * library allocates out->pairs and out->dist (free with ej_result_free).
  * Errors: EJ_EINVAL (n >= 2^31, r*z*m == 0, m > 64, r*z > 4096,
  * non-monotone offsets, a string longer than 2^31 - 1), EJ_EALPHABET (all
- * 256 byte values present), EJ_EUNSUPPORTED (K > 1022), EJ_ENOMEM, EJ_EHIP. */
+ * 256 byte values present), EJ_EUNSUPPORTED (K > 2046), EJ_ENOMEM, EJ_EHIP. */
 ej_status ej_join(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
                   uint32_t K, uint32_t r, uint32_t z, uint32_t m, uint64_t seed,
                   ej_result *out);
@@ -174,7 +195,7 @@ ej_status ej_candidates(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_i
  * bit-parallel banded kernel: d_dist[k] = ED(s_a, s_b) if it is <= K_k,
  * else K_k + 1, where K_k = d_Kq[k] when d_Kq is not NULL and K otherwise.
  * Pairs are uint64 codes (a << 32) | b.  EJ_EUNSUPPORTED if a threshold
- * exceeds 1022. */
+ * exceeds 2046. */
 ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
                     const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
                     int32_t *d_dist);

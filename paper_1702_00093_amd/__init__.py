@@ -26,6 +26,7 @@ FLAG_PLAIN, FLAG_GRAPH, FLAG_TIMING = 0, 1, 2
 # Every symbol declared in include/embedjoin.h.
 EXPORTS = [
     "ej_create", "ej_destroy", "ej_last_error", "ej_version", "ej_workspace_bytes",
+    "ej_tune_set", "ej_tune_get",
     "ej_join", "ej_join_ex", "ej_join_device", "ej_result_free",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_set_explicit_randomness",
     "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
@@ -51,7 +52,8 @@ class _Result(ctypes.Structure):
                 ("n_raw", ctypes.c_uint64), ("sigma", ctypes.c_uint32), ("L", ctypes.c_uint32),
                 ("ms_prep", ctypes.c_float), ("ms_embed", ctypes.c_float),
                 ("ms_bucket", ctypes.c_float), ("ms_candidates", ctypes.c_float),
-                ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float)]
+                ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float),
+                ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64)]
 
 
 class _QResult(ctypes.Structure):
@@ -81,6 +83,8 @@ def lib():
         "ej_last_error": (ctypes.c_char_p, [vp]),
         "ej_version": (c_int, []),
         "ej_workspace_bytes": (u64, [vp]),
+        "ej_tune_set": (c_int, [vp, ctypes.c_char_p, u32]),
+        "ej_tune_get": (c_int, [vp, ctypes.c_char_p, u32p]),
         "ej_join": (c_int, [vp, vp, vp, u32, u32, u32, u32, u32, u64, ctypes.POINTER(_Result)]),
         "ej_join_ex": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), ctypes.POINTER(_Result)]),
         "ej_join_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params),
@@ -151,6 +155,8 @@ class JoinResult:
     sigma: int
     L: int
     ms: dict
+    walk_steps: int = 0
+    verify_columns: int = 0
 
     @property
     def codes(self) -> np.ndarray:
@@ -184,6 +190,14 @@ class Context:
         if st != EJ_OK:
             msg = lib().ej_last_error(self._h)
             raise EmbedJoinError(st, msg.decode() if msg else "")
+
+    def tune_set(self, name: str, value: int):
+        self._check(lib().ej_tune_set(self._h, name.encode(), int(value)))
+
+    def tune_get(self, name: str) -> int:
+        v = ctypes.c_uint32()
+        self._check(lib().ej_tune_get(self._h, name.encode(), ctypes.byref(v)))
+        return int(v.value)
 
     @property
     def workspace_bytes(self) -> int:
@@ -219,7 +233,8 @@ class Context:
             ms = dict(prep=res.ms_prep, embed=res.ms_embed, bucket=res.ms_bucket,
                       candidates=res.ms_candidates, verify=res.ms_verify, output=res.ms_output)
             return JoinResult(pairs, dist, int(res.n_candidates), int(res.n_raw),
-                              int(res.sigma), int(res.L), ms)
+                              int(res.sigma), int(res.L), ms, int(res.walk_steps),
+                              int(res.verify_columns))
         finally:
             lib().ej_result_free(ctypes.byref(res))
 

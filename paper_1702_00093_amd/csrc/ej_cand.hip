@@ -142,7 +142,7 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
     bk.n = n;
     uint64_t tot = (uint64_t)T * n;
     if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
-    if (key_bits == 0) key_bits = 32;
+    if (key_bits == 0) key_bits = ctx->tune.bucket_key_bits;
     if (key_bits > 32) key_bits = 32;
     bk.d_ids = ws<uint32_t>(ctx, t + "_ids", tot);
     bk.d_gid = ws<uint32_t>(ctx, t + "_gid", tot);
@@ -160,7 +160,7 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
     hipLaunchKernelGGL(k_bucket_gather, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
                        d_keys, d_perm, n, tot, 61u - key_bits, dk, ids0);
     EJ_CHECK_LAUNCH();
-    radix_sort_u32(ctx, dk, ids0, dk2, bk.d_ids, T, n, key_bits, 8);
+    radix_sort_u32(ctx, dk, ids0, dk2, bk.d_ids, T, n, key_bits, ctx->tune.radix_bits);
     uint32_t *flags = ws<uint32_t>(ctx, t + "_flags", tot);
     uint64_t *d_ng = ws<uint64_t>(ctx, t + "_ngroups", 1);
     hipLaunchKernelGGL(k_group_flags, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
@@ -210,7 +210,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                        (const uint32_t *)bk.d_gstart, tot, K, B, nullptr,
                        (const uint64_t *)counts, rawbuf);
     EJ_CHECK_LAUNCH();
-    radix_sort_u64(ctx, rawbuf, sorted, raw, 2 * B, 8);
+    radix_sort_u64(ctx, rawbuf, sorted, raw, 2 * B, ctx->tune.radix_bits);
     uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", raw);
     uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", raw);
     uint64_t *d_cnt = ws<uint64_t>(ctx, t + "_ucount", 1);

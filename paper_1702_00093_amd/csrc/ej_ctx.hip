@@ -104,6 +104,55 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx) {
     return s;
 }
 
+static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32_t *hi) {
+    struct Item {
+        const char *name;
+        uint32_t Tuning::*field;
+        uint32_t lo, hi;
+    };
+    static const Item items[] = {
+        {"verify_lds_budget", &Tuning::verify_lds_budget, 4096, 1u << 20},
+        {"verify_pass1_cols", &Tuning::verify_pass1_cols, 0, 1u << 30},
+        {"verify_blocks_per_cu", &Tuning::verify_blocks_per_cu, 1, 1024},
+        {"embed_lds_budget", &Tuning::embed_lds_budget, 8192, 1u << 20},
+        {"radix_bits", &Tuning::radix_bits, 4, 11},
+        {"bucket_key_bits", &Tuning::bucket_key_bits, 1, 32},
+    };
+    if (!name) return nullptr;
+    for (const Item &it : items)
+        if (strcmp(it.name, name) == 0) {
+            *lo = it.lo;
+            *hi = it.hi;
+            return &(t.*(it.field));
+        }
+    return nullptr;
+}
+
+ej_status ej_tune_set(ej_ctx *ctx, const char *name, uint32_t value) {
+    if (!ctx) return EJ_EINVAL;
+    uint32_t lo = 0, hi = 0;
+    uint32_t *slot = tune_slot(ctx->tune, name, &lo, &hi);
+    if (!slot || value < lo || value > hi) {
+        ctx->err = std::string("unknown knob or value out of range: ") + (name ? name : "(null)");
+        return EJ_EINVAL;
+    }
+    if (strcmp(name, "verify_pass1_cols") == 0 && (value % 32) != 0) {
+        ctx->err = "verify_pass1_cols must be a multiple of 32";
+        return EJ_EINVAL;
+    }
+    *slot = value;
+    return EJ_OK;
+}
+
+ej_status ej_tune_get(const ej_ctx *ctx, const char *name, uint32_t *value) {
+    if (!ctx || !value) return EJ_EINVAL;
+    uint32_t lo = 0, hi = 0;
+    uint32_t *slot = tune_slot(const_cast<ej_ctx *>(ctx)->tune, name, &lo, &hi);
+    if (!slot) return EJ_EINVAL;
+    *value = *slot;
+    return EJ_OK;
+}
+
 ej_status ej_set_explicit_randomness(ej_ctx *ctx, uint32_t r, uint32_t z, uint32_t m, uint32_t L,
                                      uint32_t sigma, const uint8_t *Rbits, const uint32_t *pos,
                                      const uint64_t *v) {

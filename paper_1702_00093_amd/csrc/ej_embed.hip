@@ -530,7 +530,7 @@ void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, u
     if (pp.n == 0) return;
     const uint32_t S = rd.S;
     const uint32_t sigbytes = ((S * 64 + 3) / 4) * 4;
-    uint32_t budget = 48 * 1024;
+    uint32_t budget = ctx->tune.embed_lds_budget;
     if (sigbytes + 64 * 4 * 12 > budget) budget = sigbytes + 64 * 4 * 64;
     if ((int)budget > ctx->lds_max) budget = (uint32_t)ctx->lds_max;
     if (sigbytes + 64 * 4 * 12 > budget)

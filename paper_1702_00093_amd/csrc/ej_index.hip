@@ -312,7 +312,7 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
     ej_status st = guarded(ctx, [&] {
         for (uint32_t i = 0; i < nq; i++) {
             if (q_offsets[i + 1] < q_offsets[i]) fail(EJ_EINVAL, "query offsets decrease");
-            if (verify_lanes_for(Kq[i]) == 0) fail(EJ_EUNSUPPORTED, "query threshold above 1022");
+            if (verify_lanes_for(Kq[i]) == 0) fail(EJ_EUNSUPPORTED, "query threshold above 2046");
         }
         const uint64_t qbase = q_offsets[0], qtotal = q_offsets[nq] - qbase;
         if (qtotal && !q) fail(EJ_EINVAL, "null query strings");
@@ -373,7 +373,7 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
                                (const uint32_t *)ix->d_ids, ix->n, T, B, nullptr,
                                (const uint64_t *)counts, rb);
             EJ_CHECK_LAUNCH();
-            radix_sort_u64(ctx, rb, sorted, raw, 2 * B, 8);
+            radix_sort_u64(ctx, rb, sorted, raw, 2 * B, ctx->tune.radix_bits);
             uint32_t *flags = ws<uint32_t>(ctx, "q_uflags", raw);
             uint32_t *pos = ws<uint32_t>(ctx, "q_upos", raw);
             uint64_t *d_cnt = ws<uint64_t>(ctx, "q_ucnt", 1);

@@ -81,6 +81,19 @@ struct Timers {
 
 }  // namespace ej
 
+namespace ej {
+// Launch-shape knobs.  Defaults are set at context creation; the autotuner
+// (ej_autotune) can replace them.  None of them changes a result.
+struct Tuning {
+    uint32_t verify_lds_budget = 48 * 1024;  // LDS per wave of the verification kernel
+    uint32_t verify_pass1_cols = 1024;       // columns of verification pass 1 (0: one pass)
+    uint32_t verify_blocks_per_cu = 16;      // resident-wave target of the verification grid
+    uint32_t embed_lds_budget = 48 * 1024;   // LDS per wave of the walk kernel
+    uint32_t radix_bits = 8;                 // digit width of the radix sorts
+    uint32_t bucket_key_bits = 32;           // key bits sorted when bucketing
+};
+}  // namespace ej
+
 struct ej_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -92,6 +105,7 @@ struct ej_ctx {
     int lds_max = 65536;         // max dynamic LDS per workgroup
     uint64_t *pinned = nullptr;  // small pinned host buffer for size read-backs
     ej::Timers timers;
+    ej::Tuning tune;
 };
 
 namespace ej {
@@ -193,7 +207,8 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
 void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
             uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
             const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b = nullptr,
-            const uint64_t *d_offsets_b = nullptr, uint64_t base_b = 0, uint32_t maxlen_b = 0);
+            const uint64_t *d_offsets_b = nullptr, uint64_t base_b = 0, uint32_t maxlen_b = 0,
+            unsigned long long *d_columns = nullptr);
 
 uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported
 

@@ -90,7 +90,7 @@ void check_params(const ej_params &p, uint32_t n) {
     if ((uint64_t)p.r * p.z > 4096) fail(EJ_EINVAL, "r*z must be at most 4096");
     if (n >= 0x80000000u) fail(EJ_EINVAL, "n must be below 2^31");
     if (p.K > 0x7FFFFFFFu) fail(EJ_EINVAL, "K must be below 2^31");
-    if (verify_lanes_for(p.K) == 0) fail(EJ_EUNSUPPORTED, "K above 1022 is not supported");
+    if (verify_lanes_for(p.K) == 0) fail(EJ_EUNSUPPORTED, "K above 2046 is not supported");
 }
 
 struct StageTimer {
@@ -141,25 +141,30 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     prepare(ctx, d_chars, d_offsets, n, p.L, pp, "j");
     out->sigma = pp.sigma;
     out->L = pp.L;
-    tm.mark();  // 1
     Rand rd;
     draw_randomness(ctx, p, pp.L, pp.sigma, rd, "j");
     const uint32_t T = p.r * p.z;
     uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
+    tm.mark();  // 1: the walk kernel alone follows
     embed_keys(ctx, pp, rd, keys, nullptr);
     tm.mark();  // 2
     Buckets bk;
-    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, 32, bk, "j");
+    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, 0, bk, "j");
     tm.mark();  // 3
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
     uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j");
     out->n_candidates = cnt;
     out->n_raw = raw;
-    tm.mark();  // 4
     int32_t *dist = ws<int32_t>(ctx, "j_dist", cnt);
+    unsigned long long *d_cols = nullptr;
+    if (tm.on) {
+        d_cols = ws<unsigned long long>(ctx, "j_vcols", 1);
+        EJ_HIP(hipMemsetAsync(d_cols, 0, 8, ctx->stream));
+    }
+    tm.mark();  // 4: the verification kernel alone follows
     verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, pairs, cnt, p.K, nullptr,
-           dist);
+           dist, nullptr, nullptr, 0, 0, d_cols);
     tm.mark();  // 5
     uint64_t nout = 0;
     uint32_t *opairs = nullptr;
@@ -204,6 +209,15 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     out->ms_candidates = tm.between(3, 4);
     out->ms_verify = tm.between(4, 5);
     out->ms_output = tm.between(5, 6);
+    if (tm.on) {
+        std::vector<uint32_t> J(p.r);
+        EJ_HIP(hipMemcpyAsync(J.data(), rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        uint64_t steps = 0;
+        for (uint32_t x : J) steps += x;
+        out->walk_steps = steps * n;
+        if (cnt) read_back(ctx, d_cols, 8, &out->verify_columns);
+    }
 }
 
 }  // namespace ej
@@ -387,7 +401,7 @@ ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offse
     if (!d_offsets || (count && (!d_pairs || !d_dist))) return EJ_EINVAL;
     return run_guarded(ctx, [&] {
         if (!d_Kq && verify_lanes_for(K) == 0)
-            fail(EJ_EUNSUPPORTED, "K above 1022 is not supported");
+            fail(EJ_EUNSUPPORTED, "K above 2046 is not supported");
         Prep pp;
         prepare(ctx, d_chars, d_offsets, n, 0, pp, "v", nullptr, 0, 0, false);
         if (count) {

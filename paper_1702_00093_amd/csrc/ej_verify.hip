@@ -1,36 +1,41 @@
 // Stage A5: threshold edit distance of candidate pairs (Section 3.3).
 //
-// Ukkonen's observation is that only the 2K+1 diagonals |i - j| <= K of the
-// dynamic-programming table matter when the answer is compared with K.  The
-// kernel evaluates that band with Myers' bit-vector recurrence (vertical and
-// horizontal +1/-1 deltas as bit masks, one column of the table per step),
-// in a diagonal-aligned form: bit k of the state always holds diagonal
-// k - Kb, so the band slides down one row per column by shifting the state
-// right by one bit.
+// Ukkonen's observation is that only a band of diagonals of the
+// dynamic-programming table matters when the answer is compared with K.  For
+// strings x (rows, the longer one) and y (columns), with d* = |x| - |y|, a
+// path through diagonal d costs at least |d| + |d - d*|, so a path of cost
+// <= K stays on the K + 1 diagonals lo..hi with lo = -floor((K - d*)/2) and
+// hi = d* + floor((K - d*)/2).  The kernel evaluates that band with Myers'
+// bit-vector recurrence (vertical and horizontal +1/-1 deltas as bit masks,
+// one table column per step) in a diagonal-aligned form: bit k of the state
+// always holds diagonal k + lo, so the band slides down one row per column
+// by shifting the state right by one bit.
 //
-//  * Cells just outside the band are replaced by upper bounds (the row above
-//    the band grows by +1 to the right, the row below the band by +1
-//    downwards).  Every computed value is then >= the true value, and exact
-//    wherever the true value is <= Kb, because such a cell is reached by an
-//    optimal path that never leaves the band.  The result min(value, K+1)
-//    therefore equals min(ED, K+1).
+//  * Cells just outside the band are replaced by upper bounds (no move from
+//    above the band's top row; a +1 vertical delta below its bottom row).
+//    Every computed value is then >= the true value, and exact wherever an
+//    optimal path of cost <= K passes, because such a path never leaves the
+//    band.  The result min(value, K+1) therefore equals min(ED, K+1).
 //  * Rows above row 0 are virtual rows with D[i][j] = j - i; they are
 //    consistent with the recurrence, which removes all special cases at the
 //    top-left corner.
-//  * The value on the diagonal of the final cell, d* = |x| - |y|, is tracked
-//    column by column: along a diagonal the value grows by 0 or 1, and it
-//    stays put exactly when the characters match or a horizontal or
-//    vertical -1 delta enters the cell.  Text columns past the end of a
-//    shorter text match everything (a padding character whose match mask is
-//    all ones), so finished pairs keep their value while the rest of the
-//    wave continues.  A value above K ends the pair early.
+//  * The value on diagonal d* (the final cell's) is tracked column by
+//    column: along a diagonal the value grows by 0 or 1, and it stays put
+//    exactly when the characters match or a horizontal or vertical -1 delta
+//    enters the cell.  Cells of diagonal d* whose true value is <= K are
+//    exact (their optimal paths obey the same diagonal bound), so a value
+//    above K ends the pair early.
 //
 // GPU mapping: a pair owns NL lanes of a wave (32 band bits per lane, NL =
-// ceil((2K+2)/32)); a wave holds floor(64/NL) pairs.  The W-bit addition of
+// ceil((K+2)/32)); a wave holds floor(64/NL) pairs.  The W-bit addition of
 // Myers' step is a 32-bit add per lane plus a carry-lookahead across lanes
 // done on two ballots with scalar arithmetic; the one-bit shift across lanes
 // is a DPP wave_shl.  The match masks of the pattern (one bit array per
-// symbol, the "Peq" table) and the text live in LDS.
+// symbol) live in LDS; the text is streamed from HBM one 32-column block
+// ahead.  Verification runs in two passes: every pair for the first C1
+// columns (most false candidates are rejected there), then the surviving
+// pairs, compacted, from their saved state -- so that waves are not held by
+// one long pair while the rest of their lanes idle.
 #include <algorithm>
 
 #include "ej_internal.h"
@@ -39,72 +44,189 @@ namespace ej {
 
 namespace {
 
-__device__ inline uint32_t dpp_from_next_lane(uint32_t x) {
-    // lane i receives x of lane i+1 (lane 63 receives 0)
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x130, 0xf, 0xf, false);
+constexpr uint32_t NO_LIMIT = 0xFFFFFFFFu;
+constexpr uint32_t DECIDED = 0xFFFFFFFFu;
+
+// How a pair's lanes are laid out in the wave, which decides how the
+// one-bit shift and the carries cross lanes:
+//   LANES_ONE  one lane per pair: no cross-lane traffic at all;
+//   LANES_ROW  16 lanes per pair = one DPP row: row_shl gives the top lane 0;
+//   LANES_WAVE 64 lanes per pair: wave_shl gives lane 63 zero and the carry
+//              out of lane 63 falls off the 64-bit scalar add;
+//   LANES_ANY  any other width: wave_shl plus a mask, carries cut per pair.
+enum { LANES_ONE = 0, LANES_ROW = 1, LANES_WAVE = 2, LANES_ANY = 3 };
+
+// s = a + b; the carry-out of every lane lands in one wave-wide mask.
+__device__ inline uint32_t add_carry_mask(uint32_t a, uint32_t b, uint64_t &carry) {
+    uint32_t s;
+    asm("v_add_co_u32 %0, %1, %2, %3" : "=v"(s), "=s"(carry) : "v"(a), "v"(b));
+    return s;
 }
 
+template <int MODE>
+__device__ inline uint32_t from_next_lane(uint32_t x, uint32_t keep) {
+    if (MODE == LANES_ROW)  // row_shl:1, lanes 15/31/47/63 read 0
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x101, 0xf, 0xf, true);
+    const uint32_t y = (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130, 0xf, 0xf, true);
+    return MODE == LANES_WAVE ? y : (y & keep);
+}
+
+// 32 columns of Myers' step in the diagonal-aligned band.  FAST counts the
+// tracked diagonal with a masked popcount (no pair's text ends inside the
+// block); otherwise one bit per column is collected into acc.
+template <int MODE, bool FAST>
+__device__ inline void myers_block(const uint32_t *Eq, uint32_t &Pv, uint32_t &Mv, uint32_t &Z,
+                                   uint32_t &acc, uint32_t kmask, uint32_t kbit, uint64_t notlast,
+                                   uint32_t keep) {
+#pragma unroll
+    for (uint32_t s = 0; s < 32; s++) {
+        const uint32_t eq = Eq[s];
+        const uint32_t Xv = eq | Mv;
+        uint32_t sum;
+        if (MODE == LANES_ONE) {
+            sum = (eq & Pv) + Pv;
+        } else {
+            uint64_t G;
+            sum = add_carry_mask(eq & Pv, Pv, G);
+            uint64_t P = __builtin_amdgcn_ballot_w64(sum == 0xFFFFFFFFu);
+            if (MODE != LANES_WAVE) {
+                G &= notlast;
+                P &= notlast;
+            }
+            const uint64_t cin = ((G | P) + G) ^ P;
+            sum += __builtin_amdgcn_inverse_ballot_w64(cin) ? 1u : 0u;
+        }
+        const uint32_t Xh = (sum ^ Pv) | eq;
+        const uint32_t Ph = Mv | ~(Xh | Pv);
+        const uint32_t Mh = Pv & Xh;
+        const uint32_t nx = MODE == LANES_ONE ? 0u : from_next_lane<MODE>(Xv, keep);
+        const uint32_t Xv1 = __builtin_amdgcn_alignbit(nx, Xv, 1);
+        Pv = Mh | ~(Xv1 | Ph);
+        Mv = Ph & Xv1;
+        if (FAST)
+            Z += (uint32_t)__builtin_popcount((Xv1 | Mh) & kmask);
+        else
+            acc |= (((Xv1 | Mh) >> kbit) & 1u) << s;
+    }
+}
+
+// The 32 text symbols of columns jb+1 .. jb+32 (bytes y[jb .. jb+31]) as 8
+// little-endian dwords; symbols at or past position nn read as 0.  Reads
+// stay within y[0 .. nn+35] (the code arrays carry 64 bytes of padding).
+__device__ inline void load_text_block(const uint8_t *y, uint32_t nn, uint32_t jb, uint32_t tw[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; q++) tw[q] = 0;
+    if (jb >= nn) return;
+    const uintptr_t a = (uintptr_t)(y + jb);
+    const uint32_t *base = (const uint32_t *)(a & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3) * 8;
+    uint32_t w[9];
+#pragma unroll
+    for (int q = 0; q < 9; q++) w[q] = base[q];
+#pragma unroll
+    for (int q = 0; q < 8; q++) tw[q] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh);
+    const uint32_t valid = nn - jb;  // > 0
+    if (valid < 32) {
+#pragma unroll
+        for (uint32_t q = 0; q < 8; q++) {
+            const uint32_t b0 = 4 * q;
+            uint32_t keep;
+            if (valid >= b0 + 4)
+                keep = 0xFFFFFFFFu;
+            else if (valid <= b0)
+                keep = 0u;
+            else
+                keep = (1u << (8 * (valid - b0))) - 1u;
+            tw[q] &= keep;
+        }
+    }
+}
+
+struct PairView {
+    const uint8_t *xp, *yp;
+    uint32_t m, nn, Kp, dstar, O;  // O = -lo = floor((Kp - d*)/2)
+    bool skip;
+};
+
+__device__ inline PairView view_pair(const uint8_t *codes_a, const uint64_t *off_a, uint64_t base_a,
+                                     const uint8_t *codes_b, const uint64_t *off_b, uint64_t base_b,
+                                     const uint64_t *pairs, const uint32_t *Kq, uint32_t K,
+                                     uint64_t pidx, bool act) {
+    PairView v;
+    v.xp = codes_a;
+    v.yp = codes_a;
+    v.m = 0;
+    v.nn = 0;
+    v.Kp = K;
+    if (act) {
+        uint64_t code = pairs[pidx];
+        uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
+        uint64_t oa = off_a[a], ob = off_b[b];
+        uint32_t la = (uint32_t)(off_a[a + 1] - oa), lb = (uint32_t)(off_b[b + 1] - ob);
+        const uint8_t *pa = codes_a + (oa - base_a), *pb = codes_b + (ob - base_b);
+        if (Kq) v.Kp = Kq[pidx];
+        if (la >= lb) {
+            v.xp = pa; v.m = la; v.yp = pb; v.nn = lb;
+        } else {
+            v.xp = pb; v.m = lb; v.yp = pa; v.nn = la;
+        }
+    }
+    v.skip = !act || v.m - v.nn > v.Kp;
+    if (v.skip) {
+        v.m = 0;
+        v.nn = 0;
+    }
+    // a skipped pair keeps d* = 0 so that one lane of its tile owns the
+    // (constant) result K_p + 1
+    v.dstar = v.m - v.nn;
+    v.O = v.skip ? 0u : (v.Kp - v.dstar) / 2;
+    return v;
+}
+
+// One pass over a list of pairs.  Pass 1 (resume == 0) starts every pair at
+// column 0 and stops at column jlim; the owner lane writes aux[pidx] = Z for
+// a pair still undecided there (its Pv/Mv go to `state`) and DECIDED for the
+// others.  Pass 2 (resume == 1) takes the pairs listed in `list`, restores
+// their state and runs them to the end.
+template <int MODE>
 __global__ void __launch_bounds__(64)
     k_verify(const uint8_t *__restrict__ codes_a, const uint64_t *__restrict__ off_a,
              uint64_t base_a, const uint8_t *__restrict__ codes_b,
              const uint64_t *__restrict__ off_b, uint64_t base_b,
-             const uint64_t *__restrict__ pairs, uint64_t count, uint32_t K,
-             const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL, uint32_t tpw,
-             uint32_t wpp, uint32_t tstride, uint32_t tile_words, int32_t *__restrict__ dist) {
+             const uint64_t *__restrict__ pairs, uint64_t count, const uint32_t *__restrict__ list,
+             uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL,
+             uint32_t tpw, uint32_t wpp, uint32_t jbeg, uint32_t jlim, int resume,
+             uint32_t *__restrict__ state, uint32_t *__restrict__ aux,
+             int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
-    const uint32_t Kb = 16 * NL - 1;  // band half-width: 32*NL >= 2*Kb + 2
-    uint64_t last = 0;
+    const uint32_t tile_words = sigma * wpp;
+    uint64_t last = 0;  // top lane of every pair, and lanes outside pairs
     for (uint32_t q = 0; q < 64; q++)
         if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
+    const uint64_t notlast = ~last;
     const uint32_t keep = (l == NL - 1 || !in_tile) ? 0u : 0xFFFFFFFFu;
-    uint32_t *tb = lds + (in_tile ? tile : 0) * tile_words;
-
-    // padding symbol: matches every row
-    for (uint32_t t = 0; t < tpw; t++)
-        for (uint32_t w = lane; w < wpp; w += 64) lds[t * tile_words + sigma * wpp + w] = ~0u;
+    const uint32_t *peq = lds + (in_tile ? tile : 0) * tile_words;
 
     for (uint64_t g = blockIdx.x; g * tpw < count; g += gridDim.x) {
-        const uint64_t pidx = g * tpw + tile;
-        const bool act = in_tile && pidx < count;
-        uint32_t m = 0, nn = 0, Kp = K;
-        const uint8_t *xp = codes_a, *yp = codes_a;
-        if (act) {
-            uint64_t code = pairs[pidx];
-            uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
-            uint64_t oa = off_a[a], ob = off_b[b];
-            uint32_t la = (uint32_t)(off_a[a + 1] - oa), lb = (uint32_t)(off_b[b + 1] - ob);
-            const uint8_t *pa = codes_a + (oa - base_a), *pb = codes_b + (ob - base_b);
-            if (Kq) Kp = Kq[pidx];
-            if (la >= lb) {
-                xp = pa; m = la; yp = pb; nn = lb;
-            } else {
-                xp = pb; m = lb; yp = pa; nn = la;
-            }
-        }
-        const bool skip = !act || m - nn > Kp;
-        if (skip) {
-            m = 0;
-            nn = 0;
-        }
-        // a skipped pair keeps d* = 0 so that one lane of its tile owns the
-        // (constant) result K_p + 1
-        const uint32_t dstar = m - nn;
+        const uint64_t k = g * tpw + tile;  // index into the (listed) pairs
+        const bool act = in_tile && k < count;
+        const uint64_t pidx = act ? (list ? (uint64_t)list[k] : k) : 0;
+        const PairView v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K,
+                                     pidx, act);
         __syncthreads();
-        // ---- match masks of each pattern and the text of each pair -> LDS
+        // ---- match masks of each tile's pattern -> LDS; the bit index of
+        //      pattern row i (1-based) is i + O
         for (uint32_t t = 0; t < tpw; t++) {
-            const uint32_t mt = readlane_u32(m, t * NL);
-            const uint32_t nt = readlane_u32(nn, t * NL);
-            const uint64_t xa = readlane_u64((uint64_t)(uintptr_t)xp, t * NL);
-            const uint64_t ya = readlane_u64((uint64_t)(uintptr_t)yp, t * NL);
-            const uint8_t *xt = (const uint8_t *)(uintptr_t)xa;
-            const uint8_t *yt = (const uint8_t *)(uintptr_t)ya;
+            const uint32_t mt = readlane_u32(v.m, t * NL);
+            const uint32_t Ot = readlane_u32(v.O, t * NL);
+            const uint8_t *xt =
+                (const uint8_t *)(uintptr_t)readlane_u64((uint64_t)(uintptr_t)v.xp, t * NL);
             uint32_t *pq = lds + t * tile_words;
-            // bit index of pattern row i (1-based) is i + Kb
             for (uint32_t q = 0; q < wpp / 2; q++) {
-                const int row = (int)(64 * q + lane) - (int)Kb;
+                const int row = (int)(64 * q + lane) - (int)Ot;
                 uint32_t c = 0xFFFFFFFFu;
                 if (row >= 1 && row <= (int)mt) c = xt[row - 1];
                 for (uint32_t ch = 0; ch < sigma; ch++) {
@@ -113,70 +235,91 @@ __global__ void __launch_bounds__(64)
                     if (lane == 1) pq[ch * wpp + 2 * q + 1] = (uint32_t)(msk >> 32);
                 }
             }
-            uint8_t *tx = (uint8_t *)(pq + (sigma + 1) * wpp);
-            for (uint32_t u = lane; u < tstride; u += 64) tx[u] = u < nt ? yt[u] : (uint8_t)sigma;
         }
         __syncthreads();
 
-        uint32_t nmax = nn;
-        for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, d, 64));
-
-        // ---- column 0: D[i][0] = |i|; bit k holds row k - Kb
-        const int lo = 32 * (int)l;
-        uint32_t Mv;
-        if ((int)Kb >= lo + 31)
-            Mv = ~0u;
-        else if ((int)Kb < lo)
-            Mv = 0u;
-        else
-            Mv = (1u << ((int)Kb - lo + 1)) - 1u;
-        uint32_t Pv = ~Mv;
-        const uint32_t kstar = Kb + dstar;
+        // ---- state at column jbeg
+        const uint32_t kstar = v.O + v.dstar;
         const bool owner = in_tile && (kstar >> 5) == l;
-        const uint32_t kmask = owner ? (1u << (kstar & 31)) : 0u;
-        uint32_t Z = 0;  // columns in which the tracked diagonal did not grow
-        const uint32_t *peq = tb;
-        const uint32_t *txt = tb + (sigma + 1) * wpp;
-        uint32_t jdone = 0;
-        for (uint32_t jb = 0; jb < nmax; jb += 32) {
+        const uint32_t kbit = kstar & 31;
+        uint32_t Pv, Mv, Z = 0;
+        if (resume) {
+            Pv = act ? state[(pidx * NL + l) * 2] : 0u;
+            Mv = act ? state[(pidx * NL + l) * 2 + 1] : 0u;
+            if (owner && act) Z = aux[pidx];
+        } else {
+            // D[i][0] = |i|: bit k holds row k - O, rows <= 0 have delta -1
+            const int lo = 32 * (int)l;
+            const int Oi = (int)v.O;
+            if (Oi >= lo + 31)
+                Mv = ~0u;
+            else if (Oi < lo)
+                Mv = 0u;
+            else
+                Mv = (1u << (Oi - lo + 1)) - 1u;
+            Pv = ~Mv;
+        }
+        uint32_t nmax = v.nn;
+        for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, d, 64));
+        const uint32_t jend = min(nmax, jlim);
+        uint32_t jdone = jbeg;
+        uint32_t tw[8], tn[8];
+        load_text_block(v.yp, v.nn, jbeg, tw);
+        for (uint32_t jb = jbeg; jb < jend; jb += 32) {
+            load_text_block(v.yp, v.nn, jb + 32, tn);
             uint32_t Eq[32];
             const uint32_t wbase = (jb >> 5) + l;
-            uint32_t tw = 0;
 #pragma unroll
             for (uint32_t s = 0; s < 32; s++) {
-                if ((s & 3) == 0) tw = txt[(jb + s) >> 2];
-                const uint32_t c = (tw >> (8 * (s & 3))) & 0xFFu;
+                const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
                 const uint32_t *pa = peq + c * wpp + wbase;
                 Eq[s] = __builtin_amdgcn_alignbit(pa[1], pa[0], s);
             }
-#pragma unroll
-            for (uint32_t s = 0; s < 32; s++) {
-                const uint32_t eq = Eq[s];
-                const uint32_t Xv = eq | Mv;
-                uint32_t sum = (eq & Pv) + Pv;
-                const uint64_t G = __builtin_amdgcn_ballot_w64(sum < Pv);
-                const uint64_t P = __builtin_amdgcn_ballot_w64(sum == 0xFFFFFFFFu);
-                const uint64_t U = (G | P) & ~last, V = G & ~last;
-                const uint64_t cin = (U + V) ^ U ^ V;
-                sum += __builtin_amdgcn_inverse_ballot_w64(cin) ? 1u : 0u;
-                const uint32_t Xh = (sum ^ Pv) | eq;
-                const uint32_t Ph = Mv | ~(Xh | Pv);
-                const uint32_t Mh = Pv & Xh;
-                const uint32_t nx = dpp_from_next_lane(Xv) & keep;
-                const uint32_t Xv1 = __builtin_amdgcn_alignbit(nx, Xv, 1);
-                Pv = Mh | ~(Xv1 | Ph);
-                Mv = Ph & Xv1;
-                Z += __builtin_popcount((Xv1 | Mh) & kmask);
+            // columns past the end of a pair's text do not count; a block
+            // where no text ends takes the masked-popcount path
+            const bool ends_here = in_tile && v.nn > jb && v.nn < jb + 32;
+            if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
+                const uint32_t km = (owner && jb + 32 <= v.nn) ? (1u << kbit) : 0u;
+                uint32_t unused = 0;
+                myers_block<MODE, true>(Eq, Pv, Mv, Z, unused, km, kbit, notlast, keep);
+            } else {
+                uint32_t acc = 0;
+                myers_block<MODE, false>(Eq, Pv, Mv, Z, acc, 0u, kbit, notlast, keep);
+                const uint32_t ncol = v.nn > jb ? min(v.nn - jb, 32u) : 0u;
+                const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
+                if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
             }
             jdone = jb + 32;
-            const uint32_t Vd = dstar + jdone - Z;
-            const bool live = owner && !skip && Vd <= Kp && jdone < nn;
+#pragma unroll
+            for (int q = 0; q < 8; q++) tw[q] = tn[q];
+            const uint32_t cols = min(jdone, v.nn);
+            const bool live = owner && !v.skip && v.dstar + cols - Z <= v.Kp && jdone < v.nn;
             if (__builtin_amdgcn_ballot_w64(live) == 0) break;
         }
+        const uint32_t cols = min(jdone, v.nn);
+        const uint32_t Vd = v.dstar + cols - Z;
+        // Z (hence the decision) lives in the owner lane; every lane of the
+        // tile learns it from a ballot
+        const bool und_owner =
+            owner && act && !v.skip && Vd <= v.Kp && jdone < v.nn && jlim != NO_LIMIT;
+        const uint64_t und_mask = __builtin_amdgcn_ballot_w64(und_owner);
+        const uint32_t owner_lane = tile * NL + (kstar >> 5);
+        const bool undecided = in_tile && ((und_mask >> (owner_lane & 63)) & 1ull);
+        if (act && undecided) {
+            // pass 1 stops here: keep the state of the pair for pass 2
+            state[(pidx * NL + l) * 2] = Pv;
+            state[(pidx * NL + l) * 2 + 1] = Mv;
+        }
         if (owner && act) {
-            uint32_t res = skip ? Kp + 1 : dstar + jdone - Z;
-            if (res > Kp + 1) res = Kp + 1;
-            dist[pidx] = (int32_t)res;
+            if (undecided) {
+                aux[pidx] = Z;
+            } else {
+                uint32_t res = v.skip ? v.Kp + 1 : Vd;
+                if (res > v.Kp + 1) res = v.Kp + 1;
+                dist[pidx] = (int32_t)res;
+                if (aux && !resume) aux[pidx] = DECIDED;
+            }
+            if (columns) atomicAdd(columns, (unsigned long long)(cols - min(jbeg, cols)));
         }
     }
 }
@@ -190,63 +333,124 @@ __global__ void k_max_u32(const uint32_t *__restrict__ a, uint64_t n, uint32_t *
     if ((threadIdx.x & 63) == 0) atomicMax(out, mx);
 }
 
+// flags[k] = 1 for the pairs pass 1 left undecided
+__global__ void k_alive_flags(const uint32_t *__restrict__ aux, uint64_t count,
+                              uint32_t *__restrict__ flags) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < count;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        flags[e] = aux[e] != DECIDED ? 1u : 0u;
+}
+
+__global__ void k_alive_list(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
+                             uint64_t count, uint32_t *__restrict__ list) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < count;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        if (flags[e]) list[pos[e]] = (uint32_t)e;
+}
+
+inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
+    uint64_t g = (work + block - 1) / block;
+    uint64_t cap = (uint64_t)ctx->num_cu * 16;
+    if (g > cap) g = cap;
+    if (g == 0) g = 1;
+    return (uint32_t)g;
+}
+
 }  // namespace
 
 uint32_t verify_lanes_for(uint32_t K) {
-    uint64_t nl = (2ull * K + 2 + 31) / 32;
-    if (nl == 0) nl = 1;
+    uint64_t nl = (K + 2ull + 31) / 32;
     return nl <= 64 ? (uint32_t)nl : 0u;
 }
 
 void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
             uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
             const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b,
-            const uint64_t *d_offsets_b, uint64_t base_b, uint32_t maxlen_b) {
+            const uint64_t *d_offsets_b, uint64_t base_b, uint32_t maxlen_b,
+            unsigned long long *d_columns) {
     if (count == 0) return;
+    if (count >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "more than 2^32 pairs in one verification");
     uint32_t Kmax = K;
     if (d_Kq) {
         uint32_t *d_mx = ws<uint32_t>(ctx, "verify_kmax", 1);
         EJ_HIP(hipMemsetAsync(d_mx, 0, 4, ctx->stream));
-        uint64_t g = std::min<uint64_t>((count + 255) / 256, (uint64_t)ctx->num_cu * 8);
-        hipLaunchKernelGGL(k_max_u32, dim3((uint32_t)g), dim3(256), 0, ctx->stream, d_Kq, count,
-                           d_mx);
+        hipLaunchKernelGGL(k_max_u32, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
+                           d_Kq, count, d_mx);
         EJ_CHECK_LAUNCH();
         read_back(ctx, d_mx, 4, &Kmax);
     }
     const uint32_t NL = verify_lanes_for(Kmax);
     if (NL == 0)
-        fail(EJ_EUNSUPPORTED, "threshold " + std::to_string(Kmax) + " exceeds 1022 (band > 2048 bits)");
+        fail(EJ_EUNSUPPORTED,
+             "threshold " + std::to_string(Kmax) + " exceeds 2046 (band > 2048 bits)");
     if (!d_codes_b) {
         d_codes_b = d_codes;
         d_offsets_b = d_offsets;
         base_b = base;
         maxlen_b = maxlen;
     }
+    const uint32_t sig = sigma ? sigma : 1;
     const uint32_t W = 32 * NL;
-    const uint32_t mx = std::max(maxlen, maxlen_b);
     const uint32_t mtext = std::min(maxlen, maxlen_b);
-    uint32_t wpp = (mx + W + 95) / 32;
+    // Eq reads reach word (ncols-1)/32 + NL; pattern bits reach ncols + K
+    uint32_t wpp = (mtext + W + 64) / 32 + 2;
     wpp = (wpp + 1) & ~1u;
-    const uint32_t tstride = ((mtext + 31) / 32) * 32 + 32;
-    const uint32_t tile_words = (sigma + 1) * wpp + tstride / 4;
-    const uint32_t tile_bytes = tile_words * 4;
+    const uint32_t tile_bytes = sig * wpp * 4;
     uint32_t tpw = 64 / NL;
-    uint32_t budget = 48 * 1024;
+    uint32_t budget = ctx->tune.verify_lds_budget;
     if ((int)budget > ctx->lds_max) budget = (uint32_t)ctx->lds_max;
     if (tile_bytes > budget) budget = (uint32_t)ctx->lds_max;
     if (tile_bytes > budget)
-        fail(EJ_EUNSUPPORTED, "strings too long for the LDS-resident verification tile (" +
-                                  std::to_string(tile_bytes) + " bytes)");
+        fail(EJ_EUNSUPPORTED, "strings too long for the LDS-resident match masks (" +
+                                  std::to_string(tile_bytes) + " bytes per pair)");
     tpw = std::min(tpw, budget / tile_bytes);
-    size_t lds = (size_t)tpw * tile_bytes;
-    uint64_t ngroups = (count + tpw - 1) / tpw;
-    uint64_t grid = std::min<uint64_t>(ngroups, (uint64_t)ctx->num_cu * 16);
+    const size_t lds = (size_t)tpw * tile_bytes;
+    const int mode = NL == 1 ? LANES_ONE : NL == 16 ? LANES_ROW : NL == 64 ? LANES_WAVE : LANES_ANY;
+    auto kern = mode == LANES_ONE    ? k_verify<LANES_ONE>
+                : mode == LANES_ROW  ? k_verify<LANES_ROW>
+                : mode == LANES_WAVE ? k_verify<LANES_WAVE>
+                                     : k_verify<LANES_ANY>;
     if (lds > 65536)
-        EJ_HIP(hipFuncSetAttribute((const void *)k_verify,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(k_verify, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
-                       d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs, count, K, d_Kq,
-                       sigma, NL, tpw, wpp, tstride, tile_words, d_dist);
+        EJ_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds));
+    const uint32_t C1 = ctx->tune.verify_pass1_cols & ~31u;
+    const bool two_pass = C1 > 0 && C1 < mtext;
+    uint32_t *state = nullptr, *aux = nullptr;
+    if (two_pass) {
+        state = ws<uint32_t>(ctx, "verify_state", count * NL * 2);
+        aux = ws<uint32_t>(ctx, "verify_aux", count);
+    }
+    const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;
+    {
+        uint64_t ngroups = (count + tpw - 1) / tpw;
+        uint64_t grid = std::min<uint64_t>(ngroups, cap);
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
+                           d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs, count,
+                           (const uint32_t *)nullptr, K, d_Kq, sig, NL, tpw, wpp, 0u,
+                           two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
+        EJ_CHECK_LAUNCH();
+    }
+    if (!two_pass) return;
+    uint32_t *flags = ws<uint32_t>(ctx, "verify_flags", count);
+    uint32_t *pos = ws<uint32_t>(ctx, "verify_pos", count);
+    uint64_t *d_nalive = ws<uint64_t>(ctx, "verify_nalive", 1);
+    hipLaunchKernelGGL(k_alive_flags, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
+                       (const uint32_t *)aux, count, flags);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, flags, pos, count, d_nalive);
+    uint64_t nalive = 0;
+    read_back(ctx, d_nalive, 8, &nalive);
+    if (nalive == 0) return;
+    uint32_t *list = ws<uint32_t>(ctx, "verify_list", nalive);
+    hipLaunchKernelGGL(k_alive_list, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
+                       (const uint32_t *)flags, (const uint32_t *)pos, count, list);
+    EJ_CHECK_LAUNCH();
+    uint64_t ngroups = (nalive + tpw - 1) / tpw;
+    uint64_t grid = std::min<uint64_t>(ngroups, cap);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
+                       d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs, nalive,
+                       (const uint32_t *)list, K, d_Kq, sig, NL, tpw, wpp, C1, NO_LIMIT, 1,
+                       state, aux, d_dist, d_columns);
     EJ_CHECK_LAUNCH();
 }
 

@@ -57,3 +57,12 @@ def test_version_and_null_handling(libpath):
 def test_gfx950_code_object_present(libpath):
     data = open(libpath, "rb").read()
     assert b"gfx950" in data
+
+
+def test_tune_calls_reject_null_context(libpath):
+    import ctypes as C
+    import paper_1702_00093_amd as ej
+    L = ej.lib()
+    v = C.c_uint32()
+    assert L.ej_tune_set(None, b"radix_bits", 8) == ej.EJ_EINVAL
+    assert L.ej_tune_get(None, b"radix_bits", C.byref(v)) == ej.EJ_EINVAL

@@ -146,7 +146,7 @@ def test_bucket_key_bits_do_not_change_candidates(ej, ctx, oracle_lib):
 
 # ------------------------------------------------------- verification ----
 
-@pytest.mark.parametrize("K", [0, 1, 7, 15, 16, 31, 50, 63, 100, 250, 400, 500, 1000, 1022])
+@pytest.mark.parametrize("K", [0, 1, 7, 15, 16, 29, 30, 31, 50, 63, 100, 250, 400, 500, 1000, 1022, 2046])
 def test_verify_matches_ukkonen(ej, ctx, oracle_lib, K):
     import torch
     rng = np.random.default_rng(K)
@@ -223,7 +223,7 @@ def test_invalid_arguments_are_rejected(ej, ctx):
         ctx.join(col.chars, col.offsets, 2, 0, 4, 4)
     assert e.value.status == ej.EJ_EINVAL
     with pytest.raises(ej.EmbedJoinError) as e:
-        ctx.join(col.chars, col.offsets, 2000, 1, 1, 1)
+        ctx.join(col.chars, col.offsets, 3000, 1, 1, 1)
     assert e.value.status == ej.EJ_EUNSUPPORTED
     bad = np.array([0, 4, 2], dtype=np.uint64)
     with pytest.raises(ej.EmbedJoinError) as e:
@@ -266,3 +266,53 @@ def test_tiny_dna_recall_point(ej, ctx, oracle_lib):
     S = col.strings()
     for (a, b), d in zip(res.pairs.tolist(), res.dist.tolist()):
         assert oracle_lib.ed_full(S[a], S[b]) == d <= K
+
+
+# ------------------------------------------------------- launch knobs ----
+
+@pytest.mark.parametrize("c1", [0, 32, 64, 160])
+def test_verify_two_pass_resume(ej, ctx, oracle_lib, c1):
+    """Pass 1 stops after c1 columns and pass 2 resumes the undecided pairs
+    from their saved state: same distances as one pass and as the oracle."""
+    import torch
+    rng = np.random.default_rng(c1 + 1)
+    col = sd.clusters(200 + c1, 10, lambda rr, b: 4, lambda rr: rr.integers(150, 700),
+                      lambda rr, LL: rr.poisson(25))
+    n = col.n
+    a = rng.integers(0, n, size=300)
+    b = rng.integers(0, n, size=300)
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    chars, offs = to_device(col)
+    old = ctx.tune_get("verify_pass1_cols")
+    try:
+        ctx.tune_set("verify_pass1_cols", c1)
+        for K in (3, 60, 130):
+            want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+            _say(f"two-pass c1={c1} K={K}")
+            got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+            assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+    finally:
+        ctx.tune_set("verify_pass1_cols", old)
+
+
+def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
+    col = sd.clusters(9, 40, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(100, 900),
+                      lambda rr, LL: rr.poisson(12))
+    K, r, z, m, L = 40, 4, 6, 4, 64
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 5, L)
+    knobs = [("radix_bits", 4), ("radix_bits", 11), ("bucket_key_bits", 5),
+             ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
+             ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64)]
+    for name, val in knobs:
+        old = ctx.tune_get(name)
+        try:
+            ctx.tune_set(name, val)
+            _say(f"knob {name}={val}")
+            res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=5, L=L)
+            _assert_join_equal(res, ref)
+        finally:
+            ctx.tune_set(name, old)
+    with pytest.raises(ej.EmbedJoinError):
+        ctx.tune_set("radix_bits", 3)
+    with pytest.raises(ej.EmbedJoinError):
+        ctx.tune_set("no_such_knob", 1)
