@@ -50,7 +50,22 @@ def parse():
                     help="use the workload's stated (r, z, m, L) instead of the recall-calibrated point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES bytes (5 times): "
+                         "the reference for scaling HBM traffic counters")
     return ap.parse_args()
+
+
+def copy_probe(nbytes):
+    import torch
+    x = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reads_per_copy": nbytes,
+                      "writes_per_copy": nbytes, "copies": 5}), flush=True)
 
 
 # Recall-calibrated parameter points: at the stated parameters
@@ -148,6 +163,9 @@ def main():
                                    "part of this build (see DESIGN.md for the sharding plan)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     import torch
     import paper_1702_00093_amd as ej
     from oracle import oracle

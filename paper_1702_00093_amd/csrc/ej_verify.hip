@@ -74,13 +74,19 @@ __device__ inline uint32_t from_next_lane(uint32_t x, uint32_t keep) {
 // 32 columns of Myers' step in the diagonal-aligned band.  FAST counts the
 // tracked diagonal with a masked popcount (no pair's text ends inside the
 // block); otherwise one bit per column is collected into acc.
+// The match word of column jb+1+s is read from LDS inside the step (text
+// symbol s of tw selects the symbol's bit array; the lane's two words at
+// `slot` are funnel-shifted by s), which keeps the live registers low.
 template <int MODE, bool FAST>
-__device__ inline void myers_block(const uint32_t *Eq, uint32_t &Pv, uint32_t &Mv, uint32_t &Z,
+__device__ inline void myers_block(const uint32_t *peq, uint32_t stride, uint32_t slot,
+                                   const uint32_t tw[8], uint32_t &Pv, uint32_t &Mv, uint32_t &Z,
                                    uint32_t &acc, uint32_t kmask, uint32_t kbit, uint64_t notlast,
                                    uint32_t keep) {
 #pragma unroll
     for (uint32_t s = 0; s < 32; s++) {
-        const uint32_t eq = Eq[s];
+        const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
+        const uint32_t *pa = peq + c * stride + slot;
+        const uint32_t eq = __builtin_amdgcn_alignbit(pa[1], pa[0], s);
         const uint32_t Xv = eq | Mv;
         uint32_t sum;
         if (MODE == LANES_ONE) {
@@ -183,12 +189,22 @@ __device__ inline PairView view_pair(const uint8_t *codes_a, const uint64_t *off
     return v;
 }
 
+// Match masks of a pair live in LDS in one of two layouts:
+//   full (RING = false): word w of symbol c at c*stride + w, stride = wpp,
+//        the whole pattern;
+//   ring (RING = true):  only the NL+1 words the band touches at a time,
+//        word w at slots w % RW and w % RW + RW (stride = 2*RW) so that two
+//        consecutive words are always adjacent; the word entering the band
+//        is computed from the pattern once per 32-column block.
+// Bit b of word w is pattern row 32w + b - O (1-based; rows outside
+// 1..m never match).
+//
 // One pass over a list of pairs.  Pass 1 (resume == 0) starts every pair at
 // column 0 and stops at column jlim; the owner lane writes aux[pidx] = Z for
 // a pair still undecided there (its Pv/Mv go to `state`) and DECIDED for the
 // others.  Pass 2 (resume == 1) takes the pairs listed in `list`, restores
 // their state and runs them to the end.
-template <int MODE>
+template <int MODE, bool RING>
 __global__ void __launch_bounds__(64)
     k_verify(const uint8_t *__restrict__ codes_a, const uint64_t *__restrict__ off_a,
              uint64_t base_a, const uint8_t *__restrict__ codes_b,
@@ -202,13 +218,18 @@ __global__ void __launch_bounds__(64)
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
-    const uint32_t tile_words = sigma * wpp;
+    const uint32_t RW = wpp;                          // ring: words per ring
+    const uint32_t stride = RING ? 2 * RW : wpp;      // words per symbol
+    const uint32_t tile_words = sigma * stride;
+    const uint32_t R = (32 + NL - 1) / NL;            // ring: rows per lane per word
+    const uint32_t nlmask = NL >= 32 ? 0xFFFFFFFFu : ((1u << NL) - 1u);
     uint64_t last = 0;  // top lane of every pair, and lanes outside pairs
     for (uint32_t q = 0; q < 64; q++)
         if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
     const uint64_t notlast = ~last;
     const uint32_t keep = (l == NL - 1 || !in_tile) ? 0u : 0xFFFFFFFFu;
-    const uint32_t *peq = lds + (in_tile ? tile : 0) * tile_words;
+    uint32_t *pq_mine = lds + (in_tile ? tile : 0) * tile_words;
+    const uint32_t *peq = pq_mine;
 
     for (uint64_t g = blockIdx.x; g * tpw < count; g += gridDim.x) {
         const uint64_t k = g * tpw + tile;  // index into the (listed) pairs
@@ -217,22 +238,39 @@ __global__ void __launch_bounds__(64)
         const PairView v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K,
                                      pidx, act);
         __syncthreads();
-        // ---- match masks of each tile's pattern -> LDS; the bit index of
-        //      pattern row i (1-based) is i + O
-        for (uint32_t t = 0; t < tpw; t++) {
-            const uint32_t mt = readlane_u32(v.m, t * NL);
-            const uint32_t Ot = readlane_u32(v.O, t * NL);
-            const uint8_t *xt =
-                (const uint8_t *)(uintptr_t)readlane_u64((uint64_t)(uintptr_t)v.xp, t * NL);
-            uint32_t *pq = lds + t * tile_words;
-            for (uint32_t q = 0; q < wpp / 2; q++) {
-                const int row = (int)(64 * q + lane) - (int)Ot;
-                uint32_t c = 0xFFFFFFFFu;
-                if (row >= 1 && row <= (int)mt) c = xt[row - 1];
-                for (uint32_t ch = 0; ch < sigma; ch++) {
-                    uint64_t msk = __builtin_amdgcn_ballot_w64(c == ch);
-                    if (lane == 0) pq[ch * wpp + 2 * q] = (uint32_t)msk;
-                    if (lane == 1) pq[ch * wpp + 2 * q + 1] = (uint32_t)(msk >> 32);
+        // ---- match masks of the words the first block needs (ring) or of
+        //      the whole pattern (full), 64 rows per ballot
+        {
+            const uint32_t w0 = RING ? (jbeg >> 5) : 0u;
+            const uint32_t nw = RING ? NL + 1 : wpp;
+            for (uint32_t t = 0; t < tpw; t++) {
+                const uint32_t mt = readlane_u32(v.m, t * NL);
+                const uint32_t Ot = readlane_u32(v.O, t * NL);
+                const uint8_t *xt =
+                    (const uint8_t *)(uintptr_t)readlane_u64((uint64_t)(uintptr_t)v.xp, t * NL);
+                uint32_t *pq = lds + t * tile_words;
+                for (uint32_t q = 0; 2 * q < nw; q++) {
+                    const int64_t row = (int64_t)32 * w0 + 64 * q + lane - Ot;
+                    uint32_t c = 0xFFFFFFFFu;
+                    if (row >= 1 && row <= (int64_t)mt) c = xt[row - 1];
+                    const uint32_t wa = w0 + 2 * q, wb = wa + 1;
+                    for (uint32_t ch = 0; ch < sigma; ch++) {
+                        const uint64_t msk = __builtin_amdgcn_ballot_w64(c == ch);
+                        if (RING) {
+                            const uint32_t sa = wa & (RW - 1), sb = wb & (RW - 1);
+                            if (lane == 0) {
+                                pq[ch * stride + sa] = (uint32_t)msk;
+                                pq[ch * stride + sa + RW] = (uint32_t)msk;
+                            }
+                            if (lane == 1) {
+                                pq[ch * stride + sb] = (uint32_t)(msk >> 32);
+                                pq[ch * stride + sb + RW] = (uint32_t)(msk >> 32);
+                            }
+                        } else {
+                            if (lane == 0) pq[ch * stride + wa] = (uint32_t)msk;
+                            if (lane == 1 && wb < wpp) pq[ch * stride + wb] = (uint32_t)(msk >> 32);
+                        }
+                    }
                 }
             }
         }
@@ -267,27 +305,49 @@ __global__ void __launch_bounds__(64)
         load_text_block(v.yp, v.nn, jbeg, tw);
         for (uint32_t jb = jbeg; jb < jend; jb += 32) {
             load_text_block(v.yp, v.nn, jb + 32, tn);
-            uint32_t Eq[32];
-            const uint32_t wbase = (jb >> 5) + l;
+            // ring: pattern rows of the word that enters the band next
+            uint32_t rc[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+            const uint32_t wn = (jb >> 5) + NL + 1;
+            if (RING && in_tile) {
 #pragma unroll
-            for (uint32_t s = 0; s < 32; s++) {
-                const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
-                const uint32_t *pa = peq + c * wpp + wbase;
-                Eq[s] = __builtin_amdgcn_alignbit(pa[1], pa[0], s);
+                for (uint32_t q = 0; q < 4; q++) {
+                    const uint32_t bq = q * NL + l;
+                    const int64_t row = (int64_t)32 * wn + bq - v.O;
+                    if (q < R && bq < 32 && row >= 1 && row <= (int64_t)v.m) rc[q] = v.xp[row - 1];
+                }
             }
+            const uint32_t slot = RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l);
             // columns past the end of a pair's text do not count; a block
             // where no text ends takes the masked-popcount path
             const bool ends_here = in_tile && v.nn > jb && v.nn < jb + 32;
             if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
                 const uint32_t km = (owner && jb + 32 <= v.nn) ? (1u << kbit) : 0u;
                 uint32_t unused = 0;
-                myers_block<MODE, true>(Eq, Pv, Mv, Z, unused, km, kbit, notlast, keep);
+                myers_block<MODE, true>(peq, stride, slot, tw, Pv, Mv, Z, unused, km, kbit, notlast, keep);
             } else {
                 uint32_t acc = 0;
-                myers_block<MODE, false>(Eq, Pv, Mv, Z, acc, 0u, kbit, notlast, keep);
+                myers_block<MODE, false>(peq, stride, slot, tw, Pv, Mv, Z, acc, 0u, kbit, notlast, keep);
                 const uint32_t ncol = v.nn > jb ? min(v.nn - jb, 32u) : 0u;
                 const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
                 if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
+            }
+            if (RING) {
+                // the entering word, for every symbol; the slot it replaces
+                // held word wn - RW, which no lane reads any more
+                const uint32_t sl = wn & (RW - 1);
+                for (uint32_t ch = 0; ch < sigma; ch++) {
+                    uint32_t word = 0;
+                    for (uint32_t q = 0; q < R; q++) {
+                        const uint64_t B = __builtin_amdgcn_ballot_w64(rc[q] == ch);
+                        const uint32_t part = (uint32_t)(B >> (tile * NL)) & nlmask;
+                        word |= q * NL < 32 ? (part << (q * NL)) : 0u;
+                    }
+                    if (in_tile && l == 0) {
+                        pq_mine[ch * stride + sl] = word;
+                        pq_mine[ch * stride + sl + RW] = word;
+                    }
+                }
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
             }
             jdone = jb + 32;
 #pragma unroll
@@ -392,10 +452,19 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     const uint32_t sig = sigma ? sigma : 1;
     const uint32_t W = 32 * NL;
     const uint32_t mtext = std::min(maxlen, maxlen_b);
-    // Eq reads reach word (ncols-1)/32 + NL; pattern bits reach ncols + K
-    uint32_t wpp = (mtext + W + 64) / 32 + 2;
-    wpp = (wpp + 1) & ~1u;
-    const uint32_t tile_bytes = sig * wpp * 4;
+    // full layout: Eq reads reach word (ncols-1)/32 + NL; pattern bits reach
+    // ncols + K
+    uint32_t wpp_full = (mtext + W + 64) / 32 + 2;
+    wpp_full = (wpp_full + 1) & ~1u;
+    // ring layout: NL+1 live words, one more being filled
+    uint32_t RW = 1;
+    while (RW < NL + 2) RW <<= 1;
+    const uint32_t R = (32 + NL - 1) / NL;
+    const uint32_t ring_mode = ctx->tune.verify_ring;
+    const bool ring = ring_mode != 0 && NL >= 8 && sig * R <= 32 &&
+                      (ring_mode == 2 || 2 * RW < wpp_full);
+    const uint32_t wpp = ring ? RW : wpp_full;
+    const uint32_t tile_bytes = sig * (ring ? 2 * RW : wpp_full) * 4;
     uint32_t tpw = 64 / NL;
     uint32_t budget = ctx->tune.verify_lds_budget;
     if ((int)budget > ctx->lds_max) budget = (uint32_t)ctx->lds_max;
@@ -406,10 +475,10 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     tpw = std::min(tpw, budget / tile_bytes);
     const size_t lds = (size_t)tpw * tile_bytes;
     const int mode = NL == 1 ? LANES_ONE : NL == 16 ? LANES_ROW : NL == 64 ? LANES_WAVE : LANES_ANY;
-    auto kern = mode == LANES_ONE    ? k_verify<LANES_ONE>
-                : mode == LANES_ROW  ? k_verify<LANES_ROW>
-                : mode == LANES_WAVE ? k_verify<LANES_WAVE>
-                                     : k_verify<LANES_ANY>;
+    auto kern = mode == LANES_ONE    ? k_verify<LANES_ONE, false>
+                : mode == LANES_ROW  ? (ring ? k_verify<LANES_ROW, true> : k_verify<LANES_ROW, false>)
+                : mode == LANES_WAVE ? (ring ? k_verify<LANES_WAVE, true> : k_verify<LANES_WAVE, false>)
+                : (ring ? k_verify<LANES_ANY, true> : k_verify<LANES_ANY, false>);
     if (lds > 65536)
         EJ_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));

@@ -198,6 +198,35 @@ def test_verify_long_strings_random_and_similar(ej, ctx, oracle_lib):
         assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
 
 
+@pytest.mark.parametrize("K", [254, 300, 500, 700, 1000, 2046])
+def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
+    """Whole-pattern and ring layouts of the match masks, with one and two
+    passes, give the oracle's distances (bands of 8 to 64 lanes)."""
+    import torch
+    rng = np.random.default_rng(K + 7)
+    col = sd.clusters(300 + K, 8, lambda rr, b: 4, lambda rr: rr.integers(K // 2, 2 * K + 400),
+                      lambda rr, LL: rr.poisson(max(1, K // 3)))
+    n = col.n
+    a = rng.integers(0, n, size=120)
+    b = rng.integers(0, n, size=120)
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K).tolist()
+    chars, offs = to_device(col)
+    d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
+    old = (ctx.tune_get("verify_ring"), ctx.tune_get("verify_pass1_cols"))
+    try:
+        for ring in (0, 2):
+            for c1 in (0, 64, 1024):
+                ctx.tune_set("verify_ring", ring)
+                ctx.tune_set("verify_pass1_cols", c1)
+                _say(f"verify layout K={K} ring={ring} c1={c1}")
+                got = ctx.verify(chars, offs, d_codes, K)
+                assert got.cpu().numpy().astype(np.uint32).tolist() == want
+    finally:
+        ctx.tune_set("verify_ring", old[0])
+        ctx.tune_set("verify_pass1_cols", old[1])
+
+
 # ------------------------------------------------------------ edge cases ----
 
 def test_edge_cases(ej, ctx, oracle_lib):
@@ -302,7 +331,8 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
     ref = _oracle_join(oracle_lib, col, K, r, z, m, 5, L)
     knobs = [("radix_bits", 4), ("radix_bits", 11), ("bucket_key_bits", 5),
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
-             ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64)]
+             ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
+             ("verify_ring", 2)]
     for name, val in knobs:
         old = ctx.tune_get(name)
         try:
