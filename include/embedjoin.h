@@ -87,14 +87,19 @@ typedef struct {
     uint32_t L;            /* truncation length used */
     /* EJ_FLAG_TIMING: device time of each stage, from events on the context
      * stream: prep = A0 and the random streams, embed = the walk kernel (A1-A2),
-     * bucket = A3, candidates = A4, verify = the verification kernel (A5),
-     * output = compaction and copy-out (A6). */
+     * bucket = A3, candidates = A4, verify = verification (A5: its kernel
+     * launches and the compaction of the pairs still undecided after the first
+     * pass), output = compaction and copy-out (A6). */
     float ms_prep, ms_embed, ms_bucket, ms_candidates, ms_verify, ms_output;
     /* EJ_FLAG_TIMING: work done, for rooflines.  walk_steps = CGK steps taken
      * (each walk stops after its seed's last sampled step); verify_columns =
      * text columns evaluated over all candidates (a pair stops early once its
      * distance provably exceeds K). */
     uint64_t walk_steps, verify_columns;
+    /* EJ_FLAG_TIMING: summed device time of the verification kernel's own
+     * launches (events right around each launch) and their number. */
+    float ms_verify_kernel;
+    uint32_t verify_launches;
 } ej_result;
 
 /* ---------------------------------------------------------------- lifecycle */

@@ -53,7 +53,8 @@ class _Result(ctypes.Structure):
                 ("ms_prep", ctypes.c_float), ("ms_embed", ctypes.c_float),
                 ("ms_bucket", ctypes.c_float), ("ms_candidates", ctypes.c_float),
                 ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float),
-                ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64)]
+                ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64),
+                ("ms_verify_kernel", ctypes.c_float), ("verify_launches", ctypes.c_uint32)]
 
 
 class _QResult(ctypes.Structure):
@@ -157,6 +158,8 @@ class JoinResult:
     ms: dict
     walk_steps: int = 0
     verify_columns: int = 0
+    ms_verify_kernel: float = 0.0
+    verify_launches: int = 0
 
     @property
     def codes(self) -> np.ndarray:
@@ -234,7 +237,8 @@ class Context:
                       candidates=res.ms_candidates, verify=res.ms_verify, output=res.ms_output)
             return JoinResult(pairs, dist, int(res.n_candidates), int(res.n_raw),
                               int(res.sigma), int(res.L), ms, int(res.walk_steps),
-                              int(res.verify_columns))
+                              int(res.verify_columns), float(res.ms_verify_kernel),
+                              int(res.verify_launches))
         finally:
             lib().ej_result_free(ctypes.byref(res))
 

@@ -72,6 +72,7 @@ ej_status ej_create(ej_ctx **out, int device, void *hip_stream) {
         ctx->lds_max = lds;
         EJ_HIP(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
         for (int i = 0; i < 8; i++) EJ_HIP(hipEventCreate(&ctx->timers.ev[i]));
+        for (int i = 0; i < 4; i++) EJ_HIP(hipEventCreate(&ctx->timers.kv[i]));
     } catch (const Error &e) {
         ej_status c = e.code;
         ej_destroy(ctx);
@@ -90,6 +91,8 @@ void ej_destroy(ej_ctx *ctx) {
     ctx->ws.clear();
     for (int i = 0; i < 8; i++)
         if (ctx->timers.ev[i]) (void)hipEventDestroy(ctx->timers.ev[i]);
+    for (int i = 0; i < 4; i++)
+        if (ctx->timers.kv[i]) (void)hipEventDestroy(ctx->timers.kv[i]);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

@@ -76,6 +76,9 @@ struct Explicit {
 
 struct Timers {
     hipEvent_t ev[8] = {};
+    // around each launch of the verification kernel while `on`
+    hipEvent_t kv[4] = {};
+    int nkv = 0;
     bool on = false;
 };
 

@@ -162,9 +162,12 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         d_cols = ws<unsigned long long>(ctx, "j_vcols", 1);
         EJ_HIP(hipMemsetAsync(d_cols, 0, 8, ctx->stream));
     }
-    tm.mark();  // 4: the verification kernel alone follows
+    tm.mark();  // 4: the verification stage follows
+    ctx->timers.on = tm.on;
+    ctx->timers.nkv = 0;
     verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, pairs, cnt, p.K, nullptr,
            dist, nullptr, nullptr, 0, 0, d_cols);
+    ctx->timers.on = false;
     tm.mark();  // 5
     uint64_t nout = 0;
     uint32_t *opairs = nullptr;
@@ -217,6 +220,14 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         for (uint32_t x : J) steps += x;
         out->walk_steps = steps * n;
         if (cnt) read_back(ctx, d_cols, 8, &out->verify_columns);
+        float kms = 0.f;
+        for (int i = 0; i + 1 < ctx->timers.nkv; i += 2) {
+            float ms = 0.f;
+            EJ_HIP(hipEventElapsedTime(&ms, ctx->timers.kv[i], ctx->timers.kv[i + 1]));
+            kms += ms;
+        }
+        out->ms_verify_kernel = kms;
+        out->verify_launches = (uint32_t)(ctx->timers.nkv / 2);
     }
 }
 

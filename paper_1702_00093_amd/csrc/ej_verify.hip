@@ -63,6 +63,22 @@ __device__ inline uint32_t add_carry_mask(uint32_t a, uint32_t b, uint64_t &carr
     return s;
 }
 
+// s = a + (bit `lane` of the wave-wide mask cin): one add with the carry-in
+// taken straight from the scalar mask.
+__device__ inline uint32_t add_carry_in(uint32_t a, uint64_t cin) {
+    uint32_t s;
+    uint64_t unused;
+    asm("v_addc_co_u32 %0, %1, %2, 0, %3" : "=v"(s), "=s"(unused) : "v"(a), "s"(cin));
+    return s;
+}
+
+// popcount(x) + acc in one v_bcnt.
+__device__ inline uint32_t popc_acc(uint32_t x, uint32_t acc) {
+    uint32_t r;
+    asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 template <int MODE>
 __device__ inline uint32_t from_next_lane(uint32_t x, uint32_t keep) {
     if (MODE == LANES_ROW)  // row_shl:1, lanes 15/31/47/63 read 0
@@ -77,15 +93,17 @@ __device__ inline uint32_t from_next_lane(uint32_t x, uint32_t keep) {
 // The match word of column jb+1+s is read from LDS inside the step (text
 // symbol s of tw selects the symbol's bit array; the lane's two words at
 // `slot` are funnel-shifted by s), which keeps the live registers low.
+// Addresses are LDS byte offsets: symbol c's words start at c * stride4
+// (a 24-bit multiply-add, full rate) and the lane's word at slot4.
 template <int MODE, bool FAST>
-__device__ inline void myers_block(const uint32_t *peq, uint32_t stride, uint32_t slot,
+__device__ inline void myers_block(const uint8_t *peq, uint32_t stride4, uint32_t slot4,
                                    const uint32_t tw[8], uint32_t &Pv, uint32_t &Mv, uint32_t &Z,
                                    uint32_t &acc, uint32_t kmask, uint32_t kbit, uint64_t notlast,
                                    uint32_t keep) {
 #pragma unroll
     for (uint32_t s = 0; s < 32; s++) {
         const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
-        const uint32_t *pa = peq + c * stride + slot;
+        const uint32_t *pa = (const uint32_t *)(peq + (__umul24(c, stride4) + slot4));
         const uint32_t eq = __builtin_amdgcn_alignbit(pa[1], pa[0], s);
         const uint32_t Xv = eq | Mv;
         uint32_t sum;
@@ -100,7 +118,7 @@ __device__ inline void myers_block(const uint32_t *peq, uint32_t stride, uint32_
                 P &= notlast;
             }
             const uint64_t cin = ((G | P) + G) ^ P;
-            sum += __builtin_amdgcn_inverse_ballot_w64(cin) ? 1u : 0u;
+            sum = add_carry_in(sum, cin);
         }
         const uint32_t Xh = (sum ^ Pv) | eq;
         const uint32_t Ph = Mv | ~(Xh | Pv);
@@ -110,7 +128,7 @@ __device__ inline void myers_block(const uint32_t *peq, uint32_t stride, uint32_
         Pv = Mh | ~(Xv1 | Ph);
         Mv = Ph & Xv1;
         if (FAST)
-            Z += (uint32_t)__builtin_popcount((Xv1 | Mh) & kmask);
+            Z = popc_acc((Xv1 | Mh) & kmask, Z);
         else
             acc |= (((Xv1 | Mh) >> kbit) & 1u) << s;
     }
@@ -229,7 +247,7 @@ __global__ void __launch_bounds__(64)
     const uint64_t notlast = ~last;
     const uint32_t keep = (l == NL - 1 || !in_tile) ? 0u : 0xFFFFFFFFu;
     uint32_t *pq_mine = lds + (in_tile ? tile : 0) * tile_words;
-    const uint32_t *peq = pq_mine;
+    const uint8_t *peq8 = (const uint8_t *)pq_mine;
 
     for (uint64_t g = blockIdx.x; g * tpw < count; g += gridDim.x) {
         const uint64_t k = g * tpw + tile;  // index into the (listed) pairs
@@ -316,17 +334,17 @@ __global__ void __launch_bounds__(64)
                     if (q < R && bq < 32 && row >= 1 && row <= (int64_t)v.m) rc[q] = v.xp[row - 1];
                 }
             }
-            const uint32_t slot = RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l);
+            const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
             // columns past the end of a pair's text do not count; a block
             // where no text ends takes the masked-popcount path
             const bool ends_here = in_tile && v.nn > jb && v.nn < jb + 32;
             if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
                 const uint32_t km = (owner && jb + 32 <= v.nn) ? (1u << kbit) : 0u;
                 uint32_t unused = 0;
-                myers_block<MODE, true>(peq, stride, slot, tw, Pv, Mv, Z, unused, km, kbit, notlast, keep);
+                myers_block<MODE, true>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, unused, km, kbit, notlast, keep);
             } else {
                 uint32_t acc = 0;
-                myers_block<MODE, false>(peq, stride, slot, tw, Pv, Mv, Z, acc, 0u, kbit, notlast, keep);
+                myers_block<MODE, false>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, acc, 0u, kbit, notlast, keep);
                 const uint32_t ncol = v.nn > jb ? min(v.nn - jb, 32u) : 0u;
                 const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
                 if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
@@ -490,7 +508,12 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         aux = ws<uint32_t>(ctx, "verify_aux", count);
     }
     const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;
+    Timers &tk = ctx->timers;
+    auto kmark = [&]() {
+        if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
+    };
     {
+        kmark();
         uint64_t ngroups = (count + tpw - 1) / tpw;
         uint64_t grid = std::min<uint64_t>(ngroups, cap);
         hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
@@ -498,6 +521,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
                            (const uint32_t *)nullptr, K, d_Kq, sig, NL, tpw, wpp, 0u,
                            two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
         EJ_CHECK_LAUNCH();
+        kmark();
     }
     if (!two_pass) return;
     uint32_t *flags = ws<uint32_t>(ctx, "verify_flags", count);
@@ -516,11 +540,13 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     EJ_CHECK_LAUNCH();
     uint64_t ngroups = (nalive + tpw - 1) / tpw;
     uint64_t grid = std::min<uint64_t>(ngroups, cap);
+    kmark();
     hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
                        d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs, nalive,
                        (const uint32_t *)list, K, d_Kq, sig, NL, tpw, wpp, C1, NO_LIMIT, 1,
                        state, aux, d_dist, d_columns);
     EJ_CHECK_LAUNCH();
+    kmark();
 }
 
 }  // namespace ej
