@@ -50,6 +50,14 @@ def parse():
                     help="use the workload's stated (r, z, m, L) instead of the recall-calibrated point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (index of 320,000 strings, 10,000 queries)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="run only the serving leg")
+    ap.add_argument("--serving-params", default="", metavar="r,z,m,L",
+                    help="override the serving index parameters")
+    ap.add_argument("--serving-sweep", default="", metavar="r,z,m,L;r,z,m,L;..",
+                    help="with --serving-only: one serving run per parameter point, same data")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times): "
                          "the reference for scaling HBM traffic counters")
@@ -176,6 +184,134 @@ def cpu_baseline(col, prm, oracle, budget_s=12.0):
                        f"({nc} candidates, {no} output pairs), same parameters")
 
 
+# Serving parameters, recall-calibrated by a sweep on this query mix
+# (re-mutated members at 5% edits plus fresh random strings): with the
+# stated r=3, z=7 no (m, L) reaches recall 0.99 against the source member
+# (0.81-0.93), because an edit near the start of a string desynchronises the
+# walks of all seeds at once; 32 seeds x 8 functions with m=20, L=64 reach
+# 0.993 at 26 candidates per query.
+SERVING = dict(r=32, z=8, m=20, L=64)
+
+
+_SERVING_DATA = {}
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
+    """Device-resident index over 320,000 DNA strings; 10,000 queries of mixed
+    lengths and thresholds.  Saturation throughput from back-to-back batches,
+    then a Poisson arrival stream at 0.5/0.8/1.0x that rate served by an
+    arrival batcher (everything that has arrived, at most max_batch, halved
+    while the index refuses admission); latency = completion - arrival."""
+    import torch
+    import synthdata as sd
+    t0 = time.perf_counter()
+    if seed not in _SERVING_DATA:
+        col, _ = sd.serving_index(seed)
+        _SERVING_DATA[seed] = (col,) + tuple(sd.serving_queries(col, seed))
+    col, q, Kq, src = _SERVING_DATA[seed]
+    gen_s = time.perf_counter() - t0
+    _log(f"serving data ready ({gen_s:.1f} s), params {SERVING}")
+    chars = torch.from_numpy(col.chars).cuda()
+    offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix = ej.Index(ctx, chars, offs, SERVING["r"], SERVING["z"], SERVING["m"], seed=seed,
+                  L=SERVING["L"])
+    build_s = time.perf_counter() - t0
+    del chars, offs
+    _log(f"index built in {build_s:.3f} s")
+    qc, qo = q.chars, q.offsets.astype(np.uint64)
+    nq = q.n
+
+    def run(i0, i1):
+        # queries i0..i1-1: their offsets index into the whole query buffer
+        return ix.query(qc, qo[i0:i1 + 1], Kq[i0:i1])
+
+    def run_admitted(i0, i1):
+        out = []
+        stack = [(i0, i1)]
+        while stack:
+            a, b = stack.pop()
+            try:
+                out.append((a, run(a, b)))
+            except ej.EmbedJoinError as e:
+                if e.status != ej.EJ_ENOMEM or b - a <= 1:
+                    raise
+                mid = (a + b) // 2
+                stack += [(mid, b), (a, mid)]
+        return out
+
+    run_admitted(0, min(nq, 256))   # warm-up
+    # saturation
+    found = {}
+    t0 = time.perf_counter()
+    ncand = 0
+    for i0 in range(0, nq, max_batch):
+        for a, res in run_admitted(i0, min(nq, i0 + max_batch)):
+            ncand += res.n_candidates
+            for k in range(len(res.offsets) - 1):
+                found[a + k] = res.of(k)[0]
+    sat_s = time.perf_counter() - t0
+    sat_qps = nq / sat_s
+    _log(f"saturation {sat_qps:.0f} queries/s, {ncand / nq:.1f} candidates per query")
+    # Poisson arrivals
+    sweeps = []
+    for load in (0.5, 0.8, 1.0):
+        rng = np.random.default_rng(seed + int(load * 100))
+        arrive = np.cumsum(rng.exponential(1.0 / (load * sat_qps), size=nq))
+        lat = np.zeros(nq)
+        nb = 0
+        start = time.perf_counter()
+        i = 0
+        while i < nq:
+            now = time.perf_counter() - start
+            if arrive[i] > now:
+                time.sleep(arrive[i] - now)
+                now = time.perf_counter() - start
+            j = int(np.searchsorted(arrive, now, side="right"))
+            j = max(j, i + 1)
+            j = min(j, i + max_batch, nq)
+            run_admitted(i, j)
+            done = time.perf_counter() - start
+            lat[i:j] = done - arrive[i:j]
+            nb += 1
+            i = j
+        wall = time.perf_counter() - start
+        _log(f"poisson load {load}: {nb} batches")
+        sweeps.append(dict(load=load, offered_qps=round(load * sat_qps, 1),
+                           achieved_qps=round(nq / wall, 1), batches=nb,
+                           p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                           p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3)))
+    # recall against the source member of re-mutated queries (oracle ED)
+    rng = np.random.default_rng(seed + 7)
+    members = np.nonzero(src >= 0)[0]
+    pick = rng.choice(members, size=min(n_recall, len(members)), replace=False)
+    S_off = col.offsets
+    true_n, hit = 0, 0
+    for qi in pick.tolist():
+        s = int(src[qi])
+        x = col.chars[int(S_off[s]):int(S_off[s + 1])]
+        y = qc[int(qo[qi]):int(qo[qi + 1])]
+        if oracle.ed_banded(x, y, int(Kq[qi])) <= int(Kq[qi]):
+            true_n += 1
+            hit += int(s in set(found[qi].tolist()))
+    ix.close()
+    return dict(workload="serving: index 320,000 DNA strings (32,000 bases U{4500..5500} x 10 "
+                         "copies, Poisson(0.05 len) edits); 10,000 queries (70% re-mutated "
+                         "members, 30% fresh U{1000..10000}), K_q in {2,5,10}% of |q|",
+                params=SERVING, gen_s=round(gen_s, 1), index_build_s=round(build_s, 3),
+                saturation_qps=round(sat_qps, 1), saturation_batch=max_batch,
+                candidates_per_query=round(ncand / nq, 2),
+                poisson=sweeps, p50_ms=sweeps[-1]["p50_ms"], p99_ms=sweeps[-1]["p99_ms"],
+                recall_vs_source=dict(sampled_member_queries=int(len(pick)),
+                                      source_within_Kq=true_n, found=hit,
+                                      recall=round(hit / true_n, 4) if true_n else None))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -188,6 +324,17 @@ def main():
     import torch
     import paper_1702_00093_amd as ej
     from oracle import oracle
+    if args.serving_params:
+        r_, z_, m_, L_ = (int(x) for x in args.serving_params.split(","))
+        SERVING.update(r=r_, z=z_, m=m_, L=L_)
+    if args.serving_only:
+        sctx = ej.Context(0)
+        points = [tuple(int(x) for x in pt.split(",")) for pt in args.serving_sweep.split(";")] \
+            if args.serving_sweep else [(SERVING["r"], SERVING["z"], SERVING["m"], SERVING["L"])]
+        for r_, z_, m_, L_ in points:
+            SERVING.update(r=r_, z=z_, m=m_, L=L_)
+            print(json.dumps({"serving": serving_bench(ej, sctx, oracle)}), flush=True)
+        return
     col, name, stated, prm = workload(args)
     chars = torch.from_numpy(col.chars.copy()).cuda()
     offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
@@ -249,6 +396,11 @@ def main():
         out["config"]["stated_params_run"] = stated_info
     if not args.no_recall:
         out["config"]["recall"] = recall_estimate(col, res, prm["K"], oracle)
+    if not args.no_serving:
+        try:
+            out["serving"] = serving_bench(ej, ctx, oracle)
+        except Exception as e:  # reported, never hides the join line
+            out["serving"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(col, prm, oracle)
     print(json.dumps(out), flush=True)

@@ -241,6 +241,8 @@ typedef struct {
 ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
                          const ej_params *p, int on_device, ej_index **index);
 /* Answers nq queries (host strings) with per-query thresholds Kq (host).
+ * Query i is q[q_offsets[i] .. q_offsets[i+1]); q_offsets[0] need not be 0,
+ * so a batch can be a window of a larger buffer.
  * EJ_EALPHABET if a query byte is outside the index alphabet; EJ_ENOMEM if
  * the batch's workspace estimate exceeds the free HBM (or the admission
  * limit set with ej_index_set_hbm_limit). */

@@ -454,6 +454,90 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
 }
 
 /* Verification only: min(ED, K+1) for each pair (a_k, b_k). */
+/* ------------------------------------------------------------- serving --
+ * Serving is a systems layer on the method, not a step of the paper: an
+ * index fixes the alphabet (its sorted distinct bytes), the truncation L and
+ * the random streams; query q's result is every index string s that shares
+ * the key of some table (l, j) with q, whose length differs from |q| by at
+ * most K_q and whose edit distance to q is at most K_q, in increasing
+ * position order.  Written as a plain double loop over (query, index
+ * string), with the keys from the same embedding and key functions as the
+ * join.  Returns the number of results (entries beyond cap are not
+ * written), -1 for invalid sizes, -2 if a query byte is outside the index
+ * alphabet. */
+static void string_keys(const uint8_t *codes, uint32_t len, const uint8_t *Rbits, uint64_t rb,
+                        uint32_t sigma, uint32_t L, const uint32_t *pos, const uint64_t *v,
+                        uint32_t r, uint32_t z, uint32_t m, uint8_t *t, uint64_t *keys) {
+    for (uint32_t l = 0; l < r; l++) {
+        ejo_cgk_embed(codes, len, Rbits + l * rb, sigma, L, t);
+        for (uint32_t j = 0; j < z; j++)
+            keys[l * z + j] = ejo_key(t, pos + ((uint64_t)l * z + j) * m,
+                                      v + ((uint64_t)l * z + j) * m, m);
+    }
+}
+
+int64_t ejo_query(const uint8_t *ichars, const uint64_t *ioff, uint32_t n, const uint8_t *qchars,
+                  const uint64_t *qoff, uint32_t nq, const uint32_t *Kq, uint32_t r, uint32_t z,
+                  uint32_t m, uint32_t L_req, uint64_t seed, uint64_t *res_off,
+                  uint32_t *res_ids, uint32_t *res_dist, uint64_t cap) {
+    if (r == 0 || z == 0 || m == 0) return -1;
+    uint64_t itotal = n ? ioff[n] - ioff[0] : 0;
+    int32_t lut[256];
+    int sigma = ejo_alphabet(ichars + (n ? ioff[0] : 0), itotal, lut);
+    uint32_t L = ejo_effective_L(ioff, n, L_req);
+    uint32_t T = r * z;
+    uint64_t qtotal = nq ? qoff[nq] - qoff[0] : 0;
+    for (uint64_t i = 0; i < qtotal; i++)
+        if (lut[qchars[qoff[0] + i]] < 0) return -2;
+    uint8_t *icodes = (uint8_t *)malloc(itotal + 1);
+    uint8_t *qcodes = (uint8_t *)malloc(qtotal + 1);
+    for (uint64_t i = 0; i < itotal; i++) icodes[i] = (uint8_t)lut[ichars[ioff[0] + i]];
+    for (uint64_t i = 0; i < qtotal; i++) qcodes[i] = (uint8_t)lut[qchars[qoff[0] + i]];
+    uint64_t rb = (uint64_t)L * (uint64_t)sigma;
+    uint8_t *Rbits = (uint8_t *)malloc(r * rb + 1);
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * T * m);
+    uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * T * m);
+    ejo_draw(seed, r, z, m, L, (uint32_t)sigma, Rbits, pos, v);
+    uint8_t *t = (uint8_t *)malloc(L);
+    uint64_t *ikeys = (uint64_t *)malloc(sizeof(uint64_t) * T * (n ? n : 1));
+    uint64_t *qk = (uint64_t *)malloc(sizeof(uint64_t) * T);
+    for (uint32_t s = 0; s < n; s++)
+        string_keys(icodes + (ioff[s] - ioff[0]), (uint32_t)(ioff[s + 1] - ioff[s]), Rbits, rb,
+                    (uint32_t)sigma, L, pos, v, r, z, m, t, ikeys + (uint64_t)s * T);
+    uint64_t cnt = 0;
+    res_off[0] = 0;
+    for (uint32_t q = 0; q < nq; q++) {
+        const uint8_t *xq = qcodes + (qoff[q] - qoff[0]);
+        uint32_t lq = (uint32_t)(qoff[q + 1] - qoff[q]);
+        string_keys(xq, lq, Rbits, rb, (uint32_t)sigma, L, pos, v, r, z, m, t, qk);
+        for (uint32_t s = 0; s < n; s++) {
+            uint32_t ls = (uint32_t)(ioff[s + 1] - ioff[s]);
+            uint32_t gap = ls > lq ? ls - lq : lq - ls;
+            if (gap > Kq[q]) continue;
+            int hit = 0;
+            for (uint32_t e = 0; e < T && !hit; e++) hit = ikeys[(uint64_t)s * T + e] == qk[e];
+            if (!hit) continue;
+            uint32_t d = ejo_ed_banded(icodes + (ioff[s] - ioff[0]), ls, xq, lq, Kq[q]);
+            if (d > Kq[q]) continue;
+            if (cnt < cap) {
+                res_ids[cnt] = s;
+                res_dist[cnt] = d;
+            }
+            cnt++;
+        }
+        res_off[q + 1] = cnt;
+    }
+    free(icodes);
+    free(qcodes);
+    free(Rbits);
+    free(pos);
+    free(v);
+    free(t);
+    free(ikeys);
+    free(qk);
+    return (int64_t)cnt;
+}
+
 void ejo_verify_pairs(const uint8_t *chars, const uint64_t *offsets, const uint64_t *pairs,
                       uint64_t count, uint32_t K, uint32_t *dist) {
     for (uint64_t e = 0; e < count; e++) {

@@ -86,6 +86,10 @@ def lib():
         L.ejo_result_free.argtypes = [ctypes.POINTER(_Result)]
         L.ejo_verify_pairs.restype = None
         L.ejo_verify_pairs.argtypes = [u8p, u64p, u64p, ctypes.c_uint64, ctypes.c_uint32, u32p]
+        L.ejo_query.restype = ctypes.c_int64
+        L.ejo_query.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, u32p,
+                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.c_uint64, u64p, u32p, u32p, ctypes.c_uint64]
         L.ejo_brute_join.restype = ctypes.c_uint64
         L.ejo_brute_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
                                      u64p, u32p, ctypes.c_uint64, ctypes.c_int]
@@ -257,4 +261,36 @@ def brute_join(chars, offsets, K: int, full: bool = False):
                                        1 if full else 0))
         if cnt <= cap:
             return out[:cnt], d[:cnt]
+        cap = cnt
+
+
+def query(index_chars, index_offsets, q_chars, q_offsets, Kq, r: int, z: int, m: int,
+          seed: int = 0, L: int = 0):
+    """Serving semantics: per query, the index positions sharing a key with
+    it in some table, within K_q in length and in edit distance, sorted.
+    Returns (offsets[nq+1], ids, dist); raises ValueError for a query byte
+    outside the index alphabet."""
+    ic, qc = _u8(index_chars), _u8(q_chars)
+    io = np.ascontiguousarray(index_offsets, dtype=np.uint64)
+    qo = np.ascontiguousarray(q_offsets, dtype=np.uint64)
+    K = np.ascontiguousarray(Kq, dtype=np.uint32)
+    n, nq = io.shape[0] - 1, qo.shape[0] - 1
+    cap = 1 << 12
+    while True:
+        off = np.zeros(nq + 1, dtype=np.uint64)
+        ids = np.zeros(cap, dtype=np.uint32)
+        d = np.zeros(cap, dtype=np.uint32)
+        cnt = int(lib().ejo_query(_ptr(ic, ctypes.c_uint8) if ic.size else None,
+                                  _ptr(io, ctypes.c_uint64), n,
+                                  _ptr(qc, ctypes.c_uint8) if qc.size else None,
+                                  _ptr(qo, ctypes.c_uint64), nq,
+                                  _ptr(K, ctypes.c_uint32) if K.size else None, r, z, m, L, seed,
+                                  _ptr(off, ctypes.c_uint64), _ptr(ids, ctypes.c_uint32),
+                                  _ptr(d, ctypes.c_uint32), cap))
+        if cnt == -2:
+            raise ValueError("query byte outside the index alphabet")
+        if cnt < 0:
+            raise ValueError("invalid query arguments")
+        if cnt <= cap:
+            return off, ids[:cnt], d[:cnt]
         cap = cnt

@@ -147,6 +147,12 @@ def _is_device(x) -> bool:
     return hasattr(x, "is_cuda") and x.is_cuda
 
 
+def _torch_stream_done():
+    """The library runs on its own stream: device buffers that torch's current
+    stream writes (or will reuse) must be settled before a call."""
+    _torch().cuda.current_stream().synchronize()
+
+
 @dataclass
 class JoinResult:
     pairs: np.ndarray          # [count, 2] int64, i < j, sorted
@@ -219,6 +225,9 @@ class Context:
             assert chars.dtype == torch.uint8 and offsets.dtype == torch.int64
             assert chars.is_contiguous() and offsets.is_contiguous()
             n = offsets.numel() - 1
+            # the library works on its own stream: inputs written on torch's
+            # current stream must be complete first
+            torch.cuda.current_stream().synchronize()
             st = lib().ej_join_device(self._h, _ptr(chars), _ptr(offsets), n, ctypes.byref(p),
                                       ctypes.byref(res))
         else:
@@ -254,6 +263,7 @@ class Context:
             if want_sig else None
         p = Params(0, r, z, m, L, 0, seed)
         Lu, sg = ctypes.c_uint32(), ctypes.c_uint32()
+        _torch_stream_done()
         self._check(lib().ej_embed(self._h, _ptr(d_chars) if d_chars.numel() else None,
                                    _ptr(d_offsets), n, ctypes.byref(p), _ptr(sig), _ptr(keys),
                                    ctypes.byref(Lu), ctypes.byref(sg)))
@@ -267,7 +277,9 @@ class Context:
         ids = torch.empty(max(T * n, 1), dtype=torch.int32, device=d_keys.device)
         gs = torch.empty(T * n + 1, dtype=torch.int32, device=d_keys.device)
         ng = ctypes.c_uint64()
-        self._check(lib().ej_lsh_bucket(self._h, _ptr(d_keys.contiguous()), _ptr(d_len), n, T,
+        kc = d_keys.contiguous()
+        _torch_stream_done()
+        self._check(lib().ej_lsh_bucket(self._h, _ptr(kc), _ptr(d_len), n, T,
                                         key_bits, _ptr(ids), _ptr(gs), ctypes.byref(ng)))
         return ids[:T * n], gs[:int(ng.value) + 1]
 
@@ -279,7 +291,9 @@ class Context:
         while True:
             out = torch.empty(max(cap, 1), dtype=torch.int64, device=d_keys.device)
             cnt, raw = ctypes.c_uint64(), ctypes.c_uint64()
-            st = lib().ej_candidates(self._h, _ptr(d_keys.contiguous()), _ptr(d_ids),
+            kc = d_keys.contiguous()
+            _torch_stream_done()
+            st = lib().ej_candidates(self._h, _ptr(kc), _ptr(d_ids),
                                      _ptr(d_group_start), d_group_start.numel() - 1, _ptr(d_len),
                                      n, T, K, _ptr(out), cap, ctypes.byref(cnt), ctypes.byref(raw))
             if st == EJ_ECAPACITY and capacity is None:
@@ -294,6 +308,7 @@ class Context:
         n = d_offsets.numel() - 1
         cnt = d_pairs.numel()
         dist = torch.empty(max(cnt, 1), dtype=torch.int32, device=d_offsets.device)
+        _torch_stream_done()
         self._check(lib().ej_verify(self._h, _ptr(d_chars) if d_chars.numel() else None,
                                     _ptr(d_offsets), n, _ptr(d_pairs) if cnt else None, cnt, K,
                                     _ptr(d_Kq), _ptr(dist)))
@@ -311,6 +326,89 @@ class Context:
 
 
 _default: dict[int, Context] = {}
+
+
+@dataclass
+class QueryResult:
+    offsets: np.ndarray        # [nq + 1] uint64: results of query q are [offsets[q], offsets[q+1])
+    ids: np.ndarray            # index positions, sorted within each query
+    dist: np.ndarray           # edit distances
+    n_candidates: int          # (query, index string) pairs verified
+    ms: float                  # device time of the batch
+
+    def of(self, q: int):
+        lo, hi = int(self.offsets[q]), int(self.offsets[q + 1])
+        return self.ids[lo:hi], self.dist[lo:hi]
+
+
+class Index:
+    """Device-resident LSH index (ej_index_build / ej_query_batch)."""
+
+    def __init__(self, ctx: Context, chars, offsets, r: int, z: int, m: int, seed: int = 0,
+                 L: int = 0):
+        self._ctx = ctx
+        self._h = None
+        p = Params(0, r, z, m, L, 0, seed)
+        h = ctypes.c_void_p()
+        if _is_device(chars):
+            torch = _torch()
+            o = offsets if _is_device(offsets) else torch.from_numpy(
+                _host_u64(offsets).astype(np.int64)).cuda()
+            n = int(o.shape[0]) - 1
+            torch.cuda.current_stream().synchronize()
+            st = lib().ej_index_build(ctx._h, _ptr(chars), _ptr(o), n, ctypes.byref(p), 1,
+                                      ctypes.byref(h))
+        else:
+            c, o = _host_u8(chars), _host_u64(offsets)
+            n = int(o.shape[0]) - 1
+            st = lib().ej_index_build(ctx._h, _ptr(c) if c.size else None, _ptr(o), n,
+                                      ctypes.byref(p), 0, ctypes.byref(h))
+        ctx._check(st)
+        self._h = h.value
+        self.n = n
+
+    def close(self):
+        if self._h is not None:
+            lib().ej_index_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_hbm_limit(self, nbytes: int):
+        lib().ej_index_set_hbm_limit(self._h, int(nbytes))
+
+    def size(self) -> int:
+        return int(lib().ej_index_size(self._h))
+
+    def workspace_estimate(self, q_offsets, Kq) -> int:
+        o = _host_u64(q_offsets)
+        k = np.ascontiguousarray(Kq, dtype=np.uint32)
+        return int(lib().ej_query_workspace_estimate(self._h, _ptr(o), o.shape[0] - 1,
+                                                     _ptr(k) if k.size else None))
+
+    def query(self, q_chars, q_offsets, Kq) -> QueryResult:
+        c, o = _host_u8(q_chars), _host_u64(q_offsets)
+        k = np.ascontiguousarray(Kq, dtype=np.uint32)
+        nq = o.shape[0] - 1
+        res = _QResult()
+        st = lib().ej_query_batch(self._h, _ptr(c) if c.size else None, _ptr(o), nq,
+                                  _ptr(k) if k.size else None, ctypes.byref(res))
+        self._ctx._check(st)
+        try:
+            offs = np.ctypeslib.as_array(res.offsets, (nq + 1,)).copy() if nq else \
+                np.zeros(1, dtype=np.uint64)
+            tot = int(offs[-1])
+            ids = np.ctypeslib.as_array(res.ids, (max(tot, 1),))[:tot].copy() if tot else \
+                np.zeros(0, dtype=np.uint32)
+            dist = np.ctypeslib.as_array(res.dist, (max(tot, 1),))[:tot].copy() if tot else \
+                np.zeros(0, dtype=np.int32)
+            return QueryResult(offs, ids, dist, int(res.n_candidates), float(res.ms_total))
+        finally:
+            lib().ej_qresult_free(ctypes.byref(res))
 
 
 def context(device: int = 0) -> Context:

@@ -1,0 +1,151 @@
+"""GPU parity of the serving path: a device-resident index answering batches
+of queries with per-query thresholds, called through the C ABI, against the
+oracle's serving definition on the same seeded inputs (bit-exact ids and
+distances)."""
+import sys
+
+import numpy as np
+import pytest
+
+import synthdata as sd
+from tests._gpu_util import to_device
+
+pytestmark = pytest.mark.gpu
+DNA = np.frombuffer(b"ACGT", dtype=np.uint8)
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ej():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1702_00093_amd as ej
+    ej.lib()
+    return ej
+
+
+@pytest.fixture(scope="module")
+def ctx(ej):
+    return ej.Context(0)
+
+
+def _queries(index, seed, nq, fresh_len, member_frac=0.7, edit_rate=0.05):
+    """The serving query mix at test size: re-mutated index members and
+    fresh random strings; K_q a fraction {2%, 5%, 10%} of the length."""
+    rng = np.random.default_rng(seed)
+    pieces = []
+    for _ in range(nq):
+        if rng.random() < member_frac:
+            s = int(rng.integers(0, index.n))
+            base = index.chars[int(index.offsets[s]):int(index.offsets[s + 1])]
+            pieces.append(bytes(sd.mutate(rng, base, int(rng.poisson(edit_rate * base.shape[0])),
+                                          DNA)))
+        else:
+            pieces.append(bytes(DNA[rng.integers(0, 4, size=int(rng.integers(*fresh_len)))]))
+    q = sd.from_strings(pieces)
+    frac = np.array([0.02, 0.05, 0.10])[rng.integers(0, 3, size=nq)]
+    Kq = np.floor(frac * q.lengths()).astype(np.uint32)
+    return q, Kq
+
+
+def _check(res, ref_off, ref_ids, ref_dist):
+    assert res.offsets.astype(np.uint64).tolist() == ref_off.tolist()
+    assert res.ids.astype(np.uint32).tolist() == ref_ids.tolist()
+    assert res.dist.astype(np.int64).tolist() == ref_dist.astype(np.int64).tolist()
+
+
+def test_index_queries_match_oracle(ej, ctx, oracle_lib):
+    col = sd.clusters(21, 80, lambda rr, b: 5, lambda rr: rr.integers(200, 801),
+                      lambda rr, L: rr.poisson(0.05 * L))
+    r, z, m, L, seed = 3, 5, 4, 48, 7
+    _say(f"index build n={col.n}")
+    ix = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
+    assert ix.size() == col.n
+    for b in range(3):
+        q, Kq = _queries(col, 100 + b, 60, (100, 1000))
+        ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
+                               seed=seed, L=L)
+        _say(f"query batch {b} nq={q.n} expected={len(ref[1])}")
+        res = ix.query(q.chars, q.offsets, Kq)
+        _check(res, *ref)
+        assert res.n_candidates >= len(ref[1])
+    ix.close()
+
+
+def test_index_long_strings_and_large_thresholds(ej, ctx, oracle_lib):
+    """Thresholds up to 1,000 (32-lane bands) and 5,000-symbol strings."""
+    col = sd.clusters(22, 8, lambda rr, b: 5, lambda rr: rr.integers(4500, 5501),
+                      lambda rr, L: rr.poisson(0.05 * L))
+    r, z, m, L, seed = 2, 3, 6, 32, 3
+    ix = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
+    q, Kq = _queries(col, 5, 12, (1000, 10001))
+    Kq = np.maximum(Kq, np.floor(0.10 * q.lengths()).astype(np.uint32))
+    Kq = np.minimum(Kq, 2046).astype(np.uint32)
+    ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
+                           seed=seed, L=L)
+    _say(f"long queries nq={q.n} Kmax={int(Kq.max())} expected={len(ref[1])}")
+    res = ix.query(q.chars, q.offsets, Kq)
+    _check(res, *ref)
+    ix.close()
+
+
+def test_index_built_from_device_strings(ej, ctx, oracle_lib):
+    col = sd.clusters(23, 40, lambda rr, b: 4, lambda rr: rr.integers(50, 300),
+                      lambda rr, L: rr.poisson(4))
+    r, z, m, L, seed = 3, 4, 3, 0, 2
+    chars, offs = to_device(col)
+    ixd = ej.Index(ctx, chars, offs, r, z, m, seed=seed, L=L)
+    ixh = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
+    q, Kq = _queries(col, 9, 40, (40, 300))
+    ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
+                           seed=seed, L=L)
+    _say("device-built index")
+    _check(ixd.query(q.chars, q.offsets, Kq), *ref)
+    _check(ixh.query(q.chars, q.offsets, Kq), *ref)
+    ixd.close()
+    ixh.close()
+
+
+def test_index_edge_cases_and_admission(ej, ctx, oracle_lib):
+    col = sd.clusters(24, 30, lambda rr, b: 3, lambda rr: rr.integers(60, 200),
+                      lambda rr, L: rr.poisson(3))
+    r, z, m, L, seed = 3, 4, 3, 32, 5
+    ix = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
+    # an empty batch
+    _say("empty batch")
+    res = ix.query(b"", np.zeros(1, dtype=np.uint64), np.zeros(0, dtype=np.uint32))
+    assert res.offsets.tolist() == [0] and res.ids.size == 0
+    # empty query strings, K = 0, an exact copy of an index string
+    S = col.strings()
+    Q = [b"", S[3], S[7], b"A"]
+    q = sd.from_strings(Q)
+    Kq = np.array([0, 0, 5, 1], dtype=np.uint32)
+    ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
+                           seed=seed, L=L)
+    _say("degenerate queries")
+    res = ix.query(q.chars, q.offsets, Kq)
+    _check(res, *ref)
+    assert 3 in res.of(1)[0].tolist()
+    # a byte outside the index alphabet
+    bad = sd.from_strings([b"ACGTN"])
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ix.query(bad.chars, bad.offsets, np.array([2], dtype=np.uint32))
+    assert e.value.status == ej.EJ_EALPHABET
+    # admission: a limit below the batch's estimate is refused, then lifted
+    q2, K2 = _queries(col, 11, 20, (60, 200))
+    need = ix.workspace_estimate(q2.offsets, K2)
+    assert need > 0
+    ix.set_hbm_limit(need // 2)
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ix.query(q2.chars, q2.offsets, K2)
+    assert e.value.status == ej.EJ_ENOMEM
+    ix.set_hbm_limit(0)
+    ref = oracle_lib.query(col.chars, col.offsets, q2.chars, q2.offsets, K2, r, z, m,
+                           seed=seed, L=L)
+    _say("after admission refusal")
+    _check(ix.query(q2.chars, q2.offsets, K2), *ref)
+    ix.close()

@@ -374,3 +374,54 @@ def test_empty_and_degenerate_inputs(oracle_lib):
     assert res.out.size == 0
     with pytest.raises(ValueError):
         oracle_lib.join(col.chars, col.offsets, 3, 0, 2, 2)
+
+
+# -------------------------------------------------------------- serving --
+
+@pytest.mark.parametrize("seed,K", [(0, 6), (1, 15), (2, 0)])
+def test_query_over_the_set_equals_the_self_join(oracle_lib, seed, K):
+    """Serving query of string a against index S (same alphabet, truncation
+    and streams) returns exactly a itself and the self-join's partners of a:
+    two independent code paths (hash tables in length order vs. a double
+    loop over all pairs) for the same set."""
+    col = sd.clusters(seed, 20, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(20, 70),
+                      lambda rr, L: rr.poisson(3))
+    r, z, m = 3, 4, 3
+    res = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=0)
+    partners = {a: {a: 0} for a in range(col.n)}
+    for (a, b), d in zip(res.out_pairs.tolist(), res.out_dist.tolist()):
+        partners[a][b] = d
+        partners[b][a] = d
+    off, ids, dist = oracle_lib.query(col.chars, col.offsets, col.chars, col.offsets,
+                                      [K] * col.n, r, z, m, seed=seed, L=0)
+    for q in range(col.n):
+        lo, hi = int(off[q]), int(off[q + 1])
+        got = dict(zip(ids[lo:hi].tolist(), dist[lo:hi].tolist()))
+        assert got == partners[q]
+        assert ids[lo:hi].tolist() == sorted(got)
+
+
+def test_query_results_are_true_matches(oracle_lib):
+    rng = np.random.default_rng(4)
+    col = sd.clusters(4, 15, lambda rr, b: 3, lambda rr: rr.integers(40, 120),
+                      lambda rr, L: rr.poisson(5))
+    S = col.strings()
+    Q, Kq = [], []
+    for i in range(12):
+        base = S[int(rng.integers(0, col.n))]
+        Q.append(base if i % 3 == 0 else bytes(sd.mutate(rng, np.frombuffer(base, np.uint8),
+                                                         int(rng.integers(0, 6)),
+                                                         np.frombuffer(b"ACGT", np.uint8))))
+        Kq.append(int(rng.integers(0, 12)))
+    qc = sd.from_strings(Q)
+    off, ids, dist = oracle_lib.query(col.chars, col.offsets, qc.chars, qc.offsets, Kq, 4, 6, 2,
+                                      seed=9, L=0)
+    for q in range(len(Q)):
+        lo, hi = int(off[q]), int(off[q + 1])
+        for s, d in zip(ids[lo:hi].tolist(), dist[lo:hi].tolist()):
+            assert oracle_lib.ed_full(Q[q], S[s]) == d <= Kq[q]
+        if q % 3 == 0:   # an exact copy of an index string finds it
+            assert 0 in dist[lo:hi].tolist()
+    with pytest.raises(ValueError):
+        bad = sd.from_strings([b"ACGZ"])
+        oracle_lib.query(col.chars, col.offsets, bad.chars, bad.offsets, [1], 2, 2, 2)
