@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=["medium", "tiny"])
+    ap.add_argument("--workload", default="medium", choices=["medium", "tiny", "uneven"])
     ap.add_argument("--K", type=int, default=None)
     ap.add_argument("--r", type=int, default=None)
     ap.add_argument("--z", type=int, default=None)
@@ -50,6 +50,10 @@ def parse():
                     help="use the workload's stated (r, z, m, L) instead of the recall-calibrated point")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched form with default knobs instead of the autotuner's")
+    ap.add_argument("--no-uneven", action="store_true",
+                    help="skip the uneven-length join (80,000 strings, K=400)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (index of 320,000 strings, 10,000 queries)")
     ap.add_argument("--serving-only", action="store_true",
@@ -83,6 +87,7 @@ def copy_probe(nbytes):
 CALIBRATED = {
     "medium": dict(r=32, z=16, m=18, L=64),
     "tiny": dict(r=7, z=16, m=8, L=64),
+    "uneven": dict(r=32, z=16, m=18, L=64),
 }
 
 
@@ -109,6 +114,10 @@ def workload(args):
     if args.workload == "medium":
         col, prm = sd.medium_dna(0, K=args.K or 500)
         name = "medium DNA: 20,000 strings (2,000 bases U{4500..5500} x 10 copies, Poisson(0.04 len) edits)"
+    elif args.workload == "uneven":
+        col, prm = sd.uneven_dna(0)
+        name = ("uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, clusters "
+                "geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)")
     else:
         col, prm = sd.tiny_dna(0)
         name = "tiny DNA: 2,000 strings (200 bases U{900..1100} x 10 copies, Poisson(30) edits)"
@@ -312,6 +321,91 @@ def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
                                       recall=round(hit / true_n, 4) if true_n else None))
 
 
+def run_forms(ej, ctx, chars, offs, prm, args):
+    """The plain per-stage form (default knobs, two-pass verification) and the
+    batched form (persistent verification, knobs from the autotuner), timed
+    on the same device-resident input."""
+    flags = ej.FLAG_TIMING
+    defaults = ctx.knobs()
+    ctx.tune_set("verify_mode", 0)
+    res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, flags)
+    plain = dict(res=res, ms=ms, stage=stage, knobs=ctx.knobs(), kernel="k_verify")
+    if args.no_autotune:
+        ctx.tune_set("verify_mode", 1)
+        tune_ms = None
+    else:
+        tune_ms, _ = ctx.autotune(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
+                                  L=prm["L"], reps=2)
+    knobs = ctx.knobs()
+    res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, flags)
+    batched = dict(res=res, ms=ms, stage=stage, knobs=knobs, autotune_best_ms=tune_ms,
+                   kernel="k_verify_queue" if knobs["verify_mode"] == 1 else "k_verify")
+    for k, v in defaults.items():
+        ctx.tune_set(k, v)
+    return dict(plain=plain, batched=batched)
+
+
+def roofline(res, stage, prm, kern):
+    """Algorithmic integer operations per step of the dominant kernel over
+    its own device time per step (events around each launch)."""
+    if stage.get("verify", 0.0) >= stage.get("embed", 0.0) and res.verify_columns:
+        cells = res.verify_columns * (prm["K"] + 1)
+        ops = cells / 32.0 * OPS_PER_WORD_STEP
+        t = stage["verify_kernel"] / 1000.0
+        nl = max(1, res.verify_launches)
+        work = dict(launches_per_step=res.verify_launches,
+                    avg_launch_ms=round(stage["verify_kernel"] / nl, 4),
+                    band_cells=int(cells), text_columns=int(res.verify_columns),
+                    gcells_per_s=round(cells / t / 1e9, 2) if t > 0 else None,
+                    ukkonen_2k1_gcells_per_s=round(res.verify_columns * (2 * prm["K"] + 1)
+                                                   / t / 1e9, 2) if t > 0 else None)
+    else:
+        kern = "k_embed"
+        ops = res.walk_steps * OPS_PER_WALK_STEP
+        t = stage["embed"] / 1000.0
+        work = dict(walk_steps=int(res.walk_steps),
+                    gsteps_per_s=round(res.walk_steps / t / 1e9, 2) if t > 0 else None)
+    achieved = ops / t / 1e12 if t > 0 else 0.0
+    peak = MI355X_INT32_LANE_OPS / 1e12
+    return dict(bound="alu", kernel=kern, achieved=round(achieved, 4), peak=round(peak, 2),
+                unit="T int32 lane-op/s", frac=round(achieved / peak, 5), traffic=None,
+                traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, "
+                             "copy-scaled)",
+                kernel_ms=round(t * 1000.0, 4), **work)
+
+
+def form_summary(f, prm):
+    res, ms, stage = f["res"], f["ms"], f["stage"]
+    roof = roofline(res, stage, prm, f["kernel"])
+    return dict(join_sec=round(ms / 1000.0, 5),
+                verified_pairs_per_s=round(res.n_candidates / (ms / 1000.0), 3),
+                stage_ms={k: round(v, 3) for k, v in stage.items()},
+                kernel=roof["kernel"], kernel_ms=roof["kernel_ms"], roofline_frac=roof["frac"],
+                knobs=f["knobs"])
+
+
+def uneven_bench(ej, ctx, oracle, args):
+    """The batched uneven-length join (80,000 DNA strings, log-uniform
+    lengths, K=400) in both forms at its recall-calibrated point."""
+    import torch
+    import synthdata as sd
+    col, stated = sd.uneven_dna(0)
+    prm = dict(K=stated["K"], **CALIBRATED["uneven"])
+    chars = torch.from_numpy(col.chars).cuda()
+    offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
+    forms = run_forms(ej, ctx, chars, offs, prm, args)
+    b = forms["batched"]
+    out = dict(workload="uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, "
+                        "clusters geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)",
+               params=prm, stated=dict(K=stated["K"], r=stated["r"], z=stated["z"],
+                                       m=stated["m"]),
+               candidates=b["res"].n_candidates, output_pairs=int(len(b["res"].pairs)),
+               batched=form_summary(b, prm), plain=form_summary(forms["plain"], prm))
+    if not args.no_recall:
+        out["recall"] = recall_estimate(col, b["res"], prm["K"], oracle)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -339,47 +433,22 @@ def main():
     chars = torch.from_numpy(col.chars.copy()).cuda()
     offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
     ctx = ej.Context(0)
-    flags = ej.FLAG_TIMING
-    res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, flags)
+    forms = run_forms(ej, ctx, chars, offs, prm, args)
+    head = forms["batched"]
+    res, ms, stage = head["res"], head["ms"], head["stage"]
     cand = res.n_candidates
     value = cand / (ms / 1000.0)
     # context run at the stated parameters (one join, not the headline)
     stated_info = None
     if prm != stated:
-        r2, ms2, st2 = time_join(ctx, chars, offs, stated, 2, 1, flags)
+        r2, ms2, st2 = time_join(ctx, chars, offs, stated, 2, 1, ej.FLAG_TIMING)
         stated_info = dict(params=stated, join_ms=round(ms2, 3), candidates=r2.n_candidates,
                            output_pairs=int(len(r2.pairs)),
                            stage_ms={k: round(v, 3) for k, v in st2.items()})
-    # roofline of the dominant kernel: algorithmic integer operations per step
-    # over the kernel's own device time per step (events around each launch)
-    if stage.get("verify", 0.0) >= stage.get("embed", 0.0) and res.verify_columns:
-        kern = "k_verify"
-        cells = res.verify_columns * (prm["K"] + 1)
-        ops = cells / 32.0 * OPS_PER_WORD_STEP
-        t = stage["verify_kernel"] / 1000.0
-        nl = max(1, res.verify_launches)
-        work = dict(launches_per_step=res.verify_launches,
-                    avg_launch_ms=round(stage["verify_kernel"] / nl, 4),
-                    band_cells=int(cells), text_columns=int(res.verify_columns),
-                    gcells_per_s=round(cells / t / 1e9, 2) if t > 0 else None,
-                    ukkonen_2k1_gcells_per_s=round(res.verify_columns * (2 * prm["K"] + 1)
-                                                   / t / 1e9, 2) if t > 0 else None)
-    else:
-        kern = "k_embed"
-        ops = res.walk_steps * OPS_PER_WALK_STEP
-        t = stage["embed"] / 1000.0
-        work = dict(walk_steps=int(res.walk_steps),
-                    gsteps_per_s=round(res.walk_steps / t / 1e9, 2) if t > 0 else None)
-    achieved = ops / t / 1e12 if t > 0 else 0.0
-    peak = MI355X_INT32_LANE_OPS / 1e12
-    traffic = None
-    if (kern == "k_verify" and args.workload == "medium" and prm["K"] == 500
+    roof = roofline(res, stage, prm, head["kernel"])
+    if (roof["kernel"].startswith("k_verify") and args.workload == "medium" and prm["K"] == 500
             and prm == dict(stated, **CALIBRATED["medium"])):
-        traffic = measured_traffic("k_verify", "medium_K500")
-    roof = dict(bound="alu", kernel=kern, achieved=round(achieved, 4), peak=round(peak, 2),
-                unit="T int32 lane-op/s", frac=round(achieved / peak, 5), traffic=traffic,
-                traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
-                kernel_ms=round(t * 1000.0, 4), **work)
+        roof["traffic"] = measured_traffic(roof["kernel"], "medium_K500")
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "verified candidate pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
@@ -387,15 +456,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "K": prm["K"], "r": prm["r"], "z": prm["z"], "m": prm["m"],
                    "L": res.L, "params": "stated" if prm == stated else "recall-calibrated",
+                   "form": "batched (persistent verification, autotuned launch knobs)",
                    "candidates": cand, "raw_candidates": res.n_raw,
                    "output_pairs": int(len(res.pairs)), "join_sec": round(ms / 1000.0, 5),
-                   "stage_ms": {k: round(v, 3) for k, v in stage.items()}},
+                   "stage_ms": {k: round(v, 3) for k, v in stage.items()},
+                   "knobs": head["knobs"],
+                   "plain_form": form_summary(forms["plain"], prm)},
         "roofline": roof,
     }
     if stated_info:
         out["config"]["stated_params_run"] = stated_info
     if not args.no_recall:
         out["config"]["recall"] = recall_estimate(col, res, prm["K"], oracle)
+    if not args.no_uneven:
+        try:
+            out["uneven"] = uneven_bench(ej, ctx, oracle, args)
+        except Exception as e:  # reported, never hides the join line
+            out["uneven"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_serving:
         try:
             out["serving"] = serving_bench(ej, ctx, oracle)

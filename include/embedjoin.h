@@ -120,6 +120,10 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_pass1_cols"     columns of verification pass 1 (multiple of 32;
  *                           0 = a single pass)
  *   "verify_blocks_per_cu"  workgroups per CU of the verification grid
+ *   "verify_mode"           0: two passes over fixed groups of pairs (the
+ *                           first C1 columns of all, then the survivors);
+ *                           1: one persistent launch in which each pair's
+ *                           lanes take the next pair from a device counter
  *   "verify_ring"           match-mask layout in LDS: 0 the whole pattern,
  *                           1 a ring of the words the band covers when it is
  *                           smaller, 2 the ring whenever the band has at
@@ -155,6 +159,17 @@ ej_status ej_join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_
                          uint32_t n, const ej_params *p, ej_result *out);
 
 void ej_result_free(ej_result *res);
+
+/* Autotuner of the batched form, for callers that run many joins of one
+ * shape.  Joins the caller's device-resident strings (as ej_join_device)
+ * repeatedly and descends one launch knob at a time (verification form,
+ * first-pass columns, grid, match-mask layout, radix width), keeping in the
+ * context the setting with the least wall time (best of `reps` joins per
+ * trial).  No knob changes any result.  *best_ms (may be NULL) receives the
+ * join time at the chosen setting.  About 15 trials; errors as
+ * ej_join_device. */
+ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                      const ej_params *p, uint32_t reps, float *best_ms);
 
 /* --------------------------------------------------------- stage entry points
  * Each stage can be called on its own; ej_join chains the same kernels.

@@ -27,7 +27,7 @@ FLAG_PLAIN, FLAG_GRAPH, FLAG_TIMING = 0, 1, 2
 EXPORTS = [
     "ej_create", "ej_destroy", "ej_last_error", "ej_version", "ej_workspace_bytes",
     "ej_tune_set", "ej_tune_get",
-    "ej_join", "ej_join_ex", "ej_join_device", "ej_result_free",
+    "ej_join", "ej_join_ex", "ej_join_device", "ej_result_free", "ej_autotune",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_set_explicit_randomness",
     "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
     "ej_index_size", "ej_qresult_free", "ej_index_free",
@@ -91,6 +91,8 @@ def lib():
         "ej_join_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params),
                                    ctypes.POINTER(_Result)]),
         "ej_result_free": (None, [ctypes.POINTER(_Result)]),
+        "ej_autotune": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32,
+                                ctypes.POINTER(ctypes.c_float)]),
         "ej_embed": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), vp, vp, u32p, u32p]),
         "ej_lsh_bucket": (c_int, [vp, vp, vp, u32, u32, u32, vp, vp, u64p]),
         "ej_candidates": (c_int, [vp, vp, vp, vp, u64, vp, u32, u32, u32, vp, u64, u64p, u64p]),
@@ -250,6 +252,23 @@ class Context:
                               int(res.verify_launches))
         finally:
             lib().ej_result_free(ctypes.byref(res))
+
+    KNOBS = ("verify_mode", "verify_pass1_cols", "verify_blocks_per_cu", "verify_ring",
+             "verify_lds_budget", "embed_lds_budget", "radix_bits", "bucket_key_bits")
+
+    def knobs(self) -> dict:
+        return {k: self.tune_get(k) for k in self.KNOBS}
+
+    def autotune(self, d_chars, d_offsets, K: int, r: int, z: int, m: int, seed: int = 0,
+                 L: int = 0, reps: int = 2):
+        """ej_autotune on device tensors; returns (best join ms, chosen knobs)."""
+        p = Params(K, r, z, m, L, 0, seed)
+        best = ctypes.c_float()
+        n = d_offsets.numel() - 1
+        _torch_stream_done()
+        self._check(lib().ej_autotune(self._h, _ptr(d_chars), _ptr(d_offsets), n,
+                                      ctypes.byref(p), reps, ctypes.byref(best)))
+        return float(best.value), self.knobs()
 
     # ------------------------------------------------------------- stages --
     def embed(self, d_chars, d_offsets, r: int, z: int, m: int, seed: int = 0, L: int = 0,

@@ -2,6 +2,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
+#include <vector>
+
 #include "ej_internal.h"
 
 namespace ej {
@@ -272,6 +275,60 @@ ej_status ej_join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_
                          const ej_params *p, ej_result *out) {
     if (!p || !out || !d_offsets) return EJ_EINVAL;
     return run_guarded(ctx, [&] { join_device(ctx, d_chars, d_offsets, n, *p, out); });
+}
+
+ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                      const ej_params *p, uint32_t reps, float *best_ms) {
+    if (!p || !d_offsets) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        check_params(*p, n);
+        if (reps == 0) reps = 1;
+        ej_params q = *p;
+        q.flags &= ~(uint32_t)EJ_FLAG_TIMING;
+        auto trial = [&]() {
+            double best = 1e30;
+            for (uint32_t i = 0; i < reps; i++) {
+                ej_result res;
+                auto t0 = std::chrono::steady_clock::now();
+                join_device(ctx, d_chars, d_offsets, n, q, &res);
+                auto t1 = std::chrono::steady_clock::now();
+                ej_result_free(&res);
+                best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+            }
+            return best;
+        };
+        trial();  // warm the workspace
+        double cur = trial();
+        // coordinate descent, one knob at a time, in order of expected effect
+        struct Knob {
+            uint32_t Tuning::*field;
+            std::vector<uint32_t> vals;
+            int only_mode;  // -1: always; else only when verify_mode has this value
+        };
+        const Knob knobs[] = {
+            {&Tuning::verify_mode, {0, 1}, -1},
+            {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 0},
+            {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 0},
+            {&Tuning::verify_ring, {1, 0}, -1},
+            {&Tuning::radix_bits, {6, 8, 11}, -1},
+        };
+        for (const Knob &k : knobs) {
+            if (k.only_mode >= 0 && ctx->tune.verify_mode != (uint32_t)k.only_mode) continue;
+            const uint32_t start = ctx->tune.*(k.field);
+            uint32_t best_v = start;
+            for (uint32_t v : k.vals) {
+                if (v == start) continue;
+                ctx->tune.*(k.field) = v;
+                const double t = trial();
+                if (t < cur) {
+                    cur = t;
+                    best_v = v;
+                }
+            }
+            ctx->tune.*(k.field) = best_v;
+        }
+        if (best_ms) *best_ms = (float)cur;
+    });
 }
 
 ej_status ej_join_ex(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,

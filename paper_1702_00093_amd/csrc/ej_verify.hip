@@ -207,6 +207,48 @@ __device__ inline PairView view_pair(const uint8_t *codes_a, const uint64_t *off
     return v;
 }
 
+// Writes the match masks of words w0 .. w0+nw-1 for every tile whose
+// leader lane (lane t*NL) is set in `leaders`, 64 pattern rows per ballot:
+// the whole wave reads the rows of one tile's pattern at a time.
+template <bool RING>
+__device__ inline void fill_masks(uint32_t *lds, uint64_t leaders, const PairView &v, uint32_t NL,
+                                  uint32_t tile_words, uint32_t stride, uint32_t RW, uint32_t wpp,
+                                  uint32_t sigma, uint32_t w0, uint32_t nw, uint32_t lane) {
+    while (leaders) {
+        const uint32_t b = (uint32_t)__builtin_ctzll(leaders);
+        leaders &= leaders - 1;
+        const uint32_t t = b / NL;
+        const uint32_t mt = readlane_u32(v.m, b);
+        const uint32_t Ot = readlane_u32(v.O, b);
+        const uint8_t *xt =
+            (const uint8_t *)(uintptr_t)readlane_u64((uint64_t)(uintptr_t)v.xp, b);
+        uint32_t *pq = lds + t * tile_words;
+        for (uint32_t q = 0; 2 * q < nw; q++) {
+            const int64_t row = (int64_t)32 * w0 + 64 * q + lane - Ot;
+            uint32_t c = 0xFFFFFFFFu;
+            if (row >= 1 && row <= (int64_t)mt) c = xt[row - 1];
+            const uint32_t wa = w0 + 2 * q, wb = wa + 1;
+            for (uint32_t ch = 0; ch < sigma; ch++) {
+                const uint64_t msk = __builtin_amdgcn_ballot_w64(c == ch);
+                if (RING) {
+                    const uint32_t sa = wa & (RW - 1), sb = wb & (RW - 1);
+                    if (lane == 0) {
+                        pq[ch * stride + sa] = (uint32_t)msk;
+                        pq[ch * stride + sa + RW] = (uint32_t)msk;
+                    }
+                    if (lane == 1) {
+                        pq[ch * stride + sb] = (uint32_t)(msk >> 32);
+                        pq[ch * stride + sb + RW] = (uint32_t)(msk >> 32);
+                    }
+                } else {
+                    if (lane == 0) pq[ch * stride + wa] = (uint32_t)msk;
+                    if (lane == 1 && wb < wpp) pq[ch * stride + wb] = (uint32_t)(msk >> 32);
+                }
+            }
+        }
+    }
+}
+
 // Match masks of a pair live in LDS in one of two layouts:
 //   full (RING = false): word w of symbol c at c*stride + w, stride = wpp,
 //        the whole pattern;
@@ -257,40 +299,12 @@ __global__ void __launch_bounds__(64)
                                      pidx, act);
         __syncthreads();
         // ---- match masks of the words the first block needs (ring) or of
-        //      the whole pattern (full), 64 rows per ballot
+        //      the whole pattern (full)
         {
-            const uint32_t w0 = RING ? (jbeg >> 5) : 0u;
-            const uint32_t nw = RING ? NL + 1 : wpp;
-            for (uint32_t t = 0; t < tpw; t++) {
-                const uint32_t mt = readlane_u32(v.m, t * NL);
-                const uint32_t Ot = readlane_u32(v.O, t * NL);
-                const uint8_t *xt =
-                    (const uint8_t *)(uintptr_t)readlane_u64((uint64_t)(uintptr_t)v.xp, t * NL);
-                uint32_t *pq = lds + t * tile_words;
-                for (uint32_t q = 0; 2 * q < nw; q++) {
-                    const int64_t row = (int64_t)32 * w0 + 64 * q + lane - Ot;
-                    uint32_t c = 0xFFFFFFFFu;
-                    if (row >= 1 && row <= (int64_t)mt) c = xt[row - 1];
-                    const uint32_t wa = w0 + 2 * q, wb = wa + 1;
-                    for (uint32_t ch = 0; ch < sigma; ch++) {
-                        const uint64_t msk = __builtin_amdgcn_ballot_w64(c == ch);
-                        if (RING) {
-                            const uint32_t sa = wa & (RW - 1), sb = wb & (RW - 1);
-                            if (lane == 0) {
-                                pq[ch * stride + sa] = (uint32_t)msk;
-                                pq[ch * stride + sa + RW] = (uint32_t)msk;
-                            }
-                            if (lane == 1) {
-                                pq[ch * stride + sb] = (uint32_t)(msk >> 32);
-                                pq[ch * stride + sb + RW] = (uint32_t)(msk >> 32);
-                            }
-                        } else {
-                            if (lane == 0) pq[ch * stride + wa] = (uint32_t)msk;
-                            if (lane == 1 && wb < wpp) pq[ch * stride + wb] = (uint32_t)(msk >> 32);
-                        }
-                    }
-                }
-            }
+            uint64_t leaders = 0;
+            for (uint32_t t = 0; t < tpw; t++) leaders |= 1ull << (t * NL);
+            fill_masks<RING>(lds, leaders, v, NL, tile_words, stride, RW, wpp, sigma,
+                             RING ? (jbeg >> 5) : 0u, RING ? NL + 1 : wpp, lane);
         }
         __syncthreads();
 
@@ -402,6 +416,170 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// Persistent form.  The grid stays resident and every tile (the NL lanes of
+// one pair) takes the next pair from a device-wide counter as soon as its
+// current pair is decided, so a wave never idles on its longest pair and
+// nothing is saved between passes.  Pairs decided without any column (length
+// gap above the threshold, empty text) are written when taken.  A wave
+// leaves once the counter has passed `count` and none of its tiles holds a
+// pair; every tile takes at most `count` pairs, so every wave exits.
+template <int MODE, bool RING>
+__global__ void __launch_bounds__(64)
+    k_verify_queue(const uint8_t *__restrict__ codes_a, const uint64_t *__restrict__ off_a,
+                   uint64_t base_a, const uint8_t *__restrict__ codes_b,
+                   const uint64_t *__restrict__ off_b, uint64_t base_b,
+                   const uint64_t *__restrict__ pairs, uint32_t count, uint32_t K,
+                   const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL, uint32_t tpw,
+                   uint32_t wpp, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
+                   unsigned long long *__restrict__ columns) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t tile = lane / NL, l = lane - tile * NL;
+    const bool in_tile = tile < tpw;
+    const uint32_t RW = wpp;
+    const uint32_t stride = RING ? 2 * RW : wpp;
+    const uint32_t tile_words = sigma * stride;
+    const uint32_t R = (32 + NL - 1) / NL;
+    const uint32_t nlmask = NL >= 32 ? 0xFFFFFFFFu : ((1u << NL) - 1u);
+    uint64_t last = 0;
+    for (uint32_t q = 0; q < 64; q++)
+        if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
+    const uint64_t notlast = ~last;
+    const uint32_t keep = (l == NL - 1 || !in_tile) ? 0u : 0xFFFFFFFFu;
+    uint32_t *pq_mine = lds + (in_tile ? tile : 0) * tile_words;
+    const uint8_t *peq8 = (const uint8_t *)pq_mine;
+
+    PairView v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K, 0, false);
+    uint32_t pidx = 0;
+    bool active = in_tile;  // may still hold or take pairs
+    bool need = in_tile;    // holds no pair
+    bool owner = false;
+    uint32_t jb = 0, Pv = 0, Mv = 0, Z = 0, kstar = 0, kbit = 0;
+    uint32_t tw[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) tw[q] = 0;
+
+    for (;;) {
+        // ---- tiles without a pair take the next one
+        for (;;) {
+            if (__builtin_amdgcn_ballot_w64(need && l == 0) == 0) break;
+            uint32_t got = 0xFFFFFFFFu;
+            if (need && l == 0) got = atomicAdd(next, 1u);
+            got = (uint32_t)__shfl((int)got, (int)(tile * NL), 64);
+            bool fresh = false;
+            if (need) {
+                if (got >= count) {
+                    need = false;
+                    active = false;
+                    owner = false;
+                    v.m = 0;
+                    v.nn = 0;
+                } else {
+                    pidx = got;
+                    v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K,
+                                  pidx, true);
+                    kstar = v.O + v.dstar;
+                    owner = (kstar >> 5) == l;
+                    kbit = kstar & 31;
+                    jb = 0;
+                    Z = 0;
+                    // D[i][0] = |i|: bit k holds row k - O, rows <= 0 have delta -1
+                    const int lo = 32 * (int)l;
+                    const int Oi = (int)v.O;
+                    Mv = Oi >= lo + 31 ? ~0u : (Oi < lo ? 0u : (1u << (Oi - lo + 1)) - 1u);
+                    Pv = ~Mv;
+                    if (v.skip || v.nn == 0) {
+                        // decided without a column: length gap > K_p, or ED = |x|
+                        if (owner) {
+                            const uint32_t res = v.skip ? v.Kp + 1 : min(v.dstar, v.Kp + 1);
+                            dist[pidx] = (int32_t)res;
+                        }
+                    } else {
+                        need = false;
+                        fresh = true;
+                    }
+                }
+            }
+            const uint64_t fill = __builtin_amdgcn_ballot_w64(fresh && l == 0);
+            if (fill) {
+                fill_masks<RING>(lds, fill, v, NL, tile_words, stride, RW, wpp, sigma, 0u,
+                                 RING ? NL + 1 : wpp, lane);
+                __syncthreads();
+                if (fresh) load_text_block(v.yp, v.nn, 0, tw);
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+
+        // ---- one 32-column block of every tile that holds a pair
+        uint32_t tn[8];
+        load_text_block(v.yp, v.nn, jb + 32, tn);
+        uint32_t rc[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+        const uint32_t wn = (jb >> 5) + NL + 1;
+        if (RING && active) {
+#pragma unroll
+            for (uint32_t q = 0; q < 4; q++) {
+                const uint32_t bq = q * NL + l;
+                const int64_t row = (int64_t)32 * wn + bq - v.O;
+                if (q < R && bq < 32 && row >= 1 && row <= (int64_t)v.m) rc[q] = v.xp[row - 1];
+            }
+        }
+        const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
+        const bool ends_here = active && v.nn > jb && v.nn < jb + 32;
+        if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
+            const uint32_t km = (owner && jb + 32 <= v.nn) ? (1u << kbit) : 0u;
+            uint32_t unused = 0;
+            myers_block<MODE, true>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, unused, km, kbit,
+                                    notlast, keep);
+        } else {
+            uint32_t acc = 0;
+            myers_block<MODE, false>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, acc, 0u, kbit,
+                                     notlast, keep);
+            const uint32_t ncol = v.nn > jb ? min(v.nn - jb, 32u) : 0u;
+            const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
+            if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
+        }
+        if (RING) {
+            const uint32_t sl = wn & (RW - 1);
+            for (uint32_t ch = 0; ch < sigma; ch++) {
+                uint32_t word = 0;
+                for (uint32_t q = 0; q < R; q++) {
+                    const uint64_t B = __builtin_amdgcn_ballot_w64(rc[q] == ch);
+                    const uint32_t part = (uint32_t)(B >> (tile * NL)) & nlmask;
+                    word |= q * NL < 32 ? (part << (q * NL)) : 0u;
+                }
+                if (active && l == 0) {
+                    pq_mine[ch * stride + sl] = word;
+                    pq_mine[ch * stride + sl + RW] = word;
+                }
+            }
+            __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        }
+        if (active) jb += 32;
+#pragma unroll
+        for (int q = 0; q < 8; q++) tw[q] = tn[q];
+
+        // ---- decisions live in the owner lane; the tile learns them by ballot
+        const uint32_t cols = min(jb, v.nn);
+        const uint32_t Vd = v.dstar + cols - Z;
+        const bool fin_owner = owner && active && !(Vd <= v.Kp && jb < v.nn);
+        const uint64_t fin = __builtin_amdgcn_ballot_w64(fin_owner);
+        const uint32_t owner_lane = tile * NL + (kstar >> 5);
+        const bool tile_fin = in_tile && active && ((fin >> (owner_lane & 63)) & 1ull);
+        if (fin_owner) {
+            dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
+            if (columns) atomicAdd(columns, (unsigned long long)cols);
+        }
+        if (tile_fin) {
+            need = true;
+            owner = false;
+        }
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *__restrict__ p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
+}
+
 __global__ void k_max_u32(const uint32_t *__restrict__ a, uint64_t n, uint32_t *__restrict__ out) {
     uint32_t mx = 0;
     for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
@@ -500,6 +678,37 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     if (lds > 65536)
         EJ_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
+    Timers &tk = ctx->timers;
+    auto kmark = [&]() {
+        if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
+    };
+    if (ctx->tune.verify_mode == 1) {
+        // persistent form: one resident grid, a device-wide pair counter
+        auto qkern = mode == LANES_ONE    ? k_verify_queue<LANES_ONE, false>
+                     : mode == LANES_ROW  ? (ring ? k_verify_queue<LANES_ROW, true>
+                                                  : k_verify_queue<LANES_ROW, false>)
+                     : mode == LANES_WAVE ? (ring ? k_verify_queue<LANES_WAVE, true>
+                                                  : k_verify_queue<LANES_WAVE, false>)
+                     : (ring ? k_verify_queue<LANES_ANY, true> : k_verify_queue<LANES_ANY, false>);
+        if (lds > 65536)
+            EJ_HIP(hipFuncSetAttribute((const void *)qkern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int occ = 0;
+        EJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, qkern, 64, lds));
+        if (occ < 1) occ = 1;
+        const uint64_t ngroups = (count + tpw - 1) / tpw;
+        const uint64_t grid = std::min<uint64_t>(ngroups, (uint64_t)ctx->num_cu * occ);
+        uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
+        EJ_CHECK_LAUNCH();
+        kmark();
+        hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
+                           d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs,
+                           (uint32_t)count, K, d_Kq, sig, NL, tpw, wpp, next, d_dist, d_columns);
+        EJ_CHECK_LAUNCH();
+        kmark();
+        return;
+    }
     const uint32_t C1 = ctx->tune.verify_pass1_cols & ~31u;
     const bool two_pass = C1 > 0 && C1 < mtext;
     uint32_t *state = nullptr, *aux = nullptr;
@@ -508,10 +717,6 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         aux = ws<uint32_t>(ctx, "verify_aux", count);
     }
     const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;
-    Timers &tk = ctx->timers;
-    auto kmark = [&]() {
-        if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
-    };
     {
         kmark();
         uint64_t ngroups = (count + tpw - 1) / tpw;

@@ -34,6 +34,17 @@ def ctx(ej):
     return ej.Context(0)
 
 
+def _each_verify_mode(ctx):
+    """Runs the body once per verification form (two-pass, persistent)."""
+    old = ctx.tune_get("verify_mode")
+    try:
+        for mode in (0, 1):
+            ctx.tune_set("verify_mode", mode)
+            yield mode
+    finally:
+        ctx.tune_set("verify_mode", old)
+
+
 def _oracle_join(oracle_lib, col, K, r, z, m, seed, L=0):
     return oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
 
@@ -159,9 +170,10 @@ def test_verify_matches_ukkonen(ej, ctx, oracle_lib, K):
     codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
     want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
     chars, offs = to_device(col)
-    _say(f"verify K={K} n={n}")
-    got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
-    assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+    for mode in _each_verify_mode(ctx):
+        _say(f"verify K={K} n={n} mode={mode}")
+        got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+        assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
 
 
 def test_verify_per_pair_thresholds(ej, ctx, oracle_lib):
@@ -177,10 +189,11 @@ def test_verify_per_pair_thresholds(ej, ctx, oracle_lib):
     want = [int(oracle_lib.verify_pairs(col.chars, col.offsets, codes[i:i + 1], int(Kq[i]))[0])
             for i in range(300)]
     chars, offs = to_device(col)
-    _say("verify per-pair thresholds")
-    got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), 0,
-                     d_Kq=torch.from_numpy(Kq.astype(np.int32)).cuda())
-    assert got.cpu().numpy().tolist() == want
+    for mode in _each_verify_mode(ctx):
+        _say(f"verify per-pair thresholds mode={mode}")
+        got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), 0,
+                         d_Kq=torch.from_numpy(Kq.astype(np.int32)).cuda())
+        assert got.cpu().numpy().tolist() == want
 
 
 def test_verify_long_strings_random_and_similar(ej, ctx, oracle_lib):
@@ -193,9 +206,10 @@ def test_verify_long_strings_random_and_similar(ej, ctx, oracle_lib):
     chars, offs = to_device(col)
     for K in (250, 500):
         want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
-        _say(f"verify long K={K}")
-        got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
-        assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+        for mode in _each_verify_mode(ctx):
+            _say(f"verify long K={K} mode={mode}")
+            got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+            assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
 
 
 @pytest.mark.parametrize("K", [254, 300, 500, 700, 1000, 2046])
@@ -213,18 +227,21 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
     want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K).tolist()
     chars, offs = to_device(col)
     d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
-    old = (ctx.tune_get("verify_ring"), ctx.tune_get("verify_pass1_cols"))
+    old = (ctx.tune_get("verify_ring"), ctx.tune_get("verify_pass1_cols"),
+           ctx.tune_get("verify_mode"))
     try:
         for ring in (0, 2):
-            for c1 in (0, 64, 1024):
+            for mode, c1 in ((0, 0), (0, 64), (0, 1024), (1, 0)):
                 ctx.tune_set("verify_ring", ring)
                 ctx.tune_set("verify_pass1_cols", c1)
-                _say(f"verify layout K={K} ring={ring} c1={c1}")
+                ctx.tune_set("verify_mode", mode)
+                _say(f"verify layout K={K} ring={ring} mode={mode} c1={c1}")
                 got = ctx.verify(chars, offs, d_codes, K)
                 assert got.cpu().numpy().astype(np.uint32).tolist() == want
     finally:
         ctx.tune_set("verify_ring", old[0])
         ctx.tune_set("verify_pass1_cols", old[1])
+        ctx.tune_set("verify_mode", old[2])
 
 
 # ------------------------------------------------------------ edge cases ----
@@ -240,10 +257,11 @@ def test_edge_cases(ej, ctx, oracle_lib):
     for name, S in cases:
         col = sd.from_strings(S)
         for K in (0, 1, 3):
-            _say(f"edge {name} K={K}")
             ref = _oracle_join(oracle_lib, col, K, 3, 4, 2, 11)
-            res = ctx.join(col.chars, col.offsets, K, 3, 4, 2, seed=11)
-            _assert_join_equal(res, ref)
+            for mode in _each_verify_mode(ctx):
+                _say(f"edge {name} K={K} mode={mode}")
+                res = ctx.join(col.chars, col.offsets, K, 3, 4, 2, seed=11)
+                _assert_join_equal(res, ref)
 
 
 def test_invalid_arguments_are_rejected(ej, ctx):
@@ -279,8 +297,9 @@ def test_tiny_dna_workload_full(ej, ctx, oracle_lib):
     res = ctx.join(col.chars, col.offsets, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
     _assert_join_equal(res, ref)
     chars, offs = to_device(col)
-    res2 = ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
-    _assert_join_equal(res2, ref)
+    for mode in _each_verify_mode(ctx):
+        res2 = ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
+        _assert_join_equal(res2, ref)
 
 
 def test_tiny_dna_recall_point(ej, ctx, oracle_lib):
@@ -332,7 +351,7 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
     knobs = [("radix_bits", 4), ("radix_bits", 11), ("bucket_key_bits", 5),
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
              ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
-             ("verify_ring", 2)]
+             ("verify_ring", 2), ("verify_mode", 1)]
     for name, val in knobs:
         old = ctx.tune_get(name)
         try:
@@ -346,3 +365,24 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
         ctx.tune_set("radix_bits", 3)
     with pytest.raises(ej.EmbedJoinError):
         ctx.tune_set("no_such_knob", 1)
+
+
+def test_autotune_keeps_results(ej, ctx, oracle_lib):
+    """The autotuner picks launch knobs on the caller's workload; the join
+    at the chosen setting still equals the oracle's."""
+    col = sd.clusters(31, 30, lambda rr, b: 4, lambda rr: rr.integers(200, 700),
+                      lambda rr, LL: rr.poisson(15))
+    K, r, z, m, L = 60, 4, 6, 4, 48
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 8, L)
+    chars, offs = to_device(col)
+    before = ctx.knobs()
+    try:
+        _say("autotune")
+        best, knobs = ctx.autotune(chars, offs, K, r, z, m, seed=8, L=L, reps=1)
+        assert best > 0
+        assert knobs["verify_mode"] in (0, 1) and 4 <= knobs["radix_bits"] <= 11
+        res = ctx.join(chars, offs, K, r, z, m, seed=8, L=L)
+        _assert_join_equal(res, ref)
+    finally:
+        for k, v in before.items():
+            ctx.tune_set(k, v)
