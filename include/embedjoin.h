@@ -124,6 +124,9 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *                           first C1 columns of all, then the survivors);
  *                           1: one persistent launch in which each pair's
  *                           lanes take the next pair from a device counter
+ *   "verify_order"          persistent form, joins only: 0 pairs in list
+ *                           order, 1 most frequent pairs (found by the most
+ *                           tables) first, which shortens the tail
  *   "verify_ring"           match-mask layout in LDS: 0 the whole pattern,
  *                           1 a ring of the words the band covers when it is
  *                           smaller, 2 the ring whenever the band has at

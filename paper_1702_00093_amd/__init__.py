@@ -253,7 +253,7 @@ class Context:
         finally:
             lib().ej_result_free(ctypes.byref(res))
 
-    KNOBS = ("verify_mode", "verify_pass1_cols", "verify_blocks_per_cu", "verify_ring",
+    KNOBS = ("verify_mode", "verify_order", "verify_pass1_cols", "verify_blocks_per_cu", "verify_ring",
              "verify_lds_budget", "embed_lds_budget", "radix_bits", "bucket_key_bits")
 
     def knobs(self) -> dict:

@@ -122,14 +122,29 @@ __global__ void k_unique_flags(const uint64_t *__restrict__ codes, uint64_t cnt,
 
 __global__ void k_unique_compact(const uint64_t *__restrict__ codes, uint64_t cnt, uint32_t B,
                                  const uint32_t *__restrict__ flags,
-                                 const uint32_t *__restrict__ pos, uint64_t *__restrict__ out) {
+                                 const uint32_t *__restrict__ pos, uint64_t *__restrict__ out,
+                                 uint32_t *__restrict__ first) {
     const uint64_t mask = (1ULL << B) - 1ULL;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (uint64_t)gridDim.x * blockDim.x) {
         if (flags[e]) {
             uint64_t c = codes[e];
             out[pos[e]] = ((c >> B) << 32) | (c & mask);
+            if (first) first[pos[e]] = (uint32_t)e;
         }
+    }
+}
+
+// Sort key of unique pair u: 0xFFFF - (number of raw copies, at most 0xFFFF),
+// so that an ascending sort puts the most frequent pairs first.
+__global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, uint64_t raw,
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < cnt;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t end = u + 1 < cnt ? first[u + 1] : raw;
+        const uint64_t m = end - first[u];
+        key[u] = 0xFFFFu - (uint32_t)(m < 0xFFFFu ? m : 0xFFFFu);
+        idx[u] = (uint32_t)u;
     }
 }
 
@@ -175,7 +190,8 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
 }
 
 uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, const uint32_t *d_len,
-                    uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag) {
+                    uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag,
+                    uint32_t **d_order_out) {
     std::string t(tag);
     const uint32_t n = bk.n;
     const uint64_t tot = (uint64_t)bk.T * n;
@@ -221,11 +237,23 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     uint64_t cnt = 0;
     read_back(ctx, d_cnt, 8, &cnt);
     uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
+    uint32_t *first = d_order_out ? ws<uint32_t>(ctx, t + "_first", cnt) : nullptr;
     hipLaunchKernelGGL(k_unique_compact, dim3(grid_for(ctx, raw, 256)), dim3(256), 0, ctx->stream,
                        (const uint64_t *)sorted, raw, B, (const uint32_t *)flags,
-                       (const uint32_t *)pos, pairs);
+                       (const uint32_t *)pos, pairs, first);
     EJ_CHECK_LAUNCH();
     *d_pairs_out = pairs;
+    if (d_order_out && cnt) {
+        uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
+        uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
+        uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", cnt);
+        uint32_t *order = ws<uint32_t>(ctx, t + "_order", cnt);
+        hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)first, cnt, raw, k0, v0);
+        EJ_CHECK_LAUNCH();
+        radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt, 16, 8);
+        *d_order_out = order;
+    }
     return cnt;
 }
 

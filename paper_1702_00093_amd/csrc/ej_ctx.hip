@@ -119,6 +119,7 @@ static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32
         {"verify_blocks_per_cu", &Tuning::verify_blocks_per_cu, 1, 1024},
         {"verify_ring", &Tuning::verify_ring, 0, 2},
         {"verify_mode", &Tuning::verify_mode, 0, 1},
+        {"verify_order", &Tuning::verify_order, 0, 1},
         {"embed_lds_budget", &Tuning::embed_lds_budget, 8192, 1u << 20},
         {"radix_bits", &Tuning::radix_bits, 4, 11},
         {"bucket_key_bits", &Tuning::bucket_key_bits, 1, 32},

@@ -91,6 +91,7 @@ struct Tuning {
     uint32_t verify_lds_budget = 48 * 1024;  // LDS per wave of the verification kernel
     uint32_t verify_pass1_cols = 1024;       // columns of verification pass 1 (0: one pass)
     uint32_t verify_blocks_per_cu = 32;      // resident-wave target of the verification grid
+    uint32_t verify_order = 1;               // persistent form: 0 pair order, 1 by table multiplicity
     uint32_t verify_mode = 0;                // 0 two passes over pair tiles, 1 persistent pair queue
     uint32_t verify_ring = 1;                // match masks: 0 whole pattern, 1 auto, 2 ring if it fits
     uint32_t embed_lds_budget = 48 * 1024;   // LDS per wave of the walk kernel
@@ -204,8 +205,12 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
 
 // Candidate pairs as packed codes (a << 32 | b), a < b, sorted and unique.
 // Returns the count; *n_raw gets the pre-dedup count.
+// With d_order_out, also a verification order of the pairs: by decreasing
+// number of tables that produced the pair (ties by position), so that pairs
+// likely to run their full length start first.
 uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, const uint32_t *d_len,
-                    uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag);
+                    uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag,
+                    uint32_t **d_order_out = nullptr);
 
 // Threshold edit distance of `count` pairs (codes a << 32 | b) over the
 // symbol codes of a string set.
@@ -213,7 +218,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
             const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b = nullptr,
             const uint64_t *d_offsets_b = nullptr, uint64_t base_b = 0, uint32_t maxlen_b = 0,
-            unsigned long long *d_columns = nullptr);
+            unsigned long long *d_columns = nullptr, const uint32_t *d_order = nullptr);
 
 uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported
 

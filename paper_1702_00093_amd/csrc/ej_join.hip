@@ -156,7 +156,10 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     tm.mark();  // 3
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
-    uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j");
+    uint32_t *order = nullptr;
+    const bool want_order = ctx->tune.verify_mode == 1 && ctx->tune.verify_order == 1;
+    uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j",
+                              want_order ? &order : nullptr);
     out->n_candidates = cnt;
     out->n_raw = raw;
     int32_t *dist = ws<int32_t>(ctx, "j_dist", cnt);
@@ -169,7 +172,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     ctx->timers.on = tm.on;
     ctx->timers.nkv = 0;
     verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, pairs, cnt, p.K, nullptr,
-           dist, nullptr, nullptr, 0, 0, d_cols);
+           dist, nullptr, nullptr, 0, 0, d_cols, order);
     ctx->timers.on = false;
     tm.mark();  // 5
     uint64_t nout = 0;
@@ -309,6 +312,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             {&Tuning::verify_mode, {0, 1}, -1},
             {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 0},
             {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 0},
+            {&Tuning::verify_order, {1, 0}, 1},
             {&Tuning::verify_ring, {1, 0}, -1},
             {&Tuning::radix_bits, {6, 8, 11}, -1},
         };

@@ -56,6 +56,13 @@ constexpr uint32_t DECIDED = 0xFFFFFFFFu;
 //   LANES_ANY  any other width: wave_shl plus a mask, carries cut per pair.
 enum { LANES_ONE = 0, LANES_ROW = 1, LANES_WAVE = 2, LANES_ANY = 3 };
 
+// Lanes per pair: fixed by the layout except for LANES_ANY, so that the
+// per-block index arithmetic folds to constants in the common layouts.
+template <int MODE>
+__device__ inline uint32_t lanes_of(uint32_t nl) {
+    return MODE == LANES_ONE ? 1u : MODE == LANES_ROW ? 16u : MODE == LANES_WAVE ? 64u : nl;
+}
+
 // s = a + b; the carry-out of every lane lands in one wave-wide mask.
 __device__ inline uint32_t add_carry_mask(uint32_t a, uint32_t b, uint64_t &carry) {
     uint32_t s;
@@ -270,11 +277,12 @@ __global__ void __launch_bounds__(64)
              uint64_t base_a, const uint8_t *__restrict__ codes_b,
              const uint64_t *__restrict__ off_b, uint64_t base_b,
              const uint64_t *__restrict__ pairs, uint64_t count, const uint32_t *__restrict__ list,
-             uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL,
+             uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL_arg,
              uint32_t tpw, uint32_t wpp, uint32_t jbeg, uint32_t jlim, int resume,
              uint32_t *__restrict__ state, uint32_t *__restrict__ aux,
              int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    const uint32_t NL = lanes_of<MODE>(NL_arg);
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
@@ -343,9 +351,11 @@ __global__ void __launch_bounds__(64)
             if (RING && in_tile) {
 #pragma unroll
                 for (uint32_t q = 0; q < 4; q++) {
+                    // pattern row 32*wn + bq - O (1-based), in 32-bit arithmetic
                     const uint32_t bq = q * NL + l;
-                    const int64_t row = (int64_t)32 * wn + bq - v.O;
-                    if (q < R && bq < 32 && row >= 1 && row <= (int64_t)v.m) rc[q] = v.xp[row - 1];
+                    const uint32_t r1 = 32 * wn + bq;
+                    if (q < R && bq < 32 && r1 > v.O && r1 - v.O <= v.m)
+                        rc[q] = v.xp[r1 - v.O - 1];
                 }
             }
             const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
@@ -422,17 +432,21 @@ __global__ void __launch_bounds__(64)
 // nothing is saved between passes.  Pairs decided without any column (length
 // gap above the threshold, empty text) are written when taken.  A wave
 // leaves once the counter has passed `count` and none of its tiles holds a
-// pair; every tile takes at most `count` pairs, so every wave exits.
+// pair; every tile takes at most `count` pairs, so every wave exits.  The
+// k-th pair taken is order[k] (or k): the order only schedules, results go
+// to dist[pair].
 template <int MODE, bool RING>
 __global__ void __launch_bounds__(64)
     k_verify_queue(const uint8_t *__restrict__ codes_a, const uint64_t *__restrict__ off_a,
                    uint64_t base_a, const uint8_t *__restrict__ codes_b,
                    const uint64_t *__restrict__ off_b, uint64_t base_b,
-                   const uint64_t *__restrict__ pairs, uint32_t count, uint32_t K,
-                   const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL, uint32_t tpw,
+                   const uint64_t *__restrict__ pairs, uint32_t count,
+                   const uint32_t *__restrict__ order, uint32_t K,
+                   const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL_arg, uint32_t tpw,
                    uint32_t wpp, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                    unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    const uint32_t NL = lanes_of<MODE>(NL_arg);
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
@@ -475,7 +489,7 @@ __global__ void __launch_bounds__(64)
                     v.m = 0;
                     v.nn = 0;
                 } else {
-                    pidx = got;
+                    pidx = order ? order[got] : got;
                     v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K,
                                   pidx, true);
                     kstar = v.O + v.dstar;
@@ -518,9 +532,11 @@ __global__ void __launch_bounds__(64)
         if (RING && active) {
 #pragma unroll
             for (uint32_t q = 0; q < 4; q++) {
+                // pattern row 32*wn + bq - O (1-based), in 32-bit arithmetic:
+                // 32*wn + bq stays below |x| + 32*NL + 64
                 const uint32_t bq = q * NL + l;
-                const int64_t row = (int64_t)32 * wn + bq - v.O;
-                if (q < R && bq < 32 && row >= 1 && row <= (int64_t)v.m) rc[q] = v.xp[row - 1];
+                const uint32_t r1 = 32 * wn + bq;
+                if (q < R && bq < 32 && r1 > v.O && r1 - v.O <= v.m) rc[q] = v.xp[r1 - v.O - 1];
             }
         }
         const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
@@ -623,7 +639,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
             const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b,
             const uint64_t *d_offsets_b, uint64_t base_b, uint32_t maxlen_b,
-            unsigned long long *d_columns) {
+            unsigned long long *d_columns, const uint32_t *d_order) {
     if (count == 0) return;
     if (count >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "more than 2^32 pairs in one verification");
     uint32_t Kmax = K;
@@ -704,7 +720,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         kmark();
         hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
                            d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs,
-                           (uint32_t)count, K, d_Kq, sig, NL, tpw, wpp, next, d_dist, d_columns);
+                           (uint32_t)count, d_order, K, d_Kq, sig, NL, tpw, wpp, next, d_dist,
+                           d_columns);
         EJ_CHECK_LAUNCH();
         kmark();
         return;

@@ -352,6 +352,16 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
              ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
              ("verify_ring", 2), ("verify_mode", 1)]
+    # the persistent form with and without the multiplicity order
+    ctx.tune_set("verify_mode", 1)
+    try:
+        for order in (0, 1):
+            ctx.tune_set("verify_order", order)
+            _say(f"persistent verification order={order}")
+            _assert_join_equal(ctx.join(col.chars, col.offsets, K, r, z, m, seed=5, L=L), ref)
+    finally:
+        ctx.tune_set("verify_mode", 0)
+        ctx.tune_set("verify_order", 1)
     for name, val in knobs:
         old = ctx.tune_get(name)
         try:
