@@ -62,7 +62,10 @@ typedef enum {
 
 /* Flags of ej_params.flags */
 #define EJ_FLAG_PLAIN 0u   /* one launch per stage, host-sized buffers */
-#define EJ_FLAG_GRAPH 1u   /* batched form: stages A1-A6 replayed from a captured HIP graph */
+#define EJ_FLAG_GRAPH 1u   /* with the persistent verification form ("verify_mode" 1): its
+                            launches are captured once into a HIP graph, cached in the
+                            context by launch arguments and replayed by later joins of
+                            the same shape */
 #define EJ_FLAG_TIMING 2u  /* record per-stage device times in ej_result */
 
 typedef struct ej_ctx ej_ctx;

@@ -33,6 +33,36 @@ void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes) {
 
 void sync(ej_ctx *ctx) { EJ_HIP(hipStreamSynchronize(ctx->stream)); }
 
+void run_captured(ej_ctx *ctx, const std::string &key, const std::function<void()> &enqueue) {
+    if (!ctx->graph_on) {
+        enqueue();
+        return;
+    }
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 32) {  // launch shapes changed often: start over
+            for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+            ctx->graphs.clear();
+        }
+        hipGraph_t g = nullptr;
+        EJ_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        try {
+            enqueue();
+        } catch (...) {
+            (void)hipStreamEndCapture(ctx->stream, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        EJ_HIP(hipStreamEndCapture(ctx->stream, &g));
+        hipGraphExec_t ge = nullptr;
+        hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) fail(EJ_EHIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+        it = ctx->graphs.emplace(key, ge).first;
+    }
+    EJ_HIP(hipGraphLaunch(it->second, ctx->stream));
+}
+
 void read_back(ej_ctx *ctx, const void *dsrc, size_t bytes, void *hdst) {
     if (bytes > 4096) fail(EJ_EINVAL, "read_back larger than the pinned staging buffer");
     EJ_HIP(hipMemcpyAsync(ctx->pinned, dsrc, bytes, hipMemcpyDeviceToHost, ctx->stream));
@@ -93,6 +123,8 @@ void ej_destroy(ej_ctx *ctx) {
         if (ctx->timers.ev[i]) (void)hipEventDestroy(ctx->timers.ev[i]);
     for (int i = 0; i < 4; i++)
         if (ctx->timers.kv[i]) (void)hipEventDestroy(ctx->timers.kv[i]);
+    for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -112,6 +113,10 @@ struct ej_ctx {
     uint64_t *pinned = nullptr;  // small pinned host buffer for size read-backs
     ej::Timers timers;
     ej::Tuning tune;
+    // EJ_FLAG_GRAPH: graphs of fixed launch sequences, keyed by every
+    // argument of their launches (pointers included), replayed on a match
+    bool graph_on = false;
+    std::map<std::string, hipGraphExec_t> graphs;
 };
 
 namespace ej {
@@ -122,6 +127,10 @@ T *ws(ej_ctx *ctx, const std::string &name, size_t count) {
     return (T *)ws_get(ctx, name, count * sizeof(T));
 }
 void sync(ej_ctx *ctx);
+// Runs `enqueue` (kernel launches only: no allocation, synchronisation or
+// memset) directly, or, with the context's graph mode on, as a captured graph
+// cached under `key`, which must identify every argument of the launches.
+void run_captured(ej_ctx *ctx, const std::string &key, const std::function<void()> &enqueue);
 // Copies `count` u64 words from device to host through the pinned buffer.
 void read_back(ej_ctx *ctx, const void *dsrc, size_t bytes, void *hdst);
 

@@ -171,9 +171,11 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     tm.mark();  // 4: the verification stage follows
     ctx->timers.on = tm.on;
     ctx->timers.nkv = 0;
+    ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode == 1;
     verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, pairs, cnt, p.K, nullptr,
            dist, nullptr, nullptr, 0, 0, d_cols, order);
     ctx->timers.on = false;
+    ctx->graph_on = false;
     tm.mark();  // 5
     uint64_t nout = 0;
     uint32_t *opairs = nullptr;

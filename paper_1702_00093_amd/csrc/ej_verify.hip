@@ -36,6 +36,8 @@
 // columns (most false candidates are rejected there), then the surviving
 // pairs, compacted, from their saved state -- so that waves are not held by
 // one long pair while the rest of their lanes idle.
+#include <stdio.h>
+
 #include <algorithm>
 
 #include "ej_internal.h"
@@ -715,14 +717,27 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         const uint64_t ngroups = (count + tpw - 1) / tpw;
         const uint64_t grid = std::min<uint64_t>(ngroups, (uint64_t)ctx->num_cu * occ);
         uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
-        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
-        EJ_CHECK_LAUNCH();
+        // the counter reset and the persistent launch: one captured graph in
+        // graph mode (keyed by every launch argument)
+        char key[512];
+        snprintf(key, sizeof(key),
+                 "verify_queue %d %d %p %p %llu %p %p %llu %p %u %p %u %p %u %u %u %u %p %p %p "
+                 "%llu %zu",
+                 mode, (int)ring, (const void *)d_codes, (const void *)d_offsets,
+                 (unsigned long long)base, (const void *)d_codes_b, (const void *)d_offsets_b,
+                 (unsigned long long)base_b, (const void *)d_pairs, (unsigned)count,
+                 (const void *)d_order, K, (const void *)d_Kq, sig, NL, tpw, wpp, (void *)next,
+                 (void *)d_dist, (void *)d_columns, (unsigned long long)grid, lds);
         kmark();
-        hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
-                           d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs,
-                           (uint32_t)count, d_order, K, d_Kq, sig, NL, tpw, wpp, next, d_dist,
-                           d_columns);
-        EJ_CHECK_LAUNCH();
+        run_captured(ctx, key, [&] {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
+            EJ_CHECK_LAUNCH();
+            hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
+                               d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs,
+                               (uint32_t)count, d_order, K, d_Kq, sig, NL, tpw, wpp, next,
+                               d_dist, d_columns);
+            EJ_CHECK_LAUNCH();
+        });
         kmark();
         return;
     }

@@ -396,3 +396,35 @@ def test_autotune_keeps_results(ej, ctx, oracle_lib):
     finally:
         for k, v in before.items():
             ctx.tune_set(k, v)
+
+
+def test_graph_replays_match_eager(ej, ctx, oracle_lib):
+    """Persistent verification captured into a HIP graph: the first join
+    captures, later joins of the same shape replay it, with eager joins and
+    synchronisations in between; every replay equals the oracle."""
+    import torch
+    col = sd.clusters(41, 40, lambda rr, b: 4, lambda rr: rr.integers(150, 600),
+                      lambda rr, LL: rr.poisson(10))
+    K, r, z, m, L = 50, 4, 6, 4, 48
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 4, L)
+    chars, offs = to_device(col)
+    old = ctx.tune_get("verify_mode")
+    try:
+        ctx.tune_set("verify_mode", 1)
+        for i in range(4):
+            _say(f"graph replay {i}")
+            res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
+            _assert_join_equal(res, ref)
+            eager = ctx.join(chars, offs, K, r, z, m, seed=4, L=L)
+            _assert_join_equal(eager, ref)
+            torch.cuda.synchronize()
+        # a different shape in between, then the first shape again
+        col2 = sd.clusters(42, 20, lambda rr, b: 3, lambda rr: rr.integers(100, 300),
+                           lambda rr, LL: rr.poisson(5))
+        ref2 = _oracle_join(oracle_lib, col2, 20, r, z, m, 4, L)
+        _assert_join_equal(ctx.join(col2.chars, col2.offsets, 20, r, z, m, seed=4, L=L,
+                                     flags=ej.FLAG_GRAPH), ref2)
+        _assert_join_equal(ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH),
+                           ref)
+    finally:
+        ctx.tune_set("verify_mode", old)
