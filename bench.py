@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched form with default knobs instead of the autotuner's")
+    ap.add_argument("--knobs", default="", metavar="name=value,..",
+                    help="batched form with these launch knobs instead of the autotuner's")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-length join (80,000 strings, K=400)")
     ap.add_argument("--no-serving", action="store_true",
@@ -330,7 +332,12 @@ def run_forms(ej, ctx, chars, offs, prm, args):
     ctx.tune_set("verify_mode", 0)
     res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, flags)
     plain = dict(res=res, ms=ms, stage=stage, knobs=ctx.knobs(), kernel="k_verify")
-    if args.no_autotune:
+    if args.knobs:
+        for kv in args.knobs.split(","):
+            k, v = kv.split("=")
+            ctx.tune_set(k.strip(), int(v))
+        tune_ms = None
+    elif args.no_autotune:
         ctx.tune_set("verify_mode", 1)
         tune_ms = None
     else:
