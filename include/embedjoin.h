@@ -136,7 +136,8 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *                           least 8 lanes and the alphabet is small
  *   "embed_lds_budget"      LDS bytes per wave of the walk kernel
  *   "radix_bits"            digit width of the radix sorts (4..11)
- *   "bucket_key_bits"       key bits sorted when bucketing (1..32)
+ *   "bucket_key_bits"       key bits sorted when bucketing (1..32; 0 =
+ *                           ceil(log2 n) + 6)
  * EJ_EINVAL for an unknown name or a value out of range. */
 ej_status ej_tune_set(ej_ctx *ctx, const char *name, uint32_t value);
 ej_status ej_tune_get(const ej_ctx *ctx, const char *name, uint32_t *value);

@@ -158,6 +158,9 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
     uint64_t tot = (uint64_t)T * n;
     if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
     if (key_bits == 0) key_bits = ctx->tune.bucket_key_bits;
+    // enough bits that different keys rarely share a group (the pair scan
+    // compares full keys, so a shared group costs time, never results)
+    if (key_bits == 0) key_bits = std::min(32u, bits_for(n) + 6);
     if (key_bits > 32) key_bits = 32;
     bk.d_ids = ws<uint32_t>(ctx, t + "_ids", tot);
     bk.d_gid = ws<uint32_t>(ctx, t + "_gid", tot);

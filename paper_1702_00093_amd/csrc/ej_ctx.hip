@@ -154,7 +154,7 @@ static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32
         {"verify_order", &Tuning::verify_order, 0, 1},
         {"embed_lds_budget", &Tuning::embed_lds_budget, 8192, 1u << 20},
         {"radix_bits", &Tuning::radix_bits, 4, 11},
-        {"bucket_key_bits", &Tuning::bucket_key_bits, 1, 32},
+        {"bucket_key_bits", &Tuning::bucket_key_bits, 0, 32},
     };
     if (!name) return nullptr;
     for (const Item &it : items)

@@ -113,31 +113,43 @@ __global__ void k_presence(const uint8_t *__restrict__ chars, uint64_t base, uin
     if (threadIdx.x < 8 && m[threadIdx.x]) atomicOr(&info->mask[threadIdx.x], m[threadIdx.x]);
 }
 
-// codes[k] = lut[chars[base + k]]
-__global__ void k_encode(const uint8_t *__restrict__ chars, uint64_t base, uint64_t total,
-                         const uint8_t *__restrict__ lut_g, uint8_t *__restrict__ codes) {
+// One pass over the characters: thread w maps characters w*CPD ..
+// w*CPD+CPD-1 through the alphabet table, stores their codes (as whole
+// dwords: CPD is a multiple of 4) and their packed word; words nwords ..
+// nwords+7 are the zero padding the walk may read past the end.
+template <int BW>
+__global__ void k_encode_pack(const uint8_t *__restrict__ chars, uint64_t base, uint64_t total,
+                              const uint8_t *__restrict__ lut_g, uint8_t *__restrict__ codes,
+                              uint64_t nwords, uint32_t *__restrict__ packed) {
+    constexpr int CPD = 32 / BW;
     __shared__ uint8_t lut[256];
     lut[threadIdx.x & 255] = lut_g[threadIdx.x & 255];
     __syncthreads();
-    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < total;
-         k += (uint64_t)gridDim.x * blockDim.x)
-        codes[k] = lut[chars[base + k]];
-}
-
-// packed[w] holds codes w*CPD .. w*CPD+CPD-1, BW bits each, first code in
-// the low bits; codes past the end are 0.
-template <int BW>
-__global__ void k_pack(const uint8_t *__restrict__ codes, uint64_t total, uint64_t nwords,
-                       uint32_t *__restrict__ packed) {
-    constexpr int CPD = 32 / BW;
-    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords;
+    const uint8_t *p = chars + base;
+    for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords + 8;
          w += (uint64_t)gridDim.x * blockDim.x) {
+        if (w >= nwords) {
+            packed[w] = 0;
+            continue;
+        }
+        const uint64_t k0 = w * CPD;
         uint32_t x = 0;
-        uint64_t k0 = w * CPD;
+        uint32_t cw[CPD / 4];
 #pragma unroll
-        for (int t = 0; t < CPD; t++)
-            if (k0 + t < total) x |= (uint32_t)codes[k0 + t] << (t * BW);
+        for (int q = 0; q < CPD / 4; q++) cw[q] = 0;
+#pragma unroll
+        for (int t = 0; t < CPD; t++) {
+            if (k0 + t < total) {
+                const uint32_t c = lut[p[k0 + t]];
+                x |= c << (t * BW);
+                cw[t >> 2] |= c << (8 * (t & 3));
+            }
+        }
         packed[w] = x;
+        uint32_t *cd = (uint32_t *)(codes + k0);
+#pragma unroll
+        for (int q = 0; q < CPD / 4; q++)
+            if (k0 + 4 * q < total) cd[q] = cw[q];
     }
 }
 
@@ -277,12 +289,14 @@ __global__ void __launch_bounds__(64)
             nd = need < slot_words ? (uint32_t)need : slot_words;
         }
         ps = live ? p0 : 0;
-        for (uint32_t q = 0; q < 64; q++) {
-            const uint32_t ndq = readlane_u32(nd, q);
-            if (ndq == 0) continue;
-            const uint64_t gqq = readlane_u64(gq, q);
-            uint32_t *dst = slots + q * stride;
-            for (uint32_t t = lane; t < ndq; t += 64) dst[t] = packed[gqq + t];
+        // every lane copies its own window: independent loads, eight in flight
+        for (uint32_t t0 = 0; t0 < slot_words; t0 += 8) {
+            uint32_t w[8];
+#pragma unroll
+            for (uint32_t i = 0; i < 8; i++) w[i] = (t0 + i < nd) ? packed[gq + t0 + i] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < 8; i++)
+                if (t0 + i < nd) myslot[t0 + i] = w[i];
         }
         __syncthreads();
 
@@ -336,20 +350,27 @@ __global__ void __launch_bounds__(64)
 
     // ---- two-level hash of the z signatures of this seed:
     //      key = sum_k u_k v_k mod 2^61-1, u_k = symbol + 1 <= 256.
-    //      lo/hi accumulate u*v_lo and u*v_hi exactly (no overflow for m <= 64).
+    //      v_k is split into four 16-bit limbs (wave-uniform, scalar); each
+    //      limb sum sum_k u_k * limb is exact in 32 bits for m <= 64
+    //      (64 * 257 * 2^16 < 2^31), one full-rate 24-bit multiply-add per
+    //      limb and sample; the limbs recombine once per key.
     if (!valid) return;
     for (uint32_t t = 0; t < z; t++) {
         const uint64_t *vt = v + ((size_t)l * z + t) * m;
-        uint64_t lo = 0, hi = 0;
+        uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
         for (uint32_t kk = 0; kk < m; kk++) {
             const uint32_t u = (uint32_t)sig[(t * m + kk) * 64 + lane] + 1u;
             const uint64_t vv = vt[kk];
-            lo += (uint64_t)u * (uint32_t)vv;
-            hi += (uint64_t)u * (uint32_t)(vv >> 32);
+            s0 += __umul24(u, (uint32_t)vv & 0xFFFFu);
+            s1 += __umul24(u, (uint32_t)(vv >> 16) & 0xFFFFu);
+            s2 += __umul24(u, (uint32_t)(vv >> 32) & 0xFFFFu);
+            s3 += __umul24(u, (uint32_t)(vv >> 48));
         }
-        // lo + hi*2^32 mod P, using 2^61 == 1 (mod P)
-        uint64_t x = lo + ((hi & ((1ull << 29) - 1ull)) << 32) + (hi >> 29);
-        uint64_t res = (x & P61) + (x >> 61);
+        // s0 + s1 2^16 + s2 2^32 + s3 2^48 < 2^80, reduced with 2^61 == 1 (mod P)
+        const unsigned __int128 x = (unsigned __int128)s0 + ((unsigned __int128)s1 << 16) +
+                                    ((unsigned __int128)s2 << 32) + ((unsigned __int128)s3 << 48);
+        uint64_t res = (uint64_t)(x & P61) + (uint64_t)(x >> 61);
+        res = (res & P61) + (res >> 61);
         if (res >= P61) res -= P61;
         keys[((size_t)l * z + t) * n + id] = res;
         if (sig_out) {
@@ -437,22 +458,19 @@ void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uin
     uint32_t cpd = 32 / pp.bw;
     uint64_t nwords = (pp.total + cpd - 1) / cpd;
     pp.d_packed = ws<uint32_t>(ctx, t + "_packed", nwords + 8);
-    EJ_HIP(hipMemsetAsync(pp.d_packed, 0, (nwords + 8) * sizeof(uint32_t), ctx->stream));
-    if (pp.total) {
-        hipLaunchKernelGGL(k_encode, dim3(grid_for(ctx, pp.total, 256)), dim3(256), 0, ctx->stream,
-                           d_chars, pp.base, pp.total, (const uint8_t *)d_lut, pp.d_codes);
-        EJ_CHECK_LAUNCH();
-        dim3 g(grid_for(ctx, nwords, 256));
+    {
+        dim3 g(grid_for(ctx, nwords + 8, 256));
+        auto launch = [&](auto kern) {
+            hipLaunchKernelGGL(kern, g, dim3(256), 0, ctx->stream, d_chars, pp.base, pp.total,
+                               (const uint8_t *)d_lut, pp.d_codes, nwords, pp.d_packed);
+            EJ_CHECK_LAUNCH();
+        };
         if (pp.bw == 2)
-            hipLaunchKernelGGL(k_pack<2>, g, dim3(256), 0, ctx->stream,
-                               (const uint8_t *)pp.d_codes, pp.total, nwords, pp.d_packed);
+            launch(k_encode_pack<2>);
         else if (pp.bw == 4)
-            hipLaunchKernelGGL(k_pack<4>, g, dim3(256), 0, ctx->stream,
-                               (const uint8_t *)pp.d_codes, pp.total, nwords, pp.d_packed);
+            launch(k_encode_pack<4>);
         else
-            hipLaunchKernelGGL(k_pack<8>, g, dim3(256), 0, ctx->stream,
-                               (const uint8_t *)pp.d_codes, pp.total, nwords, pp.d_packed);
-        EJ_CHECK_LAUNCH();
+            launch(k_encode_pack<8>);
     }
     // length order (stable: ties keep input order)
     pp.d_perm = nullptr;

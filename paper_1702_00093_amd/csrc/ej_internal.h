@@ -97,7 +97,7 @@ struct Tuning {
     uint32_t verify_ring = 1;                // match masks: 0 whole pattern, 1 auto, 2 ring if it fits
     uint32_t embed_lds_budget = 48 * 1024;   // LDS per wave of the walk kernel
     uint32_t radix_bits = 8;                 // digit width of the radix sorts
-    uint32_t bucket_key_bits = 32;           // key bits sorted when bucketing
+    uint32_t bucket_key_bits = 0;            // key bits sorted when bucketing, 0 = ceil(log2 n) + 6
 };
 }  // namespace ej
 

@@ -316,7 +316,8 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 0},
             {&Tuning::verify_order, {1, 0}, 1},
             {&Tuning::verify_ring, {1, 0}, -1},
-            {&Tuning::radix_bits, {6, 8, 11}, -1},
+            {&Tuning::radix_bits, {6, 7, 8, 11}, -1},
+            {&Tuning::bucket_key_bits, {0, 32}, -1},
         };
         for (const Knob &k : knobs) {
             if (k.only_mode >= 0 && ctx->tune.verify_mode != (uint32_t)k.only_mode) continue;

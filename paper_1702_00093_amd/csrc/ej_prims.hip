@@ -153,9 +153,11 @@ __global__ void __launch_bounds__(BLK) k_rs_hist(const K *__restrict__ keys, uin
         hist[((uint64_t)seg * NB + d) * tps + tile] = cnt[d];
 }
 
-// Stable scatter: element order inside a tile is round-major, then thread
-// order, so waves rank their lanes with a ballot-based match on the digit
-// and add the counts of lower waves and earlier rounds.
+// Stable scatter of one tile.  Element order inside a tile is round-major,
+// then thread order; waves rank their lanes with a ballot-based match on the
+// digit and add the counts of lower waves and earlier rounds.  The tile is
+// first placed in LDS in digit order, then written out in that order, so
+// that consecutive threads write consecutive addresses of a digit's run.
 template <typename K, bool HAS_VAL>
 __global__ void __launch_bounds__(BLK) k_rs_scatter(const K *__restrict__ kin,
                                                     const uint32_t *__restrict__ vin,
@@ -164,55 +166,104 @@ __global__ void __launch_bounds__(BLK) k_rs_scatter(const K *__restrict__ kin,
                                                     uint32_t tps, uint32_t shift, uint32_t dbits,
                                                     const uint32_t *__restrict__ hist) {
     extern __shared__ uint32_t sm[];
+    __shared__ uint32_t scan_tmp[NWAVE];
     const uint32_t NB = 1u << dbits, mask = NB - 1;
-    uint32_t *base_off = sm;           // [NB]
-    uint32_t *run = sm + NB;           // [NB]
-    uint32_t *wc = sm + 2 * NB;        // [NWAVE][NB] tagged wave counts
-    uint32_t seg = blockIdx.x / tps, tile = blockIdx.x % tps;
-    uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *base_off = sm;           // [NB] output position of the tile's digit-d run
+    uint32_t *lstart = sm + NB;        // [NB] start of digit d inside the tile
+    uint32_t *run = sm + 2 * NB;       // [NB]
+    uint32_t *wc = sm + 3 * NB;        // [NWAVE][NB] tagged wave counts
+    K *lkey = (K *)(sm + (3 + NWAVE) * NB);     // [TILE]
+    uint32_t *lval = (uint32_t *)(lkey + TILE);  // [TILE]
+    const uint32_t seg = blockIdx.x / tps, tile = blockIdx.x % tps;
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (uint32_t d = threadIdx.x; d < NB; d += BLK) {
         base_off[d] = hist[((uint64_t)seg * NB + d) * tps + tile];
+        lstart[d] = 0;
         run[d] = 0;
         for (int w = 0; w < NWAVE; w++) wc[w * NB + d] = 0;
     }
     __syncthreads();
-    uint64_t segbase = (uint64_t)seg * seglen;
-    uint32_t t0 = tile * TILE;
-    const uint64_t lt_mask = (1ULL << lane) - 1ULL;
+    const uint64_t segbase = (uint64_t)seg * seglen;
+    const uint32_t t0 = tile * TILE;
+    const uint32_t nvalid = seglen - t0 < (uint32_t)TILE ? seglen - t0 : (uint32_t)TILE;
+    // ---- load the tile, count its digits
+    K key[IPT];
+    uint32_t val[IPT], dg[IPT];
+#pragma unroll
     for (int rd = 0; rd < IPT; rd++) {
-        uint32_t e = t0 + rd * BLK + threadIdx.x;
-        bool valid = e < seglen;
-        K key = 0;
-        uint32_t val = 0, d = 0;
-        if (valid) {
-            key = kin[segbase + e];
-            if (HAS_VAL) val = vin[segbase + e];
-            d = (uint32_t)(key >> shift) & mask;
+        const uint32_t i = rd * BLK + threadIdx.x;
+        key[rd] = 0;
+        val[rd] = 0;
+        dg[rd] = 0;
+        if (i < nvalid) {
+            key[rd] = kin[segbase + t0 + i];
+            if (HAS_VAL) val[rd] = vin[segbase + t0 + i];
+            dg[rd] = (uint32_t)(key[rd] >> shift) & mask;
+            atomicAdd(&lstart[dg[rd]], 1u);
         }
+    }
+    __syncthreads();
+    // ---- exclusive scan of the digit counts (NB / BLK consecutive digits per thread)
+    {
+        const uint32_t per = (NB + BLK - 1) / BLK;
+        const uint32_t d0 = threadIdx.x * per;
+        uint32_t sum = 0;
+        for (uint32_t q = 0; q < per; q++)
+            if (d0 + q < NB) sum += lstart[d0 + q];
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(sum, scan_tmp, total);
+        __syncthreads();
+        for (uint32_t q = 0; q < per; q++)
+            if (d0 + q < NB) {
+                const uint32_t c = lstart[d0 + q];
+                lstart[d0 + q] = ex;
+                ex += c;
+            }
+    }
+    __syncthreads();
+    // ---- stable ranks -> digit-ordered tile in LDS
+    const uint64_t lt_mask = (1ULL << lane) - 1ULL;
+#pragma unroll
+    for (int rd = 0; rd < IPT; rd++) {
+        const bool valid = rd * BLK + threadIdx.x < nvalid;
+        const uint32_t d = dg[rd];
         uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
         for (uint32_t b = 0; b < dbits; b++) {
-            bool bit = (d >> b) & 1u;
-            uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bb = __builtin_amdgcn_ballot_w64(bit);
             peers &= bit ? bb : ~bb;
         }
-        uint64_t lower = peers & lt_mask;
-        uint32_t rank = (uint32_t)__popcll(lower);
-        uint32_t cnt = (uint32_t)__popcll(peers);
-        uint32_t tag = (uint32_t)(rd + 1) << 16;
+        const uint64_t lower = peers & lt_mask;
+        const uint32_t rank = (uint32_t)__popcll(lower);
+        const uint32_t cnt = (uint32_t)__popcll(peers);
+        const uint32_t tag = (uint32_t)(rd + 1) << 16;
         if (valid && lower == 0) wc[wave * NB + d] = tag | cnt;
         __syncthreads();
         if (valid) {
             uint32_t prefix = 0;
             for (uint32_t w = 0; w < wave; w++) {
-                uint32_t x = wc[w * NB + d];
+                const uint32_t x = wc[w * NB + d];
                 if ((x & 0xFFFF0000u) == tag) prefix += x & 0xFFFFu;
             }
-            uint32_t pos = base_off[d] + run[d] + prefix + rank;
-            kout[pos] = key;
-            if (HAS_VAL) vout[pos] = val;
+            const uint32_t lpos = lstart[d] + run[d] + prefix + rank;
+            lkey[lpos] = key[rd];
+            if (HAS_VAL) lval[lpos] = val[rd];
         }
         __syncthreads();
         if (valid && lower == 0) atomicAdd(&run[d], cnt);
+    }
+    __syncthreads();
+    // ---- write out in digit order
+#pragma unroll
+    for (int rd = 0; rd < IPT; rd++) {
+        const uint32_t i = rd * BLK + threadIdx.x;
+        if (i < nvalid) {
+            const K k = lkey[i];
+            const uint32_t d = (uint32_t)(k >> shift) & mask;
+            const uint32_t pos = base_off[d] + (i - lstart[d]);
+            kout[pos] = k;
+            if (HAS_VAL) vout[pos] = lval[i];
+        }
     }
 }
 
@@ -221,9 +272,25 @@ void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout
                      uint32_t seglen, uint32_t key_bits, uint32_t dbits) {
     uint64_t n = (uint64_t)nseg * seglen;
     if (n == 0) return;
+    // widest digit whose staged scatter fits the LDS of one workgroup
+    uint32_t dmax = 11;
+    while (dmax > 4 && (3 + NWAVE) * 4 * ((size_t)1 << dmax) + (size_t)TILE * (sizeof(K) + 4) >
+                           (size_t)ctx->lds_max)
+        dmax--;
     if (dbits < 4) dbits = 4;
-    if (dbits > 11) dbits = 11;
+    if (dbits > dmax) dbits = dmax;
     uint32_t passes = (key_bits + dbits - 1) / dbits;
+    // an odd number of passes ends in kout without a copy: take one pass
+    // fewer with wider digits when they stay within dmax bits, else one more
+    if (passes > 0 && passes % 2 == 0) {
+        if ((key_bits + passes - 2) / (passes - 1) <= dmax)
+            passes -= 1;
+        else
+            passes += 1;
+    }
+    // bits split as evenly as possible: the first key_bits % passes passes
+    // take one bit more
+    if (passes > 0) dbits = (key_bits + passes - 1) / passes;
     if (passes == 0) {
         EJ_HIP(hipMemcpyAsync(kout, kin, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
         if (HAS_VAL)
@@ -231,31 +298,24 @@ void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout
                                   ctx->stream));
         return;
     }
-    // with an odd number of passes the first pass writes kout; with an even
-    // number it writes kin's partner so that the last pass lands in kout
+    // passes alternate kin -> kout -> kin ...; with an odd count the last
+    // one writes kout
     uint32_t tps = ceil_div(seglen, TILE);
     uint32_t NB = 1u << dbits;
     uint64_t hn = (uint64_t)nseg * NB * tps;
     uint32_t *hist = ws<uint32_t>(ctx, "rs_hist", hn);
     K *a = kin, *b = kout;
     uint32_t *va = vin, *vb = vout;
-    if (passes % 2 == 0) {
-        // even: pass 0 kin->kout, 1 kout->kin, ... ends in kin; copy once up
-        // front instead so the final pass writes kout
-        EJ_HIP(hipMemcpyAsync(kout, kin, n * sizeof(K), hipMemcpyDeviceToDevice, ctx->stream));
-        if (HAS_VAL)
-            EJ_HIP(hipMemcpyAsync(vout, vin, n * sizeof(uint32_t), hipMemcpyDeviceToDevice,
-                                  ctx->stream));
-        a = kout;
-        b = kin;
-        va = vout;
-        vb = vin;
-    }
     size_t hist_lds = NB * sizeof(uint32_t);
-    size_t scat_lds = (2 + NWAVE) * NB * sizeof(uint32_t);
+    size_t scat_lds = (3 + NWAVE) * NB * sizeof(uint32_t) + (size_t)TILE * (sizeof(K) + 4);
+    if (scat_lds > (size_t)ctx->lds_max) fail(EJ_EUNSUPPORTED, "radix sort: digit too wide for LDS");
+    if (scat_lds > 65536)
+        EJ_HIP(hipFuncSetAttribute((const void *)k_rs_scatter<K, HAS_VAL>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)scat_lds));
+    const uint32_t base_bits = key_bits / passes, extra = key_bits % passes;
+    uint32_t shift = 0;
     for (uint32_t p = 0; p < passes; p++) {
-        uint32_t shift = p * dbits;
-        uint32_t db = (key_bits - shift < dbits) ? key_bits - shift : dbits;
+        const uint32_t db = base_bits + (p < extra ? 1u : 0u);
         hipLaunchKernelGGL(k_rs_hist<K>, dim3(nseg * tps), dim3(BLK), hist_lds, ctx->stream,
                            (const K *)a, seglen, tps, shift, db, hist);
         EJ_CHECK_LAUNCH();
@@ -265,6 +325,7 @@ void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout
                            ctx->stream, (const K *)a, (const uint32_t *)va, b, vb, seglen, tps,
                            shift, db, (const uint32_t *)hist);
         EJ_CHECK_LAUNCH();
+        shift += db;
         K *t = a;
         a = b;
         b = t;
