@@ -115,8 +115,9 @@ __global__ void k_presence(const uint8_t *__restrict__ chars, uint64_t base, uin
 
 // One pass over the characters: thread w maps characters w*CPD ..
 // w*CPD+CPD-1 through the alphabet table, stores their codes (as whole
-// dwords: CPD is a multiple of 4) and their packed word; words nwords ..
-// nwords+7 are the zero padding the walk may read past the end.
+// dwords: CPD is a multiple of 4; the last dword's bytes past the end are 0)
+// and their packed word; threads nwords .. nwords+7 write the zero padding:
+// 8 packed words, which the walk may read past the end, and 64 code bytes.
 template <int BW>
 __global__ void k_encode_pack(const uint8_t *__restrict__ chars, uint64_t base, uint64_t total,
                               const uint8_t *__restrict__ lut_g, uint8_t *__restrict__ codes,
@@ -129,7 +130,13 @@ __global__ void k_encode_pack(const uint8_t *__restrict__ chars, uint64_t base, 
     for (uint64_t w = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; w < nwords + 8;
          w += (uint64_t)gridDim.x * blockDim.x) {
         if (w >= nwords) {
+            // zero padding: 8 packed words, and the 64 code bytes after the
+            // text that the verification's text window may read
             packed[w] = 0;
+            const uint64_t pad0 = ((total + 3) & ~3ull) + 8 * (w - nwords);
+            uint32_t *cp = (uint32_t *)(codes + pad0);
+            cp[0] = 0;
+            cp[1] = 0;
             continue;
         }
         const uint64_t k0 = w * CPD;
@@ -454,7 +461,7 @@ void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uin
     // encodings
     uint8_t *d_lut = ws<uint8_t>(ctx, t + "_lut", 256);
     EJ_HIP(hipMemcpyAsync(d_lut, pp.lut, 256, hipMemcpyHostToDevice, ctx->stream));
-    pp.d_codes = ws<uint8_t>(ctx, t + "_codes", pp.total + 64);
+    pp.d_codes = ws<uint8_t>(ctx, t + "_codes", ((pp.total + 3) & ~3ull) + 64);
     uint32_t cpd = 32 / pp.bw;
     uint64_t nwords = (pp.total + cpd - 1) / cpd;
     pp.d_packed = ws<uint32_t>(ctx, t + "_packed", nwords + 8);

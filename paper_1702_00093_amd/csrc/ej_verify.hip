@@ -144,8 +144,11 @@ __device__ inline void myers_block(const uint8_t *peq, uint32_t stride4, uint32_
 }
 
 // The 32 text symbols of columns jb+1 .. jb+32 (bytes y[jb .. jb+31]) as 8
-// little-endian dwords; symbols at or past position nn read as 0.  Reads
-// stay within y[0 .. nn+35] (the code arrays carry 64 bytes of padding).
+// little-endian dwords, or zeros once jb >= nn.  Bytes past position nn are
+// the next strings' codes or the array's zeroed padding -- valid symbols
+// either way; the columns they feed are past the end of the text and never
+// counted.  Reads stay within y[0 .. nn+35] (the code arrays carry 64 bytes
+// of padding).
 __device__ inline void load_text_block(const uint8_t *y, uint32_t nn, uint32_t jb, uint32_t tw[8]) {
 #pragma unroll
     for (int q = 0; q < 8; q++) tw[q] = 0;
@@ -158,21 +161,6 @@ __device__ inline void load_text_block(const uint8_t *y, uint32_t nn, uint32_t j
     for (int q = 0; q < 9; q++) w[q] = base[q];
 #pragma unroll
     for (int q = 0; q < 8; q++) tw[q] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh);
-    const uint32_t valid = nn - jb;  // > 0
-    if (valid < 32) {
-#pragma unroll
-        for (uint32_t q = 0; q < 8; q++) {
-            const uint32_t b0 = 4 * q;
-            uint32_t keep;
-            if (valid >= b0 + 4)
-                keep = 0xFFFFFFFFu;
-            else if (valid <= b0)
-                keep = 0u;
-            else
-                keep = (1u << (8 * (valid - b0))) - 1u;
-            tw[q] &= keep;
-        }
-    }
 }
 
 struct PairView {
