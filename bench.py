@@ -464,7 +464,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "K": prm["K"], "r": prm["r"], "z": prm["z"], "m": prm["m"],
                    "L": res.L, "params": "stated" if prm == stated else "recall-calibrated",
-                   "form": "batched (persistent graph-captured verification, autotuned knobs)",
+                   "form": ("batched: autotuned knobs, verification "
+                            + ("persistent, replayed from a captured HIP graph"
+                               if head["knobs"]["verify_mode"] == 1 else "two-pass")),
                    "candidates": cand, "raw_candidates": res.n_raw,
                    "output_pairs": int(len(res.pairs)), "join_sec": round(ms / 1000.0, 5),
                    "stage_ms": {k: round(v, 3) for k, v in stage.items()},

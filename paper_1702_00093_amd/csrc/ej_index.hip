@@ -32,6 +32,7 @@ struct ej_index {
     uint64_t *d_key_s = nullptr;   // [T][n] full keys in sorted order
     uint32_t *d_len_s = nullptr;   // [T][n] lengths in sorted order
     uint32_t *d_ids = nullptr;     // [T][n] positions in sorted order
+    RowMasks masks;                // match masks of the index strings (verification)
     Rand rd;                       // random streams (owned copies)
     std::vector<void *> owned;
 };
@@ -271,6 +272,13 @@ ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *of
                                (const uint32_t *)pp.d_len, n, tot, ix->d_dk, ix->d_key_s,
                                ix->d_len_s);
         EJ_CHECK_LAUNCH();
+        // match masks of the index strings, kept for every query batch
+        {
+            uint32_t *mw = own_copy<uint32_t>(ix, nullptr, mask_words_bound(pp.total, n, pp.sigma));
+            uint64_t *mo = own_copy<uint64_t>(ix, nullptr, (uint64_t)n + 1);
+            build_masks(ctx, pp.d_codes, d_off, pp.base, n, pp.total, pp.sigma, ix->masks, "ixm",
+                        mw, mo);
+        }
         // the owned offsets must be relative to the owned codes: base 0
         if (pp.base) {
             std::vector<uint64_t> h(n + 1);
@@ -398,8 +406,10 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
         int32_t *odist = nullptr;
         if (cnt) {
             int32_t *dist = ws<int32_t>(ctx, "q_dist", cnt);
-            verify(ctx, ix->d_codes, ix->d_offsets, 0, ix->sigma, ix->maxlen, pairs, cnt, 0, pk,
-                   dist, pq.d_codes, dqo, 0, pq.maxlen);
+            RowMasks qmasks;
+            build_masks(ctx, pq.d_codes, dqo, 0, nq, pq.total, ix->sigma, qmasks, "qm");
+            verify(ctx, ix->d_codes, ix->d_offsets, 0, ix->sigma, ix->maxlen, ix->masks, pairs,
+                   cnt, 0, pk, dist, pq.d_codes, dqo, 0, pq.maxlen, &qmasks);
             uint32_t *flags = ws<uint32_t>(ctx, "q_oflags", cnt);
             uint32_t *pos = ws<uint32_t>(ctx, "q_opos", cnt);
             uint64_t *d_no = ws<uint64_t>(ctx, "q_nout", 1);

@@ -221,12 +221,30 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                     uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag,
                     uint32_t **d_order_out = nullptr);
 
+// Match masks of a string set, one bit array per (string, symbol): bit b of
+// word w of string s and symbol c is set iff x_s[32w + b] == c, for
+// W_s = ceil(|x_s| / 32) words; string s's arrays start at word off[s].
+struct RowMasks {
+    const uint32_t *words = nullptr;
+    const uint64_t *off = nullptr;
+};
+// Builds the masks of n strings (codes laid out like the characters, offsets
+// relative to `base`) into workspace buffers named after `tag`, or into
+// `own_words`/`own_off` when given (capacity mask_words_bound / n).
+void build_masks(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
+                 uint32_t n, uint64_t total, uint32_t sigma, RowMasks &rm, const char *tag,
+                 uint32_t *own_words = nullptr, uint64_t *own_off = nullptr);
+inline uint64_t mask_words_bound(uint64_t total, uint32_t n, uint32_t sigma) {
+    return (uint64_t)(sigma ? sigma : 1) * (total / 32 + n + 1);
+}
+
 // Threshold edit distance of `count` pairs (codes a << 32 | b) over the
-// symbol codes of a string set.
+// symbol codes of a string set (a) and a second set (b, or a again).
 void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
-            uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
-            const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b = nullptr,
-            const uint64_t *d_offsets_b = nullptr, uint64_t base_b = 0, uint32_t maxlen_b = 0,
+            uint32_t sigma, uint32_t maxlen, const RowMasks &masks, const uint64_t *d_pairs,
+            uint64_t count, uint32_t K, const uint32_t *d_Kq, int32_t *d_dist,
+            const uint8_t *d_codes_b = nullptr, const uint64_t *d_offsets_b = nullptr,
+            uint64_t base_b = 0, uint32_t maxlen_b = 0, const RowMasks *masks_b = nullptr,
             unsigned long long *d_columns = nullptr, const uint32_t *d_order = nullptr);
 
 uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported

@@ -172,8 +172,11 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     ctx->timers.on = tm.on;
     ctx->timers.nkv = 0;
     ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode == 1;
-    verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, pairs, cnt, p.K, nullptr,
-           dist, nullptr, nullptr, 0, 0, d_cols, order);
+    RowMasks masks;
+    if (cnt)
+        build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
+    verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, pairs, cnt, p.K,
+           nullptr, dist, nullptr, nullptr, 0, 0, nullptr, d_cols, order);
     ctx->timers.on = false;
     ctx->graph_on = false;
     tm.mark();  // 5
@@ -489,8 +492,11 @@ ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offse
             read_back(ctx, d_bad, 4, &bad);
             if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
         }
-        verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, d_pairs, count, K, d_Kq,
-               d_dist);
+        RowMasks masks;
+        if (count)
+            build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "v");
+        verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, d_pairs, count, K,
+               d_Kq, d_dist);
         sync(ctx);
     });
 }

@@ -163,39 +163,55 @@ __device__ inline void load_text_block(const uint8_t *y, uint32_t nn, uint32_t j
     for (int q = 0; q < 8; q++) tw[q] = __builtin_amdgcn_alignbit(w[q + 1], w[q], sh);
 }
 
+// One string set as the kernels see it: symbol codes (offsets relative to
+// base) and the precomputed match masks of every string.
+struct StrSet {
+    const uint8_t *codes;
+    const uint64_t *off;
+    uint64_t base;
+    const uint32_t *mw;    // mask words
+    const uint64_t *moff;  // [n] first mask word of each string
+};
+
 struct PairView {
     const uint8_t *xp, *yp;
+    const uint32_t *mw;            // pattern's masks: symbol c at mw + c * W
+    uint32_t W;                    // mask words per symbol of the pattern
     uint32_t m, nn, Kp, dstar, O;  // O = -lo = floor((Kp - d*)/2)
     bool skip;
 };
 
-__device__ inline PairView view_pair(const uint8_t *codes_a, const uint64_t *off_a, uint64_t base_a,
-                                     const uint8_t *codes_b, const uint64_t *off_b, uint64_t base_b,
-                                     const uint64_t *pairs, const uint32_t *Kq, uint32_t K,
-                                     uint64_t pidx, bool act) {
+__device__ inline PairView view_pair(const StrSet &A, const StrSet &B, const uint64_t *pairs,
+                                     const uint32_t *Kq, uint32_t K, uint64_t pidx, bool act) {
     PairView v;
-    v.xp = codes_a;
-    v.yp = codes_a;
+    v.xp = A.codes;
+    v.yp = A.codes;
+    v.mw = A.mw;
+    v.W = 0;
     v.m = 0;
     v.nn = 0;
     v.Kp = K;
     if (act) {
         uint64_t code = pairs[pidx];
         uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
-        uint64_t oa = off_a[a], ob = off_b[b];
-        uint32_t la = (uint32_t)(off_a[a + 1] - oa), lb = (uint32_t)(off_b[b + 1] - ob);
-        const uint8_t *pa = codes_a + (oa - base_a), *pb = codes_b + (ob - base_b);
+        uint64_t oa = A.off[a], ob = B.off[b];
+        uint32_t la = (uint32_t)(A.off[a + 1] - oa), lb = (uint32_t)(B.off[b + 1] - ob);
+        const uint8_t *pa = A.codes + (oa - A.base), *pb = B.codes + (ob - B.base);
         if (Kq) v.Kp = Kq[pidx];
         if (la >= lb) {
             v.xp = pa; v.m = la; v.yp = pb; v.nn = lb;
+            v.mw = A.mw + A.moff[a];
         } else {
             v.xp = pb; v.m = lb; v.yp = pa; v.nn = la;
+            v.mw = B.mw + B.moff[b];
         }
+        v.W = (v.m + 31) / 32;
     }
     v.skip = !act || v.m - v.nn > v.Kp;
     if (v.skip) {
         v.m = 0;
         v.nn = 0;
+        v.W = 0;
     }
     // a skipped pair keeps d* = 0 so that one lane of its tile owns the
     // (constant) result K_p + 1
@@ -204,46 +220,38 @@ __device__ inline PairView view_pair(const uint8_t *codes_a, const uint64_t *off
     return v;
 }
 
-// Writes the match masks of words w0 .. w0+nw-1 for every tile whose
-// leader lane (lane t*NL) is set in `leaders`, 64 pattern rows per ballot:
-// the whole wave reads the rows of one tile's pattern at a time.
+// Word `wabs` of the band's match mask for symbol c: bit b is pattern row
+// 32*wabs + b - O (1-based), i.e. pattern index p = 32*wabs + b - O - 1,
+// funnel-shifted out of the pattern's precomputed masks; indexes below 0 or
+// past the pattern read as zero.
+__device__ inline uint32_t mask_word(const PairView &v, uint32_t c, uint32_t wabs) {
+    const int32_t p0 = 32 * (int32_t)wabs - (int32_t)v.O - 1;
+    const int32_t q = p0 >> 5;  // floor(p0 / 32)
+    const uint32_t sh = (uint32_t)p0 & 31u;
+    const uint32_t *mc = v.mw + (size_t)c * v.W;
+    const uint32_t lo = (uint32_t)q < v.W ? mc[q] : 0u;
+    const uint32_t hi = (uint32_t)(q + 1) < v.W ? mc[q + 1] : 0u;
+    return __builtin_amdgcn_alignbit(hi, lo, sh);
+}
+
+// Match-mask words w0 .. w0+nw-1 of every symbol into one tile's LDS region
+// `pq`, shared among the tile's NL lanes (lane l of the tile).
 template <bool RING>
-__device__ inline void fill_masks(uint32_t *lds, uint64_t leaders, const PairView &v, uint32_t NL,
-                                  uint32_t tile_words, uint32_t stride, uint32_t RW, uint32_t wpp,
-                                  uint32_t sigma, uint32_t w0, uint32_t nw, uint32_t lane) {
-    while (leaders) {
-        const uint32_t b = (uint32_t)__builtin_ctzll(leaders);
-        leaders &= leaders - 1;
-        const uint32_t t = b / NL;
-        const uint32_t mt = readlane_u32(v.m, b);
-        const uint32_t Ot = readlane_u32(v.O, b);
-        const uint8_t *xt =
-            (const uint8_t *)(uintptr_t)readlane_u64((uint64_t)(uintptr_t)v.xp, b);
-        uint32_t *pq = lds + t * tile_words;
-        for (uint32_t q = 0; 2 * q < nw; q++) {
-            const int64_t row = (int64_t)32 * w0 + 64 * q + lane - Ot;
-            uint32_t c = 0xFFFFFFFFu;
-            if (row >= 1 && row <= (int64_t)mt) c = xt[row - 1];
-            const uint32_t wa = w0 + 2 * q, wb = wa + 1;
-            for (uint32_t ch = 0; ch < sigma; ch++) {
-                const uint64_t msk = __builtin_amdgcn_ballot_w64(c == ch);
-                if (RING) {
-                    const uint32_t sa = wa & (RW - 1), sb = wb & (RW - 1);
-                    if (lane == 0) {
-                        pq[ch * stride + sa] = (uint32_t)msk;
-                        pq[ch * stride + sa + RW] = (uint32_t)msk;
-                    }
-                    if (lane == 1) {
-                        pq[ch * stride + sb] = (uint32_t)(msk >> 32);
-                        pq[ch * stride + sb + RW] = (uint32_t)(msk >> 32);
-                    }
-                } else {
-                    if (lane == 0) pq[ch * stride + wa] = (uint32_t)msk;
-                    if (lane == 1 && wb < wpp) pq[ch * stride + wb] = (uint32_t)(msk >> 32);
-                }
+__device__ inline void fill_tile(uint32_t *pq, const PairView &v, uint32_t l, uint32_t NL,
+                                 uint32_t sigma, uint32_t stride, uint32_t RW, uint32_t wpp,
+                                 uint32_t w0, uint32_t nw) {
+    for (uint32_t c = 0; c < sigma; c++)
+        for (uint32_t w = l; w < nw; w += NL) {
+            const uint32_t word = mask_word(v, c, w0 + w);
+            if (RING) {
+                const uint32_t sl = (w0 + w) & (RW - 1);
+                pq[c * stride + sl] = word;
+                pq[c * stride + sl + RW] = word;
+            } else if (w0 + w < wpp) {
+                pq[c * stride + w0 + w] = word;
             }
         }
-    }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
 // Match masks of a pair live in LDS in one of two layouts:
@@ -263,10 +271,7 @@ __device__ inline void fill_masks(uint32_t *lds, uint64_t leaders, const PairVie
 // their state and runs them to the end.
 template <int MODE, bool RING>
 __global__ void __launch_bounds__(64)
-    k_verify(const uint8_t *__restrict__ codes_a, const uint64_t *__restrict__ off_a,
-             uint64_t base_a, const uint8_t *__restrict__ codes_b,
-             const uint64_t *__restrict__ off_b, uint64_t base_b,
-             const uint64_t *__restrict__ pairs, uint64_t count, const uint32_t *__restrict__ list,
+    k_verify(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count, const uint32_t *__restrict__ list,
              uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL_arg,
              uint32_t tpw, uint32_t wpp, uint32_t jbeg, uint32_t jlim, int resume,
              uint32_t *__restrict__ state, uint32_t *__restrict__ aux,
@@ -279,8 +284,6 @@ __global__ void __launch_bounds__(64)
     const uint32_t RW = wpp;                          // ring: words per ring
     const uint32_t stride = RING ? 2 * RW : wpp;      // words per symbol
     const uint32_t tile_words = sigma * stride;
-    const uint32_t R = (32 + NL - 1) / NL;            // ring: rows per lane per word
-    const uint32_t nlmask = NL >= 32 ? 0xFFFFFFFFu : ((1u << NL) - 1u);
     uint64_t last = 0;  // top lane of every pair, and lanes outside pairs
     for (uint32_t q = 0; q < 64; q++)
         if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
@@ -293,17 +296,13 @@ __global__ void __launch_bounds__(64)
         const uint64_t k = g * tpw + tile;  // index into the (listed) pairs
         const bool act = in_tile && k < count;
         const uint64_t pidx = act ? (list ? (uint64_t)list[k] : k) : 0;
-        const PairView v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K,
-                                     pidx, act);
+        const PairView v = view_pair(A, B, pairs, Kq, K, pidx, act);
         __syncthreads();
         // ---- match masks of the words the first block needs (ring) or of
-        //      the whole pattern (full)
-        {
-            uint64_t leaders = 0;
-            for (uint32_t t = 0; t < tpw; t++) leaders |= 1ull << (t * NL);
-            fill_masks<RING>(lds, leaders, v, NL, tile_words, stride, RW, wpp, sigma,
-                             RING ? (jbeg >> 5) : 0u, RING ? NL + 1 : wpp, lane);
-        }
+        //      the whole pattern (full), every tile its own
+        if (in_tile)
+            fill_tile<RING>(pq_mine, v, l, NL, sigma, stride, RW, wpp, RING ? (jbeg >> 5) : 0u,
+                            RING ? NL + 1 : wpp);
         __syncthreads();
 
         // ---- state at column jbeg
@@ -335,19 +334,7 @@ __global__ void __launch_bounds__(64)
         load_text_block(v.yp, v.nn, jbeg, tw);
         for (uint32_t jb = jbeg; jb < jend; jb += 32) {
             load_text_block(v.yp, v.nn, jb + 32, tn);
-            // ring: pattern rows of the word that enters the band next
-            uint32_t rc[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-            const uint32_t wn = (jb >> 5) + NL + 1;
-            if (RING && in_tile) {
-#pragma unroll
-                for (uint32_t q = 0; q < 4; q++) {
-                    // pattern row 32*wn + bq - O (1-based), in 32-bit arithmetic
-                    const uint32_t bq = q * NL + l;
-                    const uint32_t r1 = 32 * wn + bq;
-                    if (q < R && bq < 32 && r1 > v.O && r1 - v.O <= v.m)
-                        rc[q] = v.xp[r1 - v.O - 1];
-                }
-            }
+            const uint32_t wn = (jb >> 5) + NL + 1;  // ring: the word entering next
             const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
             // columns past the end of a pair's text do not count; a block
             // where no text ends takes the masked-popcount path
@@ -363,21 +350,14 @@ __global__ void __launch_bounds__(64)
                 const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
                 if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
             }
-            if (RING) {
-                // the entering word, for every symbol; the slot it replaces
-                // held word wn - RW, which no lane reads any more
+            if (RING && in_tile) {
+                // the entering word, lane c of the tile for symbol c; the slot
+                // it replaces held word wn - RW, which no lane reads any more
                 const uint32_t sl = wn & (RW - 1);
-                for (uint32_t ch = 0; ch < sigma; ch++) {
-                    uint32_t word = 0;
-                    for (uint32_t q = 0; q < R; q++) {
-                        const uint64_t B = __builtin_amdgcn_ballot_w64(rc[q] == ch);
-                        const uint32_t part = (uint32_t)(B >> (tile * NL)) & nlmask;
-                        word |= q * NL < 32 ? (part << (q * NL)) : 0u;
-                    }
-                    if (in_tile && l == 0) {
-                        pq_mine[ch * stride + sl] = word;
-                        pq_mine[ch * stride + sl + RW] = word;
-                    }
+                for (uint32_t c = l; c < sigma; c += NL) {
+                    const uint32_t word = mask_word(v, c, wn);
+                    pq_mine[c * stride + sl] = word;
+                    pq_mine[c * stride + sl + RW] = word;
                 }
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
             }
@@ -427,10 +407,7 @@ __global__ void __launch_bounds__(64)
 // to dist[pair].
 template <int MODE, bool RING>
 __global__ void __launch_bounds__(64)
-    k_verify_queue(const uint8_t *__restrict__ codes_a, const uint64_t *__restrict__ off_a,
-                   uint64_t base_a, const uint8_t *__restrict__ codes_b,
-                   const uint64_t *__restrict__ off_b, uint64_t base_b,
-                   const uint64_t *__restrict__ pairs, uint32_t count,
+    k_verify_queue(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
                    const uint32_t *__restrict__ order, uint32_t K,
                    const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL_arg, uint32_t tpw,
                    uint32_t wpp, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
@@ -443,8 +420,6 @@ __global__ void __launch_bounds__(64)
     const uint32_t RW = wpp;
     const uint32_t stride = RING ? 2 * RW : wpp;
     const uint32_t tile_words = sigma * stride;
-    const uint32_t R = (32 + NL - 1) / NL;
-    const uint32_t nlmask = NL >= 32 ? 0xFFFFFFFFu : ((1u << NL) - 1u);
     uint64_t last = 0;
     for (uint32_t q = 0; q < 64; q++)
         if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
@@ -453,7 +428,7 @@ __global__ void __launch_bounds__(64)
     uint32_t *pq_mine = lds + (in_tile ? tile : 0) * tile_words;
     const uint8_t *peq8 = (const uint8_t *)pq_mine;
 
-    PairView v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K, 0, false);
+    PairView v = view_pair(A, B, pairs, Kq, K, 0, false);
     uint32_t pidx = 0;
     bool active = in_tile;  // may still hold or take pairs
     bool need = in_tile;    // holds no pair
@@ -478,10 +453,10 @@ __global__ void __launch_bounds__(64)
                     owner = false;
                     v.m = 0;
                     v.nn = 0;
+                    v.W = 0;
                 } else {
                     pidx = order ? order[got] : got;
-                    v = view_pair(codes_a, off_a, base_a, codes_b, off_b, base_b, pairs, Kq, K,
-                                  pidx, true);
+                    v = view_pair(A, B, pairs, Kq, K, pidx, true);
                     kstar = v.O + v.dstar;
                     owner = (kstar >> 5) == l;
                     kbit = kstar & 31;
@@ -504,12 +479,10 @@ __global__ void __launch_bounds__(64)
                     }
                 }
             }
-            const uint64_t fill = __builtin_amdgcn_ballot_w64(fresh && l == 0);
-            if (fill) {
-                fill_masks<RING>(lds, fill, v, NL, tile_words, stride, RW, wpp, sigma, 0u,
-                                 RING ? NL + 1 : wpp, lane);
-                __syncthreads();
-                if (fresh) load_text_block(v.yp, v.nn, 0, tw);
+            if (fresh) {
+                fill_tile<RING>(pq_mine, v, l, NL, sigma, stride, RW, wpp, 0u,
+                                RING ? NL + 1 : wpp);
+                load_text_block(v.yp, v.nn, 0, tw);
             }
         }
         if (__builtin_amdgcn_ballot_w64(active) == 0) break;
@@ -517,18 +490,7 @@ __global__ void __launch_bounds__(64)
         // ---- one 32-column block of every tile that holds a pair
         uint32_t tn[8];
         load_text_block(v.yp, v.nn, jb + 32, tn);
-        uint32_t rc[4] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-        const uint32_t wn = (jb >> 5) + NL + 1;
-        if (RING && active) {
-#pragma unroll
-            for (uint32_t q = 0; q < 4; q++) {
-                // pattern row 32*wn + bq - O (1-based), in 32-bit arithmetic:
-                // 32*wn + bq stays below |x| + 32*NL + 64
-                const uint32_t bq = q * NL + l;
-                const uint32_t r1 = 32 * wn + bq;
-                if (q < R && bq < 32 && r1 > v.O && r1 - v.O <= v.m) rc[q] = v.xp[r1 - v.O - 1];
-            }
-        }
+        const uint32_t wn = (jb >> 5) + NL + 1;  // ring: the word entering next
         const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
         const bool ends_here = active && v.nn > jb && v.nn < jb + 32;
         if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
@@ -544,19 +506,13 @@ __global__ void __launch_bounds__(64)
             const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
             if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
         }
-        if (RING) {
+        if (RING && active) {
+            // the entering word, lane c of the tile for symbol c
             const uint32_t sl = wn & (RW - 1);
-            for (uint32_t ch = 0; ch < sigma; ch++) {
-                uint32_t word = 0;
-                for (uint32_t q = 0; q < R; q++) {
-                    const uint64_t B = __builtin_amdgcn_ballot_w64(rc[q] == ch);
-                    const uint32_t part = (uint32_t)(B >> (tile * NL)) & nlmask;
-                    word |= q * NL < 32 ? (part << (q * NL)) : 0u;
-                }
-                if (active && l == 0) {
-                    pq_mine[ch * stride + sl] = word;
-                    pq_mine[ch * stride + sl + RW] = word;
-                }
+            for (uint32_t c = l; c < sigma; c += NL) {
+                const uint32_t word = mask_word(v, c, wn);
+                pq_mine[c * stride + sl] = word;
+                pq_mine[c * stride + sl + RW] = word;
             }
             __atomic_signal_fence(__ATOMIC_SEQ_CST);
         }
@@ -578,6 +534,59 @@ __global__ void __launch_bounds__(64)
         if (tile_fin) {
             need = true;
             owner = false;
+        }
+    }
+}
+
+// Mask words of every string: sigma * ceil(len / 32).
+__global__ void k_mask_sizes(const uint64_t *__restrict__ off, uint32_t n, uint32_t sigma,
+                             uint64_t *__restrict__ sz) {
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        const uint64_t len = off[s + 1] - off[s];
+        sz[s] = (uint64_t)sigma * ((len + 31) / 32);
+    }
+}
+
+// Match masks, one wave per string, lane w building word w of every symbol:
+// the 32 codes of the word are compared with the symbol four at a time (a
+// byte is zero after the xor iff it matches).
+__global__ void k_build_masks(const uint8_t *__restrict__ codes, const uint64_t *__restrict__ off,
+                              uint64_t base, uint32_t n, uint32_t sigma,
+                              const uint64_t *__restrict__ moff, uint32_t *__restrict__ words) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t wave = (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t s = wave; s < n; s += nwaves) {
+        const uint64_t o = off[s] - base;
+        const uint32_t len = (uint32_t)(off[s + 1] - off[s]);
+        const uint32_t W = (len + 31) / 32;
+        uint32_t *dst = words + moff[s];
+        for (uint32_t w = lane; w < W; w += 64) {
+            // codes x[32w .. 32w+31]: reads stay within the array's 64-byte padding
+            const uintptr_t a = (uintptr_t)(codes + o + 32ull * w);
+            const uint32_t *b4 = (const uint32_t *)(a & ~(uintptr_t)3);
+            const uint32_t sh = (uint32_t)(a & 3) * 8;
+            uint32_t d[9], t[8];
+#pragma unroll
+            for (int q = 0; q < 9; q++) d[q] = b4[q];
+#pragma unroll
+            for (int q = 0; q < 8; q++) t[q] = __builtin_amdgcn_alignbit(d[q + 1], d[q], sh);
+            const uint32_t valid = len - 32 * w;
+            const uint32_t vmask = valid >= 32 ? 0xFFFFFFFFu : ((1u << valid) - 1u);
+            for (uint32_t c = 0; c < sigma; c++) {
+                const uint32_t rep = c * 0x01010101u;
+                uint32_t word = 0;
+#pragma unroll
+                for (int q = 0; q < 8; q++) {
+                    const uint32_t x = t[q] ^ rep;
+                    // bit 7 of a byte of z is set iff that byte of x is zero
+                    const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x) & 0x80808080u;
+                    const uint32_t nib = ((z >> 7) & 1u) | ((z >> 14) & 2u) | ((z >> 21) & 4u) |
+                                         ((z >> 28) & 8u);
+                    word |= nib << (4 * q);
+                }
+                dst[(uint64_t)c * W + w] = word & vmask;
+            }
         }
     }
 }
@@ -625,11 +634,33 @@ uint32_t verify_lanes_for(uint32_t K) {
     return nl <= 64 ? (uint32_t)nl : 0u;
 }
 
+void build_masks(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
+                 uint32_t n, uint64_t total, uint32_t sigma, RowMasks &rm, const char *tag,
+                 uint32_t *own_words, uint64_t *own_off) {
+    std::string t(tag);
+    uint64_t *off = own_off ? own_off : ws<uint64_t>(ctx, t + "_moff", (uint64_t)n + 1);
+    uint32_t *words =
+        own_words ? own_words : ws<uint32_t>(ctx, t + "_mwords", mask_words_bound(total, n, sigma));
+    rm.words = words;
+    rm.off = off;
+    if (n == 0) return;
+    uint64_t *sz = ws<uint64_t>(ctx, t + "_msz", (uint64_t)n + 1);
+    hipLaunchKernelGGL(k_mask_sizes, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
+                       d_offsets, n, sigma, sz);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u64(ctx, sz, off, n, nullptr);
+    hipLaunchKernelGGL(k_build_masks, dim3(grid_for(ctx, (uint64_t)n * 64, 256)), dim3(256), 0,
+                       ctx->stream, d_codes, d_offsets, base, n, sigma, (const uint64_t *)off,
+                       words);
+    EJ_CHECK_LAUNCH();
+}
+
 void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint64_t base,
-            uint32_t sigma, uint32_t maxlen, const uint64_t *d_pairs, uint64_t count, uint32_t K,
-            const uint32_t *d_Kq, int32_t *d_dist, const uint8_t *d_codes_b,
-            const uint64_t *d_offsets_b, uint64_t base_b, uint32_t maxlen_b,
-            unsigned long long *d_columns, const uint32_t *d_order) {
+            uint32_t sigma, uint32_t maxlen, const RowMasks &masks, const uint64_t *d_pairs,
+            uint64_t count, uint32_t K, const uint32_t *d_Kq, int32_t *d_dist,
+            const uint8_t *d_codes_b, const uint64_t *d_offsets_b, uint64_t base_b,
+            uint32_t maxlen_b, const RowMasks *masks_b, unsigned long long *d_columns,
+            const uint32_t *d_order) {
     if (count == 0) return;
     if (count >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "more than 2^32 pairs in one verification");
     uint32_t Kmax = K;
@@ -650,7 +681,10 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         d_offsets_b = d_offsets;
         base_b = base;
         maxlen_b = maxlen;
+        masks_b = &masks;
     }
+    const StrSet A{d_codes, d_offsets, base, masks.words, masks.off};
+    const StrSet B{d_codes_b, d_offsets_b, base_b, masks_b->words, masks_b->off};
     const uint32_t sig = sigma ? sigma : 1;
     const uint32_t W = 32 * NL;
     const uint32_t mtext = std::min(maxlen, maxlen_b);
@@ -661,10 +695,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     // ring layout: NL+1 live words, one more being filled
     uint32_t RW = 1;
     while (RW < NL + 2) RW <<= 1;
-    const uint32_t R = (32 + NL - 1) / NL;
     const uint32_t ring_mode = ctx->tune.verify_ring;
-    const bool ring = ring_mode != 0 && NL >= 8 && sig * R <= 32 &&
-                      (ring_mode == 2 || 2 * RW < wpp_full);
+    const bool ring = ring_mode != 0 && NL >= 8 && (ring_mode == 2 || 2 * RW < wpp_full);
     const uint32_t wpp = ring ? RW : wpp_full;
     const uint32_t tile_bytes = sig * (ring ? 2 * RW : wpp_full) * 4;
     uint32_t tpw = 64 / NL;
@@ -709,21 +741,21 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         // graph mode (keyed by every launch argument)
         char key[512];
         snprintf(key, sizeof(key),
-                 "verify_queue %d %d %p %p %llu %p %p %llu %p %u %p %u %p %u %u %u %u %p %p %p "
-                 "%llu %zu",
+                 "verify_queue %d %d %p %p %llu %p %p %p %p %llu %p %p %p %u %p %u %p %u %u %u %u "
+                 "%p %p %p %llu %zu",
                  mode, (int)ring, (const void *)d_codes, (const void *)d_offsets,
-                 (unsigned long long)base, (const void *)d_codes_b, (const void *)d_offsets_b,
-                 (unsigned long long)base_b, (const void *)d_pairs, (unsigned)count,
+                 (unsigned long long)base, (const void *)A.mw, (const void *)A.moff,
+                 (const void *)d_codes_b, (const void *)d_offsets_b, (unsigned long long)base_b,
+                 (const void *)B.mw, (const void *)B.moff, (const void *)d_pairs, (unsigned)count,
                  (const void *)d_order, K, (const void *)d_Kq, sig, NL, tpw, wpp, (void *)next,
                  (void *)d_dist, (void *)d_columns, (unsigned long long)grid, lds);
         kmark();
         run_captured(ctx, key, [&] {
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
             EJ_CHECK_LAUNCH();
-            hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
-                               d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs,
-                               (uint32_t)count, d_order, K, d_Kq, sig, NL, tpw, wpp, next,
-                               d_dist, d_columns);
+            hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B,
+                               d_pairs, (uint32_t)count, d_order, K, d_Kq, sig, NL, tpw, wpp,
+                               next, d_dist, d_columns);
             EJ_CHECK_LAUNCH();
         });
         kmark();
@@ -741,9 +773,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         kmark();
         uint64_t ngroups = (count + tpw - 1) / tpw;
         uint64_t grid = std::min<uint64_t>(ngroups, cap);
-        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
-                           d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs, count,
-                           (const uint32_t *)nullptr, K, d_Kq, sig, NL, tpw, wpp, 0u,
+        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
+                           count, (const uint32_t *)nullptr, K, d_Kq, sig, NL, tpw, wpp, 0u,
                            two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
         EJ_CHECK_LAUNCH();
         kmark();
@@ -766,9 +797,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     uint64_t ngroups = (nalive + tpw - 1) / tpw;
     uint64_t grid = std::min<uint64_t>(ngroups, cap);
     kmark();
-    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, d_codes,
-                       d_offsets, base, d_codes_b, d_offsets_b, base_b, d_pairs, nalive,
-                       (const uint32_t *)list, K, d_Kq, sig, NL, tpw, wpp, C1, NO_LIMIT, 1,
+    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
+                       nalive, (const uint32_t *)list, K, d_Kq, sig, NL, tpw, wpp, C1, NO_LIMIT, 1,
                        state, aux, d_dist, d_columns);
     EJ_CHECK_LAUNCH();
     kmark();
