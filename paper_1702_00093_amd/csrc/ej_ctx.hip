@@ -31,6 +31,11 @@ void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes) {
     return b.p;
 }
 
+size_t ws_capacity(ej_ctx *ctx, const std::string &name) {
+    auto it = ctx->ws.find(name);
+    return it == ctx->ws.end() ? 0 : it->second.bytes;
+}
+
 void sync(ej_ctx *ctx) { EJ_HIP(hipStreamSynchronize(ctx->stream)); }
 
 void run_captured(ej_ctx *ctx, const std::string &key, const std::function<void()> &enqueue) {

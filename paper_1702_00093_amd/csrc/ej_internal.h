@@ -122,6 +122,8 @@ struct ej_ctx {
 namespace ej {
 
 void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes);
+// Bytes the workspace buffer `name` holds now (0 if it does not exist).
+size_t ws_capacity(ej_ctx *ctx, const std::string &name);
 template <typename T>
 T *ws(ej_ctx *ctx, const std::string &name, size_t count) {
     return (T *)ws_get(ctx, name, count * sizeof(T));
