@@ -151,7 +151,8 @@ __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, ui
 }  // namespace
 
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
-            uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag) {
+            uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
+            bool want_ngroups) {
     std::string t(tag);
     bk.T = T;
     bk.n = n;
@@ -189,7 +190,7 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
                        (const uint32_t *)dk2, n, tot, (const uint32_t *)flags, bk.d_gid,
                        bk.d_gstart, (const uint64_t *)d_ng);
     EJ_CHECK_LAUNCH();
-    read_back(ctx, d_ng, 8, &bk.ngroups);
+    if (want_ngroups) read_back(ctx, d_ng, 8, &bk.ngroups);
 }
 
 uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, const uint32_t *d_len,

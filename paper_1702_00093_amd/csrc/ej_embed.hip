@@ -74,8 +74,11 @@ __global__ void k_lengths(const uint64_t *__restrict__ offsets, uint32_t n,
 
 // Presence bitmap of the bytes in [base, base+total): 16-byte loads over the
 // aligned body, single bytes for the unaligned head and tail.
-__global__ void k_presence(const uint8_t *__restrict__ chars, uint64_t base, uint64_t total,
-                           PrepInfo *__restrict__ info) {
+__global__ void k_presence(const uint8_t *__restrict__ chars, PrepInfo *__restrict__ info) {
+    // [base, base+total) from the offsets (k_prep_info ran first on the stream);
+    // decreasing offsets are reported through info->err and scan nothing here
+    const uint64_t base = info->off0;
+    const uint64_t total = info->offn >= info->off0 ? info->offn - info->off0 : 0;
     __shared__ uint32_t m[8];
     if (threadIdx.x < 8) m[threadIdx.x] = 0;
     __syncthreads();
@@ -412,6 +415,12 @@ void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uin
         hipLaunchKernelGGL(k_lengths, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
                            d_offsets, n, pp.d_len, d_info);
     EJ_CHECK_LAUNCH();
+    // the byte presence bitmap in the same round trip as the offsets summary
+    if (d_chars) {
+        hipLaunchKernelGGL(k_presence, dim3((uint32_t)ctx->num_cu * 16), dim3(256), 0,
+                           ctx->stream, d_chars, d_info);
+        EJ_CHECK_LAUNCH();
+    }
     PrepInfo info;
     read_back(ctx, d_info, sizeof(PrepInfo), &info);
     if (info.err & 1u) fail(EJ_EINVAL, "offsets are not non-decreasing");
@@ -422,13 +431,7 @@ void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uin
     pp.maxlen = info.maxlen;
     if (pp.total && !d_chars) fail(EJ_EINVAL, "null character buffer");
     uint32_t mask[8] = {0};
-    if (pp.total) {
-        hipLaunchKernelGGL(k_presence, dim3(grid_for(ctx, pp.total / 16 + 1, 256)), dim3(256), 0,
-                           ctx->stream, d_chars, pp.base, pp.total, d_info);
-        EJ_CHECK_LAUNCH();
-        read_back(ctx, d_info, sizeof(PrepInfo), &info);
-        memcpy(mask, info.mask, sizeof(mask));
-    }
+    memcpy(mask, info.mask, sizeof(mask));
     if (fixed_lut) {
         for (int b = 0; b < 256; b++)
             if (((mask[b >> 5] >> (b & 31)) & 1u) && fixed_lut[b] == 0xFF)

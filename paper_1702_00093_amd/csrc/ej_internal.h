@@ -211,8 +211,10 @@ struct Buckets {
     uint32_t *d_gstart = nullptr;     // [ngroups + 1]
     uint64_t ngroups = 0;
 };
+// bk.ngroups is read back to the host only when want_ngroups is set.
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
-            uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag);
+            uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
+            bool want_ngroups = false);
 
 // Candidate pairs as packed codes (a << 32 | b), a < b, sorted and unique.
 // Returns the count; *n_raw gets the pre-dedup count.

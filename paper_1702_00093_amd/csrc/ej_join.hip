@@ -417,7 +417,7 @@ ej_status ej_lsh_bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_l
             radix_sort_u32(ctx, lk, iota, lk2, perm, 1, n, bits_for(maxlen), 8);
         }
         Buckets bk;
-        bucket(ctx, d_keys, d_len, perm, n, ntables, key_bits, bk, "b");
+        bucket(ctx, d_keys, d_len, perm, n, ntables, key_bits, bk, "b", true);
         uint64_t tot = (uint64_t)ntables * n;
         if (tot)
             EJ_HIP(hipMemcpyAsync(d_ids_sorted, bk.d_ids, 4 * tot, hipMemcpyDeviceToDevice,

@@ -271,13 +271,16 @@ __device__ inline void fill_tile(uint32_t *pq, const PairView &v, uint32_t l, ui
 // their state and runs them to the end.
 template <int MODE, bool RING>
 __global__ void __launch_bounds__(64)
-    k_verify(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count, const uint32_t *__restrict__ list,
+    k_verify(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count_arg,
+             const uint64_t *__restrict__ count_dev, const uint32_t *__restrict__ list,
              uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL_arg,
              uint32_t tpw, uint32_t wpp, uint32_t jbeg, uint32_t jlim, int resume,
              uint32_t *__restrict__ state, uint32_t *__restrict__ aux,
              int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
     const uint32_t NL = lanes_of<MODE>(NL_arg);
+    // pass 2 takes its pair count from the device (a grid sized for all pairs)
+    const uint64_t count = count_dev ? *count_dev : count_arg;
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
@@ -774,7 +777,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         uint64_t ngroups = (count + tpw - 1) / tpw;
         uint64_t grid = std::min<uint64_t>(ngroups, cap);
         hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
-                           count, (const uint32_t *)nullptr, K, d_Kq, sig, NL, tpw, wpp, 0u,
+                           count, (const uint64_t *)nullptr, (const uint32_t *)nullptr, K, d_Kq,
+                           sig, NL, tpw, wpp, 0u,
                            two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
         EJ_CHECK_LAUNCH();
         kmark();
@@ -787,18 +791,18 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
                        (const uint32_t *)aux, count, flags);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u32(ctx, flags, pos, count, d_nalive);
-    uint64_t nalive = 0;
-    read_back(ctx, d_nalive, 8, &nalive);
-    if (nalive == 0) return;
-    uint32_t *list = ws<uint32_t>(ctx, "verify_list", nalive);
+    // no host round trip: the list and pass 2 are sized for all pairs and
+    // pass 2 reads the number of undecided pairs from the device
+    uint32_t *list = ws<uint32_t>(ctx, "verify_list", count);
     hipLaunchKernelGGL(k_alive_list, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
                        (const uint32_t *)flags, (const uint32_t *)pos, count, list);
     EJ_CHECK_LAUNCH();
-    uint64_t ngroups = (nalive + tpw - 1) / tpw;
+    uint64_t ngroups = (count + tpw - 1) / tpw;
     uint64_t grid = std::min<uint64_t>(ngroups, cap);
     kmark();
     hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
-                       nalive, (const uint32_t *)list, K, d_Kq, sig, NL, tpw, wpp, C1, NO_LIMIT, 1,
+                       count, (const uint64_t *)d_nalive, (const uint32_t *)list, K, d_Kq, sig, NL,
+                       tpw, wpp, C1, NO_LIMIT, 1,
                        state, aux, d_dist, d_columns);
     EJ_CHECK_LAUNCH();
     kmark();
