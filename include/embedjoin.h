@@ -133,7 +133,7 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_ring"           match-mask layout in LDS: 0 the whole pattern,
  *                           1 a ring of the words the band covers when it is
  *                           smaller, 2 the ring whenever the band has at
- *                           least 8 lanes and the alphabet is small
+ *                           least 2 lanes
  *   "embed_lds_budget"      LDS bytes per wave of the walk kernel
  *   "radix_bits"            digit width of the radix sorts (4..11)
  *   "bucket_key_bits"       key bits sorted when bucketing (1..32; 0 =

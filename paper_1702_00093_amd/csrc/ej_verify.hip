@@ -699,7 +699,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     uint32_t RW = 1;
     while (RW < NL + 2) RW <<= 1;
     const uint32_t ring_mode = ctx->tune.verify_ring;
-    const bool ring = ring_mode != 0 && NL >= 8 && (ring_mode == 2 || 2 * RW < wpp_full);
+    const bool ring = ring_mode != 0 && NL >= 2 && (ring_mode == 2 || 2 * RW < wpp_full);
     const uint32_t wpp = ring ? RW : wpp_full;
     const uint32_t tile_bytes = sig * (ring ? 2 * RW : wpp_full) * 4;
     uint32_t tpw = 64 / NL;
