@@ -56,6 +56,9 @@ def parse():
                     help="batched form with these launch knobs instead of the autotuner's")
     ap.add_argument("--no-uneven", action="store_true",
                     help="skip the uneven-length join (80,000 strings, K=400)")
+    ap.add_argument("--with-protein", action="store_true",
+                    help="also run the protein-like join (400,000 strings, K=100; ~1 min of "
+                         "data generation)")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (index of 320,000 strings, 10,000 queries)")
     ap.add_argument("--serving-only", action="store_true",
@@ -392,26 +395,43 @@ def form_summary(f, prm):
                 knobs=f["knobs"])
 
 
-def uneven_bench(ej, ctx, oracle, args):
-    """The batched uneven-length join (80,000 DNA strings, log-uniform
-    lengths, K=400) in both forms at its recall-calibrated point."""
+def leg_bench(ej, ctx, oracle, args, col, desc, prm, stated):
+    """One more workload in both forms (plain, batched) at parameters prm."""
     import torch
-    import synthdata as sd
-    col, stated = sd.uneven_dna(0)
-    prm = dict(K=stated["K"], **CALIBRATED["uneven"])
+    _log(f"leg: {desc}")
     chars = torch.from_numpy(col.chars).cuda()
     offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
     forms = run_forms(ej, ctx, chars, offs, prm, args)
     b = forms["batched"]
-    out = dict(workload="uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, "
-                        "clusters geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)",
-               params=prm, stated=dict(K=stated["K"], r=stated["r"], z=stated["z"],
-                                       m=stated["m"]),
+    out = dict(workload=desc, params=prm, stated=stated,
                candidates=b["res"].n_candidates, output_pairs=int(len(b["res"].pairs)),
                batched=form_summary(b, prm), plain=form_summary(forms["plain"], prm))
     if not args.no_recall:
         out["recall"] = recall_estimate(col, b["res"], prm["K"], oracle)
     return out
+
+
+def uneven_bench(ej, ctx, oracle, args):
+    """The batched uneven-length join (80,000 DNA strings, log-uniform
+    lengths, K=400) in both forms at its recall-calibrated point."""
+    import synthdata as sd
+    col, stated = sd.uneven_dna(0)
+    prm = dict(K=stated["K"], **CALIBRATED["uneven"])
+    return leg_bench(ej, ctx, oracle, args, col,
+                     "uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, clusters "
+                     "geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)", prm, stated)
+
+
+def protein_bench(ej, ctx, oracle, args):
+    """The protein-like join (400,000 strings over 25 Zipf letters, K=100)
+    at its stated parameters with L = ceil(2 avg)."""
+    import synthdata as sd
+    col, stated = sd.protein_like(0)
+    prm = dict(stated, L=int(np.ceil(2 * col.lengths().mean())))
+    return leg_bench(ej, ctx, oracle, args, col,
+                     "protein-like: 400,000 strings over 25 letters (Zipf 1.1), lengths lognormal "
+                     "(median 400, sigma 0.8) clipped 50..4,000, clusters of mean 4, edit rate "
+                     "U(0.02, 0.15)", prm, stated)
 
 
 def main():
@@ -483,6 +503,11 @@ def main():
             out["uneven"] = uneven_bench(ej, ctx, oracle, args)
         except Exception as e:  # reported, never hides the join line
             out["uneven"] = {"error": f"{type(e).__name__}: {e}"}
+    if args.with_protein:
+        try:
+            out["protein"] = protein_bench(ej, ctx, oracle, args)
+        except Exception as e:  # reported, never hides the join line
+            out["protein"] = {"error": f"{type(e).__name__}: {e}"}
     if not args.no_serving:
         try:
             out["serving"] = serving_bench(ej, ctx, oracle)
