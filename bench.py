@@ -25,13 +25,18 @@ MI355X_HBM = 8.0e12
 
 # Work the method itself must do, in 32-bit integer lane operations:
 #  - verification: Myers' bit-parallel step over one 32-cell word of the band
-#    is 15 operations (Xv, Eq&Pv, +Pv, ^Pv, |Eq, Ph (3), Mh, two shifts,
-#    Pv (3), Mv), i.e. 15/32 operations per DP cell; the band a threshold-K
-#    verification needs is K+1 diagonals wide (a path through diagonal d
-#    costs at least |d| + |d - d*|);
+#    is 10 gfx950 instructions (the match word, Xv, Eq&Pv, the add, Xh/Ph/Mh
+#    in three 3-input logic operations, the one-bit shift, Pv and Mv), i.e.
+#    10/32 operations per DP cell; with 2-input logic alone it would be 15.
+#    The band a threshold-K verification needs is K+1 diagonals wide (a path
+#    through diagonal d costs at least |d| + |d - d*|);
 #  - walk: 3 operations per CGK step (read the symbol, select its pi bit,
 #    advance the pointer).
-OPS_PER_WORD_STEP = 15
+OPS_PER_WORD_STEP = 10
+# the verification kernel of each form (JoinResult.verify_form)
+VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane"}
+VERIFY_FORM = {0: "two-pass", 1: "persistent, replayed from a captured HIP graph",
+               2: "one pair per lane, persistent, replayed from a captured HIP graph"}
 OPS_PER_WALK_STEP = 3
 
 
@@ -341,16 +346,16 @@ def run_forms(ej, ctx, chars, offs, prm, args):
             ctx.tune_set(k.strip(), int(v))
         tune_ms = None
     elif args.no_autotune:
-        ctx.tune_set("verify_mode", 1)
+        ctx.tune_set("verify_mode", 2)
         tune_ms = None
     else:
         tune_ms, _ = ctx.autotune(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
                                   L=prm["L"], reps=2)
     knobs = ctx.knobs()
-    gflags = flags | (ej.FLAG_GRAPH if knobs["verify_mode"] == 1 else 0)
+    gflags = flags | (ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0)
     res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, gflags)
     batched = dict(res=res, ms=ms, stage=stage, knobs=knobs, autotune_best_ms=tune_ms,
-                   kernel="k_verify_queue" if knobs["verify_mode"] == 1 else "k_verify")
+                   kernel=VERIFY_KERNEL[res.verify_form])
     for k, v in defaults.items():
         ctx.tune_set(k, v)
     return dict(plain=plain, batched=batched)
@@ -485,8 +490,7 @@ def main():
         "config": {"workload": name, "K": prm["K"], "r": prm["r"], "z": prm["z"], "m": prm["m"],
                    "L": res.L, "params": "stated" if prm == stated else "recall-calibrated",
                    "form": ("batched: autotuned knobs, verification "
-                            + ("persistent, replayed from a captured HIP graph"
-                               if head["knobs"]["verify_mode"] == 1 else "two-pass")),
+                            + VERIFY_FORM[res.verify_form]),
                    "candidates": cand, "raw_candidates": res.n_raw,
                    "output_pairs": int(len(res.pairs)), "join_sec": round(ms / 1000.0, 5),
                    "stage_ms": {k: round(v, 3) for k, v in stage.items()},

@@ -62,10 +62,10 @@ typedef enum {
 
 /* Flags of ej_params.flags */
 #define EJ_FLAG_PLAIN 0u   /* one launch per stage, host-sized buffers */
-#define EJ_FLAG_GRAPH 1u   /* with the persistent verification form ("verify_mode" 1): its
-                            launches are captured once into a HIP graph, cached in the
-                            context by launch arguments and replayed by later joins of
-                            the same shape */
+#define EJ_FLAG_GRAPH 1u   /* with a persistent verification form ("verify_mode" 1 or 2):
+                            its launches are captured once into a HIP graph, cached in
+                            the context by launch arguments and replayed by later joins
+                            of the same shape */
 #define EJ_FLAG_TIMING 2u  /* record per-stage device times in ej_result */
 
 typedef struct ej_ctx ej_ctx;
@@ -103,6 +103,9 @@ typedef struct {
      * launches (events right around each launch) and their number. */
     float ms_verify_kernel;
     uint32_t verify_launches;
+    /* The verification form that ran: 0 two passes over groups of pairs,
+     * 1 persistent groups of pairs, 2 one pair per lane (see "verify_mode"). */
+    uint32_t verify_form;
 } ej_result;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -122,12 +125,22 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_lds_budget"     LDS bytes per wave of the verification kernel
  *   "verify_pass1_cols"     columns of verification pass 1 (multiple of 32;
  *                           0 = a single pass)
- *   "verify_blocks_per_cu"  workgroups per CU of the verification grid
- *   "verify_mode"           0: two passes over fixed groups of pairs (the
- *                           first C1 columns of all, then the survivors);
+ *   "verify_blocks_per_cu"  workgroups per CU of the verification grid (the
+ *                           lane form: at most, below the occupancy limit)
+ *   "verify_mode"           0: two passes over fixed groups of pairs, one
+ *                           band word per lane (the first C1 columns of all,
+ *                           then the survivors);
  *                           1: one persistent launch in which each pair's
- *                           lanes take the next pair from a device counter
- *   "verify_order"          persistent form, joins only: 0 pairs in list
+ *                           lanes take the next pair from a device counter;
+ *                           2: the lane form, persistent, with several band
+ *                           words per lane ("verify_split" lanes per pair),
+ *                           for alphabets of up to 4 symbols and bands of up
+ *                           to 8 words per lane (16 with one lane per pair);
+ *                           other inputs take form 1
+ *   "verify_split"          lane form: lanes per pair, 1, 2, 4, 8 or 16
+ *                           (0 = by band width: 1 up to 4 words, 2 up to 8,
+ *                           then 4)
+ *   "verify_order"          persistent forms, joins only: 0 pairs in list
  *                           order, 1 most frequent pairs (found by the most
  *                           tables) first, which shortens the tail
  *   "verify_ring"           match-mask layout in LDS: 0 the whole pattern,

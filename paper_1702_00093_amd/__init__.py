@@ -54,7 +54,8 @@ class _Result(ctypes.Structure):
                 ("ms_bucket", ctypes.c_float), ("ms_candidates", ctypes.c_float),
                 ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float),
                 ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64),
-                ("ms_verify_kernel", ctypes.c_float), ("verify_launches", ctypes.c_uint32)]
+                ("ms_verify_kernel", ctypes.c_float), ("verify_launches", ctypes.c_uint32),
+                ("verify_form", ctypes.c_uint32)]
 
 
 class _QResult(ctypes.Structure):
@@ -168,6 +169,7 @@ class JoinResult:
     verify_columns: int = 0
     ms_verify_kernel: float = 0.0
     verify_launches: int = 0
+    verify_form: int = 0       # 0 two-pass, 1 persistent groups, 2 one pair per lane
 
     @property
     def codes(self) -> np.ndarray:
@@ -249,11 +251,12 @@ class Context:
             return JoinResult(pairs, dist, int(res.n_candidates), int(res.n_raw),
                               int(res.sigma), int(res.L), ms, int(res.walk_steps),
                               int(res.verify_columns), float(res.ms_verify_kernel),
-                              int(res.verify_launches))
+                              int(res.verify_launches), int(res.verify_form))
         finally:
             lib().ej_result_free(ctypes.byref(res))
 
-    KNOBS = ("verify_mode", "verify_order", "verify_pass1_cols", "verify_blocks_per_cu", "verify_ring",
+    KNOBS = ("verify_mode", "verify_order", "verify_split", "verify_pass1_cols",
+             "verify_blocks_per_cu", "verify_ring",
              "verify_lds_budget", "embed_lds_budget", "radix_bits", "bucket_key_bits")
 
     def knobs(self) -> dict:

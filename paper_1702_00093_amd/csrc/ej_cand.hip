@@ -16,6 +16,7 @@
 //   3. the pairs are counted, scanned and emitted at deterministic offsets,
 //      then sorted and de-duplicated across tables.
 #include <algorithm>
+#include <type_traits>
 
 #include "ej_internal.h"
 
@@ -83,13 +84,13 @@ __global__ void k_sorted_attrs(const uint64_t *__restrict__ keys, const uint32_t
 
 // Pairs of entry e: following entries of its group inside the length window
 // with an equal full key.  EMIT = false counts, EMIT = true writes packed
-// codes (min << B | max) from out + offs[e].
-template <bool EMIT>
+// codes (min << B | max) from out + offs[e]; C is 32 bits when 2B <= 32.
+template <bool EMIT, typename C>
 __global__ void k_pairs(const uint64_t *__restrict__ key_s, const uint32_t *__restrict__ len_s,
                         const uint32_t *__restrict__ ids, const uint32_t *__restrict__ gid,
                         const uint32_t *__restrict__ gstart, uint64_t tot, uint32_t K,
                         uint32_t B, uint64_t *__restrict__ counts,
-                        const uint64_t *__restrict__ offs, uint64_t *__restrict__ out) {
+                        const uint64_t *__restrict__ offs, C *__restrict__ out) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < tot;
          e += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t ge = gstart[gid[e] + 1];
@@ -104,7 +105,7 @@ __global__ void k_pairs(const uint64_t *__restrict__ key_s, const uint32_t *__re
                 if (EMIT) {
                     uint32_t idq = ids[q];
                     uint32_t a = min(ide, idq), b = max(ide, idq);
-                    out[o + c] = ((uint64_t)a << B) | b;
+                    out[o + c] = (C)(((uint64_t)a << B) | b);
                 }
                 c++;
             }
@@ -113,14 +114,16 @@ __global__ void k_pairs(const uint64_t *__restrict__ key_s, const uint32_t *__re
     }
 }
 
-__global__ void k_unique_flags(const uint64_t *__restrict__ codes, uint64_t cnt,
+template <typename C>
+__global__ void k_unique_flags(const C *__restrict__ codes, uint64_t cnt,
                                uint32_t *__restrict__ flags) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (uint64_t)gridDim.x * blockDim.x)
         flags[e] = (e == 0 || codes[e] != codes[e - 1]) ? 1u : 0u;
 }
 
-__global__ void k_unique_compact(const uint64_t *__restrict__ codes, uint64_t cnt, uint32_t B,
+template <typename C>
+__global__ void k_unique_compact(const C *__restrict__ codes, uint64_t cnt, uint32_t B,
                                  const uint32_t *__restrict__ flags,
                                  const uint32_t *__restrict__ pos, uint64_t *__restrict__ out,
                                  uint32_t *__restrict__ first) {
@@ -128,7 +131,7 @@ __global__ void k_unique_compact(const uint64_t *__restrict__ codes, uint64_t cn
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (uint64_t)gridDim.x * blockDim.x) {
         if (flags[e]) {
-            uint64_t c = codes[e];
+            const uint64_t c = codes[e];
             out[pos[e]] = ((c >> B) << 32) | (c & mask);
             if (first) first[pos[e]] = (uint32_t)e;
         }
@@ -210,10 +213,11 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     uint64_t *counts = ws<uint64_t>(ctx, t + "_counts", tot);
     uint64_t *d_raw = ws<uint64_t>(ctx, t + "_nraw", 1);
     const uint32_t B = std::max(1u, bits_for(n - 1));
-    hipLaunchKernelGGL(k_pairs<false>, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
-                       (const uint64_t *)key_s, (const uint32_t *)len_s,
+    hipLaunchKernelGGL((k_pairs<false, uint64_t>), dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                       ctx->stream, (const uint64_t *)key_s, (const uint32_t *)len_s,
                        (const uint32_t *)bk.d_ids, (const uint32_t *)bk.d_gid,
-                       (const uint32_t *)bk.d_gstart, tot, K, B, counts, nullptr, nullptr);
+                       (const uint32_t *)bk.d_gstart, tot, K, B, counts, nullptr,
+                       (uint64_t *)nullptr);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u64(ctx, counts, counts, tot, d_raw);
     uint64_t raw = 0;
@@ -222,38 +226,55 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     if (raw == 0) return 0;
     if (raw >= 0xFFFFFFFFull)
         fail(EJ_EUNSUPPORTED, "more than 2^32 raw candidate pairs (" + std::to_string(raw) + ")");
-    uint64_t *rawbuf = ws<uint64_t>(ctx, t + "_raw", raw);
-    uint64_t *sorted = ws<uint64_t>(ctx, t + "_raw_sorted", raw);
-    hipLaunchKernelGGL(k_pairs<true>, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
-                       (const uint64_t *)key_s, (const uint32_t *)len_s,
-                       (const uint32_t *)bk.d_ids, (const uint32_t *)bk.d_gid,
-                       (const uint32_t *)bk.d_gstart, tot, K, B, nullptr,
-                       (const uint64_t *)counts, rawbuf);
-    EJ_CHECK_LAUNCH();
-    radix_sort_u64(ctx, rawbuf, sorted, raw, 2 * B, ctx->tune.radix_bits);
     uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", raw);
     uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", raw);
     uint64_t *d_cnt = ws<uint64_t>(ctx, t + "_ucount", 1);
-    hipLaunchKernelGGL(k_unique_flags, dim3(grid_for(ctx, raw, 256)), dim3(256), 0, ctx->stream,
-                       (const uint64_t *)sorted, raw, flags);
-    EJ_CHECK_LAUNCH();
-    scan_exclusive_u32(ctx, flags, pos, raw, d_cnt);
-    uint64_t cnt = 0;
-    read_back(ctx, d_cnt, 8, &cnt);
-    uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
-    uint32_t *first = d_order_out ? ws<uint32_t>(ctx, t + "_first", cnt) : nullptr;
-    hipLaunchKernelGGL(k_unique_compact, dim3(grid_for(ctx, raw, 256)), dim3(256), 0, ctx->stream,
-                       (const uint64_t *)sorted, raw, B, (const uint32_t *)flags,
-                       (const uint32_t *)pos, pairs, first);
-    EJ_CHECK_LAUNCH();
-    *d_pairs_out = pairs;
+    // the packed codes are sorted, then the first of each run of equal codes
+    // kept; 32-bit codes when both indexes fit in 16 bits, which halves the
+    // sort's traffic
+    auto emit_sort_unique = [&](auto *rawbuf, auto *sorted) -> uint64_t {
+        using C = std::remove_pointer_t<decltype(rawbuf)>;
+        hipLaunchKernelGGL((k_pairs<true, C>), dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                           ctx->stream, (const uint64_t *)key_s, (const uint32_t *)len_s,
+                           (const uint32_t *)bk.d_ids, (const uint32_t *)bk.d_gid,
+                           (const uint32_t *)bk.d_gstart, tot, K, B, (uint64_t *)nullptr,
+                           (const uint64_t *)counts, rawbuf);
+        EJ_CHECK_LAUNCH();
+        if constexpr (sizeof(C) == 4)
+            radix_sort_u32(ctx, rawbuf, nullptr, sorted, nullptr, 1, (uint32_t)raw, 2 * B,
+                           ctx->tune.radix_bits);
+        else
+            radix_sort_u64(ctx, rawbuf, sorted, raw, 2 * B, ctx->tune.radix_bits);
+        hipLaunchKernelGGL(k_unique_flags<C>, dim3(grid_for(ctx, raw, 256)), dim3(256), 0,
+                           ctx->stream, (const C *)sorted, raw, flags);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, flags, pos, raw, d_cnt);
+        uint64_t cnt = 0;
+        read_back(ctx, d_cnt, 8, &cnt);
+        uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
+        uint32_t *first = d_order_out ? ws<uint32_t>(ctx, t + "_first", cnt) : nullptr;
+        hipLaunchKernelGGL(k_unique_compact<C>, dim3(grid_for(ctx, raw, 256)), dim3(256), 0,
+                           ctx->stream, (const C *)sorted, raw, B, (const uint32_t *)flags,
+                           (const uint32_t *)pos, pairs, first);
+        EJ_CHECK_LAUNCH();
+        *d_pairs_out = pairs;
+        return cnt;
+    };
+    uint64_t cnt;
+    if (2 * B <= 32)
+        cnt = emit_sort_unique(ws<uint32_t>(ctx, t + "_raw32", raw),
+                               ws<uint32_t>(ctx, t + "_raw32_sorted", raw));
+    else
+        cnt = emit_sort_unique(ws<uint64_t>(ctx, t + "_raw", raw),
+                               ws<uint64_t>(ctx, t + "_raw_sorted", raw));
     if (d_order_out && cnt) {
+        const uint32_t *first = ws<uint32_t>(ctx, t + "_first", cnt);
         uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
         uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
         uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", cnt);
         uint32_t *order = ws<uint32_t>(ctx, t + "_order", cnt);
         hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
-                           (const uint32_t *)first, cnt, raw, k0, v0);
+                           first, cnt, raw, k0, v0);
         EJ_CHECK_LAUNCH();
         radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt, 16, 8);
         *d_order_out = order;

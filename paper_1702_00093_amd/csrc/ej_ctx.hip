@@ -155,8 +155,9 @@ static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32
         {"verify_pass1_cols", &Tuning::verify_pass1_cols, 0, 1u << 30},
         {"verify_blocks_per_cu", &Tuning::verify_blocks_per_cu, 1, 1024},
         {"verify_ring", &Tuning::verify_ring, 0, 2},
-        {"verify_mode", &Tuning::verify_mode, 0, 1},
+        {"verify_mode", &Tuning::verify_mode, 0, 2},
         {"verify_order", &Tuning::verify_order, 0, 1},
+        {"verify_split", &Tuning::verify_split, 0, 16},
         {"embed_lds_budget", &Tuning::embed_lds_budget, 8192, 1u << 20},
         {"radix_bits", &Tuning::radix_bits, 4, 11},
         {"bucket_key_bits", &Tuning::bucket_key_bits, 0, 32},
@@ -181,6 +182,10 @@ ej_status ej_tune_set(ej_ctx *ctx, const char *name, uint32_t value) {
     }
     if (strcmp(name, "verify_pass1_cols") == 0 && (value % 32) != 0) {
         ctx->err = "verify_pass1_cols must be a multiple of 32";
+        return EJ_EINVAL;
+    }
+    if (strcmp(name, "verify_split") == 0 && (value & (value - 1)) != 0) {
+        ctx->err = "verify_split must be 0 or a power of two up to 16";
         return EJ_EINVAL;
     }
     *slot = value;

@@ -94,6 +94,7 @@ struct Tuning {
     uint32_t verify_blocks_per_cu = 32;      // resident-wave target of the verification grid
     uint32_t verify_order = 1;               // persistent form: 0 pair order, 1 by table multiplicity
     uint32_t verify_mode = 0;                // 0 two passes over pair tiles, 1 persistent pair queue
+    uint32_t verify_split = 0;               // lane form: lanes per pair (0 auto, 1, 2, 4, 8, 16)
     uint32_t verify_ring = 1;                // match masks: 0 whole pattern, 1 auto, 2 ring if it fits
     uint32_t embed_lds_budget = 48 * 1024;   // LDS per wave of the walk kernel
     uint32_t radix_bits = 8;                 // digit width of the radix sorts
@@ -117,6 +118,7 @@ struct ej_ctx {
     // argument of their launches (pointers included), replayed on a match
     bool graph_on = false;
     std::map<std::string, hipGraphExec_t> graphs;
+    uint32_t last_verify_form = 0;  // form of the last verification launched
 };
 
 namespace ej {

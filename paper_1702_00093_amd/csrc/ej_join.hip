@@ -157,7 +157,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
     uint32_t *order = nullptr;
-    const bool want_order = ctx->tune.verify_mode == 1 && ctx->tune.verify_order == 1;
+    const bool want_order = ctx->tune.verify_mode >= 1 && ctx->tune.verify_order == 1;
     uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j",
                               want_order ? &order : nullptr);
     out->n_candidates = cnt;
@@ -171,7 +171,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     tm.mark();  // 4: the verification stage follows
     ctx->timers.on = tm.on;
     ctx->timers.nkv = 0;
-    ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode == 1;
+    ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode >= 1;
     RowMasks masks;
     if (cnt)
         build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
@@ -239,6 +239,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         }
         out->ms_verify_kernel = kms;
         out->verify_launches = (uint32_t)(ctx->timers.nkv / 2);
+        out->verify_form = ctx->last_verify_form;
     }
 }
 
@@ -308,22 +309,26 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
         trial();  // warm the workspace
         double cur = trial();
         // coordinate descent, one knob at a time, in order of expected effect
+        // which verification forms a knob affects, as a bit mask of verify_mode
+        // values (1: two-pass, 2: persistent tiles, 4: lanes)
         struct Knob {
             uint32_t Tuning::*field;
             std::vector<uint32_t> vals;
-            int only_mode;  // -1: always; else only when verify_mode has this value
+            uint32_t modes;
         };
         const Knob knobs[] = {
-            {&Tuning::verify_mode, {0, 1}, -1},
-            {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 0},
-            {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 0},
-            {&Tuning::verify_order, {1, 0}, 1},
-            {&Tuning::verify_ring, {1, 0}, -1},
-            {&Tuning::radix_bits, {6, 7, 8, 11}, -1},
-            {&Tuning::bucket_key_bits, {0, 32}, -1},
+            {&Tuning::verify_mode, {0, 1, 2}, 7},
+            {&Tuning::verify_split, {0, 1, 2, 4, 8}, 4},
+            {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 1},
+            {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 1},
+            {&Tuning::verify_blocks_per_cu, {2, 4, 8, 16, 32}, 4},
+            {&Tuning::verify_order, {1, 0}, 6},
+            {&Tuning::verify_ring, {1, 0}, 3},
+            {&Tuning::radix_bits, {6, 7, 8, 11}, 7},
+            {&Tuning::bucket_key_bits, {0, 32}, 7},
         };
         for (const Knob &k : knobs) {
-            if (k.only_mode >= 0 && ctx->tune.verify_mode != (uint32_t)k.only_mode) continue;
+            if (!((k.modes >> ctx->tune.verify_mode) & 1u)) continue;
             const uint32_t start = ctx->tune.*(k.field);
             uint32_t best_v = start;
             for (uint32_t v : k.vals) {

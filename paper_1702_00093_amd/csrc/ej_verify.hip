@@ -541,6 +541,489 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Lane form: one pair per lane.  The band's NW words live in the lane's own
+// registers, so the W-bit addition is a chain of add-with-carry instructions
+// and the one-bit shift a funnel shift between neighbouring registers -- no
+// ballots and no cross-lane moves, about ten VALU instructions per 32 band
+// cells and column.
+//
+//  * Each lane keeps in LDS, one row per symbol, the match-mask words of the
+//    NW+1 band words its next 32 columns read; after every block the rows
+//    move down one word and the entering word is taken from the pattern's
+//    precomputed masks.
+//  * Row `sigma` is all ones: the symbol of padding columns after the end of
+//    the text.  In a column where every cell matches, every diagonal keeps
+//    its value (the match move keeps it and no diagonal ever decreases), so
+//    the whole state stays fixed.  A pair whose text ends inside a block
+//    therefore runs the whole block, and its state at the block end is its
+//    state at the last text column.
+//  * The value on diagonal d* is not counted column by column.  The kernel
+//    counts the top diagonal instead (band bit 0: one fixed register, 0 or 1
+//    added per column as for any diagonal) and, at block ends, reads the
+//    value on d* as the top value plus the vertical deltas of bits 1..k*.
+//  * Pairs come from a device-wide counter, one per lane.  Lanes whose pair is
+//    decided take the next one before the following block, and the whole wave
+//    fills the mask windows of the pairs just taken.
+template <int NW>
+__device__ inline void lane_state_init(uint32_t O, uint32_t (&Pv)[NW], uint32_t (&Mv)[NW]) {
+    // D[i][0] = |i|: bit k holds row k - O, rows <= 0 have delta -1
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        const int d = (int)O - 32 * w;
+        const uint32_t mv = d >= 31 ? 0xFFFFFFFFu : (d < 0 ? 0u : (2u << d) - 1u);
+        Mv[w] = mv;
+        Pv[w] = ~mv;
+    }
+}
+
+// Text of columns jb+1 .. jb+32 with the columns past nn set to the
+// match-all symbol `pad`.
+__device__ inline void lane_text_block(const uint8_t *y, uint32_t nn, uint32_t jb, uint32_t pad,
+                                       uint32_t tw[8]) {
+    load_text_block(y, nn, jb, tw);
+    const uint32_t r = nn > jb ? nn - jb : 0u;
+    const uint32_t fill = pad * 0x01010101u;
+#pragma unroll
+    for (uint32_t q = 0; q < 8; q++) {
+        const uint32_t v = r > 4 * q ? r - 4 * q : 0u;
+        const uint32_t keep = v >= 4 ? 0xFFFFFFFFu : ((1u << (8 * v)) - 1u);
+        tw[q] = (tw[q] & keep) | (fill & ~keep);
+    }
+}
+
+// s = a + b + (bit `lane` of cin); carry-outs of every lane in cout.
+__device__ inline uint32_t add_carry_chain(uint32_t a, uint32_t b, uint64_t cin, uint64_t &cout) {
+    uint32_t s;
+    asm("v_addc_co_u32 %0, %1, %2, %3, %4" : "=v"(s), "=s"(cout) : "v"(a), "v"(b), "s"(cin));
+    return s;
+}
+
+// 32 columns of one pair per lane.  Row c of the lane's window holds the
+// match-mask words of band words jb/32 .. jb/32+NW for symbol c.  The words
+// of column s+1 are read while column s is computed; a scheduling barrier
+// per column keeps the compiler from hoisting the reads of every column of
+// the block at once (which would take hundreds of registers).
+template <int NW>
+__device__ inline void lane_block(const uint32_t *win, const uint32_t tw[8], uint32_t (&Pv)[NW],
+                                  uint32_t (&Mv)[NW], uint32_t &Zt) {
+    const uint8_t *w8 = (const uint8_t *)win;
+    uint32_t cur[NW + 1], nxt[NW + 1];
+    {
+        const uint32_t *src = (const uint32_t *)(w8 + __umul24(tw[0] & 0xFFu, 4u * (NW + 1)));
+#pragma unroll
+        for (int w = 0; w <= NW; w++) cur[w] = src[w];
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < 32; s++) {
+        if (s < 31) {
+            const uint32_t c = (tw[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 0xFFu;
+            const uint32_t *src = (const uint32_t *)(w8 + __umul24(c, 4u * (NW + 1)));
+#pragma unroll
+            for (int w = 0; w <= NW; w++) nxt[w] = src[w];
+        }
+        uint32_t Xv[NW + 1], Ph[NW], Mh[NW];
+        uint64_t cy = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const uint32_t eq = s == 0 ? cur[w] : __builtin_amdgcn_alignbit(cur[w + 1], cur[w], s);
+            Xv[w] = eq | Mv[w];
+            uint32_t sum;
+            if (NW == 1)
+                sum = (eq & Pv[w]) + Pv[w];
+            else if (w == 0)
+                sum = add_carry_mask(eq & Pv[w], Pv[w], cy);
+            else
+                sum = add_carry_chain(eq & Pv[w], Pv[w], cy, cy);
+            const uint32_t Xh = (sum ^ Pv[w]) | eq;
+            Ph[w] = Mv[w] | ~(Xh | Pv[w]);
+            Mh[w] = Pv[w] & Xh;
+        }
+        Xv[NW] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const uint32_t Xv1 = __builtin_amdgcn_alignbit(Xv[w + 1], Xv[w], 1);
+            if (w == 0) Zt = popc_acc((Xv1 | Mh[0]) & 1u, Zt);
+            Pv[w] = Mh[w] | ~(Xv1 | Ph[w]);
+            Mv[w] = Ph[w] & Xv1;
+        }
+        // the state is materialised every column: left free, the compiler
+        // re-associates the bit operations across columns and keeps every
+        // column's intermediates alive to the end of the block
+#pragma unroll
+        for (int w = 0; w < NW; w++) asm volatile("" : "+v"(Pv[w]), "+v"(Mv[w]));
+#pragma unroll
+        for (int w = 0; w <= NW; w++) cur[w] = nxt[w];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__device__ inline uint32_t readlane_u32(uint32_t x, uint32_t L) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)L);
+}
+
+template <int NW, int SIGMAX>
+__global__ void __launch_bounds__(64)
+    k_verify_lane(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
+                  const uint32_t *__restrict__ order, uint32_t K, const uint32_t *__restrict__ Kq,
+                  uint32_t sigma, uint32_t region, uint32_t *__restrict__ next,
+                  int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
+    constexpr uint32_t RS = NW + 1;  // words per symbol row of a window
+    extern __shared__ uint32_t lds[];
+    const uint32_t lane = threadIdx.x;
+    uint32_t *win = lds + lane * region;
+#pragma unroll
+    for (uint32_t w = 0; w < RS; w++) win[sigma * RS + w] = 0xFFFFFFFFu;
+
+    PairView v = view_pair(A, B, pairs, Kq, K, 0, false);
+    uint32_t pidx = 0, jb = 0, Zt = 0, kstar = 0;
+    uint32_t Pv[NW], Mv[NW], tw[8];
+#pragma unroll
+    for (int w = 0; w < NW; w++) Pv[w] = Mv[w] = 0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) tw[q] = 0;
+    bool has = false;     // holds an undecided pair
+    bool drained = false; // the counter has passed `count` for this lane
+
+    for (;;) {
+        // ---- lanes without a pair take the next ones; pairs decided without
+        //      any column (length gap above the threshold, empty text) are
+        //      written at once
+        bool fresh = false;
+        for (;;) {
+            const bool need = !has && !drained;
+            const uint64_t nm = __builtin_amdgcn_ballot_w64(need);
+            if (nm == 0) break;
+            const uint32_t leader = (uint32_t)__builtin_ctzll(nm);
+            uint32_t got = 0;
+            if (lane == leader) got = atomicAdd(next, (uint32_t)__popcll(nm));
+            got = readlane_u32(got, leader);
+            if (need) {
+                const uint32_t k = got + (uint32_t)__popcll(nm & ((1ull << lane) - 1ull));
+                if (k >= count) {
+                    drained = true;
+                } else {
+                    pidx = order ? order[k] : k;
+                    v = view_pair(A, B, pairs, Kq, K, pidx, true);
+                    if (v.skip || v.nn == 0) {
+                        dist[pidx] = (int32_t)(v.skip ? v.Kp + 1 : min(v.dstar, v.Kp + 1));
+                    } else {
+                        has = true;
+                        fresh = true;
+                        jb = 0;
+                        Zt = 0;
+                        kstar = v.O + v.dstar;
+                        lane_state_init<NW>(v.O, Pv, Mv);
+                        lane_text_block(v.yp, v.nn, 0, sigma, tw);
+                    }
+                }
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(has) == 0) break;
+        // ---- the windows of the pairs just taken, filled by the whole wave
+        uint64_t fm = __builtin_amdgcn_ballot_w64(fresh);
+        while (fm) {
+            const uint32_t L = (uint32_t)__builtin_ctzll(fm);
+            fm &= fm - 1;
+            PairView u = v;
+            const uint64_t mp = (uint64_t)(uintptr_t)v.mw;
+            u.mw = (const uint32_t *)(uintptr_t)(((uint64_t)readlane_u32((uint32_t)(mp >> 32), L)
+                                                  << 32) |
+                                                 readlane_u32((uint32_t)mp, L));
+            u.W = readlane_u32(v.W, L);
+            u.O = readlane_u32(v.O, L);
+            uint32_t *wl = lds + L * region;
+            for (uint32_t t = lane; t < sigma * RS; t += 64) {
+                const uint32_t c = t / RS, w = t - c * RS;
+                wl[c * RS + w] = mask_word(u, c, w);
+            }
+        }
+        // other lanes wrote these windows: the barrier orders their writes
+        // before the owners' reads
+        __syncthreads();
+
+        // ---- one block of 32 columns; the next block's text and entering
+        //      mask words are fetched first
+        uint32_t tn[8];
+        lane_text_block(v.yp, has ? v.nn : 0u, jb + 32, sigma, tn);
+        const uint32_t wn = (jb >> 5) + RS;
+        uint32_t nwd[SIGMAX];
+#pragma unroll
+        for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
+            nwd[c] = (has && c < sigma) ? mask_word(v, c, wn) : 0u;
+        lane_block<NW>(win, tw, Pv, Mv, Zt);
+#pragma unroll
+        for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++) {
+            if (c < sigma) {
+                uint32_t *row = win + c * RS;
+                uint32_t t[RS];
+#pragma unroll
+                for (uint32_t w = 1; w < RS; w++) t[w] = row[w];
+#pragma unroll
+                for (uint32_t w = 1; w < RS; w++) row[w - 1] = t[w];
+                row[NW] = nwd[c];
+            }
+        }
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        jb += 32;
+#pragma unroll
+        for (int q = 0; q < 8; q++) tw[q] = tn[q];
+
+        // ---- decisions: the value on d* is the top value plus the vertical
+        //      deltas of bits 1..k*
+        if (has) {
+            uint32_t P = 0, M = 0;
+#pragma unroll
+            for (int w = 0; w < NW; w++) {
+                const int d = (int)kstar - 32 * w;
+                uint32_t mk = d >= 31 ? 0xFFFFFFFFu : (d < 0 ? 0u : (2u << d) - 1u);
+                if (w == 0) mk &= ~1u;
+                P = popc_acc(Pv[w] & mk, P);
+                M = popc_acc(Mv[w] & mk, M);
+            }
+            const uint32_t Vd = v.O + jb - Zt + P - M;
+            if (Vd > v.Kp || jb >= v.nn) {
+                dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
+                if (columns) atomicAdd(columns, (unsigned long long)min(jb, v.nn));
+                has = false;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split form: KL lanes per pair (KL = 2, 4, 8 or 16, one DPP row at most),
+// each holding WPL consecutive words of the band in registers.  Inside a lane
+// the addition is an add-with-carry chain and the shift a funnel shift; only
+// the lane boundaries need the carry-lookahead (two ballots and scalar
+// arithmetic, then the carry-in rippled through the lane's words) and one DPP
+// move for the shift.  The lane form's windows, padding symbol, top-diagonal
+// count and pair counter carry over, with one window per pair that its KL
+// lanes share.  Compared with one pair per lane, a pair's columns take KL
+// times fewer steps one after the other, which matters when there are few
+// pairs per lane of the grid and they differ much in length.
+
+// s = a + (bit `lane` of cin); carry-outs of every lane in cout.
+__device__ inline uint32_t add_carry_ripple(uint32_t a, uint64_t cin, uint64_t &cout) {
+    uint32_t s;
+    asm("v_addc_co_u32 %0, %1, %2, 0, %3" : "=v"(s), "=s"(cout) : "v"(a), "s"(cin));
+    return s;
+}
+
+template <int WPL>
+__device__ inline void split_block(const uint32_t *wl, uint32_t rs4, const uint32_t tw[8],
+                                   uint32_t (&Pv)[WPL], uint32_t (&Mv)[WPL], uint32_t &Zt,
+                                   uint64_t notlast, uint32_t keep) {
+    const uint8_t *w8 = (const uint8_t *)wl;
+    uint32_t cur[WPL + 1], nxt[WPL + 1];
+    {
+        const uint32_t *src = (const uint32_t *)(w8 + __umul24(tw[0] & 0xFFu, rs4));
+#pragma unroll
+        for (int w = 0; w <= WPL; w++) cur[w] = src[w];
+    }
+#pragma unroll
+    for (uint32_t s = 0; s < 32; s++) {
+        if (s < 31) {
+            const uint32_t c = (tw[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 0xFFu;
+            const uint32_t *src = (const uint32_t *)(w8 + __umul24(c, rs4));
+#pragma unroll
+            for (int w = 0; w <= WPL; w++) nxt[w] = src[w];
+        }
+        uint32_t eq[WPL], sum[WPL], Xv[WPL + 1], Ph[WPL], Mh[WPL];
+        uint64_t cy = 0;
+        uint32_t all = 0xFFFFFFFFu;
+#pragma unroll
+        for (int w = 0; w < WPL; w++) {
+            eq[w] = s == 0 ? cur[w] : __builtin_amdgcn_alignbit(cur[w + 1], cur[w], s);
+            Xv[w] = eq[w] | Mv[w];
+            if (w == 0)
+                sum[w] = add_carry_mask(eq[w] & Pv[w], Pv[w], cy);
+            else
+                sum[w] = add_carry_chain(eq[w] & Pv[w], Pv[w], cy, cy);
+            all &= sum[w];
+        }
+        // carries across the pair's lanes: G = carry out of the lane, P = the
+        // lane's words are all ones (a carry in passes through)
+        uint64_t G = cy & notlast;
+        uint64_t P = __builtin_amdgcn_ballot_w64(all == 0xFFFFFFFFu) & notlast;
+        const uint64_t cin = ((G | P) + G) ^ P;
+        uint64_t rc = cin;
+#pragma unroll
+        for (int w = 0; w < WPL; w++) sum[w] = add_carry_ripple(sum[w], rc, rc);
+#pragma unroll
+        for (int w = 0; w < WPL; w++) {
+            const uint32_t Xh = (sum[w] ^ Pv[w]) | eq[w];
+            Ph[w] = Mv[w] | ~(Xh | Pv[w]);
+            Mh[w] = Pv[w] & Xh;
+        }
+        // word 0 of the next lane of the pair (row_shl:1; zero above the band)
+        Xv[WPL] = (uint32_t)__builtin_amdgcn_mov_dpp((int)Xv[0], 0x101, 0xf, 0xf, true) & keep;
+#pragma unroll
+        for (int w = 0; w < WPL; w++) {
+            const uint32_t Xv1 = __builtin_amdgcn_alignbit(Xv[w + 1], Xv[w], 1);
+            if (w == 0) Zt = popc_acc((Xv1 | Mh[0]) & 1u, Zt);
+            Pv[w] = Mh[w] | ~(Xv1 | Ph[w]);
+            Mv[w] = Ph[w] & Xv1;
+        }
+#pragma unroll
+        for (int w = 0; w < WPL; w++) asm volatile("" : "+v"(Pv[w]), "+v"(Mv[w]));
+#pragma unroll
+        for (int w = 0; w <= WPL; w++) cur[w] = nxt[w];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int WPL, int SIGMAX>
+__global__ void __launch_bounds__(64)
+    k_verify_split(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
+                   const uint32_t *__restrict__ order, uint32_t K,
+                   const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t KL,
+                   uint32_t region, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
+                   unsigned long long *__restrict__ columns) {
+    extern __shared__ uint32_t lds[];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t tile = lane / KL, l = lane - tile * KL;
+    const uint32_t head = tile * KL;  // lane 0 of the tile
+    const uint32_t NW = WPL * KL;     // band words of a pair
+    const uint32_t RS = NW + 1;       // words per symbol row of a window
+    uint32_t *win = lds + tile * region;
+    uint64_t last = 0;
+    for (uint32_t q = 0; q < 64; q++)
+        if (q % KL == KL - 1) last |= 1ull << q;
+    const uint64_t notlast = ~last;
+    const uint32_t keep = l == KL - 1 ? 0u : 0xFFFFFFFFu;
+    for (uint32_t w = l; w < RS; w += KL) win[sigma * RS + w] = 0xFFFFFFFFu;
+
+    PairView v = view_pair(A, B, pairs, Kq, K, 0, false);
+    uint32_t pidx = 0, jb = 0, Zt = 0, kstar = 0;
+    uint32_t Pv[WPL], Mv[WPL], tw[8];
+#pragma unroll
+    for (int w = 0; w < WPL; w++) Pv[w] = Mv[w] = 0;
+#pragma unroll
+    for (int q = 0; q < 8; q++) tw[q] = 0;
+    bool has = false, drained = false;  // per tile, equal in its lanes
+
+    for (;;) {
+        // ---- tiles without a pair take the next ones (lane 0 of the tile
+        //      asks, the tile learns the index by shuffle)
+        bool fresh = false;
+        for (;;) {
+            const bool need = !has && !drained;
+            const uint64_t nm = __builtin_amdgcn_ballot_w64(need && l == 0);
+            if (nm == 0) break;
+            const uint32_t leader = (uint32_t)__builtin_ctzll(nm);
+            uint32_t got = 0;
+            if (lane == leader) got = atomicAdd(next, (uint32_t)__popcll(nm));
+            got = readlane_u32(got, leader);
+            uint32_t k = got + (uint32_t)__popcll(nm & ((1ull << lane) - 1ull));
+            k = (uint32_t)__shfl((int)k, (int)head, 64);
+            if (need) {
+                if (k >= count) {
+                    drained = true;
+                } else {
+                    pidx = order ? order[k] : k;
+                    v = view_pair(A, B, pairs, Kq, K, pidx, true);
+                    if (v.skip || v.nn == 0) {
+                        if (l == 0)
+                            dist[pidx] = (int32_t)(v.skip ? v.Kp + 1 : min(v.dstar, v.Kp + 1));
+                    } else {
+                        has = true;
+                        fresh = true;
+                        jb = 0;
+                        Zt = 0;
+                        kstar = v.O + v.dstar;
+                        // D[i][0] = |i|: bit k holds row k - O, rows <= 0 have delta -1
+#pragma unroll
+                        for (int w = 0; w < WPL; w++) {
+                            const int d = (int)v.O - 32 * (int)(l * WPL + w);
+                            const uint32_t mv =
+                                d >= 31 ? 0xFFFFFFFFu : (d < 0 ? 0u : (2u << d) - 1u);
+                            Mv[w] = mv;
+                            Pv[w] = ~mv;
+                        }
+                        lane_text_block(v.yp, v.nn, 0, sigma, tw);
+                    }
+                }
+            }
+        }
+        if (__builtin_amdgcn_ballot_w64(has) == 0) break;
+        // ---- the windows of the pairs just taken, filled by the whole wave
+        uint64_t fm = __builtin_amdgcn_ballot_w64(fresh && l == 0);
+        while (fm) {
+            const uint32_t L = (uint32_t)__builtin_ctzll(fm);
+            fm &= fm - 1;
+            PairView u = v;
+            const uint64_t mp = (uint64_t)(uintptr_t)v.mw;
+            u.mw = (const uint32_t *)(uintptr_t)(((uint64_t)readlane_u32((uint32_t)(mp >> 32), L)
+                                                  << 32) |
+                                                 readlane_u32((uint32_t)mp, L));
+            u.W = readlane_u32(v.W, L);
+            u.O = readlane_u32(v.O, L);
+            uint32_t *wt = lds + (L / KL) * region;
+            for (uint32_t t = lane; t < sigma * RS; t += 64) {
+                const uint32_t c = t / RS, w = t - c * RS;
+                wt[c * RS + w] = mask_word(u, c, w);
+            }
+        }
+        __syncthreads();
+
+        // ---- one block of 32 columns; the next block's text and entering
+        //      mask words (symbol c by lane c mod KL) are fetched first
+        uint32_t tn[8];
+        lane_text_block(v.yp, has ? v.nn : 0u, jb + 32, sigma, tn);
+        const uint32_t wn = (jb >> 5) + RS;
+        uint32_t nwd[SIGMAX];
+#pragma unroll
+        for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
+            nwd[c] = (has && c < sigma && c % KL == l) ? mask_word(v, c, wn) : 0u;
+        split_block<WPL>(win + l * WPL, 4 * RS, tw, Pv, Mv, Zt, notlast, keep);
+        // shift the window down one word: every lane moves its own words,
+        // reading all before any lane writes
+        uint32_t mv[SIGMAX][WPL];
+#pragma unroll
+        for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
+#pragma unroll
+            for (uint32_t w = 0; w < (uint32_t)WPL; w++)
+                mv[c][w] = c < sigma ? win[c * RS + l * WPL + w + 1] : 0u;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++) {
+            if (c < sigma) {
+#pragma unroll
+                for (uint32_t w = 0; w < (uint32_t)WPL; w++) win[c * RS + l * WPL + w] = mv[c][w];
+                if (c % KL == l) win[c * RS + NW] = nwd[c];
+            }
+        }
+        __syncthreads();
+        jb += 32;
+#pragma unroll
+        for (int q = 0; q < 8; q++) tw[q] = tn[q];
+
+        // ---- decisions: the value on d* is the top value (lane 0 of the
+        //      tile) plus the vertical deltas of bits 1..k* (all lanes)
+        int32_t D = 0;
+#pragma unroll
+        for (int w = 0; w < WPL; w++) {
+            const int d = (int)kstar - 32 * (int)(l * WPL + w);
+            uint32_t mk = d >= 31 ? 0xFFFFFFFFu : (d < 0 ? 0u : (2u << d) - 1u);
+            if (w == 0 && l == 0) mk &= ~1u;
+            D += __builtin_popcount(Pv[w] & mk) - __builtin_popcount(Mv[w] & mk);
+        }
+        for (uint32_t o = 1; o < KL; o <<= 1) D += __shfl_xor(D, (int)o, 64);
+        const uint32_t Z0 = (uint32_t)__shfl((int)Zt, (int)head, 64);
+        if (has) {
+            const uint32_t Vd = (uint32_t)((int32_t)(v.O + jb - Z0) + D);
+            if (Vd > v.Kp || jb >= v.nn) {
+                if (l == 0) {
+                    dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
+                    if (columns) atomicAdd(columns, (unsigned long long)min(jb, v.nn));
+                }
+                has = false;
+            }
+        }
+    }
+}
+
 // Mask words of every string: sigma * ceil(len / 32).
 __global__ void k_mask_sizes(const uint64_t *__restrict__ off, uint32_t n, uint32_t sigma,
                              uint64_t *__restrict__ sz) {
@@ -620,6 +1103,64 @@ __global__ void k_alive_list(const uint32_t *__restrict__ flags, const uint32_t 
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < count;
          e += (uint64_t)gridDim.x * blockDim.x)
         if (flags[e]) list[pos[e]] = (uint32_t)e;
+}
+
+// Lane form limits: bands of up to 16 words (K <= 510) in registers, and
+// alphabets of up to 4 symbols (the windows of 64 lanes stay within LDS at a
+// few waves per CU).
+constexpr uint32_t LANE_MAX_WORDS = 16;
+constexpr uint32_t LANE_MAX_SIGMA = 4;
+
+using LaneKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint32_t *,
+                            uint32_t, const uint32_t *, uint32_t, uint32_t, uint32_t *, int32_t *,
+                            unsigned long long *);
+
+LaneKernel lane_kernel(uint32_t nw) {
+    switch (nw) {
+        case 1: return k_verify_lane<1, LANE_MAX_SIGMA>;
+        case 2: return k_verify_lane<2, LANE_MAX_SIGMA>;
+        case 3: return k_verify_lane<3, LANE_MAX_SIGMA>;
+        case 4: return k_verify_lane<4, LANE_MAX_SIGMA>;
+        case 5: return k_verify_lane<5, LANE_MAX_SIGMA>;
+        case 6: return k_verify_lane<6, LANE_MAX_SIGMA>;
+        case 7: return k_verify_lane<7, LANE_MAX_SIGMA>;
+        case 8: return k_verify_lane<8, LANE_MAX_SIGMA>;
+        case 9: return k_verify_lane<9, LANE_MAX_SIGMA>;
+        case 10: return k_verify_lane<10, LANE_MAX_SIGMA>;
+        case 11: return k_verify_lane<11, LANE_MAX_SIGMA>;
+        case 12: return k_verify_lane<12, LANE_MAX_SIGMA>;
+        case 13: return k_verify_lane<13, LANE_MAX_SIGMA>;
+        case 14: return k_verify_lane<14, LANE_MAX_SIGMA>;
+        case 15: return k_verify_lane<15, LANE_MAX_SIGMA>;
+        case 16: return k_verify_lane<16, LANE_MAX_SIGMA>;
+        default: return nullptr;
+    }
+}
+
+using SplitKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint32_t *,
+                             uint32_t, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *,
+                             int32_t *, unsigned long long *);
+constexpr uint32_t SPLIT_MAX_WPL = 8;
+
+SplitKernel split_kernel(uint32_t wpl) {
+    switch (wpl) {
+        case 1: return k_verify_split<1, LANE_MAX_SIGMA>;
+        case 2: return k_verify_split<2, LANE_MAX_SIGMA>;
+        case 3: return k_verify_split<3, LANE_MAX_SIGMA>;
+        case 4: return k_verify_split<4, LANE_MAX_SIGMA>;
+        case 5: return k_verify_split<5, LANE_MAX_SIGMA>;
+        case 6: return k_verify_split<6, LANE_MAX_SIGMA>;
+        case 7: return k_verify_split<7, LANE_MAX_SIGMA>;
+        case 8: return k_verify_split<8, LANE_MAX_SIGMA>;
+        default: return nullptr;
+    }
+}
+
+// Words per lane window: (sigma + 1) rows of NW + 1 words, padded to an odd
+// count so that the 64 lanes' windows start in distinct LDS banks.
+inline uint32_t lane_region(uint32_t nw, uint32_t sigma) {
+    const uint32_t r = (sigma + 1) * (nw + 1);
+    return r | 1u;
 }
 
 inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
@@ -723,8 +1264,59 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     auto kmark = [&]() {
         if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
     };
-    if (ctx->tune.verify_mode == 1) {
+    // the lane family: KL lanes per pair (1: the whole band in one lane)
+    uint32_t KL = ctx->tune.verify_split;
+    if (KL == 0) KL = NL <= 4 ? 1u : NL <= 8 ? 2u : 4u;
+    while (KL > 1 && KL / 2 >= NL) KL /= 2;  // no lane without a word of the band
+    const uint32_t WPL = (NL + KL - 1) / KL;
+    const uint32_t NWf = KL * WPL;
+    const bool lane_ok = KL == 1 ? NL <= LANE_MAX_WORDS : WPL <= SPLIT_MAX_WPL;
+    if (ctx->tune.verify_mode == 2 && lane_ok && sig <= LANE_MAX_SIGMA &&
+        (int)((64 / KL) * lane_region(NWf, sig) * 4) <= ctx->lds_max) {
+        // lane form: KL lanes per pair, a device-wide pair counter
+        ctx->last_verify_form = 2;
+        const void *kf = KL == 1 ? (const void *)lane_kernel(NWf) : (const void *)split_kernel(WPL);
+        const uint32_t region = lane_region(NWf, sig);
+        const size_t llds = (size_t)(64 / KL) * region * 4;
+        if (llds > 65536)
+            EJ_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds));
+        int occ = 0;
+        EJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kf, 64, llds));
+        if (occ < 1) occ = 1;
+        const uint32_t per_cu = std::max(1u, std::min((uint32_t)occ, ctx->tune.verify_blocks_per_cu));
+        const uint64_t grid =
+            std::min<uint64_t>((count * KL + 63) / 64, (uint64_t)ctx->num_cu * per_cu);
+        uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
+        char key[512];
+        snprintf(key, sizeof(key),
+                 "verify_lane %u %u %p %p %llu %p %p %p %p %llu %p %p %p %u %p %u %p %u %u %p %p "
+                 "%p %llu %zu",
+                 NWf, KL, (const void *)d_codes, (const void *)d_offsets, (unsigned long long)base,
+                 (const void *)A.mw, (const void *)A.moff, (const void *)d_codes_b,
+                 (const void *)d_offsets_b, (unsigned long long)base_b, (const void *)B.mw,
+                 (const void *)B.moff, (const void *)d_pairs, (unsigned)count,
+                 (const void *)d_order, K, (const void *)d_Kq, sig, region, (void *)next,
+                 (void *)d_dist, (void *)d_columns, (unsigned long long)grid, llds);
+        kmark();
+        run_captured(ctx, key, [&] {
+            hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
+            EJ_CHECK_LAUNCH();
+            if (KL == 1)
+                hipLaunchKernelGGL(lane_kernel(NWf), dim3((uint32_t)grid), dim3(64), llds,
+                                   ctx->stream, A, B, d_pairs, (uint32_t)count, d_order, K, d_Kq,
+                                   sig, region, next, d_dist, d_columns);
+            else
+                hipLaunchKernelGGL(split_kernel(WPL), dim3((uint32_t)grid), dim3(64), llds,
+                                   ctx->stream, A, B, d_pairs, (uint32_t)count, d_order, K, d_Kq,
+                                   sig, KL, region, next, d_dist, d_columns);
+            EJ_CHECK_LAUNCH();
+        });
+        kmark();
+        return;
+    }
+    if (ctx->tune.verify_mode >= 1) {
         // persistent form: one resident grid, a device-wide pair counter
+        ctx->last_verify_form = 1;
         auto qkern = mode == LANES_ONE    ? k_verify_queue<LANES_ONE, false>
                      : mode == LANES_ROW  ? (ring ? k_verify_queue<LANES_ROW, true>
                                                   : k_verify_queue<LANES_ROW, false>)
@@ -764,6 +1356,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         kmark();
         return;
     }
+    ctx->last_verify_form = 0;
     const uint32_t C1 = ctx->tune.verify_pass1_cols & ~31u;
     const bool two_pass = C1 > 0 && C1 < mtext;
     uint32_t *state = nullptr, *aux = nullptr;

@@ -78,7 +78,7 @@ def _check_workload(ej, ctx, oracle_lib, col, K, r, z, m, L, seed=0):
         _say(f"autotune n={n} K={K} r={r} z={z} m={m} L={L}")
         ctx.autotune(chars, offs, K, r, z, m, seed=seed, L=L, reps=1)
         knobs = ctx.knobs()
-        flags = ej.FLAG_GRAPH if knobs["verify_mode"] == 1 else 0
+        flags = ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0
         _say(f"join knobs={knobs}")
         res = ctx.join(chars, offs, K, r, z, m, seed=seed, L=L, flags=flags)
         # the same candidates through the stage entry points

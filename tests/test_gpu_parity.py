@@ -35,10 +35,11 @@ def ctx(ej):
 
 
 def _each_verify_mode(ctx):
-    """Runs the body once per verification form (two-pass, persistent)."""
+    """Runs the body once per verification form (two-pass, persistent tiles,
+    one pair per lane)."""
     old = ctx.tune_get("verify_mode")
     try:
-        for mode in (0, 1):
+        for mode in (0, 1, 2):
             ctx.tune_set("verify_mode", mode)
             yield mode
     finally:
@@ -215,7 +216,8 @@ def test_verify_long_strings_random_and_similar(ej, ctx, oracle_lib):
 @pytest.mark.parametrize("K", [40, 100, 254, 300, 500, 700, 1000, 2046])
 def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
     """Whole-pattern and ring layouts of the match masks, with one and two
-    passes, give the oracle's distances (bands of 2 to 64 lanes)."""
+    passes, and the lane form at every split width give the oracle's
+    distances (bands of 2 to 64 words)."""
     import torch
     rng = np.random.default_rng(K + 7)
     col = sd.clusters(300 + K, 8, lambda rr, b: 4, lambda rr: rr.integers(K // 2, 2 * K + 400),
@@ -228,7 +230,7 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
     chars, offs = to_device(col)
     d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
     old = (ctx.tune_get("verify_ring"), ctx.tune_get("verify_pass1_cols"),
-           ctx.tune_get("verify_mode"))
+           ctx.tune_get("verify_mode"), ctx.tune_get("verify_split"))
     try:
         for ring in (0, 2):
             for mode, c1 in ((0, 0), (0, 64), (0, 1024), (1, 0)):
@@ -238,10 +240,17 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
                 _say(f"verify layout K={K} ring={ring} mode={mode} c1={c1}")
                 got = ctx.verify(chars, offs, d_codes, K)
                 assert got.cpu().numpy().astype(np.uint32).tolist() == want
+        ctx.tune_set("verify_mode", 2)
+        for split in (0, 1, 2, 4, 8, 16):
+            ctx.tune_set("verify_split", split)
+            _say(f"verify lane form K={K} split={split}")
+            got = ctx.verify(chars, offs, d_codes, K)
+            assert got.cpu().numpy().astype(np.uint32).tolist() == want
     finally:
         ctx.tune_set("verify_ring", old[0])
         ctx.tune_set("verify_pass1_cols", old[1])
         ctx.tune_set("verify_mode", old[2])
+        ctx.tune_set("verify_split", old[3])
 
 
 # ------------------------------------------------------------ edge cases ----
@@ -352,16 +361,20 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
              ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
              ("verify_ring", 2), ("verify_mode", 1)]
-    # the persistent form with and without the multiplicity order
-    ctx.tune_set("verify_mode", 1)
+    # the persistent forms with and without the multiplicity order
     try:
-        for order in (0, 1):
-            ctx.tune_set("verify_order", order)
-            _say(f"persistent verification order={order}")
-            _assert_join_equal(ctx.join(col.chars, col.offsets, K, r, z, m, seed=5, L=L), ref)
+        for mode, split in ((1, 0), (2, 0), (2, 1), (2, 4)):
+            ctx.tune_set("verify_mode", mode)
+            ctx.tune_set("verify_split", split)
+            for order in (0, 1):
+                ctx.tune_set("verify_order", order)
+                _say(f"persistent verification mode={mode} split={split} order={order}")
+                _assert_join_equal(ctx.join(col.chars, col.offsets, K, r, z, m, seed=5, L=L),
+                                   ref)
     finally:
         ctx.tune_set("verify_mode", 0)
         ctx.tune_set("verify_order", 1)
+        ctx.tune_set("verify_split", 0)
     for name, val in knobs:
         old = ctx.tune_get(name)
         try:
@@ -373,6 +386,8 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
             ctx.tune_set(name, old)
     with pytest.raises(ej.EmbedJoinError):
         ctx.tune_set("radix_bits", 3)
+    with pytest.raises(ej.EmbedJoinError):
+        ctx.tune_set("verify_split", 3)
     with pytest.raises(ej.EmbedJoinError):
         ctx.tune_set("no_such_knob", 1)
 
@@ -390,7 +405,7 @@ def test_autotune_keeps_results(ej, ctx, oracle_lib):
         _say("autotune")
         best, knobs = ctx.autotune(chars, offs, K, r, z, m, seed=8, L=L, reps=1)
         assert best > 0
-        assert knobs["verify_mode"] in (0, 1) and 4 <= knobs["radix_bits"] <= 11
+        assert knobs["verify_mode"] in (0, 1, 2) and 4 <= knobs["radix_bits"] <= 11
         res = ctx.join(chars, offs, K, r, z, m, seed=8, L=L)
         _assert_join_equal(res, ref)
     finally:
@@ -399,32 +414,33 @@ def test_autotune_keeps_results(ej, ctx, oracle_lib):
 
 
 def test_graph_replays_match_eager(ej, ctx, oracle_lib):
-    """Persistent verification captured into a HIP graph: the first join
-    captures, later joins of the same shape replay it, with eager joins and
-    synchronisations in between; every replay equals the oracle."""
+    """Persistent verification (both forms) captured into a HIP graph: the
+    first join captures, later joins of the same shape replay it, with eager
+    joins and synchronisations in between; every replay equals the oracle."""
     import torch
     col = sd.clusters(41, 40, lambda rr, b: 4, lambda rr: rr.integers(150, 600),
                       lambda rr, LL: rr.poisson(10))
     K, r, z, m, L = 50, 4, 6, 4, 48
     ref = _oracle_join(oracle_lib, col, K, r, z, m, 4, L)
     chars, offs = to_device(col)
+    col2 = sd.clusters(42, 20, lambda rr, b: 3, lambda rr: rr.integers(100, 300),
+                       lambda rr, LL: rr.poisson(5))
+    ref2 = _oracle_join(oracle_lib, col2, 20, r, z, m, 4, L)
     old = ctx.tune_get("verify_mode")
     try:
-        ctx.tune_set("verify_mode", 1)
-        for i in range(4):
-            _say(f"graph replay {i}")
-            res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
-            _assert_join_equal(res, ref)
-            eager = ctx.join(chars, offs, K, r, z, m, seed=4, L=L)
-            _assert_join_equal(eager, ref)
-            torch.cuda.synchronize()
-        # a different shape in between, then the first shape again
-        col2 = sd.clusters(42, 20, lambda rr, b: 3, lambda rr: rr.integers(100, 300),
-                           lambda rr, LL: rr.poisson(5))
-        ref2 = _oracle_join(oracle_lib, col2, 20, r, z, m, 4, L)
-        _assert_join_equal(ctx.join(col2.chars, col2.offsets, 20, r, z, m, seed=4, L=L,
-                                     flags=ej.FLAG_GRAPH), ref2)
-        _assert_join_equal(ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH),
-                           ref)
+        for mode in (1, 2):
+            ctx.tune_set("verify_mode", mode)
+            for i in range(4):
+                _say(f"graph replay mode={mode} {i}")
+                res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
+                _assert_join_equal(res, ref)
+                eager = ctx.join(chars, offs, K, r, z, m, seed=4, L=L)
+                _assert_join_equal(eager, ref)
+                torch.cuda.synchronize()
+            # a different shape in between, then the first shape again
+            _assert_join_equal(ctx.join(col2.chars, col2.offsets, 20, r, z, m, seed=4, L=L,
+                                         flags=ej.FLAG_GRAPH), ref2)
+            _assert_join_equal(ctx.join(chars, offs, K, r, z, m, seed=4, L=L,
+                                        flags=ej.FLAG_GRAPH), ref)
     finally:
         ctx.tune_set("verify_mode", old)

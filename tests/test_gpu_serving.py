@@ -65,14 +65,20 @@ def test_index_queries_match_oracle(ej, ctx, oracle_lib):
     _say(f"index build n={col.n}")
     ix = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
     assert ix.size() == col.n
-    for b in range(3):
-        q, Kq = _queries(col, 100 + b, 60, (100, 1000))
-        ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
-                               seed=seed, L=L)
-        _say(f"query batch {b} nq={q.n} expected={len(ref[1])}")
-        res = ix.query(q.chars, q.offsets, Kq)
-        _check(res, *ref)
-        assert res.n_candidates >= len(ref[1])
+    old = ctx.tune_get("verify_mode")
+    try:
+        for b in range(3):
+            q, Kq = _queries(col, 100 + b, 60, (100, 1000))
+            ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
+                                   seed=seed, L=L)
+            for mode in (0, 2):
+                ctx.tune_set("verify_mode", mode)
+                _say(f"query batch {b} nq={q.n} expected={len(ref[1])} mode={mode}")
+                res = ix.query(q.chars, q.offsets, Kq)
+                _check(res, *ref)
+                assert res.n_candidates >= len(ref[1])
+    finally:
+        ctx.tune_set("verify_mode", old)
     ix.close()
 
 
