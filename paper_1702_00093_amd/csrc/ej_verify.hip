@@ -810,24 +810,77 @@ __device__ inline uint32_t add_carry_ripple(uint32_t a, uint64_t cin, uint64_t &
     return s;
 }
 
+// Dwords q0 .. q0+nq-1 (nq <= TQ) of the text of columns jb+1 .. jb+32, the
+// columns past nn set to the match-all symbol `pad`.  Reads stay within
+// y[0 .. nn+35], as for load_text_block.
+template <int TQ>
+__device__ inline void text_part(const uint8_t *y, uint32_t nn, uint32_t jb, uint32_t pad,
+                                 uint32_t q0, uint32_t nq, uint32_t (&out)[TQ]) {
+    const uint32_t fill = pad * 0x01010101u;
+#pragma unroll
+    for (int i = 0; i < TQ; i++) out[i] = fill;
+    if (jb >= nn || q0 >= 8) return;
+    const uintptr_t a = (uintptr_t)(y + jb);
+    const uint32_t *base = (const uint32_t *)(a & ~(uintptr_t)3) + q0;
+    const uint32_t sh = (uint32_t)(a & 3) * 8;
+    uint32_t w[TQ + 1];
+#pragma unroll
+    for (int i = 0; i <= TQ; i++) w[i] = (uint32_t)i <= nq ? base[i] : 0u;
+    const uint32_t r = nn - jb;
+#pragma unroll
+    for (int i = 0; i < TQ; i++) {
+        const uint32_t q = q0 + i;
+        const uint32_t v = r > 4 * q ? r - 4 * q : 0u;
+        const uint32_t keep = v >= 4 ? 0xFFFFFFFFu : ((1u << (8 * v)) - 1u);
+        out[i] = (__builtin_amdgcn_alignbit(w[i + 1], w[i], sh) & keep) | (fill & ~keep);
+    }
+}
+
+// The WPL+1 window words of a lane: its WPL words in as few 16- or 8-byte
+// LDS reads as they allow (rows and lane slices are 16-byte aligned when WPL
+// is a multiple of 4), then the first word of the next lane.
 template <int WPL>
-__device__ inline void split_block(const uint32_t *wl, uint32_t rs4, const uint32_t tw[8],
+__device__ inline void window_words(const uint32_t *src, uint32_t (&o)[WPL + 1]) {
+    if constexpr (WPL % 4 == 0) {
+#pragma unroll
+        for (int i = 0; i < WPL / 4; i++) {
+            const uint4 q = ((const uint4 *)src)[i];
+            o[4 * i] = q.x;
+            o[4 * i + 1] = q.y;
+            o[4 * i + 2] = q.z;
+            o[4 * i + 3] = q.w;
+        }
+    } else if constexpr (WPL % 2 == 0) {
+#pragma unroll
+        for (int i = 0; i < WPL / 2; i++) {
+            const uint2 q = ((const uint2 *)src)[i];
+            o[2 * i] = q.x;
+            o[2 * i + 1] = q.y;
+        }
+    } else {
+#pragma unroll
+        for (int w = 0; w < WPL; w++) o[w] = src[w];
+    }
+    o[WPL] = src[WPL];
+}
+
+// 32 columns of a pair whose band is split over its tile's lanes.  `wl` is
+// the lane's first window word, `txt` the tile's 32 text symbols in LDS.  The
+// symbol of column s+2 and the words of column s+1 are read while column s is
+// computed; a scheduling barrier per column bounds the registers.
+template <int WPL>
+__device__ inline void split_block(const uint32_t *wl, uint32_t rs4, const uint8_t *txt,
                                    uint32_t (&Pv)[WPL], uint32_t (&Mv)[WPL], uint32_t &Zt,
                                    uint64_t notlast, uint32_t keep) {
     const uint8_t *w8 = (const uint8_t *)wl;
     uint32_t cur[WPL + 1], nxt[WPL + 1];
-    {
-        const uint32_t *src = (const uint32_t *)(w8 + __umul24(tw[0] & 0xFFu, rs4));
-#pragma unroll
-        for (int w = 0; w <= WPL; w++) cur[w] = src[w];
-    }
+    window_words<WPL>((const uint32_t *)(w8 + __umul24((uint32_t)txt[0], rs4)), cur);
+    uint32_t cn = txt[1];
 #pragma unroll
     for (uint32_t s = 0; s < 32; s++) {
         if (s < 31) {
-            const uint32_t c = (tw[(s + 1) >> 2] >> (8 * ((s + 1) & 3))) & 0xFFu;
-            const uint32_t *src = (const uint32_t *)(w8 + __umul24(c, rs4));
-#pragma unroll
-            for (int w = 0; w <= WPL; w++) nxt[w] = src[w];
+            window_words<WPL>((const uint32_t *)(w8 + __umul24(cn, rs4)), nxt);
+            if (s < 30) cn = txt[s + 2];
         }
         uint32_t eq[WPL], sum[WPL], Xv[WPL + 1], Ph[WPL], Mh[WPL];
         uint64_t cy = 0;
@@ -873,20 +926,31 @@ __device__ inline void split_block(const uint32_t *wl, uint32_t rs4, const uint3
     }
 }
 
+// Region of one tile: (sigma + 1) symbol rows of RS words (NW + 1 rounded up
+// to a multiple of 4, so that rows start 16-byte aligned), then 8 words of
+// text (the current block's 32 symbols); regions are multiples of 4 words.  Up to 4 words per lane the kernel
+// is held to 80 registers, so that 6 waves share a SIMD: then a medium-sized
+// join's long pairs all find a tile at once instead of some tiles running two
+// of them one after the other.
 template <int WPL, int SIGMAX>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, WPL <= 4 ? 6 : 1)
     k_verify_split(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
                    const uint32_t *__restrict__ order, uint32_t K,
                    const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t KL,
                    uint32_t region, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                    unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    constexpr int TQ = 4;  // text dwords per lane, at most (8 / KL, KL >= 2)
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / KL, l = lane - tile * KL;
     const uint32_t head = tile * KL;  // lane 0 of the tile
     const uint32_t NW = WPL * KL;     // band words of a pair
-    const uint32_t RS = NW + 1;       // words per symbol row of a window
+    const uint32_t RS = (NW + 4) & ~3u;  // words per symbol row of a window
+    const uint32_t nq = KL >= 8 ? 1u : 8u / KL;  // text dwords of this lane
+    const uint32_t q0 = l * nq;                  // (none when q0 >= 8)
     uint32_t *win = lds + tile * region;
+    uint32_t *txtw = win + (sigma + 1) * RS;
+    const uint8_t *txt = (const uint8_t *)txtw;
     uint64_t last = 0;
     for (uint32_t q = 0; q < 64; q++)
         if (q % KL == KL - 1) last |= 1ull << q;
@@ -896,11 +960,9 @@ __global__ void __launch_bounds__(64)
 
     PairView v = view_pair(A, B, pairs, Kq, K, 0, false);
     uint32_t pidx = 0, jb = 0, Zt = 0, kstar = 0;
-    uint32_t Pv[WPL], Mv[WPL], tw[8];
+    uint32_t Pv[WPL], Mv[WPL], tp[TQ];
 #pragma unroll
     for (int w = 0; w < WPL; w++) Pv[w] = Mv[w] = 0;
-#pragma unroll
-    for (int q = 0; q < 8; q++) tw[q] = 0;
     bool has = false, drained = false;  // per tile, equal in its lanes
 
     for (;;) {
@@ -941,7 +1003,10 @@ __global__ void __launch_bounds__(64)
                             Mv[w] = mv;
                             Pv[w] = ~mv;
                         }
-                        lane_text_block(v.yp, v.nn, 0, sigma, tw);
+                        text_part<TQ>(v.yp, v.nn, 0, sigma, q0, nq, tp);
+#pragma unroll
+                        for (int i = 0; i < TQ; i++)
+                            if ((uint32_t)i < nq && q0 + i < 8) txtw[q0 + i] = tp[i];
                     }
                 }
             }
@@ -967,18 +1032,18 @@ __global__ void __launch_bounds__(64)
         }
         __syncthreads();
 
-        // ---- one block of 32 columns; the next block's text and entering
-        //      mask words (symbol c by lane c mod KL) are fetched first
-        uint32_t tn[8];
-        lane_text_block(v.yp, has ? v.nn : 0u, jb + 32, sigma, tn);
-        const uint32_t wn = (jb >> 5) + RS;
+        // ---- one block of 32 columns; this lane's part of the next block's
+        //      text and the entering mask words (symbol c by lane c mod KL)
+        //      are fetched first
+        text_part<TQ>(v.yp, has ? v.nn : 0u, jb + 32, sigma, q0, nq, tp);
+        const uint32_t wn = (jb >> 5) + NW + 1;  // band word entering the window
         uint32_t nwd[SIGMAX];
 #pragma unroll
         for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
             nwd[c] = (has && c < sigma && c % KL == l) ? mask_word(v, c, wn) : 0u;
-        split_block<WPL>(win + l * WPL, 4 * RS, tw, Pv, Mv, Zt, notlast, keep);
+        split_block<WPL>(win + l * WPL, 4 * RS, txt, Pv, Mv, Zt, notlast, keep);
         // shift the window down one word: every lane moves its own words,
-        // reading all before any lane writes
+        // reading all before any lane writes; then the next block's text
         uint32_t mv[SIGMAX][WPL];
 #pragma unroll
         for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
@@ -994,10 +1059,11 @@ __global__ void __launch_bounds__(64)
                 if (c % KL == l) win[c * RS + NW] = nwd[c];
             }
         }
+#pragma unroll
+        for (int i = 0; i < TQ; i++)
+            if ((uint32_t)i < nq && q0 + i < 8) txtw[q0 + i] = tp[i];
         __syncthreads();
         jb += 32;
-#pragma unroll
-        for (int q = 0; q < 8; q++) tw[q] = tn[q];
 
         // ---- decisions: the value on d* is the top value (lane 0 of the
         //      tile) plus the vertical deltas of bits 1..k* (all lanes)
@@ -1272,11 +1338,14 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     const uint32_t NWf = KL * WPL;
     const bool lane_ok = KL == 1 ? NL <= LANE_MAX_WORDS : WPL <= SPLIT_MAX_WPL;
     if (ctx->tune.verify_mode == 2 && lane_ok && sig <= LANE_MAX_SIGMA &&
-        (int)((64 / KL) * lane_region(NWf, sig) * 4) <= ctx->lds_max) {
+        (int)((64 / KL) * ((sig + 1) * (NWf + 4) + 12) * 4) <= ctx->lds_max) {
         // lane form: KL lanes per pair, a device-wide pair counter
         ctx->last_verify_form = 2;
         const void *kf = KL == 1 ? (const void *)lane_kernel(NWf) : (const void *)split_kernel(WPL);
-        const uint32_t region = lane_region(NWf, sig);
+        // split tiles: rows of NW+1 words rounded up to a multiple of 4, then
+        // the text block (8 words)
+        const uint32_t region =
+            KL == 1 ? lane_region(NWf, sig) : ((sig + 1) * ((NWf + 4) & ~3u) + 8 + 3) & ~3u;
         const size_t llds = (size_t)(64 / KL) * region * 4;
         if (llds > 65536)
             EJ_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)llds));
