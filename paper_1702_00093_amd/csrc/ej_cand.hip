@@ -138,6 +138,146 @@ __global__ void k_unique_compact(const C *__restrict__ codes, uint64_t cnt, uint
     }
 }
 
+// Partitioned de-duplication of 32-bit codes.  The raw codes are grouped by
+// their top bits (k_group_count / k_group_place); one workgroup per group then
+// collects the group's distinct codes and their multiplicities in an LDS hash
+// table and ranks them, so that the groups in order and each group's codes in
+// rank order are the distinct codes sorted.  A group with more than DD_UCAP
+// distinct codes sets *overflow and the caller sorts the raw codes instead.
+constexpr uint32_t DD_HCAP = 4096;  // hash slots per group (a power of two)
+constexpr uint32_t DD_UCAP = 1024;  // distinct codes per group handled here
+constexpr uint32_t DD_EMPTY = 0xFFFFFFFFu;  // never a code: a < b < 2^16
+
+__global__ void __launch_bounds__(256)
+    k_dedup_groups(const uint32_t *__restrict__ codes, const uint32_t *__restrict__ gstart,
+                   uint32_t *__restrict__ ucode, uint32_t *__restrict__ umult,
+                   uint32_t *__restrict__ ucount, uint32_t *__restrict__ overflow) {
+    __shared__ uint32_t hk[DD_HCAP], hc[DD_HCAP], lk[DD_UCAP], lc[DD_UCAP];
+    __shared__ uint32_t nuniq, npos, bad;
+    const uint32_t g = blockIdx.x, tid = threadIdx.x;
+    for (uint32_t i = tid; i < DD_HCAP; i += 256) {
+        hk[i] = DD_EMPTY;
+        hc[i] = 0;
+    }
+    if (tid == 0) {
+        nuniq = 0;
+        npos = 0;
+        bad = 0;
+    }
+    __syncthreads();
+    const uint32_t b = gstart[g], e = gstart[g + 1];
+    for (uint32_t i = b + tid; i < e; i += 256) {
+        if (nuniq > DD_UCAP) break;  // this group goes to the fallback anyway
+        const uint32_t c = codes[i];
+        uint32_t h = (c * 0x9E3779B1u) >> 20;  // 12 bits
+        uint32_t probe = 0;
+        for (;;) {
+            const uint32_t old = atomicCAS(&hk[h], DD_EMPTY, c);
+            if (old == DD_EMPTY) atomicAdd(&nuniq, 1u);
+            if (old == DD_EMPTY || old == c) {
+                atomicAdd(&hc[h], 1u);
+                break;
+            }
+            if (++probe >= DD_HCAP) {
+                bad = 1u;
+                break;
+            }
+            h = (h + 1) & (DD_HCAP - 1);
+        }
+    }
+    __syncthreads();
+    const uint32_t u = nuniq;
+    if (u > DD_UCAP || bad) {
+        if (tid == 0) {
+            atomicOr(overflow, 1u);
+            ucount[g] = 0;
+        }
+        return;
+    }
+    for (uint32_t i = tid; i < DD_HCAP; i += 256)
+        if (hk[i] != DD_EMPTY) {
+            const uint32_t j = atomicAdd(&npos, 1u);
+            lk[j] = hk[i];
+            lc[j] = hc[i];
+        }
+    __syncthreads();
+    for (uint32_t i = tid; i < u; i += 256) {
+        const uint32_t c = lk[i];
+        uint32_t r = 0;
+        for (uint32_t j = 0; j < u; j++) r += lk[j] < c ? 1u : 0u;
+        ucode[(uint64_t)g * DD_UCAP + r] = c;
+        umult[(uint64_t)g * DD_UCAP + r] = lc[i];
+    }
+    if (tid == 0) ucount[g] = u;
+}
+
+// Grouping of the raw codes by their top GB bits (GB <= DD_GBITS), not
+// stable: each workgroup counts the groups of its chunk of DD_CHUNK codes in
+// LDS (k_group_count, hist[g * nwg + wg]); after an exclusive scan of the
+// counts it places its codes from LDS cursors (k_group_place).
+constexpr uint32_t DD_GBITS = 11;
+constexpr uint32_t DD_CHUNK = 16384;
+
+__global__ void __launch_bounds__(256)
+    k_group_count(const uint32_t *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
+                  uint32_t *__restrict__ hist) {
+    __shared__ uint32_t cnt[1u << DD_GBITS];
+    const uint32_t wg = blockIdx.x, nwg = gridDim.x;
+    for (uint32_t g = threadIdx.x; g < NG; g += 256) cnt[g] = 0;
+    __syncthreads();
+    const uint32_t b = wg * DD_CHUNK, e = min(n, b + DD_CHUNK);
+    for (uint32_t i = b + threadIdx.x; i < e; i += 256) atomicAdd(&cnt[codes[i] >> shift], 1u);
+    __syncthreads();
+    for (uint32_t g = threadIdx.x; g < NG; g += 256) hist[(uint64_t)g * nwg + wg] = cnt[g];
+}
+
+__global__ void __launch_bounds__(256)
+    k_group_place(const uint32_t *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
+                  const uint32_t *__restrict__ offs, uint32_t *__restrict__ out) {
+    __shared__ uint32_t cur[1u << DD_GBITS];
+    const uint32_t wg = blockIdx.x, nwg = gridDim.x;
+    for (uint32_t g = threadIdx.x; g < NG; g += 256) cur[g] = offs[(uint64_t)g * nwg + wg];
+    __syncthreads();
+    const uint32_t b = wg * DD_CHUNK, e = min(n, b + DD_CHUNK);
+    for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
+        const uint32_t c = codes[i];
+        out[atomicAdd(&cur[c >> shift], 1u)] = c;
+    }
+}
+
+// First position of group g: the scanned count of its first chunk.
+__global__ void k_group_first(const uint32_t *__restrict__ offs, uint32_t nwg, uint32_t NG,
+                              uint32_t n, uint32_t *__restrict__ gstart) {
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g <= NG; g += gridDim.x * blockDim.x)
+        gstart[g] = g < NG ? offs[(uint64_t)g * nwg] : n;
+}
+
+// The groups' distinct codes at their scanned offsets, unpacked to
+// (a << 32 | b); the multiplicities alongside when `mult` is given.
+__global__ void k_dedup_out(const uint32_t *__restrict__ ucode, const uint32_t *__restrict__ umult,
+                            const uint32_t *__restrict__ ucount, const uint32_t *__restrict__ uoff,
+                            uint32_t B, uint64_t *__restrict__ out, uint32_t *__restrict__ mult) {
+    const uint32_t g = blockIdx.x;
+    const uint32_t m = ucount[g], o = uoff[g];
+    const uint32_t mask = (1u << B) - 1u;
+    for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
+        const uint32_t c = ucode[(uint64_t)g * DD_UCAP + i];
+        out[o + i] = ((uint64_t)(c >> B) << 32) | (c & mask);
+        if (mult) mult[o + i] = umult[(uint64_t)g * DD_UCAP + i];
+    }
+}
+
+// Order key of unique pair u from its multiplicity (see k_mult_keys).
+__global__ void k_mult_keys_direct(const uint32_t *__restrict__ mult, uint64_t cnt,
+                                   uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < cnt;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t m = mult[u];
+        key[u] = 0xFFFFu - (m < 0xFFFFu ? m : 0xFFFFu);
+        idx[u] = (uint32_t)u;
+    }
+}
+
 // Sort key of unique pair u: 0xFFFF - (number of raw copies, at most 0xFFFF),
 // so that an ascending sort puts the most frequent pairs first.
 __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, uint64_t raw,
@@ -229,10 +369,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", raw);
     uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", raw);
     uint64_t *d_cnt = ws<uint64_t>(ctx, t + "_ucount", 1);
-    // the packed codes are sorted, then the first of each run of equal codes
-    // kept; 32-bit codes when both indexes fit in 16 bits, which halves the
-    // sort's traffic
-    auto emit_sort_unique = [&](auto *rawbuf, auto *sorted) -> uint64_t {
+    auto emit = [&](auto *rawbuf) {
         using C = std::remove_pointer_t<decltype(rawbuf)>;
         hipLaunchKernelGGL((k_pairs<true, C>), dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
                            ctx->stream, (const uint64_t *)key_s, (const uint32_t *)len_s,
@@ -240,6 +377,11 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                            (const uint32_t *)bk.d_gstart, tot, K, B, (uint64_t *)nullptr,
                            (const uint64_t *)counts, rawbuf);
         EJ_CHECK_LAUNCH();
+    };
+    // sort the packed codes, keep the first of each run of equal codes; the
+    // multiplicity order comes from the runs' first positions
+    auto sort_unique = [&](auto *rawbuf, auto *sorted) -> uint64_t {
+        using C = std::remove_pointer_t<decltype(rawbuf)>;
         if constexpr (sizeof(C) == 4)
             radix_sort_u32(ctx, rawbuf, nullptr, sorted, nullptr, 1, (uint32_t)raw, 2 * B,
                            ctx->tune.radix_bits);
@@ -258,24 +400,86 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                            (const uint32_t *)pos, pairs, first);
         EJ_CHECK_LAUNCH();
         *d_pairs_out = pairs;
+        if (d_order_out && cnt) {
+            uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
+            uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
+            hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)first, cnt, raw, k0, v0);
+            EJ_CHECK_LAUNCH();
+        }
         return cnt;
     };
-    uint64_t cnt;
-    if (2 * B <= 32)
-        cnt = emit_sort_unique(ws<uint32_t>(ctx, t + "_raw32", raw),
-                               ws<uint32_t>(ctx, t + "_raw32_sorted", raw));
-    else
-        cnt = emit_sort_unique(ws<uint64_t>(ctx, t + "_raw", raw),
-                               ws<uint64_t>(ctx, t + "_raw_sorted", raw));
+    uint64_t cnt = 0;
+    bool done = false;
+    if (2 * B <= 32) {
+        // 32-bit codes (both indexes below 2^16): grouped by their top bits in
+        // one pass, de-duplicated per group in LDS (k_dedup_groups)
+        uint32_t *raw32 = ws<uint32_t>(ctx, t + "_raw32", raw);
+        emit(raw32);
+        uint32_t *part = ws<uint32_t>(ctx, t + "_raw32_sorted", raw);
+        const uint32_t GB = std::min(DD_GBITS, 2 * B);
+        const uint32_t NG = 1u << GB;
+        const uint32_t nwg = (uint32_t)((raw + DD_CHUNK - 1) / DD_CHUNK);
+        uint32_t *ghist = ws<uint32_t>(ctx, t + "_dd_hist", (uint64_t)NG * nwg);
+        uint32_t *gst = ws<uint32_t>(ctx, t + "_dd_gstart", NG + 1);
+        hipLaunchKernelGGL(k_group_count, dim3(nwg), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)raw32, (uint32_t)raw, 2 * B - GB, NG, ghist);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, ghist, ghist, (uint64_t)NG * nwg, nullptr);
+        hipLaunchKernelGGL(k_group_place, dim3(nwg), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)raw32, (uint32_t)raw, 2 * B - GB, NG,
+                           (const uint32_t *)ghist, part);
+        EJ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_group_first, dim3((NG + 256) / 256), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)ghist, nwg, NG, (uint32_t)raw, gst);
+        EJ_CHECK_LAUNCH();
+        uint32_t *ucode = ws<uint32_t>(ctx, t + "_dd_code", (uint64_t)NG * DD_UCAP);
+        uint32_t *umult = ws<uint32_t>(ctx, t + "_dd_mult", (uint64_t)NG * DD_UCAP);
+        uint32_t *ucnt = ws<uint32_t>(ctx, t + "_dd_count", NG);
+        uint32_t *uoff = ws<uint32_t>(ctx, t + "_dd_off", NG);
+        uint64_t *info = ws<uint64_t>(ctx, t + "_dd_info", 2);  // distinct codes, overflow
+        EJ_HIP(hipMemsetAsync(info, 0, 16, ctx->stream));
+        hipLaunchKernelGGL(k_dedup_groups, dim3(NG), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)part, (const uint32_t *)gst, ucode, umult, ucnt,
+                           (uint32_t *)(info + 1));
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, ucnt, uoff, NG, info);
+        uint64_t hinfo[2] = {0, 0};
+        read_back(ctx, info, 16, hinfo);
+        if (hinfo[1] == 0) {
+            cnt = hinfo[0];
+            uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
+            uint32_t *mult = d_order_out ? ws<uint32_t>(ctx, t + "_mult", cnt) : nullptr;
+            hipLaunchKernelGGL(k_dedup_out, dim3(NG), dim3(256), 0, ctx->stream,
+                               (const uint32_t *)ucode, (const uint32_t *)umult,
+                               (const uint32_t *)ucnt, (const uint32_t *)uoff, B, pairs, mult);
+            EJ_CHECK_LAUNCH();
+            *d_pairs_out = pairs;
+            if (d_order_out && cnt) {
+                hipLaunchKernelGGL(k_mult_keys_direct, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
+                                   ctx->stream, (const uint32_t *)mult, cnt,
+                                   ws<uint32_t>(ctx, t + "_okey", cnt),
+                                   ws<uint32_t>(ctx, t + "_oidx", cnt));
+                EJ_CHECK_LAUNCH();
+            }
+            done = true;
+        } else {
+            // a group with too many distinct codes: sort them all (raw32 is
+            // intact, the partition wrote `part`)
+            cnt = sort_unique(raw32, part);
+            done = true;
+        }
+    }
+    if (!done) {
+        uint64_t *raw64 = ws<uint64_t>(ctx, t + "_raw", raw);
+        emit(raw64);
+        cnt = sort_unique(raw64, ws<uint64_t>(ctx, t + "_raw_sorted", raw));
+    }
     if (d_order_out && cnt) {
-        const uint32_t *first = ws<uint32_t>(ctx, t + "_first", cnt);
         uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
         uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
         uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", cnt);
         uint32_t *order = ws<uint32_t>(ctx, t + "_order", cnt);
-        hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
-                           first, cnt, raw, k0, v0);
-        EJ_CHECK_LAUNCH();
         radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt, 16, 8);
         *d_order_out = order;
     }

@@ -163,6 +163,7 @@ void radix_sort_u32(ej_ctx *ctx, uint32_t *keys_in, uint32_t *vals_in, uint32_t 
 void radix_sort_u64(ej_ctx *ctx, uint64_t *keys_in, uint64_t *keys_out, uint64_t n,
                     uint32_t key_bits, uint32_t digit_bits);
 
+
 // ------------------------------------------------------------------ stages --
 struct Prep {
     uint32_t n = 0;

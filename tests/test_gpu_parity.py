@@ -253,6 +253,27 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
         ctx.tune_set("verify_split", old[3])
 
 
+def test_candidate_groups_with_many_distinct_pairs(ej, ctx, oracle_lib):
+    """One cluster of 1,100 near-copies among 2,000 strings: the string
+    groups of the 32-bit candidate de-duplication then hold more distinct
+    pairs than the LDS table takes, and the join falls back to sorting all
+    raw pairs; the result is still the oracle's."""
+    rng = np.random.default_rng(77)
+    DNA = np.frombuffer(b"ACGT", dtype=np.uint8)
+    base = DNA[rng.integers(0, 4, size=40)]
+    pieces = [bytes(sd.mutate(rng, base, int(rng.integers(0, 2)), DNA)) for _ in range(1100)]
+    pieces += [bytes(DNA[rng.integers(0, 4, size=int(rng.integers(30, 60)))]) for _ in range(900)]
+    order = rng.permutation(len(pieces))
+    col = sd.from_strings([pieces[i] for i in order])
+    K, r, z, m = 3, 2, 3, 2
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 13, 32)
+    _say(f"dense cluster n={col.n} candidates={len(ref.cand)}")
+    for mode in _each_verify_mode(ctx):
+        res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=13, L=32)
+        _assert_join_equal(res, ref)
+        assert res.n_candidates == len(ref.cand)
+
+
 # ------------------------------------------------------------ edge cases ----
 
 def test_edge_cases(ej, ctx, oracle_lib):
