@@ -34,9 +34,10 @@ MI355X_HBM = 8.0e12
 #    advance the pointer).
 OPS_PER_WORD_STEP = 10
 # the verification kernel of each form (JoinResult.verify_form)
-VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane"}
+VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane", 3: "k_verify_split"}
 VERIFY_FORM = {0: "two-pass", 1: "persistent, replayed from a captured HIP graph",
-               2: "one pair per lane, persistent, replayed from a captured HIP graph"}
+               2: "one pair per lane, persistent, replayed from a captured HIP graph",
+               3: "several band words per lane, persistent, replayed from a captured HIP graph"}
 OPS_PER_WALK_STEP = 3
 
 

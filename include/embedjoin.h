@@ -104,7 +104,8 @@ typedef struct {
     float ms_verify_kernel;
     uint32_t verify_launches;
     /* The verification form that ran: 0 two passes over groups of pairs,
-     * 1 persistent groups of pairs, 2 one pair per lane (see "verify_mode"). */
+     * 1 persistent groups of pairs, 2 one pair per lane, 3 several lanes per
+     * pair with several band words each (2 and 3: "verify_mode" 2). */
     uint32_t verify_form;
 } ej_result;
 

@@ -169,7 +169,7 @@ class JoinResult:
     verify_columns: int = 0
     ms_verify_kernel: float = 0.0
     verify_launches: int = 0
-    verify_form: int = 0       # 0 two-pass, 1 persistent groups, 2 one pair per lane
+    verify_form: int = 0       # 0 two-pass, 1 persistent groups, 2 one pair per lane, 3 split
 
     @property
     def codes(self) -> np.ndarray:

@@ -1340,7 +1340,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     if (ctx->tune.verify_mode == 2 && lane_ok && sig <= LANE_MAX_SIGMA &&
         (int)((64 / KL) * ((sig + 1) * (NWf + 4) + 12) * 4) <= ctx->lds_max) {
         // lane form: KL lanes per pair, a device-wide pair counter
-        ctx->last_verify_form = 2;
+        ctx->last_verify_form = KL == 1 ? 2 : 3;
         const void *kf = KL == 1 ? (const void *)lane_kernel(NWf) : (const void *)split_kernel(WPL);
         // split tiles: rows of NW+1 words rounded up to a multiple of 4, then
         // the text block (8 words)
