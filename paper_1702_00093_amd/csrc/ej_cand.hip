@@ -293,19 +293,30 @@ __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, ui
 
 }  // namespace
 
+uint32_t bucket_key_bits(ej_ctx *ctx, uint32_t n, uint32_t key_bits) {
+    if (key_bits == 0) key_bits = ctx->tune.bucket_key_bits;
+    // enough bits that different keys rarely share a group (the pair scan
+    // compares full keys, so a shared group costs time, never results)
+    if (key_bits == 0) key_bits = std::min(32u, bits_for(n) + 6);
+    return std::min(key_bits, 32u);
+}
+
+void bucket_inputs(ej_ctx *ctx, uint64_t tot, const char *tag, uint32_t **d_dk, uint32_t **d_ids) {
+    if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
+    std::string t(tag);
+    *d_dk = ws<uint32_t>(ctx, t + "_dk", tot);
+    *d_ids = ws<uint32_t>(ctx, t + "_ids0", tot);
+}
+
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
             uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
-            bool want_ngroups) {
+            bool want_ngroups, bool inputs_ready) {
     std::string t(tag);
     bk.T = T;
     bk.n = n;
     uint64_t tot = (uint64_t)T * n;
     if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
-    if (key_bits == 0) key_bits = ctx->tune.bucket_key_bits;
-    // enough bits that different keys rarely share a group (the pair scan
-    // compares full keys, so a shared group costs time, never results)
-    if (key_bits == 0) key_bits = std::min(32u, bits_for(n) + 6);
-    if (key_bits > 32) key_bits = 32;
+    key_bits = bucket_key_bits(ctx, n, key_bits);
     bk.d_ids = ws<uint32_t>(ctx, t + "_ids", tot);
     bk.d_gid = ws<uint32_t>(ctx, t + "_gid", tot);
     bk.d_gstart = ws<uint32_t>(ctx, t + "_gstart", tot + 1);
@@ -316,12 +327,14 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
         sync(ctx);
         return;
     }
-    uint32_t *dk = ws<uint32_t>(ctx, t + "_dk", tot);
+    uint32_t *dk = nullptr, *ids0 = nullptr;
+    bucket_inputs(ctx, tot, tag, &dk, &ids0);
     uint32_t *dk2 = ws<uint32_t>(ctx, t + "_dk2", tot);
-    uint32_t *ids0 = ws<uint32_t>(ctx, t + "_ids0", tot);
-    hipLaunchKernelGGL(k_bucket_gather, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
-                       d_keys, d_perm, n, tot, 61u - key_bits, dk, ids0);
-    EJ_CHECK_LAUNCH();
+    if (!inputs_ready) {
+        hipLaunchKernelGGL(k_bucket_gather, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                           ctx->stream, d_keys, d_perm, n, tot, 61u - key_bits, dk, ids0);
+        EJ_CHECK_LAUNCH();
+    }
     radix_sort_u32(ctx, dk, ids0, dk2, bk.d_ids, T, n, key_bits, ctx->tune.radix_bits);
     uint32_t *flags = ws<uint32_t>(ctx, t + "_flags", tot);
     uint64_t *d_ng = ws<uint64_t>(ctx, t + "_ngroups", 1);

@@ -99,21 +99,31 @@ __global__ void k_presence(const uint8_t *__restrict__ chars, PrepInfo *__restri
         uint32_t byte = p[k];
         loc[byte >> 5] |= 1u << (byte & 31);
     }
+    // the body: bytes 64..127 (letters) go to a 64-bit register mask without
+    // branches; any other byte to the block's LDS mask, one atomic each
     const uint4 *body = (const uint4 *)(p + head);
+    uint64_t letters = 0;
     for (uint64_t c = tid; c < nbody; c += nth) {
         uint4 v = body[c];
         uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int q = 0; q < 16; q++) {
-            uint32_t byte = (w[q >> 2] >> ((q & 3) * 8)) & 0xFFu;
-            loc[byte >> 5] |= 1u << (byte & 31);
+            const uint32_t byte = (w[q >> 2] >> ((q & 3) * 8)) & 0xFFu;
+            const bool letter = (byte >> 6) == 1u;
+            letters |= letter ? (1ull << (byte & 63)) : 0ull;
+            if (!letter) atomicOr(&m[byte >> 5], 1u << (byte & 31));
         }
     }
+    loc[2] |= (uint32_t)letters;
+    loc[3] |= (uint32_t)(letters >> 32);
 #pragma unroll
     for (int q = 0; q < 8; q++)
         if (loc[q]) atomicOr(&m[q], loc[q]);
     __syncthreads();
-    if (threadIdx.x < 8 && m[threadIdx.x]) atomicOr(&info->mask[threadIdx.x], m[threadIdx.x]);
+    // most blocks find nothing new: read first, so that the device-wide
+    // word sees one atomic per new bit pattern instead of one per block
+    if (threadIdx.x < 8 && (m[threadIdx.x] & ~__atomic_load_n(&info->mask[threadIdx.x], __ATOMIC_RELAXED)))
+        atomicOr(&info->mask[threadIdx.x], m[threadIdx.x]);
 }
 
 // One pass over the characters: thread w maps characters w*CPD ..
@@ -147,12 +157,34 @@ __global__ void k_encode_pack(const uint8_t *__restrict__ chars, uint64_t base, 
         uint32_t cw[CPD / 4];
 #pragma unroll
         for (int q = 0; q < CPD / 4; q++) cw[q] = 0;
+        if (k0 + CPD + 4 <= total) {
+            // a whole word with 4 more characters after it: its characters in
+            // aligned dwords, funnel-shifted, every read inside the text
+            const uint32_t mis = (uint32_t)((uintptr_t)(p + k0) & 3);
+            const uint32_t *b4 = (const uint32_t *)(p + k0 - mis);
+            const uint32_t sh = mis * 8;
+            uint32_t d[CPD / 4 + 1];
 #pragma unroll
-        for (int t = 0; t < CPD; t++) {
-            if (k0 + t < total) {
-                const uint32_t c = lut[p[k0 + t]];
-                x |= c << (t * BW);
-                cw[t >> 2] |= c << (8 * (t & 3));
+            for (int q = 0; q < CPD / 4; q++) d[q] = b4[q];
+            d[CPD / 4] = sh ? b4[CPD / 4] : 0u;
+#pragma unroll
+            for (int q = 0; q < CPD / 4; q++) {
+                const uint32_t ch = __builtin_amdgcn_alignbit(d[q + 1], d[q], sh);
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const uint32_t c = lut[(ch >> (8 * j)) & 0xFFu];
+                    x |= c << ((4 * q + j) * BW);
+                    cw[q] |= c << (8 * j);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < CPD; t++) {
+                if (k0 + t < total) {
+                    const uint32_t c = lut[p[k0 + t]];
+                    x |= c << (t * BW);
+                    cw[t >> 2] |= c << (8 * (t & 3));
+                }
             }
         }
         packed[w] = x;
@@ -258,7 +290,8 @@ __global__ void __launch_bounds__(64)
             const uint32_t *__restrict__ Rwords, uint32_t nw, const uint32_t *__restrict__ spos,
             const uint32_t *__restrict__ sslot, const uint32_t *__restrict__ Jarr,
             const uint64_t *__restrict__ v, uint32_t r, uint32_t z, uint32_t m, uint32_t sigma,
-            uint32_t slot_words, uint64_t *__restrict__ keys, uint8_t *__restrict__ sig_out) {
+            uint32_t slot_words, uint64_t *__restrict__ keys, uint8_t *__restrict__ sig_out,
+            uint32_t *__restrict__ dk_out, uint32_t *__restrict__ ids_out, uint32_t dk_shift) {
     constexpr uint32_t CPD = 32 / BW;
     constexpr uint32_t LOGBW = BW == 2 ? 1 : (BW == 4 ? 2 : 3);
     constexpr uint32_t LOGCPD = 5 - LOGBW;
@@ -383,6 +416,10 @@ __global__ void __launch_bounds__(64)
         res = (res & P61) + (res >> 61);
         if (res >= P61) res -= P61;
         keys[((size_t)l * z + t) * n + id] = res;
+        if (dk_out) {
+            dk_out[((size_t)l * z + t) * n + rank] = (uint32_t)(res >> dk_shift);
+            ids_out[((size_t)l * z + t) * n + rank] = id;
+        }
         if (sig_out) {
             uint8_t *dst = sig_out + (((size_t)id * r + l) * z + t) * m;
             for (uint32_t kk = 0; kk < m; kk++) dst[kk] = sig[(t * m + kk) * 64 + lane];
@@ -554,7 +591,8 @@ void draw_randomness(ej_ctx *ctx, const ej_params &p, uint32_t L, uint32_t sigma
     rd.Jmax = L;
 }
 
-void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, uint8_t *d_sig) {
+void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, uint8_t *d_sig,
+                uint32_t *d_dk, uint32_t *d_rank_ids, uint32_t dk_shift) {
     if (pp.n == 0) return;
     const uint32_t S = rd.S;
     const uint32_t sigbytes = ((S * 64 + 3) / 4) * 4;
@@ -581,7 +619,7 @@ void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, u
                            (const uint32_t *)rd.d_Rwords, rd.nw, (const uint32_t *)rd.d_spos,
                            (const uint32_t *)rd.d_sslot, (const uint32_t *)rd.d_J,
                            (const uint64_t *)rd.d_v, rd.r, rd.z, rd.m, rd.sigma, slot_words, d_keys,
-                           d_sig);
+                           d_sig, d_dk, d_rank_ids, dk_shift);
         EJ_CHECK_LAUNCH();
     };
     if (pp.bw == 2)

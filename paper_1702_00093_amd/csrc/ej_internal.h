@@ -205,7 +205,11 @@ void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uin
              uint32_t fixed_sigma = 0, uint32_t fixed_L = 0, bool need_perm = true);
 void draw_randomness(ej_ctx *ctx, const ej_params &p, uint32_t L, uint32_t sigma, Rand &rd,
                      const char *tag);
-void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, uint8_t *d_sig);
+// With d_dk (and d_rank_ids), also the bucketing sort's input: for table t
+// and length rank k, d_dk[t*n + k] = key >> dk_shift of the string of rank k
+// and d_rank_ids[t*n + k] = that string's index.
+void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, uint8_t *d_sig,
+                uint32_t *d_dk = nullptr, uint32_t *d_rank_ids = nullptr, uint32_t dk_shift = 0);
 
 struct Buckets {
     uint32_t T = 0, n = 0;
@@ -214,10 +218,17 @@ struct Buckets {
     uint32_t *d_gstart = nullptr;     // [ngroups + 1]
     uint64_t ngroups = 0;
 };
+// Key bits the bucketing sorts (key_bits 0: the context's knob, then
+// ceil(log2 n) + 6).
+uint32_t bucket_key_bits(ej_ctx *ctx, uint32_t n, uint32_t key_bits);
+// The workspace buffers of bucket()'s sort input (top key bits and string
+// indexes in length order, per table); inputs_ready = the caller filled them
+// (embed_keys with d_dk) and bucket() skips its gather.
+void bucket_inputs(ej_ctx *ctx, uint64_t tot, const char *tag, uint32_t **d_dk, uint32_t **d_ids);
 // bk.ngroups is read back to the host only when want_ngroups is set.
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
             uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
-            bool want_ngroups = false);
+            bool want_ngroups = false, bool inputs_ready = false);
 
 // Candidate pairs as packed codes (a << 32 | b), a < b, sorted and unique.
 // Returns the count; *n_raw gets the pre-dedup count.

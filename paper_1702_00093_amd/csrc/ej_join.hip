@@ -149,10 +149,15 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     const uint32_t T = p.r * p.z;
     uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
     tm.mark();  // 1: the walk kernel alone follows
-    embed_keys(ctx, pp, rd, keys, nullptr);
+    // the walk also writes the bucketing sort's input (top key bits and
+    // string indexes in length order)
+    const uint32_t kb = bucket_key_bits(ctx, n, 0);
+    uint32_t *bdk = nullptr, *bids = nullptr;
+    bucket_inputs(ctx, (uint64_t)T * n, "j", &bdk, &bids);
+    embed_keys(ctx, pp, rd, keys, nullptr, bdk, bids, 61u - kb);
     tm.mark();  // 2
     Buckets bk;
-    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, 0, bk, "j");
+    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true);
     tm.mark();  // 3
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
