@@ -138,15 +138,17 @@ __global__ void k_unique_compact(const C *__restrict__ codes, uint64_t cnt, uint
     }
 }
 
-// Partitioned de-duplication of 32-bit codes.  The raw codes are grouped by
-// their top bits (k_group_count / k_group_place); one workgroup per group then
-// collects the group's distinct codes and their multiplicities in an LDS hash
-// table and ranks them, so that the groups in order and each group's codes in
-// rank order are the distinct codes sorted.  A group with more than DD_UCAP
-// distinct codes sets *overflow and the caller sorts the raw codes instead.
+// Partitioned de-duplication.  The raw codes (2B bits) are grouped by their
+// top GB bits (k_group_count / k_group_place), which leaves each code's low
+// 2B - GB <= 31 bits as a 32-bit local code; one workgroup per group then
+// collects the group's distinct local codes and their multiplicities in an
+// LDS hash table and ranks them, so that the groups in order and each group's
+// codes in rank order are the distinct codes sorted.  A group with more than
+// DD_UCAP distinct codes sets *overflow and the caller sorts the raw codes
+// instead.
 constexpr uint32_t DD_HCAP = 4096;  // hash slots per group (a power of two)
 constexpr uint32_t DD_UCAP = 1024;  // distinct codes per group handled here
-constexpr uint32_t DD_EMPTY = 0xFFFFFFFFu;  // never a code: a < b < 2^16
+constexpr uint32_t DD_EMPTY = 0xFFFFFFFFu;  // never a local code (< 2^31)
 
 __global__ void __launch_bounds__(256)
     k_dedup_groups(const uint32_t *__restrict__ codes, const uint32_t *__restrict__ gstart,
@@ -214,34 +216,39 @@ __global__ void __launch_bounds__(256)
 // Grouping of the raw codes by their top GB bits (GB <= DD_GBITS), not
 // stable: each workgroup counts the groups of its chunk of DD_CHUNK codes in
 // LDS (k_group_count, hist[g * nwg + wg]); after an exclusive scan of the
-// counts it places its codes from LDS cursors (k_group_place).
+// counts it places the low `shift` bits of its codes from LDS cursors
+// (k_group_place).
 constexpr uint32_t DD_GBITS = 11;
 constexpr uint32_t DD_CHUNK = 16384;
 
+template <typename C>
 __global__ void __launch_bounds__(256)
-    k_group_count(const uint32_t *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
+    k_group_count(const C *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
                   uint32_t *__restrict__ hist) {
     __shared__ uint32_t cnt[1u << DD_GBITS];
     const uint32_t wg = blockIdx.x, nwg = gridDim.x;
     for (uint32_t g = threadIdx.x; g < NG; g += 256) cnt[g] = 0;
     __syncthreads();
     const uint32_t b = wg * DD_CHUNK, e = min(n, b + DD_CHUNK);
-    for (uint32_t i = b + threadIdx.x; i < e; i += 256) atomicAdd(&cnt[codes[i] >> shift], 1u);
+    for (uint32_t i = b + threadIdx.x; i < e; i += 256)
+        atomicAdd(&cnt[(uint32_t)(codes[i] >> shift)], 1u);
     __syncthreads();
     for (uint32_t g = threadIdx.x; g < NG; g += 256) hist[(uint64_t)g * nwg + wg] = cnt[g];
 }
 
+template <typename C>
 __global__ void __launch_bounds__(256)
-    k_group_place(const uint32_t *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
+    k_group_place(const C *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
                   const uint32_t *__restrict__ offs, uint32_t *__restrict__ out) {
     __shared__ uint32_t cur[1u << DD_GBITS];
     const uint32_t wg = blockIdx.x, nwg = gridDim.x;
     for (uint32_t g = threadIdx.x; g < NG; g += 256) cur[g] = offs[(uint64_t)g * nwg + wg];
     __syncthreads();
     const uint32_t b = wg * DD_CHUNK, e = min(n, b + DD_CHUNK);
+    const C low = ((C)1 << shift) - 1;
     for (uint32_t i = b + threadIdx.x; i < e; i += 256) {
-        const uint32_t c = codes[i];
-        out[atomicAdd(&cur[c >> shift], 1u)] = c;
+        const C c = codes[i];
+        out[atomicAdd(&cur[(uint32_t)(c >> shift)], 1u)] = (uint32_t)(c & low);
     }
 }
 
@@ -252,17 +259,19 @@ __global__ void k_group_first(const uint32_t *__restrict__ offs, uint32_t nwg, u
         gstart[g] = g < NG ? offs[(uint64_t)g * nwg] : n;
 }
 
-// The groups' distinct codes at their scanned offsets, unpacked to
-// (a << 32 | b); the multiplicities alongside when `mult` is given.
+// The groups' distinct codes at their scanned offsets, rebuilt from the group
+// and the local code and unpacked to (a << 32 | b); the multiplicities
+// alongside when `mult` is given.
 __global__ void k_dedup_out(const uint32_t *__restrict__ ucode, const uint32_t *__restrict__ umult,
                             const uint32_t *__restrict__ ucount, const uint32_t *__restrict__ uoff,
-                            uint32_t B, uint64_t *__restrict__ out, uint32_t *__restrict__ mult) {
+                            uint32_t B, uint32_t shift, uint64_t *__restrict__ out,
+                            uint32_t *__restrict__ mult) {
     const uint32_t g = blockIdx.x;
     const uint32_t m = ucount[g], o = uoff[g];
-    const uint32_t mask = (1u << B) - 1u;
+    const uint64_t mask = (1ull << B) - 1ull;
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
-        const uint32_t c = ucode[(uint64_t)g * DD_UCAP + i];
-        out[o + i] = ((uint64_t)(c >> B) << 32) | (c & mask);
+        const uint64_t c = ((uint64_t)g << shift) | ucode[(uint64_t)g * DD_UCAP + i];
+        out[o + i] = ((c >> B) << 32) | (c & mask);
         if (mult) mult[o + i] = umult[(uint64_t)g * DD_UCAP + i];
     }
 }
@@ -423,25 +432,21 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         return cnt;
     };
     uint64_t cnt = 0;
-    bool done = false;
-    if (2 * B <= 32) {
-        // 32-bit codes (both indexes below 2^16): grouped by their top bits in
-        // one pass, de-duplicated per group in LDS (k_dedup_groups)
-        uint32_t *raw32 = ws<uint32_t>(ctx, t + "_raw32", raw);
-        emit(raw32);
-        uint32_t *part = ws<uint32_t>(ctx, t + "_raw32_sorted", raw);
+    // grouped de-duplication while the low 2B - GB bits fit 31 bits
+    auto grouped = [&](auto *rawbuf, uint32_t *part) -> bool {
+        using C = std::remove_pointer_t<decltype(rawbuf)>;
         const uint32_t GB = std::min(DD_GBITS, 2 * B);
-        const uint32_t NG = 1u << GB;
+        const uint32_t NG = 1u << GB, shift = 2 * B - GB;
         const uint32_t nwg = (uint32_t)((raw + DD_CHUNK - 1) / DD_CHUNK);
         uint32_t *ghist = ws<uint32_t>(ctx, t + "_dd_hist", (uint64_t)NG * nwg);
         uint32_t *gst = ws<uint32_t>(ctx, t + "_dd_gstart", NG + 1);
-        hipLaunchKernelGGL(k_group_count, dim3(nwg), dim3(256), 0, ctx->stream,
-                           (const uint32_t *)raw32, (uint32_t)raw, 2 * B - GB, NG, ghist);
+        hipLaunchKernelGGL(k_group_count<C>, dim3(nwg), dim3(256), 0, ctx->stream,
+                           (const C *)rawbuf, (uint32_t)raw, shift, NG, ghist);
         EJ_CHECK_LAUNCH();
         scan_exclusive_u32(ctx, ghist, ghist, (uint64_t)NG * nwg, nullptr);
-        hipLaunchKernelGGL(k_group_place, dim3(nwg), dim3(256), 0, ctx->stream,
-                           (const uint32_t *)raw32, (uint32_t)raw, 2 * B - GB, NG,
-                           (const uint32_t *)ghist, part);
+        hipLaunchKernelGGL(k_group_place<C>, dim3(nwg), dim3(256), 0, ctx->stream,
+                           (const C *)rawbuf, (uint32_t)raw, shift, NG, (const uint32_t *)ghist,
+                           part);
         EJ_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_group_first, dim3((NG + 256) / 256), dim3(256), 0, ctx->stream,
                            (const uint32_t *)ghist, nwg, NG, (uint32_t)raw, gst);
@@ -459,34 +464,39 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         scan_exclusive_u32(ctx, ucnt, uoff, NG, info);
         uint64_t hinfo[2] = {0, 0};
         read_back(ctx, info, 16, hinfo);
-        if (hinfo[1] == 0) {
-            cnt = hinfo[0];
-            uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
-            uint32_t *mult = d_order_out ? ws<uint32_t>(ctx, t + "_mult", cnt) : nullptr;
-            hipLaunchKernelGGL(k_dedup_out, dim3(NG), dim3(256), 0, ctx->stream,
-                               (const uint32_t *)ucode, (const uint32_t *)umult,
-                               (const uint32_t *)ucnt, (const uint32_t *)uoff, B, pairs, mult);
+        if (hinfo[1] != 0) return false;
+        cnt = hinfo[0];
+        uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
+        uint32_t *mult = d_order_out ? ws<uint32_t>(ctx, t + "_mult", cnt) : nullptr;
+        hipLaunchKernelGGL(k_dedup_out, dim3(NG), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)ucode, (const uint32_t *)umult, (const uint32_t *)ucnt,
+                           (const uint32_t *)uoff, B, shift, pairs, mult);
+        EJ_CHECK_LAUNCH();
+        *d_pairs_out = pairs;
+        if (d_order_out && cnt) {
+            hipLaunchKernelGGL(k_mult_keys_direct, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)mult, cnt,
+                               ws<uint32_t>(ctx, t + "_okey", cnt),
+                               ws<uint32_t>(ctx, t + "_oidx", cnt));
             EJ_CHECK_LAUNCH();
-            *d_pairs_out = pairs;
-            if (d_order_out && cnt) {
-                hipLaunchKernelGGL(k_mult_keys_direct, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
-                                   ctx->stream, (const uint32_t *)mult, cnt,
-                                   ws<uint32_t>(ctx, t + "_okey", cnt),
-                                   ws<uint32_t>(ctx, t + "_oidx", cnt));
-                EJ_CHECK_LAUNCH();
-            }
-            done = true;
-        } else {
-            // a group with too many distinct codes: sort them all (raw32 is
-            // intact, the partition wrote `part`)
-            cnt = sort_unique(raw32, part);
-            done = true;
         }
-    }
-    if (!done) {
+        return true;
+    };
+    const bool fits_grouped = 2 * B <= DD_GBITS + 31;
+    if (2 * B <= 32) {
+        // 32-bit codes (both indexes below 2^16)
+        uint32_t *raw32 = ws<uint32_t>(ctx, t + "_raw32", raw);
+        emit(raw32);
+        uint32_t *part = ws<uint32_t>(ctx, t + "_raw32_sorted", raw);
+        // on overflow: sort them all (raw32 is intact, the grouping wrote `part`)
+        if (!grouped(raw32, part)) cnt = sort_unique(raw32, part);
+    } else {
         uint64_t *raw64 = ws<uint64_t>(ctx, t + "_raw", raw);
+        uint64_t *sorted = ws<uint64_t>(ctx, t + "_raw_sorted", raw);
         emit(raw64);
-        cnt = sort_unique(raw64, ws<uint64_t>(ctx, t + "_raw_sorted", raw));
+        // the 32-bit local codes go to the first half of `sorted`, which
+        // the fallback sort overwrites only after the grouping has failed
+        if (!fits_grouped || !grouped(raw64, (uint32_t *)sorted)) cnt = sort_unique(raw64, sorted);
     }
     if (d_order_out && cnt) {
         uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);

@@ -274,6 +274,26 @@ def test_candidate_groups_with_many_distinct_pairs(ej, ctx, oracle_lib):
         assert res.n_candidates == len(ref.cand)
 
 
+def test_candidates_above_65536_strings(ej, ctx, oracle_lib):
+    """70,000 strings: pair codes need more than 32 bits, and the grouped
+    de-duplication works on the codes' low bits; the join equals the
+    oracle's."""
+    col = sd.clusters(71, 23000, lambda rr, b: rr.integers(1, 6), lambda rr: rr.integers(12, 31),
+                      lambda rr, LL: rr.poisson(1))
+    assert col.n > 65536
+    K, r, z, m = 2, 1, 3, 16
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 3, 24)
+    _say(f"n={col.n} candidates={len(ref.cand)}")
+    for mode in (0, 2):
+        ctx.tune_set("verify_mode", mode)
+        try:
+            res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=3, L=24)
+        finally:
+            ctx.tune_set("verify_mode", 0)
+        _assert_join_equal(res, ref)
+        assert res.n_candidates == len(ref.cand)
+
+
 # ------------------------------------------------------------ edge cases ----
 
 def test_edge_cases(ej, ctx, oracle_lib):
