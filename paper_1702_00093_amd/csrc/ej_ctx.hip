@@ -131,6 +131,7 @@ void ej_destroy(ej_ctx *ctx) {
     for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
     ctx->graphs.clear();
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->pinned_out) (void)hipHostFree(ctx->pinned_out);
     if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
 }

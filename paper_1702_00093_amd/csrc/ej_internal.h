@@ -112,6 +112,8 @@ struct ej_ctx {
     int num_cu = 256;
     int lds_max = 65536;         // max dynamic LDS per workgroup
     uint64_t *pinned = nullptr;  // small pinned host buffer for size read-backs
+    uint8_t *pinned_out = nullptr;  // grow-only pinned staging of join results
+    size_t pinned_out_bytes = 0;
     ej::Timers timers;
     ej::Tuning tune;
     // EJ_FLAG_GRAPH: graphs of fixed launch sequences, keyed by every

@@ -197,8 +197,9 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         EJ_CHECK_LAUNCH();
         scan_exclusive_u32(ctx, flags, pos, cnt, d_no);
         read_back(ctx, d_no, 8, &nout);
-        opairs = ws<uint32_t>(ctx, "j_opairs", 2 * nout);
-        odist = ws<int32_t>(ctx, "j_odist", nout);
+        // pairs then distances in one buffer: one copy to the host
+        opairs = ws<uint32_t>(ctx, "j_out", 3 * nout);
+        odist = (int32_t *)(opairs + 2 * nout);
         hipLaunchKernelGGL(k_out_compact, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
                            (const uint64_t *)pairs, (const int32_t *)dist, cnt,
                            (const uint32_t *)flags, (const uint32_t *)pos, opairs, odist);
@@ -214,14 +215,26 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         out->dist = nullptr;
         fail(EJ_ENOMEM, "host allocation of the result failed");
     }
-    if (nout) {
-        EJ_HIP(hipMemcpyAsync(out->pairs, opairs, sizeof(uint32_t) * 2 * nout,
-                              hipMemcpyDeviceToHost, ctx->stream));
-        EJ_HIP(hipMemcpyAsync(out->dist, odist, sizeof(int32_t) * nout, hipMemcpyDeviceToHost,
-                              ctx->stream));
+    // through the context's pinned staging buffer (grown when too small): one
+    // DMA at full link speed instead of staged copies to pageable memory
+    const size_t obytes = 12 * nout;
+    if (nout && ctx->pinned_out_bytes < obytes) {
+        if (ctx->pinned_out) EJ_HIP(hipHostFree(ctx->pinned_out));
+        ctx->pinned_out = nullptr;
+        ctx->pinned_out_bytes = 0;
+        const size_t want = std::max<size_t>(obytes + obytes / 4, 1 << 20);
+        EJ_HIP(hipHostMalloc((void **)&ctx->pinned_out, want, hipHostMallocDefault));
+        ctx->pinned_out_bytes = want;
     }
+    if (nout)
+        EJ_HIP(hipMemcpyAsync(ctx->pinned_out, opairs, obytes, hipMemcpyDeviceToHost,
+                              ctx->stream));
     tm.mark();  // 6
     sync(ctx);
+    if (nout) {
+        memcpy(out->pairs, ctx->pinned_out, 8 * nout);
+        memcpy(out->dist, ctx->pinned_out + 8 * nout, 4 * nout);
+    }
     out->ms_prep = tm.between(0, 1);
     out->ms_embed = tm.between(1, 2);
     out->ms_bucket = tm.between(2, 3);
@@ -230,8 +243,13 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     out->ms_output = tm.between(5, 6);
     if (tm.on) {
         std::vector<uint32_t> J(p.r);
-        EJ_HIP(hipMemcpyAsync(J.data(), rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost, ctx->stream));
-        sync(ctx);
+        if (4ull * p.r <= 4096) {
+            read_back(ctx, rd.d_J, 4ull * p.r, J.data());
+        } else {
+            EJ_HIP(hipMemcpyAsync(J.data(), rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            sync(ctx);
+        }
         uint64_t steps = 0;
         for (uint32_t x : J) steps += x;
         out->walk_steps = steps * n;
