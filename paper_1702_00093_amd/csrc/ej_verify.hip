@@ -1229,6 +1229,28 @@ inline uint32_t lane_region(uint32_t nw, uint32_t sigma) {
     return r | 1u;
 }
 
+// Sort keys of the pass-2 list: pairs with longer texts first (key
+// 0xFFFE - columns/32), entries past the number of survivors last (0xFFFF).
+__global__ void k_alive_keys(StrSet A, StrSet B, const uint64_t *__restrict__ pairs,
+                             const uint32_t *__restrict__ list, const uint64_t *__restrict__ nalive,
+                             uint64_t count, uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const uint64_t na = *nalive;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t kk = 0xFFFFu, v = 0;
+        if (k < na) {
+            v = list[k];
+            const uint64_t code = pairs[v];
+            const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
+            const uint64_t la = A.off[a + 1] - A.off[a], lb = B.off[b + 1] - B.off[b];
+            const uint64_t blocks = (la < lb ? la : lb) >> 5;
+            kk = 0xFFFEu - (uint32_t)(blocks < 0xFFFEu ? blocks : 0xFFFEu);
+        }
+        key[k] = kk;
+        val[k] = v;
+    }
+}
+
 inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
     uint64_t g = (work + block - 1) / block;
     uint64_t cap = (uint64_t)ctx->num_cu * 16;
@@ -1455,10 +1477,21 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     scan_exclusive_u32(ctx, flags, pos, count, d_nalive);
     // no host round trip: the list and pass 2 are sized for all pairs and
     // pass 2 reads the number of undecided pairs from the device
-    uint32_t *list = ws<uint32_t>(ctx, "verify_list", count);
+    uint32_t *list0 = ws<uint32_t>(ctx, "verify_list0", count);
     hipLaunchKernelGGL(k_alive_list, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
-                       (const uint32_t *)flags, (const uint32_t *)pos, count, list);
+                       (const uint32_t *)flags, (const uint32_t *)pos, count, list0);
     EJ_CHECK_LAUNCH();
+    // longest texts first, so that each wave's pairs run about as long as
+    // one another and the longest start early
+    uint32_t *lkey = ws<uint32_t>(ctx, "verify_lkey", count);
+    uint32_t *lkey2 = ws<uint32_t>(ctx, "verify_lkey2", count);
+    uint32_t *lval = ws<uint32_t>(ctx, "verify_lval", count);
+    uint32_t *list = ws<uint32_t>(ctx, "verify_list", count);
+    hipLaunchKernelGGL(k_alive_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
+                       A, B, d_pairs, (const uint32_t *)list0, (const uint64_t *)d_nalive, count,
+                       lkey, lval);
+    EJ_CHECK_LAUNCH();
+    radix_sort_u32(ctx, lkey, lval, lkey2, list, 1, (uint32_t)count, 16, 8);
     uint64_t ngroups = (count + tpw - 1) / tpw;
     uint64_t grid = std::min<uint64_t>(ngroups, cap);
     kmark();
