@@ -205,16 +205,6 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
                            (const uint32_t *)flags, (const uint32_t *)pos, opairs, odist);
         EJ_CHECK_LAUNCH();
     }
-    out->count = nout;
-    out->pairs = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (nout ? nout : 1));
-    out->dist = (int32_t *)malloc(sizeof(int32_t) * (nout ? nout : 1));
-    if (!out->pairs || !out->dist) {
-        free(out->pairs);
-        free(out->dist);
-        out->pairs = nullptr;
-        out->dist = nullptr;
-        fail(EJ_ENOMEM, "host allocation of the result failed");
-    }
     // through the context's pinned staging buffer (grown when too small): one
     // DMA at full link speed instead of staged copies to pageable memory
     const size_t obytes = 12 * nout;
@@ -225,6 +215,16 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         const size_t want = std::max<size_t>(obytes + obytes / 4, 1 << 20);
         EJ_HIP(hipHostMalloc((void **)&ctx->pinned_out, want, hipHostMallocDefault));
         ctx->pinned_out_bytes = want;
+    }
+    out->count = nout;
+    out->pairs = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (nout ? nout : 1));
+    out->dist = (int32_t *)malloc(sizeof(int32_t) * (nout ? nout : 1));
+    if (!out->pairs || !out->dist) {
+        free(out->pairs);
+        free(out->dist);
+        out->pairs = nullptr;
+        out->dist = nullptr;
+        fail(EJ_ENOMEM, "host allocation of the result failed");
     }
     if (nout)
         EJ_HIP(hipMemcpyAsync(ctx->pinned_out, opairs, obytes, hipMemcpyDeviceToHost,
