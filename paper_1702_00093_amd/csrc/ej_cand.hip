@@ -114,6 +114,118 @@ __global__ void k_pairs(const uint64_t *__restrict__ key_s, const uint32_t *__re
     }
 }
 
+// ---- pair walk over groups told apart by the sorted top key bits dk
+//
+// Same pairs, in the same entry order, as k_pairs over gid/gstart.  An entry
+// whose successor in its table has other top bits is alone in its group and
+// reads nothing else, which is most entries on workloads with small clusters.
+// Entry indexes are 32-bit (the bucketing keeps T*n below 2^32).
+
+// Full key and length of the entries that share their top bits with a
+// neighbour in their table; the others are never read by the walk.
+__global__ void k_sorted_attrs_dk(const uint64_t *__restrict__ keys,
+                                  const uint32_t *__restrict__ ids,
+                                  const uint32_t *__restrict__ len,
+                                  const uint32_t *__restrict__ dk, uint32_t n, uint32_t tot,
+                                  uint64_t *__restrict__ key_s, uint32_t *__restrict__ len_s) {
+    for (uint64_t e64 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e64 < tot;
+         e64 += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t e = (uint32_t)e64;
+        const uint32_t t = e / n, s0 = t * n, s1 = s0 + n;
+        const uint32_t d = dk[e];
+        const bool grouped = (e > s0 && dk[e - 1] == d) || (e + 1 < s1 && dk[e + 1] == d);
+        if (!grouped) continue;
+        const uint32_t id = ids[e];
+        key_s[e] = keys[(uint64_t)t * n + id];
+        len_s[e] = len[id];
+    }
+}
+
+template <bool EMIT, typename C>
+__device__ inline uint32_t pair_walk(uint32_t e, uint32_t send, const uint32_t *__restrict__ dk,
+                                     const uint64_t *__restrict__ key_s,
+                                     const uint32_t *__restrict__ len_s,
+                                     const uint32_t *__restrict__ ids, uint32_t K, uint32_t B,
+                                     C *__restrict__ out) {
+    const uint32_t d = dk[e];
+    uint32_t q = e + 1;
+    if (q >= send || dk[q] != d) return 0;
+    const uint64_t ke = key_s[e];
+    const uint64_t lim = (uint64_t)len_s[e] + K;
+    const uint32_t ide = EMIT ? ids[e] : 0u;
+    uint32_t c = 0;
+    for (; q < send; q++) {
+        if (dk[q] != d || (uint64_t)len_s[q] > lim) break;
+        if (key_s[q] == ke) {
+            if (EMIT) {
+                const uint32_t idq = ids[q];
+                const uint32_t a = min(ide, idq), b = max(ide, idq);
+                out[c] = (C)(((uint64_t)a << B) | b);
+            }
+            c++;
+        }
+    }
+    return c;
+}
+
+constexpr uint32_t PW_IPT = 8;                 // entries per thread
+constexpr uint32_t PW_TILE = 256 * PW_IPT;     // entries per workgroup
+
+// EMIT = false: per-thread pair counts (saturated to 32 bits; a total that
+// large is rejected before the emit pass) and per-workgroup totals.
+// EMIT = true: each thread writes its entries' pairs, in entry order, from
+// the workgroup's offset plus the exclusive scan of the thread counts.
+// Entry of (thread x, round i) = tile start + 256 i + x.
+template <bool EMIT, typename C>
+__global__ void __launch_bounds__(256)
+    k_pairs_dk(const uint32_t *__restrict__ dk, const uint64_t *__restrict__ key_s,
+               const uint32_t *__restrict__ len_s, const uint32_t *__restrict__ ids, uint32_t n,
+               uint32_t tot, uint32_t K, uint32_t B, uint32_t *__restrict__ tcount,
+               uint64_t *__restrict__ wg_count, const uint64_t *__restrict__ wg_off,
+               C *__restrict__ out) {
+    __shared__ uint64_t red[4];
+    const uint32_t x = threadIdx.x, lane = x & 63, wave = x >> 6;
+    const uint64_t base = (uint64_t)blockIdx.x * PW_TILE;
+    if (!EMIT) {
+        uint64_t s = 0;
+#pragma unroll 1
+        for (uint32_t i = 0; i < PW_IPT; i++) {
+            const uint64_t e = base + 256 * i + x;
+            if (e < tot)
+                s += pair_walk<false, C>((uint32_t)e, ((uint32_t)e / n + 1) * n, dk, key_s, len_s,
+                                         ids, K, B, nullptr);
+        }
+        tcount[blockIdx.x * 256 + x] = s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
+        uint64_t w = s;
+        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
+        if (lane == 0) red[wave] = w;
+        __syncthreads();
+        if (x == 0) wg_count[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        return;
+    }
+    // exclusive scan of the thread counts inside the workgroup (the total is
+    // below 2^32: the host has checked the sum of all counts)
+    const uint32_t v = tcount[blockIdx.x * 256 + x];
+    uint32_t incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(incl, d, 64);
+        if (lane >= (uint32_t)d) incl += y;
+    }
+    if (lane == 63) red[wave] = incl;
+    __syncthreads();
+    uint64_t o = wg_off[blockIdx.x] + incl - v;
+    for (uint32_t w = 0; w < wave; w++) o += red[w];
+    if (v == 0) return;
+#pragma unroll 1
+    for (uint32_t i = 0; i < PW_IPT; i++) {
+        const uint64_t e = base + 256 * i + x;
+        if (e < tot)
+            o += pair_walk<true, C>((uint32_t)e, ((uint32_t)e / n + 1) * n, dk, key_s, len_s, ids,
+                                    K, B, out + o);
+    }
+}
+
 template <typename C>
 __global__ void k_unique_flags(const C *__restrict__ codes, uint64_t cnt,
                                uint32_t *__restrict__ flags) {
@@ -319,7 +431,7 @@ void bucket_inputs(ej_ctx *ctx, uint64_t tot, const char *tag, uint32_t **d_dk, 
 
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
             uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
-            bool want_ngroups, bool inputs_ready) {
+            bool want_ngroups, bool inputs_ready, bool want_groups) {
     std::string t(tag);
     bk.T = T;
     bk.n = n;
@@ -327,10 +439,16 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
     if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
     key_bits = bucket_key_bits(ctx, n, key_bits);
     bk.d_ids = ws<uint32_t>(ctx, t + "_ids", tot);
-    bk.d_gid = ws<uint32_t>(ctx, t + "_gid", tot);
-    bk.d_gstart = ws<uint32_t>(ctx, t + "_gstart", tot + 1);
+    bk.d_gid = nullptr;
+    bk.d_gstart = nullptr;
+    bk.d_dk = nullptr;
     bk.ngroups = 0;
+    if (want_groups) {
+        bk.d_gid = ws<uint32_t>(ctx, t + "_gid", tot);
+        bk.d_gstart = ws<uint32_t>(ctx, t + "_gstart", tot + 1);
+    }
     if (tot == 0) {
+        if (!want_groups) return;
         uint32_t zero = 0;
         EJ_HIP(hipMemcpyAsync(bk.d_gstart, &zero, 4, hipMemcpyHostToDevice, ctx->stream));
         sync(ctx);
@@ -345,6 +463,10 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
         EJ_CHECK_LAUNCH();
     }
     radix_sort_u32(ctx, dk, ids0, dk2, bk.d_ids, T, n, key_bits, ctx->tune.radix_bits);
+    if (!want_groups) {
+        bk.d_dk = dk2;
+        return;
+    }
     uint32_t *flags = ws<uint32_t>(ctx, t + "_flags", tot);
     uint64_t *d_ng = ws<uint64_t>(ctx, t + "_ngroups", 1);
     hipLaunchKernelGGL(k_group_flags, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
@@ -369,19 +491,41 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     if (tot == 0 || n < 2) return 0;
     uint64_t *key_s = ws<uint64_t>(ctx, t + "_key_s", tot);
     uint32_t *len_s = ws<uint32_t>(ctx, t + "_len_s", tot);
-    hipLaunchKernelGGL(k_sorted_attrs, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
-                       d_keys, (const uint32_t *)bk.d_ids, d_len, n, tot, key_s, len_s);
-    EJ_CHECK_LAUNCH();
-    uint64_t *counts = ws<uint64_t>(ctx, t + "_counts", tot);
     uint64_t *d_raw = ws<uint64_t>(ctx, t + "_nraw", 1);
     const uint32_t B = std::max(1u, bits_for(n - 1));
-    hipLaunchKernelGGL((k_pairs<false, uint64_t>), dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
-                       ctx->stream, (const uint64_t *)key_s, (const uint32_t *)len_s,
-                       (const uint32_t *)bk.d_ids, (const uint32_t *)bk.d_gid,
-                       (const uint32_t *)bk.d_gstart, tot, K, B, counts, nullptr,
-                       (uint64_t *)nullptr);
-    EJ_CHECK_LAUNCH();
-    scan_exclusive_u64(ctx, counts, counts, tot, d_raw);
+    // groups from the sorted top key bits (the join) or from group starts
+    const bool by_dk = bk.d_dk != nullptr;
+    if (by_dk && tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
+    const uint32_t nwg = (uint32_t)((tot + PW_TILE - 1) / PW_TILE);
+    uint64_t *counts = nullptr;
+    uint32_t *tcount = nullptr;
+    if (by_dk) {
+        hipLaunchKernelGGL(k_sorted_attrs_dk, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                           ctx->stream, d_keys, (const uint32_t *)bk.d_ids, d_len,
+                           (const uint32_t *)bk.d_dk, n, (uint32_t)tot, key_s, len_s);
+        EJ_CHECK_LAUNCH();
+        tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
+        counts = ws<uint64_t>(ctx, t + "_counts", nwg);
+        hipLaunchKernelGGL((k_pairs_dk<false, uint64_t>), dim3(nwg), dim3(256), 0, ctx->stream,
+                           (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                           (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot,
+                           K, B, tcount, counts, (const uint64_t *)nullptr, (uint64_t *)nullptr);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
+    } else {
+        hipLaunchKernelGGL(k_sorted_attrs, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                           ctx->stream, d_keys, (const uint32_t *)bk.d_ids, d_len, n, tot, key_s,
+                           len_s);
+        EJ_CHECK_LAUNCH();
+        counts = ws<uint64_t>(ctx, t + "_counts", tot);
+        hipLaunchKernelGGL((k_pairs<false, uint64_t>), dim3(grid_for(ctx, tot, 256)), dim3(256),
+                           0, ctx->stream, (const uint64_t *)key_s, (const uint32_t *)len_s,
+                           (const uint32_t *)bk.d_ids, (const uint32_t *)bk.d_gid,
+                           (const uint32_t *)bk.d_gstart, tot, K, B, counts, nullptr,
+                           (uint64_t *)nullptr);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u64(ctx, counts, counts, tot, d_raw);
+    }
     uint64_t raw = 0;
     read_back(ctx, d_raw, 8, &raw);
     if (n_raw) *n_raw = raw;
@@ -393,6 +537,15 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     uint64_t *d_cnt = ws<uint64_t>(ctx, t + "_ucount", 1);
     auto emit = [&](auto *rawbuf) {
         using C = std::remove_pointer_t<decltype(rawbuf)>;
+        if (by_dk) {
+            hipLaunchKernelGGL((k_pairs_dk<true, C>), dim3(nwg), dim3(256), 0, ctx->stream,
+                               (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                               (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n,
+                               (uint32_t)tot, K, B, tcount, (uint64_t *)nullptr,
+                               (const uint64_t *)counts, rawbuf);
+            EJ_CHECK_LAUNCH();
+            return;
+        }
         hipLaunchKernelGGL((k_pairs<true, C>), dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
                            ctx->stream, (const uint64_t *)key_s, (const uint32_t *)len_s,
                            (const uint32_t *)bk.d_ids, (const uint32_t *)bk.d_gid,

@@ -219,6 +219,9 @@ struct Buckets {
     uint32_t *d_gid = nullptr;        // [T*n] group id of each sorted entry
     uint32_t *d_gstart = nullptr;     // [ngroups + 1]
     uint64_t ngroups = 0;
+    // [T*n] sorted top key bits: set instead of d_gid/d_gstart when the
+    // groups are not built (the pair walk then ends a group where they change)
+    uint32_t *d_dk = nullptr;
 };
 // Key bits the bucketing sorts (key_bits 0: the context's knob, then
 // ceil(log2 n) + 6).
@@ -228,9 +231,11 @@ uint32_t bucket_key_bits(ej_ctx *ctx, uint32_t n, uint32_t key_bits);
 // (embed_keys with d_dk) and bucket() skips its gather.
 void bucket_inputs(ej_ctx *ctx, uint64_t tot, const char *tag, uint32_t **d_dk, uint32_t **d_ids);
 // bk.ngroups is read back to the host only when want_ngroups is set.
+// want_groups = false skips the group ids and starts and leaves the sorted
+// top key bits in bk.d_dk (all that candidates() needs).
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
             uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
-            bool want_ngroups = false, bool inputs_ready = false);
+            bool want_ngroups = false, bool inputs_ready = false, bool want_groups = true);
 
 // Candidate pairs as packed codes (a << 32 | b), a < b, sorted and unique.
 // Returns the count; *n_raw gets the pre-dedup count.

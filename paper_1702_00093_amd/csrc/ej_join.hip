@@ -157,7 +157,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     embed_keys(ctx, pp, rd, keys, nullptr, bdk, bids, 61u - kb);
     tm.mark();  // 2
     Buckets bk;
-    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true);
+    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true, false);
     tm.mark();  // 3
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
