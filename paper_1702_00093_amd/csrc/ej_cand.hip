@@ -141,15 +141,15 @@ __global__ void k_sorted_attrs_dk(const uint64_t *__restrict__ keys,
     }
 }
 
+// Entry e's walk, given that entry e + 1 is in its group (top bits d).
 template <bool EMIT, typename C>
-__device__ inline uint32_t pair_walk(uint32_t e, uint32_t send, const uint32_t *__restrict__ dk,
+__device__ inline uint32_t pair_walk(uint32_t e, uint32_t d, uint32_t send,
+                                     const uint32_t *__restrict__ dk,
                                      const uint64_t *__restrict__ key_s,
                                      const uint32_t *__restrict__ len_s,
                                      const uint32_t *__restrict__ ids, uint32_t K, uint32_t B,
                                      C *__restrict__ out) {
-    const uint32_t d = dk[e];
     uint32_t q = e + 1;
-    if (q >= send || dk[q] != d) return 0;
     const uint64_t ke = key_s[e];
     const uint64_t lim = (uint64_t)len_s[e] + K;
     const uint32_t ide = EMIT ? ids[e] : 0u;
@@ -186,15 +186,31 @@ __global__ void __launch_bounds__(256)
     __shared__ uint64_t red[4];
     const uint32_t x = threadIdx.x, lane = x & 63, wave = x >> 6;
     const uint64_t base = (uint64_t)blockIdx.x * PW_TILE;
+    // the group test of all the thread's entries first (coalesced loads
+    // issued together); only entries with a partner in their group walk
+    uint32_t dd[PW_IPT], send[PW_IPT], act = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < PW_IPT; i++) {
+        const uint64_t e = base + 256 * i + x;
+        dd[i] = 0;
+        send[i] = 0;
+        if (e < tot) {
+            send[i] = ((uint32_t)e / n + 1) * n;
+            dd[i] = dk[e];
+        }
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < PW_IPT; i++) {
+        const uint64_t e = base + 256 * i + x;
+        if (e + 1 < send[i] && dk[e + 1] == dd[i]) act |= 1u << i;
+    }
     if (!EMIT) {
         uint64_t s = 0;
-#pragma unroll 1
-        for (uint32_t i = 0; i < PW_IPT; i++) {
-            const uint64_t e = base + 256 * i + x;
-            if (e < tot)
-                s += pair_walk<false, C>((uint32_t)e, ((uint32_t)e / n + 1) * n, dk, key_s, len_s,
-                                         ids, K, B, nullptr);
-        }
+#pragma unroll
+        for (uint32_t i = 0; i < PW_IPT; i++)
+            if (act & (1u << i))
+                s += pair_walk<false, C>((uint32_t)(base + 256 * i + x), dd[i], send[i], dk, key_s,
+                                         len_s, ids, K, B, nullptr);
         tcount[blockIdx.x * 256 + x] = s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
         uint64_t w = s;
         for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
@@ -217,13 +233,11 @@ __global__ void __launch_bounds__(256)
     uint64_t o = wg_off[blockIdx.x] + incl - v;
     for (uint32_t w = 0; w < wave; w++) o += red[w];
     if (v == 0) return;
-#pragma unroll 1
-    for (uint32_t i = 0; i < PW_IPT; i++) {
-        const uint64_t e = base + 256 * i + x;
-        if (e < tot)
-            o += pair_walk<true, C>((uint32_t)e, ((uint32_t)e / n + 1) * n, dk, key_s, len_s, ids,
-                                    K, B, out + o);
-    }
+#pragma unroll
+    for (uint32_t i = 0; i < PW_IPT; i++)
+        if (act & (1u << i))
+            o += pair_walk<true, C>((uint32_t)(base + 256 * i + x), dd[i], send[i], dk, key_s,
+                                    len_s, ids, K, B, out + o);
 }
 
 template <typename C>
