@@ -158,7 +158,7 @@ void scan_exclusive_u64(ej_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, uint
 // Stable LSD radix sort of `nseg` independent equal-length segments of
 // `seglen` entries, ordered by bits [0, key_bits) of the keys.  Values
 // (nullable) move with the keys.  Results end in the _out arrays; the _in
-// arrays are clobbered.  digit_bits in {4..11}.
+// arrays may be clobbered.  digit_bits in {4..11}.
 void radix_sort_u32(ej_ctx *ctx, uint32_t *keys_in, uint32_t *vals_in, uint32_t *keys_out,
                     uint32_t *vals_out, uint32_t nseg, uint32_t seglen, uint32_t key_bits,
                     uint32_t digit_bits);

@@ -280,13 +280,15 @@ void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout
     if (dbits < 4) dbits = 4;
     if (dbits > dmax) dbits = dmax;
     uint32_t passes = (key_bits + dbits - 1) / dbits;
-    // an odd number of passes ends in kout without a copy: take one pass
-    // fewer with wider digits when they stay within dmax bits, else one more
+    // an odd number of passes ends in kout: take one pass fewer with wider
+    // digits when they stay within dmax bits; otherwise the first pass writes
+    // a scratch buffer, so that an even count ends in kout too
+    bool via_tmp = false;
     if (passes > 0 && passes % 2 == 0) {
         if ((key_bits + passes - 2) / (passes - 1) <= dmax)
             passes -= 1;
         else
-            passes += 1;
+            via_tmp = true;
     }
     // bits split as evenly as possible: the first key_bits % passes passes
     // take one bit more
@@ -298,14 +300,18 @@ void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout
                                   ctx->stream));
         return;
     }
-    // passes alternate kin -> kout -> kin ...; with an odd count the last
-    // one writes kout
+    // passes alternate kin -> kout -> kin ... (odd count), or kin -> tmp ->
+    // kout -> tmp ... (even count): the last one writes kout
     uint32_t tps = ceil_div(seglen, TILE);
     uint32_t NB = 1u << dbits;
     uint64_t hn = (uint64_t)nseg * NB * tps;
     uint32_t *hist = ws<uint32_t>(ctx, "rs_hist", hn);
     K *a = kin, *b = kout;
     uint32_t *va = vin, *vb = vout;
+    if (via_tmp) {
+        b = ws<K>(ctx, "rs_tmp_keys", n);
+        if (HAS_VAL) vb = ws<uint32_t>(ctx, "rs_tmp_vals", n);
+    }
     size_t hist_lds = NB * sizeof(uint32_t);
     size_t scat_lds = (3 + NWAVE) * NB * sizeof(uint32_t) + (size_t)TILE * (sizeof(K) + 4);
     if (scat_lds > (size_t)ctx->lds_max) fail(EJ_EUNSUPPORTED, "radix sort: digit too wide for LDS");
@@ -328,10 +334,10 @@ void radix_sort_impl(ej_ctx *ctx, K *kin, uint32_t *vin, K *kout, uint32_t *vout
         shift += db;
         K *t = a;
         a = b;
-        b = t;
+        b = (via_tmp && p == 0) ? kout : t;
         uint32_t *tv = va;
         va = vb;
-        vb = tv;
+        vb = (via_tmp && p == 0) ? vout : tv;
     }
 }
 
