@@ -107,11 +107,60 @@ __global__ void __launch_bounds__(BLK) k_scan_down(const T *in, T *out, uint64_t
     }
 }
 
+// Small inputs: one workgroup of 1024 threads walks the array in tiles of
+// 1024 * IPT with a running carry (one launch instead of three).  In place
+// is fine: each element is read and written by the same thread.
+constexpr int SBLK = 1024, SNWAVE = SBLK / 64;
+constexpr uint64_t SCAN_SINGLE_MAX = 4ull * SBLK * IPT;
+
+template <typename T>
+__global__ void __launch_bounds__(SBLK) k_scan_single(const T *in, T *out, uint64_t n,
+                                                      uint64_t *__restrict__ total_out) {
+    __shared__ T wsum[SNWAVE];
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    T carry = 0;
+    for (uint64_t base = 0; base < n; base += (uint64_t)SBLK * IPT) {
+        const uint64_t e0 = base + (uint64_t)threadIdx.x * IPT;
+        T v[IPT];
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < IPT; i++) {
+            v[i] = e0 + i < n ? in[e0 + i] : 0;
+            s += v[i];
+        }
+        const T x = wave_inclusive_scan(s, lane);
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        T before = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < SNWAVE; w++) {
+            const T sw = wsum[w];
+            if (w < (int)wave) before += sw;
+            tot += sw;
+        }
+        __syncthreads();
+        T ex = carry + before + x - s;
+#pragma unroll
+        for (int i = 0; i < IPT; i++) {
+            if (e0 + i < n) out[e0 + i] = ex;
+            ex += v[i];
+        }
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total_out) *total_out = (uint64_t)carry;
+}
+
 template <typename T>
 void scan_exclusive(ej_ctx *ctx, const T *d_in, T *d_out, uint64_t n, uint64_t *d_total,
                     const char *name) {
     if (n == 0) {
         if (d_total) EJ_HIP(hipMemsetAsync(d_total, 0, sizeof(uint64_t), ctx->stream));
+        return;
+    }
+    if (n <= SCAN_SINGLE_MAX) {
+        hipLaunchKernelGGL(k_scan_single<T>, dim3(1), dim3(SBLK), 0, ctx->stream, d_in, d_out, n,
+                           d_total);
+        EJ_CHECK_LAUNCH();
         return;
     }
     uint64_t nb = (n + TILE - 1) / TILE;
