@@ -294,6 +294,26 @@ def test_candidates_above_65536_strings(ej, ctx, oracle_lib):
         assert res.n_candidates == len(ref.cand)
 
 
+
+def test_join_top_bit_groups_span_tiles(ej, ctx, oracle_lib):
+    """The join's pair walk ends a group where the sorted top key bits change.
+    With the bucketing cut to 1, 3 or 8 top bits, groups mix many different
+    full keys and a 1-bit group (about 2,100 entries per table) spans two
+    2,048-entry workgroup tiles; candidates and results stay the oracle's."""
+    col = sd.clusters(19, 1700, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(20, 41),
+                      lambda rr, LL: rr.poisson(1))
+    K, r, z, m = 3, 1, 2, 4
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 19, 16)
+    old = ctx.tune_get("bucket_key_bits")
+    try:
+        for bits in (1, 3, 8, 0):
+            _say(f"join bucket_key_bits={bits} n={col.n} candidates={len(ref.cand)}")
+            ctx.tune_set("bucket_key_bits", bits)
+            res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=19, L=16)
+            _assert_join_equal(res, ref)
+    finally:
+        ctx.tune_set("bucket_key_bits", old)
+
 # ------------------------------------------------------------ edge cases ----
 
 def test_edge_cases(ej, ctx, oracle_lib):
