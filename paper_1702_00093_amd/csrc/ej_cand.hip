@@ -116,10 +116,11 @@ __global__ void k_pairs(const uint64_t *__restrict__ key_s, const uint32_t *__re
 
 // ---- pair walk over groups told apart by the sorted top key bits dk
 //
-// Same pairs, in the same entry order, as k_pairs over gid/gstart.  An entry
-// whose successor in its table has other top bits is alone in its group and
-// reads nothing else, which is most entries on workloads with small clusters.
-// Entry indexes are 32-bit (the bucketing keeps T*n below 2^32).
+// The same pairs as k_pairs over gid/gstart, in another deterministic order
+// (the de-duplication that follows does not depend on it).  An entry whose
+// successor in its table has other top bits is alone in its group and reads
+// nothing else.  Entry indexes are 32-bit (the bucketing keeps T*n below
+// 2^32).
 
 // Full key and length of the entries that share their top bits with a
 // neighbour in their table; the others are never read by the walk.
