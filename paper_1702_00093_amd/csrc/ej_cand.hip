@@ -169,7 +169,7 @@ __device__ inline uint32_t pair_walk(uint32_t e, uint32_t d, uint32_t send,
     return c;
 }
 
-constexpr uint32_t PW_IPT = 8;                 // entries per thread
+constexpr uint32_t PW_IPT = 4;                 // entries per thread
 constexpr uint32_t PW_TILE = 256 * PW_IPT;     // entries per workgroup
 
 // EMIT = false: per-thread pair counts (saturated to 32 bits; a total that

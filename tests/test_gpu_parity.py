@@ -298,8 +298,8 @@ def test_candidates_above_65536_strings(ej, ctx, oracle_lib):
 def test_join_top_bit_groups_span_tiles(ej, ctx, oracle_lib):
     """The join's pair walk ends a group where the sorted top key bits change.
     With the bucketing cut to 1, 3 or 8 top bits, groups mix many different
-    full keys and a 1-bit group (about 2,100 entries per table) spans two
-    2,048-entry workgroup tiles; candidates and results stay the oracle's."""
+    full keys and a 1-bit group (about 2,100 entries per table) spans several
+    1,024-entry workgroup tiles; candidates and results stay the oracle's."""
     col = sd.clusters(19, 1700, lambda rr, b: rr.integers(1, 5), lambda rr: rr.integers(20, 41),
                       lambda rr, LL: rr.poisson(1))
     K, r, z, m = 3, 1, 2, 4
