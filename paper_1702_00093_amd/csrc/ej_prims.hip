@@ -109,9 +109,10 @@ __global__ void __launch_bounds__(BLK) k_scan_down(const T *in, T *out, uint64_t
 
 // Small inputs: one workgroup of 1024 threads walks the array in tiles of
 // 1024 * IPT with a running carry (one launch instead of three).  In place
-// is fine: each element is read and written by the same thread.
+// is fine: each element is read and written by the same thread.  Used up to
+// one tile: each further tile costs about as much as the three-kernel scan.
 constexpr int SBLK = 1024, SNWAVE = SBLK / 64;
-constexpr uint64_t SCAN_SINGLE_MAX = 4ull * SBLK * IPT;
+constexpr uint64_t SCAN_SINGLE_MAX = (uint64_t)SBLK * IPT;
 
 template <typename T>
 __global__ void __launch_bounds__(SBLK) k_scan_single(const T *in, T *out, uint64_t n,
