@@ -405,24 +405,28 @@ __global__ void k_dedup_out(const uint32_t *__restrict__ ucode, const uint32_t *
 
 // Order key of unique pair u from its multiplicity (see k_mult_keys).
 __global__ void k_mult_keys_direct(const uint32_t *__restrict__ mult, uint64_t cnt,
-                                   uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+                                   uint32_t cap, uint32_t *__restrict__ key,
+                                   uint32_t *__restrict__ idx) {
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < cnt;
          u += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t m = mult[u];
-        key[u] = 0xFFFFu - (m < 0xFFFFu ? m : 0xFFFFu);
+        key[u] = cap - (m < cap ? m : cap);
         idx[u] = (uint32_t)u;
     }
 }
 
-// Sort key of unique pair u: 0xFFFF - (number of raw copies, at most 0xFFFF),
-// so that an ascending sort puts the most frequent pairs first.
+// Sort key of unique pair u: cap - (number of raw copies), so that an
+// ascending sort puts the most frequent pairs first.  A pair has at most one
+// raw copy per table, so cap = 2^bits_for(tables) - 1 keeps every count
+// apart in bits_for(tables) key bits.
 __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, uint64_t raw,
-                            uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+                            uint32_t cap, uint32_t *__restrict__ key,
+                            uint32_t *__restrict__ idx) {
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < cnt;
          u += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t end = u + 1 < cnt ? first[u + 1] : raw;
         const uint64_t m = end - first[u];
-        key[u] = 0xFFFFu - (uint32_t)(m < 0xFFFFu ? m : 0xFFFFu);
+        key[u] = cap - (uint32_t)(m < cap ? m : cap);
         idx[u] = (uint32_t)u;
     }
 }
@@ -508,6 +512,9 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     uint32_t *len_s = ws<uint32_t>(ctx, t + "_len_s", tot);
     uint64_t *d_raw = ws<uint64_t>(ctx, t + "_nraw", 1);
     const uint32_t B = std::max(1u, bits_for(n - 1));
+    // key width of the verification order (multiplicities are at most T)
+    const uint32_t mult_bits = std::max(1u, bits_for(bk.T));
+    const uint32_t mult_cap = mult_bits >= 32 ? 0xFFFFFFFFu : (1u << mult_bits) - 1u;
     // groups from the sorted top key bits (the join) or from group starts
     const bool by_dk = bk.d_dk != nullptr;
     if (by_dk && tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
@@ -594,7 +601,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
             uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
             uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
             hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)first, cnt, raw, k0, v0);
+                               ctx->stream, (const uint32_t *)first, cnt, raw, mult_cap, k0, v0);
             EJ_CHECK_LAUNCH();
         }
         return cnt;
@@ -643,7 +650,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         *d_pairs_out = pairs;
         if (d_order_out && cnt) {
             hipLaunchKernelGGL(k_mult_keys_direct, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)mult, cnt,
+                               ctx->stream, (const uint32_t *)mult, cnt, mult_cap,
                                ws<uint32_t>(ctx, t + "_okey", cnt),
                                ws<uint32_t>(ctx, t + "_oidx", cnt));
             EJ_CHECK_LAUNCH();
@@ -671,7 +678,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
         uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", cnt);
         uint32_t *order = ws<uint32_t>(ctx, t + "_order", cnt);
-        radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt, 16, 8);
+        radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt, mult_bits, 11);
         *d_order_out = order;
     }
     return cnt;

@@ -1229,22 +1229,24 @@ inline uint32_t lane_region(uint32_t nw, uint32_t sigma) {
     return r | 1u;
 }
 
-// Sort keys of the pass-2 list: pairs with longer texts first (key
-// 0xFFFE - columns/32), entries past the number of survivors last (0xFFFF).
+// Sort keys of the pass-2 list (11 bits, one radix pass): pairs with longer
+// texts first (key 0x7FE - columns/32, texts beyond 65,472 columns share key
+// 0), entries past the number of survivors last (0x7FF).  The order only
+// schedules the work.
 __global__ void k_alive_keys(StrSet A, StrSet B, const uint64_t *__restrict__ pairs,
                              const uint32_t *__restrict__ list, const uint64_t *__restrict__ nalive,
                              uint64_t count, uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
     const uint64_t na = *nalive;
     for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
          k += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t kk = 0xFFFFu, v = 0;
+        uint32_t kk = 0x7FFu, v = 0;
         if (k < na) {
             v = list[k];
             const uint64_t code = pairs[v];
             const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
             const uint64_t la = A.off[a + 1] - A.off[a], lb = B.off[b + 1] - B.off[b];
             const uint64_t blocks = (la < lb ? la : lb) >> 5;
-            kk = 0xFFFEu - (uint32_t)(blocks < 0xFFFEu ? blocks : 0xFFFEu);
+            kk = 0x7FEu - (uint32_t)(blocks < 0x7FEu ? blocks : 0x7FEu);
         }
         key[k] = kk;
         val[k] = v;
@@ -1491,7 +1493,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
                        A, B, d_pairs, (const uint32_t *)list0, (const uint64_t *)d_nalive, count,
                        lkey, lval);
     EJ_CHECK_LAUNCH();
-    radix_sort_u32(ctx, lkey, lval, lkey2, list, 1, (uint32_t)count, 16, 8);
+    radix_sort_u32(ctx, lkey, lval, lkey2, list, 1, (uint32_t)count, 11, 11);
     uint64_t ngroups = (count + tpw - 1) / tpw;
     uint64_t grid = std::min<uint64_t>(ngroups, cap);
     kmark();
