@@ -243,7 +243,8 @@ class Context:
         self._check(st)
         try:
             cnt = int(res.count)
-            pairs = np.ctypeslib.as_array(res.pairs, (max(cnt, 1) * 2,))[:2 * cnt].copy() \
+            # astype copies: the arrays stay valid after the result is freed
+            pairs = np.ctypeslib.as_array(res.pairs, (max(cnt, 1) * 2,))[:2 * cnt] \
                 .reshape(cnt, 2).astype(np.int64)
             dist = np.ctypeslib.as_array(res.dist, (max(cnt, 1),))[:cnt].copy()
             ms = dict(prep=res.ms_prep, embed=res.ms_embed, bucket=res.ms_bucket,

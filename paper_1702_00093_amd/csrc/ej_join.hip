@@ -206,13 +206,17 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         EJ_CHECK_LAUNCH();
     }
     // through the context's pinned staging buffer (grown when too small): one
-    // DMA at full link speed instead of staged copies to pageable memory
+    // DMA at full link speed instead of staged copies to pageable memory.
+    // With timing on, the verified columns and the walk lengths J follow the
+    // results in the same buffer and share their synchronisation.
     const size_t obytes = 12 * nout;
-    if (nout && ctx->pinned_out_bytes < obytes) {
+    const size_t xbytes = tm.on ? 8 + 4ull * p.r : 0;
+    const size_t need = obytes + xbytes;
+    if (need && ctx->pinned_out_bytes < need) {
         if (ctx->pinned_out) EJ_HIP(hipHostFree(ctx->pinned_out));
         ctx->pinned_out = nullptr;
         ctx->pinned_out_bytes = 0;
-        const size_t want = std::max<size_t>(obytes + obytes / 4, 1 << 20);
+        const size_t want = std::max<size_t>(need + need / 4, 1 << 20);
         EJ_HIP(hipHostMalloc((void **)&ctx->pinned_out, want, hipHostMallocDefault));
         ctx->pinned_out_bytes = want;
     }
@@ -230,6 +234,12 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         EJ_HIP(hipMemcpyAsync(ctx->pinned_out, opairs, obytes, hipMemcpyDeviceToHost,
                               ctx->stream));
     tm.mark();  // 6
+    uint8_t *xp = ctx->pinned_out + obytes;
+    if (xbytes) {
+        if (cnt)
+            EJ_HIP(hipMemcpyAsync(xp, d_cols, 8, hipMemcpyDeviceToHost, ctx->stream));
+        EJ_HIP(hipMemcpyAsync(xp + 8, rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost, ctx->stream));
+    }
     sync(ctx);
     if (nout) {
         memcpy(out->pairs, ctx->pinned_out, 8 * nout);
@@ -243,17 +253,11 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     out->ms_output = tm.between(5, 6);
     if (tm.on) {
         std::vector<uint32_t> J(p.r);
-        if (4ull * p.r <= 4096) {
-            read_back(ctx, rd.d_J, 4ull * p.r, J.data());
-        } else {
-            EJ_HIP(hipMemcpyAsync(J.data(), rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost,
-                                  ctx->stream));
-            sync(ctx);
-        }
+        memcpy(J.data(), xp + 8, 4ull * p.r);
         uint64_t steps = 0;
         for (uint32_t x : J) steps += x;
         out->walk_steps = steps * n;
-        if (cnt) read_back(ctx, d_cols, 8, &out->verify_columns);
+        if (cnt) memcpy(&out->verify_columns, xp, 8);
         float kms = 0.f;
         for (int i = 0; i + 1 < ctx->timers.nkv; i += 2) {
             float ms = 0.f;
