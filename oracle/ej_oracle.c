@@ -276,6 +276,7 @@ static int cmp_u64(const void *pa, const void *pb) {
  * malloc'ed here and released with ejo_result_free. */
 typedef struct {
     uint32_t sigma, L;
+    uint64_t n_raw;      /* pairs found by the tables before de-duplication */
     uint64_t n_cand;
     uint64_t *cand;      /* (i << 32) | j, i < j, sorted */
     uint32_t *cand_dist; /* min(ED, K+1) per candidate */
@@ -311,19 +312,26 @@ uint32_t ejo_effective_L(const uint64_t *offsets, uint32_t n, uint32_t L_req) {
     return (uint32_t)L;
 }
 
+/* Options of ejo_join_opts.  They only leave work out; none changes a value
+ * that is computed. */
+#define EJO_STOP_AFTER_CANDIDATES 1u /* the candidate set C only: no verification */
+#define EJO_NO_SIG 2u                /* do not keep the sampled symbols */
+
 /* EmbedJoin (Algorithm 3 with Algorithm 2 as preprocessing).
  * explicit_R (r * L * sigma 0/1 bytes), explicit_pos and explicit_v replace
  * the drawn randomness when non-NULL (used to replay the paper's running
- * example).  Returns 0 on success. */
-int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
-             uint32_t r, uint32_t z, uint32_t m, uint32_t L_req, uint64_t seed,
-             const uint8_t *explicit_R, const uint32_t *explicit_pos,
-             const uint64_t *explicit_v, ejo_result *res) {
+ * example).  Returns 0 on success, -1 for r, z or m of 0, -2 when all 256
+ * byte values occur (the padding symbol needs a code of its own). */
+int ejo_join_opts(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+                  uint32_t r, uint32_t z, uint32_t m, uint32_t L_req, uint64_t seed,
+                  const uint8_t *explicit_R, const uint32_t *explicit_pos,
+                  const uint64_t *explicit_v, uint32_t opts, ejo_result *res) {
     memset(res, 0, sizeof(*res));
     if (r == 0 || z == 0 || m == 0) return -1;
     uint64_t total = n ? offsets[n] - offsets[0] : 0;
     int32_t lut[256];
     int sigma = ejo_alphabet(chars + (n ? offsets[0] : 0), total, lut);
+    if (sigma > 255) return -2;
     uint32_t L = ejo_effective_L(offsets, n, L_req);
     res->sigma = (uint32_t)sigma;
     res->L = L;
@@ -352,7 +360,7 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
     qsort(order, n, sizeof(uint32_t), cmp_len_alpha);
 
     res->keys = (uint64_t *)malloc(sizeof(uint64_t) * T * (n ? n : 1));
-    res->sig = (uint8_t *)malloc((uint64_t)n * T * m + 1);
+    res->sig = (opts & EJO_NO_SIG) ? NULL : (uint8_t *)malloc((uint64_t)n * T * m + 1);
     uint8_t *t = (uint8_t *)malloc(L);
     uint8_t *u = (uint8_t *)malloc(m);
     for (uint32_t l = 0; l < r; l++) {
@@ -365,7 +373,7 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
                 const uint32_t *pj = pos + ((uint64_t)l * z + j) * m;
                 const uint64_t *vj = v + ((uint64_t)l * z + j) * m;
                 for (uint32_t k = 0; k < m; k++) u[k] = t[pj[k]];
-                memcpy(res->sig + (((uint64_t)i * r + l) * z + j) * m, u, m);
+                if (res->sig) memcpy(res->sig + (((uint64_t)i * r + l) * z + j) * m, u, m);
                 res->keys[((uint64_t)l * z + j) * n + i] = ejo_key(t, pj, vj, m);
             }
         }
@@ -411,6 +419,7 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
         }
         /* remove duplicate pairs found in this iteration; pairs from
          * different iterations differ in their later element */
+        res->n_raw += icnt;
         qsort(iter_pairs, icnt, sizeof(uint64_t), cmp_u64);
         for (uint64_t e = 0; e < icnt; e++) {
             if (e > 0 && iter_pairs[e] == iter_pairs[e - 1]) continue;
@@ -426,9 +435,18 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
     free(tables);
     qsort(cand, cnt, sizeof(uint64_t), cmp_u64);
 
-    /* verification */
     res->n_cand = cnt;
     res->cand = cand;
+    if (opts & EJO_STOP_AFTER_CANDIDATES) {
+        free(order);
+        free(codes);
+        free(Rbits);
+        free(pos);
+        free(v);
+        return 0;
+    }
+
+    /* verification */
     res->cand_dist = (uint32_t *)malloc(sizeof(uint32_t) * (cnt ? cnt : 1));
     res->out = (uint64_t *)malloc(sizeof(uint64_t) * (cnt ? cnt : 1));
     res->out_dist = (uint32_t *)malloc(sizeof(uint32_t) * (cnt ? cnt : 1));
@@ -453,7 +471,14 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
     return 0;
 }
 
-/* Verification only: min(ED, K+1) for each pair (a_k, b_k). */
+int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+             uint32_t r, uint32_t z, uint32_t m, uint32_t L_req, uint64_t seed,
+             const uint8_t *explicit_R, const uint32_t *explicit_pos,
+             const uint64_t *explicit_v, ejo_result *res) {
+    return ejo_join_opts(chars, offsets, n, K, r, z, m, L_req, seed, explicit_R, explicit_pos,
+                         explicit_v, 0u, res);
+}
+
 /* ------------------------------------------------------------- serving --
  * Serving is a systems layer on the method, not a step of the paper: an
  * index fixes the alphabet (its sorted distinct bytes), the truncation L and
@@ -464,7 +489,7 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
  * string), with the keys from the same embedding and key functions as the
  * join.  Returns the number of results (entries beyond cap are not
  * written), -1 for invalid sizes, -2 if a query byte is outside the index
- * alphabet. */
+ * alphabet, -3 when all 256 byte values occur in the index. */
 static void string_keys(const uint8_t *codes, uint32_t len, const uint8_t *Rbits, uint64_t rb,
                         uint32_t sigma, uint32_t L, const uint32_t *pos, const uint64_t *v,
                         uint32_t r, uint32_t z, uint32_t m, uint8_t *t, uint64_t *keys) {
@@ -484,6 +509,7 @@ int64_t ejo_query(const uint8_t *ichars, const uint64_t *ioff, uint32_t n, const
     uint64_t itotal = n ? ioff[n] - ioff[0] : 0;
     int32_t lut[256];
     int sigma = ejo_alphabet(ichars + (n ? ioff[0] : 0), itotal, lut);
+    if (sigma > 255) return -3;
     uint32_t L = ejo_effective_L(ioff, n, L_req);
     uint32_t T = r * z;
     uint64_t qtotal = nq ? qoff[nq] - qoff[0] : 0;
@@ -538,6 +564,44 @@ int64_t ejo_query(const uint8_t *ichars, const uint64_t *ioff, uint32_t n, const
     return (int64_t)cnt;
 }
 
+/* Bucket keys of every string of a set x under the alphabet, truncation and
+ * random streams that the set s (ichars/ioff, n strings) fixes -- the keys the
+ * serving definition compares (x = s gives the join's keys).  keys[i][q] for
+ * table q = l*z + j.  Returns 0, -1 for invalid sizes, -2 if a byte of x is
+ * outside the alphabet of s, -3 when all 256 byte values occur in s. */
+int ejo_keys(const uint8_t *ichars, const uint64_t *ioff, uint32_t n, const uint8_t *xchars,
+             const uint64_t *xoff, uint32_t nx, uint32_t r, uint32_t z, uint32_t m,
+             uint32_t L_req, uint64_t seed, uint64_t *keys) {
+    if (r == 0 || z == 0 || m == 0) return -1;
+    uint64_t itotal = n ? ioff[n] - ioff[0] : 0;
+    int32_t lut[256];
+    int sigma = ejo_alphabet(ichars + (n ? ioff[0] : 0), itotal, lut);
+    if (sigma > 255) return -3;
+    uint32_t L = ejo_effective_L(ioff, n, L_req);
+    uint32_t T = r * z;
+    uint64_t xtotal = nx ? xoff[nx] - xoff[0] : 0;
+    for (uint64_t i = 0; i < xtotal; i++)
+        if (lut[xchars[xoff[0] + i]] < 0) return -2;
+    uint8_t *xcodes = (uint8_t *)malloc(xtotal + 1);
+    for (uint64_t i = 0; i < xtotal; i++) xcodes[i] = (uint8_t)lut[xchars[xoff[0] + i]];
+    uint64_t rb = (uint64_t)L * (uint64_t)sigma;
+    uint8_t *Rbits = (uint8_t *)malloc(r * rb + 1);
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * T * m);
+    uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * T * m);
+    ejo_draw(seed, r, z, m, L, (uint32_t)sigma, Rbits, pos, v);
+    uint8_t *t = (uint8_t *)malloc(L);
+    for (uint32_t i = 0; i < nx; i++)
+        string_keys(xcodes + (xoff[i] - xoff[0]), (uint32_t)(xoff[i + 1] - xoff[i]), Rbits, rb,
+                    (uint32_t)sigma, L, pos, v, r, z, m, t, keys + (uint64_t)i * T);
+    free(xcodes);
+    free(Rbits);
+    free(pos);
+    free(v);
+    free(t);
+    return 0;
+}
+
+/* Verification only: min(ED, K+1) for each pair (a_k, b_k). */
 void ejo_verify_pairs(const uint8_t *chars, const uint64_t *offsets, const uint64_t *pairs,
                       uint64_t count, uint32_t K, uint32_t *dist) {
     for (uint64_t e = 0; e < count; e++) {

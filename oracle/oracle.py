@@ -36,7 +36,7 @@ def build(force: bool = True) -> str:
 class _Result(ctypes.Structure):
     _fields_ = [
         ("sigma", ctypes.c_uint32), ("L", ctypes.c_uint32),
-        ("n_cand", ctypes.c_uint64), ("cand", ctypes.POINTER(ctypes.c_uint64)),
+        ("n_raw", ctypes.c_uint64), ("n_cand", ctypes.c_uint64), ("cand", ctypes.POINTER(ctypes.c_uint64)),
         ("cand_dist", ctypes.POINTER(ctypes.c_uint32)),
         ("n_out", ctypes.c_uint64), ("out", ctypes.POINTER(ctypes.c_uint64)),
         ("out_dist", ctypes.POINTER(ctypes.c_uint32)),
@@ -82,6 +82,11 @@ def lib():
         L.ejo_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                ctypes.c_uint64, u8p, u32p, u64p, ctypes.POINTER(_Result)]
+        L.ejo_join_opts.restype = ctypes.c_int
+        L.ejo_join_opts.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                    ctypes.c_uint64, u8p, u32p, u64p, ctypes.c_uint32,
+                                    ctypes.POINTER(_Result)]
         L.ejo_result_free.restype = None
         L.ejo_result_free.argtypes = [ctypes.POINTER(_Result)]
         L.ejo_verify_pairs.restype = None
@@ -90,6 +95,10 @@ def lib():
         L.ejo_query.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, u32p,
                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.c_uint64, u64p, u32p, u32p, ctypes.c_uint64]
+        L.ejo_keys.restype = ctypes.c_int
+        L.ejo_keys.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32,
+                               ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                               ctypes.c_uint32, ctypes.c_uint64, u64p]
         L.ejo_brute_join.restype = ctypes.c_uint64
         L.ejo_brute_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
                                      u64p, u32p, ctypes.c_uint64, ctypes.c_int]
@@ -182,19 +191,34 @@ def effective_L(offsets, L_req: int) -> int:
 
 # -------------------------------------------------------------- the join --
 
+STOP_AFTER_CANDIDATES = 1
+NO_SIG = 2
+
+
+def _arr(ptr, count):
+    if not ptr or count == 0:
+        return None
+    return np.ctypeslib.as_array(ptr, (count,)).copy()
+
+
 class JoinResult:
     def __init__(self, res: _Result, n: int, r: int, z: int, m: int):
         self.sigma = int(res.sigma)
         self.L = int(res.L)
+        self.n_raw = int(res.n_raw)
         nc, no = int(res.n_cand), int(res.n_out)
-        self.cand = np.ctypeslib.as_array(res.cand, (max(nc, 1),))[:nc].copy()
-        self.cand_dist = np.ctypeslib.as_array(res.cand_dist, (max(nc, 1),))[:nc].copy()
-        self.out = np.ctypeslib.as_array(res.out, (max(no, 1),))[:no].copy()
-        self.out_dist = np.ctypeslib.as_array(res.out_dist, (max(no, 1),))[:no].copy()
         T = r * z
-        self.keys = np.ctypeslib.as_array(res.keys, (max(T * n, 1),))[:T * n].copy().reshape(T, n)
-        self.sig = np.ctypeslib.as_array(res.sig, (max(n * T * m, 1),))[:n * T * m].copy() \
-            .reshape(n, r, z, m)
+        empty = np.zeros(0, dtype=np.uint64)
+        self.cand = _arr(res.cand, nc) if nc else empty
+        cd = _arr(res.cand_dist, nc)
+        self.cand_dist = cd if cd is not None else np.zeros(0, dtype=np.uint32)
+        self.out = _arr(res.out, no) if no else empty
+        od = _arr(res.out_dist, no)
+        self.out_dist = od if od is not None else np.zeros(0, dtype=np.uint32)
+        keys = _arr(res.keys, T * n)
+        self.keys = keys.reshape(T, n) if keys is not None else np.zeros((T, n), np.uint64)
+        sig = _arr(res.sig, n * T * m)
+        self.sig = sig.reshape(n, r, z, m) if sig is not None else None
 
     @staticmethod
     def pairs(codes: np.ndarray) -> np.ndarray:
@@ -212,7 +236,9 @@ class JoinResult:
 
 
 def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
-         explicit_R=None, explicit_pos=None, explicit_v=None) -> JoinResult:
+         explicit_R=None, explicit_pos=None, explicit_v=None, opts: int = 0) -> JoinResult:
+    """The oracle's EmbedJoin.  opts: STOP_AFTER_CANDIDATES (the candidate set
+    only, `cand_dist`/`out` empty), NO_SIG (no sampled symbols kept)."""
     c = _u8(chars)
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     n = off.shape[0] - 1
@@ -220,18 +246,28 @@ def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int =
     eR = None if explicit_R is None else np.ascontiguousarray(explicit_R, dtype=np.uint8)
     eP = None if explicit_pos is None else np.ascontiguousarray(explicit_pos, dtype=np.uint32)
     eV = None if explicit_v is None else np.ascontiguousarray(explicit_v, dtype=np.uint64)
-    rc = lib().ejo_join(_ptr(c, ctypes.c_uint8) if c.size else None,
-                        _ptr(off, ctypes.c_uint64), n, K, r, z, m, L, seed,
-                        None if eR is None else _ptr(eR, ctypes.c_uint8),
-                        None if eP is None else _ptr(eP, ctypes.c_uint32),
-                        None if eV is None else _ptr(eV, ctypes.c_uint64),
-                        ctypes.byref(res))
+    rc = lib().ejo_join_opts(_ptr(c, ctypes.c_uint8) if c.size else None,
+                             _ptr(off, ctypes.c_uint64), n, K, r, z, m, L, seed,
+                             None if eR is None else _ptr(eR, ctypes.c_uint8),
+                             None if eP is None else _ptr(eP, ctypes.c_uint32),
+                             None if eV is None else _ptr(eV, ctypes.c_uint64),
+                             opts, ctypes.byref(res))
+    if rc == -2:
+        raise ValueError("all 256 byte values occur: no code is left for the padding symbol")
     if rc != 0:
         raise ValueError(f"oracle join rejected its arguments (rc={rc})")
     try:
         return JoinResult(res, n, r, z, m)
     finally:
         lib().ejo_result_free(ctypes.byref(res))
+
+
+def candidates(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0):
+    """Algorithm 3's candidate set C (sorted codes i << 32 | j) and the number of
+    pairs the tables found before de-duplication, from the same loop as join()
+    stopped before verification."""
+    res = join(chars, offsets, K, r, z, m, seed=seed, L=L, opts=STOP_AFTER_CANDIDATES | NO_SIG)
+    return res.cand, res.n_raw
 
 
 def verify_pairs(chars, offsets, pairs, K: int) -> np.ndarray:
@@ -264,6 +300,25 @@ def brute_join(chars, offsets, K: int, full: bool = False):
         cap = cnt
 
 
+def keys(index_chars, index_offsets, x_chars, x_offsets, r: int, z: int, m: int, seed: int = 0,
+         L: int = 0) -> np.ndarray:
+    """Bucket keys [nx, r*z] of the strings x under the alphabet, truncation
+    and random streams of the index set (x may be the index itself)."""
+    ic, xc = _u8(index_chars), _u8(x_chars)
+    io = np.ascontiguousarray(index_offsets, dtype=np.uint64)
+    xo = np.ascontiguousarray(x_offsets, dtype=np.uint64)
+    n, nx = io.shape[0] - 1, xo.shape[0] - 1
+    out = np.zeros(max(nx * r * z, 1), dtype=np.uint64)
+    rc = lib().ejo_keys(_ptr(ic, ctypes.c_uint8) if ic.size else None, _ptr(io, ctypes.c_uint64), n,
+                        _ptr(xc, ctypes.c_uint8) if xc.size else None, _ptr(xo, ctypes.c_uint64),
+                        nx, r, z, m, L, seed, _ptr(out, ctypes.c_uint64))
+    if rc == -2:
+        raise ValueError("a byte outside the index alphabet")
+    if rc != 0:
+        raise ValueError(f"invalid key arguments (rc={rc})")
+    return out[:nx * r * z].reshape(nx, r * z)
+
+
 def query(index_chars, index_offsets, q_chars, q_offsets, Kq, r: int, z: int, m: int,
           seed: int = 0, L: int = 0):
     """Serving semantics: per query, the index positions sharing a key with
@@ -289,6 +344,8 @@ def query(index_chars, index_offsets, q_chars, q_offsets, Kq, r: int, z: int, m:
                                   _ptr(d, ctypes.c_uint32), cap))
         if cnt == -2:
             raise ValueError("query byte outside the index alphabet")
+        if cnt == -3:
+            raise ValueError("all 256 byte values occur in the index")
         if cnt < 0:
             raise ValueError("invalid query arguments")
         if cnt <= cap:

@@ -1,25 +1,32 @@
 """GPU parity at the full sizes of the workloads, in the launch configuration
-the benchmark times (batched form: autotuned knobs, graph mode), on samples
-the oracle computes one by one:
-  * keys: the keys of sampled strings in every table equal the oracle's
-    (walk + two-level hash of that string alone);
-  * candidates: every sampled candidate shares an oracle key in some table
-    and is within K in length; every sampled planted or random pair that
-    shares an oracle key and is within K in length is a candidate;
-  * distances: sampled output pairs carry the oracle's exact distance, and
-    sampled candidates left out of the output are farther than K.
+the benchmark times (batched form: autotuned knobs, graph mode):
+  * candidates: the complete candidate list of the stage entry points, and the
+    join's candidate and raw-pair counts, equal the oracle's Algorithm 3 loop
+    stopped before verification (the oracle runs on the host meanwhile);
+  * output: the join's output equals the candidates whose GPU distance is
+    within K, with those distances;
+  * distances: a deterministic stratified sample of at least 5,000 candidates
+    carries the oracle's exact distance -- outputs, rejects, pairs long enough
+    to reach the second verification pass, the 100 longest texts, and pairs
+    at distance exactly K and exactly K + 1;
+  * keys: the keys of sampled strings in every table equal the oracle's;
+  * serving: the complete result lists of a batch of queries of the serving
+    mix equal the serving definition over the whole index, computed from the
+    oracle's keys and edit distances.
 The small configuration is checked in full in test_gpu_parity.py."""
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
 import synthdata as sd
+from tests._oracle_truth import oracle_dist as _oracle_dist, serving_truth
 
 pytestmark = pytest.mark.gpu
 
 N_SAMPLE_STRINGS = 24
-N_SAMPLE_PAIRS = 150
+PASS1_COLS = 1024     # the verification's default first-pass width
 
 
 def _say(msg):
@@ -41,28 +48,34 @@ def ctx(ej):
     return ej.Context(0)
 
 
-class OracleKeys:
-    """Keys of single strings under the oracle's random streams."""
+def _strata(rng, cand, d, d1, lens, K):
+    """Indexes of a stratified sample of the candidates (at least 5,000 when
+    there are that many), chosen from the GPU's distances; the expected
+    values come from the oracle alone."""
+    a = (cand >> np.uint64(32)).astype(np.int64)
+    b = (cand & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    short = np.minimum(lens[a], lens[b])
+    idx = np.arange(len(cand))
 
-    def __init__(self, oracle_lib, col, r, z, m, L_req, seed):
-        self.o = oracle_lib
-        self.sigma, self.lut = oracle_lib.alphabet(col.chars)
-        self.L = oracle_lib.effective_L(col.offsets, L_req)
-        self.Rb, self.pos, self.v = oracle_lib.draw(seed, r, z, m, self.L, self.sigma)
-        self.col, self.r, self.z = col, r, z
-        self.cache = {}
+    def pick(mask, k):
+        sel = idx[mask]
+        return sel if len(sel) <= k else rng.choice(sel, size=k, replace=False)
 
-    def __call__(self, i):
-        if i not in self.cache:
-            s = self.col.chars[int(self.col.offsets[i]):int(self.col.offsets[i + 1])]
-            codes = self.lut[s].astype(np.uint8)
-            keys = []
-            for l in range(self.r):
-                t = self.o.cgk_embed(codes, self.Rb[l], self.sigma, self.L)
-                for j in range(self.z):
-                    keys.append(self.o.key(t, self.pos[l, j], self.v[l, j]))
-            self.cache[i] = np.array(keys, dtype=np.uint64)
-        return self.cache[i]
+    parts = {
+        "outputs": pick(d <= K, 1500),
+        "rejects": pick(d > K, 1500),
+        "second pass": pick(short > PASS1_COLS, 700),
+        "longest": idx[np.argsort(-short, kind="stable")[:100]],
+        "exactly K": pick(d == K, 300),
+        "exactly K+1": pick(d1 == K + 1, 300),
+        "uniform": pick(np.ones(len(cand), bool), 1000),
+    }
+    chosen = np.unique(np.concatenate(list(parts.values())))
+    if len(chosen) < min(5000, len(cand)):
+        rest = np.setdiff1d(idx, chosen)
+        chosen = np.union1d(chosen, rng.choice(rest, size=min(len(rest), 5000 - len(chosen)),
+                                               replace=False))
+    return chosen, {k: len(v) for k, v in parts.items()}
 
 
 def _check_workload(ej, ctx, oracle_lib, col, K, r, z, m, L, seed=0):
@@ -73,76 +86,73 @@ def _check_workload(ej, ctx, oracle_lib, col, K, r, z, m, L, seed=0):
     chars = torch.from_numpy(col.chars).cuda()
     offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
     before = ctx.knobs()
-    try:
-        # the benchmark's batched form
-        _say(f"autotune n={n} K={K} r={r} z={z} m={m} L={L}")
-        ctx.autotune(chars, offs, K, r, z, m, seed=seed, L=L, reps=1)
-        knobs = ctx.knobs()
-        flags = ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0
-        _say(f"join knobs={knobs}")
-        res = ctx.join(chars, offs, K, r, z, m, seed=seed, L=L, flags=flags)
-        # the same candidates through the stage entry points
-        keys, _, L_used, sigma = ctx.embed(chars, offs, r, z, m, seed=seed, L=L)
-        d_len = torch.from_numpy(lens.astype(np.int32)).cuda()
-        ids, gstart = ctx.lsh_bucket(keys, d_len)
-        cand, _ = ctx.candidates(keys, ids, gstart, d_len, K)
-        cand = cand.cpu().numpy().astype(np.uint64)
-        _say(f"candidates={len(cand)} outputs={len(res.pairs)}")
-        assert res.n_candidates == len(cand)
-        ok = OracleKeys(oracle_lib, col, r, z, m, L, seed)
-        assert (L_used, sigma) == (ok.L, ok.sigma)
-        # keys of sampled strings, every table
-        sample = rng.choice(n, size=min(N_SAMPLE_STRINGS, n), replace=False)
-        gk = keys[:, torch.from_numpy(sample).cuda()].cpu().numpy().astype(np.uint64)
-        for c, i in enumerate(sample.tolist()):
-            assert np.array_equal(gk[:, c], ok(i)), f"keys of string {i}"
-        _say("sampled keys match")
-        cset = set(cand.tolist())
+    with ThreadPoolExecutor(1) as pool:
+        # the oracle's candidate set, computed on the host while the GPU works
+        fut = pool.submit(oracle_lib.candidates, col.chars, col.offsets, K, r, z, m, seed, L)
+        try:
+            _say(f"autotune n={n} K={K} r={r} z={z} m={m} L={L}")
+            ctx.autotune(chars, offs, K, r, z, m, seed=seed, L=L, reps=1)
+            knobs = ctx.knobs()
+            flags = ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0
+            _say(f"join knobs={knobs}")
+            res = ctx.join(chars, offs, K, r, z, m, seed=seed, L=L, flags=flags)
+            # the same candidates through the stage entry points
+            keys, _, L_used, sigma = ctx.embed(chars, offs, r, z, m, seed=seed, L=L)
+            d_len = torch.from_numpy(lens.astype(np.int32)).cuda()
+            ids, gstart = ctx.lsh_bucket(keys, d_len)
+            dcand, _ = ctx.candidates(keys, ids, gstart, d_len, K)
+            _say(f"candidates={dcand.numel()} outputs={len(res.pairs)}; verifying all")
+            d = ctx.verify(chars, offs, dcand, K).cpu().numpy()
+            d1 = ctx.verify(chars, offs, dcand, K + 1).cpu().numpy()
+            cand = dcand.cpu().numpy().astype(np.uint64)
+            key_ids = np.random.default_rng(999).choice(n, size=min(N_SAMPLE_STRINGS, n),
+                                                         replace=False)
+            gk = keys[:, torch.from_numpy(key_ids).cuda()].cpu().numpy().astype(np.uint64)
+        finally:
+            for k, v in before.items():
+                ctx.tune_set(k, v)
+        del dcand, keys
+        _say("waiting for the oracle's candidates")
+        ocand, oraw = fut.result()
+    # ---- complete candidate list and counts
+    assert len(cand) == len(ocand) and np.array_equal(cand, ocand), "candidate lists differ"
+    assert res.n_candidates == len(ocand) and res.n_raw == oraw
+    _say(f"complete candidate list equal ({len(ocand)} pairs, {oraw} raw)")
+    # ---- the join's output is the candidates within K, with their distances
+    within = d <= K
+    assert np.array_equal(res.codes, cand[within])
+    assert res.dist.tolist() == d[within].tolist()
+    assert np.array_equal(d1[within], d[within])          # a larger threshold changes no ED <= K
+    assert np.all(d[~within] == K + 1) and np.all(d1[~within] >= K + 1)
+    # ---- keys of sampled strings, every table
+    sigma_o, _ = oracle_lib.alphabet(col.chars)
+    assert (L_used, sigma) == (oracle_lib.effective_L(col.offsets, L), sigma_o)
+    okeys = oracle_lib.keys(col.chars, col.offsets, *_sub(col, key_ids), r, z, m, seed=seed, L=L)
+    assert np.array_equal(gk, okeys.T)
+    _say("sampled keys equal")
+    # ---- stratified exact distances
+    if len(cand):
+        sel, sizes = _strata(rng, cand, d, d1, lens, K)
+        _say(f"oracle distances of {len(sel)} candidates: {sizes}")
+        want = _oracle_dist(oracle_lib, col, cand[sel], K)
+        assert np.array_equal(d[sel].astype(np.uint32), want)
+        k1 = sel[d1[sel] == K + 1]
+        if len(k1):
+            assert np.all(_oracle_dist(oracle_lib, col, cand[k1], K + 1) == K + 1)
+        _say("stratified distances equal")
+    return len(cand)
 
-        def shares_key(a, b):
-            return bool(np.any(ok(a) == ok(b)))
 
-        # sampled candidates are pairs the definition admits
-        for c in rng.choice(cand, size=min(N_SAMPLE_PAIRS // 3, len(cand)), replace=False):
-            a, b = int(c) >> 32, int(c) & 0xFFFFFFFF
-            assert a < b and abs(int(lens[a]) - int(lens[b])) <= K and shares_key(a, b)
-        # sampled planted and random pairs the definition admits are candidates
-        planted = sd.planted_pairs(col)
-        pick = planted[rng.choice(len(planted), size=min(N_SAMPLE_PAIRS // 3, len(planted)),
-                                  replace=False)] if len(planted) else np.zeros((0, 2), np.int64)
-        rand = rng.integers(0, n, size=(N_SAMPLE_PAIRS // 3, 2))
-        for a, b in np.concatenate([pick, rand]).tolist():
-            if a == b:
-                continue
-            a, b = min(a, b), max(a, b)
-            admit = abs(int(lens[a]) - int(lens[b])) <= K and shares_key(a, b)
-            assert admit == (((a << 32) | b) in cset), f"pair {a},{b}"
-        _say("sampled candidates match the definition")
-        # distances: sampled outputs exact; sampled candidates not output exceed K
-        S = lambda i: col.chars[int(col.offsets[i]):int(col.offsets[i + 1])]
-        out_codes = set(((res.pairs[:, 0].astype(np.uint64) << np.uint64(32))
-                         | res.pairs[:, 1].astype(np.uint64)).tolist())
-        for t in rng.choice(len(res.pairs), size=min(N_SAMPLE_PAIRS // 3, len(res.pairs)),
-                            replace=False):
-            a, b = res.pairs[t]
-            assert oracle_lib.ed_banded(S(a), S(b), K) == int(res.dist[t]) <= K
-        left = [int(c) for c in cand.tolist() if int(c) not in out_codes]
-        for c in rng.choice(left, size=min(N_SAMPLE_PAIRS // 3, len(left)), replace=False) \
-                if left else []:
-            a, b = int(c) >> 32, int(c) & 0xFFFFFFFF
-            assert oracle_lib.ed_banded(S(a), S(b), K) > K
-        assert out_codes <= cset
-        _say("sampled distances match")
-    finally:
-        for k, v in before.items():
-            ctx.tune_set(k, v)
+def _sub(col, ids):
+    s = sd.from_strings([col.string(int(i)) for i in ids])
+    return s.chars, s.offsets
 
 
 def test_medium_full_size(ej, ctx, oracle_lib):
     """20,000 DNA strings (2,000 bases x 10 copies, 4.5-5.5k), K=500 at the
     recall-calibrated point the benchmark quotes."""
     col, prm = sd.medium_dna(0, K=500)
-    _check_workload(ej, ctx, oracle_lib, col, 500, 32, 16, 18, 64)
+    assert _check_workload(ej, ctx, oracle_lib, col, 500, 32, 16, 18, 64) > 5000
 
 
 def test_medium_k250_stated(ej, ctx, oracle_lib):
@@ -155,22 +165,25 @@ def test_uneven_full_size(ej, ctx, oracle_lib):
     """80,000 DNA strings of log-uniform lengths 500..20,000, K=400, at the
     recall-calibrated point."""
     col, prm = sd.uneven_dna(0)
-    _check_workload(ej, ctx, oracle_lib, col, 400, 32, 16, 18, 64)
+    assert _check_workload(ej, ctx, oracle_lib, col, 400, 32, 16, 18, 64) > 5000
 
 
 def test_protein_full_size(ej, ctx, oracle_lib):
     """400,000 strings over 25 Zipf letters, lengths lognormal(400, 0.8),
-    K=100 at the stated r=5, z=10, m=32 with L = ceil(2 avg)."""
+    K=100 at the stated r=5, z=10, m=32 with L = ceil(2 avg): about 10^8
+    candidates, whose 64-bit pair codes take the sort-based de-duplication."""
     col, prm = sd.protein_like(0)
     L = int(np.ceil(2 * col.lengths().mean()))
-    _check_workload(ej, ctx, oracle_lib, col, prm["K"], prm["r"], prm["z"], prm["m"], L)
+    assert _check_workload(ej, ctx, oracle_lib, col, prm["K"], prm["r"], prm["z"], prm["m"],
+                           L) > 5000
 
 
 def test_serving_full_size(ej, ctx, oracle_lib):
-    """Index over 320,000 DNA strings; a batch of sampled queries of the
-    serving mix: every returned id shares an oracle key with the query and is
-    within K_q in length and edit distance; a re-mutated query's source is
-    returned whenever it shares a key and is within K_q."""
+    """Index over 320,000 DNA strings; 400 queries of the serving mix.  Each
+    query's complete result list equals the definition over the whole index:
+    every string that shares the oracle's key with the query in some table,
+    is within K_q in length, and is within K_q in edit distance (oracle),
+    sorted by position."""
     col, _ = sd.serving_index(0)
     q, Kq, src = sd.serving_queries(col, 0, n_queries=400)
     r, z, m, L, seed = 32, 8, 20, 64, 0
@@ -180,36 +193,14 @@ def test_serving_full_size(ej, ctx, oracle_lib):
     _say(f"serving index n={col.n}")
     ix = ej.Index(ctx, chars, offs, r, z, m, seed=seed, L=L)
     res = ix.query(q.chars, q.offsets.astype(np.uint64), Kq)
-    ok = OracleKeys(oracle_lib, col, r, z, m, L, seed)
-    # the queries are embedded with the index's alphabet, truncation and streams
-    qcodes = ok.lut[q.chars].astype(np.uint8)
-
-    def qkeys(i):
-        s = qcodes[int(q.offsets[i]):int(q.offsets[i + 1])]
-        out = []
-        for l in range(r):
-            t = oracle_lib.cgk_embed(s, ok.Rb[l], ok.sigma, ok.L)
-            for j in range(z):
-                out.append(oracle_lib.key(t, ok.pos[l, j], ok.v[l, j]))
-        return np.array(out, dtype=np.uint64)
-
-    S = lambda i: col.chars[int(col.offsets[i]):int(col.offsets[i + 1])]
-    Q = lambda i: q.chars[int(q.offsets[i]):int(q.offsets[i + 1])]
-    rng = np.random.default_rng(7)
-    checked = 0
-    for qi in rng.choice(q.n, size=60, replace=False).tolist():
-        ids, dist = res.of(qi)
-        assert list(ids) == sorted(ids)
-        kq = qkeys(qi)
-        for s, d in zip(ids.tolist(), dist.tolist()):
-            assert abs(len(Q(qi)) - len(S(s))) <= Kq[qi]
-            assert np.any(ok(s) == kq)
-            assert oracle_lib.ed_banded(Q(qi), S(s), int(Kq[qi])) == d <= Kq[qi]
-        if src[qi] >= 0:
-            s = int(src[qi])
-            admit = (abs(len(Q(qi)) - len(S(s))) <= Kq[qi] and np.any(ok(s) == kq)
-                     and oracle_lib.ed_banded(Q(qi), S(s), int(Kq[qi])) <= Kq[qi])
-            assert admit == (s in set(ids.tolist())), f"query {qi} source {s}"
-        checked += 1
-    _say(f"serving: {checked} sampled queries match")
     ix.close()
+    _say("serving definition over the whole index (oracle keys and distances)")
+    want, n_admitted = serving_truth(oracle_lib, col, q, Kq, r, z, m, seed, L)
+    found_src = 0
+    for qi in range(q.n):
+        ids, dist = res.of(qi)
+        assert ids.tolist() == want[qi][0], f"query {qi}"
+        assert dist.tolist() == want[qi][1], f"query {qi}"
+        found_src += int(src[qi] >= 0 and int(src[qi]) in want[qi][0])
+    assert res.n_candidates == n_admitted
+    _say(f"serving: all {q.n} result lists equal ({found_src} sources found)")

@@ -54,6 +54,126 @@ def test_coordinates_uniform(oracle_lib):
     assert chi2 < 118
 
 
+class SpecRNG:
+    """The randomness layout written out a second time, in plain Python
+    integers, from its specification alone: W(key, c) is the (c+1)-th output of
+    a SplitMix64 generator seeded with key; stream keys are W(seed, tag << 32 |
+    idx) (tag 0: the random string of seed l, idx l; tag 1: coordinates of
+    table (l, j), idx l z + j; tag 2: second-level vector of that table); bit b
+    of R^l is bit b mod 64 of W(key_R, floor(b / 64)); coordinate k is
+    floor(W(key_POS, k) L / 2^64); v_k = (W(key_V, k) >> 3) mod (2^61 - 1).
+    The generator is stepped sequentially here (state += gamma, then the
+    output mix), not through the oracle's counter form."""
+
+    M64 = (1 << 64) - 1
+
+    @classmethod
+    def stream(cls, seed, count):
+        out, s = [], seed
+        for _ in range(count):
+            s = (s + 0x9E3779B97F4A7C15) & cls.M64
+            z = s
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & cls.M64
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & cls.M64
+            out.append(z ^ (z >> 31))
+        return out
+
+    @classmethod
+    def key(cls, seed, tag, idx):
+        # word number (tag << 32 | idx) of the seed's stream: step the state
+        # that many times at once (a Weyl sequence), then mix
+        c = (tag << 32) | idx
+        s = (seed + (c + 1) * 0x9E3779B97F4A7C15) & cls.M64
+        z = ((s ^ (s >> 30)) * 0xBF58476D1CE4E5B9) & cls.M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & cls.M64
+        return z ^ (z >> 31)
+
+    @classmethod
+    def r_bits(cls, seed, l, nbits):
+        words = cls.stream(cls.key(seed, 0, l), (nbits + 63) // 64)
+        return [(words[b // 64] >> (b % 64)) & 1 for b in range(nbits)]
+
+    @classmethod
+    def coords(cls, seed, l, j, z, m, L):
+        words = cls.stream(cls.key(seed, 1, l * z + j), m)
+        return [(w * L) >> 64 for w in words]
+
+    @classmethod
+    def vvec(cls, seed, l, j, z, m):
+        words = cls.stream(cls.key(seed, 2, l * z + j), m)
+        return [(w >> 3) % ((1 << 61) - 1) for w in words]
+
+
+def test_spec_rng_reproduces_published_vector():
+    # the second implementation is itself pinned to the published outputs
+    g = _load("splitmix64.json")
+    assert SpecRNG.stream(g["seed"], len(g["outputs"])) == [int(x) for x in g["outputs"]]
+
+
+@pytest.mark.parametrize("seed,r,z,m,L,sigma", [(0, 2, 3, 5, 40, 4), (0xC0FFEE, 3, 2, 7, 1000, 25),
+                                               (1 << 63, 1, 4, 3, 7, 2)])
+def test_randomness_layout_matches_its_specification(oracle_lib, seed, r, z, m, L, sigma):
+    # catches a swapped stream tag, an MSB-first bit order, v = W mod P, a
+    # floor-vs-high-product coordinate, or l*z+j vs j*r+l table numbering
+    R, pos, v = oracle_lib.draw(seed, r, z, m, L, sigma)
+    for l in range(r):
+        assert R[l].tolist() == SpecRNG.r_bits(seed, l, L * sigma), f"R bits of seed {l}"
+        for j in range(z):
+            assert pos[l, j].tolist() == SpecRNG.coords(seed, l, j, z, m, L), f"pos ({l},{j})"
+            assert [int(x) for x in v[l, j]] == SpecRNG.vvec(seed, l, j, z, m), f"v ({l},{j})"
+
+
+def test_randomness_golden_values(oracle_lib):
+    # a few values written out once from the specification by hand-checkable
+    # integer arithmetic: the first R word of seed 0 and its low bits
+    w0 = SpecRNG.stream(SpecRNG.key(0, 0, 0), 1)[0]
+    R, _, _ = oracle_lib.draw(0, 1, 1, 1, 16, 4)
+    assert R[0].tolist() == [(w0 >> b) & 1 for b in range(64)]
+
+
+# ------------------------------------------------------------ truncation --
+
+def _offsets(lengths):
+    o = np.zeros(len(lengths) + 1, dtype=np.uint64)
+    o[1:] = np.cumsum(lengths)
+    return o
+
+
+@pytest.mark.parametrize("lengths,L_req,expect", [
+    ([3, 4], 0, 4),            # average 3.5: the ceiling, not the floor (3)
+    ([1, 1, 2], 0, 2),         # average 4/3 -> 2
+    ([5, 5], 0, 5),            # an exact average stays
+    ([2, 5], 100, 15),         # a requested L above 3N is clamped to 3N = 15
+    ([2, 5], 15, 15),          # 3N itself is allowed
+    ([2, 5], 7, 7),            # a requested L below 3N is kept
+    ([0, 0, 0], 0, 1),         # all empty: 3N = 0, raised to the floor of 1
+    ([], 0, 1),                # no strings at all
+    ([0, 0], 9, 1),            # a request on empty strings: clamped to 0, then 1
+])
+def test_effective_truncation(oracle_lib, lengths, L_req, expect):
+    assert oracle_lib.effective_L(_offsets(lengths), L_req) == expect
+
+
+def test_join_uses_effective_truncation(oracle_lib):
+    col = sd.from_strings([b"ACG", b"ACGT"])
+    assert oracle_lib.join(col.chars, col.offsets, 1, 1, 1, 1).L == 4
+    assert oracle_lib.join(col.chars, col.offsets, 1, 1, 1, 1, L=50).L == 12
+
+
+# ------------------------------------------------------------- alphabet --
+
+def test_full_byte_alphabet_is_rejected(oracle_lib):
+    # with all 256 byte values present no code is left for the padding symbol
+    col = sd.from_strings([bytes(range(256)), b"AB"])
+    with pytest.raises(ValueError):
+        oracle_lib.join(col.chars, col.offsets, 2, 1, 1, 1)
+    q = sd.from_strings([b"AB"])
+    with pytest.raises(ValueError):
+        oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, [1], 1, 1, 1)
+    col255 = sd.from_strings([bytes(range(255)), b"AB"])
+    assert oracle_lib.join(col255.chars, col255.offsets, 2, 1, 1, 1).sigma == 255
+
+
 # -------------------------------------------------- running example ----
 
 def _running_example_randomness(g):
@@ -322,6 +442,15 @@ def test_candidates_equal_definition(oracle_lib, seed, K, r, z, m, L):
                       lambda rr, LL: rr.poisson(3))
     res = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
     assert set(map(tuple, res.cand_pairs.tolist())) == _brute_candidates(col, res.keys, K)
+    # pairs found before de-duplication: one per table in which the pair's
+    # keys agree (and the lengths are within K)
+    lens = col.lengths()
+    raw = sum(int((res.keys[:, a] == res.keys[:, b]).sum())
+              for a in range(col.n) for b in range(a + 1, col.n) if abs(lens[a] - lens[b]) <= K)
+    assert res.n_raw == raw
+    # the candidates-only mode is the same loop stopped before verification
+    cand, n_raw = oracle_lib.candidates(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
+    assert cand.tolist() == res.cand.tolist() and n_raw == raw
 
 
 def test_buckets_by_key_equal_buckets_by_signature(oracle_lib):
@@ -425,3 +554,29 @@ def test_query_results_are_true_matches(oracle_lib):
     with pytest.raises(ValueError):
         bad = sd.from_strings([b"ACGZ"])
         oracle_lib.query(col.chars, col.offsets, bad.chars, bad.offsets, [1], 2, 2, 2)
+
+
+def test_keys_of_a_set_equal_the_joins_keys(oracle_lib):
+    col = sd.clusters(21, 10, lambda rr, b: 3, lambda rr: rr.integers(5, 60),
+                      lambda rr, L: rr.poisson(2))
+    res = oracle_lib.join(col.chars, col.offsets, 5, 3, 4, 5, seed=2, L=30)
+    k = oracle_lib.keys(col.chars, col.offsets, col.chars, col.offsets, 3, 4, 5, seed=2, L=30)
+    assert np.array_equal(k.T, res.keys)
+    q = sd.from_strings([b"ACGTTT", b"QQ"])
+    with pytest.raises(ValueError):
+        oracle_lib.keys(col.chars, col.offsets, q.chars, q.offsets, 3, 4, 5)
+
+
+def test_serving_truth_equals_the_query_definition(oracle_lib):
+    # the threaded, sorted-key form of the serving definition that the
+    # full-size GPU test uses equals the oracle's plain double loop
+    from tests._oracle_truth import serving_truth
+    col, _ = sd.serving_index(3, n_bases=40, copies=4)
+    q, Kq, _ = sd.serving_queries(col, 3, n_queries=30)
+    want, _ = serving_truth(oracle_lib, col, q, Kq, 6, 4, 6, 1, 40)
+    off, ids, dist = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, 6, 4, 6,
+                                      seed=1, L=40)
+    assert sum(len(w[0]) for w in want) > 0
+    for qi in range(q.n):
+        lo, hi = int(off[qi]), int(off[qi + 1])
+        assert want[qi][0] == ids[lo:hi].tolist() and want[qi][1] == dist[lo:hi].tolist()
