@@ -245,6 +245,25 @@ ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offse
                     const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
                     int32_t *d_dist);
 
+/* ej_verify for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as ej_verify; it calls no device allocator.
+ * Its workspace (symbol codes, match masks, counters) is carved from one
+ * static device array of 64 MiB per GPU, which each GPU the library runs on
+ * holds from the first context created on it until the process ends.  Inputs
+ * whose workspace exceeds it are refused with EJ_ENOMEM before any
+ * distance is written (a DNA set needs about 1.3 bytes per character plus 24
+ * bytes per string; 25 letters about 4.2 bytes per character); use ej_verify
+ * for those.  The two-pass verification form ("verify_mode" 0) runs as the
+ * persistent form, which needs no per-pair state; no result changes.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind: calls that overlap on one GPU (from several host threads, or on
+ * several contexts' streams without ordering between them) race, and the
+ * caller must serialise them. */
+ej_status ej_verify_static(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                           uint32_t n, const uint64_t *d_pairs, uint64_t count, uint32_t K,
+                           const uint32_t *d_Kq, int32_t *d_dist);
+
 /* Test hook: replace the drawn randomness of the next calls by explicit
  * values (host arrays): Rbits [r][L*sigma] 0/1 bytes (pi_j(sigma_k) at
  * (j-1)*sigma + k-1), pos [r][z][m] coordinates < L, v [r][z][m] values

@@ -28,7 +28,8 @@ EXPORTS = [
     "ej_create", "ej_destroy", "ej_last_error", "ej_version", "ej_workspace_bytes",
     "ej_tune_set", "ej_tune_get",
     "ej_join", "ej_join_ex", "ej_join_device", "ej_result_free", "ej_autotune",
-    "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_set_explicit_randomness",
+    "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_verify_static",
+    "ej_set_explicit_randomness",
     "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
     "ej_index_size", "ej_qresult_free", "ej_index_free",
 ]
@@ -98,6 +99,7 @@ def lib():
         "ej_lsh_bucket": (c_int, [vp, vp, vp, u32, u32, u32, vp, vp, u64p]),
         "ej_candidates": (c_int, [vp, vp, vp, vp, u64, vp, u32, u32, u32, vp, u64, u64p, u64p]),
         "ej_verify": (c_int, [vp, vp, vp, u32, vp, u64, u32, vp, vp]),
+        "ej_verify_static": (c_int, [vp, vp, vp, u32, vp, u64, u32, vp, vp]),
         "ej_set_explicit_randomness": (c_int, [vp, u32, u32, u32, u32, u32, vp, vp, vp]),
         "ej_index_build": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), c_int,
                                    ctypes.POINTER(vp)]),
@@ -325,16 +327,21 @@ class Context:
             self._check(st)
             return out[:int(cnt.value)], int(raw.value)
 
-    def verify(self, d_chars, d_offsets, d_pairs, K: int, d_Kq=None):
-        """A5.  Returns int32 distances, min(ED, K+1) per pair."""
+    def verify(self, d_chars, d_offsets, d_pairs, K: int, d_Kq=None, dist=None,
+               no_alloc: bool = False):
+        """A5.  Returns int32 distances, min(ED, K+1) per pair.  With
+        no_alloc, ej_verify_static (no device allocation inside the library;
+        `dist` may be given to avoid torch's allocation too)."""
         torch = _torch()
         n = d_offsets.numel() - 1
         cnt = d_pairs.numel()
-        dist = torch.empty(max(cnt, 1), dtype=torch.int32, device=d_offsets.device)
+        if dist is None:
+            dist = torch.empty(max(cnt, 1), dtype=torch.int32, device=d_offsets.device)
+        fn = lib().ej_verify_static if no_alloc else lib().ej_verify
         _torch_stream_done()
-        self._check(lib().ej_verify(self._h, _ptr(d_chars) if d_chars.numel() else None,
-                                    _ptr(d_offsets), n, _ptr(d_pairs) if cnt else None, cnt, K,
-                                    _ptr(d_Kq), _ptr(dist)))
+        self._check(fn(self._h, _ptr(d_chars) if d_chars.numel() else None,
+                       _ptr(d_offsets), n, _ptr(d_pairs) if cnt else None, cnt, K,
+                       _ptr(d_Kq), _ptr(dist)))
         return dist[:cnt]
 
     def set_explicit_randomness(self, r, z, m, L, sigma, Rbits=None, pos=None, v=None):

@@ -1,16 +1,75 @@
 // Context, workspace and error plumbing of the C ABI.
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "ej_internal.h"
 
 namespace ej {
 
+// Scratch memory of ej_verify_static, for callers that cannot allocate: one
+// array per device, held from the library's first use on that device until
+// the process ends.  Host code never passes `scratch` itself to a kernel or a
+// copy (its host-side name is a stand-in, not a device address); it uses the
+// address that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) uint8_t scratch[STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Called by ej_create with the context's device current.  A failed lookup
+// is kept as the device's error and reported by ej_verify_static; the other
+// entry points do not need the array.
+hipError_t g_scratch_err[MAX_DEVICES] = {};
+
+void static_scratch_init(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        (void)hipGetLastError();
+        return;
+    }
+    g_scratch_ptr[device] = p;
+}
+}  // namespace
+
+void *static_scratch(ej_ctx *ctx) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (ctx->device < 0 || ctx->device >= MAX_DEVICES)
+        fail(EJ_EUNSUPPORTED, "no static scratch for device " + std::to_string(ctx->device));
+    if (!g_scratch_ptr[ctx->device])
+        fail(EJ_EHIP, std::string("hipGetSymbolAddress of the static scratch array failed: ") +
+                          hipGetErrorString(g_scratch_err[ctx->device]));
+    return g_scratch_ptr[ctx->device];
+}
+
 void fail(ej_status code, const std::string &msg) { throw Error{code, msg}; }
+
+static void *arena_get(ej_ctx *ctx, const std::string &name, size_t bytes) {
+    Arena &a = ctx->arena;
+    auto it = a.named.find(name);
+    if (it != a.named.end() && it->second.second >= bytes) return a.base + it->second.first;
+    const size_t off = (a.used + 255) & ~(size_t)255;
+    if (off > a.cap || bytes > a.cap - off)
+        fail(EJ_ENOMEM, "the call needs more than the " + std::to_string(a.cap >> 20) +
+                            " MiB of static scratch (buffer '" + name + "' of " +
+                            std::to_string(bytes) + " bytes at offset " + std::to_string(off) +
+                            "); use the allocating entry point for inputs this large");
+    a.used = off + bytes;
+    a.named[name] = {off, bytes};
+    return a.base + off;
+}
 
 void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes) {
     if (bytes == 0) bytes = 16;
+    if (ctx->arena.base) return arena_get(ctx, name, bytes);
     DevBuf &b = ctx->ws[name];
     if (b.bytes < bytes) {
         if (b.p) {
@@ -106,6 +165,7 @@ ej_status ej_create(ej_ctx **out, int device, void *hip_stream) {
         EJ_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
         ctx->lds_max = lds;
         EJ_HIP(hipHostMalloc((void **)&ctx->pinned, 4096, hipHostMallocDefault));
+        static_scratch_init(device);
         for (int i = 0; i < 8; i++) EJ_HIP(hipEventCreate(&ctx->timers.ev[i]));
         for (int i = 0; i < 4; i++) EJ_HIP(hipEventCreate(&ctx->timers.kv[i]));
     } catch (const Error &e) {

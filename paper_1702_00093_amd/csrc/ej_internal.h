@@ -75,6 +75,15 @@ struct Explicit {
     std::vector<uint64_t> v;       // [r][z][m] (empty: drawn)
 };
 
+// Workspace carved from one fixed device buffer instead of grown with
+// hipMalloc (active while `base` is set): a bump allocator whose regions are
+// keyed by name, so that a name asked for twice gets the same memory.
+struct Arena {
+    uint8_t *base = nullptr;
+    size_t cap = 0, used = 0;
+    std::map<std::string, std::pair<size_t, size_t>> named;  // name -> (offset, bytes)
+};
+
 struct Timers {
     hipEvent_t ev[8] = {};
     // around each launch of the verification kernel while `on`
@@ -116,6 +125,7 @@ struct ej_ctx {
     size_t pinned_out_bytes = 0;
     ej::Timers timers;
     ej::Tuning tune;
+    ej::Arena arena;             // set only inside ej_verify_static
     // EJ_FLAG_GRAPH: graphs of fixed launch sequences, keyed by every
     // argument of their launches (pointers included), replayed on a match
     bool graph_on = false;
@@ -126,6 +136,11 @@ struct ej_ctx {
 namespace ej {
 
 void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes);
+// Size of the static scratch array of ej_verify_static (one per device).
+constexpr size_t STATIC_SCRATCH_BYTES = 64ull << 20;
+// Device address of the context device's static scratch array, looked up
+// once per device when a context is created.
+void *static_scratch(ej_ctx *ctx);
 // Bytes the workspace buffer `name` holds now (0 if it does not exist).
 size_t ws_capacity(ej_ctx *ctx, const std::string &name);
 template <typename T>

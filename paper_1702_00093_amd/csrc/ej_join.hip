@@ -270,6 +270,32 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     }
 }
 
+// ej_verify's work: preparation of the strings, their match masks and the
+// verification kernels, on the context's workspace.
+void verify_entry(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                  const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
+                  int32_t *d_dist) {
+    if (!d_Kq && verify_lanes_for(K) == 0) fail(EJ_EUNSUPPORTED, "K above 2046 is not supported");
+    Prep pp;
+    prepare(ctx, d_chars, d_offsets, n, 0, pp, "v", nullptr, 0, 0, false);
+    if (count) {
+        uint32_t *d_bad = ws<uint32_t>(ctx, "v_bad", 1);
+        EJ_HIP(hipMemsetAsync(d_bad, 0, 4, ctx->stream));
+        hipLaunchKernelGGL(k_check_pairs, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
+                           ctx->stream, d_pairs, count, n, n, d_bad);
+        EJ_CHECK_LAUNCH();
+        uint32_t bad = 0;
+        read_back(ctx, d_bad, 4, &bad);
+        if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
+    }
+    RowMasks masks;
+    if (count)
+        build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "v");
+    verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, d_pairs, count, K,
+           d_Kq, d_dist);
+    sync(ctx);
+}
+
 }  // namespace ej
 
 using namespace ej;
@@ -509,27 +535,35 @@ ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offse
                     const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
                     int32_t *d_dist) {
     if (!d_offsets || (count && (!d_pairs || !d_dist))) return EJ_EINVAL;
+    return run_guarded(ctx, [&] { verify_entry(ctx, d_chars, d_offsets, n, d_pairs, count, K, d_Kq, d_dist); });
+}
+
+ej_status ej_verify_static(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                           uint32_t n, const uint64_t *d_pairs, uint64_t count, uint32_t K,
+                           const uint32_t *d_Kq, int32_t *d_dist) {
+    if (!d_offsets || (count && (!d_pairs || !d_dist))) return EJ_EINVAL;
     return run_guarded(ctx, [&] {
-        if (!d_Kq && verify_lanes_for(K) == 0)
-            fail(EJ_EUNSUPPORTED, "K above 2046 is not supported");
-        Prep pp;
-        prepare(ctx, d_chars, d_offsets, n, 0, pp, "v", nullptr, 0, 0, false);
-        if (count) {
-            uint32_t *d_bad = ws<uint32_t>(ctx, "v_bad", 1);
-            EJ_HIP(hipMemsetAsync(d_bad, 0, 4, ctx->stream));
-            hipLaunchKernelGGL(k_check_pairs, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
-                               ctx->stream, d_pairs, count, n, n, d_bad);
-            EJ_CHECK_LAUNCH();
-            uint32_t bad = 0;
-            read_back(ctx, d_bad, 4, &bad);
-            if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
-        }
-        RowMasks masks;
-        if (count)
-            build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "v");
-        verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, d_pairs, count, K,
-               d_Kq, d_dist);
-        sync(ctx);
+        uint8_t *base = (uint8_t *)static_scratch(ctx);
+        // sizes known before anything is enqueued: lengths and mask offsets
+        if (24ull * ((uint64_t)n + 1) + 4096 > STATIC_SCRATCH_BYTES)
+            fail(EJ_ENOMEM, std::to_string(n) + " strings exceed the " +
+                                std::to_string(STATIC_SCRATCH_BYTES >> 20) +
+                                " MiB of static scratch");
+        // every workspace request of this call is carved from the scratch
+        // array; the two-pass form (saved state per pair) becomes the
+        // persistent form, which needs only a counter
+        struct Scope {
+            ej_ctx *c;
+            uint32_t mode;
+            ~Scope() {
+                c->arena = Arena();
+                c->tune.verify_mode = mode;
+            }
+        } scope{ctx, ctx->tune.verify_mode};
+        ctx->arena.base = base;
+        ctx->arena.cap = STATIC_SCRATCH_BYTES;
+        if (ctx->tune.verify_mode == 0) ctx->tune.verify_mode = 1;
+        verify_entry(ctx, d_chars, d_offsets, n, d_pairs, count, K, d_Kq, d_dist);
     });
 }
 
