@@ -289,6 +289,9 @@ typedef struct {
     int32_t *dist;         /* host, edit distances */
     uint64_t n_candidates; /* (query, index) pairs verified */
     float ms_total;        /* device time of the batch */
+    uint64_t workspace_bytes; /* the batch's admission figure: the estimate before
+                                 embedding plus the candidate and verification
+                                 stages' bytes once their counts were known */
 } ej_qresult;
 
 /* Builds the index from host (on_device = 0) or device (1) strings.  p->K is
@@ -299,11 +302,17 @@ ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *of
  * Query i is q[q_offsets[i] .. q_offsets[i+1]); q_offsets[0] need not be 0,
  * so a batch can be a window of a larger buffer.
  * EJ_EALPHABET if a query byte is outside the index alphabet; EJ_ENOMEM if
- * the batch's workspace estimate exceeds the free HBM (or the admission
- * limit set with ej_index_set_hbm_limit). */
+ * the batch's workspace exceeds the free HBM at the call (or the admission
+ * limit set with ej_index_set_hbm_limit).  Admission is checked three times,
+ * each before the memory it counts is requested: with the estimate of
+ * ej_query_workspace_estimate, again once the candidate count before
+ * de-duplication is known, and again once the de-duplicated count (and so
+ * verification's state and the query masks) is known; a refused batch
+ * leaves the index usable. */
 ej_status ej_query_batch(ej_index *index, const uint8_t *q, const uint64_t *q_offsets,
                          uint32_t nq, const uint32_t *Kq, ej_qresult *out);
-/* Bytes of device memory the batch would need (admission estimate). */
+/* Bytes of device memory the batch needs before its candidates are known
+ * (the first admission check). */
 uint64_t ej_query_workspace_estimate(const ej_index *index, const uint64_t *q_offsets,
                                      uint32_t nq, const uint32_t *Kq);
 /* Caps the HBM the index may use for a batch (0 = free HBM reported by HIP). */

@@ -62,7 +62,8 @@ class _Result(ctypes.Structure):
 class _QResult(ctypes.Structure):
     _fields_ = [("nq", ctypes.c_uint32), ("offsets", ctypes.POINTER(ctypes.c_uint64)),
                 ("ids", ctypes.POINTER(ctypes.c_uint32)), ("dist", ctypes.POINTER(ctypes.c_int32)),
-                ("n_candidates", ctypes.c_uint64), ("ms_total", ctypes.c_float)]
+                ("n_candidates", ctypes.c_uint64), ("ms_total", ctypes.c_float),
+                ("workspace_bytes", ctypes.c_uint64)]
 
 
 _lib = None
@@ -365,6 +366,7 @@ class QueryResult:
     dist: np.ndarray           # edit distances
     n_candidates: int          # (query, index string) pairs verified
     ms: float                  # device time of the batch
+    workspace_bytes: int = 0   # the batch's admission figure (estimate + counted stages)
 
     def of(self, q: int):
         lo, hi = int(self.offsets[q]), int(self.offsets[q + 1])
@@ -436,7 +438,8 @@ class Index:
                 np.zeros(0, dtype=np.uint32)
             dist = np.ctypeslib.as_array(res.dist, (max(tot, 1),))[:tot].copy() if tot else \
                 np.zeros(0, dtype=np.int32)
-            return QueryResult(offs, ids, dist, int(res.n_candidates), float(res.ms_total))
+            return QueryResult(offs, ids, dist, int(res.n_candidates), float(res.ms_total),
+                               int(res.workspace_bytes))
         finally:
             lib().ej_qresult_free(ctypes.byref(res))
 

@@ -193,6 +193,8 @@ ej_status guarded(ej_ctx *ctx, F &&fn) {
     }
 }
 
+// Device bytes of a batch before its candidates are known (the admission
+// estimate of ej_query_workspace_estimate).
 uint64_t estimate(const ej_index *ix, uint64_t qbytes, uint32_t nq) {
     const uint64_t T = ix->T;
     uint64_t b = 0;
@@ -200,6 +202,25 @@ uint64_t estimate(const ej_index *ix, uint64_t qbytes, uint32_t nq) {
     b += (uint64_t)nq * (8 + 4 * 6);             // offsets, lengths, order, thresholds
     b += T * nq * (8 + 8 + 8);                   // keys, counts, scan
     b += T * nq * 4 * 8;                         // expected candidates (a few per table)
+    return b;
+}
+
+// Bytes of the candidate stage once the raw (pre-de-duplication) count is
+// known: raw codes, their sorted copy and the radix sort's scratch, unique
+// flags and positions, then the pairs and thresholds.
+uint64_t probe_bytes(uint64_t raw) { return raw * (8 + 8 + 8 + 4 + 4 + 8 + 4); }
+
+// Bytes of verification and output once the de-duplicated count is known:
+// distances, the queries' match masks, the two-pass form's saved state and
+// pass-2 ordering buffers (NL band words per pair), output flags and
+// positions, result ids and distances.
+uint64_t verify_bytes(const ej_ctx *ctx, uint64_t cnt, uint64_t qbytes, uint32_t nq,
+                      uint32_t sigma, uint32_t Kmax) {
+    const uint64_t NL = verify_lanes_for(Kmax);
+    uint64_t b = cnt * 4;                                           // distances
+    b += mask_words_bound(qbytes, nq, sigma) * 4 + 24ull * (nq + 1);  // query masks
+    if (ctx->tune.verify_mode == 0) b += cnt * (8 * NL + 4 * 8 + 8);  // two-pass state
+    b += cnt * (4 + 4 + 4 + 4);                                     // output
     return b;
 }
 
@@ -327,11 +348,19 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
         // admission by free HBM (or the configured limit)
         size_t freeb = 0, totalb = 0;
         EJ_HIP(hipMemGetInfo(&freeb, &totalb));
-        uint64_t avail = ix->hbm_limit ? ix->hbm_limit : (uint64_t)freeb;
+        const uint64_t avail = ix->hbm_limit ? ix->hbm_limit : (uint64_t)freeb;
+        uint32_t Kmax = 0;
+        for (uint32_t i = 0; i < nq; i++) Kmax = std::max(Kmax, Kq[i]);
+        // admission, checked again as each data-dependent size becomes known
+        // and before any of that stage's memory is requested
         uint64_t need = estimate(ix, qtotal, nq);
-        if (need > avail)
-            fail(EJ_ENOMEM, "batch needs ~" + std::to_string(need) + " bytes, " +
-                                std::to_string(avail) + " admitted");
+        auto admit = [&](const char *what) {
+            if (need > avail)
+                fail(EJ_ENOMEM, std::string("batch needs ~") + std::to_string(need) +
+                                    " bytes (" + what + "), " + std::to_string(avail) +
+                                    " admitted");
+        };
+        admit("before embedding");
         EJ_HIP(hipEventRecord(ctx->timers.ev[0], ctx->stream));
         out->nq = nq;
         out->offsets = (uint64_t *)calloc((size_t)nq + 1, sizeof(uint64_t));
@@ -366,7 +395,8 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
         scan_exclusive_u64(ctx, counts, counts, tot, d_raw);
         uint64_t raw = 0;
         read_back(ctx, d_raw, 8, &raw);
-        if (raw * 40 > avail) fail(EJ_ENOMEM, "candidate volume exceeds the admitted HBM");
+        need += probe_bytes(raw);
+        admit("with the candidate stage");
         uint64_t cnt = 0;
         uint64_t *pairs = nullptr;
         uint32_t *pk = nullptr;
@@ -399,6 +429,9 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
             EJ_CHECK_LAUNCH();
         }
         out->n_candidates = cnt;
+        need += verify_bytes(ctx, cnt, qtotal, nq, ix->sigma, Kmax);
+        admit("with verification");
+        out->workspace_bytes = need;
         uint64_t nout = 0;
         uint32_t *per_q = ws<uint32_t>(ctx, "q_perq", nq);
         EJ_HIP(hipMemsetAsync(per_q, 0, 4ull * nq, ctx->stream));

@@ -174,16 +174,25 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         EJ_HIP(hipMemsetAsync(d_cols, 0, 8, ctx->stream));
     }
     tm.mark();  // 4: the verification stage follows
-    ctx->timers.on = tm.on;
-    ctx->timers.nkv = 0;
-    ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode >= 1;
-    RowMasks masks;
-    if (cnt)
-        build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
-    verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, pairs, cnt, p.K,
-           nullptr, dist, nullptr, nullptr, 0, 0, nullptr, d_cols, order);
-    ctx->timers.on = false;
-    ctx->graph_on = false;
+    {
+        // graph mode and the kernel timers apply to this verification only,
+        // also when it fails
+        struct Reset {
+            ej_ctx *c;
+            ~Reset() {
+                c->timers.on = false;
+                c->graph_on = false;
+            }
+        } reset{ctx};
+        ctx->timers.on = tm.on;
+        ctx->timers.nkv = 0;
+        ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode >= 1;
+        RowMasks masks;
+        if (cnt)
+            build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
+        verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, pairs, cnt, p.K,
+               nullptr, dist, nullptr, nullptr, 0, 0, nullptr, d_cols, order);
+    }
     tm.mark();  // 5
     uint64_t nout = 0;
     uint32_t *opairs = nullptr;
@@ -351,15 +360,33 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             double best = 1e30;
             for (uint32_t i = 0; i < reps; i++) {
                 ej_result res;
+                memset(&res, 0, sizeof(res));
                 auto t0 = std::chrono::steady_clock::now();
-                join_device(ctx, d_chars, d_offsets, n, q, &res);
+                try {
+                    join_device(ctx, d_chars, d_offsets, n, q, &res);
+                } catch (...) {
+                    ej_result_free(&res);
+                    throw;
+                }
                 auto t1 = std::chrono::steady_clock::now();
                 ej_result_free(&res);
                 best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
             }
             return best;
         };
-        trial();  // warm the workspace
+        // a setting the kernels cannot run (say, the whole-pattern mask layout
+        // of strings too long for LDS) scores as infinitely slow; the stream
+        // is drained and the error cleared before the next trial
+        auto trial_or_inf = [&]() {
+            try {
+                return trial();
+            } catch (const Error &) {
+                (void)hipStreamSynchronize(ctx->stream);
+                (void)hipGetLastError();
+                return 1e300;
+            }
+        };
+        trial();  // warm the workspace (the starting knobs must run)
         double cur = trial();
         // coordinate descent, one knob at a time, in order of expected effect
         // which verification forms a knob affects, as a bit mask of verify_mode
@@ -387,7 +414,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             for (uint32_t v : k.vals) {
                 if (v == start) continue;
                 ctx->tune.*(k.field) = v;
-                const double t = trial();
+                const double t = trial_or_inf();
                 if (t < cur) {
                     cur = t;
                     best_v = v;

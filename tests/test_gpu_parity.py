@@ -474,6 +474,40 @@ def test_autotune_keeps_results(ej, ctx, oracle_lib):
             ctx.tune_set(k, v)
 
 
+def test_autotune_survives_settings_that_cannot_run(ej, ctx, oracle_lib):
+    """Strings of 350,000 letters: their whole-pattern match masks do not fit
+    in LDS, so the mask-layout knob 0 cannot run them.  A join at that
+    setting fails cleanly and leaves the context usable (graph mode and
+    timers reset); the autotuner scores such a trial as infinitely slow and
+    still returns a working setting."""
+    col = sd.clusters(41, 2, lambda rr, b: 3, lambda rr: rr.integers(350000, 352000),
+                      lambda rr, LL: rr.poisson(25))
+    K, r, z, m, L = 60, 2, 2, 4, 64
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 4, L)
+    chars, offs = to_device(col)
+    before = ctx.knobs()
+    try:
+        for mode in (0, 1):
+            ctx.tune_set("verify_mode", mode)
+            ctx.tune_set("verify_ring", 0)
+            _say(f"whole-pattern masks of 350k-letter strings, mode {mode}")
+            with pytest.raises(ej.EmbedJoinError) as e:
+                ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
+            assert e.value.status == ej.EJ_EUNSUPPORTED
+            ctx.tune_set("verify_ring", 1)
+            _assert_join_equal(ctx.join(chars, offs, K, r, z, m, seed=4, L=L), ref)
+        for k, v in before.items():
+            ctx.tune_set(k, v)
+        _say("autotune over long strings")
+        ctx.autotune(chars, offs, K, r, z, m, seed=4, L=L, reps=1)
+        knobs = ctx.knobs()
+        flags = ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0
+        _assert_join_equal(ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=flags), ref)
+    finally:
+        for k, v in before.items():
+            ctx.tune_set(k, v)
+
+
 def test_graph_replays_match_eager(ej, ctx, oracle_lib):
     """Persistent verification (both forms) captured into a HIP graph: the
     first join captures, later joins of the same shape replay it, with eager

@@ -155,3 +155,40 @@ def test_index_edge_cases_and_admission(ej, ctx, oracle_lib):
     _say("after admission refusal")
     _check(ix.query(q2.chars, q2.offsets, K2), *ref)
     ix.close()
+
+
+def test_admission_counts_candidates_and_verification(ej, ctx, oracle_lib):
+    """A batch whose verification workspace dwarfs the up-front estimate: a
+    tight cluster of long index strings, few coarse tables (every member
+    collides with every query), thresholds of about 1,000 (32 band words of
+    saved state per pair in the two-pass form).  A limit between the
+    up-front estimate and the batch's full figure is refused before
+    verification; the index keeps answering."""
+    col = sd.clusters(31, 2, lambda rr, b: 150, lambda rr: rr.integers(9000, 9500),
+                      lambda rr, L: rr.poisson(20))
+    r, z, m, L, seed = 2, 2, 2, 16, 3
+    ix = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
+    q = sd.from_strings([col.string(i) for i in range(0, 60, 3)])
+    Kq = np.full(q.n, 1000, dtype=np.uint32)
+    old = ctx.tune_get("verify_mode")
+    try:
+        ctx.tune_set("verify_mode", 0)
+        est = ix.workspace_estimate(q.offsets, Kq)
+        _say("admission: unlimited batch")
+        full = ix.query(q.chars, q.offsets, Kq)
+        assert full.n_candidates > 20 * q.n and full.workspace_bytes > 2 * est
+        ix.set_hbm_limit((est + full.workspace_bytes) // 2)
+        _say("admission: limit between the estimate and the full figure")
+        with pytest.raises(ej.EmbedJoinError) as e:
+            ix.query(q.chars, q.offsets, Kq)
+        assert e.value.status == ej.EJ_ENOMEM and "verification" in str(e.value)
+        ix.set_hbm_limit(full.workspace_bytes)
+        again = ix.query(q.chars, q.offsets, Kq)
+        assert again.ids.tolist() == full.ids.tolist()
+        ix.set_hbm_limit(0)
+        ref = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets, Kq, r, z, m,
+                               seed=seed, L=L)
+        _check(full, *ref)
+    finally:
+        ctx.tune_set("verify_mode", old)
+        ix.close()
