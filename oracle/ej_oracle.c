@@ -479,6 +479,198 @@ int ejo_join(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t
                          explicit_v, 0u, res);
 }
 
+/* ---------------------------------------------- Algorithms 4-5 (plus) -- */
+
+/* Number of suffixes per string, ceil(K / delta), at least 1. */
+uint32_t ejo_plus_kappa(uint32_t K, uint32_t delta) {
+    uint32_t k = delta ? (K + delta - 1) / delta : 1;
+    return k ? k : 1;
+}
+
+/* The threshold T of Section 5 when the caller leaves it open: 2 when each
+ * string has more than one suffix, else 1. */
+uint32_t ejo_plus_default_T(uint32_t K, uint32_t delta) {
+    return ejo_plus_kappa(K, delta) > 1 ? 2u : 1u;
+}
+
+typedef struct {
+    uint32_t x, y, kx, ky; /* x stored earlier in the sorted order, y the probing string */
+} ejo_tuple;
+
+static int cmp_tuple(const void *pa, const void *pb) {
+    const ejo_tuple *a = (const ejo_tuple *)pa, *b = (const ejo_tuple *)pb;
+    if (a->x != b->x) return a->x < b->x ? -1 : 1;
+    if (a->y != b->y) return a->y < b->y ? -1 : 1;
+    if (a->kx != b->kx) return a->kx < b->kx ? -1 : 1;
+    if (a->ky != b->ky) return a->ky < b->ky ? -1 : 1;
+    return 0;
+}
+
+/* EmbedJoin+ (Algorithm 5 with Algorithm 4 as preprocessing).  Every string
+ * s_i contributes kappa = ceil(K/delta) suffixes s_{i,k} = s_i[(k-1)delta ..]
+ * (0-based here; a suffix past the end is empty), each embedded with the
+ * seed's random string and truncated to L; a table bucket stores (string,
+ * suffix index) tuples.  Strings are visited in the sorted order; for each
+ * seed l, function j and suffix k, the bucket of s_{i,k} is probed: every
+ * stored tuple (s, k') of another string with |s_i| - |s| <= K adds the
+ * tuple (s, s_i, k', k) to the collection C (a multiset), the others are
+ * evicted; then (s_i, k) is stored.  A pair is a candidate when one of its
+ * tuples occurs at least T times in C; candidates are verified exactly.
+ * The result has the same layout as ejo_join's; keys are [r*z][n*kappa]
+ * (suffix (i, k) at column i*kappa + k) and sig is not kept.  Returns 0, -1
+ * for invalid sizes, -2 for a 256-symbol alphabet. */
+int ejo_join_plus(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+                  uint32_t r, uint32_t z, uint32_t m, uint32_t L_req, uint64_t seed,
+                  uint32_t delta, uint32_t T, uint32_t opts, ejo_result *res) {
+    memset(res, 0, sizeof(*res));
+    if (r == 0 || z == 0 || m == 0 || delta == 0 || T == 0) return -1;
+    const uint32_t kappa = ejo_plus_kappa(K, delta);
+    if ((uint64_t)n * kappa >= 0xFFFFFFFFull) return -1;
+    uint64_t total = n ? offsets[n] - offsets[0] : 0;
+    int32_t lut[256];
+    int sigma = ejo_alphabet(chars + (n ? offsets[0] : 0), total, lut);
+    if (sigma > 255) return -2;
+    uint32_t L = ejo_effective_L(offsets, n, L_req);
+    res->sigma = (uint32_t)sigma;
+    res->L = L;
+    const uint32_t Tn = r * z;
+    const uint64_t ns = (uint64_t)n * kappa;
+
+    uint8_t *codes = (uint8_t *)malloc(total ? total : 1);
+    for (uint64_t i = 0; i < total; i++) codes[i] = (uint8_t)lut[chars[offsets[0] + i]];
+    uint64_t rb = (uint64_t)L * (uint64_t)sigma;
+    uint8_t *Rbits = (uint8_t *)malloc(r * rb + 1);
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * Tn * m);
+    uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * Tn * m);
+    ejo_draw(seed, r, z, m, L, (uint32_t)sigma, Rbits, pos, v);
+
+    /* Algorithm 4: sort, then embed every suffix of every string r times */
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    for (uint32_t i = 0; i < n; i++) order[i] = i;
+    g_chars = chars;
+    g_offsets = offsets;
+    qsort(order, n, sizeof(uint32_t), cmp_len_alpha);
+    res->keys = (uint64_t *)malloc(sizeof(uint64_t) * Tn * (ns ? ns : 1));
+    uint8_t *t = (uint8_t *)malloc(L);
+    for (uint32_t l = 0; l < r; l++) {
+        for (uint32_t i = 0; i < n; i++) {
+            const uint32_t len = (uint32_t)(offsets[i + 1] - offsets[i]);
+            for (uint32_t k = 0; k < kappa; k++) {
+                const uint64_t start = (uint64_t)k * delta;
+                const uint32_t skip = start < len ? (uint32_t)start : len;
+                ejo_cgk_embed(codes + (offsets[i] - offsets[0]) + skip, len - skip,
+                              Rbits + l * rb, (uint32_t)sigma, L, t);
+                for (uint32_t j = 0; j < z; j++)
+                    res->keys[((uint64_t)l * z + j) * ns + (uint64_t)i * kappa + k] =
+                        ejo_key(t, pos + ((uint64_t)l * z + j) * m, v + ((uint64_t)l * z + j) * m,
+                                m);
+            }
+        }
+    }
+    free(t);
+
+    /* Algorithm 5: tables of (string, suffix) tuples, strings in sorted order */
+    ejo_table *tables = (ejo_table *)malloc(sizeof(ejo_table) * Tn);
+    uint64_t nslots = 16;
+    while (nslots < 2ULL * ns) nslots <<= 1;
+    for (uint32_t q = 0; q < Tn; q++) table_init(&tables[q], nslots);
+    uint64_t ccap = 1024, ccnt = 0;
+    ejo_tuple *C = (ejo_tuple *)malloc(sizeof(ejo_tuple) * ccap);
+    for (uint32_t oi = 0; oi < n; oi++) {
+        const uint32_t si = order[oi];
+        const uint64_t len_i = offsets[si + 1] - offsets[si];
+        for (uint32_t l = 0; l < r; l++) {
+            for (uint32_t j = 0; j < z; j++) {
+                const uint32_t q = l * z + j;
+                for (uint32_t k = 0; k < kappa; k++) {
+                    const uint64_t key = res->keys[(uint64_t)q * ns + (uint64_t)si * kappa + k];
+                    ejo_bucket *b = table_bucket(&tables[q], key);
+                    uint32_t keep = 0;
+                    for (uint32_t e = 0; e < b->count; e++) {
+                        const uint32_t tup = b->ids[e];
+                        const uint32_t s = tup / kappa, kk = tup % kappa;
+                        if (s == si) { /* the string's own earlier suffix: skipped */
+                            b->ids[keep++] = tup;
+                            continue;
+                        }
+                        const uint64_t len_s = offsets[s + 1] - offsets[s];
+                        if (len_i - len_s <= K) {
+                            if (ccnt == ccap) {
+                                ccap *= 2;
+                                C = (ejo_tuple *)realloc(C, sizeof(ejo_tuple) * ccap);
+                            }
+                            C[ccnt].x = s;
+                            C[ccnt].y = si;
+                            C[ccnt].kx = kk;
+                            C[ccnt].ky = k;
+                            ccnt++;
+                            b->ids[keep++] = tup;
+                        }
+                        /* else: evicted */
+                    }
+                    b->count = keep;
+                    bucket_push(b, si * kappa + k);
+                }
+            }
+        }
+    }
+    for (uint32_t q = 0; q < Tn; q++) table_free(&tables[q]);
+    free(tables);
+    res->n_raw = ccnt;
+
+    /* count each tuple; a pair with some tuple counted >= T is a candidate */
+    qsort(C, ccnt, sizeof(ejo_tuple), cmp_tuple);
+    uint64_t cap = 1024, cnt = 0;
+    uint64_t *cand = (uint64_t *)malloc(sizeof(uint64_t) * cap);
+    for (uint64_t e = 0; e < ccnt;) {
+        uint64_t f = e;
+        while (f < ccnt && cmp_tuple(&C[f], &C[e]) == 0) f++;
+        if (f - e >= T) {
+            const uint32_t a = C[e].x < C[e].y ? C[e].x : C[e].y;
+            const uint32_t c = C[e].x < C[e].y ? C[e].y : C[e].x;
+            if (cnt == cap) {
+                cap *= 2;
+                cand = (uint64_t *)realloc(cand, sizeof(uint64_t) * cap);
+            }
+            cand[cnt++] = ((uint64_t)a << 32) | c;
+        }
+        e = f;
+    }
+    free(C);
+    qsort(cand, cnt, sizeof(uint64_t), cmp_u64);
+    uint64_t u = 0;
+    for (uint64_t e = 0; e < cnt; e++)
+        if (e == 0 || cand[e] != cand[e - 1]) cand[u++] = cand[e];
+    cnt = u;
+    res->n_cand = cnt;
+    res->cand = cand;
+    if (!(opts & EJO_STOP_AFTER_CANDIDATES)) {
+        res->cand_dist = (uint32_t *)malloc(sizeof(uint32_t) * (cnt ? cnt : 1));
+        res->out = (uint64_t *)malloc(sizeof(uint64_t) * (cnt ? cnt : 1));
+        res->out_dist = (uint32_t *)malloc(sizeof(uint32_t) * (cnt ? cnt : 1));
+        uint64_t nout = 0;
+        for (uint64_t e = 0; e < cnt; e++) {
+            const uint32_t a = (uint32_t)(cand[e] >> 32), c = (uint32_t)cand[e];
+            const uint32_t d =
+                ejo_ed_banded(chars + offsets[a], (uint32_t)(offsets[a + 1] - offsets[a]),
+                              chars + offsets[c], (uint32_t)(offsets[c + 1] - offsets[c]), K);
+            res->cand_dist[e] = d;
+            if (d <= K) {
+                res->out[nout] = cand[e];
+                res->out_dist[nout] = d;
+                nout++;
+            }
+        }
+        res->n_out = nout;
+    }
+    free(order);
+    free(codes);
+    free(Rbits);
+    free(pos);
+    free(v);
+    return 0;
+}
+
 /* ------------------------------------------------------------- serving --
  * Serving is a systems layer on the method, not a step of the paper: an
  * index fixes the alphabet (its sorted distinct bytes), the truncation L and

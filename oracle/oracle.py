@@ -95,6 +95,13 @@ def lib():
         L.ejo_query.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32, u32p,
                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.c_uint64, u64p, u32p, u32p, ctypes.c_uint64]
+        L.ejo_join_plus.restype = ctypes.c_int
+        L.ejo_join_plus.argtypes = [u8p, u64p] + [ctypes.c_uint32] * 6 + [ctypes.c_uint64] + \
+            [ctypes.c_uint32] * 3 + [ctypes.POINTER(_Result)]
+        L.ejo_plus_kappa.restype = ctypes.c_uint32
+        L.ejo_plus_kappa.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.ejo_plus_default_T.restype = ctypes.c_uint32
+        L.ejo_plus_default_T.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         L.ejo_keys.restype = ctypes.c_int
         L.ejo_keys.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -202,7 +209,7 @@ def _arr(ptr, count):
 
 
 class JoinResult:
-    def __init__(self, res: _Result, n: int, r: int, z: int, m: int):
+    def __init__(self, res: _Result, n: int, r: int, z: int, m: int, key_cols: int | None = None):
         self.sigma = int(res.sigma)
         self.L = int(res.L)
         self.n_raw = int(res.n_raw)
@@ -215,8 +222,9 @@ class JoinResult:
         self.out = _arr(res.out, no) if no else empty
         od = _arr(res.out_dist, no)
         self.out_dist = od if od is not None else np.zeros(0, dtype=np.uint32)
-        keys = _arr(res.keys, T * n)
-        self.keys = keys.reshape(T, n) if keys is not None else np.zeros((T, n), np.uint64)
+        kc = n if key_cols is None else key_cols
+        keys = _arr(res.keys, T * kc)
+        self.keys = keys.reshape(T, kc) if keys is not None else np.zeros((T, kc), np.uint64)
         sig = _arr(res.sig, n * T * m)
         self.sig = sig.reshape(n, r, z, m) if sig is not None else None
 
@@ -258,6 +266,39 @@ def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int =
         raise ValueError(f"oracle join rejected its arguments (rc={rc})")
     try:
         return JoinResult(res, n, r, z, m)
+    finally:
+        lib().ejo_result_free(ctypes.byref(res))
+
+
+def plus_kappa(K: int, delta: int) -> int:
+    return int(lib().ejo_plus_kappa(K, delta))
+
+
+def plus_default_T(K: int, delta: int) -> int:
+    return int(lib().ejo_plus_default_T(K, delta))
+
+
+def join_plus(chars, offsets, K: int, r: int, z: int, m: int, delta: int, T: int = 0,
+              seed: int = 0, L: int = 0, opts: int = 0) -> JoinResult:
+    """The oracle's EmbedJoin+ (Algorithms 4-5): ceil(K/delta) suffixes per
+    string, a pair is a candidate when one of its suffix pairs collides in at
+    least T tables (T = 0: 2 if there is more than one suffix, else 1).
+    keys are [r*z, n*kappa] (suffix k of string i at column i*kappa + k)."""
+    c = _u8(chars)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.shape[0] - 1
+    if T == 0:
+        T = plus_default_T(K, delta)
+    res = _Result()
+    rc = lib().ejo_join_plus(_ptr(c, ctypes.c_uint8) if c.size else None,
+                             _ptr(off, ctypes.c_uint64), n, K, r, z, m, L, seed, delta, T, opts,
+                             ctypes.byref(res))
+    if rc == -2:
+        raise ValueError("all 256 byte values occur: no code is left for the padding symbol")
+    if rc != 0:
+        raise ValueError(f"oracle join_plus rejected its arguments (rc={rc})")
+    try:
+        return JoinResult(res, n, r, z, m, key_cols=n * plus_kappa(K, delta))
     finally:
         lib().ejo_result_free(ctypes.byref(res))
 

@@ -258,6 +258,29 @@ def serving_queries(index: Collection, seed: int = 0, n_queries: int = 10000,
     return col, Kq, np.asarray(src, dtype=np.int64)
 
 
+def shifted_reads(seed: int = 0, n_bases: int = 5000, copies: int = 10, base_len=(4500, 5500),
+                  shift: int = 60, edit_rate: float = 0.003, letters=DNA):
+    """Reads with shifts (the case EmbedJoin+ is built for): every cluster is
+    `copies` reads of one random genome segment; a read starts at a uniform
+    offset in [0, shift] of the segment (so two reads of a cluster differ by
+    leading insertions of up to `shift` letters, and as many at the end),
+    has the base length, and carries Poisson(edit_rate * len) edits.
+    Default: 50,000 DNA reads of length 4,500..5,500."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5F1F7]))
+    let = np.frombuffer(letters, dtype=np.uint8)
+    pieces, labels = [], []
+    for b in range(n_bases):
+        L = int(rng.integers(base_len[0], base_len[1] + 1))
+        genome = _draw_letters(rng, let, None, L + shift)
+        for _ in range(copies):
+            s0 = int(rng.integers(0, shift + 1))
+            read = genome[s0:s0 + L]
+            pieces.append(mutate(rng, read, int(rng.poisson(edit_rate * L)), let))
+            labels.append(b)
+    return (_assemble(rng, pieces, labels, f"shifted reads n={n_bases * copies}"),
+            dict(K=100, delta=50, T=2))
+
+
 def planted_pairs(col: Collection) -> np.ndarray:
     """All pairs (i < j) that share a cluster label (label >= 0)."""
     lab = col.labels

@@ -580,3 +580,125 @@ def test_serving_truth_equals_the_query_definition(oracle_lib):
     for qi in range(q.n):
         lo, hi = int(off[qi]), int(off[qi + 1])
         assert want[qi][0] == ids[lo:hi].tolist() and want[qi][1] == dist[lo:hi].tolist()
+
+
+# ----------------------------------------------------- EmbedJoin+ (§5) ----
+
+def _brute_plus(col, keys, K, kappa, T):
+    """Candidates of Algorithm 5 from their definition: pairs within K in
+    length with some suffix pair whose keys agree in at least T tables; and
+    the size of the tuple multiset (one tuple per table and agreeing suffix
+    pair)."""
+    n, lens = col.n, col.lengths()
+    cand, raw = set(), 0
+    for a in range(n):
+        for b in range(a + 1, n):
+            if abs(lens[a] - lens[b]) > K:
+                continue
+            for ka in range(kappa):
+                for kb in range(kappa):
+                    c = int((keys[:, a * kappa + ka] == keys[:, b * kappa + kb]).sum())
+                    raw += c
+                    if c >= T:
+                        cand.add((a, b))
+    return cand, raw
+
+
+def test_plus_with_one_suffix_and_T1_is_embedjoin(oracle_lib):
+    for seed in (0, 1, 2):
+        col, _ = sd.shifted_reads(seed, n_bases=12, copies=4, base_len=(60, 120), shift=10,
+                                  edit_rate=0.03)
+        a = oracle_lib.join(col.chars, col.offsets, 20, 3, 4, 3, seed=seed, L=48)
+        b = oracle_lib.join_plus(col.chars, col.offsets, 20, 3, 4, 3, delta=20, T=1, seed=seed,
+                                 L=48)
+        assert oracle_lib.plus_kappa(20, 20) == 1
+        assert b.cand.tolist() == a.cand.tolist() and b.n_raw == a.n_raw
+        assert b.out.tolist() == a.out.tolist() and b.out_dist.tolist() == a.out_dist.tolist()
+        assert np.array_equal(b.keys, a.keys)
+
+
+@pytest.mark.parametrize("seed,K,delta,T,r,z,m", [(0, 30, 10, 2, 3, 4, 2), (1, 25, 9, 1, 2, 5, 3),
+                                                  (2, 40, 15, 3, 2, 6, 2), (3, 12, 5, 2, 3, 3, 1)])
+def test_plus_candidates_equal_definition(oracle_lib, seed, K, delta, T, r, z, m):
+    col, _ = sd.shifted_reads(seed, n_bases=8, copies=4, base_len=(20, 70), shift=15,
+                              edit_rate=0.05)
+    res = oracle_lib.join_plus(col.chars, col.offsets, K, r, z, m, delta=delta, T=T, seed=seed,
+                               L=40)
+    kappa = oracle_lib.plus_kappa(K, delta)
+    assert kappa == -(-K // delta)
+    want, raw = _brute_plus(col, res.keys, K, kappa, T)
+    assert set(map(tuple, res.cand_pairs.tolist())) == want
+    assert res.n_raw == raw
+    # suffix keys: suffix k of string i is the embedding of s_i[k*delta:]
+    sub = sd.from_strings([col.string(i)[k * delta:] for i in range(col.n) for k in range(kappa)])
+    k2 = oracle_lib.keys(col.chars, col.offsets, sub.chars, sub.offsets, r, z, m, seed=seed, L=40)
+    assert np.array_equal(k2.T, res.keys)
+    # output: the candidates within K, exactly
+    d = oracle_lib.verify_pairs(col.chars, col.offsets, res.cand, K)
+    assert res.out.tolist() == res.cand[d <= K].tolist()
+    cand_only = oracle_lib.join_plus(col.chars, col.offsets, K, r, z, m, delta=delta, T=T,
+                                     seed=seed, L=40, opts=oracle_lib.STOP_AFTER_CANDIDATES)
+    assert cand_only.cand.tolist() == res.cand.tolist() and cand_only.n_raw == res.n_raw
+
+
+def test_plus_default_threshold():
+    # T = 2 when a string has more than one suffix (K > delta), else 1
+    from oracle import oracle
+    assert oracle.plus_default_T(100, 50) == 2 and oracle.plus_default_T(50, 50) == 1
+    assert oracle.plus_default_T(51, 50) == 2 and oracle.plus_kappa(101, 50) == 3
+
+
+def test_plus_finds_a_leading_shift_of_delta(oracle_lib):
+    """y = P + x with |P| = delta: y's second suffix is x itself, so the pair
+    collides in every table and is a candidate at any seed; plain EmbedJoin,
+    whose walks start out of step, misses many such pairs."""
+    rng = np.random.default_rng(4)
+    delta, K = 12, 30
+    found_plus = found_plain = 0
+    for seed in range(40):
+        x = bytes(np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, size=200)])
+        P = bytes(np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, size=delta)])
+        col = sd.from_strings([x, P + x])
+        res = oracle_lib.join_plus(col.chars, col.offsets, K, 2, 3, 8, delta=delta, seed=seed,
+                                   L=128)
+        assert res.cand.tolist() == [1] and res.out_dist.tolist() == [delta]
+        assert res.n_raw >= 2 * 3
+        found_plus += 1
+        found_plain += len(oracle_lib.join(col.chars, col.offsets, K, 2, 3, 8, seed=seed,
+                                           L=128).cand)
+    assert found_plus == 40 and found_plain < 40
+
+
+def test_plus_threshold_probability_closed_form(oracle_lib):
+    """Two fixed strings, one suffix, one seed, z functions: given the seed's
+    embeddings at Hamming distance H over L, each table's keys agree
+    independently with p = (1 - H/L)^m, so the number of agreeing tables is
+    Binomial(z, p) and the pair is a candidate with probability
+    p_T = 1 - sum_{i<T} C(z,i) p^i (1-p)^(z-i) (Section 5)."""
+    from math import comb
+    x = b"ACGTTGCAAGCTTACGGATCCATGCA" * 3
+    y = x[:20] + b"T" + x[21:40] + x[41:] + b"G"
+    col = sd.from_strings([x, y])
+    sigma, lut = oracle_lib.alphabet(col.chars)
+    L, z, m, T, K = 96, 8, 6, 3, 10
+    cx, cy = lut[np.frombuffer(x, np.uint8)], lut[np.frombuffer(y, np.uint8)]
+    exp_rate = exp_count = 0.0
+    hits = counts = 0
+    seeds = 1500
+    for seed in range(seeds):
+        R, _, _ = oracle_lib.draw(seed, 1, 1, 1, L, sigma)
+        tx = oracle_lib.cgk_embed(cx.astype(np.uint8), R[0], sigma, L)
+        ty = oracle_lib.cgk_embed(cy.astype(np.uint8), R[0], sigma, L)
+        p = (1.0 - float((tx != ty).sum()) / L) ** m
+        exp_count += z * p
+        exp_rate += 1.0 - sum(comb(z, i) * p ** i * (1 - p) ** (z - i) for i in range(T))
+        res = oracle_lib.join_plus(col.chars, col.offsets, K, 1, z, m, delta=K, T=T, seed=seed,
+                                   L=L)
+        counts += res.n_raw
+        hits += len(res.cand)
+    exp_rate /= seeds
+    exp_count /= seeds
+    se = (exp_rate * (1 - exp_rate) / seeds) ** 0.5
+    assert 0.1 < exp_rate < 0.9
+    assert abs(hits / seeds - exp_rate) < 4.5 * se
+    assert abs(counts / seeds - exp_count) < 4.5 * (z / seeds) ** 0.5
