@@ -179,6 +179,29 @@ ej_status ej_join_ex(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offset
 ej_status ej_join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
                          uint32_t n, const ej_params *p, ej_result *out);
 
+/* EmbedJoin+ (Algorithms 4-5, Section 5), the variant for strings whose
+ * alignments begin with a shift (a run of leading insertions).  Every string
+ * s_i contributes ceil(K/delta) suffixes s_i[(k-1)*delta ..] (1-based k; a
+ * suffix that starts past the end is empty), each embedded and hashed like a
+ * string of its own with the same seeds, coordinates and truncation L.  A
+ * table bucket holds (string, suffix) entries; two entries of different
+ * strings whose lengths (of the whole strings) differ by at most K and that
+ * share a bucket form a tuple (s, s', k, k').  A pair of strings is a
+ * candidate when one of its tuples is found by at least T of the r*z tables;
+ * candidates are verified exactly and the output has the layout of ej_join's
+ * (n_raw = tuples found, with repetition).
+ *   delta  suffix step; 0 selects floor(sqrt(ceil(average length))), at least 1
+ *   T      tuple threshold; 0 selects 2 when ceil(K/delta) > 1, else 1 (with
+ *          one suffix and T = 1 the result is exactly ej_join's)
+ * Host strings; ej_join_plus_device takes device-resident ones (as
+ * ej_join_device).  Errors as ej_join, plus EJ_EUNSUPPORTED when
+ * r*z*n*ceil(K/delta) reaches 2^32. */
+ej_status ej_join_plus(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                       const ej_params *p, uint32_t delta, uint32_t T, ej_result *out);
+ej_status ej_join_plus_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                              uint32_t n, const ej_params *p, uint32_t delta, uint32_t T,
+                              ej_result *out);
+
 void ej_result_free(ej_result *res);
 
 /* Autotuner of the batched form, for callers that run many joins of one

@@ -27,7 +27,8 @@ FLAG_PLAIN, FLAG_GRAPH, FLAG_TIMING = 0, 1, 2
 EXPORTS = [
     "ej_create", "ej_destroy", "ej_last_error", "ej_version", "ej_workspace_bytes",
     "ej_tune_set", "ej_tune_get",
-    "ej_join", "ej_join_ex", "ej_join_device", "ej_result_free", "ej_autotune",
+    "ej_join", "ej_join_ex", "ej_join_device", "ej_join_plus", "ej_join_plus_device",
+    "ej_result_free", "ej_autotune",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_verify_static",
     "ej_set_explicit_randomness",
     "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
@@ -93,6 +94,10 @@ def lib():
         "ej_join_ex": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), ctypes.POINTER(_Result)]),
         "ej_join_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params),
                                    ctypes.POINTER(_Result)]),
+        "ej_join_plus": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32, u32,
+                                 ctypes.POINTER(_Result)]),
+        "ej_join_plus_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32, u32,
+                                        ctypes.POINTER(_Result)]),
         "ej_result_free": (None, [ctypes.POINTER(_Result)]),
         "ej_autotune": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32,
                                 ctypes.POINTER(ctypes.c_float)]),
@@ -225,7 +230,15 @@ class Context:
         """EmbedJoin self-join.  Host inputs (bytes / numpy / CPU tensors) go
         through ej_join_ex; CUDA tensors (uint8 chars, int64 offsets) go
         through ej_join_device."""
-        p = Params(K, r, z, m, L, flags, seed)
+        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), None)
+
+    def join_plus(self, chars, offsets, K: int, r: int, z: int, m: int, delta: int = 0,
+                  T: int = 0, seed: int = 0, L: int = 0, flags: int = 0) -> JoinResult:
+        """EmbedJoin+ (ej_join_plus / ej_join_plus_device): ceil(K/delta)
+        suffixes per string, tuple threshold T (0: the paper's rule)."""
+        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), (delta, T))
+
+    def _join(self, chars, offsets, p, plus) -> JoinResult:
         res = _Result()
         if _is_device(chars) or _is_device(offsets):
             torch = _torch()
@@ -235,14 +248,23 @@ class Context:
             # the library works on its own stream: inputs written on torch's
             # current stream must be complete first
             torch.cuda.current_stream().synchronize()
-            st = lib().ej_join_device(self._h, _ptr(chars), _ptr(offsets), n, ctypes.byref(p),
-                                      ctypes.byref(res))
+            if plus is None:
+                st = lib().ej_join_device(self._h, _ptr(chars), _ptr(offsets), n,
+                                          ctypes.byref(p), ctypes.byref(res))
+            else:
+                st = lib().ej_join_plus_device(self._h, _ptr(chars), _ptr(offsets), n,
+                                               ctypes.byref(p), plus[0], plus[1],
+                                               ctypes.byref(res))
         else:
             c = _host_u8(chars)
             o = _host_u64(offsets)
             n = o.shape[0] - 1
-            st = lib().ej_join_ex(self._h, _ptr(c) if c.size else None, _ptr(o), n,
-                                  ctypes.byref(p), ctypes.byref(res))
+            cp = _ptr(c) if c.size else None
+            if plus is None:
+                st = lib().ej_join_ex(self._h, cp, _ptr(o), n, ctypes.byref(p), ctypes.byref(res))
+            else:
+                st = lib().ej_join_plus(self._h, cp, _ptr(o), n, ctypes.byref(p), plus[0],
+                                        plus[1], ctypes.byref(res))
         self._check(st)
         try:
             cnt = int(res.count)

@@ -142,27 +142,56 @@ __global__ void k_sorted_attrs_dk(const uint64_t *__restrict__ keys,
     }
 }
 
+// How the pair walk codes what it finds.  The join: entries are strings and
+// a pair is (min << B | max).  EmbedJoin+ (Algorithm 5): entry e is suffix
+// e % kappa of string e / kappa; two suffixes of one string never pair, and a
+// pair is the tuple (string a, string b, suffix of a, suffix of b), a < b,
+// coded as a << (B + 2 KB) | b << 2 KB | ka << KB | kb.
+struct PairCoder {
+    uint32_t B;
+    __device__ bool pairs(uint32_t, uint32_t) const { return true; }
+    __device__ uint64_t code(uint32_t x, uint32_t y) const {
+        const uint32_t a = min(x, y), b = max(x, y);
+        return ((uint64_t)a << B) | b;
+    }
+};
+struct TupleCoder {
+    uint32_t B, kappa, KB;
+    __device__ bool pairs(uint32_t x, uint32_t y) const { return x / kappa != y / kappa; }
+    __device__ uint64_t code(uint32_t x, uint32_t y) const {
+        const uint32_t sx = x / kappa, sy = y / kappa;
+        const uint32_t kx = x - sx * kappa, ky = y - sy * kappa;
+        const bool swap = sy < sx;
+        const uint64_t a = swap ? sy : sx, b = swap ? sx : sy;
+        const uint64_t ka = swap ? ky : kx, kb = swap ? kx : ky;
+        return (a << (B + 2 * KB)) | (b << (2 * KB)) | (ka << KB) | kb;
+    }
+};
+
 // Entry e's walk, given that entry e + 1 is in its group (top bits d).
-template <bool EMIT, typename C>
+template <bool EMIT, typename C, typename Coder>
 __device__ inline uint32_t pair_walk(uint32_t e, uint32_t d, uint32_t send,
                                      const uint32_t *__restrict__ dk,
                                      const uint64_t *__restrict__ key_s,
                                      const uint32_t *__restrict__ len_s,
-                                     const uint32_t *__restrict__ ids, uint32_t K, uint32_t B,
-                                     C *__restrict__ out) {
+                                     const uint32_t *__restrict__ ids, uint32_t K,
+                                     const Coder &coder, C *__restrict__ out) {
+    constexpr bool ALWAYS = std::is_same<Coder, PairCoder>::value;
     uint32_t q = e + 1;
     const uint64_t ke = key_s[e];
     const uint64_t lim = (uint64_t)len_s[e] + K;
-    const uint32_t ide = EMIT ? ids[e] : 0u;
+    const uint32_t ide = (EMIT || !ALWAYS) ? ids[e] : 0u;
     uint32_t c = 0;
     for (; q < send; q++) {
         if (dk[q] != d || (uint64_t)len_s[q] > lim) break;
         if (key_s[q] == ke) {
-            if (EMIT) {
-                const uint32_t idq = ids[q];
-                const uint32_t a = min(ide, idq), b = max(ide, idq);
-                out[c] = (C)(((uint64_t)a << B) | b);
+            if (ALWAYS && !EMIT) {
+                c++;
+                continue;
             }
+            const uint32_t idq = ids[q];
+            if (!coder.pairs(ide, idq)) continue;
+            if (EMIT) out[c] = (C)coder.code(ide, idq);
             c++;
         }
     }
@@ -177,11 +206,11 @@ constexpr uint32_t PW_TILE = 256 * PW_IPT;     // entries per workgroup
 // EMIT = true: each thread writes its entries' pairs, in entry order, from
 // the workgroup's offset plus the exclusive scan of the thread counts.
 // Entry of (thread x, round i) = tile start + 256 i + x.
-template <bool EMIT, typename C>
+template <bool EMIT, typename C, typename Coder>
 __global__ void __launch_bounds__(256)
     k_pairs_dk(const uint32_t *__restrict__ dk, const uint64_t *__restrict__ key_s,
                const uint32_t *__restrict__ len_s, const uint32_t *__restrict__ ids, uint32_t n,
-               uint32_t tot, uint32_t K, uint32_t B, uint32_t *__restrict__ tcount,
+               uint32_t tot, uint32_t K, Coder coder, uint32_t *__restrict__ tcount,
                uint64_t *__restrict__ wg_count, const uint64_t *__restrict__ wg_off,
                C *__restrict__ out) {
     __shared__ uint64_t red[4];
@@ -211,7 +240,7 @@ __global__ void __launch_bounds__(256)
         for (uint32_t i = 0; i < PW_IPT; i++)
             if (act & (1u << i))
                 s += pair_walk<false, C>((uint32_t)(base + 256 * i + x), dd[i], send[i], dk, key_s,
-                                         len_s, ids, K, B, nullptr);
+                                         len_s, ids, K, coder, (C *)nullptr);
         tcount[blockIdx.x * 256 + x] = s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
         uint64_t w = s;
         for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
@@ -238,7 +267,31 @@ __global__ void __launch_bounds__(256)
     for (uint32_t i = 0; i < PW_IPT; i++)
         if (act & (1u << i))
             o += pair_walk<true, C>((uint32_t)(base + 256 * i + x), dd[i], send[i], dk, key_s,
-                                    len_s, ids, K, B, out + o);
+                                    len_s, ids, K, coder, out + o);
+}
+
+// EmbedJoin+ tuple counts: in the sorted tuple codes, a run of equal codes
+// is one tuple and its length is the number of tables that found it.  Flags
+// the first entry of each run of at least T entries (the run is sorted, so
+// its T-th entry decides).
+__global__ void k_tuple_qualify(const uint64_t *__restrict__ t, uint64_t cnt, uint32_t T,
+                                uint32_t *__restrict__ flags) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = t[e];
+        const bool start = e == 0 || t[e - 1] != c;
+        flags[e] = (start && e + T - 1 < cnt && t[e + T - 1] == c) ? 1u : 0u;
+    }
+}
+
+// The pair code (a << B | b) of every flagged tuple, at its scanned position;
+// the result is sorted (the tuples were) and may repeat a pair.
+__global__ void k_tuple_pairs(const uint64_t *__restrict__ t, uint64_t cnt, uint32_t shift,
+                              const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
+                              uint64_t *__restrict__ out) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        if (flags[e]) out[pos[e]] = t[e] >> shift;
 }
 
 template <typename C>
@@ -528,10 +581,11 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         EJ_CHECK_LAUNCH();
         tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
         counts = ws<uint64_t>(ctx, t + "_counts", nwg);
-        hipLaunchKernelGGL((k_pairs_dk<false, uint64_t>), dim3(nwg), dim3(256), 0, ctx->stream,
-                           (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+        hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, PairCoder>), dim3(nwg), dim3(256), 0,
+                           ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
                            (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot,
-                           K, B, tcount, counts, (const uint64_t *)nullptr, (uint64_t *)nullptr);
+                           K, PairCoder{B}, tcount, counts, (const uint64_t *)nullptr,
+                           (uint64_t *)nullptr);
         EJ_CHECK_LAUNCH();
         scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
     } else {
@@ -560,10 +614,10 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     auto emit = [&](auto *rawbuf) {
         using C = std::remove_pointer_t<decltype(rawbuf)>;
         if (by_dk) {
-            hipLaunchKernelGGL((k_pairs_dk<true, C>), dim3(nwg), dim3(256), 0, ctx->stream,
-                               (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+            hipLaunchKernelGGL((k_pairs_dk<true, C, PairCoder>), dim3(nwg), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
                                (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n,
-                               (uint32_t)tot, K, B, tcount, (uint64_t *)nullptr,
+                               (uint32_t)tot, K, PairCoder{B}, tcount, (uint64_t *)nullptr,
                                (const uint64_t *)counts, rawbuf);
             EJ_CHECK_LAUNCH();
             return;
@@ -681,6 +735,87 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt, mult_bits, 11);
         *d_order_out = order;
     }
+    return cnt;
+}
+
+// EmbedJoin+ candidates (Algorithm 5): the bucketed entries are suffixes
+// (entry e = suffix e % kappa of string e / kappa, lengths those of the whole
+// strings).  Every pair of entries of different strings in one bucket of a
+// table within K in length is a tuple (a, b, ka, kb); the tuples are counted
+// over all tables by sorting their codes, and a pair whose some tuple occurs
+// at least T times is a candidate.
+uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
+                         const uint32_t *d_len_entry, uint32_t K, uint32_t nstr, uint32_t kappa,
+                         uint32_t T, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag) {
+    std::string t(tag);
+    const uint32_t ne = bk.n;
+    const uint64_t tot = (uint64_t)bk.T * ne;
+    *d_pairs_out = ws<uint64_t>(ctx, t + "_pairs", 1);
+    if (n_raw) *n_raw = 0;
+    if (tot == 0 || nstr < 2 || !bk.d_dk) return 0;
+    if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n*kappa must stay below 2^32");
+    const uint32_t B = std::max(1u, bits_for(nstr - 1));
+    const uint32_t KB = std::max(1u, bits_for(kappa - 1));
+    if (2 * B + 2 * KB > 64) fail(EJ_EUNSUPPORTED, "tuple codes wider than 64 bits");
+    const TupleCoder coder{B, kappa, KB};
+    uint64_t *key_s = ws<uint64_t>(ctx, t + "_key_s", tot);
+    uint32_t *len_s = ws<uint32_t>(ctx, t + "_len_s", tot);
+    uint64_t *d_raw = ws<uint64_t>(ctx, t + "_nraw", 1);
+    const uint32_t nwg = (uint32_t)((tot + PW_TILE - 1) / PW_TILE);
+    hipLaunchKernelGGL(k_sorted_attrs_dk, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
+                       d_keys, (const uint32_t *)bk.d_ids, d_len_entry, (const uint32_t *)bk.d_dk,
+                       ne, (uint32_t)tot, key_s, len_s);
+    EJ_CHECK_LAUNCH();
+    uint32_t *tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
+    uint64_t *counts = ws<uint64_t>(ctx, t + "_counts", nwg);
+    hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, TupleCoder>), dim3(nwg), dim3(256), 0,
+                       ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                       (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K,
+                       coder, tcount, counts, (const uint64_t *)nullptr, (uint64_t *)nullptr);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
+    uint64_t raw = 0;
+    read_back(ctx, d_raw, 8, &raw);
+    if (n_raw) *n_raw = raw;
+    if (raw == 0) return 0;
+    if (raw >= 0xFFFFFFFFull)
+        fail(EJ_EUNSUPPORTED, "more than 2^32 candidate tuples (" + std::to_string(raw) + ")");
+    uint64_t *tup = ws<uint64_t>(ctx, t + "_tuples", raw);
+    uint64_t *sorted = ws<uint64_t>(ctx, t + "_tuples_sorted", raw);
+    hipLaunchKernelGGL((k_pairs_dk<true, uint64_t, TupleCoder>), dim3(nwg), dim3(256), 0,
+                       ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                       (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K,
+                       coder, tcount, (uint64_t *)nullptr, (const uint64_t *)counts, tup);
+    EJ_CHECK_LAUNCH();
+    radix_sort_u64(ctx, tup, sorted, raw, 2 * B + 2 * KB, ctx->tune.radix_bits);
+    uint32_t *flags = ws<uint32_t>(ctx, t + "_tflags", raw);
+    uint32_t *pos = ws<uint32_t>(ctx, t + "_tpos", raw);
+    uint64_t *d_n = ws<uint64_t>(ctx, t + "_tcount_q", 1);
+    hipLaunchKernelGGL(k_tuple_qualify, dim3(grid_for(ctx, raw, 256)), dim3(256), 0, ctx->stream,
+                       (const uint64_t *)sorted, raw, T, flags);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, flags, pos, raw, d_n);
+    uint64_t nq = 0;
+    read_back(ctx, d_n, 8, &nq);
+    if (nq == 0) return 0;
+    // the qualifying tuples' pair codes, sorted, then one of each pair
+    uint64_t *q = tup;  // the unsorted tuples are no longer needed
+    hipLaunchKernelGGL(k_tuple_pairs, dim3(grid_for(ctx, raw, 256)), dim3(256), 0, ctx->stream,
+                       (const uint64_t *)sorted, raw, 2 * KB, (const uint32_t *)flags,
+                       (const uint32_t *)pos, q);
+    EJ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_unique_flags<uint64_t>, dim3(grid_for(ctx, nq, 256)), dim3(256), 0,
+                       ctx->stream, (const uint64_t *)q, nq, flags);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, flags, pos, nq, d_n);
+    uint64_t cnt = 0;
+    read_back(ctx, d_n, 8, &cnt);
+    uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
+    hipLaunchKernelGGL(k_unique_compact<uint64_t>, dim3(grid_for(ctx, nq, 256)), dim3(256), 0,
+                       ctx->stream, (const uint64_t *)q, nq, B, (const uint32_t *)flags,
+                       (const uint32_t *)pos, pairs, (uint32_t *)nullptr);
+    EJ_CHECK_LAUNCH();
+    *d_pairs_out = pairs;
     return cnt;
 }
 

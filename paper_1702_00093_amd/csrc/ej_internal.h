@@ -261,6 +261,15 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                     uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag,
                     uint32_t **d_order_out = nullptr);
 
+// EmbedJoin+ candidates over bucketed suffix entries (entry e = suffix
+// e % kappa of string e / kappa; d_len_entry = the whole string's length):
+// pairs of strings with some (suffix, suffix) tuple found by at least T
+// tables, codes (a << 32) | b, a < b, sorted and unique.  *n_raw gets the
+// number of tuples found (with repetition).
+uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
+                         const uint32_t *d_len_entry, uint32_t K, uint32_t nstr, uint32_t kappa,
+                         uint32_t T, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag);
+
 // Match masks of a string set, one bit array per (string, symbol): bit b of
 // word w of string s and symbol c is set iff x_s[32w + b] == c, for
 // W_s = ceil(|x_s| / 32) words; string s's arrays start at word off[s].

@@ -87,6 +87,38 @@ __global__ void k_check_groups(const uint32_t *__restrict__ gs, uint64_t ng, uin
     if (b) atomicOr(bad, 1u);
 }
 
+// EmbedJoin+ suffix entries (Algorithm 4): entry e = i * kappa + k is
+// s_i[k * delta ..] (empty once k * delta >= |s_i|): its start offset and
+// length for the walk, and the whole string's length for the length window.
+__global__ void k_suffix_entries(const uint64_t *__restrict__ offsets,
+                                 const uint32_t *__restrict__ len, uint32_t n, uint32_t kappa,
+                                 uint32_t delta, uint64_t *__restrict__ sstart,
+                                 uint32_t *__restrict__ slen, uint32_t *__restrict__ flen) {
+    const uint64_t ne = (uint64_t)n * kappa;
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < ne;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(e / kappa), k = (uint32_t)(e - (uint64_t)i * kappa);
+        const uint32_t l = len[i];
+        const uint64_t want = (uint64_t)k * delta;
+        const uint32_t skip = want < l ? (uint32_t)want : l;
+        sstart[e] = offsets[i] + skip;
+        slen[e] = l - skip;
+        flen[e] = l;
+    }
+}
+
+// Entries in the strings' length order, each string's suffixes together:
+// rank r is suffix r % kappa of the string of length rank r / kappa.
+__global__ void k_entry_perm(const uint32_t *__restrict__ perm, uint32_t n, uint32_t kappa,
+                             uint32_t *__restrict__ eperm) {
+    const uint64_t ne = (uint64_t)n * kappa;
+    for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < ne;
+         r += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = (uint32_t)(r / kappa), k = (uint32_t)(r - (uint64_t)i * kappa);
+        eperm[r] = perm[i] * kappa + k;
+    }
+}
+
 void check_params(const ej_params &p, uint32_t n) {
     if (p.r == 0 || p.z == 0 || p.m == 0) fail(EJ_EINVAL, "r, z and m must be positive");
     if (p.m > 64) fail(EJ_EINVAL, "m must be at most 64");
@@ -133,38 +165,14 @@ ej_status run_guarded(ej_ctx *ctx, F &&fn) {
 
 }  // namespace
 
-// The whole path on device-resident strings.
-void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
-                 const ej_params &p, ej_result *out) {
-    check_params(p, n);
-    memset(out, 0, sizeof(*out));
-    StageTimer tm(ctx, (p.flags & EJ_FLAG_TIMING) != 0);
-    tm.mark();  // 0
-    Prep pp;
-    prepare(ctx, d_chars, d_offsets, n, p.L, pp, "j");
-    out->sigma = pp.sigma;
-    out->L = pp.L;
-    Rand rd;
-    draw_randomness(ctx, p, pp.L, pp.sigma, rd, "j");
-    const uint32_t T = p.r * p.z;
-    uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
-    tm.mark();  // 1: the walk kernel alone follows
-    // the walk also writes the bucketing sort's input (top key bits and
-    // string indexes in length order)
-    const uint32_t kb = bucket_key_bits(ctx, n, 0);
-    uint32_t *bdk = nullptr, *bids = nullptr;
-    bucket_inputs(ctx, (uint64_t)T * n, "j", &bdk, &bids);
-    embed_keys(ctx, pp, rd, keys, nullptr, bdk, bids, 61u - kb);
-    tm.mark();  // 2
-    Buckets bk;
-    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true, false);
-    tm.mark();  // 3
-    uint64_t *pairs = nullptr;
-    uint64_t raw = 0;
-    uint32_t *order = nullptr;
-    const bool want_order = ctx->tune.verify_mode >= 1 && ctx->tune.verify_order == 1;
-    uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j",
-                              want_order ? &order : nullptr);
+// Verification (A5) and output (A6) of a join whose candidates are known:
+// distances, the pairs within K with their distances in host memory, and the
+// timing fields.  walk_entries = the number of walks per seed (strings, or
+// suffixes in EmbedJoin+).
+void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const ej_params &p,
+                 const Rand &rd, uint64_t walk_entries, const uint64_t *pairs, uint64_t cnt,
+                 uint64_t raw, const uint32_t *order, StageTimer &tm, ej_result *out) {
+    const uint32_t n = pp.n;
     out->n_candidates = cnt;
     out->n_raw = raw;
     int32_t *dist = ws<int32_t>(ctx, "j_dist", cnt);
@@ -265,7 +273,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         memcpy(J.data(), xp + 8, 4ull * p.r);
         uint64_t steps = 0;
         for (uint32_t x : J) steps += x;
-        out->walk_steps = steps * n;
+        out->walk_steps = steps * walk_entries;
         if (cnt) memcpy(&out->verify_columns, xp, 8);
         float kms = 0.f;
         for (int i = 0; i + 1 < ctx->timers.nkv; i += 2) {
@@ -277,6 +285,116 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         out->verify_launches = (uint32_t)(ctx->timers.nkv / 2);
         out->verify_form = ctx->last_verify_form;
     }
+}
+
+
+// The whole path on device-resident strings.
+void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                 const ej_params &p, ej_result *out) {
+    check_params(p, n);
+    memset(out, 0, sizeof(*out));
+    StageTimer tm(ctx, (p.flags & EJ_FLAG_TIMING) != 0);
+    tm.mark();  // 0
+    Prep pp;
+    prepare(ctx, d_chars, d_offsets, n, p.L, pp, "j");
+    out->sigma = pp.sigma;
+    out->L = pp.L;
+    Rand rd;
+    draw_randomness(ctx, p, pp.L, pp.sigma, rd, "j");
+    const uint32_t T = p.r * p.z;
+    uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
+    tm.mark();  // 1: the walk kernel alone follows
+    // the walk also writes the bucketing sort's input (top key bits and
+    // string indexes in length order)
+    const uint32_t kb = bucket_key_bits(ctx, n, 0);
+    uint32_t *bdk = nullptr, *bids = nullptr;
+    bucket_inputs(ctx, (uint64_t)T * n, "j", &bdk, &bids);
+    embed_keys(ctx, pp, rd, keys, nullptr, bdk, bids, 61u - kb);
+    tm.mark();  // 2
+    Buckets bk;
+    bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true, false);
+    tm.mark();  // 3
+    uint64_t *pairs = nullptr;
+    uint64_t raw = 0;
+    uint32_t *order = nullptr;
+    const bool want_order = ctx->tune.verify_mode >= 1 && ctx->tune.verify_order == 1;
+    uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j",
+                              want_order ? &order : nullptr);
+    finish_join(ctx, pp, d_offsets, p, rd, n, pairs, cnt, raw, order, tm, out);
+}
+
+// Suffix step and threshold of EmbedJoin+ (Section 5): delta = 0 selects
+// floor(sqrt(ceil(average length))), at least 1 (the paper sets delta to about
+// the square root of the average length); T = 0 selects 2 when a string has
+// more than one suffix (ceil(K / delta) > 1), else 1.
+void plus_params(uint64_t total, uint32_t n, uint32_t K, uint32_t &delta, uint32_t &T,
+                 uint32_t &kappa) {
+    if (delta == 0) {
+        const uint64_t avg = n ? (total + n - 1) / n : 0;
+        uint64_t d = 0;
+        while ((d + 1) * (d + 1) <= avg) d++;
+        delta = (uint32_t)std::max<uint64_t>(d, 1);
+    }
+    kappa = std::max<uint32_t>(1u, (uint32_t)((K + (uint64_t)delta - 1) / delta));
+    if (T == 0) T = kappa > 1 ? 2u : 1u;
+}
+
+// EmbedJoin+ (Algorithms 4-5) on device-resident strings: every string's
+// kappa = ceil(K / delta) suffixes are walked and hashed as entries of their
+// own, bucketed by (key bits, whole-string length, entry), and a pair of
+// strings is a candidate when one (suffix, suffix) tuple is found by at least
+// T tables; verification and output are the join's.
+void join_plus_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                      const ej_params &p, uint32_t delta, uint32_t T, ej_result *out) {
+    check_params(p, n);
+    memset(out, 0, sizeof(*out));
+    StageTimer tm(ctx, (p.flags & EJ_FLAG_TIMING) != 0);
+    tm.mark();  // 0
+    Prep pp;
+    prepare(ctx, d_chars, d_offsets, n, p.L, pp, "j");
+    out->sigma = pp.sigma;
+    out->L = pp.L;
+    uint32_t kappa = 1;
+    plus_params(pp.total, n, p.K, delta, T, kappa);
+    const uint64_t ne64 = (uint64_t)n * kappa;
+    const uint32_t NT = p.r * p.z;
+    if (ne64 * NT >= 0xFFFFFFFFull)
+        fail(EJ_EUNSUPPORTED, "r*z*n*ceil(K/delta) must stay below 2^32");
+    const uint32_t ne = (uint32_t)ne64;
+    Rand rd;
+    draw_randomness(ctx, p, pp.L, pp.sigma, rd, "j");
+    // the suffix entries, as a string set of their own over the same codes
+    Prep ps = pp;
+    ps.n = ne;
+    uint64_t *sstart = ws<uint64_t>(ctx, "p_sstart", ne64 + 1);
+    uint32_t *slen = ws<uint32_t>(ctx, "p_slen", ne64 + 1);
+    uint32_t *flen = ws<uint32_t>(ctx, "p_flen", ne64 + 1);
+    uint32_t *eperm = ws<uint32_t>(ctx, "p_eperm", ne64 + 1);
+    if (ne) {
+        hipLaunchKernelGGL(k_suffix_entries, dim3(grid_for(ctx, ne64, 256)), dim3(256), 0,
+                           ctx->stream, d_offsets, (const uint32_t *)pp.d_len, n, kappa, delta,
+                           sstart, slen, flen);
+        EJ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_entry_perm, dim3(grid_for(ctx, ne64, 256)), dim3(256), 0,
+                           ctx->stream, (const uint32_t *)pp.d_perm, n, kappa, eperm);
+        EJ_CHECK_LAUNCH();
+    }
+    ps.d_offsets = sstart;
+    ps.d_len = slen;
+    ps.d_perm = eperm;
+    uint64_t *keys = ws<uint64_t>(ctx, "p_keys", ne64 * NT);
+    tm.mark();  // 1
+    embed_keys(ctx, ps, rd, keys, nullptr);
+    tm.mark();  // 2
+    const uint32_t kb = bucket_key_bits(ctx, ne, 0);
+    Buckets bk;
+    bucket(ctx, keys, flen, eperm, ne, NT, kb, bk, "p", false, false, false);
+    tm.mark();  // 3
+    uint64_t *pairs = nullptr;
+    uint64_t raw = 0;
+    const uint64_t cnt =
+        candidates_plus(ctx, keys, bk, flen, p.K, n, kappa, T, &pairs, &raw, "p");
+    finish_join(ctx, pp, d_offsets, p, rd, ne64, pairs, cnt, raw, nullptr, tm, out);
 }
 
 // ej_verify's work: preparation of the strings, their match masks and the
@@ -346,6 +464,23 @@ ej_status ej_join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_
                          const ej_params *p, ej_result *out) {
     if (!p || !out || !d_offsets) return EJ_EINVAL;
     return run_guarded(ctx, [&] { join_device(ctx, d_chars, d_offsets, n, *p, out); });
+}
+
+ej_status ej_join_plus_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                              uint32_t n, const ej_params *p, uint32_t delta, uint32_t T,
+                              ej_result *out) {
+    if (!p || !out || !d_offsets) return EJ_EINVAL;
+    return run_guarded(ctx, [&] { join_plus_device(ctx, d_chars, d_offsets, n, *p, delta, T, out); });
+}
+
+ej_status ej_join_plus(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
+                       const ej_params *p, uint32_t delta, uint32_t T, ej_result *out) {
+    if (!p || !out) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        check_params(*p, n);
+        HostInput h = upload(ctx, strings, offsets, n, "in");
+        join_plus_device(ctx, h.d_chars, h.d_offsets, n, *p, delta, T, out);
+    });
 }
 
 ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
