@@ -287,6 +287,68 @@ ej_status ej_verify_static(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *
                            uint32_t n, const uint64_t *d_pairs, uint64_t count, uint32_t K,
                            const uint32_t *d_Kq, int32_t *d_dist);
 
+/* ------------------------------------------------ diagnostics, calibration
+ * Distortion of the CGK embedding (Section 3.1: Hamming distance of the
+ * embeddings against edit distance, best of r embeddings) and the
+ * normalised Hamming distance under truncation (Section 6), on the device.
+ * d_ham [count][r] uint32: for pair e = (a << 32) | b and seed l < p->r, the
+ * Hamming distance between the first L symbols (p->L; 0 = ceil(average
+ * length), at most 3N) of the embeddings of s_a and s_b under R^l.  With
+ * delta > 0 each string contributes ceil(p->K / delta) suffixes (as in
+ * ej_join_plus) and the value is the minimum over the suffix pairs.  p->z and
+ * p->m are ignored.  Errors: EJ_EINVAL (a position >= n, r = 0),
+ * EJ_EUNSUPPORTED (more than 64 suffixes per string). */
+ej_status ej_embed_hamming(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                           uint32_t n, const ej_params *p, uint32_t delta,
+                           const uint64_t *d_pairs, uint64_t count, uint32_t *d_ham);
+
+typedef struct {
+    uint32_t K;              /* threshold of the join to calibrate */
+    uint32_t delta;          /* 0: EmbedJoin; > 0: EmbedJoin+ with this suffix step */
+    uint32_t T;              /* EmbedJoin+ tuple threshold (0: 2 if ceil(K/delta) > 1, else 1) */
+    uint32_t r_max;          /* seeds embedded; every r in 1..r_max is scored */
+    const uint32_t *z_list;  /* host arrays of the values to score */
+    uint32_t nz;
+    const uint32_t *m_list;  /* 1..64 each */
+    uint32_t nm;
+    const uint32_t *L_list;  /* truncations; 0 = ceil(average length); clamped to [1, 3N] */
+    uint32_t nL;
+    double target_recall;    /* the predicted recall the chosen point must reach */
+    uint64_t seed;           /* the seed the join will use */
+} ej_calib_opts;
+
+typedef struct {
+    uint32_t r, z, m, L;     /* the chosen point; r = 0 if no point reaches the target */
+    double recall;           /* its predicted recall over the sample pairs within K */
+    double false_rate;       /* its predicted chance that a sample pair beyond K is a candidate */
+    double work;             /* its predicted work per string (32-bit operations) */
+    uint64_t n_similar;      /* sample pairs within K (exact distance) */
+    uint64_t n_dissimilar;   /* sample pairs beyond K */
+    double best_recall;      /* the highest predicted recall on the grid */
+} ej_calib_result;
+
+/* Automated choice of (r, z, m, L) for a join of these strings at threshold
+ * K, from sample pairs (d_pairs, codes (a << 32) | b) that stand for the
+ * similar and dissimilar pairs of the workload (say, known-similar pairs and
+ * random pairs).  Each sample pair's exact distance decides whether it is
+ * within K; its embeddings' Hamming distances under the first r_max seeds
+ * (as ej_embed_hamming, at every L of the list) give, per grid point, the
+ * probability that the join makes it a candidate: with q_l = (1 - H_l/L)^m
+ * per table of seed l, 1 - prod_{l<r} (1 - q_l)^z for EmbedJoin, and for
+ * EmbedJoin+ the probability that the closest suffix pair is counted in at
+ * least T tables (a lower bound).  Predicted recall = the mean over pairs
+ * within K; false rate = the mean over pairs beyond K.  The chosen point
+ * reaches target_recall with the least predicted work per string: 3 r k L
+ * (walk) + 10 r k z m (hash) + 60 r k z (bucketing) + false_rate (n-1)/2
+ * 10 (K+1)/32 min(2K+64, average length) (rejecting false candidates), with
+ * k = ceil(K/delta) suffixes (1 for EmbedJoin).  table (host, may be NULL)
+ * receives [nL][r_max][nz][nm][3] = (recall, false rate, work) of every
+ * point.  Errors as ej_verify and ej_embed_hamming, EJ_EINVAL for an empty
+ * grid or r_max * z above 4096. */
+ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
+                       const uint64_t *d_pairs, uint64_t count, const ej_calib_opts *opts,
+                       ej_calib_result *out, double *table);
+
 /* Test hook: replace the drawn randomness of the next calls by explicit
  * values (host arrays): Rbits [r][L*sigma] 0/1 bytes (pi_j(sigma_k) at
  * (j-1)*sigma + k-1), pos [r][z][m] coordinates < L, v [r][z][m] values

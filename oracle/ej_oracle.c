@@ -671,6 +671,67 @@ int ejo_join_plus(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uin
     return 0;
 }
 
+/* ------------------------------------------- distortion diagnostics ---- */
+
+/* Section 3.1 (distortion of the CGK embedding) and Section 6 (normalised
+ * Hamming distance under truncation): for each pair (a, b) and seed l < r,
+ * the Hamming distance between the first L symbols of the two strings'
+ * embeddings under R^l.  With delta > 0 every string contributes
+ * kappa = ceil(K / delta) suffixes (as in EmbedJoin+) and the distance is the
+ * minimum over the kappa^2 suffix pairs.  ham[pair * r + l].  The alphabet and
+ * L (0 = ceil(average length), at most 3N) come from the whole set.  Returns
+ * 0, -1 for invalid sizes, -2 for a 256-symbol alphabet. */
+int ejo_embed_hamming(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t r,
+                      uint32_t L_req, uint64_t seed, uint32_t K, uint32_t delta,
+                      const uint64_t *pairs, uint64_t count, uint32_t *ham) {
+    if (r == 0) return -1;
+    uint64_t total = n ? offsets[n] - offsets[0] : 0;
+    int32_t lut[256];
+    int sigma = ejo_alphabet(chars + (n ? offsets[0] : 0), total, lut);
+    if (sigma > 255) return -2;
+    const uint32_t L = ejo_effective_L(offsets, n, L_req);
+    const uint32_t kappa = delta ? ejo_plus_kappa(K, delta) : 1;
+    uint8_t *codes = (uint8_t *)malloc(total ? total : 1);
+    for (uint64_t i = 0; i < total; i++) codes[i] = (uint8_t)lut[chars[offsets[0] + i]];
+    const uint64_t rb = (uint64_t)L * (uint64_t)sigma;
+    uint8_t *Rbits = (uint8_t *)malloc(r * rb + 1);
+    uint32_t *pos = (uint32_t *)malloc(sizeof(uint32_t) * r);
+    uint64_t *v = (uint64_t *)malloc(sizeof(uint64_t) * r);
+    ejo_draw(seed, r, 1, 1, L, (uint32_t)sigma, Rbits, pos, v);
+    uint8_t *ta = (uint8_t *)malloc(L), *tb = (uint8_t *)malloc(L);
+    for (uint64_t e = 0; e < count; e++) {
+        const uint32_t a = (uint32_t)(pairs[e] >> 32), b = (uint32_t)pairs[e];
+        const uint32_t la = (uint32_t)(offsets[a + 1] - offsets[a]);
+        const uint32_t lb = (uint32_t)(offsets[b + 1] - offsets[b]);
+        for (uint32_t l = 0; l < r; l++) {
+            uint32_t best = 0xFFFFFFFFu;
+            for (uint32_t ka = 0; ka < kappa; ka++) {
+                const uint64_t sa64 = (uint64_t)ka * delta;
+                const uint32_t sa = sa64 < la ? (uint32_t)sa64 : la;
+                ejo_cgk_embed(codes + (offsets[a] - offsets[0]) + sa, la - sa, Rbits + l * rb,
+                              (uint32_t)sigma, L, ta);
+                for (uint32_t kb = 0; kb < kappa; kb++) {
+                    const uint64_t sb64 = (uint64_t)kb * delta;
+                    const uint32_t sb = sb64 < lb ? (uint32_t)sb64 : lb;
+                    ejo_cgk_embed(codes + (offsets[b] - offsets[0]) + sb, lb - sb,
+                                  Rbits + l * rb, (uint32_t)sigma, L, tb);
+                    uint32_t h = 0;
+                    for (uint32_t j = 0; j < L; j++) h += ta[j] != tb[j];
+                    if (h < best) best = h;
+                }
+            }
+            ham[e * r + l] = best;
+        }
+    }
+    free(codes);
+    free(Rbits);
+    free(pos);
+    free(v);
+    free(ta);
+    free(tb);
+    return 0;
+}
+
 /* ------------------------------------------------------------- serving --
  * Serving is a systems layer on the method, not a step of the paper: an
  * index fixes the alphabet (its sorted distinct bytes), the truncation L and

@@ -102,6 +102,10 @@ def lib():
         L.ejo_plus_kappa.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
         L.ejo_plus_default_T.restype = ctypes.c_uint32
         L.ejo_plus_default_T.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.ejo_embed_hamming.restype = ctypes.c_int
+        L.ejo_embed_hamming.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_uint32, u64p, ctypes.c_uint64, u32p]
         L.ejo_keys.restype = ctypes.c_int
         L.ejo_keys.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -339,6 +343,24 @@ def brute_join(chars, offsets, K: int, full: bool = False):
         if cnt <= cap:
             return out[:cnt], d[:cnt]
         cap = cnt
+
+
+def embed_hamming(chars, offsets, pairs, r: int, L: int = 0, seed: int = 0, K: int = 0,
+                  delta: int = 0) -> np.ndarray:
+    """Hamming distance [count, r] between the L-symbol embeddings of each
+    pair's strings under each seed (with delta > 0: the minimum over the
+    ceil(K/delta)^2 suffix pairs)."""
+    c = _u8(chars)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    p = np.ascontiguousarray(pairs, dtype=np.uint64)
+    out = np.zeros(max(p.shape[0] * r, 1), dtype=np.uint32)
+    rc = lib().ejo_embed_hamming(_ptr(c, ctypes.c_uint8) if c.size else None,
+                                 _ptr(off, ctypes.c_uint64), off.shape[0] - 1, r, L, seed, K,
+                                 delta, _ptr(p, ctypes.c_uint64), p.shape[0],
+                                 _ptr(out, ctypes.c_uint32))
+    if rc != 0:
+        raise ValueError(f"invalid arguments (rc={rc})")
+    return out[:p.shape[0] * r].reshape(p.shape[0], r)
 
 
 def keys(index_chars, index_offsets, x_chars, x_offsets, r: int, z: int, m: int, seed: int = 0,

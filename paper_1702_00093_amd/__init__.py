@@ -30,7 +30,7 @@ EXPORTS = [
     "ej_join", "ej_join_ex", "ej_join_device", "ej_join_plus", "ej_join_plus_device",
     "ej_result_free", "ej_autotune",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_verify_static",
-    "ej_set_explicit_randomness",
+    "ej_set_explicit_randomness", "ej_embed_hamming", "ej_calibrate",
     "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
     "ej_index_size", "ej_qresult_free", "ej_index_free",
 ]
@@ -58,6 +58,23 @@ class _Result(ctypes.Structure):
                 ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64),
                 ("ms_verify_kernel", ctypes.c_float), ("verify_launches", ctypes.c_uint32),
                 ("verify_form", ctypes.c_uint32)]
+
+
+class CalibOpts(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_uint32), ("delta", ctypes.c_uint32), ("T", ctypes.c_uint32),
+                ("r_max", ctypes.c_uint32), ("z_list", ctypes.POINTER(ctypes.c_uint32)),
+                ("nz", ctypes.c_uint32), ("m_list", ctypes.POINTER(ctypes.c_uint32)),
+                ("nm", ctypes.c_uint32), ("L_list", ctypes.POINTER(ctypes.c_uint32)),
+                ("nL", ctypes.c_uint32), ("target_recall", ctypes.c_double),
+                ("seed", ctypes.c_uint64)]
+
+
+class CalibResult(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_uint32), ("z", ctypes.c_uint32), ("m", ctypes.c_uint32),
+                ("L", ctypes.c_uint32), ("recall", ctypes.c_double),
+                ("false_rate", ctypes.c_double), ("work", ctypes.c_double),
+                ("n_similar", ctypes.c_uint64), ("n_dissimilar", ctypes.c_uint64),
+                ("best_recall", ctypes.c_double)]
 
 
 class _QResult(ctypes.Structure):
@@ -107,6 +124,9 @@ def lib():
         "ej_verify": (c_int, [vp, vp, vp, u32, vp, u64, u32, vp, vp]),
         "ej_verify_static": (c_int, [vp, vp, vp, u32, vp, u64, u32, vp, vp]),
         "ej_set_explicit_randomness": (c_int, [vp, u32, u32, u32, u32, u32, vp, vp, vp]),
+        "ej_embed_hamming": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32, vp, u64, vp]),
+        "ej_calibrate": (c_int, [vp, vp, vp, u32, vp, u64, ctypes.POINTER(CalibOpts),
+                                 ctypes.POINTER(CalibResult), vp]),
         "ej_index_build": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), c_int,
                                    ctypes.POINTER(vp)]),
         "ej_query_batch": (c_int, [vp, vp, vp, u32, vp, ctypes.POINTER(_QResult)]),
@@ -366,6 +386,47 @@ class Context:
                        _ptr(d_offsets), n, _ptr(d_pairs) if cnt else None, cnt, K,
                        _ptr(d_Kq), _ptr(dist)))
         return dist[:cnt]
+
+    def embed_hamming(self, d_chars, d_offsets, d_pairs, r: int, L: int = 0, seed: int = 0,
+                      K: int = 0, delta: int = 0):
+        """ej_embed_hamming: [count, r] int32 Hamming distances of the pairs'
+        L-symbol embeddings per seed (min over suffix pairs when delta > 0)."""
+        torch = _torch()
+        n = d_offsets.numel() - 1
+        cnt = d_pairs.numel()
+        ham = torch.empty((max(cnt, 1), r), dtype=torch.int32, device=d_offsets.device)
+        p = Params(K, r, 1, 1, L, 0, seed)
+        _torch_stream_done()
+        self._check(lib().ej_embed_hamming(self._h, _ptr(d_chars) if d_chars.numel() else None,
+                                           _ptr(d_offsets), n, ctypes.byref(p), delta,
+                                           _ptr(d_pairs) if cnt else None, cnt, _ptr(ham)))
+        return ham[:cnt]
+
+    def calibrate(self, d_chars, d_offsets, d_pairs, K: int, r_max: int, z_list, m_list,
+                  L_list, target_recall: float = 0.99, seed: int = 0, delta: int = 0, T: int = 0,
+                  want_table: bool = False):
+        """ej_calibrate: returns a dict with the chosen (r, z, m, L) and its
+        predictions (and the whole grid as an array [nL, r_max, nz, nm, 3]
+        when want_table)."""
+        n = d_offsets.numel() - 1
+        cnt = d_pairs.numel()
+        zs = np.ascontiguousarray(z_list, dtype=np.uint32)
+        ms = np.ascontiguousarray(m_list, dtype=np.uint32)
+        Ls = np.ascontiguousarray(L_list, dtype=np.uint32)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        o = CalibOpts(K, delta, T, r_max, zs.ctypes.data_as(u32p), len(zs),
+                      ms.ctypes.data_as(u32p), len(ms), Ls.ctypes.data_as(u32p), len(Ls),
+                      float(target_recall), seed)
+        res = CalibResult()
+        table = np.zeros((len(Ls), r_max, len(zs), len(ms), 3)) if want_table else None
+        _torch_stream_done()
+        self._check(lib().ej_calibrate(self._h, _ptr(d_chars) if d_chars.numel() else None,
+                                       _ptr(d_offsets), n, _ptr(d_pairs) if cnt else None, cnt,
+                                       ctypes.byref(o), ctypes.byref(res), _ptr(table)))
+        out = {k: getattr(res, k) for k, _ in CalibResult._fields_}
+        if want_table:
+            out["table"] = table
+        return out
 
     def set_explicit_randomness(self, r, z, m, L, sigma, Rbits=None, pos=None, v=None):
         if Rbits is None:

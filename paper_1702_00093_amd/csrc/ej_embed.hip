@@ -427,6 +427,60 @@ __global__ void __launch_bounds__(64)
     }
 }
 
+// Distortion diagnostic (Section 3.1; normalised Hamming distance under
+// truncation, Section 6): thread (seed l, pair e, suffix pair ka, kb) walks
+// both strings' CGK embeddings side by side for L steps and counts the steps
+// whose symbols differ; the pair's value for seed l is the minimum over its
+// suffix pairs (atomicMin into ham, which starts at all ones).  Threads are
+// ordered seed-major so that a wave reads one seed's pi bits.  Once both
+// pointers are past their strings every further step emits bottom twice.
+template <bool RSTEP>
+__global__ void k_embed_hamming(const uint8_t *__restrict__ codes,
+                                const uint64_t *__restrict__ offsets, uint64_t base,
+                                const uint32_t *__restrict__ len,
+                                const uint64_t *__restrict__ pairs, uint64_t count, uint32_t r,
+                                uint32_t kappa, uint32_t delta, const uint32_t *__restrict__ Rstep,
+                                uint32_t Lpad, const uint32_t *__restrict__ Rwords, uint32_t nw,
+                                uint32_t sigma, uint32_t L, uint32_t *__restrict__ ham) {
+    const uint64_t kk = (uint64_t)kappa * kappa;
+    const uint64_t tot = (uint64_t)r * count * kk;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < tot;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t l = (uint32_t)(g / (count * kk));
+        const uint64_t rem = g - (uint64_t)l * count * kk;
+        const uint64_t e = rem / kk;
+        const uint32_t sp = (uint32_t)(rem - e * kk);
+        const uint32_t ka = sp / kappa, kb = sp - ka * kappa;
+        const uint64_t code = pairs[e];
+        const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
+        const uint32_t fa = len[a], fb = len[b];
+        const uint64_t wa = (uint64_t)ka * delta, wb = (uint64_t)kb * delta;
+        const uint32_t sa = wa < fa ? (uint32_t)wa : fa, sb = wb < fb ? (uint32_t)wb : fb;
+        const uint8_t *xa = codes + (offsets[a] - base) + sa;
+        const uint8_t *xb = codes + (offsets[b] - base) + sb;
+        const uint32_t la = fa - sa, lb = fb - sb;
+        const uint32_t *Rs = Rstep + (size_t)l * Lpad;
+        const uint32_t *Rw = Rwords + (size_t)l * nw;
+        uint32_t ia = 0, ib = 0, h = 0;
+        for (uint32_t j = 0; j < L; j++) {
+            const bool in_a = ia < la, in_b = ib < lb;
+            if (!in_a && !in_b) break;
+            const uint32_t ca = in_a ? xa[ia] : sigma, cb = in_b ? xb[ib] : sigma;
+            h += ca != cb ? 1u : 0u;
+            if (RSTEP) {
+                const uint32_t w = Rs[j];
+                ia += in_a ? (w >> ca) & 1u : 0u;
+                ib += in_b ? (w >> cb) & 1u : 0u;
+            } else {
+                const uint32_t ba = j * sigma + ca, bb = j * sigma + cb;
+                ia += in_a ? (Rw[ba >> 5] >> (ba & 31)) & 1u : 0u;
+                ib += in_b ? (Rw[bb >> 5] >> (bb & 31)) & 1u : 0u;
+            }
+        }
+        atomicMin(&ham[e * r + l], h);
+    }
+}
+
 inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
     uint64_t g = (work + block - 1) / block;
     uint64_t cap = (uint64_t)ctx->num_cu * 16;
@@ -628,6 +682,26 @@ void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, u
         rstep ? launch(k_embed<4, true>) : launch(k_embed<4, false>);
     else
         rstep ? launch(k_embed<8, true>) : launch(k_embed<8, false>);
+}
+
+void embed_hamming(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_pairs,
+                   uint64_t count, uint32_t kappa, uint32_t delta, uint32_t *d_ham) {
+    if (count == 0) return;
+    const uint64_t tot = (uint64_t)rd.r * count * kappa * kappa;
+    EJ_HIP(hipMemsetAsync(d_ham, 0xFF, 4 * count * rd.r, ctx->stream));
+    const uint32_t sig = rd.sigma ? rd.sigma : 1;
+    auto launch = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
+                           (const uint8_t *)pp.d_codes, pp.d_offsets, pp.base,
+                           (const uint32_t *)pp.d_len, d_pairs, count, rd.r, kappa, delta,
+                           (const uint32_t *)rd.d_Rstep, rd.Lpad, (const uint32_t *)rd.d_Rwords,
+                           rd.nw, sig, rd.L, d_ham);
+        EJ_CHECK_LAUNCH();
+    };
+    if (sig <= 32)
+        launch(k_embed_hamming<true>);
+    else
+        launch(k_embed_hamming<false>);
 }
 
 }  // namespace ej

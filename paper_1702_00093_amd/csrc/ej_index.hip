@@ -174,25 +174,6 @@ __global__ void k_q_out_compact(const uint64_t *__restrict__ pairs, const int32_
     }
 }
 
-template <typename F>
-ej_status guarded(ej_ctx *ctx, F &&fn) {
-    if (!ctx) return EJ_EINVAL;
-    try {
-        EJ_HIP(hipSetDevice(ctx->device));
-        fn();
-        ctx->err.clear();
-        return EJ_OK;
-    } catch (const Error &e) {
-        ctx->err = e.msg;
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipGetLastError();
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        ctx->err = "host allocation failed";
-        return EJ_ENOMEM;
-    }
-}
-
 // Device bytes of a batch before its candidates are known (the admission
 // estimate of ej_query_workspace_estimate).
 uint64_t estimate(const ej_index *ix, uint64_t qbytes, uint32_t nq) {
@@ -235,7 +216,7 @@ ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *of
     ej_index *ix = new (std::nothrow) ej_index();
     if (!ix) return EJ_ENOMEM;
     ix->ctx = ctx;
-    ej_status st = guarded(ctx, [&] {
+    ej_status st = run_guarded(ctx, [&] {
         if (p->r == 0 || p->z == 0 || p->m == 0 || p->m > 64 || (uint64_t)p->r * p->z > 4096)
             fail(EJ_EINVAL, "invalid r, z, m");
         if (n >= 0x80000000u) fail(EJ_EINVAL, "n must be below 2^31");
@@ -338,7 +319,7 @@ ej_status ej_query_batch(ej_index *ix, const uint8_t *q, const uint64_t *q_offse
     if (!ix || !q_offsets || !out || (nq && !Kq)) return EJ_EINVAL;
     ej_ctx *ctx = ix->ctx;
     memset(out, 0, sizeof(*out));
-    ej_status st = guarded(ctx, [&] {
+    ej_status st = run_guarded(ctx, [&] {
         for (uint32_t i = 0; i < nq; i++) {
             if (q_offsets[i + 1] < q_offsets[i]) fail(EJ_EINVAL, "query offsets decrease");
             if (verify_lanes_for(Kq[i]) == 0) fail(EJ_EUNSUPPORTED, "query threshold above 2046");

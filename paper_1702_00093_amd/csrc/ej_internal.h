@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <functional>
+#include <new>
 #include <map>
 #include <string>
 #include <vector>
@@ -135,6 +136,13 @@ struct ej_ctx {
 
 namespace ej {
 
+// Runs fn for an entry point of the C ABI: the context's device is made
+// current, an Error becomes its status code and message (the stream is
+// drained and the HIP error state cleared), a failed host allocation becomes
+// EJ_ENOMEM.  No exception leaves.
+template <typename F>
+ej_status run_guarded(ej_ctx *ctx, F &&fn);
+
 void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes);
 // Size of the static scratch array of ej_verify_static (one per device).
 constexpr size_t STATIC_SCRATCH_BYTES = 64ull << 20;
@@ -228,6 +236,15 @@ void draw_randomness(ej_ctx *ctx, const ej_params &p, uint32_t L, uint32_t sigma
 void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, uint8_t *d_sig,
                 uint32_t *d_dk = nullptr, uint32_t *d_rank_ids = nullptr, uint32_t dk_shift = 0);
 
+// Distortion diagnostic: d_ham[e * r + l] = Hamming distance between the
+// first L symbols of the embeddings of pair e's strings under seed l (the
+// minimum over the kappa^2 suffix pairs, suffix k starting at k * delta).
+void embed_hamming(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_pairs,
+                   uint64_t count, uint32_t kappa, uint32_t delta, uint32_t *d_ham);
+// Rejects (EJ_EINVAL) pairs whose positions are not below n_a / n_b.
+void check_pairs(ej_ctx *ctx, const uint64_t *d_pairs, uint64_t count, uint32_t n_a,
+                 uint32_t n_b);
+
 struct Buckets {
     uint32_t T = 0, n = 0;
     uint32_t *d_ids = nullptr;        // [T*n]
@@ -297,5 +314,24 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             unsigned long long *d_columns = nullptr, const uint32_t *d_order = nullptr);
 
 uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported
+
+template <typename F>
+ej_status run_guarded(ej_ctx *ctx, F &&fn) {
+    if (!ctx) return EJ_EINVAL;
+    try {
+        EJ_HIP(hipSetDevice(ctx->device));
+        fn();
+        ctx->err.clear();
+        return EJ_OK;
+    } catch (const Error &e) {
+        ctx->err = e.msg;
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipGetLastError();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        ctx->err = "host allocation failed";
+        return EJ_ENOMEM;
+    }
+}
 
 }  // namespace ej

@@ -144,25 +144,6 @@ struct StageTimer {
     }
 };
 
-template <typename F>
-ej_status run_guarded(ej_ctx *ctx, F &&fn) {
-    if (!ctx) return EJ_EINVAL;
-    try {
-        EJ_HIP(hipSetDevice(ctx->device));
-        fn();
-        ctx->err.clear();
-        return EJ_OK;
-    } catch (const Error &e) {
-        ctx->err = e.msg;
-        (void)hipStreamSynchronize(ctx->stream);
-        (void)hipGetLastError();
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        ctx->err = "host allocation failed";
-        return EJ_ENOMEM;
-    }
-}
-
 }  // namespace
 
 // Verification (A5) and output (A6) of a join whose candidates are known:
@@ -397,6 +378,19 @@ void join_plus_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
     finish_join(ctx, pp, d_offsets, p, rd, ne64, pairs, cnt, raw, nullptr, tm, out);
 }
 
+void check_pairs(ej_ctx *ctx, const uint64_t *d_pairs, uint64_t count, uint32_t n_a,
+                 uint32_t n_b) {
+    if (!count) return;
+    uint32_t *d_bad = ws<uint32_t>(ctx, "v_bad", 1);
+    EJ_HIP(hipMemsetAsync(d_bad, 0, 4, ctx->stream));
+    hipLaunchKernelGGL(k_check_pairs, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
+                       d_pairs, count, n_a, n_b, d_bad);
+    EJ_CHECK_LAUNCH();
+    uint32_t bad = 0;
+    read_back(ctx, d_bad, 4, &bad);
+    if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
+}
+
 // ej_verify's work: preparation of the strings, their match masks and the
 // verification kernels, on the context's workspace.
 void verify_entry(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
@@ -405,16 +399,7 @@ void verify_entry(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets
     if (!d_Kq && verify_lanes_for(K) == 0) fail(EJ_EUNSUPPORTED, "K above 2046 is not supported");
     Prep pp;
     prepare(ctx, d_chars, d_offsets, n, 0, pp, "v", nullptr, 0, 0, false);
-    if (count) {
-        uint32_t *d_bad = ws<uint32_t>(ctx, "v_bad", 1);
-        EJ_HIP(hipMemsetAsync(d_bad, 0, 4, ctx->stream));
-        hipLaunchKernelGGL(k_check_pairs, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
-                           ctx->stream, d_pairs, count, n, n, d_bad);
-        EJ_CHECK_LAUNCH();
-        uint32_t bad = 0;
-        read_back(ctx, d_bad, 4, &bad);
-        if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
-    }
+    check_pairs(ctx, d_pairs, count, n, n);
     RowMasks masks;
     if (count)
         build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "v");

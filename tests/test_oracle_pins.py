@@ -702,3 +702,29 @@ def test_plus_threshold_probability_closed_form(oracle_lib):
     assert 0.1 < exp_rate < 0.9
     assert abs(hits / seeds - exp_rate) < 4.5 * se
     assert abs(counts / seeds - exp_count) < 4.5 * (z / seeds) ** 0.5
+
+
+# ------------------------------------------ distortion diagnostics ----
+
+def test_embed_hamming_properties(oracle_lib):
+    rng = np.random.default_rng(2)
+    DNA = np.frombuffer(b"ACGT", np.uint8)
+    x = bytes(DNA[rng.integers(0, 4, size=150)])
+    y = bytes(sd.mutate(rng, np.frombuffer(x, np.uint8), 6, DNA))
+    P = bytes(DNA[rng.integers(0, 4, size=10)])
+    col = sd.from_strings([x, x, y, P + x, bytes(DNA[rng.integers(0, 4, size=150)])])
+    codes = lambda pr: np.array([(a << 32) | b for a, b in pr], dtype=np.uint64)
+    pr = [(0, 1), (0, 2), (2, 0), (0, 3), (0, 4)]
+    r, L = 6, 400
+    h = oracle_lib.embed_hamming(col.chars, col.offsets, codes(pr), r, L=L, seed=3)
+    assert (h[0] == 0).all()                        # identical strings
+    assert (h[1] == h[2]).all()                     # symmetric
+    assert (h <= L).all()
+    ed = oracle_lib.ed_full(x, y)
+    assert (h[1] >= ed).all()                       # walks end well within L = 400
+    hs = oracle_lib.embed_hamming(col.chars, col.offsets, codes(pr), r, L=L, seed=3, K=30,
+                                  delta=10)
+    assert (hs <= h).all()                          # the (0, 0) suffix pair is among those
+    assert (hs[3] == 0).all() and (h[3] > 0).any()  # P + x: its second suffix is x
+    # the random pair is farther than the similar pair under every seed
+    assert (h[4] > h[1]).all()
