@@ -671,6 +671,123 @@ int ejo_join_plus(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uin
     return 0;
 }
 
+/* ------------------------------------------- grouping (Section 4.1) -- */
+
+/* Group g (0-based) of the grouping alternative to truncation holds the
+ * strings of length in ((g)K, (g+2)K], for g = 0 .. G-1 with
+ * G = max(1, ceil(N/K) - 1); group 0 also holds the empty strings (they pair
+ * with every string of length <= K).  With K = 0 there is one group per
+ * length.  Every string is in at most two groups and every pair within K in
+ * length shares one. */
+static int in_group(uint64_t len, uint64_t g, uint32_t K) {
+    if (K == 0) return len == g;
+    if (g == 0 && len == 0) return 1;
+    return len > g * K && len <= (g + 2) * K;
+}
+
+static uint64_t group_count(uint64_t N, uint32_t K) {
+    if (K == 0) return N + 1;
+    uint64_t c = (N + K - 1) / K;
+    return c > 1 ? c - 1 : 1;
+}
+
+/* EmbedJoin with grouping instead of truncation: EmbedJoin (ejo_join) on each
+ * group on its own -- its own alphabet, the same seed, L = 3 N_g (N_g = the
+ * group's longest string; the walks are not truncated) unless L_req > 0 asks
+ * for a truncation -- and the union of the groups' candidates and outputs.
+ * n_raw sums the groups' raw counts.  Keys and signatures are not kept.
+ * Returns 0, or the first failing group's code. */
+int ejo_join_grouped(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+                     uint32_t r, uint32_t z, uint32_t m, uint32_t L_req, uint64_t seed,
+                     ejo_result *res) {
+    memset(res, 0, sizeof(*res));
+    if (r == 0 || z == 0 || m == 0) return -1;
+    uint64_t N = 0;
+    for (uint32_t i = 0; i < n; i++)
+        if (offsets[i + 1] - offsets[i] > N) N = offsets[i + 1] - offsets[i];
+    const uint64_t G = group_count(N, K);
+    uint64_t ccap = 1024, cc = 0, ocap = 1024, oc = 0;
+    uint64_t *cand = (uint64_t *)malloc(sizeof(uint64_t) * ccap);
+    uint64_t *outp = (uint64_t *)malloc(sizeof(uint64_t) * ocap);
+    uint32_t *outd = (uint32_t *)malloc(sizeof(uint32_t) * ocap);
+    uint32_t *ids = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint64_t *soff = (uint64_t *)malloc(sizeof(uint64_t) * (n + 1));
+    uint8_t *sub = (uint8_t *)malloc((n ? offsets[n] - offsets[0] : 0) + 1);
+    int rc = 0;
+    for (uint64_t g = 0; g < G && rc == 0; g++) {
+        uint32_t k = 0;
+        uint64_t Ng = 0, t = 0;
+        soff[0] = 0;
+        for (uint32_t i = 0; i < n; i++) {
+            const uint64_t len = offsets[i + 1] - offsets[i];
+            if (!in_group(len, g, K)) continue;
+            memcpy(sub + t, chars + offsets[i], len);
+            t += len;
+            ids[k++] = i;
+            soff[k] = t;
+            if (len > Ng) Ng = len;
+        }
+        if (k < 2) continue;
+        uint64_t Lg = L_req ? L_req : 3 * Ng;
+        if (Lg == 0) Lg = 1;
+        ejo_result gr;
+        rc = ejo_join_opts(sub, soff, k, K, r, z, m, (uint32_t)Lg, seed, NULL, NULL, NULL,
+                           EJO_NO_SIG, &gr);
+        if (rc != 0) break;
+        res->n_raw += gr.n_raw;
+        for (uint64_t e = 0; e < gr.n_cand; e++) {
+            if (cc == ccap) cand = (uint64_t *)realloc(cand, sizeof(uint64_t) * (ccap *= 2));
+            cand[cc++] = ((uint64_t)ids[gr.cand[e] >> 32] << 32) | ids[gr.cand[e] & 0xFFFFFFFFu];
+        }
+        for (uint64_t e = 0; e < gr.n_out; e++) {
+            if (oc == ocap) {
+                ocap *= 2;
+                outp = (uint64_t *)realloc(outp, sizeof(uint64_t) * ocap);
+                outd = (uint32_t *)realloc(outd, sizeof(uint32_t) * ocap);
+            }
+            outp[oc] = ((uint64_t)ids[gr.out[e] >> 32] << 32) | ids[gr.out[e] & 0xFFFFFFFFu];
+            outd[oc++] = gr.out_dist[e];
+        }
+        ejo_result_free(&gr);
+    }
+    free(ids);
+    free(soff);
+    free(sub);
+    /* union: sort and keep one of each (a pair found by two groups has one
+     * distance) */
+    qsort(cand, cc, sizeof(uint64_t), cmp_u64);
+    uint64_t u = 0;
+    for (uint64_t e = 0; e < cc; e++)
+        if (e == 0 || cand[e] != cand[e - 1]) cand[u++] = cand[e];
+    res->n_cand = u;
+    res->cand = cand;
+    /* sort the outputs with their distances; keep one of each pair (a pair
+     * found by two groups has one distance) */
+    ejo_tuple *od = (ejo_tuple *)malloc(sizeof(ejo_tuple) * (oc ? oc : 1));
+    for (uint64_t e = 0; e < oc; e++) {
+        od[e].x = (uint32_t)(outp[e] >> 32);
+        od[e].y = (uint32_t)outp[e];
+        od[e].kx = outd[e];
+        od[e].ky = 0;
+    }
+    qsort(od, oc, sizeof(ejo_tuple), cmp_tuple);
+    res->out = (uint64_t *)malloc(sizeof(uint64_t) * (oc ? oc : 1));
+    res->out_dist = (uint32_t *)malloc(sizeof(uint32_t) * (oc ? oc : 1));
+    uint64_t no = 0;
+    for (uint64_t e = 0; e < oc; e++) {
+        const uint64_t code = ((uint64_t)od[e].x << 32) | od[e].y;
+        if (no && res->out[no - 1] == code) continue;
+        res->out[no] = code;
+        res->out_dist[no] = od[e].kx;
+        no++;
+    }
+    res->n_out = no;
+    free(od);
+    free(outp);
+    free(outd);
+    return rc;
+}
+
 /* ------------------------------------------- distortion diagnostics ---- */
 
 /* Section 3.1 (distortion of the CGK embedding) and Section 6 (normalised

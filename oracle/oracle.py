@@ -106,6 +106,9 @@ def lib():
         L.ejo_embed_hamming.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_uint32, u64p, ctypes.c_uint64, u32p]
+        L.ejo_join_grouped.restype = ctypes.c_int
+        L.ejo_join_grouped.argtypes = [u8p, u64p] + [ctypes.c_uint32] * 6 + [ctypes.c_uint64] + \
+            [ctypes.POINTER(_Result)]
         L.ejo_keys.restype = ctypes.c_int
         L.ejo_keys.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
@@ -303,6 +306,26 @@ def join_plus(chars, offsets, K: int, r: int, z: int, m: int, delta: int, T: int
         raise ValueError(f"oracle join_plus rejected its arguments (rc={rc})")
     try:
         return JoinResult(res, n, r, z, m, key_cols=n * plus_kappa(K, delta))
+    finally:
+        lib().ejo_result_free(ctypes.byref(res))
+
+
+def join_grouped(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0,
+                 L: int = 0) -> JoinResult:
+    """The oracle's grouping variant (Section 4.1): EmbedJoin on each length
+    group ((g)K, (g+2)K] on its own (L = 3 x the group's longest string unless
+    L > 0), the union of the groups' candidates and outputs."""
+    c = _u8(chars)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    n = off.shape[0] - 1
+    res = _Result()
+    rc = lib().ejo_join_grouped(_ptr(c, ctypes.c_uint8) if c.size else None,
+                                _ptr(off, ctypes.c_uint64), n, K, r, z, m, L, seed,
+                                ctypes.byref(res))
+    if rc != 0:
+        raise ValueError(f"oracle join_grouped rejected its arguments (rc={rc})")
+    try:
+        return JoinResult(res, n, r, z, m, key_cols=0)
     finally:
         lib().ejo_result_free(ctypes.byref(res))
 

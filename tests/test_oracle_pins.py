@@ -728,3 +728,80 @@ def test_embed_hamming_properties(oracle_lib):
     assert (hs[3] == 0).all() and (h[3] > 0).any()  # P + x: its second suffix is x
     # the random pair is farther than the similar pair under every seed
     assert (h[4] > h[1]).all()
+
+
+# ------------------------------------------------ grouping (§4.1) ----
+
+def _groups(lens, K):
+    """Member lists of the length groups ((g)K, (g+2)K] (group 0 with the
+    empty strings; one group per length when K = 0)."""
+    N = int(lens.max()) if len(lens) else 0
+    if K == 0:
+        return [np.nonzero(lens == g)[0] for g in range(N + 1)]
+    G = max(1, -(-N // K) - 1)
+    return [np.nonzero(((lens > g * K) & (lens <= (g + 2) * K)) | ((g == 0) & (lens == 0)))[0]
+            for g in range(G)]
+
+
+@pytest.mark.parametrize("seed,K,r,z,m", [(0, 40, 3, 4, 3), (1, 25, 2, 5, 2), (2, 0, 2, 3, 1)])
+def test_grouped_candidates_equal_definition(oracle_lib, seed, K, r, z, m):
+    """A grouped candidate is a pair of one group, within K in length, that
+    shares a key in some table of that group's own join (its alphabet,
+    L = 3 x its longest string); keys from the oracle's key function."""
+    col = sd.clusters(seed, 12, lambda rr, b: rr.integers(2, 5), lambda rr: rr.integers(0, 160),
+                      lambda rr, LL: rr.poisson(2))
+    res = oracle_lib.join_grouped(col.chars, col.offsets, K, r, z, m, seed=seed)
+    lens = col.lengths()
+    want = set()
+    raw = 0
+    for ids in _groups(lens, K):
+        if len(ids) < 2:
+            continue
+        sub = sd.from_strings([col.string(int(i)) for i in ids])
+        Lg = max(1, 3 * int(lens[ids].max()))
+        k = oracle_lib.keys(sub.chars, sub.offsets, sub.chars, sub.offsets, r, z, m, seed=seed,
+                            L=Lg)
+        for x in range(len(ids)):
+            for y in range(x + 1, len(ids)):
+                if abs(int(lens[ids[x]]) - int(lens[ids[y]])) <= K:
+                    c = int((k[x] == k[y]).sum())
+                    raw += c
+                    if c:
+                        want.add((int(ids[x]), int(ids[y])))
+    assert set(map(tuple, res.cand_pairs.tolist())) == want
+    assert res.n_raw == raw
+    d = oracle_lib.verify_pairs(col.chars, col.offsets, res.cand, K)
+    assert res.out.tolist() == res.cand[d <= K].tolist()
+    assert res.out_dist.tolist() == d[d <= K].tolist()
+
+
+def test_grouping_covers_every_length_pair(oracle_lib):
+    """Every pair within K in length shares a group (the paper's premise), at
+    the group boundaries too: identical strings of lengths 0, K, 2K, 2K+1,
+    3K ... always join (identical strings collide in every table)."""
+    K = 10
+    DNA = np.frombuffer(b"ACGT", np.uint8)
+    rng = np.random.default_rng(6)
+    strings = []
+    for L in (0, 1, K - 1, K, K + 1, 2 * K, 2 * K + 1, 3 * K, 3 * K + 1, 5 * K):
+        s = bytes(DNA[rng.integers(0, 4, size=L)])
+        strings += [s, s]
+    col = sd.from_strings(strings)
+    res = oracle_lib.join_grouped(col.chars, col.offsets, K, 1, 1, 4, seed=2)
+    got = set(map(tuple, res.out_pairs.tolist()))
+    assert all((2 * i, 2 * i + 1) in got for i in range(len(strings) // 2))
+    lens = col.lengths()
+    for a in range(col.n):
+        for b in range(a + 1, col.n):
+            if abs(int(lens[a]) - int(lens[b])) <= K:
+                assert any(a in g and b in g for g in _groups(lens, K))
+
+
+def test_grouping_with_one_group_is_the_join_untruncated(oracle_lib):
+    col, _ = sd.tiny_dna(3, n_bases=12)
+    K = 3000  # above every length: one group
+    g = oracle_lib.join_grouped(col.chars, col.offsets, K, 2, 3, 6, seed=1)
+    N = int(col.lengths().max())
+    a = oracle_lib.join(col.chars, col.offsets, K, 2, 3, 6, seed=1, L=3 * N)
+    assert g.cand.tolist() == a.cand.tolist() and g.n_raw == a.n_raw
+    assert g.out.tolist() == a.out.tolist()
