@@ -202,6 +202,23 @@ ej_status ej_join_plus_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_
                               uint32_t n, const ej_params *p, uint32_t delta, uint32_t T,
                               ej_result *out);
 
+/* EmbedJoin with grouping instead of truncation (Section 4.1): the strings
+ * are split into length groups -- group g (0-based) holds the strings of
+ * length in (gK, (g+2)K], g < max(1, ceil(N/K) - 1), N the longest length;
+ * group 0 also holds the empty strings; with K = 0 one group per length --
+ * so every string is in at most two groups and every pair within K in
+ * length shares one.  Each group is joined as a set of its own (its own
+ * alphabet; walks of L = 3 x the group's longest string, untruncated, or the
+ * caller's p->L; the same seed), and the result is the union: candidates are
+ * the distinct pairs of all groups (a pair two groups find is verified
+ * once), n_raw the sum of the groups' raw counts, out->L = p->L.  Host
+ * strings; ej_join_grouped_device takes device-resident ones.  Errors as
+ * ej_join. */
+ej_status ej_join_grouped(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets,
+                          uint32_t n, const ej_params *p, ej_result *out);
+ej_status ej_join_grouped_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                                 uint32_t n, const ej_params *p, ej_result *out);
+
 void ej_result_free(ej_result *res);
 
 /* Autotuner of the batched form, for callers that run many joins of one

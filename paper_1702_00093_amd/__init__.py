@@ -28,6 +28,7 @@ EXPORTS = [
     "ej_create", "ej_destroy", "ej_last_error", "ej_version", "ej_workspace_bytes",
     "ej_tune_set", "ej_tune_get",
     "ej_join", "ej_join_ex", "ej_join_device", "ej_join_plus", "ej_join_plus_device",
+    "ej_join_grouped", "ej_join_grouped_device",
     "ej_result_free", "ej_autotune",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_verify_static",
     "ej_set_explicit_randomness", "ej_embed_hamming", "ej_calibrate",
@@ -115,6 +116,10 @@ def lib():
                                  ctypes.POINTER(_Result)]),
         "ej_join_plus_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32, u32,
                                         ctypes.POINTER(_Result)]),
+        "ej_join_grouped": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params),
+                                    ctypes.POINTER(_Result)]),
+        "ej_join_grouped_device": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params),
+                                           ctypes.POINTER(_Result)]),
         "ej_result_free": (None, [ctypes.POINTER(_Result)]),
         "ej_autotune": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32,
                                 ctypes.POINTER(ctypes.c_float)]),
@@ -258,6 +263,12 @@ class Context:
         suffixes per string, tuple threshold T (0: the paper's rule)."""
         return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), (delta, T))
 
+    def join_grouped(self, chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0,
+                     L: int = 0, flags: int = 0) -> JoinResult:
+        """EmbedJoin with grouping instead of truncation (ej_join_grouped /
+        ej_join_grouped_device)."""
+        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), "grouped")
+
     def _join(self, chars, offsets, p, plus) -> JoinResult:
         res = _Result()
         if _is_device(chars) or _is_device(offsets):
@@ -271,6 +282,9 @@ class Context:
             if plus is None:
                 st = lib().ej_join_device(self._h, _ptr(chars), _ptr(offsets), n,
                                           ctypes.byref(p), ctypes.byref(res))
+            elif plus == "grouped":
+                st = lib().ej_join_grouped_device(self._h, _ptr(chars), _ptr(offsets), n,
+                                                  ctypes.byref(p), ctypes.byref(res))
             else:
                 st = lib().ej_join_plus_device(self._h, _ptr(chars), _ptr(offsets), n,
                                                ctypes.byref(p), plus[0], plus[1],
@@ -282,6 +296,9 @@ class Context:
             cp = _ptr(c) if c.size else None
             if plus is None:
                 st = lib().ej_join_ex(self._h, cp, _ptr(o), n, ctypes.byref(p), ctypes.byref(res))
+            elif plus == "grouped":
+                st = lib().ej_join_grouped(self._h, cp, _ptr(o), n, ctypes.byref(p),
+                                           ctypes.byref(res))
             else:
                 st = lib().ej_join_plus(self._h, cp, _ptr(o), n, ctypes.byref(p), plus[0],
                                         plus[1], ctypes.byref(res))

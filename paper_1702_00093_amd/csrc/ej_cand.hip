@@ -819,4 +819,28 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     return cnt;
 }
 
+uint64_t unique_sorted_pairs(ej_ctx *ctx, const uint64_t *d_sorted, uint64_t cnt, uint32_t B,
+                             uint64_t **d_out, const char *tag) {
+    std::string t(tag);
+    *d_out = ws<uint64_t>(ctx, t + "_upairs", 1);
+    if (cnt == 0) return 0;
+    if (cnt >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "more than 2^32 pairs to de-duplicate");
+    uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", cnt);
+    uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", cnt);
+    uint64_t *d_n = ws<uint64_t>(ctx, t + "_ucnt", 1);
+    hipLaunchKernelGGL(k_unique_flags<uint64_t>, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
+                       ctx->stream, d_sorted, cnt, flags);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, flags, pos, cnt, d_n);
+    uint64_t u = 0;
+    read_back(ctx, d_n, 8, &u);
+    uint64_t *out = ws<uint64_t>(ctx, t + "_upairs", u);
+    hipLaunchKernelGGL(k_unique_compact<uint64_t>, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
+                       ctx->stream, d_sorted, cnt, B, (const uint32_t *)flags,
+                       (const uint32_t *)pos, out, (uint32_t *)nullptr);
+    EJ_CHECK_LAUNCH();
+    *d_out = out;
+    return u;
+}
+
 }  // namespace ej

@@ -287,6 +287,11 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
                          const uint32_t *d_len_entry, uint32_t K, uint32_t nstr, uint32_t kappa,
                          uint32_t T, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag);
 
+// One of each code of a sorted array of pair codes (a << B | b), unpacked to
+// (a << 32) | b into a workspace buffer named after `tag`; returns the count.
+uint64_t unique_sorted_pairs(ej_ctx *ctx, const uint64_t *d_sorted, uint64_t cnt, uint32_t B,
+                             uint64_t **d_out, const char *tag);
+
 // Match masks of a string set, one bit array per (string, symbol): bit b of
 // word w of string s and symbol c is set iff x_s[32w + b] == c, for
 // W_s = ceil(|x_s| / 32) words; string s's arrays start at word off[s].

@@ -119,6 +119,30 @@ __global__ void k_entry_perm(const uint32_t *__restrict__ perm, uint32_t n, uint
     }
 }
 
+// Grouping: the strings of one length group copied into a compact set
+// (block b copies string ids[b] to dst + soff[b]).
+__global__ void k_gather_strings(const uint8_t *__restrict__ chars,
+                                 const uint64_t *__restrict__ offsets,
+                                 const uint32_t *__restrict__ ids, uint32_t k,
+                                 const uint64_t *__restrict__ soff, uint8_t *__restrict__ dst) {
+    for (uint32_t b = blockIdx.x; b < k; b += gridDim.x) {
+        const uint8_t *src = chars + offsets[ids[b]];
+        uint8_t *d = dst + soff[b];
+        const uint64_t len = soff[b + 1] - soff[b];
+        for (uint64_t i = threadIdx.x; i < len; i += blockDim.x) d[i] = src[i];
+    }
+}
+
+// A group's candidate codes (local positions) to positions in the whole set.
+__global__ void k_map_pairs(const uint64_t *__restrict__ pairs, uint64_t cnt,
+                            const uint32_t *__restrict__ ids, uint64_t *__restrict__ out) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t c = pairs[e];
+        out[e] = ((uint64_t)ids[c >> 32] << 32) | ids[(uint32_t)c];
+    }
+}
+
 void check_params(const ej_params &p, uint32_t n) {
     if (p.r == 0 || p.z == 0 || p.m == 0) fail(EJ_EINVAL, "r, z and m must be positive");
     if (p.m > 64) fail(EJ_EINVAL, "m must be at most 64");
@@ -236,7 +260,10 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
     if (xbytes) {
         if (cnt)
             EJ_HIP(hipMemcpyAsync(xp, d_cols, 8, hipMemcpyDeviceToHost, ctx->stream));
-        EJ_HIP(hipMemcpyAsync(xp + 8, rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost, ctx->stream));
+        if (rd.d_J)
+            EJ_HIP(hipMemcpyAsync(xp + 8, rd.d_J, 4ull * p.r, hipMemcpyDeviceToHost, ctx->stream));
+        else
+            memset(xp + 8, 0, 4ull * p.r);
     }
     sync(ctx);
     if (nout) {
@@ -391,6 +418,116 @@ void check_pairs(ej_ctx *ctx, const uint64_t *d_pairs, uint64_t count, uint32_t 
     if (bad) fail(EJ_EINVAL, "a pair refers to a position >= n");
 }
 
+// Length groups of the grouping alternative to truncation (Section 4.1):
+// group g holds the strings of length in (gK, (g+2)K] (group 0 also the
+// empty ones; one group per length when K = 0), g < max(1, ceil(N/K) - 1).
+inline bool in_group(uint64_t len, uint64_t g, uint32_t K) {
+    if (K == 0) return len == g;
+    if (g == 0 && len == 0) return true;
+    return len > g * K && len <= (g + 2) * K;
+}
+
+// EmbedJoin with grouping instead of truncation: the front end (A0-A4) runs
+// on each group's strings as a set of its own (its alphabet; walks of
+// L = 3 x its longest string, or the caller's L), the groups' candidates are
+// mapped to positions in the whole set and de-duplicated, and the union is
+// verified once (a pair found by two groups is verified once, not twice).
+void join_grouped_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                         uint32_t n, const ej_params &p, ej_result *out) {
+    check_params(p, n);
+    memset(out, 0, sizeof(*out));
+    StageTimer tm(ctx, (p.flags & EJ_FLAG_TIMING) != 0);
+    tm.mark();  // 0
+    Prep pp;
+    prepare(ctx, d_chars, d_offsets, n, 0, pp, "j");
+    out->sigma = pp.sigma;
+    std::vector<uint32_t> len(n);
+    if (n) {
+        EJ_HIP(hipMemcpyAsync(len.data(), pp.d_len, 4ull * n, hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+    }
+    const uint64_t N = pp.maxlen;
+    const uint64_t G = p.K == 0 ? N + 1 : std::max<uint64_t>(1, (N + p.K - 1) / p.K - 1);
+    const uint32_t NT = p.r * p.z;
+    tm.mark();  // 1: the groups' front ends follow
+    // the grouping's own buffers ("grp_*") must not share a name with the
+    // stage buffers of the groups' front ends (tag "g": "g_ids", "g_keys" ...),
+    // which grow -- and so free -- their buffers as the groups change size
+    uint64_t raw = 0, ucount = 0, ucap = 0;
+    uint64_t *uni = nullptr;
+    int which = 0;  // the union grows into two alternating buffers
+    std::vector<uint32_t> ids;
+    std::vector<uint64_t> soff;
+    for (uint64_t g = 0; g < G; g++) {
+        ids.clear();
+        soff.assign(1, 0);
+        uint64_t Ng = 0;
+        for (uint32_t i = 0; i < n; i++)
+            if (in_group(len[i], g, p.K)) {
+                ids.push_back(i);
+                soff.push_back(soff.back() + len[i]);
+                Ng = std::max<uint64_t>(Ng, len[i]);
+            }
+        const uint32_t k = (uint32_t)ids.size();
+        if (k < 2) continue;
+        uint32_t *d_ids = ws<uint32_t>(ctx, "grp_ids", k);
+        uint64_t *d_soff = ws<uint64_t>(ctx, "grp_soff", (uint64_t)k + 1);
+        uint8_t *d_sub = ws<uint8_t>(ctx, "grp_chars", soff.back() + 16);
+        EJ_HIP(hipMemcpyAsync(d_ids, ids.data(), 4ull * k, hipMemcpyHostToDevice, ctx->stream));
+        EJ_HIP(hipMemcpyAsync(d_soff, soff.data(), 8ull * (k + 1), hipMemcpyHostToDevice,
+                              ctx->stream));
+        hipLaunchKernelGGL(k_gather_strings, dim3(std::min<uint32_t>(k, 65535)), dim3(256), 0,
+                           ctx->stream, d_chars, d_offsets, (const uint32_t *)d_ids, k,
+                           (const uint64_t *)d_soff, d_sub);
+        EJ_CHECK_LAUNCH();
+        const uint64_t Lg = p.L ? p.L : std::max<uint64_t>(1, 3 * Ng);
+        if (Lg > 0x7FFFFFFFull) fail(EJ_EUNSUPPORTED, "group walk length too large");
+        Prep pg;
+        prepare(ctx, d_sub, d_soff, k, (uint32_t)Lg, pg, "g");
+        Rand rd;
+        draw_randomness(ctx, p, pg.L, pg.sigma, rd, "g");
+        uint64_t *keys = ws<uint64_t>(ctx, "g_keys", (uint64_t)NT * k);
+        const uint32_t kb = bucket_key_bits(ctx, k, 0);
+        uint32_t *bdk = nullptr, *bids = nullptr;
+        bucket_inputs(ctx, (uint64_t)NT * k, "g", &bdk, &bids);
+        embed_keys(ctx, pg, rd, keys, nullptr, bdk, bids, 61u - kb);
+        Buckets bk;
+        bucket(ctx, keys, pg.d_len, pg.d_perm, k, NT, kb, bk, "g", false, true, false);
+        uint64_t *gp = nullptr;
+        uint64_t graw = 0;
+        const uint64_t gc = candidates(ctx, keys, bk, pg.d_len, p.K, &gp, &graw, "g");
+        raw += graw;
+        if (!gc) continue;
+        if (ucount + gc > ucap) {
+            const uint64_t cap = std::max<uint64_t>(2 * ucap, ucount + gc);
+            uint64_t *nb = ws<uint64_t>(ctx, which ? "grp_unionA" : "grp_unionB", cap);
+            if (ucount)
+                EJ_HIP(hipMemcpyAsync(nb, uni, 8 * ucount, hipMemcpyDeviceToDevice, ctx->stream));
+            uni = nb;
+            ucap = cap;
+            which ^= 1;
+        }
+        hipLaunchKernelGGL(k_map_pairs, dim3(grid_for(ctx, gc, 256)), dim3(256), 0, ctx->stream,
+                           (const uint64_t *)gp, gc, (const uint32_t *)d_ids, uni + ucount);
+        EJ_CHECK_LAUNCH();
+        ucount += gc;
+        sync(ctx);  // the host vectors of this group are reused by the next
+    }
+    out->L = p.L;  // 0: each group walked 3 x its longest string
+    tm.mark();  // 2
+    tm.mark();  // 3: the union's de-duplication follows
+    uint64_t *pairs = nullptr;
+    uint64_t cnt = 0;
+    if (ucount) {
+        uint64_t *sorted = ws<uint64_t>(ctx, "grp_union_sorted", ucount);
+        radix_sort_u64(ctx, uni, sorted, ucount, 32 + std::max(1u, bits_for(n - 1)),
+                       ctx->tune.radix_bits);
+        cnt = unique_sorted_pairs(ctx, sorted, ucount, 32, &pairs, "grp");
+    }
+    Rand none;
+    finish_join(ctx, pp, d_offsets, p, none, 0, pairs, cnt, raw, nullptr, tm, out);
+}
+
 // ej_verify's work: preparation of the strings, their match masks and the
 // verification kernels, on the context's workspace.
 void verify_entry(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
@@ -465,6 +602,22 @@ ej_status ej_join_plus(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offs
         check_params(*p, n);
         HostInput h = upload(ctx, strings, offsets, n, "in");
         join_plus_device(ctx, h.d_chars, h.d_offsets, n, *p, delta, T, out);
+    });
+}
+
+ej_status ej_join_grouped_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
+                                 uint32_t n, const ej_params *p, ej_result *out) {
+    if (!p || !out || !d_offsets) return EJ_EINVAL;
+    return run_guarded(ctx, [&] { join_grouped_device(ctx, d_chars, d_offsets, n, *p, out); });
+}
+
+ej_status ej_join_grouped(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets,
+                          uint32_t n, const ej_params *p, ej_result *out) {
+    if (!p || !out) return EJ_EINVAL;
+    return run_guarded(ctx, [&] {
+        check_params(*p, n);
+        HostInput h = upload(ctx, strings, offsets, n, "in");
+        join_grouped_device(ctx, h.d_chars, h.d_offsets, n, *p, out);
     });
 }
 
