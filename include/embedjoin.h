@@ -400,6 +400,19 @@ typedef struct {
  * ignored (thresholds come per query); p->L = 0 picks ceil(average length). */
 ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, uint32_t n,
                          const ej_params *p, int on_device, ej_index **index);
+/* Adds n_new strings (host, or device with on_device = 1) to the index
+ * (Algorithm 3 stores each string in its tables as it is visited; here a
+ * batch at once).  They take positions ej_index_size() .. + n_new - 1 and are
+ * embedded with the index's alphabet, truncation and random streams (fixed
+ * at build: a byte outside the alphabet is EJ_EALPHABET).  The indexed
+ * strings are not embedded again: each table's sorted entries are merged
+ * with the new strings' (one binary search per entry), and the strings'
+ * codes and match masks are extended.  Later queries answer over the grown
+ * set exactly as an index built from all the strings with that alphabet,
+ * truncation and seed.  On failure (EJ_ENOMEM for the grown arrays, which
+ * are allocated beside the current ones) the index is unchanged. */
+ej_status ej_index_insert(ej_index *index, const uint8_t *strings, const uint64_t *offsets,
+                          uint32_t n_new, int on_device);
 /* Answers nq queries (host strings) with per-query thresholds Kq (host).
  * Query i is q[q_offsets[i] .. q_offsets[i+1]); q_offsets[0] need not be 0,
  * so a batch can be a window of a larger buffer.

@@ -32,7 +32,7 @@ EXPORTS = [
     "ej_result_free", "ej_autotune",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_verify_static",
     "ej_set_explicit_randomness", "ej_embed_hamming", "ej_calibrate",
-    "ej_index_build", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
+    "ej_index_build", "ej_index_insert", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
     "ej_index_size", "ej_qresult_free", "ej_index_free",
 ]
 
@@ -134,6 +134,7 @@ def lib():
                                  ctypes.POINTER(CalibResult), vp]),
         "ej_index_build": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), c_int,
                                    ctypes.POINTER(vp)]),
+        "ej_index_insert": (c_int, [vp, vp, vp, u32, c_int]),
         "ej_query_batch": (c_int, [vp, vp, vp, u32, vp, ctypes.POINTER(_QResult)]),
         "ej_query_workspace_estimate": (u64, [vp, vp, u32, vp]),
         "ej_index_set_hbm_limit": (None, [vp, u64]),
@@ -509,6 +510,23 @@ class Index:
             self.close()
         except Exception:
             pass
+
+    def insert(self, chars, offsets):
+        """ej_index_insert: adds strings (host arrays or CUDA tensors) at the
+        next positions."""
+        if _is_device(chars):
+            torch = _torch()
+            o = offsets if _is_device(offsets) else torch.from_numpy(
+                _host_u64(offsets).astype(np.int64)).cuda()
+            n = int(o.shape[0]) - 1
+            torch.cuda.current_stream().synchronize()
+            st = lib().ej_index_insert(self._h, _ptr(chars), _ptr(o), n, 1)
+        else:
+            c, o = _host_u8(chars), _host_u64(offsets)
+            n = int(o.shape[0]) - 1
+            st = lib().ej_index_insert(self._h, _ptr(c) if c.size else None, _ptr(o), n, 0)
+        self._ctx._check(st)
+        self.n += n
 
     def set_hbm_limit(self, nbytes: int):
         lib().ej_index_set_hbm_limit(self._h, int(nbytes))

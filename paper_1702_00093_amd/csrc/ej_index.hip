@@ -23,6 +23,7 @@ struct ej_index {
     ej_ctx *ctx = nullptr;
     ej_params p{};
     uint32_t n = 0, sigma = 0, L = 0, maxlen = 0, T = 0;
+    uint64_t total = 0;            // characters of the indexed strings
     uint8_t lut[256];
     uint64_t hbm_limit = 0;
     // owned device memory
@@ -125,6 +126,83 @@ __global__ void k_query_probe(const uint64_t *__restrict__ qkeys, const uint32_t
         }
         if (!EMIT) counts[e] = c;
     }
+}
+
+// Incremental insert (Algorithm 3 inserts strings one by one in length
+// order; here a batch at once).  Per table, the index's entries and the new
+// ones are each sorted by (top key bits, length, position), and every new
+// position is above every old one, so the merged order puts an old entry
+// before a new one with equal (top bits, length).  Each entry's merged
+// position is its own rank plus the number of the other list's entries that
+// go before it (binary search); old and new entries are scattered there.
+__device__ inline bool before_or_tie(uint32_t d0, uint32_t l0, uint32_t d1, uint32_t l1) {
+    return d0 < d1 || (d0 == d1 && l0 <= l1);
+}
+
+__global__ void k_merge_tables(const uint32_t *__restrict__ dkA, const uint64_t *__restrict__ keyA,
+                               const uint32_t *__restrict__ lenA, const uint32_t *__restrict__ idA,
+                               uint32_t nA, const uint32_t *__restrict__ dkB,
+                               const uint64_t *__restrict__ keyB, const uint32_t *__restrict__ lenB,
+                               const uint32_t *__restrict__ idB, uint32_t nB, uint32_t T,
+                               uint32_t *__restrict__ dk, uint64_t *__restrict__ key,
+                               uint32_t *__restrict__ len, uint32_t *__restrict__ id) {
+    const uint64_t nN = (uint64_t)nA + nB;
+    const uint64_t tot = (uint64_t)T * nN;
+    for (uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; g < tot;
+         g += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t t = (uint32_t)(g / nN);
+        const uint32_t x = (uint32_t)(g - (uint64_t)t * nN);
+        const uint64_t a0 = (uint64_t)t * nA, b0 = (uint64_t)t * nB;
+        uint32_t rank, d, l;
+        uint64_t k;
+        uint32_t i;
+        if (x < nA) {  // old entry: new entries strictly before it
+            d = dkA[a0 + x];
+            l = lenA[a0 + x];
+            uint32_t lo = 0, hi = nB;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const uint32_t dm = dkB[b0 + mid], lm = lenB[b0 + mid];
+                if (dm < d || (dm == d && lm < l)) lo = mid + 1; else hi = mid;
+            }
+            rank = x + lo;
+            k = keyA[a0 + x];
+            i = idA[a0 + x];
+        } else {  // new entry: old entries before it or tied with it
+            const uint32_t y = x - nA;
+            d = dkB[b0 + y];
+            l = lenB[b0 + y];
+            uint32_t lo = 0, hi = nA;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (before_or_tie(dkA[a0 + mid], lenA[a0 + mid], d, l)) lo = mid + 1; else hi = mid;
+            }
+            rank = y + lo;
+            k = keyB[b0 + y];
+            i = idB[b0 + y];
+        }
+        const uint64_t o = (uint64_t)t * nN + rank;
+        dk[o] = d;
+        key[o] = k;
+        len[o] = l;
+        id[o] = i;
+    }
+}
+
+// New entries' positions after the index's n0 strings.
+__global__ void k_add_u32(uint32_t *__restrict__ a, uint64_t cnt, uint32_t add) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        a[e] += add;
+}
+
+// Offsets of the inserted strings, relative to the new strings' first
+// character, placed after the index's characters.
+__global__ void k_append_offsets(const uint64_t *__restrict__ off, uint32_t n, uint64_t base,
+                                 uint64_t shift, uint64_t *__restrict__ out) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e <= n;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        out[e] = off[e] - base + shift;
 }
 
 __global__ void k_uniq_flags(const uint64_t *__restrict__ codes, uint64_t cnt,
@@ -244,6 +322,7 @@ ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *of
         ix->sigma = pp.sigma;
         ix->L = pp.L;
         ix->maxlen = pp.maxlen;
+        ix->total = pp.total;
         memcpy(ix->lut, pp.lut, 256);
         Rand rd;
         draw_randomness(ctx, *p, pp.L, pp.sigma, rd, "ix");
@@ -299,6 +378,123 @@ ej_status ej_index_build(ej_ctx *ctx, const uint8_t *strings, const uint64_t *of
     }
     *out = ix;
     return EJ_OK;
+}
+
+ej_status ej_index_insert(ej_index *ix, const uint8_t *strings, const uint64_t *offsets,
+                          uint32_t n_new, int on_device) {
+    if (!ix || !offsets) return EJ_EINVAL;
+    ej_ctx *ctx = ix->ctx;
+    std::vector<void *> fresh;  // allocations of this call, released on failure
+    ej_status st = run_guarded(ctx, [&] {
+        if (n_new == 0) return;
+        if ((uint64_t)ix->n + n_new >= 0x80000000ull) fail(EJ_EINVAL, "n must stay below 2^31");
+        const uint64_t nN = (uint64_t)ix->n + n_new;
+        if (nN * ix->T >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
+        const uint8_t *d_chars = strings;
+        const uint64_t *d_off = offsets;
+        if (!on_device) {
+            std::vector<uint64_t> reb(offsets, offsets + n_new + 1);
+            for (uint32_t i = 0; i < n_new; i++)
+                if (offsets[i + 1] < offsets[i]) fail(EJ_EINVAL, "offsets are not non-decreasing");
+            const uint64_t base = offsets[0], total = offsets[n_new] - base;
+            if (total && !strings) fail(EJ_EINVAL, "null strings");
+            for (auto &o : reb) o -= base;
+            uint8_t *dc = ws<uint8_t>(ctx, "ii_hchars", total + 16);
+            uint64_t *dofs = ws<uint64_t>(ctx, "ii_hoff", (uint64_t)n_new + 1);
+            if (total)
+                EJ_HIP(hipMemcpyAsync(dc, strings + base, total, hipMemcpyHostToDevice,
+                                      ctx->stream));
+            EJ_HIP(hipMemcpyAsync(dofs, reb.data(), 8ull * (n_new + 1), hipMemcpyHostToDevice,
+                                  ctx->stream));
+            sync(ctx);
+            d_chars = dc;
+            d_off = dofs;
+        }
+        // the new strings under the index's alphabet, truncation and streams
+        Prep pq;
+        prepare(ctx, d_chars, d_off, n_new, 0, pq, "ii", ix->lut, ix->sigma, ix->L);
+        const uint32_t T = ix->T;
+        const uint64_t totB = (uint64_t)T * n_new;
+        uint64_t *keys = ws<uint64_t>(ctx, "ii_keys", totB);
+        embed_keys(ctx, pq, ix->rd, keys, nullptr);
+        Buckets bk;
+        bucket(ctx, keys, pq.d_len, pq.d_perm, n_new, T, 32, bk, "ii");
+        uint32_t *dkB = ws<uint32_t>(ctx, "ii_dkB", totB);
+        uint64_t *keyB = ws<uint64_t>(ctx, "ii_keyB", totB);
+        uint32_t *lenB = ws<uint32_t>(ctx, "ii_lenB", totB);
+        hipLaunchKernelGGL(k_sorted_attrs_full, dim3(grid_for(ctx, totB, 256)), dim3(256), 0,
+                           ctx->stream, (const uint64_t *)keys, (const uint32_t *)bk.d_ids,
+                           (const uint32_t *)pq.d_len, n_new, totB, dkB, keyB, lenB);
+        EJ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_add_u32, dim3(grid_for(ctx, totB, 256)), dim3(256), 0, ctx->stream,
+                           bk.d_ids, totB, ix->n);
+        EJ_CHECK_LAUNCH();
+        // the grown index, built beside the current one (which stays whole
+        // until every allocation has succeeded)
+        auto alloc = [&](size_t bytes) -> void * {
+            void *p = nullptr;
+            if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+                (void)hipGetLastError();
+                fail(EJ_ENOMEM, "index insert: device allocation failed");
+            }
+            fresh.push_back(p);
+            return p;
+        };
+        const uint64_t totN = (uint64_t)T * nN;
+        const uint64_t charsN = ix->total + pq.total;
+        uint32_t *dk = (uint32_t *)alloc(4 * totN);
+        uint64_t *key = (uint64_t *)alloc(8 * totN);
+        uint32_t *len = (uint32_t *)alloc(4 * totN);
+        uint32_t *id = (uint32_t *)alloc(4 * totN);
+        uint8_t *codes = (uint8_t *)alloc(charsN + 64);
+        uint64_t *offs = (uint64_t *)alloc(8 * (nN + 1));
+        uint32_t *mw = (uint32_t *)alloc(4 * mask_words_bound(charsN, (uint32_t)nN, ix->sigma));
+        uint64_t *mo = (uint64_t *)alloc(8 * (nN + 1));
+        hipLaunchKernelGGL(k_merge_tables, dim3(grid_for(ctx, totN, 256)), dim3(256), 0,
+                           ctx->stream, (const uint32_t *)ix->d_dk, (const uint64_t *)ix->d_key_s,
+                           (const uint32_t *)ix->d_len_s, (const uint32_t *)ix->d_ids, ix->n,
+                           (const uint32_t *)dkB, (const uint64_t *)keyB, (const uint32_t *)lenB,
+                           (const uint32_t *)bk.d_ids, n_new, T, dk, key, len, id);
+        EJ_CHECK_LAUNCH();
+        // codes and offsets: the new strings after the indexed ones (the new
+        // codes carry their zero padding along)
+        if (ix->total)
+            EJ_HIP(hipMemcpyAsync(codes, ix->d_codes, ix->total, hipMemcpyDeviceToDevice,
+                                  ctx->stream));
+        EJ_HIP(hipMemcpyAsync(codes + ix->total, pq.d_codes, pq.total + 64,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+        EJ_HIP(hipMemcpyAsync(offs, ix->d_offsets, 8ull * ix->n, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+        hipLaunchKernelGGL(k_append_offsets, dim3(grid_for(ctx, (uint64_t)n_new + 1, 256)),
+                           dim3(256), 0, ctx->stream, d_off, n_new, pq.base, ix->total,
+                           offs + ix->n);
+        EJ_CHECK_LAUNCH();
+        RowMasks masks;
+        build_masks(ctx, codes, offs, 0, (uint32_t)nN, charsN, ix->sigma, masks, "ixm", mw, mo);
+        sync(ctx);
+        // swap in the grown arrays; release the replaced ones
+        void *old[] = {ix->d_dk, ix->d_key_s, ix->d_len_s, ix->d_ids, ix->d_codes, ix->d_offsets,
+                       (void *)ix->masks.words, (void *)ix->masks.off};
+        for (void *p : old) {
+            auto it = std::find(ix->owned.begin(), ix->owned.end(), p);
+            if (it != ix->owned.end()) ix->owned.erase(it);
+            (void)hipFree(p);
+        }
+        ix->owned.insert(ix->owned.end(), fresh.begin(), fresh.end());
+        fresh.clear();
+        ix->d_dk = dk;
+        ix->d_key_s = key;
+        ix->d_len_s = len;
+        ix->d_ids = id;
+        ix->d_codes = codes;
+        ix->d_offsets = offs;
+        ix->masks = masks;
+        ix->n = (uint32_t)nN;
+        ix->total = charsN;
+        ix->maxlen = std::max(ix->maxlen, pq.maxlen);
+    });
+    for (void *p : fresh) (void)hipFree(p);
+    return st;
 }
 
 uint64_t ej_query_workspace_estimate(const ej_index *ix, const uint64_t *q_offsets, uint32_t nq,

@@ -192,3 +192,51 @@ def test_admission_counts_candidates_and_verification(ej, ctx, oracle_lib):
     finally:
         ctx.tune_set("verify_mode", old)
         ix.close()
+
+
+def test_index_insert_equals_an_index_of_all_strings(ej, ctx, oracle_lib):
+    """Strings added to a built index (host and device batches) are found by
+    later queries exactly as in an index built from all the strings with the
+    same alphabet, truncation and seed: result lists equal the oracle's
+    serving definition over the concatenated set; a batch with a byte outside
+    the alphabet is refused and leaves the index as it was."""
+    import torch
+    A = sd.clusters(41, 25, lambda rr, b: 3, lambda rr: rr.integers(80, 400),
+                    lambda rr, L: rr.poisson(4))
+    B = sd.clusters(42, 15, lambda rr, b: 4, lambda rr: rr.integers(50, 600),
+                    lambda rr, L: rr.poisson(5))
+    C = sd.clusters(43, 10, lambda rr, b: 2, lambda rr: rr.integers(100, 300),
+                    lambda rr, L: rr.poisson(3))
+    r, z, m, L, seed = 3, 4, 5, 48, 5
+    ix = ej.Index(ctx, A.chars, A.offsets, r, z, m, seed=seed, L=L)
+    ix.insert(B.chars, B.offsets)
+    assert ix.size() == A.n + B.n
+    AB = sd.from_strings(A.strings() + B.strings())
+    q, Kq = _queries(AB, 21, 60, (50, 600))
+    _say("queries after one insert")
+    _check(ix.query(q.chars, q.offsets, Kq),
+           *oracle_lib.query(AB.chars, AB.offsets, q.chars, q.offsets, Kq, r, z, m,
+                             seed=seed, L=L))
+    chars, offs = to_device(C)
+    ix.insert(chars, offs)
+    ix.insert(b"", np.zeros(1, dtype=np.uint64))  # an empty batch changes nothing
+    ABC = sd.from_strings(AB.strings() + C.strings())
+    assert ix.size() == ABC.n
+    q2, K2 = _queries(ABC, 22, 60, (50, 600))
+    ref = oracle_lib.query(ABC.chars, ABC.offsets, q2.chars, q2.offsets, K2, r, z, m, seed=seed,
+                           L=L)
+    _say("queries after a device insert")
+    got = ix.query(q2.chars, q2.offsets, K2)
+    _check(got, *ref)
+    assert got.ids.size > 0 and (got.ids >= AB.n).any()   # the new strings are found
+    whole = ej.Index(ctx, ABC.chars, ABC.offsets, r, z, m, seed=seed, L=L)
+    w = whole.query(q2.chars, q2.offsets, K2)
+    assert w.ids.tolist() == got.ids.tolist() and w.n_candidates == got.n_candidates
+    whole.close()
+    bad = sd.from_strings([b"ACGTN"])
+    with pytest.raises(ej.EmbedJoinError) as e:
+        ix.insert(bad.chars, bad.offsets)
+    assert e.value.status == ej.EJ_EALPHABET
+    assert ix.size() == ABC.n
+    _check(ix.query(q2.chars, q2.offsets, K2), *ref)
+    ix.close()
