@@ -2,16 +2,24 @@
 
 A step is one complete self-join (A0-A6: preparation, CGK walk + keys,
 bucketing, candidate pairs, verification, output) of a device-resident
-synthetic string collection.  Prints one JSON line.
+synthetic string collection.  Prints one JSON line: the headline workload
+(20,000 DNA strings, K=500, at its recall-calibrated point) in the batched
+form, beside the plain per-stage form, and the other workloads as keys of
+their own (tiny, uneven, protein, plus, serving) plus the oracle's CPU
+baseline.
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload medium|tiny]
-                  [--K ..] [--r ..] [--z ..] [--m ..] [--L ..] [--stated]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--legs tiny,uneven,...]
 """
 import argparse
 import json
+import multiprocessing
 import os
+import platform
+import shutil
 import sys
+import tempfile
 import time
+from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
 
 import numpy as np
 
@@ -20,25 +28,44 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("end-to-end join sec & verified candidate pairs/s at recall≥0.99; "
           "query p99 ms")
-MI355X_INT32_LANE_OPS = 256 * 4 * 16 * 2.4e9    # CUs x SIMDs x lanes x clock
-MI355X_HBM = 8.0e12
+# vendor-derived integer VALU peak: CUs x SIMDs x lanes x clock (a wave64
+# instruction holds a 16-lane SIMD for 4 cycles)
+MI355X_INT32_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
-# Work the method itself must do, in 32-bit integer lane operations:
-#  - verification: Myers' bit-parallel step over one 32-cell word of the band
-#    is 10 gfx950 instructions (the match word, Xv, Eq&Pv, the add, Xh/Ph/Mh
-#    in three 3-input logic operations, the one-bit shift, Pv and Mv), i.e.
-#    10/32 operations per DP cell; with 2-input logic alone it would be 15.
-#    The band a threshold-K verification needs is K+1 diagonals wide (a path
-#    through diagonal d costs at least |d| + |d - d*|);
-#  - walk: 3 operations per CGK step (read the symbol, select its pi bit,
-#    advance the pointer).
+# Work units of verification, in 32-bit integer lane operations per 32-cell
+# word of the K+1 band (diagonals a threshold-K distance needs):
+#  - the recurrence unit: Myers' step is 10 gfx950 instructions (the match
+#    word, Xv, Eq&Pv, the add, Xh/Ph/Mh as 3-input logic, the one-bit shift,
+#    Pv, Mv) -- the method's own work;
+#  - the unit of the work estimate the build started from: about 20 per word,
+#    which also counts the cross-word carry and band shift of a band split
+#    over lanes.
 OPS_PER_WORD_STEP = 10
-# the verification kernel of each form (JoinResult.verify_form)
+SURVEY_OPS_PER_WORD = 20
+OPS_PER_WALK_STEP = 3    # walk: read the symbol, select its pi bit, advance
 VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane", 3: "k_verify_split"}
 VERIFY_FORM = {0: "two-pass", 1: "persistent, replayed from a captured HIP graph",
                2: "one pair per lane, persistent, replayed from a captured HIP graph",
                3: "several band words per lane, persistent, replayed from a captured HIP graph"}
-OPS_PER_WALK_STEP = 3
+LEGS = ("tiny", "uneven", "protein", "plus", "serving")
+
+# Recall-calibrated parameter points, found by sweeps of (r, z, m, L) on these
+# workloads (recall against the planted pairs >= 0.99 at the least join time):
+# at the stated parameters the uniformly spread indels of the synthetic copies
+# keep the CGK walks out of step and few true pairs become candidates.
+CALIBRATED = {
+    "medium": dict(r=32, z=16, m=18, L=64),
+    "tiny": dict(r=7, z=16, m=8, L=64),
+    "uneven": dict(r=32, z=16, m=18, L=64),
+}
+# EmbedJoin+ on reads with shifts (K=100, delta=50 -> two suffixes, T=2), at
+# the point ej_calibrate chose for a predicted recall of 0.995 (L = 0: the
+# average length, as the paper truncates genome reads)
+PLUS = dict(K=100, delta=50, T=2, r=6, z=16, m=8, L=0)
+# Serving parameters, recall-calibrated by a sweep on this query mix
+# (re-mutated members at 5% edits plus fresh random strings): with the stated
+# r=3, z=7 no (m, L) reaches recall 0.99 against the source member (0.81-0.93)
+SERVING = dict(r=32, z=8, m=20, L=64)
 
 
 def parse():
@@ -54,30 +81,80 @@ def parse():
     ap.add_argument("--L", type=int, default=None)
     ap.add_argument("--stated", action="store_true",
                     help="use the workload's stated (r, z, m, L) instead of the recall-calibrated point")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help="workloads run besides the headline one (comma list of "
+                         f"{', '.join(LEGS)}; empty for none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched form with default knobs instead of the autotuner's")
     ap.add_argument("--knobs", default="", metavar="name=value,..",
                     help="batched form with these launch knobs instead of the autotuner's")
-    ap.add_argument("--no-uneven", action="store_true",
-                    help="skip the uneven-length join (80,000 strings, K=400)")
-    ap.add_argument("--with-protein", action="store_true",
-                    help="also run the protein-like join (400,000 strings, K=100; ~1 min of "
-                         "data generation)")
-    ap.add_argument("--no-serving", action="store_true",
-                    help="skip the serving leg (index of 320,000 strings, 10,000 queries)")
-    ap.add_argument("--serving-only", action="store_true",
-                    help="run only the serving leg")
+    ap.add_argument("--serving-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--serving-params", default="", metavar="r,z,m,L",
                     help="override the serving index parameters")
-    ap.add_argument("--serving-sweep", default="", metavar="r,z,m,L;r,z,m,L;..",
-                    help="with --serving-only: one serving run per parameter point, same data")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times): "
                          "the reference for scaling HBM traffic counters")
+    ap.add_argument("--valu-probe", action="store_true",
+                    help="only run the integer-VALU issue-rate probe (for its counter profile)")
     return ap.parse_args()
 
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------ data generation --
+# The larger collections are generated in worker processes (spawned: they
+# never touch the GPU) while the GPU runs the earlier legs, and handed over as
+# .npz files in a private temporary directory.
+
+def _gen_worker(name, path):
+    import synthdata as sd
+    if name == "uneven":
+        col, _ = sd.uneven_dna(0)
+    elif name == "protein":
+        col, _ = sd.protein_like(0)
+    elif name == "shifted":
+        col, _ = sd.shifted_reads(0)
+    elif name == "serving":
+        col, _ = sd.serving_index(0)
+        q, Kq, src = sd.serving_queries(col, 0)
+        np.savez(path, chars=col.chars, offsets=col.offsets, labels=col.labels, qchars=q.chars,
+                 qoffsets=q.offsets, qlabels=q.labels, Kq=Kq, src=src)
+        return path
+    else:
+        raise ValueError(name)
+    np.savez(path, chars=col.chars, offsets=col.offsets, labels=col.labels)
+    return path
+
+
+class DataPool:
+    def __init__(self, names):
+        self.dir = tempfile.mkdtemp(prefix="ej_bench_")
+        self.ex = ProcessPoolExecutor(max_workers=max(1, len(names)),
+                                      mp_context=multiprocessing.get_context("spawn"))
+        self.fut = {n: self.ex.submit(_gen_worker, n, os.path.join(self.dir, n + ".npz"))
+                    for n in names}
+
+    def get(self, name):
+        import synthdata as sd
+        t0 = time.perf_counter()
+        path = self.fut[name].result()
+        z = np.load(path)
+        d = {k: z[k] for k in z.files}
+        os.remove(path)
+        col = sd.Collection(d["chars"], d["offsets"], d["labels"], name)
+        _log(f"data {name} ready (waited {time.perf_counter() - t0:.1f} s)")
+        return col, d
+
+    def close(self):
+        self.ex.shutdown(cancel_futures=True)
+        shutil.rmtree(self.dir, ignore_errors=True)
+
+
+# ---------------------------------------------------------------- probes --
 
 def copy_probe(nbytes):
     import torch
@@ -91,15 +168,17 @@ def copy_probe(nbytes):
                       "writes_per_copy": nbytes, "copies": 5}), flush=True)
 
 
-# Recall-calibrated parameter points, found by a sweep of (r, z, m, L) on these
-# workloads (recall against the planted pairs >= 0.99 at the least join time):
-# at the stated parameters the uniformly spread indels of the synthetic copies
-# keep the CGK walks out of step and no true pair becomes a candidate.
-CALIBRATED = {
-    "medium": dict(r=32, z=16, m=18, L=64),
-    "tiny": dict(r=7, z=16, m=8, L=64),
-    "uneven": dict(r=32, z=16, m=18, L=64),
-}
+def valu_peak(ctx):
+    """The integer-VALU issue rate the probe kernel reaches: the best of a
+    few occupancies (workgroups of 256 lanes per CU)."""
+    best = (0.0, 0, 0.0)
+    runs = []
+    for bpc in (8, 16, 32):
+        ops, ms = ctx.probe_valu(4096, bpc)
+        runs.append(dict(blocks_per_cu=bpc, tops=round(ops / 1e12, 3), ms=round(ms, 4)))
+        if ops > best[0]:
+            best = (ops, bpc, ms)
+    return best[0], runs
 
 
 def measured_traffic(kernel, workload_tag):
@@ -120,37 +199,26 @@ def measured_traffic(kernel, workload_tag):
     return rec["hbm_bytes_per_launch"]
 
 
-def workload(args):
-    import synthdata as sd
-    if args.workload == "medium":
-        col, prm = sd.medium_dna(0, K=args.K or 500)
-        name = "medium DNA: 20,000 strings (2,000 bases U{4500..5500} x 10 copies, Poisson(0.04 len) edits)"
-    elif args.workload == "uneven":
-        col, prm = sd.uneven_dna(0)
-        name = ("uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, clusters "
-                "geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)")
-    else:
-        col, prm = sd.tiny_dna(0)
-        name = "tiny DNA: 2,000 strings (200 bases U{900..1100} x 10 copies, Poisson(30) edits)"
-    stated = dict(K=prm["K"], r=prm["r"], z=prm["z"], m=prm["m"], L=0)
-    run = dict(stated) if args.stated else dict(stated, **CALIBRATED[args.workload])
-    for k in ("K", "r", "z", "m", "L"):
-        if getattr(args, k) is not None:
-            run[k] = getattr(args, k)
-    return col, name, stated, run
+# ----------------------------------------------------------- the joins --
+
+def device(col):
+    import torch
+    chars = torch.from_numpy(col.chars).cuda()
+    offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
+    return chars, offs
 
 
-def time_join(ctx, chars, offs, prm, steps, warmup, flags):
+def time_join(fn, steps, warmup):
+    """Wall time of `steps` joins after `warmup` (fn returns a JoinResult
+    with stage times), between torch.cuda.synchronize() calls."""
     import torch
     for _ in range(warmup):
-        res = ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0, L=prm["L"],
-                       flags=flags)
+        res = fn()
     torch.cuda.synchronize()
     stage = {}
     t0 = time.perf_counter()
     for _ in range(steps):
-        res = ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0, L=prm["L"],
-                       flags=flags)
+        res = fn()
         for k, v in res.ms.items():
             stage[k] = stage.get(k, 0.0) + v / steps
         stage["verify_kernel"] = stage.get("verify_kernel", 0.0) + res.ms_verify_kernel / steps
@@ -159,96 +227,422 @@ def time_join(ctx, chars, offs, prm, steps, warmup, flags):
     return res, (t1 - t0) * 1000.0 / max(steps, 1), stage
 
 
-def recall_estimate(col, res, K, oracle, n_sample=200, seed=1):
-    """Recall against the planted pairs: the fraction of planted pairs within
-    K is estimated with the oracle on a sample; every reported pair is exact."""
+def run_forms(ej, ctx, chars, offs, prm, args, steps=None, warmup=None, tune_reps=2):
+    """The plain per-stage form (default knobs, two-pass verification) and the
+    batched form (persistent verification replayed from a captured HIP graph,
+    knobs from the autotuner), timed on the same device-resident input."""
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
+    flags = ej.FLAG_TIMING
+    defaults = ctx.knobs()
+    ctx.tune_set("verify_mode", 0)
+
+    def join(fl):
+        return lambda: ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
+                                L=prm["L"], flags=fl)
+
+    res, ms, stage = time_join(join(flags), steps, warmup)
+    plain = dict(res=res, ms=ms, stage=stage, knobs=ctx.knobs(), kernel="k_verify")
+    if args.knobs:
+        for kv in args.knobs.split(","):
+            k, v = kv.split("=")
+            ctx.tune_set(k.strip(), int(v))
+        tune_ms = None
+    elif args.no_autotune:
+        ctx.tune_set("verify_mode", 2)
+        tune_ms = None
+    else:
+        tune_ms, _ = ctx.autotune(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
+                                  L=prm["L"], reps=tune_reps)
+    knobs = ctx.knobs()
+    gflags = flags | (ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0)
+    res, ms, stage = time_join(join(gflags), steps, warmup)
+    batched = dict(res=res, ms=ms, stage=stage, knobs=knobs, autotune_best_ms=tune_ms,
+                   kernel=VERIFY_KERNEL[res.verify_form])
+    for k, v in defaults.items():
+        ctx.tune_set(k, v)
+    return dict(plain=plain, batched=batched)
+
+
+def roofline(res, stage, prm, kern, peak_measured=None):
+    """Algorithmic integer operations per step of the dominant kernel over its
+    own device time per step (events around each launch), in two units, each
+    against the vendor-derived and the probe-measured peak."""
+    if stage.get("verify", 0.0) >= stage.get("embed", 0.0) and res.verify_columns:
+        words = res.verify_columns * (prm["K"] + 1) / 32.0
+        ops = words * OPS_PER_WORD_STEP
+        ops_s = words * SURVEY_OPS_PER_WORD
+        t = stage["verify_kernel"] / 1000.0
+        nl = max(1, res.verify_launches)
+        cells = res.verify_columns * (prm["K"] + 1)
+        work = dict(launches_per_step=res.verify_launches,
+                    avg_launch_ms=round(stage["verify_kernel"] / nl, 4),
+                    band_cells=int(cells), text_columns=int(res.verify_columns),
+                    gcells_per_s=round(cells / t / 1e9, 2) if t > 0 else None,
+                    ukkonen_2k1_gcells_per_s=round(res.verify_columns * (2 * prm["K"] + 1)
+                                                   / t / 1e9, 2) if t > 0 else None)
+    else:
+        kern = "k_embed"
+        ops = res.walk_steps * OPS_PER_WALK_STEP
+        ops_s = None
+        t = stage["embed"] / 1000.0
+        work = dict(walk_steps=int(res.walk_steps),
+                    gsteps_per_s=round(res.walk_steps / t / 1e9, 2) if t > 0 else None)
+    achieved = ops / t / 1e12 if t > 0 else 0.0
+    peak = MI355X_INT32_LANE_OPS / 1e12
+    out = dict(bound="alu", kernel=kern, achieved=round(achieved, 4), peak=round(peak, 2),
+               unit="T int32 lane-op/s", frac=round(achieved / peak, 5), traffic=None,
+               traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-scaled)",
+               work_unit=("10 ops per 32-cell word of the K+1 band (Myers' recurrence)"
+                          if ops_s is not None else "3 ops per CGK walk step"),
+               kernel_ms=round(t * 1000.0, 4), **work)
+    if peak_measured:
+        pm = peak_measured / 1e12
+        out["peak_measured"] = round(pm, 3)
+        out["frac_vs_measured"] = round(achieved / pm, 5)
+    if ops_s is not None and t > 0:
+        a2 = ops_s / t / 1e12
+        out["achieved_survey_unit"] = round(a2, 4)
+        out["survey_unit"] = "20 ops per 32-cell word (recurrence + cross-lane carry + shift)"
+        out["frac_survey_unit"] = round(a2 / peak, 5)
+        if peak_measured:
+            out["frac_survey_unit_vs_measured"] = round(a2 / (peak_measured / 1e12), 5)
+    return out
+
+
+def form_summary(f, prm, peak_measured=None):
+    res, ms, stage = f["res"], f["ms"], f["stage"]
+    roof = roofline(res, stage, prm, f["kernel"], peak_measured)
+    return dict(join_sec=round(ms / 1000.0, 5),
+                verified_pairs_per_s=round(res.n_candidates / (ms / 1000.0), 3),
+                stage_ms={k: round(v, 3) for k, v in stage.items()},
+                kernel=roof["kernel"], kernel_ms=roof["kernel_ms"], roofline_frac=roof["frac"],
+                roofline_frac_vs_measured=roof.get("frac_vs_measured"), knobs=f["knobs"])
+
+
+# ------------------------------------------------------------ recall --
+
+def _codes(pairs):
+    p = np.asarray(pairs, dtype=np.uint64).reshape(-1, 2)
+    return (p[:, 0] << np.uint64(32)) | p[:, 1]
+
+
+def gpu_within(ctx, chars, offs, codes, K, chunk=1 << 23):
+    """Which pairs are within K: the library's verification (bit-exact with
+    the oracle in the parity tests), in chunks."""
+    import torch
+    out = np.zeros(len(codes), dtype=bool)
+    for i in range(0, len(codes), chunk):
+        c = torch.from_numpy(np.ascontiguousarray(codes[i:i + chunk]).astype(np.int64)).cuda()
+        out[i:i + chunk] = ctx.verify(chars, offs, c, K).cpu().numpy() <= K
+    return out
+
+
+def exact_recall(ctx, chars, offs, col, K, res, oracle, extra_true=None, check=300, seed=1):
+    """Recall against the planted pairs within K, all of them verified (the
+    denominator is exact), optionally united with further true pairs; a
+    sample of the GPU's decisions is checked against the oracle."""
     import synthdata as sd
-    planted = sd.planted_pairs(col)
-    if len(planted) == 0:
-        return None
+    planted = _codes(sd.planted_pairs(col))
+    w = gpu_within(ctx, chars, offs, planted, K)
     rng = np.random.default_rng(seed)
-    idx = rng.choice(len(planted), size=min(n_sample, len(planted)), replace=False)
-    codes = (planted[idx, 0].astype(np.uint64) << np.uint64(32)) | planted[idx, 1].astype(np.uint64)
-    d = oracle.verify_pairs(col.chars, col.offsets, codes, K)
-    frac_true = float((d <= K).mean())
-    lab = col.labels
-    out = res.pairs
-    found_planted = int(((lab[out[:, 0]] == lab[out[:, 1]]) & (lab[out[:, 0]] >= 0)).sum())
-    denom = frac_true * len(planted)
-    return dict(planted_pairs=int(len(planted)), planted_within_K_frac=round(frac_true, 4),
-                planted_within_K_sample=int(len(idx)), found_planted=found_planted,
-                recall_vs_planted=(round(found_planted / denom, 4) if denom > 0 else None),
-                output_pairs=int(len(out)))
+    pick = rng.choice(len(planted), size=min(check, len(planted)), replace=False)
+    o = oracle.verify_pairs(col.chars, col.offsets, planted[pick], K) <= K
+    assert np.array_equal(o, w[pick]), "GPU and oracle disagree on planted pairs"
+    truth = planted[w]
+    if extra_true is not None and len(extra_true):
+        truth = np.union1d(truth, extra_true)
+    out = res.codes
+    found = int(np.isin(truth, out).sum()) if len(truth) else 0
+    return dict(planted_pairs=int(len(planted)), planted_within_K=int(w.sum()),
+                true_pairs=int(len(truth)), found=found,
+                recall=round(found / len(truth), 5) if len(truth) else None,
+                output_pairs=int(len(out)), oracle_checked_pairs=int(len(pick)))
 
 
-def cpu_baseline(col, prm, oracle, budget_s=12.0):
-    """The oracle (single thread) on growing prefixes of the workload until
-    it runs for about budget_s; rate = candidate pairs verified per second."""
+def short_string_truth(ctx, chars, offs, col, K, max_len):
+    """Pairs among the strings no longer than max_len that are within K (all
+    pairs with lengths within K, verified on the GPU): the accidental true
+    pairs that random strings of such lengths form."""
+    lens = col.lengths()
+    ids = np.nonzero(lens <= max_len)[0]
+    ids = ids[np.argsort(lens[ids], kind="stable")]
+    L = lens[ids]
+    parts = []
+    for i in range(len(ids)):
+        j1 = np.searchsorted(L, L[i] + K, side="right")
+        if j1 <= i + 1:
+            continue
+        a = np.full(j1 - i - 1, ids[i], dtype=np.uint64)
+        b = ids[i + 1:j1].astype(np.uint64)
+        lo, hi = np.minimum(a, b), np.maximum(a, b)
+        parts.append((lo << np.uint64(32)) | hi)
+    if not parts:
+        return np.zeros(0, dtype=np.uint64), 0
+    cand = np.concatenate(parts)
+    w = gpu_within(ctx, chars, offs, cand, K)
+    return np.sort(cand[w]), int(len(cand))
+
+
+def brute_truth(col, K, oracle, threads=16):
+    """The exact join by brute force with the oracle: every pair within K in
+    length, its threshold distance (Ukkonen), over host threads."""
+    lens = col.lengths()
+    order = np.argsort(lens, kind="stable")
+    L = lens[order]
+    parts = []
+    for i in range(col.n):
+        j1 = np.searchsorted(L, L[i] + K, side="right")
+        if j1 > i + 1:
+            a = np.full(j1 - i - 1, order[i], dtype=np.uint64)
+            b = order[i + 1:j1].astype(np.uint64)
+            parts.append((np.minimum(a, b) << np.uint64(32)) | np.maximum(a, b))
+    cand = np.concatenate(parts) if parts else np.zeros(0, np.uint64)
+    chunks = np.array_split(cand, threads * 8)
+    with ThreadPoolExecutor(threads) as ex:
+        d = np.concatenate(list(ex.map(lambda c: oracle.verify_pairs(col.chars, col.offsets, c,
+                                                                     K), chunks)))
+    return np.sort(cand[d <= K]), int(len(cand))
+
+
+def sample_pairs(col, n_planted, n_random, seed=1):
     import synthdata as sd
-    n = 250
-    last = None
-    while True:
-        sub = sd.from_strings(col.strings()[:n])
+    rng = np.random.default_rng(seed)
+    planted = sd.planted_pairs(col)
+    pick = planted[rng.choice(len(planted), size=min(n_planted, len(planted)), replace=False)]
+    rand = rng.integers(0, col.n, size=(n_random, 2))
+    rand = np.sort(rand[rand[:, 0] != rand[:, 1]], axis=1)
+    return _codes(np.concatenate([pick, rand]))
+
+
+def calibration_block(ej, ctx, chars, offs, col, K, oracle, target=0.99, r_max=32,
+                      zl=(4, 8, 16), ml=(8, 12, 16, 18, 20, 24), Ll=(64, 128, 0), delta=0, T=0):
+    """ej_calibrate on a sample of planted and random pairs, then one join at
+    the chosen point and its measured recall."""
+    import torch
+    codes = sample_pairs(col, 1000, 2000)
+    dp = torch.from_numpy(codes.astype(np.int64)).cuda()
+    t0 = time.perf_counter()
+    cal = ctx.calibrate(chars, offs, dp, K, r_max, list(zl), list(ml), list(Ll),
+                        target_recall=target, seed=0, delta=delta, T=T)
+    cal_s = time.perf_counter() - t0
+    out = dict(target_recall=target, grid=dict(r_max=r_max, z=list(zl), m=list(ml),
+                                               L=list(Ll)),
+               seconds=round(cal_s, 3), n_similar=cal["n_similar"],
+               n_dissimilar=cal["n_dissimilar"], best_predicted_recall=round(cal["best_recall"], 5))
+    if cal["r"]:
+        prm = dict(r=cal["r"], z=cal["z"], m=cal["m"], L=cal["L"])
         t0 = time.perf_counter()
-        r = oracle.join(sub.chars, sub.offsets, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
-                        L=prm["L"])
-        dt = time.perf_counter() - t0
-        last = (n, dt, len(r.cand), len(r.out))
-        if dt >= budget_s or n >= col.n:
-            break
-        n = min(col.n, int(n * max(1.5, min(4.0, (budget_s / max(dt, 1e-3)) ** 0.5))))
-    n, dt, nc, no = last
-    return dict(value=round(nc / dt, 3), unit="verified candidate pairs/s", cores=1,
-                kind="oracle", seconds=round(dt, 2), joins_per_s=round(1.0 / dt, 4),
-                sample=f"oracle join of the first {n} of {col.n} strings "
-                       f"({nc} candidates, {no} output pairs), same parameters")
+        if delta:
+            res = ctx.join_plus(chars, offs, K, prm["r"], prm["z"], prm["m"], delta=delta, T=T,
+                                seed=0, L=prm["L"])
+        else:
+            res = ctx.join(chars, offs, K, prm["r"], prm["z"], prm["m"], seed=0, L=prm["L"])
+        torch.cuda.synchronize()
+        out.update(chosen=prm, predicted_recall=round(cal["recall"], 5),
+                   predicted_false_rate=round(cal["false_rate"], 6),
+                   join_ms=round((time.perf_counter() - t0) * 1e3, 3),
+                   measured=exact_recall(ctx, chars, offs, col, K, res, oracle, check=100))
+    return out
 
 
-# Serving parameters, recall-calibrated by a sweep on this query mix
-# (re-mutated members at 5% edits plus fresh random strings): with the
-# stated r=3, z=7 no (m, L) reaches recall 0.99 against the source member
-# (0.81-0.93), because an edit near the start of a string desynchronises the
-# walks of all seeds at once; 32 seeds x 8 functions with m=20, L=64 reach
-# 0.993 at 26 candidates per query.
-SERVING = dict(r=32, z=8, m=20, L=64)
+# ------------------------------------------------------------ the legs --
+
+def leg_forms(ej, ctx, oracle, args, col, desc, prm, stated, peak, steps=None, warmup=None,
+              tune_reps=2, extra_true=None):
+    chars, offs = device(col)
+    forms = run_forms(ej, ctx, chars, offs, prm, args, steps, warmup, tune_reps)
+    b = forms["batched"]
+    out = dict(workload=desc, params=prm, stated=stated,
+               candidates=b["res"].n_candidates, raw_candidates=b["res"].n_raw,
+               output_pairs=int(len(b["res"].pairs)),
+               batched=form_summary(b, prm, peak), plain=form_summary(forms["plain"], prm, peak))
+    return out, chars, offs, b["res"]
 
 
-_SERVING_DATA = {}
+def tiny_leg(ej, ctx, oracle, args, peak):
+    """2,000 DNA strings (200 bases x 10 copies, Poisson(30) edits), K=50, at
+    its calibrated point; recall against the exact join by brute force."""
+    import synthdata as sd
+    col, stated = sd.tiny_dna(0)
+    prm = dict(K=stated["K"], **CALIBRATED["tiny"])
+    out, chars, offs, res = leg_forms(ej, ctx, oracle, args, col,
+                                      "tiny DNA: 2,000 strings (200 bases U{900..1100} x 10 "
+                                      "copies, Poisson(30) edits)", prm, stated, peak)
+    t0 = time.perf_counter()
+    truth, npairs = brute_truth(col, prm["K"], oracle)
+    got = res.codes
+    out["recall_vs_brute_force"] = dict(
+        pairs_examined=npairs, true_pairs=int(len(truth)),
+        found=int(np.isin(truth, got).sum()),
+        recall=round(float(np.isin(truth, got).mean()), 5) if len(truth) else None,
+        output_subset_of_truth=bool(np.isin(got, truth).all()),
+        oracle_seconds=round(time.perf_counter() - t0, 2))
+    out["stated_params_run"] = stated_run(ctx, chars, offs, dict(stated, L=0))
+    return out
 
 
-def _log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+def stated_run(ctx, chars, offs, prm):
+    import torch
+    ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0, L=prm.get("L", 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r2 = ctx.join(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0, L=prm.get("L", 0))
+    torch.cuda.synchronize()
+    return dict(params=prm, join_ms=round((time.perf_counter() - t0) * 1e3, 3),
+                candidates=r2.n_candidates, output_pairs=int(len(r2.pairs)))
 
 
-def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
+def uneven_leg(ej, ctx, oracle, args, peak, col):
+    """80,000 DNA strings, log-uniform lengths, K=400, calibrated point; the
+    recall denominator is exact: every planted pair verified, plus the
+    accidental true pairs among the strings short enough to form them (all
+    pairs of strings of length <= 2K verified).  The grouping alternative to
+    truncation runs beside it at the same (r, z, m)."""
+    import torch
+    import synthdata as sd
+    stated = dict(K=400, r=3, z=7, m=24)
+    prm = dict(K=400, **CALIBRATED["uneven"])
+    out, chars, offs, res = leg_forms(ej, ctx, oracle, args, col,
+                                      "uneven DNA: 80,000 strings, base lengths log-uniform "
+                                      "500..20,000, clusters geometric(0.3) <= 20, per-copy edit "
+                                      "rate U(0, 0.08)", prm, stated, peak)
+    if not args.no_recall:
+        short, examined = short_string_truth(ctx, chars, offs, col, prm["K"], 2 * prm["K"])
+        rec = exact_recall(ctx, chars, offs, col, prm["K"], res, oracle, extra_true=short)
+        rec["short_string_pairs_examined"] = examined
+        rec["short_string_true_pairs"] = int(len(short))
+        planted = _codes(sd.planted_pairs(col))
+        rec["recall_vs_planted_only"] = round(
+            float(np.isin(planted[gpu_within(ctx, chars, offs, planted, prm["K"])],
+                          res.codes).mean()), 5)
+        out["recall"] = rec
+    # grouping (Section 4.1) at the same r, z, m: untruncated walks per group
+    ctx.join_grouped(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = ctx.join_grouped(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0)
+    torch.cuda.synchronize()
+    gms = (time.perf_counter() - t0) * 1e3
+    out["grouping"] = dict(params=dict(r=prm["r"], z=prm["z"], m=prm["m"],
+                                       L="3 x each group's longest string"),
+                           join_ms=round(gms, 3), candidates=g.n_candidates,
+                           output_pairs=int(len(g.pairs)),
+                           recall_vs_planted=(exact_recall(ctx, chars, offs, col, prm["K"], g,
+                                                           oracle, check=50)["recall"]
+                                              if not args.no_recall else None))
+    return out
+
+
+def protein_leg(ej, ctx, oracle, args, peak, col):
+    """400,000 strings over 25 Zipf letters, K=100, at the stated r=5, z=10,
+    m=32 with L = ceil(2 avg).  Truth: the planted pairs within K (all
+    verified) and the pairs of strings both no longer than K (ED <= K is
+    guaranteed), counted exactly."""
+    stated = dict(K=100, r=5, z=10, m=32)
+    prm = dict(stated, L=int(np.ceil(2 * col.lengths().mean())))
+    out, chars, offs, res = leg_forms(ej, ctx, oracle, args, col,
+                                      "protein-like: 400,000 strings over 25 letters (Zipf 1.1), "
+                                      "lengths lognormal (median 400, sigma 0.8) clipped 50..4,000,"
+                                      " clusters of mean 4, edit rate U(0.02, 0.15)", prm, stated,
+                                      peak, steps=3, warmup=1, tune_reps=1)
+    if not args.no_recall:
+        import synthdata as sd
+        K = prm["K"]
+        lens = col.lengths()
+        short = np.nonzero(lens <= K)[0]
+        planted = _codes(sd.planted_pairs(col))
+        w = planted[gpu_within(ctx, chars, offs, planted, K)]
+        got = res.codes
+        ga = (got >> np.uint64(32)).astype(np.int64)
+        gb = (got & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        both_short = (lens[ga] <= K) & (lens[gb] <= K)
+        pa = (w >> np.uint64(32)).astype(np.int64)
+        pb = (w & np.uint64(0xFFFFFFFF)).astype(np.int64)
+        planted_short = int(((lens[pa] <= K) & (lens[pb] <= K)).sum())
+        n_short_pairs = len(short) * (len(short) - 1) // 2
+        denom = len(w) + n_short_pairs - planted_short
+        found = int(both_short.sum()) + int(np.isin(w[~((lens[pa] <= K) & (lens[pb] <= K))],
+                                                    got).sum())
+        out["recall"] = dict(planted_within_K=int(len(w)), short_strings=int(len(short)),
+                             guaranteed_short_pairs=int(n_short_pairs), true_pairs=int(denom),
+                             found=found, recall=round(found / denom, 5) if denom else None,
+                             recall_vs_planted=round(float(np.isin(w, got).mean()), 5),
+                             other_true_pairs_found=int(len(got)) - found)
+    return out
+
+
+def plus_leg(ej, ctx, oracle, args, peak, col):
+    """EmbedJoin+ on 50,000 DNA reads with shifts (4,500-5,500 letters, reads
+    of a cluster start up to 60 letters apart, 0.3% edits), K=100, delta=50,
+    T=2; plain EmbedJoin at the same (r, z, m, L) beside it."""
+    import torch
+    chars, offs = device(col)
+    P = PLUS
+    prm = dict(K=P["K"], r=P["r"], z=P["z"], m=P["m"], L=P["L"])
+    fl = ej.FLAG_TIMING
+
+    def plus_join(flags):
+        return lambda: ctx.join_plus(chars, offs, P["K"], P["r"], P["z"], P["m"], delta=P["delta"],
+                                     T=P["T"], seed=0, L=P["L"], flags=flags)
+
+    defaults = ctx.knobs()
+    out = dict(workload="EmbedJoin+ on reads with shifts: 50,000 DNA reads (5,000 genome "
+                        "segments x 10 reads starting up to 60 letters apart, lengths "
+                        "4,500..5,500, Poisson(0.003 len) edits)", params=dict(P))
+    res, ms, stage = time_join(plus_join(fl), args.steps, args.warmup)
+    out["plain_form"] = dict(join_sec=round(ms / 1e3, 5), candidates=res.n_candidates,
+                             tuples=res.n_raw, output_pairs=int(len(res.pairs)),
+                             verified_pairs_per_s=round(res.n_candidates / (ms / 1e3), 3),
+                             stage_ms={k: round(v, 3) for k, v in stage.items()},
+                             roofline=roofline(res, stage, prm, "k_verify", peak))
+    try:
+        ctx.tune_set("verify_mode", 1)
+        res_b, ms_b, stage_b = time_join(plus_join(fl | ej.FLAG_GRAPH), args.steps, args.warmup)
+    finally:
+        for k, v in defaults.items():
+            ctx.tune_set(k, v)
+    out["batched_form"] = dict(join_sec=round(ms_b / 1e3, 5),
+                               verified_pairs_per_s=round(res_b.n_candidates / (ms_b / 1e3), 3),
+                               stage_ms={k: round(v, 3) for k, v in stage_b.items()},
+                               roofline=roofline(res_b, stage_b, prm, "k_verify_queue", peak))
+    if not args.no_recall:
+        out["recall"] = exact_recall(ctx, chars, offs, col, P["K"], res, oracle, check=100)
+    ctx.join(chars, offs, P["K"], P["r"], P["z"], P["m"], seed=0, L=P["L"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pl = ctx.join(chars, offs, P["K"], P["r"], P["z"], P["m"], seed=0, L=P["L"])
+    torch.cuda.synchronize()
+    out["embedjoin_same_params"] = dict(
+        join_ms=round((time.perf_counter() - t0) * 1e3, 3), candidates=pl.n_candidates,
+        recall=(exact_recall(ctx, chars, offs, col, P["K"], pl, oracle, check=50)["recall"]
+                if not args.no_recall else None))
+    return out
+
+
+# ------------------------------------------------------------- serving --
+
+def serving_leg(ej, ctx, oracle, col, d, max_batch=4096, n_recall=1000, seed=0):
     """Device-resident index over 320,000 DNA strings; 10,000 queries of mixed
     lengths and thresholds.  Saturation throughput from back-to-back batches,
     then a Poisson arrival stream at 0.5/0.8/1.0x that rate served by an
     arrival batcher (everything that has arrived, at most max_batch, halved
-    while the index refuses admission); latency = completion - arrival."""
+    while the index refuses admission); latency = completion - arrival.  Then
+    the incremental insert: the index built over 90% of the strings and the
+    last 10% inserted, timed against a rebuild over all of them."""
     import torch
     import synthdata as sd
-    t0 = time.perf_counter()
-    if seed not in _SERVING_DATA:
-        col, _ = sd.serving_index(seed)
-        _SERVING_DATA[seed] = (col,) + tuple(sd.serving_queries(col, seed))
-    col, q, Kq, src = _SERVING_DATA[seed]
-    gen_s = time.perf_counter() - t0
-    _log(f"serving data ready ({gen_s:.1f} s), params {SERVING}")
-    chars = torch.from_numpy(col.chars).cuda()
-    offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
+    qc, qo, Kq, src = d["qchars"], d["qoffsets"].astype(np.uint64), d["Kq"], d["src"]
+    nq = len(qo) - 1
+    chars, offs = device(col)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ix = ej.Index(ctx, chars, offs, SERVING["r"], SERVING["z"], SERVING["m"], seed=seed,
                   L=SERVING["L"])
     build_s = time.perf_counter() - t0
-    del chars, offs
     _log(f"index built in {build_s:.3f} s")
-    qc, qo = q.chars, q.offsets.astype(np.uint64)
-    nq = q.n
 
     def run(i0, i1):
-        # queries i0..i1-1: their offsets index into the whole query buffer
         return ix.query(qc, qo[i0:i1 + 1], Kq[i0:i1])
 
     def run_admitted(i0, i1):
@@ -266,7 +660,6 @@ def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
         return out
 
     run_admitted(0, min(nq, 256))   # warm-up
-    # saturation
     found = {}
     t0 = time.perf_counter()
     ncand = 0
@@ -277,8 +670,6 @@ def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
                 found[a + k] = res.of(k)[0]
     sat_s = time.perf_counter() - t0
     sat_qps = nq / sat_s
-    _log(f"saturation {sat_qps:.0f} queries/s, {ncand / nq:.1f} candidates per query")
-    # Poisson arrivals
     sweeps = []
     for load in (0.5, 0.8, 1.0):
         rng = np.random.default_rng(seed + int(load * 100))
@@ -301,7 +692,6 @@ def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
             nb += 1
             i = j
         wall = time.perf_counter() - start
-        _log(f"poisson load {load}: {nb} batches")
         sweeps.append(dict(load=load, offered_qps=round(load * sat_qps, 1),
                            achieved_qps=round(nq / wall, 1), batches=nb,
                            p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
@@ -320,124 +710,108 @@ def serving_bench(ej, ctx, oracle, max_batch=4096, n_recall=1000, seed=0):
             true_n += 1
             hit += int(s in set(found[qi].tolist()))
     ix.close()
+    # incremental insert: 90% built, 10% inserted, against a full rebuild
+    n90 = int(col.n * 0.9)
+    head = sd.Collection(col.chars[:int(col.offsets[n90])], col.offsets[:n90 + 1], col.labels[:n90])
+    hc, ho = device(head)
+    tail_off = torch.from_numpy(col.offsets[n90:].astype(np.int64)).cuda()
+    ix2 = ej.Index(ctx, hc, ho, SERVING["r"], SERVING["z"], SERVING["m"], seed=seed,
+                   L=SERVING["L"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ix2.insert(chars, tail_off)
+    torch.cuda.synchronize()
+    ins_s = time.perf_counter() - t0
+    qa = ix2.query(qc, qo[:1025], Kq[:1024])
+    ix3 = ej.Index(ctx, chars, offs, SERVING["r"], SERVING["z"], SERVING["m"], seed=seed,
+                   L=SERVING["L"])
+    qb = ix3.query(qc, qo[:1025], Kq[:1024])
+    same = qa.ids.tolist() == qb.ids.tolist()
+    ix2.close()
+    ix3.close()
     return dict(workload="serving: index 320,000 DNA strings (32,000 bases U{4500..5500} x 10 "
                          "copies, Poisson(0.05 len) edits); 10,000 queries (70% re-mutated "
                          "members, 30% fresh U{1000..10000}), K_q in {2,5,10}% of |q|",
-                params=SERVING, gen_s=round(gen_s, 1), index_build_s=round(build_s, 3),
+                params=SERVING, index_build_s=round(build_s, 3),
                 saturation_qps=round(sat_qps, 1), saturation_batch=max_batch,
                 candidates_per_query=round(ncand / nq, 2),
                 poisson=sweeps, p50_ms=sweeps[-1]["p50_ms"], p99_ms=sweeps[-1]["p99_ms"],
                 recall_vs_source=dict(sampled_member_queries=int(len(pick)),
                                       source_within_Kq=true_n, found=hit,
-                                      recall=round(hit / true_n, 4) if true_n else None))
+                                      recall=round(hit / true_n, 4) if true_n else None),
+                insert=dict(strings=int(col.n - n90), insert_s=round(ins_s, 4),
+                            rebuild_s=round(build_s, 4),
+                            queries_equal_rebuilt_index=bool(same)))
 
 
-def run_forms(ej, ctx, chars, offs, prm, args):
-    """The plain per-stage form (default knobs, two-pass verification) and the
-    batched form (persistent verification replayed from a captured HIP graph,
-    knobs from the autotuner), timed on the same device-resident input."""
-    flags = ej.FLAG_TIMING
-    defaults = ctx.knobs()
-    ctx.tune_set("verify_mode", 0)
-    res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, flags)
-    plain = dict(res=res, ms=ms, stage=stage, knobs=ctx.knobs(), kernel="k_verify")
-    if args.knobs:
-        for kv in args.knobs.split(","):
-            k, v = kv.split("=")
-            ctx.tune_set(k.strip(), int(v))
-        tune_ms = None
-    elif args.no_autotune:
-        ctx.tune_set("verify_mode", 2)
-        tune_ms = None
-    else:
-        tune_ms, _ = ctx.autotune(chars, offs, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
-                                  L=prm["L"], reps=2)
-    knobs = ctx.knobs()
-    gflags = flags | (ej.FLAG_GRAPH if knobs["verify_mode"] >= 1 else 0)
-    res, ms, stage = time_join(ctx, chars, offs, prm, args.steps, args.warmup, gflags)
-    batched = dict(res=res, ms=ms, stage=stage, knobs=knobs, autotune_best_ms=tune_ms,
-                   kernel=VERIFY_KERNEL[res.verify_form])
-    for k, v in defaults.items():
-        ctx.tune_set(k, v)
-    return dict(plain=plain, batched=batched)
+# ----------------------------------------------------------- baseline --
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return dict(nproc=os.cpu_count(), cpu_model=model)
 
 
-def roofline(res, stage, prm, kern):
-    """Algorithmic integer operations per step of the dominant kernel over
-    its own device time per step (events around each launch)."""
-    if stage.get("verify", 0.0) >= stage.get("embed", 0.0) and res.verify_columns:
-        cells = res.verify_columns * (prm["K"] + 1)
-        ops = cells / 32.0 * OPS_PER_WORD_STEP
-        t = stage["verify_kernel"] / 1000.0
-        nl = max(1, res.verify_launches)
-        work = dict(launches_per_step=res.verify_launches,
-                    avg_launch_ms=round(stage["verify_kernel"] / nl, 4),
-                    band_cells=int(cells), text_columns=int(res.verify_columns),
-                    gcells_per_s=round(cells / t / 1e9, 2) if t > 0 else None,
-                    ukkonen_2k1_gcells_per_s=round(res.verify_columns * (2 * prm["K"] + 1)
-                                                   / t / 1e9, 2) if t > 0 else None)
-    else:
-        kern = "k_embed"
-        ops = res.walk_steps * OPS_PER_WALK_STEP
-        t = stage["embed"] / 1000.0
-        work = dict(walk_steps=int(res.walk_steps),
-                    gsteps_per_s=round(res.walk_steps / t / 1e9, 2) if t > 0 else None)
-    achieved = ops / t / 1e12 if t > 0 else 0.0
-    peak = MI355X_INT32_LANE_OPS / 1e12
-    return dict(bound="alu", kernel=kern, achieved=round(achieved, 4), peak=round(peak, 2),
-                unit="T int32 lane-op/s", frac=round(achieved / peak, 5), traffic=None,
-                traffic_unit="HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, "
-                             "copy-scaled)",
-                kernel_ms=round(t * 1000.0, 4), **work)
-
-
-def form_summary(f, prm):
-    res, ms, stage = f["res"], f["ms"], f["stage"]
-    roof = roofline(res, stage, prm, f["kernel"])
-    return dict(join_sec=round(ms / 1000.0, 5),
-                verified_pairs_per_s=round(res.n_candidates / (ms / 1000.0), 3),
-                stage_ms={k: round(v, 3) for k, v in stage.items()},
-                kernel=roof["kernel"], kernel_ms=roof["kernel_ms"], roofline_frac=roof["frac"],
-                knobs=f["knobs"])
-
-
-def leg_bench(ej, ctx, oracle, args, col, desc, prm, stated):
-    """One more workload in both forms (plain, batched) at parameters prm."""
-    import torch
-    _log(f"leg: {desc}")
-    chars = torch.from_numpy(col.chars).cuda()
-    offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
-    forms = run_forms(ej, ctx, chars, offs, prm, args)
-    b = forms["batched"]
-    out = dict(workload=desc, params=prm, stated=stated,
-               candidates=b["res"].n_candidates, output_pairs=int(len(b["res"].pairs)),
-               batched=form_summary(b, prm), plain=form_summary(forms["plain"], prm))
-    if not args.no_recall:
-        out["recall"] = recall_estimate(col, b["res"], prm["K"], oracle)
-    return out
-
-
-def uneven_bench(ej, ctx, oracle, args):
-    """The batched uneven-length join (80,000 DNA strings, log-uniform
-    lengths, K=400) in both forms at its recall-calibrated point."""
+def cpu_baseline(col, prm, oracle, budget_s=12.0):
+    """The oracle (single thread) on growing prefixes of the workload until
+    it runs for about budget_s; rate = candidate pairs verified per second."""
     import synthdata as sd
-    col, stated = sd.uneven_dna(0)
-    prm = dict(K=stated["K"], **CALIBRATED["uneven"])
-    return leg_bench(ej, ctx, oracle, args, col,
-                     "uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, clusters "
-                     "geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)", prm, stated)
+    n = 250
+    last = None
+    while True:
+        sub = sd.from_strings(col.strings()[:n])
+        t0 = time.perf_counter()
+        r = oracle.join(sub.chars, sub.offsets, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
+                        L=prm["L"])
+        dt = time.perf_counter() - t0
+        last = (n, dt, len(r.cand), len(r.out))
+        if dt >= budget_s or n >= col.n:
+            break
+        n = min(col.n, int(n * max(1.5, min(4.0, (budget_s / max(dt, 1e-3)) ** 0.5))))
+    n, dt, nc, no = last
+    return dict(value=round(nc / dt, 3), unit="verified candidate pairs/s", cores=1,
+                kind="oracle", seconds=round(dt, 2), joins_per_s=round(1.0 / dt, 4),
+                sample=f"oracle join of the first {n} of {col.n} strings "
+                       f"({nc} candidates, {no} output pairs), same parameters", **cpu_info())
 
 
-def protein_bench(ej, ctx, oracle, args):
-    """The protein-like join (400,000 strings over 25 Zipf letters, K=100)
-    at its stated parameters with L = ceil(2 avg)."""
+# --------------------------------------------------------------- main --
+
+def headline_workload(args):
     import synthdata as sd
-    col, stated = sd.protein_like(0)
-    prm = dict(stated, L=int(np.ceil(2 * col.lengths().mean())))
-    return leg_bench(ej, ctx, oracle, args, col,
-                     "protein-like: 400,000 strings over 25 letters (Zipf 1.1), lengths lognormal "
-                     "(median 400, sigma 0.8) clipped 50..4,000, clusters of mean 4, edit rate "
-                     "U(0.02, 0.15)", prm, stated)
+    if args.workload == "medium":
+        col, prm = sd.medium_dna(0, K=args.K or 500)
+        name = ("medium DNA: 20,000 strings (2,000 bases U{4500..5500} x 10 copies, "
+                "Poisson(0.04 len) edits)")
+    elif args.workload == "uneven":
+        col, prm = sd.uneven_dna(0)
+        name = ("uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, clusters "
+                "geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)")
+    else:
+        col, prm = sd.tiny_dna(0)
+        name = "tiny DNA: 2,000 strings (200 bases U{900..1100} x 10 copies, Poisson(30) edits)"
+    stated = dict(K=prm["K"], r=prm["r"], z=prm["z"], m=prm["m"], L=0)
+    run = dict(stated) if args.stated else dict(stated, **CALIBRATED[args.workload])
+    for k in ("K", "r", "z", "m", "L"):
+        if getattr(args, k) is not None:
+            run[k] = getattr(args, k)
+    return col, name, stated, run
+
+
+def guarded(name, fn):
+    """A leg's result, or its error (reported; never hides the headline)."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001
+        _log(f"{name} failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
 
 
 def main():
@@ -449,37 +823,63 @@ def main():
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
-    import torch
+    legs = [x for x in args.legs.split(",") if x] if not args.serving_only else ["serving"]
+    for x in legs:
+        if x not in LEGS:
+            raise SystemExit(f"unknown leg {x}")
+    gen = [n for n, leg in (("uneven", "uneven"), ("protein", "protein"), ("shifted", "plus"),
+                            ("serving", "serving")) if leg in legs]
+    pool = DataPool(gen) if gen and not args.valu_probe else None
+    try:
+        _main(args, legs, pool)
+    finally:
+        if pool:
+            pool.close()
+
+
+def _main(args, legs, pool):
     import paper_1702_00093_amd as ej
     from oracle import oracle
+    ctx = ej.Context(0)
+    if args.valu_probe:
+        ops, runs = valu_peak(ctx)
+        print(json.dumps({"valu_probe_tops": round(ops / 1e12, 3), "runs": runs}), flush=True)
+        return
     if args.serving_params:
         r_, z_, m_, L_ = (int(x) for x in args.serving_params.split(","))
         SERVING.update(r=r_, z=z_, m=m_, L=L_)
+    peak, probe_runs = valu_peak(ctx)
+    _log(f"VALU probe {peak / 1e12:.2f} T lane-ops/s")
     if args.serving_only:
-        sctx = ej.Context(0)
-        points = [tuple(int(x) for x in pt.split(",")) for pt in args.serving_sweep.split(";")] \
-            if args.serving_sweep else [(SERVING["r"], SERVING["z"], SERVING["m"], SERVING["L"])]
-        for r_, z_, m_, L_ in points:
-            SERVING.update(r=r_, z=z_, m=m_, L=L_)
-            print(json.dumps({"serving": serving_bench(ej, sctx, oracle)}), flush=True)
+        col, d = pool.get("serving")
+        print(json.dumps({"serving": serving_leg(ej, ctx, oracle, col, d)}), flush=True)
         return
-    col, name, stated, prm = workload(args)
-    chars = torch.from_numpy(col.chars.copy()).cuda()
-    offs = torch.from_numpy(col.offsets.astype(np.int64)).cuda()
-    ctx = ej.Context(0)
+    col, name, stated, prm = headline_workload(args)
+    chars, offs = device(col)
     forms = run_forms(ej, ctx, chars, offs, prm, args)
     head = forms["batched"]
     res, ms, stage = head["res"], head["ms"], head["stage"]
     cand = res.n_candidates
     value = cand / (ms / 1000.0)
-    # context run at the stated parameters (one join, not the headline)
-    stated_info = None
-    if prm != stated:
-        r2, ms2, st2 = time_join(ctx, chars, offs, stated, 2, 1, ej.FLAG_TIMING)
-        stated_info = dict(params=stated, join_ms=round(ms2, 3), candidates=r2.n_candidates,
-                           output_pairs=int(len(r2.pairs)),
-                           stage_ms={k: round(v, 3) for k, v in st2.items()})
-    roof = roofline(res, stage, prm, head["kernel"])
+    stated_info = stated_run(ctx, chars, offs, stated) if prm != stated else None
+    # the same join with the strings in host memory: host-to-device copy of
+    # the input and device-to-host copy of the result included
+    import torch
+    hflags = ej.FLAG_GRAPH if head["knobs"]["verify_mode"] >= 1 else 0
+    defaults = ctx.knobs()
+    for k, v in head["knobs"].items():
+        ctx.tune_set(k, v)
+    ctx.join(col.chars, col.offsets, prm["K"], prm["r"], prm["z"], prm["m"], seed=0, L=prm["L"],
+             flags=hflags)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        ctx.join(col.chars, col.offsets, prm["K"], prm["r"], prm["z"], prm["m"], seed=0,
+                 L=prm["L"], flags=hflags)
+    torch.cuda.synchronize()
+    h2d_ms = (time.perf_counter() - t0) * 1000.0 / 3
+    for k, v in defaults.items():
+        ctx.tune_set(k, v)
+    roof = roofline(res, stage, prm, head["kernel"], peak)
     if (roof["kernel"].startswith("k_verify") and args.workload == "medium" and prm["K"] == 500
             and prm == dict(stated, **CALIBRATED["medium"])):
         roof["traffic"] = measured_traffic(roof["kernel"], "medium_K500")
@@ -494,30 +894,41 @@ def main():
                             + VERIFY_FORM[res.verify_form]),
                    "candidates": cand, "raw_candidates": res.n_raw,
                    "output_pairs": int(len(res.pairs)), "join_sec": round(ms / 1000.0, 5),
+                   "join_sec_with_h2d_d2h": round(h2d_ms / 1000.0, 5),
                    "stage_ms": {k: round(v, 3) for k, v in stage.items()},
                    "knobs": head["knobs"],
-                   "plain_form": form_summary(forms["plain"], prm)},
+                   "plain_form": form_summary(forms["plain"], prm, peak)},
         "roofline": roof,
+        "valu_probe": dict(peak_tops=round(peak / 1e12, 3), runs=probe_runs,
+                           kernel="k_probe_valu: independent add / 3-input logic / funnel-shift "
+                                  "chains, 96 VALU instructions per loop iteration"),
     }
     if stated_info:
         out["config"]["stated_params_run"] = stated_info
     if not args.no_recall:
-        out["config"]["recall"] = recall_estimate(col, res, prm["K"], oracle)
-    if not args.no_uneven:
-        try:
-            out["uneven"] = uneven_bench(ej, ctx, oracle, args)
-        except Exception as e:  # reported, never hides the join line
-            out["uneven"] = {"error": f"{type(e).__name__}: {e}"}
-    if args.with_protein:
-        try:
-            out["protein"] = protein_bench(ej, ctx, oracle, args)
-        except Exception as e:  # reported, never hides the join line
-            out["protein"] = {"error": f"{type(e).__name__}: {e}"}
-    if not args.no_serving:
-        try:
-            out["serving"] = serving_bench(ej, ctx, oracle)
-        except Exception as e:  # reported, never hides the join line
-            out["serving"] = {"error": f"{type(e).__name__}: {e}"}
+        out["config"]["recall"] = guarded("recall", lambda: exact_recall(
+            ctx, chars, offs, col, prm["K"], res, oracle))
+        out["config"]["calibration"] = guarded("calibration", lambda: calibration_block(
+            ej, ctx, chars, offs, col, prm["K"], oracle))
+    del chars, offs
+    if "tiny" in legs:
+        out["tiny"] = guarded("tiny", lambda: tiny_leg(ej, ctx, oracle, args, peak))
+    if "uneven" in legs:
+        ucol, _ = pool.get("uneven")
+        out["uneven"] = guarded("uneven", lambda: uneven_leg(ej, ctx, oracle, args, peak, ucol))
+        del ucol
+    if "protein" in legs:
+        pcol, _ = pool.get("protein")
+        out["protein"] = guarded("protein", lambda: protein_leg(ej, ctx, oracle, args, peak, pcol))
+        del pcol
+    if "plus" in legs:
+        scol, _ = pool.get("shifted")
+        out["plus"] = guarded("plus", lambda: plus_leg(ej, ctx, oracle, args, peak, scol))
+        del scol
+    if "serving" in legs:
+        vcol, vd = pool.get("serving")
+        out["serving"] = guarded("serving", lambda: serving_leg(ej, ctx, oracle, vcol, vd))
+        del vcol, vd
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(col, prm, oracle)
     print(json.dumps(out), flush=True)

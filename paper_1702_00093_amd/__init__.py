@@ -31,7 +31,7 @@ EXPORTS = [
     "ej_join_grouped", "ej_join_grouped_device",
     "ej_result_free", "ej_autotune",
     "ej_embed", "ej_lsh_bucket", "ej_candidates", "ej_verify", "ej_verify_static",
-    "ej_set_explicit_randomness", "ej_embed_hamming", "ej_calibrate",
+    "ej_set_explicit_randomness", "ej_embed_hamming", "ej_calibrate", "ej_probe_valu",
     "ej_index_build", "ej_index_insert", "ej_query_batch", "ej_query_workspace_estimate", "ej_index_set_hbm_limit",
     "ej_index_size", "ej_qresult_free", "ej_index_free",
 ]
@@ -132,6 +132,8 @@ def lib():
         "ej_embed_hamming": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32, vp, u64, vp]),
         "ej_calibrate": (c_int, [vp, vp, vp, u32, vp, u64, ctypes.POINTER(CalibOpts),
                                  ctypes.POINTER(CalibResult), vp]),
+        "ej_probe_valu": (c_int, [vp, u32, u32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_float)]),
         "ej_index_build": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), c_int,
                                    ctypes.POINTER(vp)]),
         "ej_index_insert": (c_int, [vp, vp, vp, u32, c_int]),
@@ -215,6 +217,9 @@ class Context:
     """A library context bound to one device and one HIP stream."""
 
     def __init__(self, device: int = 0, stream=None):
+        # torch carries a HIP runtime of its own besides the one this library
+        # links; torch's must start first or it finds no device afterwards
+        _torch().cuda.init()
         L = lib()
         self._h = ctypes.c_void_p()
         st = L.ej_create(ctypes.byref(self._h), device, stream)
@@ -445,6 +450,13 @@ class Context:
         if want_table:
             out["table"] = table
         return out
+
+    def probe_valu(self, iters: int = 4096, blocks_per_cu: int = 8):
+        """ej_probe_valu: (achieved int32 lane-ops/s, kernel ms)."""
+        ops, ms = ctypes.c_double(), ctypes.c_float()
+        self._check(lib().ej_probe_valu(self._h, iters, blocks_per_cu, ctypes.byref(ops),
+                                        ctypes.byref(ms)))
+        return float(ops.value), float(ms.value)
 
     def set_explicit_randomness(self, r, z, m, L, sigma, Rbits=None, pos=None, v=None):
         if Rbits is None:

@@ -34,34 +34,23 @@ namespace ej {
 
 namespace {
 
-// P[X >= T] for X = sum over seeds l < r of Binomial(z, q[l]).
-double tail_at_least(const double *q, uint32_t r, uint32_t z, uint32_t T, std::vector<double> &dp,
-                     std::vector<double> &nx, std::vector<double> &bin) {
-    if (T == 0) return 1.0;
-    if (T == 1) {
-        double miss = 1.0;
-        for (uint32_t l = 0; l < r; l++) miss *= pow(1.0 - q[l], (double)z);
-        return 1.0 - miss;
-    }
-    dp.assign(T + 1, 0.0);  // dp[c] = P[count = c], c = T collects ">= T"
-    dp[0] = 1.0;
+// Distribution of the number of agreeing tables, capped at T (dp[T] holds
+// P[count >= T]), extended by one seed whose z tables agree each with
+// probability q: a convolution with Binomial(z, q).
+void add_seed(std::vector<double> &dp, std::vector<double> &nx, std::vector<double> &bin,
+              uint32_t z, uint32_t T, double q) {
     bin.assign(z + 1, 0.0);
-    for (uint32_t l = 0; l < r; l++) {
-        // Binomial(z, q) probabilities
-        const double p = q[l];
-        for (uint32_t k = 0; k <= z; k++) {
-            double c = 1.0;
-            for (uint32_t i = 0; i < k; i++) c = c * (double)(z - i) / (double)(i + 1);
-            bin[k] = c * pow(p, (double)k) * pow(1.0 - p, (double)(z - k));
-        }
-        nx.assign(T + 1, 0.0);
-        for (uint32_t c = 0; c <= T; c++) {
-            if (dp[c] == 0.0) continue;
-            for (uint32_t k = 0; k <= z; k++) nx[std::min(T, c + k)] += dp[c] * bin[k];
-        }
-        dp.swap(nx);
+    for (uint32_t k = 0; k <= z; k++) {
+        double c = 1.0;
+        for (uint32_t i = 0; i < k; i++) c = c * (double)(z - i) / (double)(i + 1);
+        bin[k] = c * pow(q, (double)k) * pow(1.0 - q, (double)(z - k));
     }
-    return dp[T];
+    nx.assign(T + 1, 0.0);
+    for (uint32_t c = 0; c <= T; c++) {
+        if (dp[c] == 0.0) continue;
+        for (uint32_t k = 0; k <= z; k++) nx[std::min(T, c + k)] += dp[c] * bin[k];
+    }
+    dp.swap(nx);
 }
 
 uint32_t effective_L(const Prep &pp, uint32_t L_req) {
@@ -181,15 +170,20 @@ ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_of
                     for (uint64_t e = 0; e < count; e++) {
                         for (uint32_t l = 0; l < R; l++)
                             q[l] = pow(1.0 - (double)ham[e * R + l] / L, (double)m);
-                        // every r in 1..R: the first r seeds
+                        // every r in 1..R: the first r seeds, one seed added at a time
                         double miss = 1.0;
+                        if (T > 1) {
+                            dp.assign(T + 1, 0.0);
+                            dp[0] = 1.0;
+                        }
                         for (uint32_t r = 1; r <= R; r++) {
                             double pc;
                             if (T == 1) {
                                 miss *= pow(1.0 - q[r - 1], (double)z);
                                 pc = 1.0 - miss;
                             } else {
-                                pc = tail_at_least(q.data(), r, z, T, dp, nx, bin);
+                                add_seed(dp, nx, bin, z, T, q[r - 1]);
+                                pc = dp[T];
                             }
                             (similar[e] ? rec : fal)[r - 1] += pc;
                         }
