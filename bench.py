@@ -28,9 +28,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = ("end-to-end join sec & verified candidate pairs/s at recall≥0.99; "
           "query p99 ms")
-# vendor-derived integer VALU peak: CUs x SIMDs x lanes x clock (a wave64
-# instruction holds a 16-lane SIMD for 4 cycles)
-MI355X_INT32_LANE_OPS = 256 * 4 * 16 * 2.4e9
+# Integer VALU peak from the unit counts and clock: 256 CUs x 4 SIMDs x 32
+# lanes per cycle x 2.4 GHz = 78.6 T lane-ops/s, the rate of the fp32 vector
+# figure (157.3 TFLOP/s counts an FMA as 2).  The probe kernel measures it for
+# 2-operand 32-bit integer instructions (v_add_u32, v_xor_b32: a wave64
+# instruction every 2 cycles per SIMD); 3-operand ones (v_bitop3_b32,
+# v_alignbit_b32, v_add_co_u32 with a scalar carry-out) issue at half that
+# rate (4 cycles), 39.3 T.
+MI355X_INT32_LANE_OPS = 256 * 4 * 32 * 2.4e9
+MI355X_INT32_LANE_OPS_3OP = 256 * 4 * 16 * 2.4e9
 
 # Work units of verification, in 32-bit integer lane operations per 32-cell
 # word of the K+1 band (diagonals a threshold-K distance needs):
@@ -96,6 +102,10 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES bytes (5 times): "
                          "the reference for scaling HBM traffic counters")
+    ap.add_argument("--no-pool", action="store_true",
+                    help="generate the collections in this process, one after another (for "
+                         "runs under a profiler, whose preloaded library has started the GPU "
+                         "before worker processes could be spawned)")
     ap.add_argument("--valu-probe", action="store_true",
                     help="only run the integer-VALU issue-rate probe (for its counter profile)")
     return ap.parse_args()
@@ -131,8 +141,13 @@ def _gen_worker(name, path):
 
 
 class DataPool:
-    def __init__(self, names):
+    def __init__(self, names, inline=False):
         self.dir = tempfile.mkdtemp(prefix="ej_bench_")
+        self.inline = inline
+        self.ex = None
+        if inline:
+            self.fut = {n: None for n in names}
+            return
         self.ex = ProcessPoolExecutor(max_workers=max(1, len(names)),
                                       mp_context=multiprocessing.get_context("spawn"))
         self.fut = {n: self.ex.submit(_gen_worker, n, os.path.join(self.dir, n + ".npz"))
@@ -141,7 +156,10 @@ class DataPool:
     def get(self, name):
         import synthdata as sd
         t0 = time.perf_counter()
-        path = self.fut[name].result()
+        if self.inline:
+            path = _gen_worker(name, os.path.join(self.dir, name + ".npz"))
+        else:
+            path = self.fut[name].result()
         z = np.load(path)
         d = {k: z[k] for k in z.files}
         os.remove(path)
@@ -150,7 +168,8 @@ class DataPool:
         return col, d
 
     def close(self):
-        self.ex.shutdown(cancel_futures=True)
+        if self.ex:
+            self.ex.shutdown(cancel_futures=True)
         shutil.rmtree(self.dir, ignore_errors=True)
 
 
@@ -168,17 +187,25 @@ def copy_probe(nbytes):
                       "writes_per_copy": nbytes, "copies": 5}), flush=True)
 
 
-def valu_peak(ctx):
-    """The integer-VALU issue rate the probe kernel reaches: the best of a
-    few occupancies (workgroups of 256 lanes per CU)."""
-    best = (0.0, 0, 0.0)
+PROBE_MIXES = {0: "verification mix (add, 3-input logic, funnel shift)", 1: "v_add_u32",
+               2: "v_xor_b32", 3: "v_bitop3_b32", 4: "v_alignbit_b32", 5: "v_add_co_u32"}
+
+
+def valu_peak(ctx, all_mixes=False):
+    """The integer-VALU issue rates the probe kernel reaches, per instruction
+    class, at the best of a few occupancies (workgroups of 256 lanes per CU):
+    returns (the best rate of any class, the runs)."""
+    best = 0.0
     runs = []
-    for bpc in (8, 16, 32):
-        ops, ms = ctx.probe_valu(4096, bpc)
-        runs.append(dict(blocks_per_cu=bpc, tops=round(ops / 1e12, 3), ms=round(ms, 4)))
-        if ops > best[0]:
-            best = (ops, bpc, ms)
-    return best[0], runs
+    mixes = PROBE_MIXES if all_mixes else (0, 1, 3)
+    occ = (8, 16, 32) if all_mixes else (32,)
+    for mix in mixes:
+        for bpc in occ:
+            ops, ms = ctx.probe_valu(4096, bpc, mix)
+            runs.append(dict(mix=PROBE_MIXES[mix], blocks_per_cu=bpc, tops=round(ops / 1e12, 3),
+                             ms=round(ms, 4)))
+            best = max(best, ops)
+    return best, runs
 
 
 def measured_traffic(kernel, workload_tag):
@@ -305,6 +332,7 @@ def roofline(res, stage, prm, kern, peak_measured=None):
         out["achieved_survey_unit"] = round(a2, 4)
         out["survey_unit"] = "20 ops per 32-cell word (recurrence + cross-lane carry + shift)"
         out["frac_survey_unit"] = round(a2 / peak, 5)
+        out["frac_vs_3_operand_peak"] = round(achieved / (MI355X_INT32_LANE_OPS_3OP / 1e12), 5)
         if peak_measured:
             out["frac_survey_unit_vs_measured"] = round(a2 / (peak_measured / 1e12), 5)
     return out
@@ -829,7 +857,7 @@ def main():
             raise SystemExit(f"unknown leg {x}")
     gen = [n for n, leg in (("uneven", "uneven"), ("protein", "protein"), ("shifted", "plus"),
                             ("serving", "serving")) if leg in legs]
-    pool = DataPool(gen) if gen and not args.valu_probe else None
+    pool = DataPool(gen, inline=args.no_pool) if gen and not args.valu_probe else None
     try:
         _main(args, legs, pool)
     finally:
@@ -842,7 +870,7 @@ def _main(args, legs, pool):
     from oracle import oracle
     ctx = ej.Context(0)
     if args.valu_probe:
-        ops, runs = valu_peak(ctx)
+        ops, runs = valu_peak(ctx, all_mixes=True)
         print(json.dumps({"valu_probe_tops": round(ops / 1e12, 3), "runs": runs}), flush=True)
         return
     if args.serving_params:
@@ -900,8 +928,8 @@ def _main(args, legs, pool):
                    "plain_form": form_summary(forms["plain"], prm, peak)},
         "roofline": roof,
         "valu_probe": dict(peak_tops=round(peak / 1e12, 3), runs=probe_runs,
-                           kernel="k_probe_valu: independent add / 3-input logic / funnel-shift "
-                                  "chains, 96 VALU instructions per loop iteration"),
+                           kernel="k_probe_valu: 8 independent dependency chains per lane, 96 "
+                                  "VALU instructions of one class per loop iteration"),
     }
     if stated_info:
         out["config"]["stated_params_run"] = stated_info

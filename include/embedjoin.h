@@ -367,14 +367,16 @@ ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_of
                        ej_calib_result *out, double *table);
 
 /* Issue-rate probe for the integer-VALU roofline of verification: runs a
- * kernel of independent 32-bit add / 3-input logic / funnel-shift chains (96
- * VALU instructions per loop iteration, no memory traffic) on
- * blocks_per_cu workgroups of 256 lanes per CU for `iters` iterations and
- * returns the achieved lane operations per second and the kernel time (one
- * untimed launch runs first).  EJ_EINVAL for iters = 0 or blocks_per_cu
- * outside 1..64. */
-ej_status ej_probe_valu(ej_ctx *ctx, uint32_t iters, uint32_t blocks_per_cu, double *lane_ops,
-                        float *ms);
+ * kernel of independent dependency chains (96 VALU instructions per loop
+ * iteration, no memory traffic) on blocks_per_cu workgroups of 256 lanes per
+ * CU for `iters` iterations and returns the achieved lane operations per
+ * second and the kernel time (one untimed launch runs first).  mix selects
+ * the instructions: 0 verification's add / 3-input logic / funnel shift in
+ * turn; 1 32-bit add; 2 xor; 3 3-input logic; 4 funnel shift; 5 add with the
+ * carry-out to a scalar mask.  EJ_EINVAL for iters = 0, blocks_per_cu
+ * outside 1..64 or mix above 5. */
+ej_status ej_probe_valu(ej_ctx *ctx, uint32_t mix, uint32_t iters, uint32_t blocks_per_cu,
+                        double *lane_ops, float *ms);
 
 /* Test hook: replace the drawn randomness of the next calls by explicit
  * values (host arrays): Rbits [r][L*sigma] 0/1 bytes (pi_j(sigma_k) at

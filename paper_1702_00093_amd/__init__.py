@@ -132,7 +132,7 @@ def lib():
         "ej_embed_hamming": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), u32, vp, u64, vp]),
         "ej_calibrate": (c_int, [vp, vp, vp, u32, vp, u64, ctypes.POINTER(CalibOpts),
                                  ctypes.POINTER(CalibResult), vp]),
-        "ej_probe_valu": (c_int, [vp, u32, u32, ctypes.POINTER(ctypes.c_double),
+        "ej_probe_valu": (c_int, [vp, u32, u32, u32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_float)]),
         "ej_index_build": (c_int, [vp, vp, vp, u32, ctypes.POINTER(Params), c_int,
                                    ctypes.POINTER(vp)]),
@@ -451,10 +451,10 @@ class Context:
             out["table"] = table
         return out
 
-    def probe_valu(self, iters: int = 4096, blocks_per_cu: int = 8):
+    def probe_valu(self, iters: int = 4096, blocks_per_cu: int = 8, mix: int = 0):
         """ej_probe_valu: (achieved int32 lane-ops/s, kernel ms)."""
         ops, ms = ctypes.c_double(), ctypes.c_float()
-        self._check(lib().ej_probe_valu(self._h, iters, blocks_per_cu, ctypes.byref(ops),
+        self._check(lib().ej_probe_valu(self._h, mix, iters, blocks_per_cu, ctypes.byref(ops),
                                         ctypes.byref(ms)))
         return float(ops.value), float(ms.value)
 
