@@ -67,6 +67,11 @@ typedef enum {
                             the context by launch arguments and replayed by later joins
                             of the same shape */
 #define EJ_FLAG_TIMING 2u  /* record per-stage device times in ej_result */
+#define EJ_FLAG_DEVICE_OUT 4u /* leave the result in device memory: out->pairs and
+                               out->dist are device pointers into the context's
+                               workspace, valid until the next call on the
+                               context (copy them out before it); out->on_device
+                               is 1 and ej_result_free frees nothing */
 
 typedef struct ej_ctx ej_ctx;
 
@@ -82,8 +87,10 @@ typedef struct {
 
 typedef struct {
     uint64_t count;        /* number of output pairs */
-    uint32_t *pairs;       /* host, [count][2], i < j, sorted lexicographically */
-    int32_t *dist;         /* host, [count], the edit distance of each pair (<= K) */
+    uint32_t *pairs;       /* host (device with EJ_FLAG_DEVICE_OUT), [count][2], i < j,
+                              sorted lexicographically */
+    int32_t *dist;         /* host (device with EJ_FLAG_DEVICE_OUT), [count], the edit
+                              distance of each pair (<= K) */
     uint64_t n_candidates; /* |C|: de-duplicated candidate pairs that were verified */
     uint64_t n_raw;        /* candidate pairs before de-duplication across tables */
     uint32_t sigma;        /* alphabet size */
@@ -107,6 +114,8 @@ typedef struct {
      * 1 persistent groups of pairs, 2 one pair per lane, 3 several lanes per
      * pair with several band words each (2 and 3: "verify_mode" 2). */
     uint32_t verify_form;
+    /* 1 when pairs and dist are device pointers (EJ_FLAG_DEVICE_OUT) */
+    uint32_t on_device;
 } ej_result;
 
 /* ---------------------------------------------------------------- lifecycle */

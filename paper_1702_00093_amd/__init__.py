@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libembedjoin.so")
 EJ_OK, EJ_EINVAL, EJ_EALPHABET, EJ_ENOMEM, EJ_ECAPACITY, EJ_EHIP, EJ_EUNSUPPORTED = range(7)
 STATUS_NAMES = {0: "EJ_OK", 1: "EJ_EINVAL", 2: "EJ_EALPHABET", 3: "EJ_ENOMEM",
                 4: "EJ_ECAPACITY", 5: "EJ_EHIP", 6: "EJ_EUNSUPPORTED"}
-FLAG_PLAIN, FLAG_GRAPH, FLAG_TIMING = 0, 1, 2
+FLAG_PLAIN, FLAG_GRAPH, FLAG_TIMING, FLAG_DEVICE_OUT = 0, 1, 2, 4
 
 # Every symbol declared in include/embedjoin.h.
 EXPORTS = [
@@ -58,7 +58,7 @@ class _Result(ctypes.Structure):
                 ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float),
                 ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64),
                 ("ms_verify_kernel", ctypes.c_float), ("verify_launches", ctypes.c_uint32),
-                ("verify_form", ctypes.c_uint32)]
+                ("verify_form", ctypes.c_uint32), ("on_device", ctypes.c_uint32)]
 
 
 class CalibOpts(ctypes.Structure):
@@ -192,10 +192,23 @@ def _torch_stream_done():
     _torch().cuda.current_stream().synchronize()
 
 
+class _DeviceArray:
+    """A device buffer described by the CUDA array interface, so that torch
+    can take it over without a copy through the host."""
+
+    def __init__(self, ptr: int, shape, typestr: str):
+        self.__cuda_array_interface__ = {"shape": tuple(shape), "typestr": typestr,
+                                         "data": (ptr, False), "version": 3, "strides": None}
+
+
 @dataclass
 class JoinResult:
-    pairs: np.ndarray          # [count, 2] int64, i < j, sorted
-    dist: np.ndarray           # [count] int32
+    """Output pairs (i < j, sorted) with their distances.  With
+    FLAG_DEVICE_OUT the result is in device memory (`pairs_device` [count, 2]
+    int32 and `dist_device` torch tensors, owned by torch); `pairs`/`dist`
+    copy it to the host when first read."""
+    pairs_host: np.ndarray | None
+    dist_host: np.ndarray | None
     n_candidates: int
     n_raw: int
     sigma: int
@@ -206,6 +219,26 @@ class JoinResult:
     ms_verify_kernel: float = 0.0
     verify_launches: int = 0
     verify_form: int = 0       # 0 two-pass, 1 persistent groups, 2 one pair per lane, 3 split
+    pairs_device: object = None
+    dist_device: object = None
+
+    @property
+    def pairs(self) -> np.ndarray:       # [count, 2] int64
+        if self.pairs_host is None:
+            self.pairs_host = self.pairs_device.cpu().numpy().astype(np.uint32) \
+                .astype(np.int64)
+        return self.pairs_host
+
+    @property
+    def dist(self) -> np.ndarray:        # [count] int32
+        if self.dist_host is None:
+            self.dist_host = self.dist_device.cpu().numpy()
+        return self.dist_host
+
+    @property
+    def count(self) -> int:
+        return int(self.pairs_device.shape[0]) if self.pairs_host is None else \
+            int(self.pairs_host.shape[0])
 
     @property
     def codes(self) -> np.ndarray:
@@ -311,16 +344,30 @@ class Context:
         self._check(st)
         try:
             cnt = int(res.count)
-            # astype copies: the arrays stay valid after the result is freed
-            pairs = np.ctypeslib.as_array(res.pairs, (max(cnt, 1) * 2,))[:2 * cnt] \
-                .reshape(cnt, 2).astype(np.int64)
-            dist = np.ctypeslib.as_array(res.dist, (max(cnt, 1),))[:cnt].copy()
             ms = dict(prep=res.ms_prep, embed=res.ms_embed, bucket=res.ms_bucket,
                       candidates=res.ms_candidates, verify=res.ms_verify, output=res.ms_output)
-            return JoinResult(pairs, dist, int(res.n_candidates), int(res.n_raw),
+            ph = dh = pd = dd = None
+            if res.on_device:
+                # the library's buffers are reused by its next call: torch copies
+                # them into memory of its own (device to device)
+                torch = _torch()
+                pa = ctypes.cast(res.pairs, ctypes.c_void_p).value or 0
+                da = ctypes.cast(res.dist, ctypes.c_void_p).value or 0
+                if cnt:
+                    pd = torch.as_tensor(_DeviceArray(pa, (cnt, 2), "<i4"), device="cuda").clone()
+                    dd = torch.as_tensor(_DeviceArray(da, (cnt,), "<i4"), device="cuda").clone()
+                else:
+                    pd = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+                    dd = torch.zeros(0, dtype=torch.int32, device="cuda")
+            else:
+                # astype copies: the arrays stay valid after the result is freed
+                ph = np.ctypeslib.as_array(res.pairs, (max(cnt, 1) * 2,))[:2 * cnt] \
+                    .reshape(cnt, 2).astype(np.int64)
+                dh = np.ctypeslib.as_array(res.dist, (max(cnt, 1),))[:cnt].copy()
+            return JoinResult(ph, dh, int(res.n_candidates), int(res.n_raw),
                               int(res.sigma), int(res.L), ms, int(res.walk_steps),
                               int(res.verify_columns), float(res.ms_verify_kernel),
-                              int(res.verify_launches), int(res.verify_form))
+                              int(res.verify_launches), int(res.verify_form), pd, dd)
         finally:
             lib().ej_result_free(ctypes.byref(res))
 

@@ -227,11 +227,14 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
                            (const uint32_t *)flags, (const uint32_t *)pos, opairs, odist);
         EJ_CHECK_LAUNCH();
     }
-    // through the context's pinned staging buffer (grown when too small): one
-    // DMA at full link speed instead of staged copies to pageable memory.
-    // With timing on, the verified columns and the walk lengths J follow the
-    // results in the same buffer and share their synchronisation.
-    const size_t obytes = 12 * nout;
+    // host results go through the context's pinned staging buffer (grown when
+    // too small): one DMA at full link speed instead of staged copies to
+    // pageable memory.  With timing on, the verified columns and the walk
+    // lengths J follow the results in the same buffer and share their
+    // synchronisation.  EJ_FLAG_DEVICE_OUT leaves the results where the
+    // compaction wrote them.
+    const bool dev_out = (p.flags & EJ_FLAG_DEVICE_OUT) != 0;
+    const size_t obytes = dev_out ? 0 : 12 * nout;
     const size_t xbytes = tm.on ? 8 + 4ull * p.r : 0;
     const size_t need = obytes + xbytes;
     if (need && ctx->pinned_out_bytes < need) {
@@ -243,18 +246,28 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
         ctx->pinned_out_bytes = want;
     }
     out->count = nout;
-    out->pairs = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (nout ? nout : 1));
-    out->dist = (int32_t *)malloc(sizeof(int32_t) * (nout ? nout : 1));
-    if (!out->pairs || !out->dist) {
-        free(out->pairs);
-        free(out->dist);
-        out->pairs = nullptr;
-        out->dist = nullptr;
-        fail(EJ_ENOMEM, "host allocation of the result failed");
+    if (dev_out) {
+        if (!opairs) {
+            opairs = ws<uint32_t>(ctx, "j_out", 3);
+            odist = (int32_t *)(opairs + 2 * nout);
+        }
+        out->pairs = opairs;
+        out->dist = odist;
+        out->on_device = 1;
+    } else {
+        out->pairs = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (nout ? nout : 1));
+        out->dist = (int32_t *)malloc(sizeof(int32_t) * (nout ? nout : 1));
+        if (!out->pairs || !out->dist) {
+            free(out->pairs);
+            free(out->dist);
+            out->pairs = nullptr;
+            out->dist = nullptr;
+            fail(EJ_ENOMEM, "host allocation of the result failed");
+        }
+        if (nout)
+            EJ_HIP(hipMemcpyAsync(ctx->pinned_out, opairs, obytes, hipMemcpyDeviceToHost,
+                                  ctx->stream));
     }
-    if (nout)
-        EJ_HIP(hipMemcpyAsync(ctx->pinned_out, opairs, obytes, hipMemcpyDeviceToHost,
-                              ctx->stream));
     tm.mark();  // 6
     uint8_t *xp = ctx->pinned_out + obytes;
     if (xbytes) {
@@ -266,7 +279,7 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
             memset(xp + 8, 0, 4ull * p.r);
     }
     sync(ctx);
-    if (nout) {
+    if (nout && !dev_out) {
         memcpy(out->pairs, ctx->pinned_out, 8 * nout);
         memcpy(out->dist, ctx->pinned_out + 8 * nout, 4 * nout);
     }
@@ -723,8 +736,10 @@ ej_status ej_join(ej_ctx *ctx, const uint8_t *strings, const uint64_t *offsets, 
 
 void ej_result_free(ej_result *res) {
     if (!res) return;
-    free(res->pairs);
-    free(res->dist);
+    if (!res->on_device) {
+        free(res->pairs);
+        free(res->dist);
+    }
     res->pairs = nullptr;
     res->dist = nullptr;
     res->count = 0;

@@ -508,6 +508,33 @@ def test_autotune_survives_settings_that_cannot_run(ej, ctx, oracle_lib):
             ctx.tune_set(k, v)
 
 
+def test_result_left_on_the_device(ej, ctx, oracle_lib):
+    """FLAG_DEVICE_OUT: the same pairs and distances, handed over in device
+    memory (torch tensors); a later join does not change them; an empty
+    result works too."""
+    col = sd.clusters(17, 30, lambda rr, b: 4, lambda rr: rr.integers(200, 600),
+                      lambda rr, LL: rr.poisson(10))
+    K, r, z, m, L = 40, 4, 6, 4, 48
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 3, L)
+    chars, offs = to_device(col)
+    for mode in _each_verify_mode(ctx):
+        _say(f"device-resident result, mode {mode}")
+        res = ctx.join(chars, offs, K, r, z, m, seed=3, L=L,
+                       flags=ej.FLAG_DEVICE_OUT | ej.FLAG_TIMING)
+        assert res.pairs_device.is_cuda and res.count == len(ref.out)
+        other = ctx.join(chars, offs, 0, r, z, m, seed=3, L=L, flags=ej.FLAG_DEVICE_OUT)
+        _assert_join_equal(res, ref)
+        assert other.count <= res.count
+        plus = ctx.join_plus(chars, offs, K, r, z, m, delta=20, T=2, seed=3, L=L,
+                             flags=ej.FLAG_DEVICE_OUT)
+        pref = oracle_lib.join_plus(col.chars, col.offsets, K, r, z, m, delta=20, T=2, seed=3,
+                                    L=L)
+        assert pairs_to_codes(plus.pairs).tolist() == pref.out.tolist()
+    none = ctx.join(chars, offs, 0, r, z, m, seed=3, L=L, flags=ej.FLAG_DEVICE_OUT)
+    assert none.count == len(_oracle_join(oracle_lib, col, 0, r, z, m, 3, L).out)
+    assert none.pairs.shape == (none.count, 2)
+
+
 def test_graph_replays_match_eager(ej, ctx, oracle_lib):
     """Persistent verification (both forms) captured into a HIP graph: the
     first join captures, later joins of the same shape replay it, with eager
