@@ -720,27 +720,42 @@ __global__ void __launch_bounds__(64)
             }
         }
         if (__builtin_amdgcn_ballot_w64(has) == 0) break;
-        // ---- the windows of the pairs just taken, filled by the whole wave
-        uint64_t fm = __builtin_amdgcn_ballot_w64(fresh);
-        while (fm) {
-            const uint32_t L = (uint32_t)__builtin_ctzll(fm);
-            fm &= fm - 1;
-            PairView u = v;
-            const uint64_t mp = (uint64_t)(uintptr_t)v.mw;
-            u.mw = (const uint32_t *)(uintptr_t)(((uint64_t)readlane_u32((uint32_t)(mp >> 32), L)
-                                                  << 32) |
-                                                 readlane_u32((uint32_t)mp, L));
-            u.W = readlane_u32(v.W, L);
-            u.O = readlane_u32(v.O, L);
-            uint32_t *wl = lds + L * region;
-            for (uint32_t t = lane; t < sigma * RS; t += 64) {
-                const uint32_t c = t / RS, w = t - c * RS;
-                wl[c * RS + w] = mask_word(u, c, w);
+        // ---- the windows of the pairs just taken
+        if (SIGMAX <= 4) {
+            // small alphabets: the whole wave fills each fresh lane's window
+            // in turn (a handful of words per lane)
+            uint64_t fm = __builtin_amdgcn_ballot_w64(fresh);
+            while (fm) {
+                const uint32_t L = (uint32_t)__builtin_ctzll(fm);
+                fm &= fm - 1;
+                PairView u = v;
+                const uint64_t mp = (uint64_t)(uintptr_t)v.mw;
+                u.mw = (const uint32_t *)(uintptr_t)(
+                    ((uint64_t)readlane_u32((uint32_t)(mp >> 32), L) << 32) |
+                    readlane_u32((uint32_t)mp, L));
+                u.W = readlane_u32(v.W, L);
+                u.O = readlane_u32(v.O, L);
+                uint32_t *wl = lds + L * region;
+                for (uint32_t t = lane; t < sigma * RS; t += 64) {
+                    const uint32_t c = t / RS, w = t - c * RS;
+                    wl[c * RS + w] = mask_word(u, c, w);
+                }
+            }
+            // other lanes wrote these windows: the barrier orders their
+            // writes before the owners' reads
+            __syncthreads();
+        } else if (fresh) {
+            // larger alphabets: every fresh lane fills its own sigma rows at
+            // once (independent loads, in parallel over the fresh lanes,
+            // where a wave-wide fill would take one global latency per lane)
+            for (uint32_t c = 0; c < sigma; c++) {
+                uint32_t t[RS];
+#pragma unroll
+                for (uint32_t w = 0; w < RS; w++) t[w] = mask_word(v, c, w);
+#pragma unroll
+                for (uint32_t w = 0; w < RS; w++) win[c * RS + w] = t[w];
             }
         }
-        // other lanes wrote these windows: the barrier orders their writes
-        // before the owners' reads
-        __syncthreads();
 
         // ---- one block of 32 columns; the next block's text and entering
         //      mask words are fetched first
@@ -1173,9 +1188,13 @@ __global__ void k_alive_list(const uint32_t *__restrict__ flags, const uint32_t 
 
 // Lane form limits: bands of up to 16 words (K <= 510) in registers, and
 // alphabets of up to 4 symbols (the windows of 64 lanes stay within LDS at a
-// few waves per CU).
+// few waves per CU).  With one lane per pair and bands of up to 8 words
+// (K <= 254), alphabets of up to 32 symbols: a lane's window of 33 rows of at
+// most 9 words, 76 KB per wave at the most (33 KB at K = 100 over 25 letters).
 constexpr uint32_t LANE_MAX_WORDS = 16;
 constexpr uint32_t LANE_MAX_SIGMA = 4;
+constexpr uint32_t LANE_WIDE_WORDS = 8;
+constexpr uint32_t LANE_WIDE_SIGMA = 32;
 
 using LaneKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint32_t *,
                             uint32_t, const uint32_t *, uint32_t, uint32_t, uint32_t *, int32_t *,
@@ -1207,6 +1226,20 @@ using SplitKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const u
                              uint32_t, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *,
                              int32_t *, unsigned long long *);
 constexpr uint32_t SPLIT_MAX_WPL = 8;
+
+LaneKernel lane_kernel_wide(uint32_t nw) {
+    switch (nw) {
+        case 1: return k_verify_lane<1, LANE_WIDE_SIGMA>;
+        case 2: return k_verify_lane<2, LANE_WIDE_SIGMA>;
+        case 3: return k_verify_lane<3, LANE_WIDE_SIGMA>;
+        case 4: return k_verify_lane<4, LANE_WIDE_SIGMA>;
+        case 5: return k_verify_lane<5, LANE_WIDE_SIGMA>;
+        case 6: return k_verify_lane<6, LANE_WIDE_SIGMA>;
+        case 7: return k_verify_lane<7, LANE_WIDE_SIGMA>;
+        case 8: return k_verify_lane<8, LANE_WIDE_SIGMA>;
+        default: return nullptr;
+    }
+}
 
 SplitKernel split_kernel(uint32_t wpl) {
     switch (wpl) {
@@ -1356,16 +1389,23 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     };
     // the lane family: KL lanes per pair (1: the whole band in one lane)
     uint32_t KL = ctx->tune.verify_split;
-    if (KL == 0) KL = NL <= 4 ? 1u : NL <= 8 ? 2u : 4u;
+    // (the split lanes take alphabets of up to 4 symbols; larger ones use one
+    // lane per pair up to 8 band words)
+    if (KL == 0)
+        KL = (NL <= 4 || (sig > LANE_MAX_SIGMA && NL <= LANE_WIDE_WORDS)) ? 1u : NL <= 8 ? 2u : 4u;
     while (KL > 1 && KL / 2 >= NL) KL /= 2;  // no lane without a word of the band
     const uint32_t WPL = (NL + KL - 1) / KL;
     const uint32_t NWf = KL * WPL;
     const bool lane_ok = KL == 1 ? NL <= LANE_MAX_WORDS : WPL <= SPLIT_MAX_WPL;
-    if (ctx->tune.verify_mode == 2 && lane_ok && sig <= LANE_MAX_SIGMA &&
+    // alphabets above 4 symbols: one lane per pair with up to 8 band words
+    const bool wide = sig > LANE_MAX_SIGMA && KL == 1 && NWf <= LANE_WIDE_WORDS &&
+                      sig <= LANE_WIDE_SIGMA;
+    if (ctx->tune.verify_mode == 2 && lane_ok && (sig <= LANE_MAX_SIGMA || wide) &&
         (int)((64 / KL) * ((sig + 1) * (NWf + 4) + 12) * 4) <= ctx->lds_max) {
         // lane form: KL lanes per pair, a device-wide pair counter
         ctx->last_verify_form = KL == 1 ? 2 : 3;
-        const void *kf = KL == 1 ? (const void *)lane_kernel(NWf) : (const void *)split_kernel(WPL);
+        const LaneKernel lk = wide ? lane_kernel_wide(NWf) : lane_kernel(NWf);
+        const void *kf = KL == 1 ? (const void *)lk : (const void *)split_kernel(WPL);
         // split tiles: rows of NW+1 words rounded up to a multiple of 4, then
         // the text block (8 words)
         const uint32_t region =
@@ -1395,7 +1435,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
             EJ_CHECK_LAUNCH();
             if (KL == 1)
-                hipLaunchKernelGGL(lane_kernel(NWf), dim3((uint32_t)grid), dim3(64), llds,
+                hipLaunchKernelGGL(lk, dim3((uint32_t)grid), dim3(64), llds,
                                    ctx->stream, A, B, d_pairs, (uint32_t)count, d_order, K, d_Kq,
                                    sig, region, next, d_dist, d_columns);
             else

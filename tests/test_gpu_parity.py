@@ -535,6 +535,40 @@ def test_result_left_on_the_device(ej, ctx, oracle_lib):
     assert none.pairs.shape == (none.count, 2)
 
 
+@pytest.mark.parametrize("letters,K", [("protein", 0), ("protein", 31), ("protein", 100),
+                                       ("protein", 254), ("protein", 300), ("wide", 63),
+                                       ("wide", 160)])
+def test_lane_form_wide_alphabets(ej, ctx, oracle_lib, letters, K):
+    """The lane form (one pair per lane, band in registers) over 25 and 32
+    letters, band widths of 1 to 8 words (and beyond: the other forms take
+    over), equals the oracle's threshold distances."""
+    import torch
+    alpha = sd.PROTEIN25 if letters == "protein" else bytes(range(65, 97))
+    probs = sd.zipf_probs(25, 1.1) if letters == "protein" else None
+    col = sd.clusters(300 + K, 20, lambda rr, b: 5, lambda rr: rr.integers(0, 2 * K + 200),
+                      lambda rr, LL: rr.poisson(max(1, K // 3)), letters=alpha, probs=probs)
+    rng = np.random.default_rng(K + 1)
+    a = rng.integers(0, col.n, size=500)
+    b = rng.integers(0, col.n, size=500)
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+    chars, offs = to_device(col)
+    old = ctx.knobs()
+    try:
+        ctx.tune_set("verify_mode", 2)
+        ctx.tune_set("verify_split", 0)
+        _say(f"lane form {letters} K={K}")
+        got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+        assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+        res = ctx.join(chars, offs, K, 3, 5, 4, seed=2, L=64, flags=ej.FLAG_TIMING)
+        _assert_join_equal(res, _oracle_join(oracle_lib, col, K, 3, 5, 4, 2, 64))
+        if K <= 254 and res.n_candidates:
+            assert res.verify_form == 2
+    finally:
+        for k, v in old.items():
+            ctx.tune_set(k, v)
+
+
 def test_graph_replays_match_eager(ej, ctx, oracle_lib):
     """Persistent verification (both forms) captured into a HIP graph: the
     first join captures, later joins of the same shape replay it, with eager
