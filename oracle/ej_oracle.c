@@ -788,6 +788,86 @@ int ejo_join_grouped(const uint8_t *chars, const uint64_t *offsets, uint32_t n, 
     return rc;
 }
 
+/* --------------------------------------------- exhaustive short strings -- */
+
+/* Short strings.  The paper observes that LSH filtering suits long strings and
+ * that short ones may call for another filter; with a threshold K that is large
+ * next to a string's length, random strings of such lengths are within K of
+ * each other by chance and no embedding brings them together.  This pass adds,
+ * for S > 0, every pair (i, j), i < j, whose strings are both no longer than S
+ * and whose lengths differ by at most K (the length filter: ED >= the length
+ * difference) to the candidates of `res` -- a result of the EmbedJoin,
+ * EmbedJoin+ or grouping join over the same strings -- verifies the union
+ * (Section 3.3, Ukkonen's band) and replaces res's candidates, their distances
+ * and its output.  n_raw keeps the tables' count.  S = 0 leaves res as it is.
+ * Returns 0, or -1 when an allocation fails. */
+int ejo_exact_short(const uint8_t *chars, const uint64_t *offsets, uint32_t n, uint32_t K,
+                    uint32_t S, ejo_result *res) {
+    if (S == 0) return 0;
+    uint32_t *sid = (uint32_t *)malloc(sizeof(uint32_t) * (n ? n : 1));
+    if (!sid) return -1;
+    uint32_t ns = 0;
+    for (uint32_t i = 0; i < n; i++)
+        if (offsets[i + 1] - offsets[i] <= S) sid[ns++] = i;
+    uint64_t extra = 0;
+    for (uint32_t a = 0; a < ns; a++)
+        for (uint32_t b = a + 1; b < ns; b++) {
+            const uint64_t la = offsets[sid[a] + 1] - offsets[sid[a]];
+            const uint64_t lb = offsets[sid[b] + 1] - offsets[sid[b]];
+            if ((la > lb ? la - lb : lb - la) <= K) extra++;
+        }
+    const uint64_t tot = res->n_cand + extra;
+    uint64_t *u = (uint64_t *)malloc(sizeof(uint64_t) * (tot ? tot : 1));
+    if (!u) {
+        free(sid);
+        return -1;
+    }
+    uint64_t t = 0;
+    for (uint64_t e = 0; e < res->n_cand; e++) u[t++] = res->cand[e];
+    for (uint32_t a = 0; a < ns; a++)
+        for (uint32_t b = a + 1; b < ns; b++) {
+            const uint64_t la = offsets[sid[a] + 1] - offsets[sid[a]];
+            const uint64_t lb = offsets[sid[b] + 1] - offsets[sid[b]];
+            if ((la > lb ? la - lb : lb - la) <= K) u[t++] = ((uint64_t)sid[a] << 32) | sid[b];
+        }
+    free(sid);
+    qsort(u, tot, sizeof(uint64_t), cmp_u64);
+    uint64_t nu = 0;
+    for (uint64_t e = 0; e < tot; e++)
+        if (e == 0 || u[e] != u[e - 1]) u[nu++] = u[e];
+    uint32_t *cd = (uint32_t *)malloc(sizeof(uint32_t) * (nu ? nu : 1));
+    uint64_t *op = (uint64_t *)malloc(sizeof(uint64_t) * (nu ? nu : 1));
+    uint32_t *od = (uint32_t *)malloc(sizeof(uint32_t) * (nu ? nu : 1));
+    if (!cd || !op || !od) {
+        free(u);
+        free(cd);
+        free(op);
+        free(od);
+        return -1;
+    }
+    uint64_t no = 0;
+    for (uint64_t e = 0; e < nu; e++) {
+        const uint32_t a = (uint32_t)(u[e] >> 32), b = (uint32_t)u[e];
+        cd[e] = ejo_ed_banded(chars + offsets[a], (uint32_t)(offsets[a + 1] - offsets[a]),
+                              chars + offsets[b], (uint32_t)(offsets[b + 1] - offsets[b]), K);
+        if (cd[e] <= K) {
+            op[no] = u[e];
+            od[no++] = cd[e];
+        }
+    }
+    free(res->cand);
+    free(res->cand_dist);
+    free(res->out);
+    free(res->out_dist);
+    res->cand = u;
+    res->n_cand = nu;
+    res->cand_dist = cd;
+    res->out = op;
+    res->out_dist = od;
+    res->n_out = no;
+    return 0;
+}
+
 /* ------------------------------------------- distortion diagnostics ---- */
 
 /* Section 3.1 (distortion of the CGK embedding) and Section 6 (normalised

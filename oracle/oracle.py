@@ -113,6 +113,9 @@ def lib():
         L.ejo_keys.argtypes = [u8p, u64p, ctypes.c_uint32, u8p, u64p, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                ctypes.c_uint32, ctypes.c_uint64, u64p]
+        L.ejo_exact_short.restype = ctypes.c_int
+        L.ejo_exact_short.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_uint32, ctypes.POINTER(_Result)]
         L.ejo_brute_join.restype = ctypes.c_uint64
         L.ejo_brute_join.argtypes = [u8p, u64p, ctypes.c_uint32, ctypes.c_uint32,
                                      u64p, u32p, ctypes.c_uint64, ctypes.c_int]
@@ -250,10 +253,21 @@ class JoinResult:
         return self.pairs(self.out)
 
 
+def _exact_short(c, off, n, K, S, res):
+    """ejo_exact_short on a result in place (S = 0: nothing)."""
+    if S and lib().ejo_exact_short(_ptr(c, ctypes.c_uint8) if c.size else None,
+                                   _ptr(off, ctypes.c_uint64), n, K, S, ctypes.byref(res)) != 0:
+        lib().ejo_result_free(ctypes.byref(res))
+        raise MemoryError("oracle short-string pass: allocation failed")
+
+
 def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
-         explicit_R=None, explicit_pos=None, explicit_v=None, opts: int = 0) -> JoinResult:
+         explicit_R=None, explicit_pos=None, explicit_v=None, opts: int = 0,
+         exact_len: int = 0) -> JoinResult:
     """The oracle's EmbedJoin.  opts: STOP_AFTER_CANDIDATES (the candidate set
-    only, `cand_dist`/`out` empty), NO_SIG (no sampled symbols kept)."""
+    only, `cand_dist`/`out` empty), NO_SIG (no sampled symbols kept).
+    exact_len > 0 adds every pair of strings no longer than exact_len whose
+    lengths differ by at most K to the candidates (ejo_exact_short)."""
     c = _u8(chars)
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     n = off.shape[0] - 1
@@ -271,6 +285,7 @@ def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int =
         raise ValueError("all 256 byte values occur: no code is left for the padding symbol")
     if rc != 0:
         raise ValueError(f"oracle join rejected its arguments (rc={rc})")
+    _exact_short(c, off, n, K, exact_len, res)
     try:
         return JoinResult(res, n, r, z, m)
     finally:
@@ -286,7 +301,7 @@ def plus_default_T(K: int, delta: int) -> int:
 
 
 def join_plus(chars, offsets, K: int, r: int, z: int, m: int, delta: int, T: int = 0,
-              seed: int = 0, L: int = 0, opts: int = 0) -> JoinResult:
+              seed: int = 0, L: int = 0, opts: int = 0, exact_len: int = 0) -> JoinResult:
     """The oracle's EmbedJoin+ (Algorithms 4-5): ceil(K/delta) suffixes per
     string, a pair is a candidate when one of its suffix pairs collides in at
     least T tables (T = 0: 2 if there is more than one suffix, else 1).
@@ -304,6 +319,7 @@ def join_plus(chars, offsets, K: int, r: int, z: int, m: int, delta: int, T: int
         raise ValueError("all 256 byte values occur: no code is left for the padding symbol")
     if rc != 0:
         raise ValueError(f"oracle join_plus rejected its arguments (rc={rc})")
+    _exact_short(c, off, n, K, exact_len, res)
     try:
         return JoinResult(res, n, r, z, m, key_cols=n * plus_kappa(K, delta))
     finally:
@@ -311,7 +327,7 @@ def join_plus(chars, offsets, K: int, r: int, z: int, m: int, delta: int, T: int
 
 
 def join_grouped(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0,
-                 L: int = 0) -> JoinResult:
+                 L: int = 0, exact_len: int = 0) -> JoinResult:
     """The oracle's grouping variant (Section 4.1): EmbedJoin on each length
     group ((g)K, (g+2)K] on its own (L = 3 x the group's longest string unless
     L > 0), the union of the groups' candidates and outputs."""
@@ -324,6 +340,7 @@ def join_grouped(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0,
                                 ctypes.byref(res))
     if rc != 0:
         raise ValueError(f"oracle join_grouped rejected its arguments (rc={rc})")
+    _exact_short(c, off, n, K, exact_len, res)
     try:
         return JoinResult(res, n, r, z, m, key_cols=0)
     finally:

@@ -80,6 +80,33 @@ static int check_join(uint32_t n, uint32_t maxlen, uint32_t sigma, uint32_t K, u
     uint32_t *qd = (uint32_t *)malloc(sizeof(uint32_t) * cap);
     if (ejo_query(chars, off, n, chars, off, n, Kq, r, z, m, L, seed, qoff, qid, qd, cap) < 0)
         bad = 1;
+    /* every string short: the exact join */
+    ejo_result c3;
+    if (ejo_join(chars, off, n, K, r, z, m, L, seed, NULL, NULL, NULL, &c3) != 0 ||
+        ejo_exact_short(chars, off, n, K, 0xFFFFFFFFu, &c3) != 0 || c3.n_out != nb)
+        bad = 1;
+    ejo_brute_join(chars, off, n, K, bp, bd, cap, 0);
+    for (uint64_t i = 0; i < c3.n_out && !bad; i++)
+        bad = c3.out[i] != bp[i] || c3.out_dist[i] != bd[i];
+    ejo_result_free(&c3);
+    /* EmbedJoin+ and grouping, each with the short-string pass */
+    ejo_result c4, c5;
+    if (ejo_join_plus(chars, off, n, K, r, z, m, L, seed, 3, ejo_plus_default_T(K, 3), 0, &c4) != 0 ||
+        ejo_exact_short(chars, off, n, K, 5, &c4) != 0)
+        bad = 1;
+    ejo_result_free(&c4);
+    if (ejo_join_grouped(chars, off, n, K, r, z, m, L, seed, &c5) != 0 ||
+        ejo_exact_short(chars, off, n, K, 7, &c5) != 0)
+        bad = 1;
+    ejo_result_free(&c5);
+    /* embedding Hamming distances of the candidates, and keys of the set */
+    uint32_t *ham = (uint32_t *)malloc(sizeof(uint32_t) * (res.n_cand * r + 1));
+    if (ejo_embed_hamming(chars, off, n, r, L, seed, K, 4, res.cand, res.n_cand, ham) != 0)
+        bad = 1;
+    free(ham);
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * ((uint64_t)r * z * n + 1));
+    if (ejo_keys(chars, off, n, chars, off, n, r, z, m, L, seed, keys) != 0) bad = 1;
+    free(keys);
     free(vd);
     free(Kq);
     free(qoff);

@@ -805,3 +805,63 @@ def test_grouping_with_one_group_is_the_join_untruncated(oracle_lib):
     a = oracle_lib.join(col.chars, col.offsets, K, 2, 3, 6, seed=1, L=3 * N)
     assert g.cand.tolist() == a.cand.tolist() and g.n_raw == a.n_raw
     assert g.out.tolist() == a.out.tolist()
+
+
+# ------------------------------------------------- exhaustive short strings --
+
+def _short_mix(seed):
+    """Clusters of mixed lengths (some strings of a few letters, some empty)
+    whose short members are within a large K of each other by chance."""
+    return sd.clusters(seed, 14, lambda rr, b: rr.integers(1, 4),
+                       lambda rr: rr.integers(0, 120), lambda rr, LL: rr.poisson(3))
+
+
+@pytest.mark.parametrize("seed,K", [(0, 30), (1, 0), (2, 60)])
+def test_exact_short_above_every_length_is_the_exact_join(oracle_lib, seed, K):
+    """With every string short, the candidates are all pairs that pass the
+    length filter, so the output is the exact join: it equals brute force by
+    textbook Wagner-Fischer, for the EmbedJoin, EmbedJoin+ and grouping
+    results alike."""
+    col = _short_mix(seed)
+    N = int(col.lengths().max())
+    truth, tdist = oracle_lib.brute_join(col.chars, col.offsets, K, full=True)
+    for res in (oracle_lib.join(col.chars, col.offsets, K, 2, 2, 6, seed=seed, exact_len=N),
+                oracle_lib.join_plus(col.chars, col.offsets, K, 2, 2, 6, delta=20, seed=seed,
+                                     exact_len=N),
+                oracle_lib.join_grouped(col.chars, col.offsets, K, 2, 2, 6, seed=seed,
+                                        exact_len=N)):
+        assert res.out.tolist() == truth.tolist()
+        assert res.out_dist.tolist() == tdist.tolist()
+        lens = col.lengths().astype(np.int64)
+        n_len_ok = sum(1 for a in range(col.n) for b in range(a + 1, col.n)
+                       if abs(lens[a] - lens[b]) <= K)
+        assert len(res.cand) == n_len_ok
+
+
+def test_exact_short_off_leaves_the_join(oracle_lib):
+    col = _short_mix(4)
+    a = oracle_lib.join(col.chars, col.offsets, 40, 2, 3, 5, seed=3)
+    b = oracle_lib.join(col.chars, col.offsets, 40, 2, 3, 5, seed=3, exact_len=0)
+    assert a.cand.tolist() == b.cand.tolist() and a.out.tolist() == b.out.tolist()
+    assert a.n_raw == b.n_raw
+
+
+@pytest.mark.parametrize("S", [1, 25, 70])
+def test_exact_short_is_the_join_plus_every_short_true_pair(oracle_lib, S):
+    """Between the extremes: the output is the LSH join's output united with
+    every true pair (brute force) whose strings are both no longer than S,
+    and nothing else; the tables' raw count is unchanged."""
+    col = _short_mix(5)
+    K = 45
+    base = oracle_lib.join(col.chars, col.offsets, K, 2, 3, 5, seed=7)
+    res = oracle_lib.join(col.chars, col.offsets, K, 2, 3, 5, seed=7, exact_len=S)
+    truth, tdist = oracle_lib.brute_join(col.chars, col.offsets, K, full=True)
+    lens = col.lengths()
+    a = (truth >> np.uint64(32)).astype(np.int64)
+    b = (truth & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    short_true = truth[(lens[a] <= S) & (lens[b] <= S)]
+    want = np.union1d(base.out, short_true)
+    assert res.out.tolist() == want.tolist()
+    assert res.out_dist.tolist() == tdist[np.isin(truth, want)].tolist()
+    assert res.n_raw == base.n_raw
+    assert np.isin(base.cand, res.cand).all()
