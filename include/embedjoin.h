@@ -83,6 +83,16 @@ typedef struct {
     uint32_t L;      /* truncation length, 0 = ceil(average length) */
     uint32_t flags;  /* EJ_FLAG_* */
     uint64_t seed;   /* seed of the counter-based random streams */
+    uint32_t exact_len; /* 0, or S > 0: every pair of strings both no longer than S
+                           whose lengths differ by at most K joins the candidates
+                           as well (an exhaustive pass over the short strings, for
+                           which the paper notes LSH filtering is a poor fit: with K
+                           large next to their length, random short strings are
+                           within K of each other by chance).  Output pairs among
+                           such strings are then exact.  Applies to ej_join*,
+                           ej_join_plus* and ej_join_grouped*; fails with
+                           EJ_EUNSUPPORTED when the union would reach 2^32 pairs */
+    uint32_t reserved; /* 0 */
 } ej_params;
 
 typedef struct {
@@ -341,6 +351,11 @@ typedef struct {
     uint32_t nL;
     double target_recall;    /* the predicted recall the chosen point must reach */
     uint64_t seed;           /* the seed the join will use */
+    uint32_t exact_len;      /* the join's ej_params.exact_len: a sample pair whose strings
+                                are both no longer than it is a candidate with certainty
+                                (in the recall, and in the false rate and work, where it
+                                adds the same amount at every grid point); 0: no short pass */
+    uint32_t reserved;       /* 0 */
 } ej_calib_opts;
 
 typedef struct {

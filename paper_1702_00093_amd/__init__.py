@@ -46,7 +46,8 @@ class EmbedJoinError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_uint32), ("r", ctypes.c_uint32), ("z", ctypes.c_uint32),
                 ("m", ctypes.c_uint32), ("L", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("exact_len", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class _Result(ctypes.Structure):
@@ -67,7 +68,8 @@ class CalibOpts(ctypes.Structure):
                 ("nz", ctypes.c_uint32), ("m_list", ctypes.POINTER(ctypes.c_uint32)),
                 ("nm", ctypes.c_uint32), ("L_list", ctypes.POINTER(ctypes.c_uint32)),
                 ("nL", ctypes.c_uint32), ("target_recall", ctypes.c_double),
-                ("seed", ctypes.c_uint64)]
+                ("seed", ctypes.c_uint64), ("exact_len", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class CalibResult(ctypes.Structure):
@@ -290,23 +292,28 @@ class Context:
 
     # ----------------------------------------------------------- the join --
     def join(self, chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
-             flags: int = 0) -> JoinResult:
+             flags: int = 0, exact_len: int = 0) -> JoinResult:
         """EmbedJoin self-join.  Host inputs (bytes / numpy / CPU tensors) go
         through ej_join_ex; CUDA tensors (uint8 chars, int64 offsets) go
-        through ej_join_device."""
-        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), None)
+        through ej_join_device.  exact_len > 0: every pair of strings no
+        longer than exact_len whose lengths differ by at most K is a
+        candidate too."""
+        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed, exact_len), None)
 
     def join_plus(self, chars, offsets, K: int, r: int, z: int, m: int, delta: int = 0,
-                  T: int = 0, seed: int = 0, L: int = 0, flags: int = 0) -> JoinResult:
+                  T: int = 0, seed: int = 0, L: int = 0, flags: int = 0,
+                  exact_len: int = 0) -> JoinResult:
         """EmbedJoin+ (ej_join_plus / ej_join_plus_device): ceil(K/delta)
         suffixes per string, tuple threshold T (0: the paper's rule)."""
-        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), (delta, T))
+        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed, exact_len),
+                          (delta, T))
 
     def join_grouped(self, chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0,
-                     L: int = 0, flags: int = 0) -> JoinResult:
+                     L: int = 0, flags: int = 0, exact_len: int = 0) -> JoinResult:
         """EmbedJoin with grouping instead of truncation (ej_join_grouped /
         ej_join_grouped_device)."""
-        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed), "grouped")
+        return self._join(chars, offsets, Params(K, r, z, m, L, flags, seed, exact_len),
+                          "grouped")
 
     def _join(self, chars, offsets, p, plus) -> JoinResult:
         res = _Result()
@@ -474,7 +481,7 @@ class Context:
 
     def calibrate(self, d_chars, d_offsets, d_pairs, K: int, r_max: int, z_list, m_list,
                   L_list, target_recall: float = 0.99, seed: int = 0, delta: int = 0, T: int = 0,
-                  want_table: bool = False):
+                  want_table: bool = False, exact_len: int = 0):
         """ej_calibrate: returns a dict with the chosen (r, z, m, L) and its
         predictions (and the whole grid as an array [nL, r_max, nz, nm, 3]
         when want_table)."""
@@ -486,7 +493,7 @@ class Context:
         u32p = ctypes.POINTER(ctypes.c_uint32)
         o = CalibOpts(K, delta, T, r_max, zs.ctypes.data_as(u32p), len(zs),
                       ms.ctypes.data_as(u32p), len(ms), Ls.ctypes.data_as(u32p), len(Ls),
-                      float(target_recall), seed)
+                      float(target_recall), seed, exact_len, 0)
         res = CalibResult()
         table = np.zeros((len(Ls), r_max, len(zs), len(ms), 3)) if want_table else None
         _torch_stream_done()
@@ -628,8 +635,9 @@ def context(device: int = 0) -> Context:
 
 
 def join(chars, offsets, K: int, r: int, z: int, m: int, seed: int = 0, L: int = 0,
-         flags: int = 0, device: int = 0) -> JoinResult:
-    return context(device).join(chars, offsets, K, r, z, m, seed=seed, L=L, flags=flags)
+         flags: int = 0, device: int = 0, exact_len: int = 0) -> JoinResult:
+    return context(device).join(chars, offsets, K, r, z, m, seed=seed, L=L, flags=flags,
+                                exact_len=exact_len)
 
 
 def version() -> int:

@@ -108,6 +108,7 @@ ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_of
         for (uint32_t i = 0; i < o->nm; i++)
             if (o->m_list[i] == 0 || o->m_list[i] > 64) fail(EJ_EINVAL, "m must be in 1..64");
         if (n >= 0x80000000u) fail(EJ_EINVAL, "n must be below 2^31");
+        if (o->reserved != 0) fail(EJ_EINVAL, "ej_calib_opts.reserved must be 0");
         const bool plus = o->delta != 0;
         const uint32_t kappa =
             plus ? std::max<uint32_t>(1u, (uint32_t)((o->K + (uint64_t)o->delta - 1) / o->delta))
@@ -128,6 +129,20 @@ ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_of
             EJ_HIP(hipMemcpyAsync(dist.data(), d_dist, 4 * count, hipMemcpyDeviceToHost,
                                   ctx->stream));
             sync(ctx);
+        }
+        // sample pairs the short pass (exact_len) makes candidates with certainty
+        std::vector<char> certain(count, 0);
+        if (o->exact_len && count) {
+            std::vector<uint32_t> len(n);
+            std::vector<uint64_t> pr(count);
+            EJ_HIP(hipMemcpyAsync(len.data(), pp.d_len, 4ull * n, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            EJ_HIP(hipMemcpyAsync(pr.data(), d_pairs, 8 * count, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            sync(ctx);
+            for (uint64_t e = 0; e < count; e++)
+                certain[e] = len[pr[e] >> 32] <= o->exact_len &&
+                             len[(uint32_t)pr[e]] <= o->exact_len;
         }
         std::vector<char> similar(count);
         for (uint64_t e = 0; e < count; e++) {
@@ -185,7 +200,7 @@ ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_of
                                 add_seed(dp, nx, bin, z, T, q[r - 1]);
                                 pc = dp[T];
                             }
-                            (similar[e] ? rec : fal)[r - 1] += pc;
+                            (similar[e] ? rec : fal)[r - 1] += certain[e] ? 1.0 : pc;
                         }
                     }
                     for (uint32_t r = 1; r <= R; r++) {

@@ -143,6 +143,70 @@ __global__ void k_map_pairs(const uint64_t *__restrict__ pairs, uint64_t cnt,
     }
 }
 
+// ---- exhaustive pass over short strings
+//
+// The paper notes that LSH filtering suits long strings and that short ones
+// may want another filter.  When K is large next to a string's length, random
+// strings of such lengths are within K of each other by chance, and no
+// embedding brings them into one bucket.  With ej_params.exact_len = S > 0,
+// every pair of strings both no longer than S whose lengths differ by at most
+// K (the length filter) joins the candidates.  In length order the short
+// strings are a prefix of the permutation, and string i pairs with the run of
+// following strings whose lengths are within K of its own.
+
+__global__ void k_sorted_lengths(const uint32_t *__restrict__ len, const uint32_t *__restrict__ perm,
+                                 uint32_t n, uint32_t *__restrict__ ls) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        ls[i] = len[perm[i]];
+}
+
+// first position in ls[lo, hi) (ascending) holding a value above x
+__device__ inline uint32_t upper_bound_u32(const uint32_t *ls, uint32_t lo, uint32_t hi,
+                                           uint64_t x) {
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo) / 2;
+        if ((uint64_t)ls[mid] <= x)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// *ns = the number of strings no longer than S (one thread)
+__global__ void k_short_count(const uint32_t *__restrict__ ls, uint32_t n, uint32_t S,
+                              uint64_t *__restrict__ ns) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ns = upper_bound_u32(ls, 0, n, S);
+}
+
+// row[i] = the number of partners of short string i among the later ones
+__global__ void k_short_rows(const uint32_t *__restrict__ ls, uint32_t ns, uint32_t K,
+                             uint64_t *__restrict__ row) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x)
+        row[i] = upper_bound_u32(ls, i + 1, ns, (uint64_t)ls[i] + K) - (i + 1);
+}
+
+// the P pairs, (lo << 32) | hi, row by row: output e belongs to the last row
+// starting at or before e (start = exclusive prefix of the row counts)
+__global__ void k_short_emit(const uint32_t *__restrict__ perm, const uint64_t *__restrict__ start,
+                             uint32_t ns, uint64_t P, uint64_t *__restrict__ out) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < P;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = ns;  // first row starting after e, minus one
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (start[mid] <= e)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        const uint32_t i = lo - 1;
+        const uint32_t j = i + 1 + (uint32_t)(e - start[i]);
+        const uint32_t a = perm[i], b = perm[j];
+        out[e] = a < b ? ((uint64_t)a << 32) | b : ((uint64_t)b << 32) | a;
+    }
+}
+
 void check_params(const ej_params &p, uint32_t n) {
     if (p.r == 0 || p.z == 0 || p.m == 0) fail(EJ_EINVAL, "r, z and m must be positive");
     if (p.m > 64) fail(EJ_EINVAL, "m must be at most 64");
@@ -150,6 +214,7 @@ void check_params(const ej_params &p, uint32_t n) {
     if (n >= 0x80000000u) fail(EJ_EINVAL, "n must be below 2^31");
     if (p.K > 0x7FFFFFFFu) fail(EJ_EINVAL, "K must be below 2^31");
     if (verify_lanes_for(p.K) == 0) fail(EJ_EUNSUPPORTED, "K above 2046 is not supported");
+    if (p.reserved != 0) fail(EJ_EINVAL, "ej_params.reserved must be 0");
 }
 
 struct StageTimer {
@@ -309,6 +374,53 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
 }
 
 
+// The candidates united with the short strings' pairs (exact_len = S > 0):
+// returns the count of the sorted, distinct union at *out; with no short pair
+// the candidates are returned as they are.
+uint64_t add_short_pairs(ej_ctx *ctx, const Prep &pp, uint32_t K, uint32_t S,
+                         const uint64_t *pairs, uint64_t cnt, const uint64_t **out) {
+    *out = pairs;
+    const uint32_t n = pp.n;
+    if (S == 0 || n < 2) return cnt;
+    uint32_t *ls = ws<uint32_t>(ctx, "sh_len", n);
+    hipLaunchKernelGGL(k_sorted_lengths, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
+                       (const uint32_t *)pp.d_len, (const uint32_t *)pp.d_perm, n, ls);
+    EJ_CHECK_LAUNCH();
+    uint64_t *d_tot = ws<uint64_t>(ctx, "sh_total", 2);
+    hipLaunchKernelGGL(k_short_count, dim3(1), dim3(64), 0, ctx->stream, (const uint32_t *)ls, n,
+                       S, d_tot);
+    EJ_CHECK_LAUNCH();
+    uint64_t ns = 0;
+    read_back(ctx, d_tot, 8, &ns);
+    if (ns < 2) return cnt;
+    uint64_t *row = ws<uint64_t>(ctx, "sh_rows", ns);
+    hipLaunchKernelGGL(k_short_rows, dim3(grid_for(ctx, ns, 256)), dim3(256), 0, ctx->stream,
+                       (const uint32_t *)ls, (uint32_t)ns, K, row);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u64(ctx, row, row, ns, d_tot + 1);
+    uint64_t P = 0;
+    read_back(ctx, d_tot + 1, 8, &P);
+    if (P == 0) return cnt;
+    const uint64_t tot = cnt + P;
+    if (tot >= 0xFFFFFFFFull)
+        fail(EJ_EUNSUPPORTED, "more than 2^32 candidates with the short strings' pairs (" +
+                                  std::to_string(tot) + ")");
+    uint64_t *uni = ws<uint64_t>(ctx, "sh_union", tot);
+    if (cnt)
+        EJ_HIP(hipMemcpyAsync(uni, pairs, 8 * cnt, hipMemcpyDeviceToDevice, ctx->stream));
+    hipLaunchKernelGGL(k_short_emit, dim3(grid_for(ctx, P, 256)), dim3(256), 0, ctx->stream,
+                       (const uint32_t *)pp.d_perm, (const uint64_t *)row, (uint32_t)ns, P,
+                       uni + cnt);
+    EJ_CHECK_LAUNCH();
+    uint64_t *sorted = ws<uint64_t>(ctx, "sh_sorted", tot);
+    radix_sort_u64(ctx, uni, sorted, tot, 32 + std::max(1u, bits_for(n - 1)),
+                   ctx->tune.radix_bits);
+    uint64_t *u = nullptr;
+    const uint64_t c = unique_sorted_pairs(ctx, sorted, tot, 32, &u, "sh");
+    *out = u;
+    return c;
+}
+
 // The whole path on device-resident strings.
 void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
                  const ej_params &p, ej_result *out) {
@@ -340,8 +452,10 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     uint32_t *order = nullptr;
     const bool want_order = ctx->tune.verify_mode >= 1 && ctx->tune.verify_order == 1;
     uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j",
-                              want_order ? &order : nullptr);
-    finish_join(ctx, pp, d_offsets, p, rd, n, pairs, cnt, raw, order, tm, out);
+                              want_order && !p.exact_len ? &order : nullptr);
+    const uint64_t *cp = pairs;
+    cnt = add_short_pairs(ctx, pp, p.K, p.exact_len, pairs, cnt, &cp);
+    finish_join(ctx, pp, d_offsets, p, rd, n, cp, cnt, raw, order, tm, out);
 }
 
 // Suffix step and threshold of EmbedJoin+ (Section 5): delta = 0 selects
@@ -413,9 +527,10 @@ void join_plus_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
     tm.mark();  // 3
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
-    const uint64_t cnt =
-        candidates_plus(ctx, keys, bk, flen, p.K, n, kappa, T, &pairs, &raw, "p");
-    finish_join(ctx, pp, d_offsets, p, rd, ne64, pairs, cnt, raw, nullptr, tm, out);
+    uint64_t cnt = candidates_plus(ctx, keys, bk, flen, p.K, n, kappa, T, &pairs, &raw, "p");
+    const uint64_t *cp = pairs;
+    cnt = add_short_pairs(ctx, pp, p.K, p.exact_len, pairs, cnt, &cp);
+    finish_join(ctx, pp, d_offsets, p, rd, ne64, cp, cnt, raw, nullptr, tm, out);
 }
 
 void check_pairs(ej_ctx *ctx, const uint64_t *d_pairs, uint64_t count, uint32_t n_a,
@@ -537,8 +652,10 @@ void join_grouped_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_
                        ctx->tune.radix_bits);
         cnt = unique_sorted_pairs(ctx, sorted, ucount, 32, &pairs, "grp");
     }
+    const uint64_t *cp = pairs;
+    cnt = add_short_pairs(ctx, pp, p.K, p.exact_len, pairs, cnt, &cp);
     Rand none;
-    finish_join(ctx, pp, d_offsets, p, none, 0, pairs, cnt, raw, nullptr, tm, out);
+    finish_join(ctx, pp, d_offsets, p, none, 0, cp, cnt, raw, nullptr, tm, out);
 }
 
 // ej_verify's work: preparation of the strings, their match masks and the

@@ -167,3 +167,33 @@ def test_calibration_plus_lower_bound(ej, ctx, oracle_lib):
     found = np.isin(pcodes, res.codes).mean()
     _say(f"plus predicted {tab[0, 5, 1, 0, 0]:.4f} measured on the sample {found:.4f}")
     assert found >= tab[0, 5, 1, 0, 0] - 0.05
+
+
+def test_calibration_with_short_pass(ej, ctx, oracle_lib):
+    """exact_len: sample pairs whose strings are both no longer than it count
+    as candidates with certainty; the others keep the closed form."""
+    import torch
+    col = sd.clusters(9, 30, lambda rr, b: 3, lambda rr: rr.integers(30, 400),
+                      lambda rr, LL: rr.poisson(0.05 * LL))
+    rng = np.random.default_rng(9)
+    codes = _sample_pairs(col, rng, 150, 250)
+    chars, offs = to_device(col)
+    dp = torch.from_numpy(codes.astype(np.int64)).cuda()
+    K, S, zl, ml, Ll = 60, 150, [4, 8], [6, 12], [64]
+    cal = ctx.calibrate(chars, offs, dp, K, 4, zl, ml, Ll, target_recall=0.9, seed=2,
+                        want_table=True, exact_len=S)
+    d = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+    sim = d <= K
+    lens = col.lengths()
+    a = (codes >> np.uint64(32)).astype(np.int64)
+    b = (codes & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    short = (lens[a] <= S) & (lens[b] <= S)
+    assert short.any() and (~short).any()
+    ham = oracle_lib.embed_hamming(col.chars, col.offsets, codes, 4, L=64,
+                                   seed=2).astype(np.float64)
+    for r in (1, 4):
+        for zi, z in enumerate(zl):
+            for mi, m in enumerate(ml):
+                pc = np.where(short, 1.0, _closed_form(ham, 64, r, z, m))
+                assert abs(cal["table"][0, r - 1, zi, mi, 0] - pc[sim].mean()) < 1e-9
+                assert abs(cal["table"][0, r - 1, zi, mi, 1] - pc[~sim].mean()) < 1e-9
