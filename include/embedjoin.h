@@ -62,10 +62,16 @@ typedef enum {
 
 /* Flags of ej_params.flags */
 #define EJ_FLAG_PLAIN 0u   /* one launch per stage, host-sized buffers */
-#define EJ_FLAG_GRAPH 1u   /* with a persistent verification form ("verify_mode" 1 or 2):
-                            its launches are captured once into a HIP graph, cached in
-                            the context by launch arguments and replayed by later joins
-                            of the same shape */
+#define EJ_FLAG_GRAPH 1u   /* the join after its preparation (A1-A6) sized on the device
+                            and replayed from a HIP graph cached in the context per input
+                            shape (buffers, sizes, alphabet, longest string, parameters,
+                            knobs): the first join of a shape runs host-sized and sets the
+                            candidate capacities, the second allocates every buffer at
+                            them, later ones replay the graph; a count above a capacity
+                            redoes the join host-sized and grows it.  With EJ_FLAG_TIMING,
+                            or exact_len, only the persistent verification forms
+                            ("verify_mode" 1 or 2) are captured, as a graph of their own.
+                            Results are identical either way. */
 #define EJ_FLAG_TIMING 2u  /* record per-stage device times in ej_result */
 #define EJ_FLAG_DEVICE_OUT 4u /* leave the result in device memory: out->pairs and
                                out->dist are device pointers into the context's
@@ -126,6 +132,11 @@ typedef struct {
     uint32_t verify_form;
     /* 1 when pairs and dist are device pointers (EJ_FLAG_DEVICE_OUT) */
     uint32_t on_device;
+    /* How the join ran (EJ_FLAG_GRAPH without EJ_FLAG_TIMING): 0 sized on the
+     * host (stage by stage, sizes read back between stages), 1 sized on the
+     * device but not captured (the run that allocates the buffers of a new
+     * shape), 2 replayed as one captured graph of A1-A6. */
+    uint32_t graph;
 } ej_result;
 
 /* ---------------------------------------------------------------- lifecycle */
@@ -267,12 +278,15 @@ ej_status ej_embed(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offset
                    uint32_t *sigma);
 
 /* A3: bucketing (the hash tables D_j^l of Algorithm 3).  Each of the
- * `ntables` tables (keys laid out [ntables][n]) is sorted by (the top
- * `key_bits` bits of the key, string length, position) with a stable
- * on-device LSD radix sort; key_bits in 1..32, 0 picks the default.
- * Entries whose top key bits agree form a group; a group contains one or
- * more whole buckets (distinct full keys sharing their top bits are rare
- * and are told apart by ej_candidates).
+ * `ntables` tables (keys laid out [ntables][n]) is sorted with a stable
+ * on-device LSD radix sort:
+ *   key_bits = 0: by (full key, string length, position); each group is
+ *                 exactly one bucket D_j^l[key], its strings in length order;
+ *   key_bits in 1..32: by (the top key_bits bits of the key, length,
+ *                 position); a group then holds one or more whole buckets
+ *                 (distinct full keys that share their top bits, rare with
+ *                 enough bits), which ej_candidates tells apart by the full
+ *                 key -- fewer sort passes, the form the join itself uses.
  *   d_len          [n] uint32 string lengths
  *   d_ids_sorted   [ntables][n] uint32 positions in sorted order
  *   d_group_start  capacity ntables*n + 1 uint32: index (into the

@@ -59,7 +59,8 @@ class _Result(ctypes.Structure):
                 ("ms_verify", ctypes.c_float), ("ms_output", ctypes.c_float),
                 ("walk_steps", ctypes.c_uint64), ("verify_columns", ctypes.c_uint64),
                 ("ms_verify_kernel", ctypes.c_float), ("verify_launches", ctypes.c_uint32),
-                ("verify_form", ctypes.c_uint32), ("on_device", ctypes.c_uint32)]
+                ("verify_form", ctypes.c_uint32), ("on_device", ctypes.c_uint32),
+                ("graph", ctypes.c_uint32)]
 
 
 class CalibOpts(ctypes.Structure):
@@ -223,6 +224,7 @@ class JoinResult:
     verify_form: int = 0       # 0 two-pass, 1 persistent groups, 2 one pair per lane, 3 split
     pairs_device: object = None
     dist_device: object = None
+    graph: int = 0             # 0 host-sized, 1 device-sized uncaptured, 2 graph replay
 
     @property
     def pairs(self) -> np.ndarray:       # [count, 2] int64
@@ -374,7 +376,8 @@ class Context:
             return JoinResult(ph, dh, int(res.n_candidates), int(res.n_raw),
                               int(res.sigma), int(res.L), ms, int(res.walk_steps),
                               int(res.verify_columns), float(res.ms_verify_kernel),
-                              int(res.verify_launches), int(res.verify_form), pd, dd)
+                              int(res.verify_launches), int(res.verify_form), pd, dd,
+                              int(res.graph))
         finally:
             lib().ej_result_free(ctypes.byref(res))
 

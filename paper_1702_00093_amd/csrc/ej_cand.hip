@@ -46,7 +46,21 @@ __global__ void k_bucket_gather(const uint64_t *__restrict__ keys,
     }
 }
 
-__global__ void k_group_flags(const uint32_t *__restrict__ dk, uint32_t n, uint64_t tot,
+// Full keys of every table in length order, for exact buckets.
+__global__ void k_bucket_gather_full(const uint64_t *__restrict__ keys,
+                                     const uint32_t *__restrict__ perm, uint32_t n, uint64_t tot,
+                                     uint64_t *__restrict__ fk, uint32_t *__restrict__ ids) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < tot;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t t = e / n;
+        const uint32_t id = perm[(uint32_t)(e - t * n)];
+        fk[e] = keys[t * n + id];
+        ids[e] = id;
+    }
+}
+
+template <typename D>
+__global__ void k_group_flags(const D *__restrict__ dk, uint32_t n, uint64_t tot,
                               uint32_t *__restrict__ flags) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < tot;
          e += (uint64_t)gridDim.x * blockDim.x) {
@@ -56,7 +70,8 @@ __global__ void k_group_flags(const uint32_t *__restrict__ dk, uint32_t n, uint6
 }
 
 // gid[e] = inclusive group index; gstart[g] = first entry of group g.
-__global__ void k_group_starts(const uint32_t *__restrict__ dk, uint32_t n, uint64_t tot,
+template <typename D>
+__global__ void k_group_starts(const D *__restrict__ dk, uint32_t n, uint64_t tot,
                                const uint32_t *__restrict__ gexcl, uint32_t *__restrict__ gid,
                                uint32_t *__restrict__ gstart, const uint64_t *__restrict__ ngroups) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < tot;
@@ -212,7 +227,7 @@ __global__ void __launch_bounds__(256)
                const uint32_t *__restrict__ len_s, const uint32_t *__restrict__ ids, uint32_t n,
                uint32_t tot, uint32_t K, Coder coder, uint32_t *__restrict__ tcount,
                uint64_t *__restrict__ wg_count, const uint64_t *__restrict__ wg_off,
-               C *__restrict__ out) {
+               C *__restrict__ out, uint64_t cap) {
     __shared__ uint64_t red[4];
     const uint32_t x = threadIdx.x, lane = x & 63, wave = x >> 6;
     const uint64_t base = (uint64_t)blockIdx.x * PW_TILE;
@@ -262,7 +277,10 @@ __global__ void __launch_bounds__(256)
     __syncthreads();
     uint64_t o = wg_off[blockIdx.x] + incl - v;
     for (uint32_t w = 0; w < wave; w++) o += red[w];
-    if (v == 0) return;
+    // a buffer sized on the host before the count (a join sized on the
+    // device) may be too small: nothing past `cap` is written, and the host
+    // sees the count and redoes the join
+    if (v == 0 || o + v > cap) return;
 #pragma unroll
     for (uint32_t i = 0; i < PW_IPT; i++)
         if (act & (1u << i))
@@ -403,10 +421,13 @@ constexpr uint32_t DD_CHUNK = 16384;
 
 template <typename C>
 __global__ void __launch_bounds__(256)
-    k_group_count(const C *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
-                  uint32_t *__restrict__ hist) {
+    k_group_count(const C *__restrict__ codes, uint32_t n, const uint64_t *__restrict__ n_dev,
+                  uint32_t shift, uint32_t NG, uint32_t *__restrict__ hist) {
     __shared__ uint32_t cnt[1u << DD_GBITS];
     const uint32_t wg = blockIdx.x, nwg = gridDim.x;
+    // a count on the device: past n the buffer holds unwritten entries, so
+    // then nothing is grouped (the host sees the count and redoes the join)
+    if (n_dev) n = *n_dev > n ? 0u : (uint32_t)*n_dev;
     for (uint32_t g = threadIdx.x; g < NG; g += 256) cnt[g] = 0;
     __syncthreads();
     const uint32_t b = wg * DD_CHUNK, e = min(n, b + DD_CHUNK);
@@ -418,10 +439,12 @@ __global__ void __launch_bounds__(256)
 
 template <typename C>
 __global__ void __launch_bounds__(256)
-    k_group_place(const C *__restrict__ codes, uint32_t n, uint32_t shift, uint32_t NG,
-                  const uint32_t *__restrict__ offs, uint32_t *__restrict__ out) {
+    k_group_place(const C *__restrict__ codes, uint32_t n, const uint64_t *__restrict__ n_dev,
+                  uint32_t shift, uint32_t NG, const uint32_t *__restrict__ offs,
+                  uint32_t *__restrict__ out) {
     __shared__ uint32_t cur[1u << DD_GBITS];
     const uint32_t wg = blockIdx.x, nwg = gridDim.x;
+    if (n_dev) n = *n_dev > n ? 0u : (uint32_t)*n_dev;  // as in k_group_count
     for (uint32_t g = threadIdx.x; g < NG; g += 256) cur[g] = offs[(uint64_t)g * nwg + wg];
     __syncthreads();
     const uint32_t b = wg * DD_CHUNK, e = min(n, b + DD_CHUNK);
@@ -434,7 +457,9 @@ __global__ void __launch_bounds__(256)
 
 // First position of group g: the scanned count of its first chunk.
 __global__ void k_group_first(const uint32_t *__restrict__ offs, uint32_t nwg, uint32_t NG,
-                              uint32_t n, uint32_t *__restrict__ gstart) {
+                              uint32_t n, const uint64_t *__restrict__ n_dev,
+                              uint32_t *__restrict__ gstart) {
+    if (n_dev) n = *n_dev > n ? 0u : (uint32_t)*n_dev;  // as in k_group_count
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g <= NG; g += gridDim.x * blockDim.x)
         gstart[g] = g < NG ? offs[(uint64_t)g * nwg] : n;
 }
@@ -445,9 +470,12 @@ __global__ void k_group_first(const uint32_t *__restrict__ offs, uint32_t nwg, u
 __global__ void k_dedup_out(const uint32_t *__restrict__ ucode, const uint32_t *__restrict__ umult,
                             const uint32_t *__restrict__ ucount, const uint32_t *__restrict__ uoff,
                             uint32_t B, uint32_t shift, uint64_t *__restrict__ out,
-                            uint32_t *__restrict__ mult) {
+                            uint32_t *__restrict__ mult, uint64_t cap) {
     const uint32_t g = blockIdx.x;
-    const uint32_t m = ucount[g], o = uoff[g];
+    const uint32_t o = uoff[g];
+    // nothing past `cap` (a buffer sized before the count; the host redoes
+    // the join when the count exceeds it)
+    const uint32_t m = o >= cap ? 0u : (uint32_t)min<uint64_t>(ucount[g], cap - o);
     const uint64_t mask = (1ull << B) - 1ull;
     for (uint32_t i = threadIdx.x; i < m; i += blockDim.x) {
         const uint64_t c = ((uint64_t)g << shift) | ucode[(uint64_t)g * DD_UCAP + i];
@@ -458,11 +486,14 @@ __global__ void k_dedup_out(const uint32_t *__restrict__ ucode, const uint32_t *
 
 // Order key of unique pair u from its multiplicity (see k_mult_keys).
 __global__ void k_mult_keys_direct(const uint32_t *__restrict__ mult, uint64_t cnt,
-                                   uint32_t cap, uint32_t *__restrict__ key,
-                                   uint32_t *__restrict__ idx) {
+                                   const uint64_t *__restrict__ cnt_dev, uint32_t cap,
+                                   uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+    // with a count on the device, the entries past it get the key cap, which
+    // no real pair has (m >= 1): a stable sort leaves them behind all real ones
+    const uint64_t live = cnt_dev ? min(*cnt_dev, cnt) : cnt;
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < cnt;
          u += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t m = mult[u];
+        const uint32_t m = u < live ? mult[u] : 0u;
         key[u] = cap - (m < cap ? m : cap);
         idx[u] = (uint32_t)u;
     }
@@ -541,15 +572,54 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
     }
     uint32_t *flags = ws<uint32_t>(ctx, t + "_flags", tot);
     uint64_t *d_ng = ws<uint64_t>(ctx, t + "_ngroups", 1);
-    hipLaunchKernelGGL(k_group_flags, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
-                       (const uint32_t *)dk2, n, tot, flags);
+    hipLaunchKernelGGL(k_group_flags<uint32_t>, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                       ctx->stream, (const uint32_t *)dk2, n, tot, flags);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u32(ctx, flags, flags, tot, d_ng);
-    hipLaunchKernelGGL(k_group_starts, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
-                       (const uint32_t *)dk2, n, tot, (const uint32_t *)flags, bk.d_gid,
-                       bk.d_gstart, (const uint64_t *)d_ng);
+    hipLaunchKernelGGL(k_group_starts<uint32_t>, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                       ctx->stream, (const uint32_t *)dk2, n, tot, (const uint32_t *)flags,
+                       bk.d_gid, bk.d_gstart, (const uint64_t *)d_ng);
     EJ_CHECK_LAUNCH();
     if (want_ngroups) read_back(ctx, d_ng, 8, &bk.ngroups);
+}
+
+void bucket_exact(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_perm, uint32_t n,
+                  uint32_t T, Buckets &bk, const char *tag) {
+    std::string t(tag);
+    bk.T = T;
+    bk.n = n;
+    bk.d_dk = nullptr;
+    bk.ngroups = 0;
+    const uint64_t tot = (uint64_t)T * n;
+    if (tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
+    bk.d_ids = ws<uint32_t>(ctx, t + "_ids", tot);
+    bk.d_gid = ws<uint32_t>(ctx, t + "_gid", tot);
+    bk.d_gstart = ws<uint32_t>(ctx, t + "_gstart", tot + 1);
+    if (tot == 0) {
+        uint32_t zero = 0;
+        EJ_HIP(hipMemcpyAsync(bk.d_gstart, &zero, 4, hipMemcpyHostToDevice, ctx->stream));
+        sync(ctx);
+        return;
+    }
+    uint64_t *fk = ws<uint64_t>(ctx, t + "_fk", tot);
+    uint64_t *fk2 = ws<uint64_t>(ctx, t + "_fk2", tot);
+    uint32_t *ids0 = ws<uint32_t>(ctx, t + "_ids0", tot);
+    hipLaunchKernelGGL(k_bucket_gather_full, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                       ctx->stream, d_keys, d_perm, n, tot, fk, ids0);
+    EJ_CHECK_LAUNCH();
+    // keys are below 2^61; the stable sort keeps the length order within a key
+    radix_sort_u64_kv(ctx, fk, ids0, fk2, bk.d_ids, T, n, 61, ctx->tune.radix_bits);
+    uint32_t *flags = ws<uint32_t>(ctx, t + "_flags", tot);
+    uint64_t *d_ng = ws<uint64_t>(ctx, t + "_ngroups", 1);
+    hipLaunchKernelGGL(k_group_flags<uint64_t>, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                       ctx->stream, (const uint64_t *)fk2, n, tot, flags);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, flags, flags, tot, d_ng);
+    hipLaunchKernelGGL(k_group_starts<uint64_t>, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
+                       ctx->stream, (const uint64_t *)fk2, n, tot, (const uint32_t *)flags,
+                       bk.d_gid, bk.d_gstart, (const uint64_t *)d_ng);
+    EJ_CHECK_LAUNCH();
+    read_back(ctx, d_ng, 8, &bk.ngroups);
 }
 
 uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, const uint32_t *d_len,
@@ -585,7 +655,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                            ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
                            (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot,
                            K, PairCoder{B}, tcount, counts, (const uint64_t *)nullptr,
-                           (uint64_t *)nullptr);
+                           (uint64_t *)nullptr, (uint64_t)0);
         EJ_CHECK_LAUNCH();
         scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
     } else {
@@ -618,7 +688,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
                                ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
                                (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n,
                                (uint32_t)tot, K, PairCoder{B}, tcount, (uint64_t *)nullptr,
-                               (const uint64_t *)counts, rawbuf);
+                               (const uint64_t *)counts, rawbuf, raw);
             EJ_CHECK_LAUNCH();
             return;
         }
@@ -670,15 +740,17 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         uint32_t *ghist = ws<uint32_t>(ctx, t + "_dd_hist", (uint64_t)NG * nwg);
         uint32_t *gst = ws<uint32_t>(ctx, t + "_dd_gstart", NG + 1);
         hipLaunchKernelGGL(k_group_count<C>, dim3(nwg), dim3(256), 0, ctx->stream,
-                           (const C *)rawbuf, (uint32_t)raw, shift, NG, ghist);
+                           (const C *)rawbuf, (uint32_t)raw, (const uint64_t *)nullptr, shift, NG,
+                           ghist);
         EJ_CHECK_LAUNCH();
         scan_exclusive_u32(ctx, ghist, ghist, (uint64_t)NG * nwg, nullptr);
         hipLaunchKernelGGL(k_group_place<C>, dim3(nwg), dim3(256), 0, ctx->stream,
-                           (const C *)rawbuf, (uint32_t)raw, shift, NG, (const uint32_t *)ghist,
-                           part);
+                           (const C *)rawbuf, (uint32_t)raw, (const uint64_t *)nullptr, shift, NG,
+                           (const uint32_t *)ghist, part);
         EJ_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_group_first, dim3((NG + 256) / 256), dim3(256), 0, ctx->stream,
-                           (const uint32_t *)ghist, nwg, NG, (uint32_t)raw, gst);
+                           (const uint32_t *)ghist, nwg, NG, (uint32_t)raw,
+                           (const uint64_t *)nullptr, gst);
         EJ_CHECK_LAUNCH();
         uint32_t *ucode = ws<uint32_t>(ctx, t + "_dd_code", (uint64_t)NG * DD_UCAP);
         uint32_t *umult = ws<uint32_t>(ctx, t + "_dd_mult", (uint64_t)NG * DD_UCAP);
@@ -699,12 +771,13 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         uint32_t *mult = d_order_out ? ws<uint32_t>(ctx, t + "_mult", cnt) : nullptr;
         hipLaunchKernelGGL(k_dedup_out, dim3(NG), dim3(256), 0, ctx->stream,
                            (const uint32_t *)ucode, (const uint32_t *)umult, (const uint32_t *)ucnt,
-                           (const uint32_t *)uoff, B, shift, pairs, mult);
+                           (const uint32_t *)uoff, B, shift, pairs, mult, cnt);
         EJ_CHECK_LAUNCH();
         *d_pairs_out = pairs;
         if (d_order_out && cnt) {
             hipLaunchKernelGGL(k_mult_keys_direct, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)mult, cnt, mult_cap,
+                               ctx->stream, (const uint32_t *)mult, cnt,
+                               (const uint64_t *)nullptr, mult_cap,
                                ws<uint32_t>(ctx, t + "_okey", cnt),
                                ws<uint32_t>(ctx, t + "_oidx", cnt));
             EJ_CHECK_LAUNCH();
@@ -736,6 +809,119 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         *d_order_out = order;
     }
     return cnt;
+}
+
+__global__ void k_zero_u64(uint64_t *__restrict__ p, uint32_t n) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// The candidate stage of a join sized on the device (the whole join captured
+// as one graph, so nothing may be read back between its kernels): the kernels
+// of candidates() with the raw pairs written into a buffer of raw_cap entries
+// and the distinct pairs into one of cnt_cap, and the counts left in device
+// memory: cnt_dev[0] = raw pairs, cnt_dev[1] = distinct pairs, cnt_dev[2] =
+// nonzero when a group of the de-duplication held more distinct codes than it
+// takes.  A count above its capacity, or that flag, makes the result invalid:
+// the caller reads the counts after the join and redoes it.  Only the grouped
+// de-duplication (2B <= DD_GBITS + 31).
+void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
+                    const uint32_t *d_len, uint32_t K, uint64_t raw_cap, uint64_t cnt_cap,
+                    bool want_order, uint64_t *cnt_dev, uint64_t **d_pairs_out,
+                    uint32_t **d_order_out, const char *tag) {
+    std::string t(tag);
+    const uint32_t n = bk.n;
+    const uint64_t tot = (uint64_t)bk.T * n;
+    if (tot == 0 || n < 2 || !bk.d_dk) fail(EJ_EINVAL, "candidates_dev: no tables");
+    if (raw_cap >= 0xFFFFFFFFull || cnt_cap >= 0xFFFFFFFFull || tot >= 0xFFFFFFFFull)
+        fail(EJ_EUNSUPPORTED, "candidates_dev: capacities must stay below 2^32");
+    const uint32_t B = std::max(1u, bits_for(n - 1));
+    if (2 * B > DD_GBITS + 31) fail(EJ_EUNSUPPORTED, "candidates_dev: codes too wide");
+    const uint32_t mult_bits = std::max(1u, bits_for(bk.T));
+    const uint32_t mult_cap = mult_bits >= 32 ? 0xFFFFFFFFu : (1u << mult_bits) - 1u;
+    uint64_t *key_s = ws<uint64_t>(ctx, t + "_key_s", tot);
+    uint32_t *len_s = ws<uint32_t>(ctx, t + "_len_s", tot);
+    const uint32_t nwg = (uint32_t)((tot + PW_TILE - 1) / PW_TILE);
+    uint32_t *tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
+    uint64_t *counts = ws<uint64_t>(ctx, t + "_counts", nwg);
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, cnt_dev + 2, 1u);
+    EJ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_sorted_attrs_dk, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
+                       d_keys, (const uint32_t *)bk.d_ids, d_len, (const uint32_t *)bk.d_dk, n,
+                       (uint32_t)tot, key_s, len_s);
+    EJ_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, PairCoder>), dim3(nwg), dim3(256), 0,
+                       ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                       (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K,
+                       PairCoder{B}, tcount, counts, (const uint64_t *)nullptr,
+                       (uint64_t *)nullptr, (uint64_t)0);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u64(ctx, counts, counts, nwg, cnt_dev);
+    const uint32_t GB = std::min(DD_GBITS, 2 * B);
+    const uint32_t NG = 1u << GB, shift = 2 * B - GB;
+    const uint32_t nwd = (uint32_t)((raw_cap + DD_CHUNK - 1) / DD_CHUNK);
+    uint32_t *ghist = ws<uint32_t>(ctx, t + "_dd_hist", (uint64_t)NG * nwd);
+    uint32_t *gst = ws<uint32_t>(ctx, t + "_dd_gstart", NG + 1);
+    auto group = [&](auto *rawbuf, uint32_t *part) {
+        using C = std::remove_pointer_t<decltype(rawbuf)>;
+        hipLaunchKernelGGL((k_pairs_dk<true, C, PairCoder>), dim3(nwg), dim3(256), 0,
+                           ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                           (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot,
+                           K, PairCoder{B}, tcount, (uint64_t *)nullptr, (const uint64_t *)counts,
+                           rawbuf, raw_cap);
+        EJ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_group_count<C>, dim3(nwd), dim3(256), 0, ctx->stream,
+                           (const C *)rawbuf, (uint32_t)raw_cap, (const uint64_t *)cnt_dev, shift,
+                           NG, ghist);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, ghist, ghist, (uint64_t)NG * nwd, nullptr);
+        hipLaunchKernelGGL(k_group_place<C>, dim3(nwd), dim3(256), 0, ctx->stream,
+                           (const C *)rawbuf, (uint32_t)raw_cap, (const uint64_t *)cnt_dev, shift,
+                           NG, (const uint32_t *)ghist, part);
+        EJ_CHECK_LAUNCH();
+    };
+    uint32_t *part = nullptr;
+    if (2 * B <= 32) {
+        uint32_t *raw32 = ws<uint32_t>(ctx, t + "_raw32", raw_cap);
+        part = ws<uint32_t>(ctx, t + "_raw32_sorted", raw_cap);
+        group(raw32, part);
+    } else {
+        uint64_t *raw64 = ws<uint64_t>(ctx, t + "_raw", raw_cap);
+        part = (uint32_t *)ws<uint64_t>(ctx, t + "_raw_sorted", raw_cap);
+        group(raw64, part);
+    }
+    hipLaunchKernelGGL(k_group_first, dim3((NG + 256) / 256), dim3(256), 0, ctx->stream,
+                       (const uint32_t *)ghist, nwd, NG, (uint32_t)raw_cap,
+                       (const uint64_t *)cnt_dev, gst);
+    EJ_CHECK_LAUNCH();
+    uint32_t *ucode = ws<uint32_t>(ctx, t + "_dd_code", (uint64_t)NG * DD_UCAP);
+    uint32_t *umult = ws<uint32_t>(ctx, t + "_dd_mult", (uint64_t)NG * DD_UCAP);
+    uint32_t *ucnt = ws<uint32_t>(ctx, t + "_dd_count", NG);
+    uint32_t *uoff = ws<uint32_t>(ctx, t + "_dd_off", NG);
+    hipLaunchKernelGGL(k_dedup_groups, dim3(NG), dim3(256), 0, ctx->stream, (const uint32_t *)part,
+                       (const uint32_t *)gst, ucode, umult, ucnt, (uint32_t *)(cnt_dev + 2));
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, ucnt, uoff, NG, cnt_dev + 1);
+    uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt_cap);
+    uint32_t *mult = want_order ? ws<uint32_t>(ctx, t + "_mult", cnt_cap) : nullptr;
+    hipLaunchKernelGGL(k_dedup_out, dim3(NG), dim3(256), 0, ctx->stream, (const uint32_t *)ucode,
+                       (const uint32_t *)umult, (const uint32_t *)ucnt, (const uint32_t *)uoff, B,
+                       shift, pairs, mult, cnt_cap);
+    EJ_CHECK_LAUNCH();
+    *d_pairs_out = pairs;
+    *d_order_out = nullptr;
+    if (want_order) {
+        uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt_cap);
+        uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt_cap);
+        uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", cnt_cap);
+        uint32_t *order = ws<uint32_t>(ctx, t + "_order", cnt_cap);
+        hipLaunchKernelGGL(k_mult_keys_direct, dim3(grid_for(ctx, cnt_cap, 256)), dim3(256), 0,
+                           ctx->stream, (const uint32_t *)mult, cnt_cap,
+                           (const uint64_t *)(cnt_dev + 1), mult_cap, k0, v0);
+        EJ_CHECK_LAUNCH();
+        radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt_cap, mult_bits, 11);
+        *d_order_out = order;
+    }
 }
 
 // EmbedJoin+ candidates (Algorithm 5): the bucketed entries are suffixes
@@ -771,7 +957,8 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, TupleCoder>), dim3(nwg), dim3(256), 0,
                        ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
                        (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K,
-                       coder, tcount, counts, (const uint64_t *)nullptr, (uint64_t *)nullptr);
+                       coder, tcount, counts, (const uint64_t *)nullptr, (uint64_t *)nullptr,
+                       (uint64_t)0);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
     uint64_t raw = 0;
@@ -785,7 +972,7 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     hipLaunchKernelGGL((k_pairs_dk<true, uint64_t, TupleCoder>), dim3(nwg), dim3(256), 0,
                        ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
                        (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K,
-                       coder, tcount, (uint64_t *)nullptr, (const uint64_t *)counts, tup);
+                       coder, tcount, (uint64_t *)nullptr, (const uint64_t *)counts, tup, raw);
     EJ_CHECK_LAUNCH();
     radix_sort_u64(ctx, tup, sorted, raw, 2 * B + 2 * KB, ctx->tune.radix_bits);
     uint32_t *flags = ws<uint32_t>(ctx, t + "_tflags", raw);

@@ -72,6 +72,11 @@ void *ws_get(ej_ctx *ctx, const std::string &name, size_t bytes) {
     if (ctx->arena.base) return arena_get(ctx, name, bytes);
     DevBuf &b = ctx->ws[name];
     if (b.bytes < bytes) {
+        // a captured graph holds the addresses of the buffers it uses: no
+        // buffer may move while a capture is open
+        if (ctx->capturing)
+            fail(EJ_EHIP, "workspace buffer '" + name + "' would grow inside a graph capture");
+        ctx->ws_gen++;
         if (b.p) {
             EJ_HIP(hipStreamSynchronize(ctx->stream));
             EJ_HIP(hipFree(b.p));
@@ -98,7 +103,9 @@ size_t ws_capacity(ej_ctx *ctx, const std::string &name) {
 void sync(ej_ctx *ctx) { EJ_HIP(hipStreamSynchronize(ctx->stream)); }
 
 void run_captured(ej_ctx *ctx, const std::string &key, const std::function<void()> &enqueue) {
-    if (!ctx->graph_on) {
+    // inside an open capture (a whole join being captured) the launches
+    // become part of that graph
+    if (!ctx->graph_on || ctx->capturing) {
         enqueue();
         return;
     }
@@ -110,13 +117,16 @@ void run_captured(ej_ctx *ctx, const std::string &key, const std::function<void(
         }
         hipGraph_t g = nullptr;
         EJ_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+        ctx->capturing = true;
         try {
             enqueue();
         } catch (...) {
+            ctx->capturing = false;
             (void)hipStreamEndCapture(ctx->stream, &g);
             if (g) (void)hipGraphDestroy(g);
             throw;
         }
+        ctx->capturing = false;
         EJ_HIP(hipStreamEndCapture(ctx->stream, &g));
         hipGraphExec_t ge = nullptr;
         hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);

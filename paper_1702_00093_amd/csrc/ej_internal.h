@@ -112,6 +112,19 @@ struct Tuning {
 };
 }  // namespace ej
 
+namespace ej {
+// Capacities of a join sized on the device (EJ_FLAG_GRAPH): raw and distinct
+// candidate pairs; gen = the workspace generation after the last uncaptured
+// run at these capacities (a capture needs every buffer to exist already);
+// no_graph = the shape needs the host-sized path (its de-duplication
+// overflows the grouped form).
+struct JoinCaps {
+    uint64_t raw_cap = 0, cnt_cap = 0;
+    uint64_t gen = ~0ull;
+    bool no_graph = false;
+};
+}  // namespace ej
+
 struct ej_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -131,6 +144,11 @@ struct ej_ctx {
     // argument of their launches (pointers included), replayed on a match
     bool graph_on = false;
     std::map<std::string, hipGraphExec_t> graphs;
+    bool capturing = false;    // a graph capture is open on the stream
+    uint64_t ws_gen = 0;       // workspace (re)allocations so far
+    // joins sized on the device, per input shape: the capacities of their
+    // candidate buffers and the workspace generation they were allocated in
+    std::map<std::string, ej::JoinCaps> join_caps;
     uint32_t last_verify_form = 0;  // form of the last verification launched
 };
 
@@ -185,6 +203,10 @@ void scan_exclusive_u64(ej_ctx *ctx, const uint64_t *d_in, uint64_t *d_out, uint
 void radix_sort_u32(ej_ctx *ctx, uint32_t *keys_in, uint32_t *vals_in, uint32_t *keys_out,
                     uint32_t *vals_out, uint32_t nseg, uint32_t seglen, uint32_t key_bits,
                     uint32_t digit_bits);
+// 64-bit keys with 32-bit values, nseg segments of seglen entries sorted each
+void radix_sort_u64_kv(ej_ctx *ctx, uint64_t *keys_in, uint32_t *vals_in, uint64_t *keys_out,
+                       uint32_t *vals_out, uint32_t nseg, uint32_t seglen, uint32_t key_bits,
+                       uint32_t digit_bits);
 void radix_sort_u64(ej_ctx *ctx, uint64_t *keys_in, uint64_t *keys_out, uint64_t n,
                     uint32_t key_bits, uint32_t digit_bits);
 
@@ -268,6 +290,18 @@ void bucket_inputs(ej_ctx *ctx, uint64_t tot, const char *tag, uint32_t **d_dk, 
 void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const uint32_t *d_perm,
             uint32_t n, uint32_t T, uint32_t key_bits, Buckets &bk, const char *tag,
             bool want_ngroups = false, bool inputs_ready = false, bool want_groups = true);
+// The candidate stage sized on the device (for a join captured as one graph):
+// raw pairs into raw_cap entries, distinct pairs into cnt_cap; counts left in
+// cnt_dev[0] (raw), [1] (distinct), [2] (nonzero: the grouped de-duplication
+// overflowed).  The result is valid only when both counts fit and [2] is 0.
+void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
+                    const uint32_t *d_len, uint32_t K, uint64_t raw_cap, uint64_t cnt_cap,
+                    bool want_order, uint64_t *cnt_dev, uint64_t **d_pairs_out,
+                    uint32_t **d_order_out, const char *tag);
+// Exact buckets: every table sorted by (full key, length, position), one group
+// per distinct key (d_gid, d_gstart and ngroups set).
+void bucket_exact(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_perm, uint32_t n,
+                  uint32_t T, Buckets &bk, const char *tag);
 
 // Candidate pairs as packed codes (a << 32 | b), a < b, sorted and unique.
 // Returns the count; *n_raw gets the pre-dedup count.
@@ -316,7 +350,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             uint64_t count, uint32_t K, const uint32_t *d_Kq, int32_t *d_dist,
             const uint8_t *d_codes_b = nullptr, const uint64_t *d_offsets_b = nullptr,
             uint64_t base_b = 0, uint32_t maxlen_b = 0, const RowMasks *masks_b = nullptr,
-            unsigned long long *d_columns = nullptr, const uint32_t *d_order = nullptr);
+            unsigned long long *d_columns = nullptr, const uint32_t *d_order = nullptr,
+            const uint64_t *d_count = nullptr);
 
 uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported
 

@@ -19,11 +19,14 @@ inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
     return (uint32_t)g;
 }
 
-__global__ void k_out_flags(const int32_t *__restrict__ dist, uint64_t cnt, uint32_t K,
+__global__ void k_out_flags(const int32_t *__restrict__ dist, uint64_t cnt,
+                            const uint64_t *__restrict__ cnt_dev, uint32_t K,
                             uint32_t *__restrict__ flags) {
+    // with a count on the device, entries past it hold no distance
+    const uint64_t live = cnt_dev ? min(*cnt_dev, cnt) : cnt;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (uint64_t)gridDim.x * blockDim.x)
-        flags[e] = (dist[e] >= 0 && (uint32_t)dist[e] <= K) ? 1u : 0u;
+        flags[e] = (e < live && dist[e] >= 0 && (uint32_t)dist[e] <= K) ? 1u : 0u;
 }
 
 __global__ void k_out_compact(const uint64_t *__restrict__ pairs, const int32_t *__restrict__ dist,
@@ -280,7 +283,7 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
         uint32_t *pos = ws<uint32_t>(ctx, "j_opos", cnt);
         uint64_t *d_no = ws<uint64_t>(ctx, "j_nout", 1);
         hipLaunchKernelGGL(k_out_flags, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0, ctx->stream,
-                           (const int32_t *)dist, cnt, p.K, flags);
+                           (const int32_t *)dist, cnt, (const uint64_t *)nullptr, p.K, flags);
         EJ_CHECK_LAUNCH();
         scan_exclusive_u32(ctx, flags, pos, cnt, d_no);
         read_back(ctx, d_no, 8, &nout);
@@ -421,6 +424,170 @@ uint64_t add_short_pairs(ej_ctx *ctx, const Prep &pp, uint32_t K, uint32_t S,
     return c;
 }
 
+// ---- the whole join as one graph (EJ_FLAG_GRAPH)
+//
+// After the preparation (whose read-back of the alphabet and lengths fixes
+// the launch shapes) the join A1-A6 runs sized on the device: its candidate
+// buffers have capacities taken from an earlier host-sized join of the same
+// input shape, every kernel after a count reads the count from device memory,
+// and only the counts come back at the end.  The first device-sized run of a
+// shape allocates every buffer at its capacity, uncaptured; later runs with
+// no buffer moved since are captured once into a graph, cached in the
+// context, and replayed.  A count above its capacity (or a de-duplication
+// group too large for the grouped form) voids the run: the join is redone
+// host-sized and the capacities grow.
+
+__global__ void k_join_counts(const uint64_t *__restrict__ c, uint64_t *__restrict__ out) {
+    if (blockIdx.x == 0 && threadIdx.x < 4) out[threadIdx.x] = c[threadIdx.x];
+}
+
+std::string join_shape(ej_ctx *ctx, const Prep &pp, const uint8_t *d_chars,
+                       const uint64_t *d_offsets, const ej_params &p) {
+    const Tuning &t = ctx->tune;
+    char key[512];
+    snprintf(key, sizeof(key),
+             "join %p %p %u %llu %llu %u %u %u %u %u %u %u %llu | %u %u %u %u %u %u %u %u %u %u",
+             (const void *)d_chars, (const void *)d_offsets, pp.n, (unsigned long long)pp.base,
+             (unsigned long long)pp.total, pp.sigma, pp.maxlen, pp.L, p.K, p.r, p.z, p.m,
+             (unsigned long long)p.seed, t.verify_mode, t.verify_order, t.verify_split,
+             t.verify_pass1_cols, t.verify_blocks_per_cu, t.verify_ring, t.verify_lds_budget,
+             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits);
+    return key;
+}
+
+// One device-sized join; returns false when its result is void (the caller
+// then runs the host-sized join, which also sets the capacities).
+bool join_graph(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_offsets,
+                const ej_params &p, const std::string &shape, JoinCaps &caps, ej_result *out) {
+    const uint32_t n = pp.n;
+    const uint32_t T = p.r * p.z;
+    const uint64_t raw_cap = caps.raw_cap, cnt_cap = caps.cnt_cap;
+    const bool want_order = ctx->tune.verify_mode >= 1 && ctx->tune.verify_order == 1;
+    uint64_t *cnt_dev = ws<uint64_t>(ctx, "jg_counts", 4);
+    uint64_t *cnt_out = ws<uint64_t>(ctx, "jg_counts_out", 4);
+    // results: pairs [2 * cnt_cap] u32, then distances [cnt_cap] (looked up
+    // here: a replay does not run the enqueue below)
+    uint32_t *opairs = ws<uint32_t>(ctx, "j_out", 3 * cnt_cap);
+    int32_t *odist = (int32_t *)(opairs + 2 * cnt_cap);
+    auto enqueue = [&] {
+        uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
+        const uint32_t kb = bucket_key_bits(ctx, n, 0);
+        uint32_t *bdk = nullptr, *bids = nullptr;
+        bucket_inputs(ctx, (uint64_t)T * n, "j", &bdk, &bids);
+        embed_keys(ctx, pp, rd, keys, nullptr, bdk, bids, 61u - kb);
+        Buckets bk;
+        bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true, false);
+        uint64_t *pairs = nullptr;
+        uint32_t *order = nullptr;
+        candidates_dev(ctx, keys, bk, pp.d_len, p.K, raw_cap, cnt_cap, want_order, cnt_dev,
+                       &pairs, &order, "j");
+        int32_t *dist = ws<int32_t>(ctx, "j_dist", cnt_cap);
+        RowMasks masks;
+        build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
+        verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, pairs, cnt_cap,
+               p.K, nullptr, dist, nullptr, nullptr, 0, 0, nullptr, nullptr, order, cnt_dev + 1);
+        uint32_t *flags = ws<uint32_t>(ctx, "j_oflags", cnt_cap);
+        uint32_t *pos = ws<uint32_t>(ctx, "j_opos", cnt_cap);
+        hipLaunchKernelGGL(k_out_flags, dim3(grid_for(ctx, cnt_cap, 256)), dim3(256), 0,
+                           ctx->stream, (const int32_t *)dist, cnt_cap,
+                           (const uint64_t *)(cnt_dev + 1), p.K, flags);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, flags, pos, cnt_cap, cnt_dev + 3);
+        hipLaunchKernelGGL(k_out_compact, dim3(grid_for(ctx, cnt_cap, 256)), dim3(256), 0,
+                           ctx->stream, (const uint64_t *)pairs, (const int32_t *)dist, cnt_cap,
+                           (const uint32_t *)flags, (const uint32_t *)pos, opairs, odist);
+        EJ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_join_counts, dim3(1), dim3(64), 0, ctx->stream,
+                           (const uint64_t *)cnt_dev, cnt_out);
+        EJ_CHECK_LAUNCH();
+    };
+    {
+        // graph mode applies to this join only; the verification inside runs
+        // as part of the outer launch sequence
+        struct Reset {
+            ej_ctx *c;
+            ~Reset() { c->graph_on = false; }
+        } reset{ctx};
+        if (caps.gen == ctx->ws_gen) {
+            char g[96];
+            snprintf(g, sizeof(g), " | %llu %llu %llu", (unsigned long long)raw_cap,
+                     (unsigned long long)cnt_cap, (unsigned long long)caps.gen);
+            ctx->graph_on = true;
+            out->graph = 2;
+            try {
+                run_captured(ctx, shape + g, enqueue);
+            } catch (const Error &) {
+                // the capture failed (an operation that cannot be captured):
+                // this shape runs host-sized from now on
+                (void)hipGetLastError();
+                caps.no_graph = true;
+                out->graph = 0;
+                return false;
+            }
+        } else {
+            // every buffer at its capacity, uncaptured: a later join of this
+            // shape can be captured without allocating
+            ctx->graph_on = false;
+            enqueue();
+            caps.gen = ctx->ws_gen;
+            out->graph = 1;
+        }
+    }
+    uint64_t c[4] = {0, 0, 0, 0};  // raw, distinct, overflow, output
+    read_back(ctx, cnt_out, sizeof(c), c);
+    if (c[2] != 0 || c[0] > raw_cap || c[1] > cnt_cap) out->graph = 0;
+    if (c[2] != 0) {
+        caps.no_graph = true;
+        return false;
+    }
+    if (c[0] > raw_cap || c[1] > cnt_cap) {
+        caps.raw_cap = std::max(raw_cap, c[0] + c[0] / 4 + 4096);
+        caps.cnt_cap = std::max(cnt_cap, c[1] + c[1] / 4 + 4096);
+        caps.gen = ~0ull;
+        return false;
+    }
+    const uint64_t nout = c[3];
+    out->n_raw = c[0];
+    out->n_candidates = c[1];
+    out->count = nout;
+    out->sigma = pp.sigma;
+    out->L = pp.L;
+    if (p.flags & EJ_FLAG_DEVICE_OUT) {
+        out->pairs = opairs;
+        out->dist = odist;
+        out->on_device = 1;
+        return true;
+    }
+    const size_t need = 12 * nout;
+    if (need && ctx->pinned_out_bytes < need) {
+        if (ctx->pinned_out) EJ_HIP(hipHostFree(ctx->pinned_out));
+        ctx->pinned_out = nullptr;
+        ctx->pinned_out_bytes = 0;
+        const size_t want = std::max<size_t>(need + need / 4, 1 << 20);
+        EJ_HIP(hipHostMalloc((void **)&ctx->pinned_out, want, hipHostMallocDefault));
+        ctx->pinned_out_bytes = want;
+    }
+    out->pairs = (uint32_t *)malloc(sizeof(uint32_t) * 2 * (nout ? nout : 1));
+    out->dist = (int32_t *)malloc(sizeof(int32_t) * (nout ? nout : 1));
+    if (!out->pairs || !out->dist) {
+        free(out->pairs);
+        free(out->dist);
+        out->pairs = nullptr;
+        out->dist = nullptr;
+        fail(EJ_ENOMEM, "host allocation of the result failed");
+    }
+    if (nout) {
+        EJ_HIP(hipMemcpyAsync(ctx->pinned_out, opairs, 8 * nout, hipMemcpyDeviceToHost,
+                              ctx->stream));
+        EJ_HIP(hipMemcpyAsync(ctx->pinned_out + 8 * nout, odist, 4 * nout,
+                              hipMemcpyDeviceToHost, ctx->stream));
+        sync(ctx);
+        memcpy(out->pairs, ctx->pinned_out, 8 * nout);
+        memcpy(out->dist, ctx->pinned_out + 8 * nout, 4 * nout);
+    }
+    return true;
+}
+
 // The whole path on device-resident strings.
 void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
                  const ej_params &p, ej_result *out) {
@@ -435,6 +602,19 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     Rand rd;
     draw_randomness(ctx, p, pp.L, pp.sigma, rd, "j");
     const uint32_t T = p.r * p.z;
+    // the whole join as one graph: not with stage timing (its events go
+    // between the stages) nor with the short-string pass
+    const bool as_graph = (p.flags & EJ_FLAG_GRAPH) != 0 && (p.flags & EJ_FLAG_TIMING) == 0 &&
+                          p.exact_len == 0 && n >= 2 &&
+                          2 * std::max(1u, bits_for(n - 1)) <= 42;
+    std::string shape;
+    if (as_graph) {
+        shape = join_shape(ctx, pp, d_chars, d_offsets, p);
+        auto it = ctx->join_caps.find(shape);
+        if (it != ctx->join_caps.end() && !it->second.no_graph &&
+            join_graph(ctx, pp, rd, d_offsets, p, shape, it->second, out))
+            return;
+    }
     uint64_t *keys = ws<uint64_t>(ctx, "j_keys", (uint64_t)T * n);
     tm.mark();  // 1: the walk kernel alone follows
     // the walk also writes the bucketing sort's input (top key bits and
@@ -456,6 +636,13 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     const uint64_t *cp = pairs;
     cnt = add_short_pairs(ctx, pp, p.K, p.exact_len, pairs, cnt, &cp);
     finish_join(ctx, pp, d_offsets, p, rd, n, cp, cnt, raw, order, tm, out);
+    if (as_graph) {
+        // capacities for the next join of this shape, with headroom
+        if (ctx->join_caps.size() >= 64) ctx->join_caps.clear();
+        JoinCaps &c = ctx->join_caps[shape];
+        c.raw_cap = std::max(c.raw_cap, raw + raw / 4 + 4096);
+        c.cnt_cap = std::max(c.cnt_cap, cnt + cnt / 4 + 4096);
+    }
 }
 
 // Suffix step and threshold of EmbedJoin+ (Section 5): delta = 0 selects
@@ -907,7 +1094,10 @@ ej_status ej_lsh_bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_l
             radix_sort_u32(ctx, lk, iota, lk2, perm, 1, n, bits_for(maxlen), 8);
         }
         Buckets bk;
-        bucket(ctx, d_keys, d_len, perm, n, ntables, key_bits, bk, "b", true);
+        if (key_bits == 0)
+            bucket_exact(ctx, d_keys, perm, n, ntables, bk, "b");
+        else
+            bucket(ctx, d_keys, d_len, perm, n, ntables, key_bits, bk, "b", true);
         uint64_t tot = (uint64_t)ntables * n;
         if (tot)
             EJ_HIP(hipMemcpyAsync(d_ids_sorted, bk.d_ids, 4 * tot, hipMemcpyDeviceToDevice,

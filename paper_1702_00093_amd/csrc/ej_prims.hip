@@ -414,6 +414,13 @@ void radix_sort_u32(ej_ctx *ctx, uint32_t *keys_in, uint32_t *vals_in, uint32_t 
                                          key_bits, digit_bits);
 }
 
+void radix_sort_u64_kv(ej_ctx *ctx, uint64_t *keys_in, uint32_t *vals_in, uint64_t *keys_out,
+                       uint32_t *vals_out, uint32_t nseg, uint32_t seglen, uint32_t key_bits,
+                       uint32_t digit_bits) {
+    radix_sort_impl<uint64_t, true>(ctx, keys_in, vals_in, keys_out, vals_out, nseg, seglen,
+                                    key_bits, digit_bits);
+}
+
 void radix_sort_u64(ej_ctx *ctx, uint64_t *keys_in, uint64_t *keys_out, uint64_t n,
                     uint32_t key_bits, uint32_t digit_bits) {
     if (n > 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "radix_sort_u64: more than 2^32 keys");

@@ -279,8 +279,9 @@ __global__ void __launch_bounds__(64)
              int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
     const uint32_t NL = lanes_of<MODE>(NL_arg);
-    // pass 2 takes its pair count from the device (a grid sized for all pairs)
-    const uint64_t count = count_dev ? *count_dev : count_arg;
+    // pass 2, and a join sized on the device, take the pair count from the
+    // device (a grid sized for all pairs; never more than count_arg)
+    const uint64_t count = count_dev ? min(*count_dev, count_arg) : count_arg;
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
@@ -411,12 +412,15 @@ __global__ void __launch_bounds__(64)
 template <int MODE, bool RING>
 __global__ void __launch_bounds__(64)
     k_verify_queue(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
-                   const uint32_t *__restrict__ order, uint32_t K,
+                   const uint64_t *__restrict__ count_dev, const uint32_t *__restrict__ order,
+                   uint32_t K,
                    const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t NL_arg, uint32_t tpw,
                    uint32_t wpp, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                    unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
     const uint32_t NL = lanes_of<MODE>(NL_arg);
+    // a count on the device (a join sized on the device): at most `count`
+    if (count_dev) count = (uint32_t)min<uint64_t>(*count_dev, count);
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
@@ -665,11 +669,13 @@ __device__ inline uint32_t readlane_u32(uint32_t x, uint32_t L) {
 template <int NW, int SIGMAX>
 __global__ void __launch_bounds__(64)
     k_verify_lane(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
-                  const uint32_t *__restrict__ order, uint32_t K, const uint32_t *__restrict__ Kq,
-                  uint32_t sigma, uint32_t region, uint32_t *__restrict__ next,
-                  int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
+                  const uint64_t *__restrict__ count_dev, const uint32_t *__restrict__ order,
+                  uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t region,
+                  uint32_t *__restrict__ next, int32_t *__restrict__ dist,
+                  unsigned long long *__restrict__ columns) {
     constexpr uint32_t RS = NW + 1;  // words per symbol row of a window
     extern __shared__ uint32_t lds[];
+    if (count_dev) count = (uint32_t)min<uint64_t>(*count_dev, count);
     const uint32_t lane = threadIdx.x;
     uint32_t *win = lds + lane * region;
 #pragma unroll
@@ -950,11 +956,12 @@ __device__ inline void split_block(const uint32_t *wl, uint32_t rs4, const uint8
 template <int WPL, int SIGMAX>
 __global__ void __launch_bounds__(64, WPL <= 4 ? 6 : 1)
     k_verify_split(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint32_t count,
-                   const uint32_t *__restrict__ order, uint32_t K,
-                   const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t KL,
+                   const uint64_t *__restrict__ count_dev, const uint32_t *__restrict__ order,
+                   uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t KL,
                    uint32_t region, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                    unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    if (count_dev) count = (uint32_t)min<uint64_t>(*count_dev, count);
     constexpr int TQ = 4;  // text dwords per lane, at most (8 / KL, KL >= 2)
     const uint32_t lane = threadIdx.x;
     const uint32_t tile = lane / KL, l = lane - tile * KL;
@@ -1173,10 +1180,13 @@ __global__ void k_max_u32(const uint32_t *__restrict__ a, uint64_t n, uint32_t *
 
 // flags[k] = 1 for the pairs pass 1 left undecided
 __global__ void k_alive_flags(const uint32_t *__restrict__ aux, uint64_t count,
+                              const uint64_t *__restrict__ count_dev,
                               uint32_t *__restrict__ flags) {
+    // pairs past a count on the device were never verified: not alive
+    const uint64_t live = count_dev ? min(*count_dev, count) : count;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < count;
          e += (uint64_t)gridDim.x * blockDim.x)
-        flags[e] = aux[e] != DECIDED ? 1u : 0u;
+        flags[e] = (e < live && aux[e] != DECIDED) ? 1u : 0u;
 }
 
 __global__ void k_alive_list(const uint32_t *__restrict__ flags, const uint32_t *__restrict__ pos,
@@ -1196,9 +1206,9 @@ constexpr uint32_t LANE_MAX_SIGMA = 4;
 constexpr uint32_t LANE_WIDE_WORDS = 8;
 constexpr uint32_t LANE_WIDE_SIGMA = 32;
 
-using LaneKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint32_t *,
-                            uint32_t, const uint32_t *, uint32_t, uint32_t, uint32_t *, int32_t *,
-                            unsigned long long *);
+using LaneKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint64_t *,
+                            const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint32_t,
+                            uint32_t *, int32_t *, unsigned long long *);
 
 LaneKernel lane_kernel(uint32_t nw) {
     switch (nw) {
@@ -1222,9 +1232,9 @@ LaneKernel lane_kernel(uint32_t nw) {
     }
 }
 
-using SplitKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint32_t *,
-                             uint32_t, const uint32_t *, uint32_t, uint32_t, uint32_t, uint32_t *,
-                             int32_t *, unsigned long long *);
+using SplitKernel = void (*)(StrSet, StrSet, const uint64_t *, uint32_t, const uint64_t *,
+                             const uint32_t *, uint32_t, const uint32_t *, uint32_t, uint32_t,
+                             uint32_t, uint32_t *, int32_t *, unsigned long long *);
 constexpr uint32_t SPLIT_MAX_WPL = 8;
 
 LaneKernel lane_kernel_wide(uint32_t nw) {
@@ -1327,7 +1337,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             uint64_t count, uint32_t K, const uint32_t *d_Kq, int32_t *d_dist,
             const uint8_t *d_codes_b, const uint64_t *d_offsets_b, uint64_t base_b,
             uint32_t maxlen_b, const RowMasks *masks_b, unsigned long long *d_columns,
-            const uint32_t *d_order) {
+            const uint32_t *d_order, const uint64_t *d_count) {
     if (count == 0) return;
     if (count >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "more than 2^32 pairs in one verification");
     uint32_t Kmax = K;
@@ -1422,26 +1432,28 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
         char key[512];
         snprintf(key, sizeof(key),
-                 "verify_lane %u %u %p %p %llu %p %p %p %p %llu %p %p %p %u %p %u %p %u %u %p %p "
-                 "%p %llu %zu",
+                 "verify_lane %u %u %p %p %llu %p %p %p %p %llu %p %p %p %u %p %p %u %p %u %u %p "
+                 "%p %p %llu %zu %llu",
                  NWf, KL, (const void *)d_codes, (const void *)d_offsets, (unsigned long long)base,
                  (const void *)A.mw, (const void *)A.moff, (const void *)d_codes_b,
                  (const void *)d_offsets_b, (unsigned long long)base_b, (const void *)B.mw,
                  (const void *)B.moff, (const void *)d_pairs, (unsigned)count,
-                 (const void *)d_order, K, (const void *)d_Kq, sig, region, (void *)next,
-                 (void *)d_dist, (void *)d_columns, (unsigned long long)grid, llds);
+                 (const void *)d_count, (const void *)d_order, K, (const void *)d_Kq, sig, region,
+                 (void *)next,
+                 (void *)d_dist, (void *)d_columns, (unsigned long long)grid, llds,
+                 (unsigned long long)ctx->ws_gen);
         kmark();
         run_captured(ctx, key, [&] {
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
             EJ_CHECK_LAUNCH();
             if (KL == 1)
                 hipLaunchKernelGGL(lk, dim3((uint32_t)grid), dim3(64), llds,
-                                   ctx->stream, A, B, d_pairs, (uint32_t)count, d_order, K, d_Kq,
-                                   sig, region, next, d_dist, d_columns);
+                                   ctx->stream, A, B, d_pairs, (uint32_t)count, d_count, d_order,
+                                   K, d_Kq, sig, region, next, d_dist, d_columns);
             else
                 hipLaunchKernelGGL(split_kernel(WPL), dim3((uint32_t)grid), dim3(64), llds,
-                                   ctx->stream, A, B, d_pairs, (uint32_t)count, d_order, K, d_Kq,
-                                   sig, KL, region, next, d_dist, d_columns);
+                                   ctx->stream, A, B, d_pairs, (uint32_t)count, d_count, d_order,
+                                   K, d_Kq, sig, KL, region, next, d_dist, d_columns);
             EJ_CHECK_LAUNCH();
         });
         kmark();
@@ -1466,24 +1478,27 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         const uint64_t grid = std::min<uint64_t>(ngroups, (uint64_t)ctx->num_cu * occ);
         uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
         // the counter reset and the persistent launch: one captured graph in
-        // graph mode (keyed by every launch argument)
+        // graph mode (keyed by every launch argument and the workspace
+        // generation, so that no buffer of a cached graph has moved)
         char key[512];
         snprintf(key, sizeof(key),
-                 "verify_queue %d %d %p %p %llu %p %p %p %p %llu %p %p %p %u %p %u %p %u %u %u %u "
-                 "%p %p %p %llu %zu",
+                 "verify_queue %d %d %p %p %llu %p %p %p %p %llu %p %p %p %u %p %p %u %p %u %u %u "
+                 "%u %p %p %p %llu %zu %llu",
                  mode, (int)ring, (const void *)d_codes, (const void *)d_offsets,
                  (unsigned long long)base, (const void *)A.mw, (const void *)A.moff,
                  (const void *)d_codes_b, (const void *)d_offsets_b, (unsigned long long)base_b,
                  (const void *)B.mw, (const void *)B.moff, (const void *)d_pairs, (unsigned)count,
-                 (const void *)d_order, K, (const void *)d_Kq, sig, NL, tpw, wpp, (void *)next,
-                 (void *)d_dist, (void *)d_columns, (unsigned long long)grid, lds);
+                 (const void *)d_count, (const void *)d_order, K, (const void *)d_Kq, sig, NL, tpw,
+                 wpp, (void *)next,
+                 (void *)d_dist, (void *)d_columns, (unsigned long long)grid, lds,
+                 (unsigned long long)ctx->ws_gen);
         kmark();
         run_captured(ctx, key, [&] {
             hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
             EJ_CHECK_LAUNCH();
             hipLaunchKernelGGL(qkern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B,
-                               d_pairs, (uint32_t)count, d_order, K, d_Kq, sig, NL, tpw, wpp,
-                               next, d_dist, d_columns);
+                               d_pairs, (uint32_t)count, d_count, d_order, K, d_Kq, sig, NL, tpw,
+                               wpp, next, d_dist, d_columns);
             EJ_CHECK_LAUNCH();
         });
         kmark();
@@ -1503,7 +1518,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         uint64_t ngroups = (count + tpw - 1) / tpw;
         uint64_t grid = std::min<uint64_t>(ngroups, cap);
         hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
-                           count, (const uint64_t *)nullptr, (const uint32_t *)nullptr, K, d_Kq,
+                           count, d_count, (const uint32_t *)nullptr, K, d_Kq,
                            sig, NL, tpw, wpp, 0u,
                            two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
         EJ_CHECK_LAUNCH();
@@ -1514,7 +1529,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     uint32_t *pos = ws<uint32_t>(ctx, "verify_pos", count);
     uint64_t *d_nalive = ws<uint64_t>(ctx, "verify_nalive", 1);
     hipLaunchKernelGGL(k_alive_flags, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
-                       (const uint32_t *)aux, count, flags);
+                       (const uint32_t *)aux, count, d_count, flags);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u32(ctx, flags, pos, count, d_nalive);
     // no host round trip: the list and pass 2 are sized for all pairs and

@@ -149,11 +149,30 @@ def test_bucket_key_bits_do_not_change_candidates(ej, ctx, oracle_lib):
     chars, offs = to_device(col)
     keys, _, _, _ = ctx.embed(chars, offs, r, z, m, seed=7, L=16)
     d_len = torch.from_numpy(col.lengths().astype(np.int32)).cuda()
-    for bits in (1, 3, 8, 17, 32):
+    for bits in (0, 1, 3, 8, 17, 32):
         _say(f"bucket key_bits={bits}")
         ids, gstart = ctx.lsh_bucket(keys, d_len, key_bits=bits)
         cand, _ = ctx.candidates(keys, ids, gstart, d_len, K)
         assert cand.cpu().numpy().astype(np.uint64).tolist() == ref.cand.tolist()
+    # key_bits = 0: each group is exactly one bucket, groups in increasing key
+    # order per table, members in (length, position) order
+    ids, gstart = ctx.lsh_bucket(keys, d_len, key_bits=0)
+    ids, gstart = ids.cpu().numpy(), gstart.cpu().numpy()
+    lens, n = col.lengths(), col.n
+    want = 0
+    for t in range(r * z):
+        kt = ref.keys[t]
+        want += len(np.unique(kt))
+        order = sorted(range(n), key=lambda i: (int(kt[i]), int(lens[i]), i))
+        assert ids[t * n:(t + 1) * n].tolist() == order
+    assert len(gstart) - 1 == want
+    for g in range(len(gstart) - 1):
+        a, b = int(gstart[g]), int(gstart[g + 1])
+        t = a // n
+        assert b <= (t + 1) * n
+        assert len(set(ref.keys[t][ids[a:b]].tolist())) == 1
+        if g + 1 < len(gstart) - 1 and b < (t + 1) * n:
+            assert ref.keys[t][ids[b]] > ref.keys[t][ids[a]]
 
 
 # ------------------------------------------------------- verification ----
@@ -584,15 +603,20 @@ def test_graph_replays_match_eager(ej, ctx, oracle_lib):
     ref2 = _oracle_join(oracle_lib, col2, 20, r, z, m, 4, L)
     old = ctx.tune_get("verify_mode")
     try:
-        for mode in (1, 2):
+        for mode in (0, 1, 2):
             ctx.tune_set("verify_mode", mode)
+            ran = []
             for i in range(4):
                 _say(f"graph replay mode={mode} {i}")
                 res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
                 _assert_join_equal(res, ref)
+                ran.append(res.graph)
                 eager = ctx.join(chars, offs, K, r, z, m, seed=4, L=L)
                 _assert_join_equal(eager, ref)
+                assert eager.graph == 0
                 torch.cuda.synchronize()
+            # host-sized, then device-sized uncaptured, then graph replays
+            assert ran[0] == 0 and ran[-1] == 2, ran
             # a different shape in between, then the first shape again
             _assert_join_equal(ctx.join(col2.chars, col2.offsets, 20, r, z, m, seed=4, L=L,
                                          flags=ej.FLAG_GRAPH), ref2)
@@ -600,3 +624,46 @@ def test_graph_replays_match_eager(ej, ctx, oracle_lib):
                                         flags=ej.FLAG_GRAPH), ref)
     finally:
         ctx.tune_set("verify_mode", old)
+
+
+def test_whole_join_graph_capacity_overflow(ej, ctx, oracle_lib):
+    """The whole join replayed from a graph, then new contents in the same
+    device buffers (same lengths, so the same shape) with many more
+    candidates than the capacities taken from the first contents: that join
+    is redone host-sized, the capacities grow, later joins replay again; every
+    result equals the oracle, in host and device output."""
+    import torch
+    rng = np.random.default_rng(5)
+    DNA = np.frombuffer(b"ACGT", np.uint8)
+    lens = rng.integers(80, 200, size=600)
+    # few candidates: unrelated random strings
+    sparse = sd.from_strings([bytes(DNA[rng.integers(0, 4, size=int(x))]) for x in lens])
+    # many candidates: 4 groups of prefixes of one string each, same lengths
+    bases = [DNA[rng.integers(0, 4, size=220)] for _ in range(4)]
+    dense = sd.from_strings([bytes(bases[i % 4][:int(x)]) for i, x in enumerate(lens)])
+    assert np.array_equal(sparse.offsets, dense.offsets)
+    K, r, z, m, L = 30, 3, 4, 8, 40
+    ref_s = _oracle_join(oracle_lib, sparse, K, r, z, m, 9, L)
+    ref_d = _oracle_join(oracle_lib, dense, K, r, z, m, 9, L)
+    assert len(ref_d.cand) > 4 * len(ref_s.cand) + 10000 and ref_d.n_raw > 100 * ref_s.n_raw
+    chars, offs = to_device(sparse)
+    dchars = torch.from_numpy(dense.chars.copy()).cuda()
+    for mode in (1, 2):
+        ctx.tune_set("verify_mode", mode)
+        chars.copy_(torch.from_numpy(sparse.chars.copy()).cuda())
+        for i in range(3):
+            res = ctx.join(chars, offs, K, r, z, m, seed=9, L=L, flags=ej.FLAG_GRAPH)
+            _assert_join_equal(res, ref_s)
+        assert res.graph == 2
+        chars.copy_(dchars)
+        torch.cuda.synchronize()
+        _say(f"overflow mode={mode}")
+        res = ctx.join(chars, offs, K, r, z, m, seed=9, L=L, flags=ej.FLAG_GRAPH)
+        _assert_join_equal(res, ref_d)
+        assert res.graph == 0
+        for i in range(3):
+            res = ctx.join(chars, offs, K, r, z, m, seed=9, L=L,
+                           flags=ej.FLAG_GRAPH | ej.FLAG_DEVICE_OUT)
+            _assert_join_equal(res, ref_d)
+        assert res.graph == 2
+    ctx.tune_set("verify_mode", 0)
