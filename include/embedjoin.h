@@ -182,6 +182,9 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "radix_bits"            digit width of the radix sorts (4..11)
  *   "bucket_key_bits"       key bits sorted when bucketing (1..32; 0 =
  *                           ceil(log2 n) + 6)
+ *   "dedup_sort"            de-duplication of the candidates: 0 grouped by
+ *                           the codes' top bits with an LDS hash per group
+ *                           (a sort when a group is too large), 1 a sort
  * EJ_EINVAL for an unknown name or a value out of range. */
 ej_status ej_tune_set(ej_ctx *ctx, const char *name, uint32_t value);
 ej_status ej_tune_get(const ej_ctx *ctx, const char *name, uint32_t *value);

@@ -312,23 +312,38 @@ __global__ void k_tuple_pairs(const uint64_t *__restrict__ t, uint64_t cnt, uint
         if (flags[e]) out[pos[e]] = t[e] >> shift;
 }
 
+// cnt_dev: a count on the device; past cnt the entries were never written,
+// so then nothing is flagged (the host sees the count and redoes the join)
 template <typename C>
 __global__ void k_unique_flags(const C *__restrict__ codes, uint64_t cnt,
+                               const uint64_t *__restrict__ cnt_dev,
                                uint32_t *__restrict__ flags) {
+    const uint64_t live = cnt_dev ? (*cnt_dev > cnt ? 0 : *cnt_dev) : cnt;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (uint64_t)gridDim.x * blockDim.x)
-        flags[e] = (e == 0 || codes[e] != codes[e - 1]) ? 1u : 0u;
+        flags[e] = (e < live && (e == 0 || codes[e] != codes[e - 1])) ? 1u : 0u;
+}
+
+// Entries past the count on the device get the largest code, which no pair
+// has (a < b), so that a sort of the whole buffer leaves them at the end.
+template <typename C>
+__global__ void k_pad_codes(C *__restrict__ codes, uint64_t cap,
+                            const uint64_t *__restrict__ cnt_dev, C pad) {
+    const uint64_t from = min(*cnt_dev, cap);
+    for (uint64_t e = from + blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cap;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        codes[e] = pad;
 }
 
 template <typename C>
 __global__ void k_unique_compact(const C *__restrict__ codes, uint64_t cnt, uint32_t B,
                                  const uint32_t *__restrict__ flags,
                                  const uint32_t *__restrict__ pos, uint64_t *__restrict__ out,
-                                 uint32_t *__restrict__ first) {
+                                 uint32_t *__restrict__ first, uint64_t cap) {
     const uint64_t mask = (1ULL << B) - 1ULL;
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < cnt;
          e += (uint64_t)gridDim.x * blockDim.x) {
-        if (flags[e]) {
+        if (flags[e] && pos[e] < cap) {
             const uint64_t c = codes[e];
             out[pos[e]] = ((c >> B) << 32) | (c & mask);
             if (first) first[pos[e]] = (uint32_t)e;
@@ -504,12 +519,17 @@ __global__ void k_mult_keys_direct(const uint32_t *__restrict__ mult, uint64_t c
 // raw copy per table, so cap = 2^bits_for(tables) - 1 keeps every count
 // apart in bits_for(tables) key bits.
 __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, uint64_t raw,
-                            uint32_t cap, uint32_t *__restrict__ key,
-                            uint32_t *__restrict__ idx) {
+                            const uint64_t *__restrict__ cnt_dev,
+                            const uint64_t *__restrict__ raw_dev, uint32_t cap,
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+    // counts on the device: entries past the distinct count get the key cap,
+    // which no real pair has (m >= 1), and sort behind all real ones
+    const uint64_t live = cnt_dev ? min(*cnt_dev, cnt) : cnt;
+    if (raw_dev) raw = *raw_dev;
     for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < cnt;
          u += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t end = u + 1 < cnt ? first[u + 1] : raw;
-        const uint64_t m = end - first[u];
+        uint64_t m = 0;
+        if (u < live) m = (u + 1 < live ? first[u + 1] : raw) - first[u];
         key[u] = cap - (uint32_t)(m < cap ? m : cap);
         idx[u] = (uint32_t)u;
     }
@@ -628,6 +648,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     std::string t(tag);
     const uint32_t n = bk.n;
     const uint64_t tot = (uint64_t)bk.T * n;
+    ctx->last_dedup_sorted = false;
     *d_pairs_out = ws<uint64_t>(ctx, t + "_pairs", 1);
     if (n_raw) *n_raw = 0;
     if (tot == 0 || n < 2) return 0;
@@ -709,7 +730,7 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         else
             radix_sort_u64(ctx, rawbuf, sorted, raw, 2 * B, ctx->tune.radix_bits);
         hipLaunchKernelGGL(k_unique_flags<C>, dim3(grid_for(ctx, raw, 256)), dim3(256), 0,
-                           ctx->stream, (const C *)sorted, raw, flags);
+                           ctx->stream, (const C *)sorted, raw, (const uint64_t *)nullptr, flags);
         EJ_CHECK_LAUNCH();
         scan_exclusive_u32(ctx, flags, pos, raw, d_cnt);
         uint64_t cnt = 0;
@@ -718,14 +739,16 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         uint32_t *first = d_order_out ? ws<uint32_t>(ctx, t + "_first", cnt) : nullptr;
         hipLaunchKernelGGL(k_unique_compact<C>, dim3(grid_for(ctx, raw, 256)), dim3(256), 0,
                            ctx->stream, (const C *)sorted, raw, B, (const uint32_t *)flags,
-                           (const uint32_t *)pos, pairs, first);
+                           (const uint32_t *)pos, pairs, first, cnt);
         EJ_CHECK_LAUNCH();
         *d_pairs_out = pairs;
         if (d_order_out && cnt) {
             uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
             uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt);
             hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)first, cnt, raw, mult_cap, k0, v0);
+                               ctx->stream, (const uint32_t *)first, cnt, raw,
+                               (const uint64_t *)nullptr, (const uint64_t *)nullptr, mult_cap,
+                               k0, v0);
             EJ_CHECK_LAUNCH();
         }
         return cnt;
@@ -784,21 +807,27 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
         }
         return true;
     };
-    const bool fits_grouped = 2 * B <= DD_GBITS + 31;
+    const bool fits_grouped = 2 * B <= DD_GBITS + 31 && ctx->tune.dedup_sort == 0;
     if (2 * B <= 32) {
         // 32-bit codes (both indexes below 2^16)
         uint32_t *raw32 = ws<uint32_t>(ctx, t + "_raw32", raw);
         emit(raw32);
         uint32_t *part = ws<uint32_t>(ctx, t + "_raw32_sorted", raw);
         // on overflow: sort them all (raw32 is intact, the grouping wrote `part`)
-        if (!grouped(raw32, part)) cnt = sort_unique(raw32, part);
+        if (!fits_grouped || !grouped(raw32, part)) {
+            cnt = sort_unique(raw32, part);
+            ctx->last_dedup_sorted = true;
+        }
     } else {
         uint64_t *raw64 = ws<uint64_t>(ctx, t + "_raw", raw);
         uint64_t *sorted = ws<uint64_t>(ctx, t + "_raw_sorted", raw);
         emit(raw64);
         // the 32-bit local codes go to the first half of `sorted`, which
         // the fallback sort overwrites only after the grouping has failed
-        if (!fits_grouped || !grouped(raw64, (uint32_t *)sorted)) cnt = sort_unique(raw64, sorted);
+        if (!fits_grouped || !grouped(raw64, (uint32_t *)sorted)) {
+            cnt = sort_unique(raw64, sorted);
+            ctx->last_dedup_sorted = true;
+        }
     }
     if (d_order_out && cnt) {
         uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt);
@@ -823,11 +852,13 @@ __global__ void k_zero_u64(uint64_t *__restrict__ p, uint32_t n) {
 // memory: cnt_dev[0] = raw pairs, cnt_dev[1] = distinct pairs, cnt_dev[2] =
 // nonzero when a group of the de-duplication held more distinct codes than it
 // takes.  A count above its capacity, or that flag, makes the result invalid:
-// the caller reads the counts after the join and redoes it.  Only the grouped
-// de-duplication (2B <= DD_GBITS + 31).
+// the caller reads the counts after the join and redoes it.  The
+// de-duplication is the grouped one (2B <= DD_GBITS + 31), or with sort_dedup
+// a sort of the whole raw buffer (its entries past the count padded to the
+// end), as candidates() falls back to when a group is too large.
 void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
                     const uint32_t *d_len, uint32_t K, uint64_t raw_cap, uint64_t cnt_cap,
-                    bool want_order, uint64_t *cnt_dev, uint64_t **d_pairs_out,
+                    bool want_order, bool sort_dedup, uint64_t *cnt_dev, uint64_t **d_pairs_out,
                     uint32_t **d_order_out, const char *tag) {
     std::string t(tag);
     const uint32_t n = bk.n;
@@ -836,7 +867,6 @@ void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     if (raw_cap >= 0xFFFFFFFFull || cnt_cap >= 0xFFFFFFFFull || tot >= 0xFFFFFFFFull)
         fail(EJ_EUNSUPPORTED, "candidates_dev: capacities must stay below 2^32");
     const uint32_t B = std::max(1u, bits_for(n - 1));
-    if (2 * B > DD_GBITS + 31) fail(EJ_EUNSUPPORTED, "candidates_dev: codes too wide");
     const uint32_t mult_bits = std::max(1u, bits_for(bk.T));
     const uint32_t mult_cap = mult_bits >= 32 ? 0xFFFFFFFFu : (1u << mult_bits) - 1u;
     uint64_t *key_s = ws<uint64_t>(ctx, t + "_key_s", tot);
@@ -857,6 +887,64 @@ void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
                        (uint64_t *)nullptr, (uint64_t)0);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u64(ctx, counts, counts, nwg, cnt_dev);
+    if (sort_dedup) {
+        // the whole raw buffer sorted (padding at the end), one of each run
+        uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", raw_cap);
+        uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", raw_cap);
+        uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt_cap);
+        uint32_t *first = want_order ? ws<uint32_t>(ctx, t + "_first", cnt_cap) : nullptr;
+        auto sorted_unique = [&](auto *rawbuf, auto *sorted) {
+            using C = std::remove_pointer_t<decltype(rawbuf)>;
+            hipLaunchKernelGGL((k_pairs_dk<true, C, PairCoder>), dim3(nwg), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                               (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n,
+                               (uint32_t)tot, K, PairCoder{B}, tcount, (uint64_t *)nullptr,
+                               (const uint64_t *)counts, rawbuf, raw_cap);
+            EJ_CHECK_LAUNCH();
+            const C pad = (C)((2 * B >= 64 ? ~0ull : (1ull << (2 * B)) - 1ull));
+            hipLaunchKernelGGL(k_pad_codes<C>, dim3(grid_for(ctx, raw_cap, 256)), dim3(256), 0,
+                               ctx->stream, rawbuf, raw_cap, (const uint64_t *)cnt_dev, pad);
+            EJ_CHECK_LAUNCH();
+            if constexpr (sizeof(C) == 4)
+                radix_sort_u32(ctx, rawbuf, nullptr, sorted, nullptr, 1, (uint32_t)raw_cap, 2 * B,
+                               ctx->tune.radix_bits);
+            else
+                radix_sort_u64(ctx, rawbuf, sorted, raw_cap, 2 * B, ctx->tune.radix_bits);
+            hipLaunchKernelGGL(k_unique_flags<C>, dim3(grid_for(ctx, raw_cap, 256)), dim3(256), 0,
+                               ctx->stream, (const C *)sorted, raw_cap, (const uint64_t *)cnt_dev,
+                               flags);
+            EJ_CHECK_LAUNCH();
+            scan_exclusive_u32(ctx, flags, pos, raw_cap, cnt_dev + 1);
+            hipLaunchKernelGGL(k_unique_compact<C>, dim3(grid_for(ctx, raw_cap, 256)), dim3(256),
+                               0, ctx->stream, (const C *)sorted, raw_cap, B,
+                               (const uint32_t *)flags, (const uint32_t *)pos, pairs, first,
+                               cnt_cap);
+            EJ_CHECK_LAUNCH();
+        };
+        if (2 * B <= 32)
+            sorted_unique(ws<uint32_t>(ctx, t + "_raw32", raw_cap),
+                          ws<uint32_t>(ctx, t + "_raw32_sorted", raw_cap));
+        else
+            sorted_unique(ws<uint64_t>(ctx, t + "_raw", raw_cap),
+                          ws<uint64_t>(ctx, t + "_raw_sorted", raw_cap));
+        *d_pairs_out = pairs;
+        *d_order_out = nullptr;
+        if (want_order) {
+            uint32_t *k0 = ws<uint32_t>(ctx, t + "_okey", cnt_cap);
+            uint32_t *v0 = ws<uint32_t>(ctx, t + "_oidx", cnt_cap);
+            uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", cnt_cap);
+            uint32_t *order = ws<uint32_t>(ctx, t + "_order", cnt_cap);
+            hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, cnt_cap, 256)), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)first, cnt_cap, raw_cap,
+                               (const uint64_t *)(cnt_dev + 1), (const uint64_t *)cnt_dev,
+                               mult_cap, k0, v0);
+            EJ_CHECK_LAUNCH();
+            radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)cnt_cap, mult_bits, 11);
+            *d_order_out = order;
+        }
+        return;
+    }
+    if (2 * B > DD_GBITS + 31) fail(EJ_EUNSUPPORTED, "candidates_dev: codes too wide to group");
     const uint32_t GB = std::min(DD_GBITS, 2 * B);
     const uint32_t NG = 1u << GB, shift = 2 * B - GB;
     const uint32_t nwd = (uint32_t)((raw_cap + DD_CHUNK - 1) / DD_CHUNK);
@@ -992,7 +1080,7 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
                        (const uint32_t *)pos, q);
     EJ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_unique_flags<uint64_t>, dim3(grid_for(ctx, nq, 256)), dim3(256), 0,
-                       ctx->stream, (const uint64_t *)q, nq, flags);
+                       ctx->stream, (const uint64_t *)q, nq, (const uint64_t *)nullptr, flags);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u32(ctx, flags, pos, nq, d_n);
     uint64_t cnt = 0;
@@ -1000,7 +1088,7 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cnt);
     hipLaunchKernelGGL(k_unique_compact<uint64_t>, dim3(grid_for(ctx, nq, 256)), dim3(256), 0,
                        ctx->stream, (const uint64_t *)q, nq, B, (const uint32_t *)flags,
-                       (const uint32_t *)pos, pairs, (uint32_t *)nullptr);
+                       (const uint32_t *)pos, pairs, (uint32_t *)nullptr, cnt);
     EJ_CHECK_LAUNCH();
     *d_pairs_out = pairs;
     return cnt;
@@ -1016,7 +1104,7 @@ uint64_t unique_sorted_pairs(ej_ctx *ctx, const uint64_t *d_sorted, uint64_t cnt
     uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", cnt);
     uint64_t *d_n = ws<uint64_t>(ctx, t + "_ucnt", 1);
     hipLaunchKernelGGL(k_unique_flags<uint64_t>, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
-                       ctx->stream, d_sorted, cnt, flags);
+                       ctx->stream, d_sorted, cnt, (const uint64_t *)nullptr, flags);
     EJ_CHECK_LAUNCH();
     scan_exclusive_u32(ctx, flags, pos, cnt, d_n);
     uint64_t u = 0;
@@ -1024,7 +1112,7 @@ uint64_t unique_sorted_pairs(ej_ctx *ctx, const uint64_t *d_sorted, uint64_t cnt
     uint64_t *out = ws<uint64_t>(ctx, t + "_upairs", u);
     hipLaunchKernelGGL(k_unique_compact<uint64_t>, dim3(grid_for(ctx, cnt, 256)), dim3(256), 0,
                        ctx->stream, d_sorted, cnt, B, (const uint32_t *)flags,
-                       (const uint32_t *)pos, out, (uint32_t *)nullptr);
+                       (const uint32_t *)pos, out, (uint32_t *)nullptr, u);
     EJ_CHECK_LAUNCH();
     *d_out = out;
     return u;

@@ -109,6 +109,7 @@ struct Tuning {
     uint32_t embed_lds_budget = 48 * 1024;   // LDS per wave of the walk kernel
     uint32_t radix_bits = 8;                 // digit width of the radix sorts
     uint32_t bucket_key_bits = 0;            // key bits sorted when bucketing, 0 = ceil(log2 n) + 6
+    uint32_t dedup_sort = 0;                 // candidates: 0 grouped (sort on overflow), 1 sort
 };
 }  // namespace ej
 
@@ -116,12 +117,14 @@ namespace ej {
 // Capacities of a join sized on the device (EJ_FLAG_GRAPH): raw and distinct
 // candidate pairs; gen = the workspace generation after the last uncaptured
 // run at these capacities (a capture needs every buffer to exist already);
-// no_graph = the shape needs the host-sized path (its de-duplication
-// overflows the grouped form).
+// no_graph = the shape stays host-sized (a capture failed, or a capacity
+// would reach 2^32); sort_dedup = de-duplicate by a sort (the grouped form
+// overflowed, or the knob asks for it).
 struct JoinCaps {
     uint64_t raw_cap = 0, cnt_cap = 0;
     uint64_t gen = ~0ull;
     bool no_graph = false;
+    bool sort_dedup = false;  // de-duplicate by a sort (the grouped form overflowed)
 };
 }  // namespace ej
 
@@ -145,6 +148,7 @@ struct ej_ctx {
     bool graph_on = false;
     std::map<std::string, hipGraphExec_t> graphs;
     bool capturing = false;    // a graph capture is open on the stream
+    bool last_dedup_sorted = false;  // the last candidates() de-duplicated by a sort
     uint64_t ws_gen = 0;       // workspace (re)allocations so far
     // joins sized on the device, per input shape: the capacities of their
     // candidate buffers and the workspace generation they were allocated in
@@ -296,7 +300,7 @@ void bucket(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_len, const ui
 // overflowed).  The result is valid only when both counts fit and [2] is 0.
 void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
                     const uint32_t *d_len, uint32_t K, uint64_t raw_cap, uint64_t cnt_cap,
-                    bool want_order, uint64_t *cnt_dev, uint64_t **d_pairs_out,
+                    bool want_order, bool sort_dedup, uint64_t *cnt_dev, uint64_t **d_pairs_out,
                     uint32_t **d_order_out, const char *tag);
 // Exact buckets: every table sorted by (full key, length, position), one group
 // per distinct key (d_gid, d_gstart and ngroups set).

@@ -446,12 +446,13 @@ std::string join_shape(ej_ctx *ctx, const Prep &pp, const uint8_t *d_chars,
     const Tuning &t = ctx->tune;
     char key[512];
     snprintf(key, sizeof(key),
-             "join %p %p %u %llu %llu %u %u %u %u %u %u %u %llu | %u %u %u %u %u %u %u %u %u %u",
+             "join %p %p %u %llu %llu %u %u %u %u %u %u %u %llu | %u %u %u %u %u %u %u %u %u %u "
+             "%u",
              (const void *)d_chars, (const void *)d_offsets, pp.n, (unsigned long long)pp.base,
              (unsigned long long)pp.total, pp.sigma, pp.maxlen, pp.L, p.K, p.r, p.z, p.m,
              (unsigned long long)p.seed, t.verify_mode, t.verify_order, t.verify_split,
              t.verify_pass1_cols, t.verify_blocks_per_cu, t.verify_ring, t.verify_lds_budget,
-             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits);
+             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits, t.dedup_sort);
     return key;
 }
 
@@ -479,8 +480,9 @@ bool join_graph(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_o
         bucket(ctx, keys, pp.d_len, pp.d_perm, n, T, kb, bk, "j", false, true, false);
         uint64_t *pairs = nullptr;
         uint32_t *order = nullptr;
-        candidates_dev(ctx, keys, bk, pp.d_len, p.K, raw_cap, cnt_cap, want_order, cnt_dev,
-                       &pairs, &order, "j");
+        candidates_dev(ctx, keys, bk, pp.d_len, p.K, raw_cap, cnt_cap, want_order,
+                       caps.sort_dedup || ctx->tune.dedup_sort != 0, cnt_dev, &pairs, &order,
+                       "j");
         int32_t *dist = ws<int32_t>(ctx, "j_dist", cnt_cap);
         RowMasks masks;
         build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
@@ -537,12 +539,14 @@ bool join_graph(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_o
     read_back(ctx, cnt_out, sizeof(c), c);
     if (c[2] != 0 || c[0] > raw_cap || c[1] > cnt_cap) out->graph = 0;
     if (c[2] != 0) {
-        caps.no_graph = true;
+        // a group too large for the grouped de-duplication: sort instead
+        caps.sort_dedup = true;
+        caps.gen = ~0ull;
         return false;
     }
     if (c[0] > raw_cap || c[1] > cnt_cap) {
-        caps.raw_cap = std::max(raw_cap, c[0] + c[0] / 4 + 4096);
-        caps.cnt_cap = std::max(cnt_cap, c[1] + c[1] / 4 + 4096);
+        caps.raw_cap = std::max(raw_cap, c[0] + c[0] / 8 + 4096);
+        caps.cnt_cap = std::max(cnt_cap, c[1] + c[1] / 8 + 4096);
         caps.gen = ~0ull;
         return false;
     }
@@ -605,8 +609,7 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     // the whole join as one graph: not with stage timing (its events go
     // between the stages) nor with the short-string pass
     const bool as_graph = (p.flags & EJ_FLAG_GRAPH) != 0 && (p.flags & EJ_FLAG_TIMING) == 0 &&
-                          p.exact_len == 0 && n >= 2 &&
-                          2 * std::max(1u, bits_for(n - 1)) <= 42;
+                          p.exact_len == 0 && n >= 2;
     std::string shape;
     if (as_graph) {
         shape = join_shape(ctx, pp, d_chars, d_offsets, p);
@@ -640,8 +643,11 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         // capacities for the next join of this shape, with headroom
         if (ctx->join_caps.size() >= 64) ctx->join_caps.clear();
         JoinCaps &c = ctx->join_caps[shape];
-        c.raw_cap = std::max(c.raw_cap, raw + raw / 4 + 4096);
-        c.cnt_cap = std::max(c.cnt_cap, cnt + cnt / 4 + 4096);
+        c.raw_cap = std::max(c.raw_cap, raw + raw / 16 + 4096);
+        c.cnt_cap = std::max(c.cnt_cap, cnt + cnt / 16 + 4096);
+        c.sort_dedup = c.sort_dedup || ctx->last_dedup_sorted;
+        // capacities at 2^32 or more: this shape stays host-sized
+        if (c.raw_cap >= 0xFFFFFFFFull || c.cnt_cap >= 0xFFFFFFFFull) c.no_graph = true;
     }
 }
 
@@ -996,6 +1002,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             {&Tuning::verify_ring, {1, 0}, 3},
             {&Tuning::radix_bits, {6, 7, 8, 11}, 7},
             {&Tuning::bucket_key_bits, {0, 32}, 7},
+            {&Tuning::dedup_sort, {0, 1}, 7},
         };
         for (const Knob &k : knobs) {
             if (!((k.modes >> ctx->tune.verify_mode) & 1u)) continue;

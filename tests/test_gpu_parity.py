@@ -617,6 +617,14 @@ def test_graph_replays_match_eager(ej, ctx, oracle_lib):
                 torch.cuda.synchronize()
             # host-sized, then device-sized uncaptured, then graph replays
             assert ran[0] == 0 and ran[-1] == 2, ran
+            # de-duplication by a sort, host-sized and replayed
+            ctx.tune_set("dedup_sort", 1)
+            for i in range(4):
+                res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
+                _assert_join_equal(res, ref)
+                _assert_join_equal(ctx.join(chars, offs, K, r, z, m, seed=4, L=L), ref)
+            assert res.graph == 2
+            ctx.tune_set("dedup_sort", 0)
             # a different shape in between, then the first shape again
             _assert_join_equal(ctx.join(col2.chars, col2.offsets, 20, r, z, m, seed=4, L=L,
                                          flags=ej.FLAG_GRAPH), ref2)
@@ -648,8 +656,9 @@ def test_whole_join_graph_capacity_overflow(ej, ctx, oracle_lib):
     assert len(ref_d.cand) > 4 * len(ref_s.cand) + 10000 and ref_d.n_raw > 100 * ref_s.n_raw
     chars, offs = to_device(sparse)
     dchars = torch.from_numpy(dense.chars.copy()).cuda()
-    for mode in (1, 2):
+    for mode, dsort in ((1, 0), (2, 0), (0, 1)):
         ctx.tune_set("verify_mode", mode)
+        ctx.tune_set("dedup_sort", dsort)
         chars.copy_(torch.from_numpy(sparse.chars.copy()).cuda())
         for i in range(3):
             res = ctx.join(chars, offs, K, r, z, m, seed=9, L=L, flags=ej.FLAG_GRAPH)
@@ -667,3 +676,4 @@ def test_whole_join_graph_capacity_overflow(ej, ctx, oracle_lib):
             _assert_join_equal(res, ref_d)
         assert res.graph == 2
     ctx.tune_set("verify_mode", 0)
+    ctx.tune_set("dedup_sort", 0)
