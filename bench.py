@@ -49,10 +49,13 @@ MI355X_INT32_LANE_OPS_3OP = 256 * 4 * 16 * 2.4e9
 OPS_PER_WORD_STEP = 10
 SURVEY_OPS_PER_WORD = 20
 OPS_PER_WALK_STEP = 3    # walk: read the symbol, select its pi bit, advance
-VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane", 3: "k_verify_split"}
+VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane", 3: "k_verify_split",
+                 4: "k_verify_grp"}
 VERIFY_FORM = {0: "two-pass", 1: "persistent, replayed from a captured HIP graph",
                2: "one pair per lane, persistent, replayed from a captured HIP graph",
-               3: "several band words per lane, persistent, replayed from a captured HIP graph"}
+               3: "several band words per lane, persistent, replayed from a captured HIP graph",
+               4: "grouped by pattern (masks shared in LDS per chunk), one pair per lane, "
+                  "persistent, replayed from a captured HIP graph"}
 LEGS = ("tiny", "uneven", "protein", "plus", "serving")
 
 # Recall-calibrated parameter points, found by sweeps of (r, z, m, L) on these
@@ -84,7 +87,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="medium", choices=["medium", "tiny", "uneven"])
+    ap.add_argument("--workload", default="medium",
+                    choices=["medium", "tiny", "uneven", "protein"])
     ap.add_argument("--K", type=int, default=None)
     ap.add_argument("--r", type=int, default=None)
     ap.add_argument("--z", type=int, default=None)
@@ -938,11 +942,21 @@ def headline_workload(args):
         col, prm = sd.uneven_dna(0)
         name = ("uneven DNA: 80,000 strings, base lengths log-uniform 500..20,000, clusters "
                 "geometric(0.3) <= 20, per-copy edit rate U(0, 0.08)")
+    elif args.workload == "protein":
+        col, prm = sd.protein_like(0)
+        name = ("protein-like: 400,000 strings over 25 letters (Zipf 1.1), lengths lognormal "
+                "(median 400, sigma 0.8) clipped 50..4,000, clusters of mean 4, edit rate "
+                "U(0.02, 0.15)")
     else:
         col, prm = sd.tiny_dna(0)
         name = "tiny DNA: 2,000 strings (200 bases U{900..1100} x 10 copies, Poisson(30) edits)"
     stated = dict(K=prm["K"], r=prm["r"], z=prm["z"], m=prm["m"], L=0)
-    run = dict(stated) if args.stated else dict(stated, **CALIBRATED[args.workload])
+    if args.workload == "protein":
+        # the stated point, truncated at twice the average length (the
+        # paper's choice for strings of varying length, Section 6)
+        run = dict(stated, L=int(np.ceil(2 * col.lengths().mean())))
+    else:
+        run = dict(stated) if args.stated else dict(stated, **CALIBRATED[args.workload])
     for k in ("K", "r", "z", "m", "L"):
         if getattr(args, k) is not None:
             run[k] = getattr(args, k)
@@ -1036,7 +1050,8 @@ def _main(args, legs, pool):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": name, "K": prm["K"], "r": prm["r"], "z": prm["z"], "m": prm["m"],
-                   "L": res.L, "params": "stated" if prm == stated else "recall-calibrated",
+                   "L": res.L, "params": ("stated" if prm == stated or args.workload == "protein"
+                                         else "recall-calibrated"),
                    "form": ("batched: autotuned knobs, " + head["graph"] + ", verification "
                             + VERIFY_FORM[res.verify_form]),
                    "join_sec_with_stage_events": round(head["timed_with_stage_events_ms"] / 1e3,

@@ -70,7 +70,7 @@ typedef enum {
                             them, later ones replay the graph; a count above a capacity
                             redoes the join host-sized and grows it.  With EJ_FLAG_TIMING,
                             or exact_len, only the persistent verification forms
-                            ("verify_mode" 1 or 2) are captured, as a graph of their own.
+                            ("verify_mode" 1 to 3) are captured, as a graph of their own.
                             Results are identical either way. */
 #define EJ_FLAG_TIMING 2u  /* record per-stage device times in ej_result */
 #define EJ_FLAG_DEVICE_OUT 4u /* leave the result in device memory: out->pairs and
@@ -128,7 +128,8 @@ typedef struct {
     uint32_t verify_launches;
     /* The verification form that ran: 0 two passes over groups of pairs,
      * 1 persistent groups of pairs, 2 one pair per lane, 3 several lanes per
-     * pair with several band words each (2 and 3: "verify_mode" 2). */
+     * pair with several band words each (2 and 3: "verify_mode" 2), 4 grouped
+     * by pattern ("verify_mode" 3). */
     uint32_t verify_form;
     /* 1 when pairs and dist are device pointers (EJ_FLAG_DEVICE_OUT) */
     uint32_t on_device;
@@ -166,8 +167,16 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *                           2: the lane form, persistent, with several band
  *                           words per lane ("verify_split" lanes per pair),
  *                           for alphabets of up to 4 symbols and bands of up
- *                           to 8 words per lane (16 with one lane per pair);
- *                           other inputs take form 1
+ *                           to 8 words per lane (16 with one lane per pair),
+ *                           and with one lane per pair up to 32 symbols and
+ *                           8 words; other inputs take form 1;
+ *                           3: grouped by pattern: the pairs ordered by their
+ *                           longer string and cut into chunks of at most 64
+ *                           pairs of one pattern; a wave copies the pattern's
+ *                           match masks into LDS once per chunk and each lane
+ *                           runs one pair, its band (up to 16 words) in
+ *                           registers; pairs of two string sets, and patterns
+ *                           too long for LDS, take form 1
  *   "verify_split"          lane form: lanes per pair, 1, 2, 4, 8 or 16
  *                           (0 = by band width: 1 up to 4 words, 2 up to 8,
  *                           then 4)

@@ -226,7 +226,7 @@ static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32
         {"verify_pass1_cols", &Tuning::verify_pass1_cols, 0, 1u << 30},
         {"verify_blocks_per_cu", &Tuning::verify_blocks_per_cu, 1, 1024},
         {"verify_ring", &Tuning::verify_ring, 0, 2},
-        {"verify_mode", &Tuning::verify_mode, 0, 2},
+        {"verify_mode", &Tuning::verify_mode, 0, 3},
         {"verify_order", &Tuning::verify_order, 0, 1},
         {"verify_split", &Tuning::verify_split, 0, 16},
         {"embed_lds_budget", &Tuning::embed_lds_budget, 8192, 1u << 20},

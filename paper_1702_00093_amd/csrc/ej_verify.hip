@@ -753,25 +753,57 @@ __global__ void __launch_bounds__(64)
         } else if (fresh) {
             // larger alphabets: every fresh lane fills its own sigma rows at
             // once (independent loads, in parallel over the fresh lanes,
-            // where a wave-wide fill would take one global latency per lane)
+            // where a wave-wide fill would take one global latency per lane).
+            // Window word w of a row is the funnel shift of pattern mask words
+            // q0 + w and q0 + w + 1 (as mask_word), so a row takes RS + 1
+            // loads; the last one is kept for the next block's entering word
+            const int32_t p0 = -(int32_t)v.O - 1;
+            const int32_t q0 = p0 >> 5;  // floor
+            const uint32_t sh = (uint32_t)p0 & 31u;
             for (uint32_t c = 0; c < sigma; c++) {
-                uint32_t t[RS];
+                const uint32_t *mc = v.mw + (size_t)c * v.W;
+                uint32_t t[RS + 1];
 #pragma unroll
-                for (uint32_t w = 0; w < RS; w++) t[w] = mask_word(v, c, w);
+                for (uint32_t i = 0; i <= RS; i++) {
+                    const int32_t q = q0 + (int32_t)i;
+                    t[i] = (uint32_t)q < v.W ? mc[q] : 0u;
+                }
 #pragma unroll
-                for (uint32_t w = 0; w < RS; w++) win[c * RS + w] = t[w];
+                for (uint32_t w = 0; w < RS; w++)
+                    win[c * RS + w] = __builtin_amdgcn_alignbit(t[w + 1], t[w], sh);
+                win[(sigma + 1) * RS + c] = t[RS];
             }
         }
 
         // ---- one block of 32 columns; the next block's text and entering
-        //      mask words are fetched first
+        //      mask words are fetched first (none once the text ends in this
+        //      block).  Larger alphabets keep the entering word's low source
+        //      word from the previous block (stored after the rows), so a
+        //      symbol costs one load per block
         uint32_t tn[8];
         lane_text_block(v.yp, has ? v.nn : 0u, jb + 32, sigma, tn);
         const uint32_t wn = (jb >> 5) + RS;
+        const bool more = has && jb + 32 < v.nn;
         uint32_t nwd[SIGMAX];
+        if (SIGMAX <= 4) {
 #pragma unroll
-        for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
-            nwd[c] = (has && c < sigma) ? mask_word(v, c, wn) : 0u;
+            for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++)
+                nwd[c] = (more && c < sigma) ? mask_word(v, c, wn) : 0u;
+        } else {
+            const int32_t p0 = 32 * (int32_t)wn - (int32_t)v.O - 1;
+            const int32_t q = (p0 >> 5) + 1;  // the high source word
+            const uint32_t sh = (uint32_t)p0 & 31u;
+#pragma unroll
+            for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++) {
+                nwd[c] = 0u;
+                if (more && c < sigma) {
+                    const uint32_t hi = (uint32_t)q < v.W ? v.mw[(size_t)c * v.W + q] : 0u;
+                    uint32_t *keep_lo = win + (sigma + 1) * RS + c;
+                    nwd[c] = __builtin_amdgcn_alignbit(hi, *keep_lo, sh);
+                    *keep_lo = hi;
+                }
+            }
+        }
         lane_block<NW>(win, tw, Pv, Mv, Zt);
 #pragma unroll
         for (uint32_t c = 0; c < (uint32_t)SIGMAX; c++) {
@@ -809,6 +841,239 @@ __global__ void __launch_bounds__(64)
                 has = false;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Form grouped by pattern ("verify_mode" 3).  The candidates are ordered by
+// their pattern (the longer string of the pair, as view_pair takes it) and
+// cut into chunks of at most 64 pairs of one pattern.  A wave takes a chunk:
+// the whole wave copies the pattern's precomputed match masks into LDS once
+// (coalesced: a pattern's masks are contiguous), then each lane runs one pair
+// of the chunk, its band in registers as in the lane form.  No lane has a
+// window of its own to fill from scattered loads and shift block by block:
+// band word w at column s of block jb is the funnel shift of pattern mask
+// words q and q + 1, q = floor((jb + s - O - 1) / 32) + w (mask_word's bits),
+// read from the shared rows, which carry `lead` zero words before the pattern
+// and NW + 2 after it.  Worth it when strings have many candidate partners
+// (the mask copy is paid once per chunk instead of once per pair) and for
+// large alphabets (a few KB of LDS per wave instead of a window per lane).
+//
+// Chunks: key = pattern of pair k (pairs past a count on the device get the
+// key 0xFFFFFFFF), sorted; a chunk starts where the key changes and every 64
+// pairs within a run of one key.
+
+__global__ void k_grp_keys(const uint64_t *__restrict__ off, const uint64_t *__restrict__ pairs,
+                           uint64_t count, const uint64_t *__restrict__ count_dev,
+                           uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const uint64_t live = count_dev ? min(*count_dev, count) : count;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t pat = 0xFFFFFFFFu;
+        if (k < live) {
+            const uint64_t code = pairs[k];
+            const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
+            const uint64_t la = off[a + 1] - off[a], lb = off[b + 1] - off[b];
+            pat = la >= lb ? a : b;  // view_pair's pattern
+        }
+        key[k] = pat;
+        val[k] = (uint32_t)k;
+    }
+}
+
+__global__ void k_grp_chunk_flags(const uint32_t *__restrict__ key, uint64_t count,
+                                  const uint64_t *__restrict__ count_dev,
+                                  uint32_t *__restrict__ flags) {
+    const uint64_t live = count_dev ? min(*count_dev, count) : count;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t f = 0;
+        if (k < live) {
+            const uint32_t x = key[k];
+            // first position of this key's run (binary search)
+            uint64_t lo = 0, hi = k;
+            while (lo < hi) {
+                const uint64_t mid = lo + (hi - lo) / 2;
+                if (key[mid] < x)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            f = ((k - lo) & 63u) == 0 ? 1u : 0u;
+        }
+        flags[k] = f;
+    }
+}
+
+__global__ void k_grp_chunk_starts(const uint32_t *__restrict__ flags,
+                                   const uint32_t *__restrict__ pos, uint64_t count,
+                                   const uint64_t *__restrict__ count_dev,
+                                   const uint64_t *__restrict__ nchunks,
+                                   uint32_t *__restrict__ start) {
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * blockDim.x)
+        if (flags[k]) start[pos[k]] = (uint32_t)k;
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        start[*nchunks] = (uint32_t)(count_dev ? min(*count_dev, count) : count);
+}
+
+// 32 columns of one pair per lane, the pattern's rows shared in LDS: row c
+// at rows + c * S (lead zero words, then the pattern's words).  b0 = jb - O - 1
+// (the pattern bit of band bit 0 at the block's first column).
+template <int NW>
+__device__ inline void grp_block(const uint32_t *rows, uint32_t S, int32_t b0,
+                                 const uint32_t tw[8], uint32_t (&Pv)[NW], uint32_t (&Mv)[NW],
+                                 uint32_t &Zt) {
+    uint32_t cur[NW + 1], nxt[NW + 1];
+    auto fetch = [&](uint32_t s, uint32_t (&o)[NW + 1]) {
+        const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
+        const int32_t p = b0 + (int32_t)s;
+        const uint32_t *src = rows + __umul24(c, S) + (p >> 5);
+#pragma unroll
+        for (int w = 0; w <= NW; w++) o[w] = src[w];
+    };
+    fetch(0, cur);
+#pragma unroll
+    for (uint32_t s = 0; s < 32; s++) {
+        if (s < 31) fetch(s + 1, nxt);
+        const uint32_t sh = (uint32_t)(b0 + (int32_t)s) & 31u;
+        uint32_t Xv[NW + 1], Ph[NW], Mh[NW];
+        uint64_t cy = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const uint32_t eq = __builtin_amdgcn_alignbit(cur[w + 1], cur[w], sh);
+            Xv[w] = eq | Mv[w];
+            uint32_t sum;
+            if (NW == 1)
+                sum = (eq & Pv[w]) + Pv[w];
+            else if (w == 0)
+                sum = add_carry_mask(eq & Pv[w], Pv[w], cy);
+            else
+                sum = add_carry_chain(eq & Pv[w], Pv[w], cy, cy);
+            const uint32_t Xh = (sum ^ Pv[w]) | eq;
+            Ph[w] = Mv[w] | ~(Xh | Pv[w]);
+            Mh[w] = Pv[w] & Xh;
+        }
+        Xv[NW] = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const uint32_t Xv1 = __builtin_amdgcn_alignbit(Xv[w + 1], Xv[w], 1);
+            if (w == 0) Zt = popc_acc((Xv1 | Mh[0]) & 1u, Zt);
+            Pv[w] = Mh[w] | ~(Xv1 | Ph[w]);
+            Mv[w] = Ph[w] & Xv1;
+        }
+#pragma unroll
+        for (int w = 0; w < NW; w++) asm volatile("" : "+v"(Pv[w]), "+v"(Mv[w]));
+#pragma unroll
+        for (int w = 0; w <= NW; w++) cur[w] = nxt[w];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+template <int NW>
+__global__ void __launch_bounds__(64)
+    k_verify_grp(StrSet A, const uint64_t *__restrict__ pairs, const uint32_t *__restrict__ order,
+                 const uint32_t *__restrict__ cstart, const uint64_t *__restrict__ nchunks_dev,
+                 uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t S,
+                 uint32_t lead, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
+                 unsigned long long *__restrict__ columns) {
+    extern __shared__ uint32_t rows[];  // (sigma + 1) rows of S words
+    const uint32_t lane = threadIdx.x;
+    const uint32_t nch = (uint32_t)*nchunks_dev;
+    for (;;) {
+        uint32_t ch = 0;
+        if (lane == 0) ch = atomicAdd(next, 1u);
+        ch = readlane_u32(ch, 0);
+        if (ch >= nch) break;
+        const uint32_t cs = cstart[ch], ce = cstart[ch + 1];
+        const bool act = cs + lane < ce;
+        const uint32_t pidx = act ? order[cs + lane] : 0u;
+        PairView v = view_pair(A, A, pairs, Kq, K, pidx, act);
+        // the chunk's pattern (every pair of the chunk has it), from its first pair
+        const uint64_t c0 = pairs[order[cs]];
+        const uint32_t a0 = (uint32_t)(c0 >> 32), b0i = (uint32_t)c0;
+        const uint64_t la0 = A.off[a0 + 1] - A.off[a0], lb0 = A.off[b0i + 1] - A.off[b0i];
+        const uint32_t pat = la0 >= lb0 ? a0 : b0i;
+        const uint32_t m = (uint32_t)(la0 >= lb0 ? la0 : lb0);
+        const uint32_t W = (m + 31) / 32;
+        const uint32_t *mw = A.mw + A.moff[pat];
+        const uint32_t used = lead + W + NW + 2;  // words of each row this pattern needs
+        // the previous chunk's lanes are done with the rows
+        __syncthreads();
+        for (uint32_t t = lane; t < (sigma + 1) * used; t += 64) {
+            const uint32_t c = t / used, i = t - c * used;
+            uint32_t x = 0xFFFFFFFFu;  // the padding symbol matches everything
+            if (c < sigma) x = (i >= lead && i - lead < W) ? mw[(size_t)c * W + (i - lead)] : 0u;
+            rows[c * S + i] = x;
+        }
+        __syncthreads();
+        bool has = false;
+        uint32_t Pv[NW], Mv[NW], tw[8], Zt = 0, kstar = 0, jb = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) Pv[w] = Mv[w] = 0;
+        if (act) {
+            if (v.skip || v.nn == 0) {
+                dist[pidx] = (int32_t)(v.skip ? v.Kp + 1 : min(v.dstar, v.Kp + 1));
+            } else {
+                has = true;
+                kstar = v.O + v.dstar;
+                lane_state_init<NW>(v.O, Pv, Mv);
+            }
+        }
+        lane_text_block(v.yp, has ? v.nn : 0u, 0, sigma, tw);
+        while (__builtin_amdgcn_ballot_w64(has)) {
+            uint32_t tn[8];
+            lane_text_block(v.yp, has ? v.nn : 0u, jb + 32, sigma, tn);
+            // lanes without a pair run on the padding row (all ones): their
+            // state stays fixed and nothing of it is read
+            grp_block<NW>(rows + lead, S, (int32_t)jb - (int32_t)v.O - 1, tw, Pv, Mv, Zt);
+            jb += 32;
+#pragma unroll
+            for (int q = 0; q < 8; q++) tw[q] = tn[q];
+            if (has) {
+                uint32_t P = 0, M = 0;
+#pragma unroll
+                for (int w = 0; w < NW; w++) {
+                    const int d = (int)kstar - 32 * w;
+                    uint32_t mk = d >= 31 ? 0xFFFFFFFFu : (d < 0 ? 0u : (2u << d) - 1u);
+                    if (w == 0) mk &= ~1u;
+                    P = popc_acc(Pv[w] & mk, P);
+                    M = popc_acc(Mv[w] & mk, M);
+                }
+                const uint32_t Vd = v.O + jb - Zt + P - M;
+                if (Vd > v.Kp || jb >= v.nn) {
+                    dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
+                    if (columns) atomicAdd(columns, (unsigned long long)min(jb, v.nn));
+                    has = false;
+                }
+            }
+        }
+    }
+}
+
+using GrpKernel = void (*)(StrSet, const uint64_t *, const uint32_t *, const uint32_t *,
+                           const uint64_t *, uint32_t, const uint32_t *, uint32_t, uint32_t,
+                           uint32_t, uint32_t *, int32_t *, unsigned long long *);
+
+GrpKernel grp_kernel(uint32_t nw) {
+    switch (nw) {
+        case 1: return k_verify_grp<1>;
+        case 2: return k_verify_grp<2>;
+        case 3: return k_verify_grp<3>;
+        case 4: return k_verify_grp<4>;
+        case 5: return k_verify_grp<5>;
+        case 6: return k_verify_grp<6>;
+        case 7: return k_verify_grp<7>;
+        case 8: return k_verify_grp<8>;
+        case 9: return k_verify_grp<9>;
+        case 10: return k_verify_grp<10>;
+        case 11: return k_verify_grp<11>;
+        case 12: return k_verify_grp<12>;
+        case 13: return k_verify_grp<13>;
+        case 14: return k_verify_grp<14>;
+        case 15: return k_verify_grp<15>;
+        case 16: return k_verify_grp<16>;
+        default: return nullptr;
     }
 }
 
@@ -1267,8 +1532,12 @@ SplitKernel split_kernel(uint32_t wpl) {
 
 // Words per lane window: (sigma + 1) rows of NW + 1 words, padded to an odd
 // count so that the 64 lanes' windows start in distinct LDS banks.
+// Words per lane of the lane form: (sigma + 1) rows of nw + 1 window words
+// (the symbols and the all-ones padding row); alphabets above 4 symbols keep
+// one more word per symbol after the rows (the low source word of the next
+// entering mask word).  Odd, so that lanes fall on different banks.
 inline uint32_t lane_region(uint32_t nw, uint32_t sigma) {
-    const uint32_t r = (sigma + 1) * (nw + 1);
+    const uint32_t r = (sigma + 1) * (nw + 1) + (sigma > 4 ? sigma : 0u);
     return r | 1u;
 }
 
@@ -1353,6 +1622,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     if (NL == 0)
         fail(EJ_EUNSUPPORTED,
              "threshold " + std::to_string(Kmax) + " exceeds 2046 (band > 2048 bits)");
+    const bool self_set = d_codes_b == nullptr;  // the pairs are of one string set
     if (!d_codes_b) {
         d_codes_b = d_codes;
         d_offsets_b = d_offsets;
@@ -1397,6 +1667,72 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     auto kmark = [&]() {
         if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
     };
+    // grouped by pattern: the candidates' patterns share LDS rows per chunk
+    if (ctx->tune.verify_mode == 3 && self_set && NL <= LANE_MAX_WORDS) {
+        const uint32_t lead = (Kmax / 2 + 1 + 31) / 32;
+        const uint32_t S = lead + (maxlen + 31) / 32 + NL + 2;
+        const size_t glds = (size_t)(sig + 1) * S * 4;
+        if (glds <= (size_t)ctx->lds_max) {
+            ctx->last_verify_form = 4;
+            uint32_t *gkey = ws<uint32_t>(ctx, "vg_key", count);
+            uint32_t *gval = ws<uint32_t>(ctx, "vg_val", count);
+            uint32_t *gkey2 = ws<uint32_t>(ctx, "vg_key2", count);
+            uint32_t *gorder = ws<uint32_t>(ctx, "vg_order", count);
+            uint32_t *cflag = ws<uint32_t>(ctx, "vg_cflag", count);
+            uint32_t *cpos = ws<uint32_t>(ctx, "vg_cpos", count);
+            uint32_t *cstart = ws<uint32_t>(ctx, "vg_cstart", count + 1);
+            uint64_t *d_nch = ws<uint64_t>(ctx, "vg_nchunks", 1);
+            uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
+            const GrpKernel gk = grp_kernel(NL);
+            if (glds > 65536)
+                EJ_HIP(hipFuncSetAttribute((const void *)gk,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)glds));
+            int occ = 0;
+            EJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gk, 64, glds));
+            if (occ < 1) occ = 1;
+            const uint32_t per_cu =
+                std::max(1u, std::min((uint32_t)occ, ctx->tune.verify_blocks_per_cu));
+            const uint64_t grid =
+                std::min<uint64_t>((count + 63) / 64, (uint64_t)ctx->num_cu * per_cu);
+            // pairs ordered by pattern, cut into chunks (no host round trip)
+            hipLaunchKernelGGL(k_grp_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
+                               ctx->stream, A.off, d_pairs, count, d_count, gkey, gval);
+            EJ_CHECK_LAUNCH();
+            radix_sort_u32(ctx, gkey, gval, gkey2, gorder, 1, (uint32_t)count, 32,
+                           ctx->tune.radix_bits);
+            hipLaunchKernelGGL(k_grp_chunk_flags, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)gkey2, count, d_count, cflag);
+            EJ_CHECK_LAUNCH();
+            scan_exclusive_u32(ctx, cflag, cpos, count, d_nch);
+            hipLaunchKernelGGL(k_grp_chunk_starts, dim3(grid_for(ctx, count, 256)), dim3(256),
+                               0, ctx->stream, (const uint32_t *)cflag, (const uint32_t *)cpos,
+                               count, d_count, (const uint64_t *)d_nch, cstart);
+            EJ_CHECK_LAUNCH();
+            char key[384];
+            snprintf(key, sizeof(key),
+                     "verify_grp %u %p %p %llu %p %p %p %p %p %p %u %p %u %u %u %p %p %p %llu "
+                     "%zu %llu",
+                     NL, (const void *)d_codes, (const void *)d_offsets, (unsigned long long)base,
+                     (const void *)A.mw, (const void *)A.moff, (const void *)d_pairs,
+                     (const void *)gorder, (const void *)cstart, (const void *)d_nch, K,
+                     (const void *)d_Kq, sig, S, lead, (void *)next, (void *)d_dist,
+                     (void *)d_columns, (unsigned long long)grid, glds,
+                     (unsigned long long)ctx->ws_gen);
+            kmark();
+            run_captured(ctx, key, [&] {
+                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
+                EJ_CHECK_LAUNCH();
+                hipLaunchKernelGGL(gk, dim3((uint32_t)grid), dim3(64), glds, ctx->stream, A,
+                                   d_pairs, (const uint32_t *)gorder, (const uint32_t *)cstart,
+                                   (const uint64_t *)d_nch, K, d_Kq, sig, S, lead, next, d_dist,
+                                   d_columns);
+                EJ_CHECK_LAUNCH();
+            });
+            kmark();
+            return;
+        }
+    }
     // the lane family: KL lanes per pair (1: the whole band in one lane)
     uint32_t KL = ctx->tune.verify_split;
     // (the split lanes take alphabets of up to 4 symbols; larger ones use one

@@ -36,10 +36,10 @@ def ctx(ej):
 
 def _each_verify_mode(ctx):
     """Runs the body once per verification form (two-pass, persistent tiles,
-    one pair per lane)."""
+    one pair per lane, grouped by pattern)."""
     old = ctx.tune_get("verify_mode")
     try:
-        for mode in (0, 1, 2):
+        for mode in (0, 1, 2, 3):
             ctx.tune_set("verify_mode", mode)
             yield mode
     finally:
@@ -265,6 +265,10 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
             _say(f"verify lane form K={K} split={split}")
             got = ctx.verify(chars, offs, d_codes, K)
             assert got.cpu().numpy().astype(np.uint32).tolist() == want
+        ctx.tune_set("verify_mode", 3)
+        _say(f"verify grouped by pattern K={K}")
+        got = ctx.verify(chars, offs, d_codes, K)
+        assert got.cpu().numpy().astype(np.uint32).tolist() == want
     finally:
         ctx.tune_set("verify_ring", old[0])
         ctx.tune_set("verify_pass1_cols", old[1])
@@ -485,7 +489,7 @@ def test_autotune_keeps_results(ej, ctx, oracle_lib):
         _say("autotune")
         best, knobs = ctx.autotune(chars, offs, K, r, z, m, seed=8, L=L, reps=1)
         assert best > 0
-        assert knobs["verify_mode"] in (0, 1, 2) and 4 <= knobs["radix_bits"] <= 11
+        assert knobs["verify_mode"] in (0, 1, 2, 3) and 4 <= knobs["radix_bits"] <= 11
         res = ctx.join(chars, offs, K, r, z, m, seed=8, L=L)
         _assert_join_equal(res, ref)
     finally:
@@ -583,6 +587,15 @@ def test_lane_form_wide_alphabets(ej, ctx, oracle_lib, letters, K):
         _assert_join_equal(res, _oracle_join(oracle_lib, col, K, 3, 5, 4, 2, 64))
         if K <= 254 and res.n_candidates:
             assert res.verify_form == 2
+        # grouped by pattern (bands up to 16 words)
+        ctx.tune_set("verify_mode", 3)
+        _say(f"grouped form {letters} K={K}")
+        got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+        assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+        res = ctx.join(chars, offs, K, 3, 5, 4, seed=2, L=64, flags=ej.FLAG_TIMING)
+        _assert_join_equal(res, _oracle_join(oracle_lib, col, K, 3, 5, 4, 2, 64))
+        if K <= 510 and res.n_candidates:
+            assert res.verify_form == 4
     finally:
         for k, v in old.items():
             ctx.tune_set(k, v)
@@ -603,7 +616,7 @@ def test_graph_replays_match_eager(ej, ctx, oracle_lib):
     ref2 = _oracle_join(oracle_lib, col2, 20, r, z, m, 4, L)
     old = ctx.tune_get("verify_mode")
     try:
-        for mode in (0, 1, 2):
+        for mode in (0, 1, 2, 3):
             ctx.tune_set("verify_mode", mode)
             ran = []
             for i in range(4):
@@ -656,7 +669,7 @@ def test_whole_join_graph_capacity_overflow(ej, ctx, oracle_lib):
     assert len(ref_d.cand) > 4 * len(ref_s.cand) + 10000 and ref_d.n_raw > 100 * ref_s.n_raw
     chars, offs = to_device(sparse)
     dchars = torch.from_numpy(dense.chars.copy()).cuda()
-    for mode, dsort in ((1, 0), (2, 0), (0, 1)):
+    for mode, dsort in ((1, 0), (2, 0), (0, 1), (3, 0)):
         ctx.tune_set("verify_mode", mode)
         ctx.tune_set("dedup_sort", dsort)
         chars.copy_(torch.from_numpy(sparse.chars.copy()).cuda())
@@ -677,3 +690,50 @@ def test_whole_join_graph_capacity_overflow(ej, ctx, oracle_lib):
         assert res.graph == 2
     ctx.tune_set("verify_mode", 0)
     ctx.tune_set("dedup_sort", 0)
+
+
+def test_grouped_form_many_partners_per_pattern(ej, ctx, oracle_lib):
+    """Grouped by pattern: runs of one pattern longer than a chunk (64 pairs),
+    patterns of very different lengths in one launch, pairs whose lengths
+    differ by more than K, empty texts, per-pair thresholds and a device
+    count (through the whole-join graph)."""
+    import torch
+    rng = np.random.default_rng(12)
+    DNA = np.frombuffer(b"ACGT", np.uint8)
+    base = DNA[rng.integers(0, 4, size=900)]
+    strings = [bytes(sd.mutate(rng, base[:int(rng.integers(600, 900))], int(rng.poisson(20)), DNA))
+               for _ in range(150)]
+    strings += [bytes(DNA[rng.integers(0, 4, size=int(x))]) for x in rng.integers(0, 120, 60)]
+    strings += [b"", b"A"]
+    col = sd.from_strings(strings)
+    n = col.n
+    a = np.repeat(np.arange(5), 200)            # five patterns with 200 partners each
+    b = rng.integers(0, n, size=a.size)
+    a2 = rng.integers(0, n, size=800)
+    b2 = rng.integers(0, n, size=800)
+    aa, bb = np.concatenate([a, a2]), np.concatenate([b, b2])
+    codes = (aa.astype(np.uint64) << np.uint64(32)) | bb.astype(np.uint64)
+    chars, offs = to_device(col)
+    d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
+    old = ctx.knobs()
+    try:
+        ctx.tune_set("verify_mode", 3)
+        for K in (0, 40, 200, 510):
+            want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+            _say(f"grouped many partners K={K}")
+            got = ctx.verify(chars, offs, d_codes, K).cpu().numpy()
+            assert got.astype(np.uint32).tolist() == want.tolist()
+        Kq = rng.integers(0, 300, size=codes.size).astype(np.int32)
+        want = np.array([oracle_lib.verify_pairs(col.chars, col.offsets, codes[i:i + 1], int(k))[0]
+                         for i, k in enumerate(Kq)])
+        got = ctx.verify(chars, offs, d_codes, 0, d_Kq=torch.from_numpy(Kq).cuda()).cpu().numpy()
+        assert got.astype(np.uint32).tolist() == want.tolist()
+        K, r, z, m, L = 60, 3, 5, 6, 64
+        ref = _oracle_join(oracle_lib, col, K, r, z, m, 6, L)
+        for i in range(4):
+            res = ctx.join(chars, offs, K, r, z, m, seed=6, L=L, flags=ej.FLAG_GRAPH)
+            _assert_join_equal(res, ref)
+        assert res.graph == 2
+    finally:
+        for k, v in old.items():
+            ctx.tune_set(k, v)

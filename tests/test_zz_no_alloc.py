@@ -80,7 +80,7 @@ def test_static_verify_every_form_and_per_pair_thresholds(ej, oracle_lib):
     dKq = torch.from_numpy(Kq).cuda()
     ctx = ej.Context(0)
     try:
-        for mode in (0, 1, 2):
+        for mode in (0, 1, 2, 3):
             ctx.tune_set("verify_mode", mode)
             for K, kq in ((300, None), (0, dKq)):
                 want = ctx.verify(chars, offs, pairs, K, d_Kq=kq).cpu().numpy()
