@@ -625,15 +625,26 @@ def uneven_leg(ej, ctx, oracle, args, peak, col):
     pa = (pw >> np.uint64(32)).astype(np.int64)
     pb = (pw & np.uint64(0xFFFFFFFF)).astype(np.int64)
     long_pw = pw[np.maximum(lens[pa], lens[pb]) > S]
-    # the join with the short pass, timed like the forms (batched knobs)
+    # the join with the short pass (every short string has thousands of
+    # partners: the form grouped by pattern against the default two-pass form)
     fl = ej.FLAG_TIMING | ej.FLAG_DEVICE_OUT
 
     def hybrid():
         return ctx.join(chars, offs, K, prm["r"], prm["z"], prm["m"], seed=0, L=prm["L"],
                         flags=fl, exact_len=S)
 
-    hres, hms, hstage = time_join(hybrid, max(1, min(args.steps, 3)), 1)
+    runs = {}
+    old_mode = ctx.tune_get("verify_mode")
+    for mode in (3, 0):
+        ctx.tune_set("verify_mode", mode)
+        runs[mode] = time_join(hybrid, max(1, min(args.steps, 3)), 1)
+    ctx.tune_set("verify_mode", old_mode)
+    best = min(runs, key=lambda k: runs[k][1])
+    hres, hms, hstage = runs[best]
     out["with_short_pass"] = dict(exact_len=S, join_sec=round(hms / 1e3, 5),
+                                  verify_mode=best, kernel=VERIFY_KERNEL[hres.verify_form],
+                                  join_sec_by_verify_mode={str(k): round(v[1] / 1e3, 5)
+                                                           for k, v in runs.items()},
                                   stage_ms={k: round(v, 3) for k, v in hstage.items()},
                                   candidates=hres.n_candidates, output_pairs=hres.count,
                                   verified_pairs_per_s=round(hres.n_candidates / (hms / 1e3), 3))
