@@ -700,18 +700,21 @@ def test_grouped_form_many_partners_per_pattern(ej, ctx, oracle_lib):
     import torch
     rng = np.random.default_rng(12)
     DNA = np.frombuffer(b"ACGT", np.uint8)
-    base = DNA[rng.integers(0, 4, size=900)]
-    strings = [bytes(sd.mutate(rng, base[:int(rng.integers(600, 900))], int(rng.poisson(20)), DNA))
-               for _ in range(150)]
+    # patterns on both sides of 1,024 letters (the two launches of the form)
+    base = DNA[rng.integers(0, 4, size=1500)]
+    strings = [bytes(sd.mutate(rng, base[:int(rng.integers(600, 1500))], int(rng.poisson(20)),
+                               DNA)) for _ in range(150)]
     strings += [bytes(DNA[rng.integers(0, 4, size=int(x))]) for x in rng.integers(0, 120, 60)]
-    strings += [b"", b"A"]
+    strings += [b"", b"A", b""]
     col = sd.from_strings(strings)
     n = col.n
     a = np.repeat(np.arange(5), 200)            # five patterns with 200 partners each
+    # pairs of empty strings (an empty pattern) among them
     b = rng.integers(0, n, size=a.size)
     a2 = rng.integers(0, n, size=800)
     b2 = rng.integers(0, n, size=800)
-    aa, bb = np.concatenate([a, a2]), np.concatenate([b, b2])
+    aa = np.concatenate([a, a2, [n - 3, n - 1, n - 3]])
+    bb = np.concatenate([b, b2, [n - 1, n - 3, n - 2]])
     codes = (aa.astype(np.uint64) << np.uint64(32)) | bb.astype(np.uint64)
     chars, offs = to_device(col)
     d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
