@@ -81,6 +81,15 @@ __device__ inline uint32_t add_carry_in(uint32_t a, uint64_t cin) {
     return s;
 }
 
+// The verified-column counter: each lane sums the columns of the pairs it
+// decided, and a wave adds once when it leaves (one atomic per wave instead of
+// one per pair, which contended on the counter's line).
+__device__ inline void add_columns(unsigned long long *columns, unsigned long long v) {
+    if (!columns) return;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63u) == 0 && v) atomicAdd(columns, v);
+}
+
 // popcount(x) + acc in one v_bcnt.
 __device__ inline uint32_t popc_acc(uint32_t x, uint32_t acc) {
     uint32_t r;
@@ -278,6 +287,7 @@ __global__ void __launch_bounds__(64)
              uint32_t *__restrict__ state, uint32_t *__restrict__ aux,
              int32_t *__restrict__ dist, unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    unsigned long long colsum = 0;  // text columns of the pairs decided here
     const uint32_t NL = lanes_of<MODE>(NL_arg);
     // pass 2, and a join sized on the device, take the pair count from the
     // device (a grid sized for all pairs; never more than count_arg)
@@ -395,9 +405,10 @@ __global__ void __launch_bounds__(64)
                 dist[pidx] = (int32_t)res;
                 if (aux && !resume) aux[pidx] = DECIDED;
             }
-            if (columns) atomicAdd(columns, (unsigned long long)(cols - min(jbeg, cols)));
+            colsum += (unsigned long long)(cols - min(jbeg, cols));
         }
     }
+    add_columns(columns, colsum);
 }
 
 // Persistent form.  The grid stays resident and every tile (the NL lanes of
@@ -418,6 +429,7 @@ __global__ void __launch_bounds__(64)
                    uint32_t wpp, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                    unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    unsigned long long colsum = 0;  // text columns of the pairs decided here
     const uint32_t NL = lanes_of<MODE>(NL_arg);
     // a count on the device (a join sized on the device): at most `count`
     if (count_dev) count = (uint32_t)min<uint64_t>(*count_dev, count);
@@ -536,13 +548,14 @@ __global__ void __launch_bounds__(64)
         const bool tile_fin = in_tile && active && ((fin >> (owner_lane & 63)) & 1ull);
         if (fin_owner) {
             dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
-            if (columns) atomicAdd(columns, (unsigned long long)cols);
+            colsum += (unsigned long long)cols;
         }
         if (tile_fin) {
             need = true;
             owner = false;
         }
     }
+    add_columns(columns, colsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -675,6 +688,7 @@ __global__ void __launch_bounds__(64)
                   unsigned long long *__restrict__ columns) {
     constexpr uint32_t RS = NW + 1;  // words per symbol row of a window
     extern __shared__ uint32_t lds[];
+    unsigned long long colsum = 0;  // text columns of the pairs decided here
     if (count_dev) count = (uint32_t)min<uint64_t>(*count_dev, count);
     const uint32_t lane = threadIdx.x;
     uint32_t *win = lds + lane * region;
@@ -837,11 +851,12 @@ __global__ void __launch_bounds__(64)
             const uint32_t Vd = v.O + jb - Zt + P - M;
             if (Vd > v.Kp || jb >= v.nn) {
                 dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
-                if (columns) atomicAdd(columns, (unsigned long long)min(jb, v.nn));
+                colsum += (unsigned long long)min(jb, v.nn);
                 has = false;
             }
         }
     }
+    add_columns(columns, colsum);
 }
 
 // ---------------------------------------------------------------------------
@@ -978,6 +993,7 @@ __global__ void __launch_bounds__(64)
                  uint32_t lead, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                  unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t rows[];  // (sigma + 1) rows of S words
+    unsigned long long colsum = 0;  // text columns of the pairs decided here
     const uint32_t lane = threadIdx.x;
     const uint32_t nch = (uint32_t)*nchunks_dev;
     for (;;) {
@@ -1043,12 +1059,13 @@ __global__ void __launch_bounds__(64)
                 const uint32_t Vd = v.O + jb - Zt + P - M;
                 if (Vd > v.Kp || jb >= v.nn) {
                     dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
-                    if (columns) atomicAdd(columns, (unsigned long long)min(jb, v.nn));
+                    colsum += (unsigned long long)min(jb, v.nn);
                     has = false;
                 }
             }
         }
     }
+    add_columns(columns, colsum);
 }
 
 using GrpKernel = void (*)(StrSet, const uint64_t *, const uint32_t *, const uint32_t *,
@@ -1226,6 +1243,7 @@ __global__ void __launch_bounds__(64, WPL <= 4 ? 6 : 1)
                    uint32_t region, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                    unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t lds[];
+    unsigned long long colsum = 0;  // text columns of the pairs decided here
     if (count_dev) count = (uint32_t)min<uint64_t>(*count_dev, count);
     constexpr int TQ = 4;  // text dwords per lane, at most (8 / KL, KL >= 2)
     const uint32_t lane = threadIdx.x;
@@ -1369,12 +1387,13 @@ __global__ void __launch_bounds__(64, WPL <= 4 ? 6 : 1)
             if (Vd > v.Kp || jb >= v.nn) {
                 if (l == 0) {
                     dist[pidx] = (int32_t)min(Vd, v.Kp + 1);
-                    if (columns) atomicAdd(columns, (unsigned long long)min(jb, v.nn));
+                    colsum += (unsigned long long)min(jb, v.nn);
                 }
                 has = false;
             }
         }
     }
+    add_columns(columns, colsum);
 }
 
 // Mask words of every string: sigma * ceil(len / 32).

@@ -740,3 +740,29 @@ def test_grouped_form_many_partners_per_pattern(ej, ctx, oracle_lib):
     finally:
         for k, v in old.items():
             ctx.tune_set(k, v)
+
+
+def test_verified_columns_counter(ej, ctx, oracle_lib):
+    """EJ_FLAG_TIMING's count of verified text columns (summed per wave, one
+    atomic each): the same over repeated joins, positive, at most the total
+    text length of the candidates rounded up to 32-column blocks, and at
+    least the text length of every output pair (those run to their end)."""
+    col = sd.clusters(51, 30, lambda rr, b: 4, lambda rr: rr.integers(100, 700),
+                      lambda rr, LL: rr.poisson(8))
+    K, r, z, m, L = 40, 4, 6, 4, 48
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 5, L)
+    lens = col.lengths().astype(np.int64)
+    ca = (ref.cand >> np.uint64(32)).astype(np.int64)
+    cb = (ref.cand & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    text = np.minimum(lens[ca], lens[cb])
+    oa = (ref.out >> np.uint64(32)).astype(np.int64)
+    ob = (ref.out & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    chars, offs = to_device(col)
+    for mode in _each_verify_mode(ctx):
+        a = ctx.join(chars, offs, K, r, z, m, seed=5, L=L, flags=ej.FLAG_TIMING)
+        b = ctx.join(chars, offs, K, r, z, m, seed=5, L=L, flags=ej.FLAG_TIMING)
+        _assert_join_equal(a, ref)
+        _say(f"verified columns mode={mode}: {a.verify_columns}")
+        assert a.verify_columns == b.verify_columns > 0
+        assert a.verify_columns <= int((((text + 31) // 32) * 32).sum())
+        assert a.verify_columns >= int(np.minimum(lens[oa], lens[ob]).sum())
