@@ -183,109 +183,296 @@ struct TupleCoder {
     }
 };
 
-// Entry e's walk, given that entry e + 1 is in its group (top bits d).
-template <bool EMIT, typename C, typename Coder>
-__device__ inline uint32_t pair_walk(uint32_t e, uint32_t d, uint32_t send,
+// The window of entry e (its table ends at send, its top bits are d): the
+// following entries with top bits d and length at most lim.  A table's
+// entries are sorted by (top bits, length), so the window is the run
+// [e + 1, e + 1 + W) and membership is monotone along the table: doubling
+// steps, then bisection, find W in O(log W) reads.
+__device__ inline uint32_t pw_window(uint32_t e, uint32_t d, uint32_t send, uint64_t lim,
                                      const uint32_t *__restrict__ dk,
-                                     const uint64_t *__restrict__ key_s,
-                                     const uint32_t *__restrict__ len_s,
-                                     const uint32_t *__restrict__ ids, uint32_t K,
-                                     const Coder &coder, C *__restrict__ out) {
-    constexpr bool ALWAYS = std::is_same<Coder, PairCoder>::value;
-    uint32_t q = e + 1;
-    const uint64_t ke = key_s[e];
-    const uint64_t lim = (uint64_t)len_s[e] + K;
-    const uint32_t ide = (EMIT || !ALWAYS) ? ids[e] : 0u;
-    uint32_t c = 0;
-    for (; q < send; q++) {
-        if (dk[q] != d || (uint64_t)len_s[q] > lim) break;
-        if (key_s[q] == ke) {
-            if (ALWAYS && !EMIT) {
-                c++;
-                continue;
-            }
-            const uint32_t idq = ids[q];
-            if (!coder.pairs(ide, idq)) continue;
-            if (EMIT) out[c] = (C)coder.code(ide, idq);
-            c++;
-        }
+                                     const uint32_t *__restrict__ len_s) {
+    auto in = [&](uint64_t q) {
+        return q < send && dk[q] == d && (uint64_t)len_s[q] <= lim;
+    };
+    uint64_t lo = e, step = 1;  // every q in (e, lo] is in the window
+    while (in(lo + step)) {
+        lo += step;
+        step *= 2;
     }
-    return c;
+    uint64_t hi = lo + step;  // not in the window
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (in(mid))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return (uint32_t)(lo - e);
 }
 
-constexpr uint32_t PW_IPT = 4;                 // entries per thread
-constexpr uint32_t PW_TILE = 256 * PW_IPT;     // entries per workgroup
+constexpr uint32_t PW_WAVES = 4;        // waves per workgroup of the light walk
+constexpr uint32_t PW_LIGHT = 64;       // windows up to this size: the light walk
+constexpr uint32_t PW_SEG = 64 * 64;    // positions per heavy task (64 sweeps of a wave)
 
-// EMIT = false: per-thread pair counts (saturated to 32 bits; a total that
-// large is rejected before the emit pass) and per-workgroup totals.
-// EMIT = true: each thread writes its entries' pairs, in entry order, from
-// the workgroup's offset plus the exclusive scan of the thread counts.
-// Entry of (thread x, round i) = tile start + 256 i + x.
+// Light walk: one wave per 64 consecutive entries, one per lane.  The lanes
+// find their windows (pw_window); windows of at most PW_LIGHT positions are
+// then run by the whole wave, laid end to end, 64 positions at a time:
+// position f belongs to the lane whose window covers it (bisection over the
+// wave's inclusive scan of window sizes, read across lanes) and is a pair
+// when the entry there has the owner's full key (and, for tuples, is a
+// suffix of another string).  Loads of consecutive positions are
+// consecutive entries, and the pairs are written contiguously (ballot and
+// popcount give the slots).  Longer windows are cut into tasks of PW_SEG
+// positions for k_pairs_heavy, so no wave runs more than 64 sweeps.
+// EMIT = false: wlen[e] = the window size, cnt[w] = the wave's light pairs,
+// ntask[w] = the wave's heavy tasks.
+// EMIT = true: writes the light pairs from cur[w] (the exclusive scan of the
+// wave totals, light and heavy) and leaves cur[w] just past them, where
+// k_pairs_heavy continues.  Nothing at or past cap is written (a buffer
+// sized before the count may be too small: the caller sees the count and
+// redoes the join).
 template <bool EMIT, typename C, typename Coder>
 __global__ void __launch_bounds__(256)
     k_pairs_dk(const uint32_t *__restrict__ dk, const uint64_t *__restrict__ key_s,
                const uint32_t *__restrict__ len_s, const uint32_t *__restrict__ ids, uint32_t n,
-               uint32_t tot, uint32_t K, Coder coder, uint32_t *__restrict__ tcount,
-               uint64_t *__restrict__ wg_count, const uint64_t *__restrict__ wg_off,
-               C *__restrict__ out, uint64_t cap) {
-    __shared__ uint64_t red[4];
-    const uint32_t x = threadIdx.x, lane = x & 63, wave = x >> 6;
-    const uint64_t base = (uint64_t)blockIdx.x * PW_TILE;
-    // the group test of all the thread's entries first (coalesced loads
-    // issued together); only entries with a partner in their group walk
-    uint32_t dd[PW_IPT], send[PW_IPT], act = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < PW_IPT; i++) {
-        const uint64_t e = base + 256 * i + x;
-        dd[i] = 0;
-        send[i] = 0;
-        if (e < tot) {
-            send[i] = ((uint32_t)e / n + 1) * n;
-            dd[i] = dk[e];
+               uint32_t tot, uint32_t K, Coder coder, uint32_t *__restrict__ wlen,
+               uint64_t *__restrict__ cnt, uint32_t *__restrict__ ntask,
+               uint64_t *__restrict__ cur, C *__restrict__ out, uint64_t cap) {
+    constexpr bool ALWAYS = std::is_same<Coder, PairCoder>::value;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wv = blockIdx.x * PW_WAVES + (threadIdx.x >> 6);
+    const uint64_t rbase = (uint64_t)wv * 64;
+    const uint64_t e64 = rbase + lane;
+    const uint32_t e = (uint32_t)e64;
+    uint32_t W = 0;
+    if (e64 < tot) {
+        if (EMIT) {
+            W = wlen[e];
+        } else {
+            const uint32_t send = (e / n + 1) * n;
+            const uint32_t d = dk[e];
+            if (e + 1 < send && dk[e + 1] == d)
+                W = pw_window(e, d, send, (uint64_t)len_s[e] + K, dk, len_s);
+            wlen[e] = W;
         }
     }
-#pragma unroll
-    for (uint32_t i = 0; i < PW_IPT; i++) {
-        const uint64_t e = base + 256 * i + x;
-        if (e + 1 < send[i] && dk[e + 1] == dd[i]) act |= 1u << i;
-    }
+    const uint32_t Wl = W <= PW_LIGHT ? W : 0u;
     if (!EMIT) {
-        uint64_t s = 0;
+        uint32_t tasks = W > PW_LIGHT ? (W + PW_SEG - 1) / PW_SEG : 0u;
 #pragma unroll
-        for (uint32_t i = 0; i < PW_IPT; i++)
-            if (act & (1u << i))
-                s += pair_walk<false, C>((uint32_t)(base + 256 * i + x), dd[i], send[i], dk, key_s,
-                                         len_s, ids, K, coder, (C *)nullptr);
-        tcount[blockIdx.x * 256 + x] = s > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)s;
-        uint64_t w = s;
-        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o, 64);
-        if (lane == 0) red[wave] = w;
-        __syncthreads();
-        if (x == 0) wg_count[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        for (int o = 32; o > 0; o >>= 1) tasks += __shfl_xor(tasks, o, 64);
+        if (lane == 0 && rbase < tot) ntask[wv] = tasks;
+    }
+    uint32_t incl = Wl;  // at most 64 * PW_LIGHT
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+        const uint32_t y = __shfl_up(incl, (unsigned)s, 64);
+        if (lane >= (uint32_t)s) incl += y;
+    }
+    const uint32_t total = __shfl(incl, 63, 64);
+    uint64_t o = 0, c = 0;
+    if (EMIT && rbase < tot) o = cur[wv];
+    if (total) {
+        const uint64_t ke = Wl ? key_s[e] : 0;
+        const uint32_t ide = (Wl && (EMIT || !ALWAYS)) ? ids[e] : 0u;
+        for (uint32_t b = 0; b < total; b += 64) {
+            const uint32_t f = b + lane;
+            // owner: the number of lanes whose windows end at or before f
+            uint32_t j = 0;
+#pragma unroll
+            for (uint32_t s = 32; s > 0; s >>= 1)
+                if ((uint32_t)__shfl(incl, (int)(j + s - 1), 64) <= f) j += s;
+            j = min(j, 63u);
+            const uint32_t jend = __shfl(incl, (int)j, 64);
+            const uint32_t jw = __shfl(Wl, (int)j, 64);
+            const uint64_t kj = __shfl(ke, (int)j, 64);
+            const uint32_t idj = (EMIT || !ALWAYS) ? __shfl(ide, (int)j, 64) : 0u;
+            bool hit = false;
+            uint32_t idq = 0;
+            if (f < total) {
+                const uint64_t q = rbase + j + 1 + (f - (jend - jw));
+                if (key_s[q] == kj) {
+                    if (EMIT || !ALWAYS) {
+                        idq = ids[q];
+                        hit = coder.pairs(idj, idq);
+                    } else {
+                        hit = true;
+                    }
+                }
+            }
+            const uint64_t m = __ballot(hit);
+            if (EMIT) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const uint64_t slot = o + below;
+                if (hit && slot < cap) out[slot] = (C)coder.code(idj, idq);
+                o += (uint64_t)__popcll(m);
+            } else {
+                c += (uint64_t)__popcll(m);
+            }
+        }
+    }
+    if (lane == 0 && rbase < tot) {
+        if (EMIT)
+            cur[wv] = o;
+        else
+            cnt[wv] = c;
+    }
+}
+
+// Heavy tasks: task t of the tasks numbered wave by wave (tbase = exclusive
+// scan of the per-wave task counts, ntot = their total) is segment s of the
+// window of one entry: positions [s * PW_SEG, min(W, (s + 1) * PW_SEG)).
+// Each wave of a persistent grid takes tasks t = its index, + the number of
+// waves: the task's wave by bisection over tbase, its lane and segment by
+// bisection over that wave's inclusive scan of task counts (read across
+// lanes).  All positions of a task share one owner.
+// EMIT = false: each task adds its pairs to cnt[w].
+// EMIT = true: a first sweep marks the pairs (one bit per sweep per lane),
+// one atomic on cur[w] reserves their slots, a second sweep writes them; the
+// slots of a wave's tasks follow its light pairs, in the order the tasks
+// reserve them.  A task total of 2^32 or more (impossible below 2^32 window
+// positions) poisons cnt[0] so that the caller's count is out of range.
+template <bool EMIT, typename C, typename Coder>
+__global__ void __launch_bounds__(256)
+    k_pairs_heavy(const uint64_t *__restrict__ key_s, const uint32_t *__restrict__ ids,
+                  uint32_t tot, Coder coder, const uint32_t *__restrict__ wlen,
+                  const uint32_t *__restrict__ tbase, uint32_t nw,
+                  const uint64_t *__restrict__ ntot, uint64_t *__restrict__ cnt,
+                  uint64_t *__restrict__ cur, C *__restrict__ out, uint64_t cap) {
+    constexpr bool ALWAYS = std::is_same<Coder, PairCoder>::value;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t nt = *ntot;
+    const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t ngw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    if (nt >> 32) {
+        if (!EMIT && gw == 0 && lane == 0) atomicAdd(cnt, 1ull << 40);
         return;
     }
-    // exclusive scan of the thread counts inside the workgroup (the total is
-    // below 2^32: the host has checked the sum of all counts)
-    const uint32_t v = tcount[blockIdx.x * 256 + x];
-    uint32_t incl = v;
+    for (uint64_t t = gw; t < nt; t += ngw) {
+        // the wave: the last w with tbase[w] <= t
+        uint32_t lo = 0, hi = nw - 1;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo + 1) / 2;
+            if ((uint64_t)tbase[mid] <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t w = lo;
+        const uint64_t e64 = (uint64_t)w * 64 + lane;
+        const uint32_t W = e64 < tot ? wlen[e64] : 0u;
+        const uint32_t segs = W > PW_LIGHT ? (W + PW_SEG - 1) / PW_SEG : 0u;
+        uint32_t incl = segs;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const uint32_t y = __shfl_up(incl, d, 64);
-        if (lane >= (uint32_t)d) incl += y;
+        for (int s = 1; s < 64; s <<= 1) {
+            const uint32_t y = __shfl_up(incl, (unsigned)s, 64);
+            if (lane >= (uint32_t)s) incl += y;
+        }
+        const uint32_t local = (uint32_t)(t - tbase[w]);
+        uint32_t j = 0;
+#pragma unroll
+        for (uint32_t s = 32; s > 0; s >>= 1)
+            if ((uint32_t)__shfl(incl, (int)(j + s - 1), 64) <= local) j += s;
+        j = min(j, 63u);
+        const uint32_t seg = local - ((uint32_t)__shfl(incl, (int)j, 64) -
+                                      (uint32_t)__shfl(segs, (int)j, 64));
+        const uint32_t Wj = (uint32_t)__shfl(W, (int)j, 64);
+        const uint64_t ej = (uint64_t)w * 64 + j;
+        const uint64_t kj = key_s[ej];
+        const uint32_t idj = (EMIT || !ALWAYS) ? ids[ej] : 0u;
+        const uint32_t p0 = seg * PW_SEG;
+        const uint32_t p1 = min(Wj, p0 + PW_SEG);
+        uint64_t bits = 0, c = 0;
+        for (uint32_t it = 0; p0 + it * 64 < p1; it++) {
+            const uint32_t p = p0 + it * 64 + lane;
+            bool hit = false;
+            if (p < p1) {
+                const uint64_t q = ej + 1 + p;
+                if (key_s[q] == kj) hit = ALWAYS ? true : coder.pairs(idj, ids[q]);
+            }
+            bits |= (uint64_t)hit << it;
+            c += (uint64_t)__popcll(__ballot(hit));
+        }
+        if (!EMIT) {
+            if (lane == 0 && c) atomicAdd(&cnt[w], c);
+            continue;
+        }
+        if (c == 0) continue;
+        uint64_t o = 0;
+        if (lane == 0) o = atomicAdd(&cur[w], c);
+        o = __shfl(o, 0, 64);
+        for (uint32_t it = 0; p0 + it * 64 < p1; it++) {
+            const bool hit = (bits >> it) & 1ull;
+            const uint64_t m = __ballot(hit);
+            if (hit) {
+                const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                const uint64_t slot = o + below;
+                if (slot < cap) out[slot] = (C)coder.code(idj, ids[ej + 1 + p0 + it * 64 + lane]);
+            }
+            o += (uint64_t)__popcll(m);
+        }
     }
-    if (lane == 63) red[wave] = incl;
-    __syncthreads();
-    uint64_t o = wg_off[blockIdx.x] + incl - v;
-    for (uint32_t w = 0; w < wave; w++) o += red[w];
-    // a buffer sized on the host before the count (a join sized on the
-    // device) may be too small: nothing past `cap` is written, and the host
-    // sees the count and redoes the join
-    if (v == 0 || o + v > cap) return;
-#pragma unroll
-    for (uint32_t i = 0; i < PW_IPT; i++)
-        if (act & (1u << i))
-            o += pair_walk<true, C>((uint32_t)(base + 256 * i + x), dd[i], send[i], dk, key_s,
-                                    len_s, ids, K, coder, out + o);
+}
+
+// Buffers of the pair walk over nw = ceil(tot / 64) waves.
+struct PairWalk {
+    uint32_t *wlen, *ntask, *tbase;
+    uint64_t *cnt, *ntot;
+    uint32_t nw, nwg;
+};
+
+PairWalk pw_buffers(ej_ctx *ctx, const std::string &t, uint64_t tot) {
+    PairWalk pw;
+    pw.nw = (uint32_t)((tot + 63) / 64);
+    pw.nwg = (pw.nw + PW_WAVES - 1) / PW_WAVES;
+    pw.wlen = ws<uint32_t>(ctx, t + "_wlen", tot);
+    pw.ntask = ws<uint32_t>(ctx, t + "_ntask", pw.nw);
+    pw.tbase = ws<uint32_t>(ctx, t + "_tbase", pw.nw);
+    pw.cnt = ws<uint64_t>(ctx, t + "_counts", pw.nw);
+    pw.ntot = ws<uint64_t>(ctx, t + "_ntasks", 1);
+    return pw;
+}
+
+uint32_t pw_heavy_grid(ej_ctx *ctx) { return (uint32_t)ctx->num_cu * 8; }
+
+// Counting pass: window sizes, per-wave pair counts, and their exclusive
+// scan in place (cnt becomes the waves' first slots); the total pairs go to
+// d_total.
+template <typename Coder>
+void pw_count(ej_ctx *ctx, const PairWalk &pw, const uint32_t *dk, const uint64_t *key_s,
+              const uint32_t *len_s, const uint32_t *ids, uint32_t n, uint32_t tot, uint32_t K,
+              const Coder &coder, uint64_t *d_total) {
+    hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, Coder>), dim3(pw.nwg), dim3(256), 0,
+                       ctx->stream, dk, key_s, len_s, ids, n, tot, K, coder, pw.wlen, pw.cnt,
+                       pw.ntask, (uint64_t *)nullptr, (uint64_t *)nullptr, (uint64_t)0);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u32(ctx, pw.ntask, pw.tbase, pw.nw, pw.ntot);
+    hipLaunchKernelGGL((k_pairs_heavy<false, uint64_t, Coder>), dim3(pw_heavy_grid(ctx)),
+                       dim3(256), 0, ctx->stream, key_s, ids, tot, coder,
+                       (const uint32_t *)pw.wlen, (const uint32_t *)pw.tbase, pw.nw,
+                       (const uint64_t *)pw.ntot, pw.cnt, (uint64_t *)nullptr,
+                       (uint64_t *)nullptr, (uint64_t)0);
+    EJ_CHECK_LAUNCH();
+    scan_exclusive_u64(ctx, pw.cnt, pw.cnt, pw.nw, d_total);
+}
+
+// Emitting pass (after pw_count on the same buffers): the pairs into out,
+// nothing at or past cap.
+template <typename C, typename Coder>
+void pw_emit(ej_ctx *ctx, const PairWalk &pw, const uint32_t *dk, const uint64_t *key_s,
+             const uint32_t *len_s, const uint32_t *ids, uint32_t n, uint32_t tot, uint32_t K,
+             const Coder &coder, C *out, uint64_t cap) {
+    hipLaunchKernelGGL((k_pairs_dk<true, C, Coder>), dim3(pw.nwg), dim3(256), 0, ctx->stream, dk,
+                       key_s, len_s, ids, n, tot, K, coder, pw.wlen, (uint64_t *)nullptr,
+                       (uint32_t *)nullptr, pw.cnt, out, cap);
+    EJ_CHECK_LAUNCH();
+    hipLaunchKernelGGL((k_pairs_heavy<true, C, Coder>), dim3(pw_heavy_grid(ctx)), dim3(256), 0,
+                       ctx->stream, key_s, ids, tot, coder, (const uint32_t *)pw.wlen,
+                       (const uint32_t *)pw.tbase, pw.nw, (const uint64_t *)pw.ntot,
+                       (uint64_t *)nullptr, pw.cnt, out, cap);
+    EJ_CHECK_LAUNCH();
 }
 
 // EmbedJoin+ tuple counts: in the sorted tuple codes, a run of equal codes
@@ -662,23 +849,17 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     // groups from the sorted top key bits (the join) or from group starts
     const bool by_dk = bk.d_dk != nullptr;
     if (by_dk && tot >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "r*z*n must stay below 2^32");
-    const uint32_t nwg = (uint32_t)((tot + PW_TILE - 1) / PW_TILE);
     uint64_t *counts = nullptr;
-    uint32_t *tcount = nullptr;
+    PairWalk pw{};
     if (by_dk) {
         hipLaunchKernelGGL(k_sorted_attrs_dk, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
                            ctx->stream, d_keys, (const uint32_t *)bk.d_ids, d_len,
                            (const uint32_t *)bk.d_dk, n, (uint32_t)tot, key_s, len_s);
         EJ_CHECK_LAUNCH();
-        tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
-        counts = ws<uint64_t>(ctx, t + "_counts", nwg);
-        hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, PairCoder>), dim3(nwg), dim3(256), 0,
-                           ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                           (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot,
-                           K, PairCoder{B}, tcount, counts, (const uint64_t *)nullptr,
-                           (uint64_t *)nullptr, (uint64_t)0);
-        EJ_CHECK_LAUNCH();
-        scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
+        pw = pw_buffers(ctx, t, tot);
+        pw_count(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                 (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K,
+                 PairCoder{B}, d_raw);
     } else {
         hipLaunchKernelGGL(k_sorted_attrs, dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
                            ctx->stream, d_keys, (const uint32_t *)bk.d_ids, d_len, n, tot, key_s,
@@ -705,12 +886,9 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     auto emit = [&](auto *rawbuf) {
         using C = std::remove_pointer_t<decltype(rawbuf)>;
         if (by_dk) {
-            hipLaunchKernelGGL((k_pairs_dk<true, C, PairCoder>), dim3(nwg), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                               (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n,
-                               (uint32_t)tot, K, PairCoder{B}, tcount, (uint64_t *)nullptr,
-                               (const uint64_t *)counts, rawbuf, raw);
-            EJ_CHECK_LAUNCH();
+            pw_emit(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                    (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K,
+                    PairCoder{B}, rawbuf, raw);
             return;
         }
         hipLaunchKernelGGL((k_pairs<true, C>), dim3(grid_for(ctx, tot, 256)), dim3(256), 0,
@@ -871,22 +1049,15 @@ void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     const uint32_t mult_cap = mult_bits >= 32 ? 0xFFFFFFFFu : (1u << mult_bits) - 1u;
     uint64_t *key_s = ws<uint64_t>(ctx, t + "_key_s", tot);
     uint32_t *len_s = ws<uint32_t>(ctx, t + "_len_s", tot);
-    const uint32_t nwg = (uint32_t)((tot + PW_TILE - 1) / PW_TILE);
-    uint32_t *tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
-    uint64_t *counts = ws<uint64_t>(ctx, t + "_counts", nwg);
+    const PairWalk pw = pw_buffers(ctx, t, tot);
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, ctx->stream, cnt_dev + 2, 1u);
     EJ_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_sorted_attrs_dk, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
                        d_keys, (const uint32_t *)bk.d_ids, d_len, (const uint32_t *)bk.d_dk, n,
                        (uint32_t)tot, key_s, len_s);
     EJ_CHECK_LAUNCH();
-    hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, PairCoder>), dim3(nwg), dim3(256), 0,
-                       ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                       (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K,
-                       PairCoder{B}, tcount, counts, (const uint64_t *)nullptr,
-                       (uint64_t *)nullptr, (uint64_t)0);
-    EJ_CHECK_LAUNCH();
-    scan_exclusive_u64(ctx, counts, counts, nwg, cnt_dev);
+    pw_count(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s, (const uint32_t *)len_s,
+             (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K, PairCoder{B}, cnt_dev);
     if (sort_dedup) {
         // the whole raw buffer sorted (padding at the end), one of each run
         uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", raw_cap);
@@ -895,12 +1066,9 @@ void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
         uint32_t *first = want_order ? ws<uint32_t>(ctx, t + "_first", cnt_cap) : nullptr;
         auto sorted_unique = [&](auto *rawbuf, auto *sorted) {
             using C = std::remove_pointer_t<decltype(rawbuf)>;
-            hipLaunchKernelGGL((k_pairs_dk<true, C, PairCoder>), dim3(nwg), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                               (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n,
-                               (uint32_t)tot, K, PairCoder{B}, tcount, (uint64_t *)nullptr,
-                               (const uint64_t *)counts, rawbuf, raw_cap);
-            EJ_CHECK_LAUNCH();
+            pw_emit(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                    (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K,
+                    PairCoder{B}, rawbuf, raw_cap);
             const C pad = (C)((2 * B >= 64 ? ~0ull : (1ull << (2 * B)) - 1ull));
             hipLaunchKernelGGL(k_pad_codes<C>, dim3(grid_for(ctx, raw_cap, 256)), dim3(256), 0,
                                ctx->stream, rawbuf, raw_cap, (const uint64_t *)cnt_dev, pad);
@@ -952,12 +1120,9 @@ void candidates_dev(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     uint32_t *gst = ws<uint32_t>(ctx, t + "_dd_gstart", NG + 1);
     auto group = [&](auto *rawbuf, uint32_t *part) {
         using C = std::remove_pointer_t<decltype(rawbuf)>;
-        hipLaunchKernelGGL((k_pairs_dk<true, C, PairCoder>), dim3(nwg), dim3(256), 0,
-                           ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                           (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot,
-                           K, PairCoder{B}, tcount, (uint64_t *)nullptr, (const uint64_t *)counts,
-                           rawbuf, raw_cap);
-        EJ_CHECK_LAUNCH();
+        pw_emit(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
+                (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, n, (uint32_t)tot, K,
+                PairCoder{B}, rawbuf, raw_cap);
         hipLaunchKernelGGL(k_group_count<C>, dim3(nwd), dim3(256), 0, ctx->stream,
                            (const C *)rawbuf, (uint32_t)raw_cap, (const uint64_t *)cnt_dev, shift,
                            NG, ghist);
@@ -1035,20 +1200,13 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
     uint64_t *key_s = ws<uint64_t>(ctx, t + "_key_s", tot);
     uint32_t *len_s = ws<uint32_t>(ctx, t + "_len_s", tot);
     uint64_t *d_raw = ws<uint64_t>(ctx, t + "_nraw", 1);
-    const uint32_t nwg = (uint32_t)((tot + PW_TILE - 1) / PW_TILE);
     hipLaunchKernelGGL(k_sorted_attrs_dk, dim3(grid_for(ctx, tot, 256)), dim3(256), 0, ctx->stream,
                        d_keys, (const uint32_t *)bk.d_ids, d_len_entry, (const uint32_t *)bk.d_dk,
                        ne, (uint32_t)tot, key_s, len_s);
     EJ_CHECK_LAUNCH();
-    uint32_t *tcount = ws<uint32_t>(ctx, t + "_tcount", (uint64_t)nwg * 256);
-    uint64_t *counts = ws<uint64_t>(ctx, t + "_counts", nwg);
-    hipLaunchKernelGGL((k_pairs_dk<false, uint64_t, TupleCoder>), dim3(nwg), dim3(256), 0,
-                       ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                       (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K,
-                       coder, tcount, counts, (const uint64_t *)nullptr, (uint64_t *)nullptr,
-                       (uint64_t)0);
-    EJ_CHECK_LAUNCH();
-    scan_exclusive_u64(ctx, counts, counts, nwg, d_raw);
+    const PairWalk pw = pw_buffers(ctx, t, tot);
+    pw_count(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s, (const uint32_t *)len_s,
+             (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K, coder, d_raw);
     uint64_t raw = 0;
     read_back(ctx, d_raw, 8, &raw);
     if (n_raw) *n_raw = raw;
@@ -1057,11 +1215,8 @@ uint64_t candidates_plus(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk,
         fail(EJ_EUNSUPPORTED, "more than 2^32 candidate tuples (" + std::to_string(raw) + ")");
     uint64_t *tup = ws<uint64_t>(ctx, t + "_tuples", raw);
     uint64_t *sorted = ws<uint64_t>(ctx, t + "_tuples_sorted", raw);
-    hipLaunchKernelGGL((k_pairs_dk<true, uint64_t, TupleCoder>), dim3(nwg), dim3(256), 0,
-                       ctx->stream, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s,
-                       (const uint32_t *)len_s, (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K,
-                       coder, tcount, (uint64_t *)nullptr, (const uint64_t *)counts, tup, raw);
-    EJ_CHECK_LAUNCH();
+    pw_emit(ctx, pw, (const uint32_t *)bk.d_dk, (const uint64_t *)key_s, (const uint32_t *)len_s,
+            (const uint32_t *)bk.d_ids, ne, (uint32_t)tot, K, coder, tup, raw);
     radix_sort_u64(ctx, tup, sorted, raw, 2 * B + 2 * KB, ctx->tune.radix_bits);
     uint32_t *flags = ws<uint32_t>(ctx, t + "_tflags", raw);
     uint32_t *pos = ws<uint32_t>(ctx, t + "_tpos", raw);

@@ -896,17 +896,29 @@ __global__ void k_grp_keys(const uint64_t *__restrict__ off, const uint64_t *__r
     }
 }
 
+// One wave per 64 consecutive positions: the run start of position k is the
+// last run start at or before k inside the wave (ballot), else the start of
+// the run that holds the wave's first position, found once per wave by
+// bisection (every lane reads the same words).
 __global__ void k_grp_chunk_flags(const uint32_t *__restrict__ key, uint64_t count,
                                   const uint64_t *__restrict__ count_dev,
                                   uint32_t *__restrict__ flags) {
     const uint64_t live = count_dev ? min(*count_dev, count) : count;
-    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
-         k += (uint64_t)gridDim.x * blockDim.x) {
-        uint32_t f = 0;
-        if (k < live) {
-            const uint32_t x = key[k];
-            // first position of this key's run (binary search)
-            uint64_t lo = 0, hi = k;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x - lane); base < count;
+         base += stride) {
+        const uint64_t k = base + lane;
+        const bool in = k < live;
+        const bool start = in && (k == 0 || key[k - 1] != key[k]);
+        const uint64_t m = __ballot(start);
+        const uint64_t upto = lane == 63 ? m : m & ((2ull << lane) - 1ull);
+        uint64_t rs = 0;
+        if (upto) {
+            rs = base + 63 - (uint64_t)__clzll(upto);
+        } else if (in) {
+            const uint32_t x = key[base];
+            uint64_t lo = 0, hi = base;
             while (lo < hi) {
                 const uint64_t mid = lo + (hi - lo) / 2;
                 if (key[mid] < x)
@@ -914,9 +926,9 @@ __global__ void k_grp_chunk_flags(const uint32_t *__restrict__ key, uint64_t cou
                 else
                     hi = mid;
             }
-            f = ((k - lo) & 63u) == 0 ? 1u : 0u;
+            rs = lo;
         }
-        flags[k] = f;
+        if (k < count) flags[k] = (in && ((k - rs) & 63u) == 0) ? 1u : 0u;
     }
 }
 
