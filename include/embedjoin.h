@@ -324,8 +324,9 @@ ej_status ej_candidates(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_i
 /* A5: threshold edit distance (Section 3.3) of each pair, with a
  * bit-parallel banded kernel: d_dist[k] = ED(s_a, s_b) if it is <= K_k,
  * else K_k + 1, where K_k = d_Kq[k] when d_Kq is not NULL and K otherwise.
- * Pairs are uint64 codes (a << 32) | b.  EJ_EUNSUPPORTED if a threshold
- * exceeds 2046. */
+ * Pairs are uint64 codes (a << 32) | b with a, b < n; the indexes are not
+ * checked (one outside the set reads and writes outside its buffers).
+ * EJ_EUNSUPPORTED if a threshold exceeds 2046. */
 ej_status ej_verify(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uint32_t n,
                     const uint64_t *d_pairs, uint64_t count, uint32_t K, const uint32_t *d_Kq,
                     int32_t *d_dist);

@@ -90,6 +90,7 @@ struct Timers {
     // around each launch of the verification kernel while `on`
     hipEvent_t kv[4] = {};
     int nkv = 0;
+    uint32_t more = 0;  // further launches inside one pair of events
     bool on = false;
 };
 
@@ -336,6 +337,7 @@ uint64_t unique_sorted_pairs(ej_ctx *ctx, const uint64_t *d_sorted, uint64_t cnt
 struct RowMasks {
     const uint32_t *words = nullptr;
     const uint64_t *off = nullptr;
+    uint32_t n = 0;  // strings (0: unknown)
 };
 // Builds the masks of n strings (codes laid out like the characters, offsets
 // relative to `base`) into workspace buffers named after `tag`, or into

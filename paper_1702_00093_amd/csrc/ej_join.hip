@@ -267,6 +267,7 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
         } reset{ctx};
         ctx->timers.on = tm.on;
         ctx->timers.nkv = 0;
+        ctx->timers.more = 0;
         ctx->graph_on = (p.flags & EJ_FLAG_GRAPH) != 0 && ctx->tune.verify_mode >= 1;
         RowMasks masks;
         if (cnt)
@@ -371,7 +372,7 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
             kms += ms;
         }
         out->ms_verify_kernel = kms;
-        out->verify_launches = (uint32_t)(ctx->timers.nkv / 2);
+        out->verify_launches = (uint32_t)(ctx->timers.nkv / 2) + ctx->timers.more;
         out->verify_form = ctx->last_verify_form;
     }
 }

@@ -874,13 +874,17 @@ __global__ void __launch_bounds__(64)
 // (the mask copy is paid once per chunk instead of once per pair) and for
 // large alphabets (a few KB of LDS per wave instead of a window per lane).
 //
-// Chunks: key = pattern of pair k (pairs past a count on the device get the
-// key 0xFFFFFFFF), sorted; a chunk starts where the key changes and every 64
-// pairs within a run of one key.
+// Chunks: key = pattern of pair k, with bit PB set when the pattern is
+// longer than `lim` letters (pairs past a count on the device get the key
+// 0xFFFFFFFF), sorted on PB + 1 bits; a chunk starts where the key changes
+// and every 64 pairs within a run of one key.  The chunks of short patterns
+// thus come first and run with LDS rows sized for `lim` letters (many waves
+// per CU); the few long ones follow in a launch of their own.
 
 __global__ void k_grp_keys(const uint64_t *__restrict__ off, const uint64_t *__restrict__ pairs,
-                           uint64_t count, const uint64_t *__restrict__ count_dev,
-                           uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+                           uint64_t count, const uint64_t *__restrict__ count_dev, uint32_t PB,
+                           uint64_t lim, uint32_t *__restrict__ key,
+                           uint32_t *__restrict__ val) {
     const uint64_t live = count_dev ? min(*count_dev, count) : count;
     for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
          k += (uint64_t)gridDim.x * blockDim.x) {
@@ -890,45 +894,40 @@ __global__ void k_grp_keys(const uint64_t *__restrict__ off, const uint64_t *__r
             const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
             const uint64_t la = off[a + 1] - off[a], lb = off[b + 1] - off[b];
             pat = la >= lb ? a : b;  // view_pair's pattern
+            if ((la >= lb ? la : lb) > lim) pat |= 1u << PB;
         }
         key[k] = pat;
         val[k] = (uint32_t)k;
     }
 }
 
-// One wave per 64 consecutive positions: the run start of position k is the
-// last run start at or before k inside the wave (ballot), else the start of
-// the run that holds the wave's first position, found once per wave by
-// bisection (every lane reads the same words).
+// Run starts of the sorted keys, into a table indexed by the key's class
+// and pattern (n slots per class); every key of a run reads the same slot.
+__device__ inline uint32_t grp_slot(uint32_t key, uint32_t PB, uint32_t n) {
+    return PB >= 32 ? key : (key & ((1u << PB) - 1u)) + ((key >> PB) & 1u) * n;
+}
+
+__global__ void k_grp_run_starts(const uint32_t *__restrict__ key, uint64_t count,
+                                 const uint64_t *__restrict__ count_dev, uint32_t PB, uint32_t n,
+                                 uint32_t *__restrict__ rstart) {
+    const uint64_t live = count_dev ? min(*count_dev, count) : count;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < live;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t x = key[k];
+        if (k == 0 || key[k - 1] != x) rstart[grp_slot(x, PB, n)] = (uint32_t)k;
+    }
+}
+
 __global__ void k_grp_chunk_flags(const uint32_t *__restrict__ key, uint64_t count,
-                                  const uint64_t *__restrict__ count_dev,
+                                  const uint64_t *__restrict__ count_dev, uint32_t PB, uint32_t n,
+                                  const uint32_t *__restrict__ rstart,
                                   uint32_t *__restrict__ flags) {
     const uint64_t live = count_dev ? min(*count_dev, count) : count;
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x - lane); base < count;
-         base += stride) {
-        const uint64_t k = base + lane;
-        const bool in = k < live;
-        const bool start = in && (k == 0 || key[k - 1] != key[k]);
-        const uint64_t m = __ballot(start);
-        const uint64_t upto = lane == 63 ? m : m & ((2ull << lane) - 1ull);
-        uint64_t rs = 0;
-        if (upto) {
-            rs = base + 63 - (uint64_t)__clzll(upto);
-        } else if (in) {
-            const uint32_t x = key[base];
-            uint64_t lo = 0, hi = base;
-            while (lo < hi) {
-                const uint64_t mid = lo + (hi - lo) / 2;
-                if (key[mid] < x)
-                    lo = mid + 1;
-                else
-                    hi = mid;
-            }
-            rs = lo;
-        }
-        if (k < count) flags[k] = (in && ((k - rs) & 63u) == 0) ? 1u : 0u;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t f = 0;
+        if (k < live) f = ((k - rstart[grp_slot(key[k], PB, n)]) & 63u) == 0 ? 1u : 0u;
+        flags[k] = f;
     }
 }
 
@@ -942,6 +941,27 @@ __global__ void k_grp_chunk_starts(const uint32_t *__restrict__ flags,
         if (flags[k]) start[pos[k]] = (uint32_t)k;
     if (blockIdx.x == 0 && threadIdx.x == 0)
         start[*nchunks] = (uint32_t)(count_dev ? min(*count_dev, count) : count);
+}
+
+// The first chunk of a long pattern (bit PB of its first key; PB >= 32:
+// none), by bisection over the chunks: range[0] = 0, range[1] = that chunk,
+// range[2] = chunks.
+__global__ void k_grp_split(const uint32_t *__restrict__ key, const uint32_t *__restrict__ start,
+                            const uint64_t *__restrict__ nchunks, uint32_t PB,
+                            uint64_t *__restrict__ range) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint64_t nch = *nchunks;
+    uint64_t lo = PB >= 32 ? nch : 0, hi = nch;
+    while (lo < hi) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if ((key[start[mid]] >> PB) & 1u)
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    range[0] = 0;
+    range[1] = lo;
+    range[2] = nch;
 }
 
 // 32 columns of one pair per lane, the pattern's rows shared in LDS: row c
@@ -1000,17 +1020,18 @@ __device__ inline void grp_block(const uint32_t *rows, uint32_t S, int32_t b0,
 template <int NW>
 __global__ void __launch_bounds__(64)
     k_verify_grp(StrSet A, const uint64_t *__restrict__ pairs, const uint32_t *__restrict__ order,
-                 const uint32_t *__restrict__ cstart, const uint64_t *__restrict__ nchunks_dev,
+                 const uint32_t *__restrict__ cstart, const uint64_t *__restrict__ crange,
                  uint32_t K, const uint32_t *__restrict__ Kq, uint32_t sigma, uint32_t S,
                  uint32_t lead, uint32_t *__restrict__ next, int32_t *__restrict__ dist,
                  unsigned long long *__restrict__ columns) {
     extern __shared__ uint32_t rows[];  // (sigma + 1) rows of S words
     unsigned long long colsum = 0;  // text columns of the pairs decided here
     const uint32_t lane = threadIdx.x;
-    const uint32_t nch = (uint32_t)*nchunks_dev;
+    // chunks [crange[0], crange[1])
+    const uint32_t c0 = (uint32_t)crange[0], nch = (uint32_t)crange[1];
     for (;;) {
         uint32_t ch = 0;
-        if (lane == 0) ch = atomicAdd(next, 1u);
+        if (lane == 0) ch = c0 + atomicAdd(next, 1u);
         ch = readlane_u32(ch, 0);
         if (ch >= nch) break;
         const uint32_t cs = cstart[ch], ce = cstart[ch + 1];
@@ -1620,6 +1641,7 @@ void build_masks(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets,
         own_words ? own_words : ws<uint32_t>(ctx, t + "_mwords", mask_words_bound(total, n, sigma));
     rm.words = words;
     rm.off = off;
+    rm.n = n;
     if (n == 0) return;
     uint64_t *sz = ws<uint64_t>(ctx, t + "_msz", (uint64_t)n + 1);
     hipLaunchKernelGGL(k_mask_sizes, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
@@ -1699,12 +1721,14 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
     };
     // grouped by pattern: the candidates' patterns share LDS rows per chunk
-    if (ctx->tune.verify_mode == 3 && self_set && NL <= LANE_MAX_WORDS) {
+    if (ctx->tune.verify_mode == 3 && self_set && NL <= LANE_MAX_WORDS && masks.n > 0) {
         const uint32_t lead = (Kmax / 2 + 1 + 31) / 32;
-        const uint32_t S = lead + (maxlen + 31) / 32 + NL + 2;
+        const uint32_t Wfull = (maxlen + 31) / 32;
+        const uint32_t S = lead + Wfull + NL + 2;
         const size_t glds = (size_t)(sig + 1) * S * 4;
         if (glds <= (size_t)ctx->lds_max) {
             ctx->last_verify_form = 4;
+            const uint32_t n = masks.n;
             uint32_t *gkey = ws<uint32_t>(ctx, "vg_key", count);
             uint32_t *gval = ws<uint32_t>(ctx, "vg_val", count);
             uint32_t *gkey2 = ws<uint32_t>(ctx, "vg_key2", count);
@@ -1713,52 +1737,105 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             uint32_t *cpos = ws<uint32_t>(ctx, "vg_cpos", count);
             uint32_t *cstart = ws<uint32_t>(ctx, "vg_cstart", count + 1);
             uint64_t *d_nch = ws<uint64_t>(ctx, "vg_nchunks", 1);
-            uint32_t *next = ws<uint32_t>(ctx, "verify_next", 1);
+            uint64_t *crange = ws<uint64_t>(ctx, "vg_crange", 3);
+            uint32_t *next = ws<uint32_t>(ctx, "vg_next", 2);
             const GrpKernel gk = grp_kernel(NL);
-            if (glds > 65536)
-                EJ_HIP(hipFuncSetAttribute((const void *)gk,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)glds));
-            int occ = 0;
-            EJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gk, 64, glds));
-            if (occ < 1) occ = 1;
-            const uint32_t per_cu =
-                std::max(1u, std::min((uint32_t)occ, ctx->tune.verify_blocks_per_cu));
-            const uint64_t grid =
+            const uint32_t want = std::max(1u, ctx->tune.verify_blocks_per_cu);
+            // waves per CU for `lds` bytes per wave (at most `want`)
+            auto resident = [&](size_t lds) {
+                if (lds > 65536)
+                    EJ_HIP(hipFuncSetAttribute((const void *)gk,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)lds));
+                int occ = 0;
+                EJ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, gk, 64, lds));
+                return std::max(1u, std::min((uint32_t)std::max(occ, 1), want));
+            };
+            // rows sized for the whole set hold fewer waves per CU than asked
+            // for: patterns up to `lim` letters then take rows of Ws words
+            // (as many as `want` waves per CU leave room for), the longer
+            // ones the full rows, in a second launch
+            const uint32_t per_cu = resident(glds);
+            int lds_cu = 0;
+            EJ_HIP(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                         ctx->device));
+            const uint64_t row_bytes = (uint64_t)(sig + 1) * 4;
+            const uint64_t fit = (uint64_t)std::max(lds_cu, 0) / want / row_bytes;
+            const uint32_t Ws =
+                fit > lead + NL + 2 ? (uint32_t)std::min<uint64_t>(fit - lead - NL - 2, Wfull)
+                                    : 0u;
+            // pattern indexes are below n: PB bits hold them and the padding
+            // key's all-ones field
+            const uint32_t PB = std::max(1u, bits_for(n));
+            const bool split = per_cu < want && Ws >= 1 && Ws < Wfull && PB < 32;
+            uint32_t *rstart = ws<uint32_t>(ctx, "vg_rstart", split ? 2ull * n : n);
+            const uint32_t Ss = split ? lead + Ws + NL + 2 : S;
+            const size_t glds_s = (size_t)(sig + 1) * Ss * 4;
+            const uint32_t per_cu_s = split ? resident(glds_s) : per_cu;
+            const uint64_t lim = split ? 32ull * Ws : ~0ull;
+            const uint64_t grid_s =
+                std::min<uint64_t>((count + 63) / 64, (uint64_t)ctx->num_cu * per_cu_s);
+            const uint64_t grid_l =
                 std::min<uint64_t>((count + 63) / 64, (uint64_t)ctx->num_cu * per_cu);
-            // pairs ordered by pattern, cut into chunks (no host round trip)
+            // pairs ordered by (length class, pattern), cut into chunks (no
+            // host round trip)
+            const uint32_t KB = split ? PB : 32u;  // the class bit (32: none)
             hipLaunchKernelGGL(k_grp_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
-                               ctx->stream, A.off, d_pairs, count, d_count, gkey, gval);
+                               ctx->stream, A.off, d_pairs, count, d_count, split ? PB : 0u, lim,
+                               gkey, gval);
             EJ_CHECK_LAUNCH();
-            radix_sort_u32(ctx, gkey, gval, gkey2, gorder, 1, (uint32_t)count, 32,
-                           ctx->tune.radix_bits);
+            radix_sort_u32(ctx, gkey, gval, gkey2, gorder, 1, (uint32_t)count,
+                           split ? PB + 1 : PB, ctx->tune.radix_bits);
+            hipLaunchKernelGGL(k_grp_run_starts, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)gkey2, count, d_count, KB, n,
+                               rstart);
+            EJ_CHECK_LAUNCH();
             hipLaunchKernelGGL(k_grp_chunk_flags, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
-                               ctx->stream, (const uint32_t *)gkey2, count, d_count, cflag);
+                               ctx->stream, (const uint32_t *)gkey2, count, d_count, KB, n,
+                               (const uint32_t *)rstart, cflag);
             EJ_CHECK_LAUNCH();
             scan_exclusive_u32(ctx, cflag, cpos, count, d_nch);
             hipLaunchKernelGGL(k_grp_chunk_starts, dim3(grid_for(ctx, count, 256)), dim3(256),
                                0, ctx->stream, (const uint32_t *)cflag, (const uint32_t *)cpos,
                                count, d_count, (const uint64_t *)d_nch, cstart);
             EJ_CHECK_LAUNCH();
-            char key[384];
+            hipLaunchKernelGGL(k_grp_split, dim3(1), dim3(64), 0, ctx->stream,
+                               (const uint32_t *)gkey2, (const uint32_t *)cstart,
+                               (const uint64_t *)d_nch, KB, crange);
+            EJ_CHECK_LAUNCH();
+            char key[448];
             snprintf(key, sizeof(key),
-                     "verify_grp %u %p %p %llu %p %p %p %p %p %p %u %p %u %u %u %p %p %p %llu "
-                     "%zu %llu",
+                     "verify_grp %u %p %p %llu %p %p %p %p %p %p %u %p %u %u %u %u %p %p %p "
+                     "%llu %llu %zu %zu %d %llu",
                      NL, (const void *)d_codes, (const void *)d_offsets, (unsigned long long)base,
                      (const void *)A.mw, (const void *)A.moff, (const void *)d_pairs,
-                     (const void *)gorder, (const void *)cstart, (const void *)d_nch, K,
-                     (const void *)d_Kq, sig, S, lead, (void *)next, (void *)d_dist,
-                     (void *)d_columns, (unsigned long long)grid, glds,
-                     (unsigned long long)ctx->ws_gen);
+                     (const void *)gorder, (const void *)cstart, (const void *)crange, K,
+                     (const void *)d_Kq, sig, S, Ss, lead, (void *)next, (void *)d_dist,
+                     (void *)d_columns, (unsigned long long)grid_s, (unsigned long long)grid_l,
+                     glds, glds_s, (int)split, (unsigned long long)ctx->ws_gen);
+            if (split && tk.on) tk.more++;  // two launches between the events
             kmark();
             run_captured(ctx, key, [&] {
                 hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next);
                 EJ_CHECK_LAUNCH();
-                hipLaunchKernelGGL(gk, dim3((uint32_t)grid), dim3(64), glds, ctx->stream, A,
-                                   d_pairs, (const uint32_t *)gorder, (const uint32_t *)cstart,
-                                   (const uint64_t *)d_nch, K, d_Kq, sig, S, lead, next, d_dist,
-                                   d_columns);
+                hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, ctx->stream, next + 1);
                 EJ_CHECK_LAUNCH();
+                // short patterns: chunks [crange[0], crange[1]); without the
+                // split every chunk is there (no key has the class bit)
+                hipLaunchKernelGGL(gk, dim3((uint32_t)(split ? grid_s : grid_l)), dim3(64),
+                                   split ? glds_s : glds, ctx->stream, A, d_pairs,
+                                   (const uint32_t *)gorder, (const uint32_t *)cstart,
+                                   (const uint64_t *)crange, K, d_Kq, sig, split ? Ss : S, lead,
+                                   next, d_dist, d_columns);
+                EJ_CHECK_LAUNCH();
+                if (split) {
+                    // long patterns: chunks [crange[1], crange[2])
+                    hipLaunchKernelGGL(gk, dim3((uint32_t)grid_l), dim3(64), glds, ctx->stream,
+                                       A, d_pairs, (const uint32_t *)gorder,
+                                       (const uint32_t *)cstart, (const uint64_t *)(crange + 1),
+                                       K, d_Kq, sig, S, lead, next + 1, d_dist, d_columns);
+                    EJ_CHECK_LAUNCH();
+                }
             });
             kmark();
             return;

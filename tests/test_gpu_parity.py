@@ -742,6 +742,56 @@ def test_grouped_form_many_partners_per_pattern(ej, ctx, oracle_lib):
             ctx.tune_set(k, v)
 
 
+def test_grouped_form_short_and_long_patterns(ej, ctx, oracle_lib):
+    """Grouped by pattern over 25 letters with strings of 0..3,000 letters at
+    32 waves per CU asked for: rows sized for the longest string leave room
+    for fewer waves than that, so the chunks of patterns up to a length limit
+    run with shorter rows and the longer ones in a second launch.  Clusters
+    of each length (pairs inside them near, random pairs far), per-pair
+    thresholds, and the whole-join graph (device count) in both launches."""
+    import torch
+    rng = np.random.default_rng(21)
+    LET = np.frombuffer(b"ACDEFGHIKLMNPQRSTVWYBZXJO", np.uint8)
+    strings = []
+    for size in (2500, 1800, 1200, 700, 300, 90):
+        bse = LET[rng.integers(0, 25, size=size)]
+        strings += [bytes(sd.mutate(rng, bse, int(rng.poisson(size * 0.02)), LET))
+                    for _ in range(16)]
+    strings += [bytes(LET[rng.integers(0, 25, size=int(x))]) for x in rng.integers(0, 3000, 40)]
+    col = sd.from_strings(strings)
+    n = col.n
+    ia, ib = np.triu_indices(16, 1)
+    a = np.concatenate([16 * c + ia for c in range(6)] + [rng.integers(0, n, 500)])
+    b = np.concatenate([16 * c + ib for c in range(6)] + [rng.integers(0, n, 500)])
+    codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
+    chars, offs = to_device(col)
+    d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
+    old = ctx.knobs()
+    try:
+        ctx.tune_set("verify_mode", 3)
+        ctx.tune_set("verify_blocks_per_cu", 32)
+        for K in (0, 100, 300):
+            want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
+            _say(f"grouped short and long patterns K={K}")
+            got = ctx.verify(chars, offs, d_codes, K).cpu().numpy()
+            assert got.astype(np.uint32).tolist() == want.tolist()
+        Kq = rng.integers(0, 200, size=codes.size).astype(np.int32)
+        want = np.array([oracle_lib.verify_pairs(col.chars, col.offsets, codes[i:i + 1], int(k))[0]
+                         for i, k in enumerate(Kq)])
+        got = ctx.verify(chars, offs, d_codes, 0, d_Kq=torch.from_numpy(Kq).cuda()).cpu().numpy()
+        assert got.astype(np.uint32).tolist() == want.tolist()
+        K, r, z, m, L = 100, 3, 4, 6, 64
+        ref = _oracle_join(oracle_lib, col, K, r, z, m, 8, L)
+        assert len(ref.cand) > 200
+        for i in range(4):
+            res = ctx.join(chars, offs, K, r, z, m, seed=8, L=L, flags=ej.FLAG_GRAPH)
+            _assert_join_equal(res, ref)
+        assert res.graph == 2
+    finally:
+        for k, v in old.items():
+            ctx.tune_set(k, v)
+
+
 def test_verified_columns_counter(ej, ctx, oracle_lib):
     """EJ_FLAG_TIMING's count of verified text columns (summed per wave, one
     atomic each): the same over repeated joins, positive, at most the total
