@@ -187,7 +187,9 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *                           1 a ring of the words the band covers when it is
  *                           smaller, 2 the ring whenever the band has at
  *                           least 2 lanes
- *   "embed_lds_budget"      LDS bytes per wave of the walk kernel
+ *   "embed_lds_budget"      LDS bytes per wave of the walk kernel (0, the
+ *                           default: the samples plus string windows of 16
+ *                           words)
  *   "radix_bits"            digit width of the radix sorts (4..11)
  *   "bucket_key_bits"       key bits sorted when bucketing (1..32; 0 =
  *                           ceil(log2 n) + 6)

@@ -229,7 +229,7 @@ static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32
         {"verify_mode", &Tuning::verify_mode, 0, 3},
         {"verify_order", &Tuning::verify_order, 0, 1},
         {"verify_split", &Tuning::verify_split, 0, 16},
-        {"embed_lds_budget", &Tuning::embed_lds_budget, 8192, 1u << 20},
+        {"embed_lds_budget", &Tuning::embed_lds_budget, 0, 1u << 20},
         {"radix_bits", &Tuning::radix_bits, 4, 11},
         {"bucket_key_bits", &Tuning::bucket_key_bits, 0, 32},
         {"dedup_sort", &Tuning::dedup_sort, 0, 1},

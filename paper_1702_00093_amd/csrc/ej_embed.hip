@@ -650,7 +650,12 @@ void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, u
     if (pp.n == 0) return;
     const uint32_t S = rd.S;
     const uint32_t sigbytes = ((S * 64 + 3) / 4) * 4;
+    // the walk is a dependent chain per lane: waves per CU hide its
+    // latency, so by default the string windows are short (16 words: 64 to
+    // 256 letters between restagings) and the LDS per wave is mostly the
+    // samples (z * m bytes per lane)
     uint32_t budget = ctx->tune.embed_lds_budget;
+    if (budget == 0) budget = sigbytes + 64 * 4 * 17;
     if (sigbytes + 64 * 4 * 12 > budget) budget = sigbytes + 64 * 4 * 64;
     if ((int)budget > ctx->lds_max) budget = (uint32_t)ctx->lds_max;
     if (sigbytes + 64 * 4 * 12 > budget)

@@ -107,7 +107,7 @@ struct Tuning {
     uint32_t verify_mode = 0;                // 0 two passes over pair tiles, 1 persistent pair queue
     uint32_t verify_split = 0;               // lane form: lanes per pair (0 auto, 1, 2, 4, 8, 16)
     uint32_t verify_ring = 1;                // match masks: 0 whole pattern, 1 auto, 2 ring if it fits
-    uint32_t embed_lds_budget = 48 * 1024;   // LDS per wave of the walk kernel
+    uint32_t embed_lds_budget = 0;  // LDS per wave of the walk kernel (0: windows of 16 words)
     uint32_t radix_bits = 8;                 // digit width of the radix sorts
     uint32_t bucket_key_bits = 0;            // key bits sorted when bucketing, 0 = ceil(log2 n) + 6
     uint32_t dedup_sort = 0;                 // candidates: 0 grouped (sort on overflow), 1 sort
