@@ -1482,6 +1482,59 @@ __global__ void k_build_masks(const uint8_t *__restrict__ codes, const uint64_t 
     }
 }
 
+// Match masks for alphabets up to MASK_LDS_SIGMA symbols, one thread per
+// mask word: thread i builds word w of string s (its words are numbered
+// from moff[s] / sigma, found by bisection; an empty string shares its
+// offset with the next one, and the last string at or below the word's
+// offset owns it) for every symbol at once.  Each of the word's 32 codes
+// sets its bit in a lane-private LDS word of its symbol; the sigma words
+// are then written out (consecutive threads: consecutive words of a row).
+// moff[n] holds the total.
+constexpr uint32_t MASK_LDS_SIGMA = 64;
+
+__global__ void __launch_bounds__(64)
+    k_build_masks_lds(const uint8_t *__restrict__ codes, const uint64_t *__restrict__ off,
+                      uint64_t base, uint32_t n, uint32_t sigma,
+                      const uint64_t *__restrict__ moff, uint32_t *__restrict__ words) {
+    extern __shared__ uint32_t acc[];  // [sigma][64]
+    const uint32_t lane = threadIdx.x;
+    const uint64_t tw = moff[n] / sigma;
+    for (uint64_t i = (uint64_t)blockIdx.x * 64 + lane; i < tw; i += (uint64_t)gridDim.x * 64) {
+        const uint64_t at = i * sigma;
+        uint32_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo + 1) / 2;
+            if (moff[mid] <= at)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const uint32_t s = lo;
+        const uint64_t o = off[s] - base;
+        const uint32_t len = (uint32_t)(off[s + 1] - off[s]);
+        const uint32_t W = (len + 31) / 32;
+        const uint32_t w = (uint32_t)(i - moff[s] / sigma);
+        for (uint32_t c = 0; c < sigma; c++) acc[c * 64 + lane] = 0u;
+        // codes x[32w .. 32w+31]: reads stay within the array's 64-byte padding
+        const uintptr_t a = (uintptr_t)(codes + o + 32ull * w);
+        const uint32_t *b4 = (const uint32_t *)(a & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(a & 3) * 8;
+        uint32_t d[9], t[8];
+#pragma unroll
+        for (int q = 0; q < 9; q++) d[q] = b4[q];
+#pragma unroll
+        for (int q = 0; q < 8; q++) t[q] = __builtin_amdgcn_alignbit(d[q + 1], d[q], sh);
+        const uint32_t valid = min(len - 32 * w, 32u);
+#pragma unroll
+        for (uint32_t q = 0; q < 32; q++) {
+            const uint32_t c = (t[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+            if (q < valid) atomicOr(&acc[c * 64 + lane], 1u << q);
+        }
+        uint32_t *dst = words + moff[s];
+        for (uint32_t c = 0; c < sigma; c++) dst[(uint64_t)c * W + w] = acc[c * 64 + lane];
+    }
+}
+
 __global__ void k_zero_u32(uint32_t *__restrict__ p) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0u;
 }
@@ -1647,10 +1700,19 @@ void build_masks(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets,
     hipLaunchKernelGGL(k_mask_sizes, dim3(grid_for(ctx, n, 256)), dim3(256), 0, ctx->stream,
                        d_offsets, n, sigma, sz);
     EJ_CHECK_LAUNCH();
-    scan_exclusive_u64(ctx, sz, off, n, nullptr);
-    hipLaunchKernelGGL(k_build_masks, dim3(grid_for(ctx, (uint64_t)n * 64, 256)), dim3(256), 0,
-                       ctx->stream, d_codes, d_offsets, base, n, sigma, (const uint64_t *)off,
-                       words);
+    scan_exclusive_u64(ctx, sz, off, n, off + n);
+    if (sigma >= 1 && sigma <= MASK_LDS_SIGMA) {
+        // at most total / 32 + n words per symbol
+        const uint64_t tw = total / 32 + n;
+        const uint64_t grid = std::min<uint64_t>((tw + 63) / 64, (uint64_t)ctx->num_cu * 32);
+        hipLaunchKernelGGL(k_build_masks_lds, dim3((uint32_t)grid), dim3(64),
+                           (size_t)sigma * 64 * 4, ctx->stream, d_codes, d_offsets, base, n,
+                           sigma, (const uint64_t *)off, words);
+    } else {
+        hipLaunchKernelGGL(k_build_masks, dim3(grid_for(ctx, (uint64_t)n * 64, 256)), dim3(256),
+                           0, ctx->stream, d_codes, d_offsets, base, n, sigma,
+                           (const uint64_t *)off, words);
+    }
     EJ_CHECK_LAUNCH();
 }
 
