@@ -282,23 +282,34 @@ __global__ void k_sample_sort(const uint32_t *__restrict__ pos, uint32_t S,
 
 // --------------------------------------------------------------- the walk --
 
-template <int BW, bool RSTEP>
+// REC = true (walks of at most EMBED_REC_STEPS steps): every step's symbol
+// is recorded in LDS (Lb bytes per lane) and the samples are read from the
+// record through the sample positions when the keys are formed, so the walk
+// itself never looks at the sample list.  REC = false: the walk stores each
+// sampled symbol as it passes the sample's step (the positions sorted, one
+// scalar read per sample).
+constexpr uint32_t EMBED_REC_STEPS = 256;
+
+template <int BW, bool RSTEP, bool REC>
 __global__ void __launch_bounds__(64)
     k_embed(const uint32_t *__restrict__ packed, const uint64_t *__restrict__ offsets,
             uint64_t base, const uint32_t *__restrict__ len, const uint32_t *__restrict__ perm,
             uint32_t n, const uint32_t *__restrict__ Rstep, uint32_t Lpad,
             const uint32_t *__restrict__ Rwords, uint32_t nw, const uint32_t *__restrict__ spos,
             const uint32_t *__restrict__ sslot, const uint32_t *__restrict__ Jarr,
-            const uint64_t *__restrict__ v, uint32_t r, uint32_t z, uint32_t m, uint32_t sigma,
-            uint32_t slot_words, uint64_t *__restrict__ keys, uint8_t *__restrict__ sig_out,
+            const uint32_t *__restrict__ pos, uint32_t Lb, const uint64_t *__restrict__ v,
+            uint32_t r, uint32_t z, uint32_t m, uint32_t sigma, uint32_t slot_words,
+            uint64_t *__restrict__ keys, uint8_t *__restrict__ sig_out,
             uint32_t *__restrict__ dk_out, uint32_t *__restrict__ ids_out, uint32_t dk_shift) {
     constexpr uint32_t CPD = 32 / BW;
     constexpr uint32_t LOGBW = BW == 2 ? 1 : (BW == 4 ? 2 : 3);
     constexpr uint32_t LOGCPD = 5 - LOGBW;
     extern __shared__ uint32_t lds[];
     const uint32_t S = z * m;
-    uint8_t *sig = (uint8_t *)lds;                       // [S][64]
-    uint32_t *slots = lds + ((S * 64 + 3) >> 2);         // [64][stride]
+    // REC: the record, [64][Lb]; otherwise the samples, [S][64]
+    uint8_t *sig = (uint8_t *)lds;
+    const uint32_t head = REC ? 64 * Lb : S * 64;
+    uint32_t *slots = lds + ((head + 3) >> 2);           // [64][stride]
     const uint32_t stride = slot_words + 1;
     const uint32_t lane = threadIdx.x;
     const uint32_t chunk = blockIdx.x / r, l = blockIdx.x % r;
@@ -318,7 +329,8 @@ __global__ void __launch_bounds__(64)
     uint32_t i = 0;   // characters consumed by this walk
     uint32_t ps = 0;  // position of character i inside the staged window
     uint32_t k = 0;   // next sample (wave-uniform)
-    uint32_t np = S ? sp[0] : 0xFFFFFFFFu;
+    uint32_t np = (!REC && S) ? sp[0] : 0xFFFFFFFFu;
+    uint8_t *rec = sig + lane * Lb;  // REC: this lane's record
 
     for (uint32_t cj = 0; cj < J; cj += chunk_steps) {
         // ---- stage the next window of every string of the wave into LDS
@@ -349,7 +361,26 @@ __global__ void __launch_bounds__(64)
             const uint32_t dq = ps >> LOGCPD, sh = (ps & (CPD - 1)) << LOGBW;
             const uint32_t win = __builtin_amdgcn_alignbit(myslot[dq + 1], myslot[dq], sh);
             uint32_t off = 0;
-            if (np >= j0 + CPD && j0 + CPD <= jend) {
+            if (REC) {
+                // every step's symbol into the record (bottom once the
+                // string is used up)
+#pragma unroll
+                for (uint32_t s = 0; s < CPD; s++) {
+                    const uint32_t j = j0 + s;
+                    if (j0 + CPD <= jend || j < jend) {
+                        const uint32_t c = (win >> off) & ((1u << BW) - 1u);
+                        rec[j] = (uint8_t)((i + (off >> LOGBW) < slen) ? c : sigma);
+                        uint32_t b;
+                        if (RSTEP) {
+                            b = (Rs[j] >> (c & 31u)) & 1u;
+                        } else {
+                            uint32_t bi = j * sigma + c;
+                            b = (Rw[bi >> 5] >> (bi & 31)) & 1u;
+                        }
+                        off += b << LOGBW;
+                    }
+                }
+            } else if (np >= j0 + CPD && j0 + CPD <= jend) {
 #pragma unroll
                 for (uint32_t s = 0; s < CPD; s++) {
                     const uint32_t c = (win >> off) & ((1u << BW) - 1u);
@@ -401,8 +432,10 @@ __global__ void __launch_bounds__(64)
     for (uint32_t t = 0; t < z; t++) {
         const uint64_t *vt = v + ((size_t)l * z + t) * m;
         uint32_t s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+        const uint32_t *pt = pos + (size_t)l * S + t * m;
         for (uint32_t kk = 0; kk < m; kk++) {
-            const uint32_t u = (uint32_t)sig[(t * m + kk) * 64 + lane] + 1u;
+            const uint32_t u =
+                (uint32_t)(REC ? rec[pt[kk]] : sig[(t * m + kk) * 64 + lane]) + 1u;
             const uint64_t vv = vt[kk];
             s0 += __umul24(u, (uint32_t)vv & 0xFFFFu);
             s1 += __umul24(u, (uint32_t)(vv >> 16) & 0xFFFFu);
@@ -422,7 +455,8 @@ __global__ void __launch_bounds__(64)
         }
         if (sig_out) {
             uint8_t *dst = sig_out + (((size_t)id * r + l) * z + t) * m;
-            for (uint32_t kk = 0; kk < m; kk++) dst[kk] = sig[(t * m + kk) * 64 + lane];
+            for (uint32_t kk = 0; kk < m; kk++)
+                dst[kk] = REC ? rec[pt[kk]] : sig[(t * m + kk) * 64 + lane];
         }
     }
 }
@@ -649,7 +683,12 @@ void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, u
                 uint32_t *d_dk, uint32_t *d_rank_ids, uint32_t dk_shift) {
     if (pp.n == 0) return;
     const uint32_t S = rd.S;
-    const uint32_t sigbytes = ((S * 64 + 3) / 4) * 4;
+    // short walks keep their whole record (Lb bytes per lane, Lb / 4 odd so
+    // that the lanes' bytes of one step fall in different banks)
+    const bool rec = rd.Jmax <= EMBED_REC_STEPS;
+    uint32_t Lb = (rd.Jmax + 3) & ~3u;
+    if (((Lb / 4) & 1u) == 0) Lb += 4;
+    const uint32_t sigbytes = rec ? 64 * Lb : ((S * 64 + 3) / 4) * 4;
     // the walk is a dependent chain per lane: waves per CU hide its
     // latency, so by default the string windows are short (16 words: 64 to
     // 256 letters between restagings) and the LDS per wave is mostly the
@@ -677,16 +716,26 @@ void embed_keys(ej_ctx *ctx, const Prep &pp, const Rand &rd, uint64_t *d_keys, u
                            (const uint32_t *)pp.d_perm, pp.n, (const uint32_t *)rd.d_Rstep, rd.Lpad,
                            (const uint32_t *)rd.d_Rwords, rd.nw, (const uint32_t *)rd.d_spos,
                            (const uint32_t *)rd.d_sslot, (const uint32_t *)rd.d_J,
-                           (const uint64_t *)rd.d_v, rd.r, rd.z, rd.m, rd.sigma, slot_words, d_keys,
+                           (const uint32_t *)rd.d_pos, Lb, (const uint64_t *)rd.d_v, rd.r, rd.z,
+                           rd.m, rd.sigma, slot_words, d_keys,
                            d_sig, d_dk, d_rank_ids, dk_shift);
         EJ_CHECK_LAUNCH();
     };
-    if (pp.bw == 2)
-        rstep ? launch(k_embed<2, true>) : launch(k_embed<2, false>);
-    else if (pp.bw == 4)
-        rstep ? launch(k_embed<4, true>) : launch(k_embed<4, false>);
-    else
-        rstep ? launch(k_embed<8, true>) : launch(k_embed<8, false>);
+    if (rec) {
+        if (pp.bw == 2)
+            rstep ? launch(k_embed<2, true, true>) : launch(k_embed<2, false, true>);
+        else if (pp.bw == 4)
+            rstep ? launch(k_embed<4, true, true>) : launch(k_embed<4, false, true>);
+        else
+            rstep ? launch(k_embed<8, true, true>) : launch(k_embed<8, false, true>);
+    } else {
+        if (pp.bw == 2)
+            rstep ? launch(k_embed<2, true, false>) : launch(k_embed<2, false, false>);
+        else if (pp.bw == 4)
+            rstep ? launch(k_embed<4, true, false>) : launch(k_embed<4, false, false>);
+        else
+            rstep ? launch(k_embed<8, true, false>) : launch(k_embed<8, false, false>);
+    }
 }
 
 void embed_hamming(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_pairs,
