@@ -196,6 +196,12 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "dedup_sort"            de-duplication of the candidates: 0 grouped by
  *                           the codes' top bits with an LDS hash per group
  *                           (a sort when a group is too large), 1 a sort
+ *   "raw_limit"             raw candidate pairs one sort of the join may hold
+ *                           (0, the default: 2^32 - 2).  A join with more
+ *                           takes its candidate stage in passes over ranges
+ *                           of the pairs' smaller index (same result); it
+ *                           then runs host-sized, without the whole-join
+ *                           graph
  * EJ_EINVAL for an unknown name or a value out of range. */
 ej_status ej_tune_set(ej_ctx *ctx, const char *name, uint32_t value);
 ej_status ej_tune_get(const ej_ctx *ctx, const char *name, uint32_t *value);

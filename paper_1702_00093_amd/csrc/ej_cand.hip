@@ -170,6 +170,20 @@ struct PairCoder {
         return ((uint64_t)a << B) | b;
     }
 };
+// The join's pairs whose smaller index lies in [lo, hi): the candidate stage
+// in passes over ranges of the first index when the raw pairs of the whole
+// join would not fit one sort (their codes are PairCoder's).
+struct RangeCoder {
+    uint32_t B, lo, hi;
+    __device__ bool pairs(uint32_t x, uint32_t y) const {
+        const uint32_t a = min(x, y);
+        return a >= lo && a < hi;
+    }
+    __device__ uint64_t code(uint32_t x, uint32_t y) const {
+        const uint32_t a = min(x, y), b = max(x, y);
+        return ((uint64_t)a << B) | b;
+    }
+};
 struct TupleCoder {
     uint32_t B, kappa, KB;
     __device__ bool pairs(uint32_t x, uint32_t y) const { return x / kappa != y / kappa; }
@@ -708,7 +722,8 @@ __global__ void k_mult_keys_direct(const uint32_t *__restrict__ mult, uint64_t c
 __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, uint64_t raw,
                             const uint64_t *__restrict__ cnt_dev,
                             const uint64_t *__restrict__ raw_dev, uint32_t cap,
-                            uint32_t *__restrict__ key, uint32_t *__restrict__ idx) {
+                            uint32_t *__restrict__ key, uint32_t *__restrict__ idx,
+                            uint64_t ibase = 0) {
     // counts on the device: entries past the distinct count get the key cap,
     // which no real pair has (m >= 1), and sort behind all real ones
     const uint64_t live = cnt_dev ? min(*cnt_dev, cnt) : cnt;
@@ -718,7 +733,7 @@ __global__ void k_mult_keys(const uint32_t *__restrict__ first, uint64_t cnt, ui
         uint64_t m = 0;
         if (u < live) m = (u + 1 < live ? first[u + 1] : raw) - first[u];
         key[u] = cap - (uint32_t)(m < cap ? m : cap);
-        idx[u] = (uint32_t)u;
+        idx[u] = (uint32_t)(ibase + u);
     }
 }
 
@@ -829,6 +844,85 @@ void bucket_exact(ej_ctx *ctx, const uint64_t *d_keys, const uint32_t *d_perm, u
     read_back(ctx, d_ng, 8, &bk.ngroups);
 }
 
+// The candidate stage in passes over ranges [lo, hi) of the pairs' smaller
+// index: a range's raw pairs are counted (a pass of the pair walk that keeps
+// only its pairs), halved while they exceed `lim`, then emitted, sorted and
+// made unique into the output from the running offset.  The ranges ascend,
+// so the concatenation is sorted like the one-pass result, and equal to it.
+// A single index has fewer than n partners, which one sort always takes.
+static uint64_t candidates_ranged(ej_ctx *ctx, const PairWalk &pw, const Buckets &bk,
+                                  const uint64_t *key_s, const uint32_t *len_s, uint32_t K,
+                                  uint32_t B, uint64_t lim, uint32_t mult_bits, uint64_t raw_all,
+                                  uint64_t **d_pairs_out, const std::string &t,
+                                  uint32_t **d_order_out) {
+    const uint32_t n = bk.n;
+    const uint64_t tot = (uint64_t)bk.T * n;
+    const uint32_t mult_cap = mult_bits >= 32 ? 0xFFFFFFFFu : (1u << mult_bits) - 1u;
+    ctx->last_dedup_sorted = true;
+    // distinct pairs: at most the raw pairs, and fewer than 2^32 (the
+    // verification's pair indexes)
+    const uint64_t cap = std::min<uint64_t>(raw_all, 0xFFFFFFFEull);
+    uint64_t *pairs = ws<uint64_t>(ctx, t + "_pairs", cap);
+    uint32_t *k0 = d_order_out ? ws<uint32_t>(ctx, t + "_okey", cap) : nullptr;
+    uint32_t *v0 = d_order_out ? ws<uint32_t>(ctx, t + "_oidx", cap) : nullptr;
+    uint64_t *d_r = ws<uint64_t>(ctx, t + "_rraw", 1);
+    uint64_t *d_c = ws<uint64_t>(ctx, t + "_rcount", 1);
+    const uint32_t *dk = (const uint32_t *)bk.d_dk, *ids = (const uint32_t *)bk.d_ids;
+    uint64_t base = 0;
+    std::vector<std::pair<uint32_t, uint32_t>> todo{{0u, n}};  // a stack, lowest range on top
+    while (!todo.empty()) {
+        const auto [lo, hi] = todo.back();
+        todo.pop_back();
+        const RangeCoder coder{B, lo, hi};
+        pw_count(ctx, pw, dk, key_s, len_s, ids, n, (uint32_t)tot, K, coder, d_r);
+        uint64_t r = 0;
+        read_back(ctx, d_r, 8, &r);
+        if (r == 0) continue;
+        if (r > lim && hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            todo.push_back({mid, hi});
+            todo.push_back({lo, mid});
+            continue;
+        }
+        uint64_t *raw64 = ws<uint64_t>(ctx, t + "_raw", r);
+        uint64_t *sorted = ws<uint64_t>(ctx, t + "_raw_sorted", r);
+        uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", r);
+        uint32_t *pos = ws<uint32_t>(ctx, t + "_upos", r);
+        uint32_t *first = d_order_out ? ws<uint32_t>(ctx, t + "_first", r) : nullptr;
+        pw_emit(ctx, pw, dk, key_s, len_s, ids, n, (uint32_t)tot, K, coder, raw64, r);
+        radix_sort_u64(ctx, raw64, sorted, r, 2 * B, ctx->tune.radix_bits);
+        hipLaunchKernelGGL(k_unique_flags<uint64_t>, dim3(grid_for(ctx, r, 256)), dim3(256), 0,
+                           ctx->stream, (const uint64_t *)sorted, r, (const uint64_t *)nullptr,
+                           flags);
+        EJ_CHECK_LAUNCH();
+        scan_exclusive_u32(ctx, flags, pos, r, d_c);
+        uint64_t c = 0;
+        read_back(ctx, d_c, 8, &c);
+        if (base + c > cap)
+            fail(EJ_EUNSUPPORTED, "2^32 or more distinct candidate pairs");
+        hipLaunchKernelGGL(k_unique_compact<uint64_t>, dim3(grid_for(ctx, r, 256)), dim3(256), 0,
+                           ctx->stream, (const uint64_t *)sorted, r, B, (const uint32_t *)flags,
+                           (const uint32_t *)pos, pairs + base, first, c);
+        EJ_CHECK_LAUNCH();
+        if (d_order_out) {
+            hipLaunchKernelGGL(k_mult_keys, dim3(grid_for(ctx, c, 256)), dim3(256), 0,
+                               ctx->stream, (const uint32_t *)first, c, r,
+                               (const uint64_t *)nullptr, (const uint64_t *)nullptr, mult_cap,
+                               k0 + base, v0 + base, base);
+            EJ_CHECK_LAUNCH();
+        }
+        base += c;
+    }
+    *d_pairs_out = pairs;
+    if (d_order_out && base) {
+        uint32_t *k1 = ws<uint32_t>(ctx, t + "_okey2", base);
+        uint32_t *order = ws<uint32_t>(ctx, t + "_order", base);
+        radix_sort_u32(ctx, k0, v0, k1, order, 1, (uint32_t)base, mult_bits, 11);
+        *d_order_out = order;
+    }
+    return base;
+}
+
 uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, const uint32_t *d_len,
                     uint32_t K, uint64_t **d_pairs_out, uint64_t *n_raw, const char *tag,
                     uint32_t **d_order_out) {
@@ -878,6 +972,12 @@ uint64_t candidates(ej_ctx *ctx, const uint64_t *d_keys, const Buckets &bk, cons
     read_back(ctx, d_raw, 8, &raw);
     if (n_raw) *n_raw = raw;
     if (raw == 0) return 0;
+    // one sort takes fewer than 2^32 raw pairs (32-bit ranks); beyond that
+    // (or beyond the raw_limit knob) the join's pairs go in passes
+    const uint64_t lim = ctx->tune.raw_limit ? ctx->tune.raw_limit : 0xFFFFFFFEull;
+    if (raw > lim && by_dk)
+        return candidates_ranged(ctx, pw, bk, key_s, len_s, K, B, lim, mult_bits, raw,
+                                 d_pairs_out, t, d_order_out);
     if (raw >= 0xFFFFFFFFull)
         fail(EJ_EUNSUPPORTED, "more than 2^32 raw candidate pairs (" + std::to_string(raw) + ")");
     uint32_t *flags = ws<uint32_t>(ctx, t + "_uflags", raw);

@@ -448,12 +448,12 @@ std::string join_shape(ej_ctx *ctx, const Prep &pp, const uint8_t *d_chars,
     char key[512];
     snprintf(key, sizeof(key),
              "join %p %p %u %llu %llu %u %u %u %u %u %u %u %llu | %u %u %u %u %u %u %u %u %u %u "
-             "%u",
+             "%u %u",
              (const void *)d_chars, (const void *)d_offsets, pp.n, (unsigned long long)pp.base,
              (unsigned long long)pp.total, pp.sigma, pp.maxlen, pp.L, p.K, p.r, p.z, p.m,
              (unsigned long long)p.seed, t.verify_mode, t.verify_order, t.verify_split,
              t.verify_pass1_cols, t.verify_blocks_per_cu, t.verify_ring, t.verify_lds_budget,
-             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits, t.dedup_sort);
+             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits, t.dedup_sort, t.raw_limit);
     return key;
 }
 
@@ -653,8 +653,12 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
         c.raw_cap = std::max(c.raw_cap, raw + raw / 16 + 4096);
         c.cnt_cap = std::max(c.cnt_cap, cnt + cnt / 16 + 4096);
         c.sort_dedup = c.sort_dedup || ctx->last_dedup_sorted;
-        // capacities at 2^32 or more: this shape stays host-sized
-        if (c.raw_cap >= 0xFFFFFFFFull || c.cnt_cap >= 0xFFFFFFFFull) c.no_graph = true;
+        // capacities at 2^32 or more (or raw pairs past the one-sort limit,
+        // which the host-sized join takes in passes): this shape stays
+        // host-sized
+        if (c.raw_cap >= 0xFFFFFFFFull || c.cnt_cap >= 0xFFFFFFFFull ||
+            (ctx->tune.raw_limit && raw > ctx->tune.raw_limit))
+            c.no_graph = true;
     }
 }
 

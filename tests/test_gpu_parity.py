@@ -792,6 +792,40 @@ def test_grouped_form_short_and_long_patterns(ej, ctx, oracle_lib):
             ctx.tune_set(k, v)
 
 
+def test_candidates_in_passes(ej, ctx, oracle_lib):
+    """More raw pairs than one sort may hold (the raw_limit knob lowers the
+    2^32 - 2 limit): the candidate stage runs in passes over ranges of the
+    pairs' smaller index, halved while a range has too many, down to single
+    indexes.  The join equals the oracle's (and the one-pass join) in the
+    two-pass form and in the persistent form with the multiplicity order;
+    with the graph flag it stays host-sized."""
+    col = sd.clusters(23, 60, lambda rr, b: rr.integers(2, 9), lambda rr: rr.integers(80, 400),
+                      lambda rr, LL: rr.poisson(6))
+    K, r, z, m, L = 40, 6, 8, 3, 48
+    ref = _oracle_join(oracle_lib, col, K, r, z, m, 4, L)
+    chars, offs = to_device(col)
+    one = ctx.join(chars, offs, K, r, z, m, seed=4, L=L)
+    _assert_join_equal(one, ref)
+    assert one.n_raw > 2000, one.n_raw
+    old = ctx.knobs()
+    try:
+        for limit in (500, 37, 1):
+            ctx.tune_set("raw_limit", limit)
+            for mode in (0, 1):
+                ctx.tune_set("verify_mode", mode)
+                _say(f"candidates in passes raw_limit={limit} verify_mode={mode}")
+                res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L)
+                _assert_join_equal(res, ref)
+                assert res.n_raw == one.n_raw
+        for i in range(3):
+            res = ctx.join(chars, offs, K, r, z, m, seed=4, L=L, flags=ej.FLAG_GRAPH)
+            _assert_join_equal(res, ref)
+            assert res.graph == 0
+    finally:
+        for k, v in old.items():
+            ctx.tune_set(k, v)
+
+
 def test_verified_columns_counter(ej, ctx, oracle_lib):
     """EJ_FLAG_TIMING's count of verified text columns (summed per wave, one
     atomic each): the same over repeated joins, positive, at most the total
