@@ -203,11 +203,16 @@ __global__ void __launch_bounds__(BLK) k_rs_hist(const K *__restrict__ keys, uin
         hist[((uint64_t)seg * NB + d) * tps + tile] = cnt[d];
 }
 
-// Stable scatter of one tile.  Element order inside a tile is round-major,
-// then thread order; waves rank their lanes with a ballot-based match on the
-// digit and add the counts of lower waves and earlier rounds.  The tile is
-// first placed in LDS in digit order, then written out in that order, so
-// that consecutive threads write consecutive addresses of a digit's run.
+// Stable scatter of one tile.  Wave w takes the tile's elements
+// [512 w, 512 w + 512) in 8 rounds of 64 consecutive ones and ranks them
+// among equal digits on its own: a ballot match gives the rank inside a
+// round, a wave-private LDS counter per digit the elements of earlier
+// rounds (no workgroup barrier while ranking).  One pass over the digits
+// then turns the per-wave counts into each wave's first position of each
+// digit inside the tile (digits in order, waves in order within a digit:
+// the tile's order, so the sort is stable).  The tile is placed in LDS in
+// digit order and written out in that order, so that consecutive threads
+// write consecutive addresses of a digit's run.
 template <typename K, bool HAS_VAL>
 __global__ void __launch_bounds__(BLK) k_rs_scatter(const K *__restrict__ kin,
                                                     const uint32_t *__restrict__ vin,
@@ -220,63 +225,36 @@ __global__ void __launch_bounds__(BLK) k_rs_scatter(const K *__restrict__ kin,
     const uint32_t NB = 1u << dbits, mask = NB - 1;
     uint32_t *base_off = sm;           // [NB] output position of the tile's digit-d run
     uint32_t *lstart = sm + NB;        // [NB] start of digit d inside the tile
-    uint32_t *run = sm + 2 * NB;       // [NB]
-    uint32_t *wc = sm + 3 * NB;        // [NWAVE][NB] tagged wave counts
+    uint32_t *wcnt = sm + 2 * NB;      // [NWAVE][NB] counts, then first positions
     K *lkey = (K *)(sm + (3 + NWAVE) * NB);     // [TILE]
     uint32_t *lval = (uint32_t *)(lkey + TILE);  // [TILE]
     const uint32_t seg = blockIdx.x / tps, tile = blockIdx.x % tps;
     const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (uint32_t d = threadIdx.x; d < NB; d += BLK) {
+    uint32_t *mycnt = wcnt + wave * NB;
+    for (uint32_t d = threadIdx.x; d < NB; d += BLK)
         base_off[d] = hist[((uint64_t)seg * NB + d) * tps + tile];
-        lstart[d] = 0;
-        run[d] = 0;
-        for (int w = 0; w < NWAVE; w++) wc[w * NB + d] = 0;
-    }
-    __syncthreads();
+    for (uint32_t d = lane; d < NB; d += 64) mycnt[d] = 0;
     const uint64_t segbase = (uint64_t)seg * seglen;
     const uint32_t t0 = tile * TILE;
     const uint32_t nvalid = seglen - t0 < (uint32_t)TILE ? seglen - t0 : (uint32_t)TILE;
-    // ---- load the tile, count its digits
+    // ---- load and rank the wave's elements (LDS reads and writes of one
+    // wave happen in program order: a round's counter reads precede the
+    // leaders' updates, which precede the next round's reads)
     K key[IPT];
-    uint32_t val[IPT], dg[IPT];
-#pragma unroll
-    for (int rd = 0; rd < IPT; rd++) {
-        const uint32_t i = rd * BLK + threadIdx.x;
-        key[rd] = 0;
-        val[rd] = 0;
-        dg[rd] = 0;
-        if (i < nvalid) {
-            key[rd] = kin[segbase + t0 + i];
-            if (HAS_VAL) val[rd] = vin[segbase + t0 + i];
-            dg[rd] = (uint32_t)(key[rd] >> shift) & mask;
-            atomicAdd(&lstart[dg[rd]], 1u);
-        }
-    }
-    __syncthreads();
-    // ---- exclusive scan of the digit counts (NB / BLK consecutive digits per thread)
-    {
-        const uint32_t per = (NB + BLK - 1) / BLK;
-        const uint32_t d0 = threadIdx.x * per;
-        uint32_t sum = 0;
-        for (uint32_t q = 0; q < per; q++)
-            if (d0 + q < NB) sum += lstart[d0 + q];
-        uint32_t total;
-        uint32_t ex = block_exclusive_scan(sum, scan_tmp, total);
-        __syncthreads();
-        for (uint32_t q = 0; q < per; q++)
-            if (d0 + q < NB) {
-                const uint32_t c = lstart[d0 + q];
-                lstart[d0 + q] = ex;
-                ex += c;
-            }
-    }
-    __syncthreads();
-    // ---- stable ranks -> digit-ordered tile in LDS
+    uint32_t val[IPT], dg[IPT], lr[IPT];
     const uint64_t lt_mask = (1ULL << lane) - 1ULL;
 #pragma unroll
     for (int rd = 0; rd < IPT; rd++) {
-        const bool valid = rd * BLK + threadIdx.x < nvalid;
-        const uint32_t d = dg[rd];
+        const uint32_t e = wave * (64 * IPT) + rd * 64 + lane;
+        const bool valid = e < nvalid;
+        key[rd] = 0;
+        val[rd] = 0;
+        if (valid) {
+            key[rd] = kin[segbase + t0 + e];
+            if (HAS_VAL) val[rd] = vin[segbase + t0 + e];
+        }
+        const uint32_t d = valid ? (uint32_t)(key[rd] >> shift) & mask : 0u;
+        dg[rd] = d;
         uint64_t peers = __builtin_amdgcn_ballot_w64(valid);
         for (uint32_t b = 0; b < dbits; b++) {
             const bool bit = (d >> b) & 1u;
@@ -284,23 +262,44 @@ __global__ void __launch_bounds__(BLK) k_rs_scatter(const K *__restrict__ kin,
             peers &= bit ? bb : ~bb;
         }
         const uint64_t lower = peers & lt_mask;
-        const uint32_t rank = (uint32_t)__popcll(lower);
-        const uint32_t cnt = (uint32_t)__popcll(peers);
-        const uint32_t tag = (uint32_t)(rd + 1) << 16;
-        if (valid && lower == 0) wc[wave * NB + d] = tag | cnt;
-        __syncthreads();
-        if (valid) {
-            uint32_t prefix = 0;
-            for (uint32_t w = 0; w < wave; w++) {
-                const uint32_t x = wc[w * NB + d];
-                if ((x & 0xFFFF0000u) == tag) prefix += x & 0xFFFFu;
+        const uint32_t before = valid ? mycnt[d] : 0u;
+        lr[rd] = before + (uint32_t)__popcll(lower);
+        if (valid && lower == 0) mycnt[d] = before + (uint32_t)__popcll(peers);
+    }
+    __syncthreads();
+    // ---- digit starts inside the tile, and each wave's first position of
+    // each digit (NB / BLK consecutive digits per thread)
+    {
+        const uint32_t per = (NB + BLK - 1) / BLK;
+        const uint32_t d0 = threadIdx.x * per;
+        uint32_t sum = 0;
+        for (uint32_t q = 0; q < per; q++)
+            if (d0 + q < NB)
+#pragma unroll
+                for (int w = 0; w < NWAVE; w++) sum += wcnt[w * NB + d0 + q];
+        uint32_t total;
+        uint32_t ex = block_exclusive_scan(sum, scan_tmp, total);
+        for (uint32_t q = 0; q < per; q++)
+            if (d0 + q < NB) {
+                lstart[d0 + q] = ex;
+#pragma unroll
+                for (int w = 0; w < NWAVE; w++) {
+                    const uint32_t c = wcnt[w * NB + d0 + q];
+                    wcnt[w * NB + d0 + q] = ex;
+                    ex += c;
+                }
             }
-            const uint32_t lpos = lstart[d] + run[d] + prefix + rank;
+    }
+    __syncthreads();
+    // ---- digit-ordered tile in LDS
+#pragma unroll
+    for (int rd = 0; rd < IPT; rd++) {
+        const uint32_t e = wave * (64 * IPT) + rd * 64 + lane;
+        if (e < nvalid) {
+            const uint32_t lpos = mycnt[dg[rd]] + lr[rd];
             lkey[lpos] = key[rd];
             if (HAS_VAL) lval[lpos] = val[rd];
         }
-        __syncthreads();
-        if (valid && lower == 0) atomicAdd(&run[d], cnt);
     }
     __syncthreads();
     // ---- write out in digit order
