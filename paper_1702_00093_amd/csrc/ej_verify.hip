@@ -105,6 +105,17 @@ __device__ inline uint32_t from_next_lane(uint32_t x, uint32_t keep) {
     return MODE == LANES_WAVE ? y : (y & keep);
 }
 
+// Words of one pair's match-mask tile in LDS: sigma rows of `stride` words,
+// padded so that consecutive tiles start 16 banks apart.  The rows' strides
+// are multiples of 32 words, so without the pad the pairs of a wave would
+// read their ring slots from the same banks in every column (4-way bank
+// conflicts at 4 pairs per wave); with it, 2-way, the least that 64 lanes
+// reading 64 words from 32 banks can have.
+__host__ __device__ inline uint32_t tile_words_for(uint32_t sigma, uint32_t stride) {
+    const uint32_t w = sigma * stride;
+    return w + ((16u - (w & 31u)) & 31u);
+}
+
 // 32 columns of Myers' step in the diagonal-aligned band.  FAST counts the
 // tracked diagonal with a masked popcount (no pair's text ends inside the
 // block); otherwise one bit per column is collected into acc.
@@ -297,7 +308,7 @@ __global__ void __launch_bounds__(64)
     const bool in_tile = tile < tpw;
     const uint32_t RW = wpp;                          // ring: words per ring
     const uint32_t stride = RING ? 2 * RW : wpp;      // words per symbol
-    const uint32_t tile_words = sigma * stride;
+    const uint32_t tile_words = tile_words_for(sigma, stride);
     uint64_t last = 0;  // top lane of every pair, and lanes outside pairs
     for (uint32_t q = 0; q < 64; q++)
         if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
@@ -438,7 +449,7 @@ __global__ void __launch_bounds__(64)
     const bool in_tile = tile < tpw;
     const uint32_t RW = wpp;
     const uint32_t stride = RING ? 2 * RW : wpp;
-    const uint32_t tile_words = sigma * stride;
+    const uint32_t tile_words = tile_words_for(sigma, stride);
     uint64_t last = 0;
     for (uint32_t q = 0; q < 64; q++)
         if ((q / NL) >= tpw || (q % NL) == NL - 1) last |= 1ull << q;
@@ -1760,7 +1771,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     const uint32_t ring_mode = ctx->tune.verify_ring;
     const bool ring = ring_mode != 0 && NL >= 2 && (ring_mode == 2 || 2 * RW < wpp_full);
     const uint32_t wpp = ring ? RW : wpp_full;
-    const uint32_t tile_bytes = sig * (ring ? 2 * RW : wpp_full) * 4;
+    const uint32_t tile_bytes = tile_words_for(sig, ring ? 2 * RW : wpp_full) * 4;
     uint32_t tpw = 64 / NL;
     uint32_t budget = ctx->tune.verify_lds_budget;
     if ((int)budget > ctx->lds_max) budget = (uint32_t)ctx->lds_max;
