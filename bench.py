@@ -50,12 +50,13 @@ OPS_PER_WORD_STEP = 10
 SURVEY_OPS_PER_WORD = 20
 OPS_PER_WALK_STEP = 3    # walk: read the symbol, select its pi bit, advance
 VERIFY_KERNEL = {0: "k_verify", 1: "k_verify_queue", 2: "k_verify_lane", 3: "k_verify_split",
-                 4: "k_verify_grp"}
+                 4: "k_verify_grp", 5: "k_verify"}
 VERIFY_FORM = {0: "two-pass", 1: "persistent, replayed from a captured HIP graph",
                2: "one pair per lane, persistent, replayed from a captured HIP graph",
                3: "several band words per lane, persistent, replayed from a captured HIP graph",
                4: "grouped by pattern (masks shared in LDS per chunk), one pair per lane, "
-                  "persistent, replayed from a captured HIP graph"}
+                  "persistent, replayed from a captured HIP graph",
+               5: "two-pass, two band words per lane"}
 LEGS = ("tiny", "uneven", "protein", "plus", "serving")
 
 # Recall-calibrated parameter points, found by sweeps of (r, z, m, L) on these

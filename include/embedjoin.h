@@ -129,7 +129,8 @@ typedef struct {
     /* The verification form that ran: 0 two passes over groups of pairs,
      * 1 persistent groups of pairs, 2 one pair per lane, 3 several lanes per
      * pair with several band words each (2 and 3: "verify_mode" 2), 4 grouped
-     * by pattern ("verify_mode" 3). */
+     * by pattern ("verify_mode" 3), 5 the two-pass form with two band words
+     * per lane ("verify_wpl" 2). */
     uint32_t verify_form;
     /* 1 when pairs and dist are device pointers (EJ_FLAG_DEVICE_OUT) */
     uint32_t on_device;
@@ -157,6 +158,9 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_lds_budget"     LDS bytes per wave of the verification kernel
  *   "verify_pass1_cols"     columns of verification pass 1 (multiple of 32;
  *                           0 = a single pass)
+ *   "verify_wpl"            two-pass verification: band words per lane, 1
+ *                           or 2 (default 2; 2 applies to bands of 4 words
+ *                           or more, narrower bands keep one)
  *   "verify_blocks_per_cu"  workgroups per CU of the verification grid (the
  *                           lane form: at most, below the occupancy limit)
  *   "verify_mode"           0: two passes over fixed groups of pairs, one

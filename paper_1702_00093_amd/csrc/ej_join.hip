@@ -448,12 +448,13 @@ std::string join_shape(ej_ctx *ctx, const Prep &pp, const uint8_t *d_chars,
     char key[512];
     snprintf(key, sizeof(key),
              "join %p %p %u %llu %llu %u %u %u %u %u %u %u %llu | %u %u %u %u %u %u %u %u %u %u "
-             "%u %u",
+             "%u %u %u",
              (const void *)d_chars, (const void *)d_offsets, pp.n, (unsigned long long)pp.base,
              (unsigned long long)pp.total, pp.sigma, pp.maxlen, pp.L, p.K, p.r, p.z, p.m,
              (unsigned long long)p.seed, t.verify_mode, t.verify_order, t.verify_split,
              t.verify_pass1_cols, t.verify_blocks_per_cu, t.verify_ring, t.verify_lds_budget,
-             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits, t.dedup_sort, t.raw_limit);
+             t.embed_lds_budget, t.radix_bits, t.bucket_key_bits, t.dedup_sort, t.raw_limit,
+             t.verify_wpl);
     return key;
 }
 
@@ -1007,6 +1008,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
         const Knob knobs[] = {
             {&Tuning::verify_mode, {0, 1, 2, 3}, 15},
             {&Tuning::verify_split, {0, 1, 2, 4, 8}, 4},
+            {&Tuning::verify_wpl, {1, 2}, 1},
             {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 1},
             {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 1},
             {&Tuning::verify_blocks_per_cu, {2, 4, 8, 16, 32}, 12},

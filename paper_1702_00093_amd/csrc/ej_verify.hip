@@ -72,12 +72,26 @@ __device__ inline uint32_t add_carry_mask(uint32_t a, uint32_t b, uint64_t &carr
     return s;
 }
 
+// s = a + b + (bit `lane` of cin); carry-outs of every lane in cout.
+__device__ inline uint32_t add_carry_chain(uint32_t a, uint32_t b, uint64_t cin, uint64_t &cout) {
+    uint32_t s;
+    asm("v_addc_co_u32 %0, %1, %2, %3, %4" : "=v"(s), "=s"(cout) : "v"(a), "v"(b), "s"(cin));
+    return s;
+}
+
 // s = a + (bit `lane` of the wave-wide mask cin): one add with the carry-in
 // taken straight from the scalar mask.
 __device__ inline uint32_t add_carry_in(uint32_t a, uint64_t cin) {
     uint32_t s;
     uint64_t unused;
     asm("v_addc_co_u32 %0, %1, %2, 0, %3" : "=v"(s), "=s"(unused) : "v"(a), "s"(cin));
+    return s;
+}
+
+// s = a + (bit `lane` of cin), with the carry-out of every lane in cout.
+__device__ inline uint32_t add_carry_in_out(uint32_t a, uint64_t cin, uint64_t &cout) {
+    uint32_t s;
+    asm("v_addc_co_u32 %0, %1, %2, 0, %3" : "=v"(s), "=s"(cout) : "v"(a), "s"(cin));
     return s;
 }
 
@@ -160,6 +174,59 @@ __device__ inline void myers_block(const uint8_t *peq, uint32_t stride4, uint32_
             Z = popc_acc((Xv1 | Mh) & kmask, Z);
         else
             acc |= (((Xv1 | Mh) >> kbit) & 1u) << s;
+    }
+}
+
+// myers_block with two band words per lane (words 2l and 2l+1 of the pair's
+// band in lane l): the lane's 64-bit sum carries between its words inside
+// the lane, and the lookahead between lanes (ballots, scalar add) and the
+// shift's word from the next lane are paid once per 64 bits.  The tracked
+// diagonal is bit kbit of word 0 (mask km0) or of word 1 (km1) of the owner
+// lane.
+template <int MODE, bool FAST>
+__device__ inline void myers_block2(const uint8_t *peq, uint32_t stride4, uint32_t slot4,
+                                    const uint32_t tw[8], uint32_t (&Pv)[2], uint32_t (&Mv)[2],
+                                    uint32_t &Z, uint32_t &acc, uint32_t km0, uint32_t km1,
+                                    uint32_t kbit, uint64_t notlast, uint32_t keep) {
+#pragma unroll
+    for (uint32_t s = 0; s < 32; s++) {
+        const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
+        const uint32_t *pa = (const uint32_t *)(peq + (__umul24(c, stride4) + slot4));
+        const uint32_t w1 = pa[1];
+        const uint32_t eq0 = __builtin_amdgcn_alignbit(w1, pa[0], s);
+        const uint32_t eq1 = __builtin_amdgcn_alignbit(pa[2], w1, s);
+        const uint32_t X0 = eq0 | Mv[0], X1 = eq1 | Mv[1];
+        uint64_t c0, G;
+        uint32_t s0 = add_carry_mask(eq0 & Pv[0], Pv[0], c0);
+        uint32_t s1 = add_carry_chain(eq1 & Pv[1], Pv[1], c0, G);
+        if (MODE != LANES_ONE) {
+            uint64_t P = __builtin_amdgcn_ballot_w64((s0 & s1) == 0xFFFFFFFFu);
+            if (MODE != LANES_WAVE) {
+                G &= notlast;
+                P &= notlast;
+            }
+            const uint64_t cin = ((G | P) + G) ^ P;
+            uint64_t c1;
+            s0 = add_carry_in_out(s0, cin, c1);
+            s1 = add_carry_in(s1, c1);
+        }
+        const uint32_t Xh0 = (s0 ^ Pv[0]) | eq0, Xh1 = (s1 ^ Pv[1]) | eq1;
+        const uint32_t Ph0 = Mv[0] | ~(Xh0 | Pv[0]), Ph1 = Mv[1] | ~(Xh1 | Pv[1]);
+        const uint32_t Mh0 = Pv[0] & Xh0, Mh1 = Pv[1] & Xh1;
+        const uint32_t nx = MODE == LANES_ONE ? 0u : from_next_lane<MODE>(X0, keep);
+        const uint32_t Xs0 = __builtin_amdgcn_alignbit(X1, X0, 1);
+        const uint32_t Xs1 = __builtin_amdgcn_alignbit(nx, X1, 1);
+        Pv[0] = Mh0 | ~(Xs0 | Ph0);
+        Pv[1] = Mh1 | ~(Xs1 | Ph1);
+        Mv[0] = Ph0 & Xs0;
+        Mv[1] = Ph1 & Xs1;
+        if (FAST) {
+            Z = popc_acc((Xs0 | Mh0) & km0, Z);
+            Z = popc_acc((Xs1 | Mh1) & km1, Z);
+        } else {
+            const uint32_t d = ((Xs0 | Mh0) & km0) | ((Xs1 | Mh1) & km1);
+            acc |= (d != 0u ? 1u : 0u) << s;
+        }
     }
 }
 
@@ -288,8 +355,10 @@ __device__ inline void fill_tile(uint32_t *pq, const PairView &v, uint32_t l, ui
 // column 0 and stops at column jlim; the owner lane writes aux[pidx] = Z for
 // a pair still undecided there (its Pv/Mv go to `state`) and DECIDED for the
 // others.  Pass 2 (resume == 1) takes the pairs listed in `list`, restores
-// their state and runs them to the end.
-template <int MODE, bool RING>
+// their state and runs them to the end.  WPL band words per lane (1 or 2):
+// lane l of a pair holds words WPL*l .. WPL*l + WPL - 1, NL_arg is the lanes
+// per pair.
+template <int MODE, bool RING, int WPL>
 __global__ void __launch_bounds__(64)
     k_verify(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count_arg,
              const uint64_t *__restrict__ count_dev, const uint32_t *__restrict__ list,
@@ -300,6 +369,8 @@ __global__ void __launch_bounds__(64)
     extern __shared__ uint32_t lds[];
     unsigned long long colsum = 0;  // text columns of the pairs decided here
     const uint32_t NL = lanes_of<MODE>(NL_arg);
+    const uint32_t NW = NL * WPL;  // band words of a pair
+    constexpr uint32_t LWB = WPL == 2 ? 6 : 5;  // log2 of the bits a lane holds
     // pass 2, and a join sized on the device, take the pair count from the
     // device (a grid sized for all pairs; never more than count_arg)
     const uint64_t count = count_dev ? min(*count_dev, count_arg) : count_arg;
@@ -327,29 +398,37 @@ __global__ void __launch_bounds__(64)
         //      the whole pattern (full), every tile its own
         if (in_tile)
             fill_tile<RING>(pq_mine, v, l, NL, sigma, stride, RW, wpp, RING ? (jbeg >> 5) : 0u,
-                            RING ? NL + 1 : wpp);
+                            RING ? NW + 1 : wpp);
         __syncthreads();
 
         // ---- state at column jbeg
         const uint32_t kstar = v.O + v.dstar;
-        const bool owner = in_tile && (kstar >> 5) == l;
+        const bool owner = in_tile && (kstar >> LWB) == l;
         const uint32_t kbit = kstar & 31;
-        uint32_t Pv, Mv, Z = 0;
+        // the tracked diagonal's word inside the owner lane (two words)
+        const uint32_t kw = WPL == 2 ? (kstar >> 5) & 1u : 0u;
+        uint32_t Pv[WPL], Mv[WPL], Z = 0;
         if (resume) {
-            Pv = act ? state[(pidx * NL + l) * 2] : 0u;
-            Mv = act ? state[(pidx * NL + l) * 2 + 1] : 0u;
+#pragma unroll
+            for (int q = 0; q < WPL; q++) {
+                Pv[q] = act ? state[(pidx * NL + l) * 2 * WPL + 2 * q] : 0u;
+                Mv[q] = act ? state[(pidx * NL + l) * 2 * WPL + 2 * q + 1] : 0u;
+            }
             if (owner && act) Z = aux[pidx];
         } else {
             // D[i][0] = |i|: bit k holds row k - O, rows <= 0 have delta -1
-            const int lo = 32 * (int)l;
-            const int Oi = (int)v.O;
-            if (Oi >= lo + 31)
-                Mv = ~0u;
-            else if (Oi < lo)
-                Mv = 0u;
-            else
-                Mv = (1u << (Oi - lo + 1)) - 1u;
-            Pv = ~Mv;
+#pragma unroll
+            for (int q = 0; q < WPL; q++) {
+                const int lo = 32 * (int)(WPL * l + q);
+                const int Oi = (int)v.O;
+                if (Oi >= lo + 31)
+                    Mv[q] = ~0u;
+                else if (Oi < lo)
+                    Mv[q] = 0u;
+                else
+                    Mv[q] = (1u << (Oi - lo + 1)) - 1u;
+                Pv[q] = ~Mv[q];
+            }
         }
         uint32_t nmax = v.nn;
         for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, d, 64));
@@ -359,18 +438,31 @@ __global__ void __launch_bounds__(64)
         load_text_block(v.yp, v.nn, jbeg, tw);
         for (uint32_t jb = jbeg; jb < jend; jb += 32) {
             load_text_block(v.yp, v.nn, jb + 32, tn);
-            const uint32_t wn = (jb >> 5) + NL + 1;  // ring: the word entering next
-            const uint32_t slot4 = 4 * (RING ? (((jb >> 5) + l) & (RW - 1)) : ((jb >> 5) + l));
+            const uint32_t wn = (jb >> 5) + NW + 1;  // ring: the word entering next
+            const uint32_t w0 = (jb >> 5) + WPL * l;   // the lane's first band word
+            const uint32_t slot4 = 4 * (RING ? (w0 & (RW - 1)) : w0);
             // columns past the end of a pair's text do not count; a block
             // where no text ends takes the masked-popcount path
             const bool ends_here = in_tile && v.nn > jb && v.nn < jb + 32;
             if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
                 const uint32_t km = (owner && jb + 32 <= v.nn) ? (1u << kbit) : 0u;
                 uint32_t unused = 0;
-                myers_block<MODE, true>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, unused, km, kbit, notlast, keep);
+                if constexpr (WPL == 2)
+                    myers_block2<MODE, true>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, unused,
+                                             kw ? 0u : km, kw ? km : 0u, kbit, notlast, keep);
+                else
+                    myers_block<MODE, true>(peq8, 4 * stride, slot4, tw, Pv[0], Mv[0], Z, unused,
+                                            km, kbit, notlast, keep);
             } else {
                 uint32_t acc = 0;
-                myers_block<MODE, false>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, acc, 0u, kbit, notlast, keep);
+                if constexpr (WPL == 2) {
+                    const uint32_t km = owner ? (1u << kbit) : 0u;
+                    myers_block2<MODE, false>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, acc,
+                                              kw ? 0u : km, kw ? km : 0u, kbit, notlast, keep);
+                } else {
+                    myers_block<MODE, false>(peq8, 4 * stride, slot4, tw, Pv[0], Mv[0], Z, acc, 0u,
+                                             kbit, notlast, keep);
+                }
                 const uint32_t ncol = v.nn > jb ? min(v.nn - jb, 32u) : 0u;
                 const uint32_t cmask = ncol >= 32 ? 0xFFFFFFFFu : ((1u << ncol) - 1u);
                 if (owner) Z += (uint32_t)__builtin_popcount(acc & cmask);
@@ -400,12 +492,15 @@ __global__ void __launch_bounds__(64)
         const bool und_owner =
             owner && act && !v.skip && Vd <= v.Kp && jdone < v.nn && jlim != NO_LIMIT;
         const uint64_t und_mask = __builtin_amdgcn_ballot_w64(und_owner);
-        const uint32_t owner_lane = tile * NL + (kstar >> 5);
+        const uint32_t owner_lane = tile * NL + (kstar >> LWB);
         const bool undecided = in_tile && ((und_mask >> (owner_lane & 63)) & 1ull);
         if (act && undecided) {
             // pass 1 stops here: keep the state of the pair for pass 2
-            state[(pidx * NL + l) * 2] = Pv;
-            state[(pidx * NL + l) * 2 + 1] = Mv;
+#pragma unroll
+            for (int q = 0; q < WPL; q++) {
+                state[(pidx * NL + l) * 2 * WPL + 2 * q] = Pv[q];
+                state[(pidx * NL + l) * 2 * WPL + 2 * q + 1] = Mv[q];
+            }
         }
         if (owner && act) {
             if (undecided) {
@@ -618,13 +713,6 @@ __device__ inline void lane_text_block(const uint8_t *y, uint32_t nn, uint32_t j
         const uint32_t keep = v >= 4 ? 0xFFFFFFFFu : ((1u << (8 * v)) - 1u);
         tw[q] = (tw[q] & keep) | (fill & ~keep);
     }
-}
-
-// s = a + b + (bit `lane` of cin); carry-outs of every lane in cout.
-__device__ inline uint32_t add_carry_chain(uint32_t a, uint32_t b, uint64_t cin, uint64_t &cout) {
-    uint32_t s;
-    asm("v_addc_co_u32 %0, %1, %2, %3, %4" : "=v"(s), "=s"(cout) : "v"(a), "v"(b), "s"(cin));
-    return s;
 }
 
 // 32 columns of one pair per lane.  Row c of the lane's window holds the
@@ -1782,10 +1870,10 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     tpw = std::min(tpw, budget / tile_bytes);
     const size_t lds = (size_t)tpw * tile_bytes;
     const int mode = NL == 1 ? LANES_ONE : NL == 16 ? LANES_ROW : NL == 64 ? LANES_WAVE : LANES_ANY;
-    auto kern = mode == LANES_ONE    ? k_verify<LANES_ONE, false>
-                : mode == LANES_ROW  ? (ring ? k_verify<LANES_ROW, true> : k_verify<LANES_ROW, false>)
-                : mode == LANES_WAVE ? (ring ? k_verify<LANES_WAVE, true> : k_verify<LANES_WAVE, false>)
-                : (ring ? k_verify<LANES_ANY, true> : k_verify<LANES_ANY, false>);
+    auto kern = mode == LANES_ONE    ? k_verify<LANES_ONE, false, 1>
+                : mode == LANES_ROW  ? (ring ? k_verify<LANES_ROW, true, 1> : k_verify<LANES_ROW, false, 1>)
+                : mode == LANES_WAVE ? (ring ? k_verify<LANES_WAVE, true, 1> : k_verify<LANES_WAVE, false, 1>)
+                : (ring ? k_verify<LANES_ANY, true, 1> : k_verify<LANES_ANY, false, 1>);
     if (lds > 65536)
         EJ_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)lds));
@@ -2024,19 +2112,53 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     ctx->last_verify_form = 0;
     const uint32_t C1 = ctx->tune.verify_pass1_cols & ~31u;
     const bool two_pass = C1 > 0 && C1 < mtext;
+    // two band words per lane (knob verify_wpl = 2, bands of 4 words or
+    // more): half the lanes per pair, so the lookahead between lanes, the
+    // shift's word from the next lane and the tracked diagonal are paid once
+    // per 64 bits; its own ring, tile and lanes
+    uint32_t vNL = NL, vtpw = tpw, vwpp = wpp;
+    size_t vlds = lds;
+    auto vkern = kern;
+    const bool w2 = ctx->tune.verify_wpl == 2 && NL >= 4;
+    if (w2) {
+        const uint32_t NL2 = (NL + 1) / 2, NW = 2 * NL2;
+        uint32_t wppf = (mtext + 32 * NW + 64) / 32 + 2;
+        wppf = (wppf + 1) & ~1u;
+        uint32_t RW2 = 1;
+        while (RW2 < NW + 2) RW2 <<= 1;
+        const bool ring2 = ring_mode != 0 && (ring_mode == 2 || 2 * RW2 < wppf);
+        const uint32_t tb = tile_words_for(sig, ring2 ? 2 * RW2 : wppf) * 4;
+        uint32_t b2 = ctx->tune.verify_lds_budget;
+        if ((int)b2 > ctx->lds_max) b2 = (uint32_t)ctx->lds_max;
+        if (tb > b2) b2 = (uint32_t)ctx->lds_max;
+        if (tb > b2)
+            fail(EJ_EUNSUPPORTED, "strings too long for the LDS-resident match masks (" +
+                                      std::to_string(tb) + " bytes per pair)");
+        vNL = NL2;
+        vtpw = std::min(64u / NL2, b2 / tb);
+        vwpp = ring2 ? RW2 : wppf;
+        vlds = (size_t)vtpw * tb;
+        vkern = NL2 == 16 ? (ring2 ? k_verify<LANES_ROW, true, 2> : k_verify<LANES_ROW, false, 2>)
+                          : (ring2 ? k_verify<LANES_ANY, true, 2> : k_verify<LANES_ANY, false, 2>);
+        if (vlds > 65536)
+            EJ_HIP(hipFuncSetAttribute((const void *)vkern,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
+        ctx->last_verify_form = 5;
+    }
     uint32_t *state = nullptr, *aux = nullptr;
     if (two_pass) {
-        state = ws<uint32_t>(ctx, "verify_state", count * NL * 2);
+        // Pv and Mv of every band word of every pair
+        state = ws<uint32_t>(ctx, "verify_state", count * vNL * (w2 ? 4 : 2));
         aux = ws<uint32_t>(ctx, "verify_aux", count);
     }
     const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;
     {
         kmark();
-        uint64_t ngroups = (count + tpw - 1) / tpw;
+        uint64_t ngroups = (count + vtpw - 1) / vtpw;
         uint64_t grid = std::min<uint64_t>(ngroups, cap);
-        hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
+        hipLaunchKernelGGL(vkern, dim3((uint32_t)grid), dim3(64), vlds, ctx->stream, A, B, d_pairs,
                            count, d_count, (const uint32_t *)nullptr, K, d_Kq,
-                           sig, NL, tpw, wpp, 0u,
+                           sig, vNL, vtpw, vwpp, 0u,
                            two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
         EJ_CHECK_LAUNCH();
         kmark();
@@ -2066,12 +2188,12 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
                        lkey, lval);
     EJ_CHECK_LAUNCH();
     radix_sort_u32(ctx, lkey, lval, lkey2, list, 1, (uint32_t)count, 11, 11);
-    uint64_t ngroups = (count + tpw - 1) / tpw;
+    uint64_t ngroups = (count + vtpw - 1) / vtpw;
     uint64_t grid = std::min<uint64_t>(ngroups, cap);
     kmark();
-    hipLaunchKernelGGL(kern, dim3((uint32_t)grid), dim3(64), lds, ctx->stream, A, B, d_pairs,
-                       count, (const uint64_t *)d_nalive, (const uint32_t *)list, K, d_Kq, sig, NL,
-                       tpw, wpp, C1, NO_LIMIT, 1,
+    hipLaunchKernelGGL(vkern, dim3((uint32_t)grid), dim3(64), vlds, ctx->stream, A, B, d_pairs,
+                       count, (const uint64_t *)d_nalive, (const uint32_t *)list, K, d_Kq, sig,
+                       vNL, vtpw, vwpp, C1, NO_LIMIT, 1,
                        state, aux, d_dist, d_columns);
     EJ_CHECK_LAUNCH();
     kmark();

@@ -35,15 +35,18 @@ def ctx(ej):
 
 
 def _each_verify_mode(ctx):
-    """Runs the body once per verification form (two-pass, persistent tiles,
-    one pair per lane, grouped by pattern)."""
-    old = ctx.tune_get("verify_mode")
+    """Runs the body once per verification form (two-pass with one and with
+    two band words per lane, persistent tiles, one pair per lane, grouped by
+    pattern); the mode yielded for the two-word two-pass form is "0w2"."""
+    old = (ctx.tune_get("verify_mode"), ctx.tune_get("verify_wpl"))
     try:
-        for mode in (0, 1, 2, 3):
+        for mode, wpl in ((0, 1), (0, 2), (1, 1), (2, 1), (3, 1)):
             ctx.tune_set("verify_mode", mode)
-            yield mode
+            ctx.tune_set("verify_wpl", wpl)
+            yield mode if wpl == 1 else "0w2"
     finally:
-        ctx.tune_set("verify_mode", old)
+        ctx.tune_set("verify_mode", old[0])
+        ctx.tune_set("verify_wpl", old[1])
 
 
 def _oracle_join(oracle_lib, col, K, r, z, m, seed, L=0):
@@ -249,14 +252,17 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
     chars, offs = to_device(col)
     d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
     old = (ctx.tune_get("verify_ring"), ctx.tune_get("verify_pass1_cols"),
-           ctx.tune_get("verify_mode"), ctx.tune_get("verify_split"))
+           ctx.tune_get("verify_mode"), ctx.tune_get("verify_split"),
+           ctx.tune_get("verify_wpl"))
     try:
         for ring in (0, 2):
-            for mode, c1 in ((0, 0), (0, 64), (0, 1024), (1, 0)):
+            for mode, c1, wpl in ((0, 0, 1), (0, 64, 1), (0, 1024, 1), (1, 0, 1), (0, 0, 2),
+                                  (0, 64, 2), (0, 1024, 2)):
                 ctx.tune_set("verify_ring", ring)
                 ctx.tune_set("verify_pass1_cols", c1)
                 ctx.tune_set("verify_mode", mode)
-                _say(f"verify layout K={K} ring={ring} mode={mode} c1={c1}")
+                ctx.tune_set("verify_wpl", wpl)
+                _say(f"verify layout K={K} ring={ring} mode={mode} c1={c1} wpl={wpl}")
                 got = ctx.verify(chars, offs, d_codes, K)
                 assert got.cpu().numpy().astype(np.uint32).tolist() == want
         ctx.tune_set("verify_mode", 2)
@@ -274,6 +280,7 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
         ctx.tune_set("verify_pass1_cols", old[1])
         ctx.tune_set("verify_mode", old[2])
         ctx.tune_set("verify_split", old[3])
+        ctx.tune_set("verify_wpl", old[4])
 
 
 def test_candidate_groups_with_many_distinct_pairs(ej, ctx, oracle_lib):
@@ -424,16 +431,19 @@ def test_verify_two_pass_resume(ej, ctx, oracle_lib, c1):
     b = rng.integers(0, n, size=300)
     codes = (a.astype(np.uint64) << np.uint64(32)) | b.astype(np.uint64)
     chars, offs = to_device(col)
-    old = ctx.tune_get("verify_pass1_cols")
+    old = (ctx.tune_get("verify_pass1_cols"), ctx.tune_get("verify_wpl"))
     try:
         ctx.tune_set("verify_pass1_cols", c1)
-        for K in (3, 60, 130):
+        for K in (3, 60, 130, 200):
             want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
-            _say(f"two-pass c1={c1} K={K}")
-            got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
-            assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
+            for wpl in (1, 2):
+                ctx.tune_set("verify_wpl", wpl)
+                _say(f"two-pass c1={c1} K={K} wpl={wpl}")
+                got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
+                assert got.cpu().numpy().astype(np.uint32).tolist() == want.tolist()
     finally:
-        ctx.tune_set("verify_pass1_cols", old)
+        ctx.tune_set("verify_pass1_cols", old[0])
+        ctx.tune_set("verify_wpl", old[1])
 
 
 def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
@@ -444,7 +454,7 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
     knobs = [("radix_bits", 4), ("radix_bits", 11), ("bucket_key_bits", 5),
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
              ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
-             ("verify_ring", 2), ("verify_mode", 1)]
+             ("verify_ring", 2), ("verify_mode", 1), ("verify_wpl", 1)]
     # the persistent forms with and without the multiplicity order
     try:
         for mode, split in ((1, 0), (2, 0), (2, 1), (2, 4)):
