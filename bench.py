@@ -31,12 +31,12 @@ METRIC = ("end-to-end join sec & verified candidate pairs/s at recall≥0.99; "
 # Integer VALU peak from the unit counts and clock: 256 CUs x 4 SIMDs x 32
 # lanes per cycle x 2.4 GHz = 78.6 T lane-ops/s, the rate of the fp32 vector
 # figure (157.3 TFLOP/s counts an FMA as 2).  The probe kernel measures it for
-# 2-operand 32-bit integer instructions (v_add_u32, v_xor_b32: a wave64
-# instruction every 2 cycles per SIMD); 3-operand ones (v_bitop3_b32,
-# v_alignbit_b32, v_add_co_u32 with a scalar carry-out) issue at half that
-# rate (4 cycles), 39.3 T.
+# the full-rate integer instructions (v_add_u32, v_xor_b32, v_bitop3_b32 with
+# register operands: a wave64 instruction every 2 cycles per SIMD); a second
+# class (v_alignbit_b32, the carry adds, compares, DPP moves, v_bcnt, v_add3)
+# issues at half that rate (4 cycles), 39.3 T.
 MI355X_INT32_LANE_OPS = 256 * 4 * 32 * 2.4e9
-MI355X_INT32_LANE_OPS_3OP = 256 * 4 * 16 * 2.4e9
+MI355X_INT32_LANE_OPS_HALF = 256 * 4 * 16 * 2.4e9
 
 # Work units of verification, in 32-bit integer lane operations per 32-cell
 # word of the K+1 band (diagonals a threshold-K distance needs):
@@ -212,7 +212,12 @@ def copy_probe(nbytes):
 
 
 PROBE_MIXES = {0: "verification mix (add, 3-input logic, funnel shift)", 1: "v_add_u32",
-               2: "v_xor_b32", 3: "v_bitop3_b32", 4: "v_alignbit_b32", 5: "v_add_co_u32"}
+               2: "v_xor_b32", 3: "v_bitop3_b32", 4: "v_alignbit_b32",
+               5: "v_add_co_u32 (carry-out to a scalar mask)",
+               6: "v_addc_co_u32 (carry chain through a scalar mask)", 7: "v_cmp_eq_u32",
+               8: "v_mov_b32_dpp wave_shl:1", 9: "v_bcnt_u32_b32", 10: "v_add3_u32",
+               11: "v_cndmask_b32 (scalar mask)", 12: "v_or3_b32", 13: "v_and_or_b32",
+               14: "v_mul_u32_u24_sdwa (byte select)"}
 
 
 def valu_peak(ctx, all_mixes=False):
@@ -376,7 +381,7 @@ def roofline(res, stage, prm, kern, peak_measured=None):
         out["achieved_survey_unit"] = round(a2, 4)
         out["survey_unit"] = "20 ops per 32-cell word (recurrence + cross-lane carry + shift)"
         out["frac_survey_unit"] = round(a2 / peak, 5)
-        out["frac_vs_3_operand_peak"] = round(achieved / (MI355X_INT32_LANE_OPS_3OP / 1e12), 5)
+        out["frac_vs_half_rate_peak"] = round(achieved / (MI355X_INT32_LANE_OPS_HALF / 1e12), 5)
         if peak_measured:
             out["frac_survey_unit_vs_measured"] = round(a2 / (peak_measured / 1e12), 5)
     return out

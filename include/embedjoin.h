@@ -130,7 +130,7 @@ typedef struct {
      * 1 persistent groups of pairs, 2 one pair per lane, 3 several lanes per
      * pair with several band words each (2 and 3: "verify_mode" 2), 4 grouped
      * by pattern ("verify_mode" 3), 5 the two-pass form with two band words
-     * per lane ("verify_wpl" 2). */
+     * per lane ("verify_wpl" 2 or 4). */
     uint32_t verify_form;
     /* 1 when pairs and dist are device pointers (EJ_FLAG_DEVICE_OUT) */
     uint32_t on_device;
@@ -158,9 +158,9 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_lds_budget"     LDS bytes per wave of the verification kernel
  *   "verify_pass1_cols"     columns of verification pass 1 (multiple of 32;
  *                           0 = a single pass)
- *   "verify_wpl"            two-pass verification: band words per lane, 1
- *                           or 2 (default 2; 2 applies to bands of 4 words
- *                           or more, narrower bands keep one)
+ *   "verify_wpl"            two-pass verification: band words per lane, 1,
+ *                           2 or 4 (default 2; 3 acts as 2; lowered until
+ *                           the band has at least twice as many words)
  *   "verify_blocks_per_cu"  workgroups per CU of the verification grid (the
  *                           lane form: at most, below the occupancy limit)
  *   "verify_mode"           0: two passes over fixed groups of pairs, one
@@ -434,10 +434,14 @@ ej_status ej_calibrate(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_of
  * iteration, no memory traffic) on blocks_per_cu workgroups of 256 lanes per
  * CU for `iters` iterations and returns the achieved lane operations per
  * second and the kernel time (one untimed launch runs first).  mix selects
- * the instructions: 0 verification's add / 3-input logic / funnel shift in
- * turn; 1 32-bit add; 2 xor; 3 3-input logic; 4 funnel shift; 5 add with the
- * carry-out to a scalar mask.  EJ_EINVAL for iters = 0, blocks_per_cu
- * outside 1..64 or mix above 5. */
+ * the instructions, all with register or inline-constant operands: 0
+ * verification's add / 3-input logic / funnel shift in turn; 1 32-bit add;
+ * 2 xor; 3 3-input logic (v_bitop3); 4 funnel shift; 5 add with the
+ * carry-out to a scalar mask; 6 add with carry in and out (a carry chain);
+ * 7 compare to VCC; 8 DPP one-lane shift across the wave; 9 popcount-add;
+ * 10 three-input add; 11 select on a scalar mask; 12 three-input or; 13
+ * and-or; 14 24-bit multiply of a selected byte.  EJ_EINVAL for iters = 0,
+ * blocks_per_cu outside 1..64 or mix above 14. */
 ej_status ej_probe_valu(ej_ctx *ctx, uint32_t mix, uint32_t iters, uint32_t blocks_per_cu,
                         double *lane_ops, float *ms);
 

@@ -112,7 +112,7 @@ struct Tuning {
     uint32_t bucket_key_bits = 0;            // key bits sorted when bucketing, 0 = ceil(log2 n) + 6
     uint32_t dedup_sort = 0;                 // candidates: 0 grouped (sort on overflow), 1 sort
     uint32_t raw_limit = 0;  // raw pairs per sort of the candidate stage (0: 2^32 - 2)
-    uint32_t verify_wpl = 2;  // two-pass verification: band words per lane (1 or 2)
+    uint32_t verify_wpl = 2;  // two-pass verification: band words per lane (1, 2, 4)
 };
 }  // namespace ej
 

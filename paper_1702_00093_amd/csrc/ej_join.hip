@@ -1008,7 +1008,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
         const Knob knobs[] = {
             {&Tuning::verify_mode, {0, 1, 2, 3}, 15},
             {&Tuning::verify_split, {0, 1, 2, 4, 8}, 4},
-            {&Tuning::verify_wpl, {1, 2}, 1},
+            {&Tuning::verify_wpl, {1, 2, 4}, 1},
             {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 1},
             {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 1},
             {&Tuning::verify_blocks_per_cu, {2, 4, 8, 16, 32}, 12},

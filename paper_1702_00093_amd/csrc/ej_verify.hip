@@ -177,56 +177,65 @@ __device__ inline void myers_block(const uint8_t *peq, uint32_t stride4, uint32_
     }
 }
 
-// myers_block with two band words per lane (words 2l and 2l+1 of the pair's
-// band in lane l): the lane's 64-bit sum carries between its words inside
-// the lane, and the lookahead between lanes (ballots, scalar add) and the
-// shift's word from the next lane are paid once per 64 bits.  The tracked
-// diagonal is bit kbit of word 0 (mask km0) or of word 1 (km1) of the owner
-// lane.
-template <int MODE, bool FAST>
-__device__ inline void myers_block2(const uint8_t *peq, uint32_t stride4, uint32_t slot4,
-                                    const uint32_t tw[8], uint32_t (&Pv)[2], uint32_t (&Mv)[2],
-                                    uint32_t &Z, uint32_t &acc, uint32_t km0, uint32_t km1,
-                                    uint32_t kbit, uint64_t notlast, uint32_t keep) {
+// myers_block with WPL band words per lane (2 or 4; words WPL*l ..
+// WPL*l + WPL - 1 of the pair's band in lane l): the lane's sum carries
+// between its words inside the lane, and the lookahead between lanes
+// (ballots, scalar add) and the shift's word from the next lane are paid once
+// per 32*WPL bits.  km[q] selects the tracked diagonal's bit in word q of the
+// owner lane (zero elsewhere).
+template <int MODE, bool FAST, int WPL>
+__device__ inline void myers_blockw(const uint8_t *peq, uint32_t stride4, uint32_t slot4,
+                                    const uint32_t tw[8], uint32_t (&Pv)[WPL],
+                                    uint32_t (&Mv)[WPL], uint32_t &Z, uint32_t &acc,
+                                    const uint32_t (&km)[WPL], uint64_t notlast, uint32_t keep) {
 #pragma unroll
     for (uint32_t s = 0; s < 32; s++) {
         const uint32_t c = (tw[s >> 2] >> (8 * (s & 3))) & 0xFFu;
         const uint32_t *pa = (const uint32_t *)(peq + (__umul24(c, stride4) + slot4));
-        const uint32_t w1 = pa[1];
-        const uint32_t eq0 = __builtin_amdgcn_alignbit(w1, pa[0], s);
-        const uint32_t eq1 = __builtin_amdgcn_alignbit(pa[2], w1, s);
-        const uint32_t X0 = eq0 | Mv[0], X1 = eq1 | Mv[1];
-        uint64_t c0, G;
-        uint32_t s0 = add_carry_mask(eq0 & Pv[0], Pv[0], c0);
-        uint32_t s1 = add_carry_chain(eq1 & Pv[1], Pv[1], c0, G);
+        uint32_t mw[WPL + 1], eq[WPL], X[WPL], sum[WPL];
+#pragma unroll
+        for (int q = 0; q <= WPL; q++) mw[q] = pa[q];
+#pragma unroll
+        for (int q = 0; q < WPL; q++) {
+            eq[q] = __builtin_amdgcn_alignbit(mw[q + 1], mw[q], s);
+            X[q] = eq[q] | Mv[q];
+        }
+        uint64_t cy;
+        sum[0] = add_carry_mask(eq[0] & Pv[0], Pv[0], cy);
+#pragma unroll
+        for (int q = 1; q < WPL; q++) sum[q] = add_carry_chain(eq[q] & Pv[q], Pv[q], cy, cy);
         if (MODE != LANES_ONE) {
-            uint64_t P = __builtin_amdgcn_ballot_w64((s0 & s1) == 0xFFFFFFFFu);
+            uint32_t all = sum[0];
+#pragma unroll
+            for (int q = 1; q < WPL; q++) all &= sum[q];
+            uint64_t G = cy;
+            uint64_t P = __builtin_amdgcn_ballot_w64(all == 0xFFFFFFFFu);
             if (MODE != LANES_WAVE) {
                 G &= notlast;
                 P &= notlast;
             }
             const uint64_t cin = ((G | P) + G) ^ P;
-            uint64_t c1;
-            s0 = add_carry_in_out(s0, cin, c1);
-            s1 = add_carry_in(s1, c1);
+            sum[0] = add_carry_in_out(sum[0], cin, cy);
+#pragma unroll
+            for (int q = 1; q < WPL - 1; q++) sum[q] = add_carry_in_out(sum[q], cy, cy);
+            sum[WPL - 1] = add_carry_in(sum[WPL - 1], cy);
         }
-        const uint32_t Xh0 = (s0 ^ Pv[0]) | eq0, Xh1 = (s1 ^ Pv[1]) | eq1;
-        const uint32_t Ph0 = Mv[0] | ~(Xh0 | Pv[0]), Ph1 = Mv[1] | ~(Xh1 | Pv[1]);
-        const uint32_t Mh0 = Pv[0] & Xh0, Mh1 = Pv[1] & Xh1;
-        const uint32_t nx = MODE == LANES_ONE ? 0u : from_next_lane<MODE>(X0, keep);
-        const uint32_t Xs0 = __builtin_amdgcn_alignbit(X1, X0, 1);
-        const uint32_t Xs1 = __builtin_amdgcn_alignbit(nx, X1, 1);
-        Pv[0] = Mh0 | ~(Xs0 | Ph0);
-        Pv[1] = Mh1 | ~(Xs1 | Ph1);
-        Mv[0] = Ph0 & Xs0;
-        Mv[1] = Ph1 & Xs1;
-        if (FAST) {
-            Z = popc_acc((Xs0 | Mh0) & km0, Z);
-            Z = popc_acc((Xs1 | Mh1) & km1, Z);
-        } else {
-            const uint32_t d = ((Xs0 | Mh0) & km0) | ((Xs1 | Mh1) & km1);
+        const uint32_t nx = MODE == LANES_ONE ? 0u : from_next_lane<MODE>(X[0], keep);
+        uint32_t d = 0;
+#pragma unroll
+        for (int q = 0; q < WPL; q++) {
+            const uint32_t Xh = (sum[q] ^ Pv[q]) | eq[q];
+            const uint32_t Ph = Mv[q] | ~(Xh | Pv[q]);
+            const uint32_t Mh = Pv[q] & Xh;
+            const uint32_t Xs = __builtin_amdgcn_alignbit(q + 1 < WPL ? X[q + 1] : nx, X[q], 1);
+            Pv[q] = Mh | ~(Xs | Ph);
+            Mv[q] = Ph & Xs;
+            d |= (Xs | Mh) & km[q];
+        }
+        if (FAST)
+            Z = popc_acc(d, Z);
+        else
             acc |= (d != 0u ? 1u : 0u) << s;
-        }
     }
 }
 
@@ -341,6 +350,28 @@ __device__ inline void fill_tile(uint32_t *pq, const PairView &v, uint32_t l, ui
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// k_verify's tile: the full layout as in fill_tile, or a ring of RW slots
+// (word w at slot w % RW) whose first WPL slots are repeated after the last
+// (stride RW + WPL), so that the WPL + 1 words a lane reads are always
+// adjacent.
+template <bool RING, int WPL>
+__device__ inline void fill_tile_w(uint32_t *pq, const PairView &v, uint32_t l, uint32_t NL,
+                                   uint32_t sigma, uint32_t stride, uint32_t RW, uint32_t wpp,
+                                   uint32_t w0, uint32_t nw) {
+    for (uint32_t c = 0; c < sigma; c++)
+        for (uint32_t w = l; w < nw; w += NL) {
+            const uint32_t word = mask_word(v, c, w0 + w);
+            if (RING) {
+                const uint32_t sl = (w0 + w) % RW;
+                pq[c * stride + sl] = word;
+                if (sl < WPL) pq[c * stride + sl + RW] = word;
+            } else if (w0 + w < wpp) {
+                pq[c * stride + w0 + w] = word;
+            }
+        }
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 // Match masks of a pair live in LDS in one of two layouts:
 //   full (RING = false): word w of symbol c at c*stride + w, stride = wpp,
 //        the whole pattern;
@@ -355,9 +386,11 @@ __device__ inline void fill_tile(uint32_t *pq, const PairView &v, uint32_t l, ui
 // column 0 and stops at column jlim; the owner lane writes aux[pidx] = Z for
 // a pair still undecided there (its Pv/Mv go to `state`) and DECIDED for the
 // others.  Pass 2 (resume == 1) takes the pairs listed in `list`, restores
-// their state and runs them to the end.  WPL band words per lane (1 or 2):
-// lane l of a pair holds words WPL*l .. WPL*l + WPL - 1, NL_arg is the lanes
-// per pair.
+// their state and runs them to the end.  WPL band words per lane (1, 2 or
+// 4): lane l of a pair holds words WPL*l .. WPL*l + WPL - 1, NL_arg is the
+// lanes per pair.  The ring here (fill_tile_w) has RW = wpp = NW + 1 slots:
+// a block reads words jb/32 .. jb/32 + NW, and the word entering after it
+// takes the slot of word jb/32, which no lane reads again.
 template <int MODE, bool RING, int WPL>
 __global__ void __launch_bounds__(64)
     k_verify(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count_arg,
@@ -370,7 +403,7 @@ __global__ void __launch_bounds__(64)
     unsigned long long colsum = 0;  // text columns of the pairs decided here
     const uint32_t NL = lanes_of<MODE>(NL_arg);
     const uint32_t NW = NL * WPL;  // band words of a pair
-    constexpr uint32_t LWB = WPL == 2 ? 6 : 5;  // log2 of the bits a lane holds
+    constexpr uint32_t LWB = WPL == 4 ? 7 : WPL == 2 ? 6 : 5;  // log2 of a lane's bits
     // pass 2, and a join sized on the device, take the pair count from the
     // device (a grid sized for all pairs; never more than count_arg)
     const uint64_t count = count_dev ? min(*count_dev, count_arg) : count_arg;
@@ -378,7 +411,7 @@ __global__ void __launch_bounds__(64)
     const uint32_t tile = lane / NL, l = lane - tile * NL;
     const bool in_tile = tile < tpw;
     const uint32_t RW = wpp;                          // ring: words per ring
-    const uint32_t stride = RING ? 2 * RW : wpp;      // words per symbol
+    const uint32_t stride = RING ? RW + WPL : wpp;    // words per symbol
     const uint32_t tile_words = tile_words_for(sigma, stride);
     uint64_t last = 0;  // top lane of every pair, and lanes outside pairs
     for (uint32_t q = 0; q < 64; q++)
@@ -397,16 +430,16 @@ __global__ void __launch_bounds__(64)
         // ---- match masks of the words the first block needs (ring) or of
         //      the whole pattern (full), every tile its own
         if (in_tile)
-            fill_tile<RING>(pq_mine, v, l, NL, sigma, stride, RW, wpp, RING ? (jbeg >> 5) : 0u,
-                            RING ? NW + 1 : wpp);
+            fill_tile_w<RING, WPL>(pq_mine, v, l, NL, sigma, stride, RW, wpp,
+                                   RING ? (jbeg >> 5) : 0u, RING ? NW + 1 : wpp);
         __syncthreads();
 
         // ---- state at column jbeg
         const uint32_t kstar = v.O + v.dstar;
         const bool owner = in_tile && (kstar >> LWB) == l;
         const uint32_t kbit = kstar & 31;
-        // the tracked diagonal's word inside the owner lane (two words)
-        const uint32_t kw = WPL == 2 ? (kstar >> 5) & 1u : 0u;
+        // the tracked diagonal's word inside the owner lane
+        const uint32_t kw = (kstar >> 5) & (WPL - 1);
         uint32_t Pv[WPL], Mv[WPL], Z = 0;
         if (resume) {
 #pragma unroll
@@ -434,31 +467,43 @@ __global__ void __launch_bounds__(64)
         for (int d = 32; d >= 1; d >>= 1) nmax = max(nmax, (uint32_t)__shfl_xor((int)nmax, d, 64));
         const uint32_t jend = min(nmax, jlim);
         uint32_t jdone = jbeg;
+        // the owner's own stopping column: the wave runs on until its last
+        // pair is decided, but only the columns a pair needed are counted
+        uint32_t jstop = NO_LIMIT;
         uint32_t tw[8], tn[8];
         load_text_block(v.yp, v.nn, jbeg, tw);
+        uint32_t sb = RING ? (jbeg >> 5) % RW : 0u;  // ring: the slot of word jb/32
         for (uint32_t jb = jbeg; jb < jend; jb += 32) {
             load_text_block(v.yp, v.nn, jb + 32, tn);
             const uint32_t wn = (jb >> 5) + NW + 1;  // ring: the word entering next
             const uint32_t w0 = (jb >> 5) + WPL * l;   // the lane's first band word
-            const uint32_t slot4 = 4 * (RING ? (w0 & (RW - 1)) : w0);
+            uint32_t slot = sb + WPL * l;               // WPL * l < RW
+            if (slot >= RW) slot -= RW;
+            const uint32_t slot4 = 4 * (RING ? slot : w0);
             // columns past the end of a pair's text do not count; a block
             // where no text ends takes the masked-popcount path
             const bool ends_here = in_tile && v.nn > jb && v.nn < jb + 32;
             if (__builtin_amdgcn_ballot_w64(ends_here) == 0) {
                 const uint32_t km = (owner && jb + 32 <= v.nn) ? (1u << kbit) : 0u;
                 uint32_t unused = 0;
-                if constexpr (WPL == 2)
-                    myers_block2<MODE, true>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, unused,
-                                             kw ? 0u : km, kw ? km : 0u, kbit, notlast, keep);
-                else
+                if constexpr (WPL > 1) {
+                    uint32_t kq[WPL];
+#pragma unroll
+                    for (int q = 0; q < WPL; q++) kq[q] = kw == (uint32_t)q ? km : 0u;
+                    myers_blockw<MODE, true, WPL>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, unused,
+                                                  kq, notlast, keep);
+                } else
                     myers_block<MODE, true>(peq8, 4 * stride, slot4, tw, Pv[0], Mv[0], Z, unused,
                                             km, kbit, notlast, keep);
             } else {
                 uint32_t acc = 0;
-                if constexpr (WPL == 2) {
+                if constexpr (WPL > 1) {
                     const uint32_t km = owner ? (1u << kbit) : 0u;
-                    myers_block2<MODE, false>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, acc,
-                                              kw ? 0u : km, kw ? km : 0u, kbit, notlast, keep);
+                    uint32_t kq[WPL];
+#pragma unroll
+                    for (int q = 0; q < WPL; q++) kq[q] = kw == (uint32_t)q ? km : 0u;
+                    myers_blockw<MODE, false, WPL>(peq8, 4 * stride, slot4, tw, Pv, Mv, Z, acc,
+                                                   kq, notlast, keep);
                 } else {
                     myers_block<MODE, false>(peq8, 4 * stride, slot4, tw, Pv[0], Mv[0], Z, acc, 0u,
                                              kbit, notlast, keep);
@@ -469,20 +514,22 @@ __global__ void __launch_bounds__(64)
             }
             if (RING && in_tile) {
                 // the entering word, lane c of the tile for symbol c; the slot
-                // it replaces held word wn - RW, which no lane reads any more
-                const uint32_t sl = wn & (RW - 1);
+                // it takes held word wn - RW = jb/32, which no lane reads any
+                // more
                 for (uint32_t c = l; c < sigma; c += NL) {
                     const uint32_t word = mask_word(v, c, wn);
-                    pq_mine[c * stride + sl] = word;
-                    pq_mine[c * stride + sl + RW] = word;
+                    pq_mine[c * stride + sb] = word;
+                    if (sb < WPL) pq_mine[c * stride + sb + RW] = word;
                 }
                 __atomic_signal_fence(__ATOMIC_SEQ_CST);
             }
+            if (RING) sb = sb + 1 == RW ? 0u : sb + 1;
             jdone = jb + 32;
 #pragma unroll
             for (int q = 0; q < 8; q++) tw[q] = tn[q];
             const uint32_t cols = min(jdone, v.nn);
             const bool live = owner && !v.skip && v.dstar + cols - Z <= v.Kp && jdone < v.nn;
+            if (owner && !live && jstop == NO_LIMIT) jstop = jdone;
             if (__builtin_amdgcn_ballot_w64(live) == 0) break;
         }
         const uint32_t cols = min(jdone, v.nn);
@@ -511,7 +558,8 @@ __global__ void __launch_bounds__(64)
                 dist[pidx] = (int32_t)res;
                 if (aux && !resume) aux[pidx] = DECIDED;
             }
-            colsum += (unsigned long long)(cols - min(jbeg, cols));
+            const uint32_t need = min(min(jdone, jstop), v.nn);
+            colsum += (unsigned long long)(need - min(jbeg, need));
         }
     }
     add_columns(columns, colsum);
@@ -1870,13 +1918,6 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     tpw = std::min(tpw, budget / tile_bytes);
     const size_t lds = (size_t)tpw * tile_bytes;
     const int mode = NL == 1 ? LANES_ONE : NL == 16 ? LANES_ROW : NL == 64 ? LANES_WAVE : LANES_ANY;
-    auto kern = mode == LANES_ONE    ? k_verify<LANES_ONE, false, 1>
-                : mode == LANES_ROW  ? (ring ? k_verify<LANES_ROW, true, 1> : k_verify<LANES_ROW, false, 1>)
-                : mode == LANES_WAVE ? (ring ? k_verify<LANES_WAVE, true, 1> : k_verify<LANES_WAVE, false, 1>)
-                : (ring ? k_verify<LANES_ANY, true, 1> : k_verify<LANES_ANY, false, 1>);
-    if (lds > 65536)
-        EJ_HIP(hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds));
     Timers &tk = ctx->timers;
     auto kmark = [&]() {
         if (tk.on && tk.nkv < 4) EJ_HIP(hipEventRecord(tk.kv[tk.nkv++], ctx->stream));
@@ -2112,43 +2153,59 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     ctx->last_verify_form = 0;
     const uint32_t C1 = ctx->tune.verify_pass1_cols & ~31u;
     const bool two_pass = C1 > 0 && C1 < mtext;
-    // two band words per lane (knob verify_wpl = 2, bands of 4 words or
-    // more): half the lanes per pair, so the lookahead between lanes, the
-    // shift's word from the next lane and the tracked diagonal are paid once
-    // per 64 bits; its own ring, tile and lanes
-    uint32_t vNL = NL, vtpw = tpw, vwpp = wpp;
-    size_t vlds = lds;
-    auto vkern = kern;
-    const bool w2 = ctx->tune.verify_wpl == 2 && NL >= 4;
-    if (w2) {
-        const uint32_t NL2 = (NL + 1) / 2, NW = 2 * NL2;
-        uint32_t wppf = (mtext + 32 * NW + 64) / 32 + 2;
-        wppf = (wppf + 1) & ~1u;
-        uint32_t RW2 = 1;
-        while (RW2 < NW + 2) RW2 <<= 1;
-        const bool ring2 = ring_mode != 0 && (ring_mode == 2 || 2 * RW2 < wppf);
-        const uint32_t tb = tile_words_for(sig, ring2 ? 2 * RW2 : wppf) * 4;
-        uint32_t b2 = ctx->tune.verify_lds_budget;
-        if ((int)b2 > ctx->lds_max) b2 = (uint32_t)ctx->lds_max;
-        if (tb > b2) b2 = (uint32_t)ctx->lds_max;
-        if (tb > b2)
-            fail(EJ_EUNSUPPORTED, "strings too long for the LDS-resident match masks (" +
-                                      std::to_string(tb) + " bytes per pair)");
-        vNL = NL2;
-        vtpw = std::min(64u / NL2, b2 / tb);
-        vwpp = ring2 ? RW2 : wppf;
-        vlds = (size_t)vtpw * tb;
-        vkern = NL2 == 16 ? (ring2 ? k_verify<LANES_ROW, true, 2> : k_verify<LANES_ROW, false, 2>)
-                          : (ring2 ? k_verify<LANES_ANY, true, 2> : k_verify<LANES_ANY, false, 2>);
-        if (vlds > 65536)
-            EJ_HIP(hipFuncSetAttribute((const void *)vkern,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
-        ctx->last_verify_form = 5;
-    }
+    // WPL band words per lane (knob verify_wpl: 1, 2 or 4, lowered until the
+    // band has at least 2 WPL words): fewer lanes per pair, so the lookahead
+    // between lanes, the shift's word from the next lane and the symbol's
+    // address are paid once per 32 WPL bits.  The ring holds exactly the
+    // NW + 1 words a block reads (RW = NW + 1), its first WPL slots repeated
+    // after the last.
+    uint32_t Wv = ctx->tune.verify_wpl >= 4 ? 4u : ctx->tune.verify_wpl >= 2 ? 2u : 1u;
+    while (Wv > 1 && NL < 2 * Wv) Wv /= 2;
+    const uint32_t vNL = (NL + Wv - 1) / Wv, NWv = vNL * Wv;
+    uint32_t wppf = (mtext + 32 * NWv + 64) / 32 + 2;
+    wppf = (wppf + 1) & ~1u;
+    const uint32_t RWv = NWv + 1;
+    const bool vring = ring_mode != 0 && vNL >= 2 && (ring_mode == 2 || RWv + Wv < wppf);
+    const uint32_t vwpp = vring ? RWv : wppf;
+    const uint32_t tb = tile_words_for(sig, vring ? RWv + Wv : wppf) * 4;
+    uint32_t vbudget = ctx->tune.verify_lds_budget;
+    if ((int)vbudget > ctx->lds_max) vbudget = (uint32_t)ctx->lds_max;
+    if (tb > vbudget) vbudget = (uint32_t)ctx->lds_max;
+    if (tb > vbudget)
+        fail(EJ_EUNSUPPORTED, "strings too long for the LDS-resident match masks (" +
+                                  std::to_string(tb) + " bytes per pair)");
+    const uint32_t vtpw = std::min(64u / vNL, vbudget / tb);
+    const size_t vlds = (size_t)vtpw * tb;
+    const int vmode =
+        vNL == 1 ? LANES_ONE : vNL == 16 ? LANES_ROW : vNL == 64 ? LANES_WAVE : LANES_ANY;
+    using VKern = decltype(&k_verify<LANES_ANY, true, 1>);
+    VKern vkern;
+    if (Wv == 1)
+        vkern = vmode == LANES_ONE    ? k_verify<LANES_ONE, false, 1>
+                : vmode == LANES_ROW  ? (vring ? k_verify<LANES_ROW, true, 1>
+                                               : k_verify<LANES_ROW, false, 1>)
+                : vmode == LANES_WAVE ? (vring ? k_verify<LANES_WAVE, true, 1>
+                                               : k_verify<LANES_WAVE, false, 1>)
+                                      : (vring ? k_verify<LANES_ANY, true, 1>
+                                               : k_verify<LANES_ANY, false, 1>);
+    else if (Wv == 2)
+        vkern = vmode == LANES_ROW ? (vring ? k_verify<LANES_ROW, true, 2>
+                                            : k_verify<LANES_ROW, false, 2>)
+                                   : (vring ? k_verify<LANES_ANY, true, 2>
+                                            : k_verify<LANES_ANY, false, 2>);
+    else
+        vkern = vmode == LANES_ROW ? (vring ? k_verify<LANES_ROW, true, 4>
+                                            : k_verify<LANES_ROW, false, 4>)
+                                   : (vring ? k_verify<LANES_ANY, true, 4>
+                                            : k_verify<LANES_ANY, false, 4>);
+    if (vlds > 65536)
+        EJ_HIP(hipFuncSetAttribute((const void *)vkern,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)vlds));
+    if (Wv > 1) ctx->last_verify_form = 5;
     uint32_t *state = nullptr, *aux = nullptr;
     if (two_pass) {
         // Pv and Mv of every band word of every pair
-        state = ws<uint32_t>(ctx, "verify_state", count * vNL * (w2 ? 4 : 2));
+        state = ws<uint32_t>(ctx, "verify_state", count * vNL * 2 * Wv);
         aux = ws<uint32_t>(ctx, "verify_aux", count);
     }
     const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;

@@ -35,15 +35,16 @@ def ctx(ej):
 
 
 def _each_verify_mode(ctx):
-    """Runs the body once per verification form (two-pass with one and with
-    two band words per lane, persistent tiles, one pair per lane, grouped by
-    pattern); the mode yielded for the two-word two-pass form is "0w2"."""
+    """Runs the body once per verification form (two-pass with one, two and
+    four band words per lane, persistent tiles, one pair per lane, grouped by
+    pattern); the mode yielded for the two-pass form with W words per lane
+    (W > 1) is "0wW"."""
     old = (ctx.tune_get("verify_mode"), ctx.tune_get("verify_wpl"))
     try:
-        for mode, wpl in ((0, 1), (0, 2), (1, 1), (2, 1), (3, 1)):
+        for mode, wpl in ((0, 1), (0, 2), (0, 4), (1, 1), (2, 1), (3, 1)):
             ctx.tune_set("verify_mode", mode)
             ctx.tune_set("verify_wpl", wpl)
-            yield mode if wpl == 1 else "0w2"
+            yield mode if wpl == 1 else f"0w{wpl}"
     finally:
         ctx.tune_set("verify_mode", old[0])
         ctx.tune_set("verify_wpl", old[1])
@@ -257,7 +258,8 @@ def test_verify_mask_layouts_agree(ej, ctx, oracle_lib, K):
     try:
         for ring in (0, 2):
             for mode, c1, wpl in ((0, 0, 1), (0, 64, 1), (0, 1024, 1), (1, 0, 1), (0, 0, 2),
-                                  (0, 64, 2), (0, 1024, 2)):
+                                  (0, 64, 2), (0, 1024, 2), (0, 0, 4), (0, 64, 4),
+                                  (0, 1024, 4)):
                 ctx.tune_set("verify_ring", ring)
                 ctx.tune_set("verify_pass1_cols", c1)
                 ctx.tune_set("verify_mode", mode)
@@ -436,7 +438,7 @@ def test_verify_two_pass_resume(ej, ctx, oracle_lib, c1):
         ctx.tune_set("verify_pass1_cols", c1)
         for K in (3, 60, 130, 200):
             want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K)
-            for wpl in (1, 2):
+            for wpl in (1, 2, 4):
                 ctx.tune_set("verify_wpl", wpl)
                 _say(f"two-pass c1={c1} K={K} wpl={wpl}")
                 got = ctx.verify(chars, offs, torch.from_numpy(codes.astype(np.int64)).cuda(), K)
@@ -454,7 +456,8 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
     knobs = [("radix_bits", 4), ("radix_bits", 11), ("bucket_key_bits", 5),
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
              ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
-             ("verify_ring", 2), ("verify_mode", 1), ("verify_wpl", 1)]
+             ("verify_ring", 2), ("verify_mode", 1), ("verify_wpl", 1),
+             ("verify_wpl", 4)]
     # the persistent forms with and without the multiplicity order
     try:
         for mode, split in ((1, 0), (2, 0), (2, 1), (2, 4)):
@@ -840,7 +843,10 @@ def test_verified_columns_counter(ej, ctx, oracle_lib):
     """EJ_FLAG_TIMING's count of verified text columns (summed per wave, one
     atomic each): the same over repeated joins, positive, at most the total
     text length of the candidates rounded up to 32-column blocks, and at
-    least the text length of every output pair (those run to their end)."""
+    least the text length of every output pair (those run to their end).
+    Each pair counts up to the 32-column block where it is decided, not where
+    its wave stops: the two-pass form at every width counts exactly what the
+    persistent form, which retires each pair at its decision, counts."""
     col = sd.clusters(51, 30, lambda rr, b: 4, lambda rr: rr.integers(100, 700),
                       lambda rr, LL: rr.poisson(8))
     K, r, z, m, L = 40, 4, 6, 4, 48
@@ -852,6 +858,7 @@ def test_verified_columns_counter(ej, ctx, oracle_lib):
     oa = (ref.out >> np.uint64(32)).astype(np.int64)
     ob = (ref.out & np.uint64(0xFFFFFFFF)).astype(np.int64)
     chars, offs = to_device(col)
+    counts = {}
     for mode in _each_verify_mode(ctx):
         a = ctx.join(chars, offs, K, r, z, m, seed=5, L=L, flags=ej.FLAG_TIMING)
         b = ctx.join(chars, offs, K, r, z, m, seed=5, L=L, flags=ej.FLAG_TIMING)
@@ -860,3 +867,17 @@ def test_verified_columns_counter(ej, ctx, oracle_lib):
         assert a.verify_columns == b.verify_columns > 0
         assert a.verify_columns <= int((((text + 31) // 32) * 32).sum())
         assert a.verify_columns >= int(np.minimum(lens[oa], lens[ob]).sum())
+        counts[mode] = a.verify_columns
+    assert counts[0] == counts["0w2"] == counts["0w4"] == counts[1]
+    # a first pass of 64 columns: pairs resumed in pass 2 count once
+    old = (ctx.tune_get("verify_mode"), ctx.tune_get("verify_pass1_cols"))
+    try:
+        ctx.tune_set("verify_mode", 0)
+        ctx.tune_set("verify_pass1_cols", 64)
+        a = ctx.join(chars, offs, K, r, z, m, seed=5, L=L, flags=ej.FLAG_TIMING)
+        _assert_join_equal(a, ref)
+        _say(f"verified columns two passes of 64 + rest: {a.verify_columns}")
+        assert a.verify_columns == counts[1]
+    finally:
+        ctx.tune_set("verify_mode", old[0])
+        ctx.tune_set("verify_pass1_cols", old[1])
