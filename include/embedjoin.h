@@ -161,6 +161,10 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_wpl"            two-pass verification: band words per lane, 1,
  *                           2 or 4 (default 2; 3 acts as 2; lowered until
  *                           the band has at least twice as many words)
+ *   "verify_len_order"      two-pass verification: 1 (default) runs the
+ *                           first pass in order of text length, longest
+ *                           first, when some text is shorter than that pass
+ *                           runs; 0 in pair order
  *   "verify_blocks_per_cu"  workgroups per CU of the verification grid (the
  *                           lane form: at most, below the occupancy limit)
  *   "verify_mode"           0: two passes over fixed groups of pairs, one

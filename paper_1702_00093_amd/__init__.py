@@ -385,7 +385,7 @@ class Context:
     KNOBS = ("verify_mode", "verify_order", "verify_split", "verify_pass1_cols",
              "verify_blocks_per_cu", "verify_ring",
              "verify_lds_budget", "embed_lds_budget", "radix_bits", "bucket_key_bits",
-             "dedup_sort", "raw_limit", "verify_wpl")
+             "dedup_sort", "raw_limit", "verify_wpl", "verify_len_order")
 
     def knobs(self) -> dict:
         return {k: self.tune_get(k) for k in self.KNOBS}

@@ -235,6 +235,7 @@ static uint32_t *tune_slot(ej::Tuning &t, const char *name, uint32_t *lo, uint32
         {"dedup_sort", &Tuning::dedup_sort, 0, 1},
         {"raw_limit", &Tuning::raw_limit, 0, 0xFFFFFFFEu},
         {"verify_wpl", &Tuning::verify_wpl, 1, 4},
+        {"verify_len_order", &Tuning::verify_len_order, 0, 1},
     };
     if (!name) return nullptr;
     for (const Item &it : items)

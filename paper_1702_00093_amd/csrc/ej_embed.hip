@@ -29,6 +29,7 @@ namespace {
 struct PrepInfo {
     uint32_t mask[8];   // presence bitmap of bytes
     uint32_t maxlen;
+    uint32_t minlen;
     uint32_t err;       // 1: offsets decrease, 2: string longer than 2^31-1
     uint64_t off0, offn;
 };
@@ -42,11 +43,12 @@ __global__ void k_prep_info(const uint64_t *__restrict__ offsets, uint32_t n,
     if (threadIdx.x < 8) info->mask[threadIdx.x] = 0;
     if (threadIdx.x == 8) info->maxlen = 0;
     if (threadIdx.x == 9) info->err = 0;
+    if (threadIdx.x == 10) info->minlen = 0xFFFFFFFFu;
 }
 
 __global__ void k_lengths(const uint64_t *__restrict__ offsets, uint32_t n,
                           uint32_t *__restrict__ len, PrepInfo *__restrict__ info) {
-    uint32_t mx = 0, err = 0;
+    uint32_t mx = 0, mn = 0xFFFFFFFFu, err = 0;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         uint64_t a = offsets[i], b = offsets[i + 1];
         uint64_t l = 0;
@@ -60,14 +62,17 @@ __global__ void k_lengths(const uint64_t *__restrict__ offsets, uint32_t n,
         }
         len[i] = (uint32_t)l;
         mx = l > mx ? (uint32_t)l : mx;
+        mn = l < mn ? (uint32_t)l : mn;
     }
     // wave reduction then one atomic per wave
     for (int d = 32; d >= 1; d >>= 1) {
         mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, 64));
+        mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, 64));
         err |= (uint32_t)__shfl_xor((int)err, d, 64);
     }
     if ((threadIdx.x & 63) == 0) {
         if (mx) atomicMax(&info->maxlen, mx);
+        if (mn != 0xFFFFFFFFu) atomicMin(&info->minlen, mn);
         if (err) atomicOr(&info->err, err);
     }
 }
@@ -554,6 +559,7 @@ void prepare(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets, uin
     pp.base = info.off0;
     pp.total = info.offn - info.off0;
     pp.maxlen = info.maxlen;
+    pp.minlen = pp.n ? info.minlen : 0u;
     if (pp.total && !d_chars) fail(EJ_EINVAL, "null character buffer");
     uint32_t mask[8] = {0};
     memcpy(mask, info.mask, sizeof(mask));

@@ -113,6 +113,7 @@ struct Tuning {
     uint32_t dedup_sort = 0;                 // candidates: 0 grouped (sort on overflow), 1 sort
     uint32_t raw_limit = 0;  // raw pairs per sort of the candidate stage (0: 2^32 - 2)
     uint32_t verify_wpl = 2;  // two-pass verification: band words per lane (1, 2, 4)
+    uint32_t verify_len_order = 1;  // two-pass: first pass in text-length order (0 off)
 };
 }  // namespace ej
 
@@ -224,6 +225,7 @@ struct Prep {
     uint64_t base = 0;      // offsets[0]
     uint64_t total = 0;     // total bytes
     uint32_t maxlen = 0;
+    uint32_t minlen = 0;    // shortest string (0 for an empty set)
     uint32_t sigma = 0;
     uint8_t lut[256];
     uint32_t L = 0;
@@ -359,7 +361,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             const uint8_t *d_codes_b = nullptr, const uint64_t *d_offsets_b = nullptr,
             uint64_t base_b = 0, uint32_t maxlen_b = 0, const RowMasks *masks_b = nullptr,
             unsigned long long *d_columns = nullptr, const uint32_t *d_order = nullptr,
-            const uint64_t *d_count = nullptr);
+            const uint64_t *d_count = nullptr, uint32_t minlen = 0);
 
 uint32_t verify_lanes_for(uint32_t K);  // lanes per pair, 0 if unsupported
 

@@ -273,7 +273,7 @@ void finish_join(ej_ctx *ctx, const Prep &pp, const uint64_t *d_offsets, const e
         if (cnt)
             build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
         verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, pairs, cnt, p.K,
-               nullptr, dist, nullptr, nullptr, 0, 0, nullptr, d_cols, order);
+               nullptr, dist, nullptr, nullptr, 0, 0, nullptr, d_cols, order, nullptr, pp.minlen);
     }
     tm.mark();  // 5
     uint64_t nout = 0;
@@ -448,13 +448,13 @@ std::string join_shape(ej_ctx *ctx, const Prep &pp, const uint8_t *d_chars,
     char key[512];
     snprintf(key, sizeof(key),
              "join %p %p %u %llu %llu %u %u %u %u %u %u %u %llu | %u %u %u %u %u %u %u %u %u %u "
-             "%u %u %u",
+             "%u %u %u %u",
              (const void *)d_chars, (const void *)d_offsets, pp.n, (unsigned long long)pp.base,
              (unsigned long long)pp.total, pp.sigma, pp.maxlen, pp.L, p.K, p.r, p.z, p.m,
              (unsigned long long)p.seed, t.verify_mode, t.verify_order, t.verify_split,
              t.verify_pass1_cols, t.verify_blocks_per_cu, t.verify_ring, t.verify_lds_budget,
              t.embed_lds_budget, t.radix_bits, t.bucket_key_bits, t.dedup_sort, t.raw_limit,
-             t.verify_wpl);
+             t.verify_wpl, t.verify_len_order);
     return key;
 }
 
@@ -492,7 +492,8 @@ bool join_graph(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_o
         RowMasks masks;
         build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "j");
         verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, pairs, cnt_cap,
-               p.K, nullptr, dist, nullptr, nullptr, 0, 0, nullptr, nullptr, order, cnt_dev + 1);
+               p.K, nullptr, dist, nullptr, nullptr, 0, 0, nullptr, nullptr, order, cnt_dev + 1,
+               pp.minlen);
         uint32_t *flags = ws<uint32_t>(ctx, "j_oflags", cnt_cap);
         uint32_t *pos = ws<uint32_t>(ctx, "j_opos", cnt_cap);
         hipLaunchKernelGGL(k_out_flags, dim3(grid_for(ctx, cnt_cap, 256)), dim3(256), 0,
@@ -876,7 +877,7 @@ void verify_entry(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets
     if (count)
         build_masks(ctx, pp.d_codes, d_offsets, pp.base, n, pp.total, pp.sigma, masks, "v");
     verify(ctx, pp.d_codes, d_offsets, pp.base, pp.sigma, pp.maxlen, masks, d_pairs, count, K,
-           d_Kq, d_dist);
+           d_Kq, d_dist, nullptr, nullptr, 0, 0, nullptr, nullptr, nullptr, nullptr, pp.minlen);
     sync(ctx);
 }
 
@@ -1009,6 +1010,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             {&Tuning::verify_mode, {0, 1, 2, 3}, 15},
             {&Tuning::verify_split, {0, 1, 2, 4, 8}, 4},
             {&Tuning::verify_wpl, {1, 2, 4}, 1},
+            {&Tuning::verify_len_order, {1, 0}, 1},
             {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 1},
             {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 1},
             {&Tuning::verify_blocks_per_cu, {2, 4, 8, 16, 32}, 12},

@@ -1817,6 +1817,29 @@ __global__ void k_alive_keys(StrSet A, StrSet B, const uint64_t *__restrict__ pa
     }
 }
 
+// Sort keys of the first pass: longest text first in 32-column blocks,
+// clamped at cap_blocks (the columns the pass runs: texts at least that long
+// all tie and keep their order); entries past a count on the device sort
+// last.  val = the pair's index.
+__global__ void k_len_keys(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count,
+                           const uint64_t *__restrict__ count_dev, uint32_t cap_blocks,
+                           uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
+    const uint64_t live = count_dev ? min(*count_dev, count) : count;
+    for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
+         k += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t kk = 0x7FFu;
+        if (k < live) {
+            const uint64_t code = pairs[k];
+            const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
+            const uint64_t la = A.off[a + 1] - A.off[a], lb = B.off[b + 1] - B.off[b];
+            const uint64_t blocks = ((la < lb ? la : lb) + 31) >> 5;
+            kk = 0x7FEu - (uint32_t)(blocks < cap_blocks ? blocks : cap_blocks);
+        }
+        key[k] = kk;
+        val[k] = (uint32_t)k;
+    }
+}
+
 inline uint32_t grid_for(ej_ctx *ctx, uint64_t work, uint32_t block) {
     uint64_t g = (work + block - 1) / block;
     uint64_t cap = (uint64_t)ctx->num_cu * 16;
@@ -1868,7 +1891,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
             uint64_t count, uint32_t K, const uint32_t *d_Kq, int32_t *d_dist,
             const uint8_t *d_codes_b, const uint64_t *d_offsets_b, uint64_t base_b,
             uint32_t maxlen_b, const RowMasks *masks_b, unsigned long long *d_columns,
-            const uint32_t *d_order, const uint64_t *d_count) {
+            const uint32_t *d_order, const uint64_t *d_count, uint32_t minlen) {
     if (count == 0) return;
     if (count >= 0xFFFFFFFFull) fail(EJ_EUNSUPPORTED, "more than 2^32 pairs in one verification");
     uint32_t Kmax = K;
@@ -2209,12 +2232,29 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         aux = ws<uint32_t>(ctx, "verify_aux", count);
     }
     const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;
+    uint32_t *lkey = ws<uint32_t>(ctx, "verify_lkey", count);
+    uint32_t *lkey2 = ws<uint32_t>(ctx, "verify_lkey2", count);
+    uint32_t *lval = ws<uint32_t>(ctx, "verify_lval", count);
+    uint32_t *list = ws<uint32_t>(ctx, "verify_list", count);
+    // the first pass in order of text length, longest first and clamped at
+    // the columns it runs, so that a wave's pairs end about together (a wave
+    // runs until its last pair is decided); skipped when every text outlasts
+    // it (minlen: a lower bound on the texts, 0 if unknown)
+    const uint32_t run1 = two_pass ? C1 : 32u * 0x7FEu;
+    const uint32_t *list1 = nullptr;
+    if (ctx->tune.verify_len_order && minlen < std::min(run1, mtext)) {
+        hipLaunchKernelGGL(k_len_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
+                           ctx->stream, A, B, d_pairs, count, d_count, run1 >> 5, lkey, lval);
+        EJ_CHECK_LAUNCH();
+        radix_sort_u32(ctx, lkey, lval, lkey2, list, 1, (uint32_t)count, 11, 11);
+        list1 = list;
+    }
     {
         kmark();
         uint64_t ngroups = (count + vtpw - 1) / vtpw;
         uint64_t grid = std::min<uint64_t>(ngroups, cap);
         hipLaunchKernelGGL(vkern, dim3((uint32_t)grid), dim3(64), vlds, ctx->stream, A, B, d_pairs,
-                           count, d_count, (const uint32_t *)nullptr, K, d_Kq,
+                           count, d_count, list1, K, d_Kq,
                            sig, vNL, vtpw, vwpp, 0u,
                            two_pass ? C1 : NO_LIMIT, 0, state, aux, d_dist, d_columns);
         EJ_CHECK_LAUNCH();
@@ -2235,11 +2275,8 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
                        (const uint32_t *)flags, (const uint32_t *)pos, count, list0);
     EJ_CHECK_LAUNCH();
     // longest texts first, so that each wave's pairs run about as long as
-    // one another and the longest start early
-    uint32_t *lkey = ws<uint32_t>(ctx, "verify_lkey", count);
-    uint32_t *lkey2 = ws<uint32_t>(ctx, "verify_lkey2", count);
-    uint32_t *lval = ws<uint32_t>(ctx, "verify_lval", count);
-    uint32_t *list = ws<uint32_t>(ctx, "verify_list", count);
+    // one another and the longest start early (the first pass's list is no
+    // longer read: pass 1 has finished on this stream)
     hipLaunchKernelGGL(k_alive_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0, ctx->stream,
                        A, B, d_pairs, (const uint32_t *)list0, (const uint64_t *)d_nalive, count,
                        lkey, lval);
