@@ -188,9 +188,12 @@ uint64_t ej_workspace_bytes(const ej_ctx *ctx);
  *   "verify_split"          lane form: lanes per pair, 1, 2, 4, 8 or 16
  *                           (0 = by band width: 1 up to 4 words, 2 up to 8,
  *                           then 4)
- *   "verify_order"          persistent forms, joins only: 0 pairs in list
- *                           order, 1 most frequent pairs (found by the most
- *                           tables) first, which shortens the tail
+ *   "verify_order"          joins only, two-pass and persistent forms: 0
+ *                           pairs in list order, 1 most frequent pairs
+ *                           (found by the most tables) first, which groups
+ *                           the pairs that run to their end (the two-pass
+ *                           form's first pass, within a text length) and
+ *                           shortens the tail
  *   "verify_ring"           match-mask layout in LDS: 0 the whole pattern,
  *                           1 a ring of the words the band covers when it is
  *                           smaller, 2 the ring whenever the band has at

@@ -103,7 +103,7 @@ struct Tuning {
     uint32_t verify_lds_budget = 48 * 1024;  // LDS per wave of the verification kernel
     uint32_t verify_pass1_cols = 1024;       // columns of verification pass 1 (0: one pass)
     uint32_t verify_blocks_per_cu = 64;      // resident-wave target of the verification grid
-    uint32_t verify_order = 1;               // persistent form: 0 pair order, 1 by table multiplicity
+    uint32_t verify_order = 1;               // joins: 0 pair order, 1 by table multiplicity
     uint32_t verify_mode = 0;                // 0 two passes over pair tiles, 1 persistent pair queue
     uint32_t verify_split = 0;               // lane form: lanes per pair (0 auto, 1, 2, 4, 8, 16)
     uint32_t verify_ring = 1;                // match masks: 0 whole pattern, 1 auto, 2 ring if it fits

@@ -465,10 +465,9 @@ bool join_graph(ej_ctx *ctx, const Prep &pp, const Rand &rd, const uint64_t *d_o
     const uint32_t n = pp.n;
     const uint32_t T = p.r * p.z;
     const uint64_t raw_cap = caps.raw_cap, cnt_cap = caps.cnt_cap;
-    // the multiplicity order schedules the persistent and lane forms (the
-    // grouped form orders by pattern itself)
-    const bool want_order = (ctx->tune.verify_mode == 1 || ctx->tune.verify_mode == 2) &&
-                            ctx->tune.verify_order == 1;
+    // the multiplicity order schedules the two-pass, persistent and lane
+    // forms (the grouped form orders by pattern itself)
+    const bool want_order = ctx->tune.verify_mode <= 2 && ctx->tune.verify_order == 1;
     uint64_t *cnt_dev = ws<uint64_t>(ctx, "jg_counts", 4);
     uint64_t *cnt_out = ws<uint64_t>(ctx, "jg_counts_out", 4);
     // results: pairs [2 * cnt_cap] u32, then distances [cnt_cap] (looked up
@@ -639,10 +638,9 @@ void join_device(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_offsets,
     uint64_t *pairs = nullptr;
     uint64_t raw = 0;
     uint32_t *order = nullptr;
-    // the multiplicity order schedules the persistent and lane forms (the
-    // grouped form orders by pattern itself)
-    const bool want_order = (ctx->tune.verify_mode == 1 || ctx->tune.verify_mode == 2) &&
-                            ctx->tune.verify_order == 1;
+    // the multiplicity order schedules the two-pass, persistent and lane
+    // forms (the grouped form orders by pattern itself)
+    const bool want_order = ctx->tune.verify_mode <= 2 && ctx->tune.verify_order == 1;
     uint64_t cnt = candidates(ctx, keys, bk, pp.d_len, p.K, &pairs, &raw, "j",
                               want_order && !p.exact_len ? &order : nullptr);
     const uint64_t *cp = pairs;
@@ -1014,7 +1012,7 @@ ej_status ej_autotune(ej_ctx *ctx, const uint8_t *d_chars, const uint64_t *d_off
             {&Tuning::verify_pass1_cols, {512, 1024, 2048, 0}, 1},
             {&Tuning::verify_blocks_per_cu, {8, 16, 32, 64}, 1},
             {&Tuning::verify_blocks_per_cu, {2, 4, 8, 16, 32}, 12},
-            {&Tuning::verify_order, {1, 0}, 6},
+            {&Tuning::verify_order, {1, 0}, 7},
             {&Tuning::verify_ring, {1, 0}, 3},
             {&Tuning::radix_bits, {6, 7, 8, 11}, 15},
             {&Tuning::bucket_key_bits, {0, 32}, 15},

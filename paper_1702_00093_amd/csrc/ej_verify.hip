@@ -1819,24 +1819,26 @@ __global__ void k_alive_keys(StrSet A, StrSet B, const uint64_t *__restrict__ pa
 
 // Sort keys of the first pass: longest text first in 32-column blocks,
 // clamped at cap_blocks (the columns the pass runs: texts at least that long
-// all tie and keep their order); entries past a count on the device sort
-// last.  val = the pair's index.
+// all tie and keep their order, the k-th being pair order[k], or k);
+// entries past a count on the device sort last.  val = the pair's index.
 __global__ void k_len_keys(StrSet A, StrSet B, const uint64_t *__restrict__ pairs, uint64_t count,
-                           const uint64_t *__restrict__ count_dev, uint32_t cap_blocks,
+                           const uint64_t *__restrict__ count_dev,
+                           const uint32_t *__restrict__ order, uint32_t cap_blocks,
                            uint32_t *__restrict__ key, uint32_t *__restrict__ val) {
     const uint64_t live = count_dev ? min(*count_dev, count) : count;
     for (uint64_t k = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; k < count;
          k += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t kk = 0x7FFu;
+        const uint32_t v = order ? order[k] : (uint32_t)k;
         if (k < live) {
-            const uint64_t code = pairs[k];
+            const uint64_t code = pairs[v];
             const uint32_t a = (uint32_t)(code >> 32), b = (uint32_t)code;
             const uint64_t la = A.off[a + 1] - A.off[a], lb = B.off[b + 1] - B.off[b];
             const uint64_t blocks = ((la < lb ? la : lb) + 31) >> 5;
             kk = 0x7FEu - (uint32_t)(blocks < cap_blocks ? blocks : cap_blocks);
         }
         key[k] = kk;
-        val[k] = (uint32_t)k;
+        val[k] = v;
     }
 }
 
@@ -2239,12 +2241,15 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     // the first pass in order of text length, longest first and clamped at
     // the columns it runs, so that a wave's pairs end about together (a wave
     // runs until its last pair is decided); skipped when every text outlasts
-    // it (minlen: a lower bound on the texts, 0 if unknown)
+    // it (minlen: a lower bound on the texts, 0 if unknown).  Within a
+    // length, and when there is no length sort, in d_order (most frequent
+    // pairs first: pairs likely within K, which run to their end, share waves)
     const uint32_t run1 = two_pass ? C1 : 32u * 0x7FEu;
-    const uint32_t *list1 = nullptr;
+    const uint32_t *list1 = d_order;
     if (ctx->tune.verify_len_order && minlen < std::min(run1, mtext)) {
         hipLaunchKernelGGL(k_len_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
-                           ctx->stream, A, B, d_pairs, count, d_count, run1 >> 5, lkey, lval);
+                           ctx->stream, A, B, d_pairs, count, d_count, d_order, run1 >> 5, lkey,
+                           lval);
         EJ_CHECK_LAUNCH();
         radix_sort_u32(ctx, lkey, lval, lkey2, list, 1, (uint32_t)count, 11, 11);
         list1 = list;
