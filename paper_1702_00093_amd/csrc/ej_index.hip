@@ -270,15 +270,16 @@ uint64_t estimate(const ej_index *ix, uint64_t qbytes, uint32_t nq) {
 uint64_t probe_bytes(uint64_t raw) { return raw * (8 + 8 + 8 + 4 + 4 + 8 + 4); }
 
 // Bytes of verification and output once the de-duplicated count is known:
-// distances, the queries' match masks, the two-pass form's saved state and
-// pass-2 ordering buffers (NL band words per pair), output flags and
-// positions, result ids and distances.
+// distances, the queries' match masks, the two-pass form's saved state (Pv
+// and Mv of NL band words per pair, rounded up to whole lanes of up to 4
+// words) and its ordering buffers, output flags and positions, result ids
+// and distances.
 uint64_t verify_bytes(const ej_ctx *ctx, uint64_t cnt, uint64_t qbytes, uint32_t nq,
                       uint32_t sigma, uint32_t Kmax) {
     const uint64_t NL = verify_lanes_for(Kmax);
     uint64_t b = cnt * 4;                                           // distances
     b += mask_words_bound(qbytes, nq, sigma) * 4 + 24ull * (nq + 1);  // query masks
-    if (ctx->tune.verify_mode == 0) b += cnt * (8 * NL + 4 * 8 + 8);  // two-pass state
+    if (ctx->tune.verify_mode == 0) b += cnt * (8 * (NL + 3) + 4 * 8 + 8);  // two-pass state
     b += cnt * (4 + 4 + 4 + 4);                                     // output
     return b;
 }
