@@ -457,7 +457,7 @@ def test_knobs_do_not_change_results(ej, ctx, oracle_lib):
              ("embed_lds_budget", 8192), ("verify_lds_budget", 4096),
              ("verify_blocks_per_cu", 1), ("verify_pass1_cols", 64), ("verify_ring", 0),
              ("verify_ring", 2), ("verify_mode", 1), ("verify_wpl", 1),
-             ("verify_wpl", 4), ("verify_len_order", 0)]
+             ("verify_wpl", 4), ("verify_len_order", 0), ("verify_order", 0)]
     # the persistent forms with and without the multiplicity order
     try:
         for mode, split in ((1, 0), (2, 0), (2, 1), (2, 4)):
