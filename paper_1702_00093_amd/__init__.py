@@ -222,7 +222,7 @@ class JoinResult:
     ms_verify_kernel: float = 0.0
     verify_launches: int = 0
     verify_form: int = 0       # 0 two-pass, 1 persistent groups, 2 one pair per lane, 3 split,
-    #                            4 grouped by pattern
+    #                            4 grouped by pattern, 5 two-pass with 2 or 4 words per lane
     pairs_device: object = None
     dist_device: object = None
     graph: int = 0             # 0 host-sized, 1 device-sized uncaptured, 2 graph replay
