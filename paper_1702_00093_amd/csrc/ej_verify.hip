@@ -2234,10 +2234,15 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         aux = ws<uint32_t>(ctx, "verify_aux", count);
     }
     const uint64_t cap = (uint64_t)ctx->num_cu * ctx->tune.verify_blocks_per_cu;
-    uint32_t *lkey = ws<uint32_t>(ctx, "verify_lkey", count);
-    uint32_t *lkey2 = ws<uint32_t>(ctx, "verify_lkey2", count);
-    uint32_t *lval = ws<uint32_t>(ctx, "verify_lval", count);
-    uint32_t *list = ws<uint32_t>(ctx, "verify_list", count);
+    // sort buffers of the passes' orders, taken when a sort runs
+    uint32_t *lkey = nullptr, *lkey2 = nullptr, *lval = nullptr, *list = nullptr;
+    auto sort_buffers = [&] {
+        if (list) return;
+        lkey = ws<uint32_t>(ctx, "verify_lkey", count);
+        lkey2 = ws<uint32_t>(ctx, "verify_lkey2", count);
+        lval = ws<uint32_t>(ctx, "verify_lval", count);
+        list = ws<uint32_t>(ctx, "verify_list", count);
+    };
     // the first pass in order of text length, longest first and clamped at
     // the columns it runs, so that a wave's pairs end about together (a wave
     // runs until its last pair is decided); skipped when every text outlasts
@@ -2247,6 +2252,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
     const uint32_t run1 = two_pass ? C1 : 32u * 0x7FEu;
     const uint32_t *list1 = d_order;
     if (ctx->tune.verify_len_order && minlen < std::min(run1, mtext)) {
+        sort_buffers();
         hipLaunchKernelGGL(k_len_keys, dim3(grid_for(ctx, count, 256)), dim3(256), 0,
                            ctx->stream, A, B, d_pairs, count, d_count, d_order, run1 >> 5, lkey,
                            lval);
@@ -2266,6 +2272,7 @@ void verify(ej_ctx *ctx, const uint8_t *d_codes, const uint64_t *d_offsets, uint
         kmark();
     }
     if (!two_pass) return;
+    sort_buffers();
     uint32_t *flags = ws<uint32_t>(ctx, "verify_flags", count);
     uint32_t *pos = ws<uint32_t>(ctx, "verify_pos", count);
     uint64_t *d_nalive = ws<uint64_t>(ctx, "verify_nalive", 1);
