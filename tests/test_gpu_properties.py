@@ -1,0 +1,107 @@
+"""GPU parity on generated inputs (hypothesis, derandomized so that every run
+draws the same examples): small sets of near-copies over DNA or a 20-letter
+alphabet, empty strings included, joined and verified through the C ABI and
+compared with the oracle bit for bit.  The fixed cases in test_gpu_parity.py
+cover sizes and layouts; these cover shapes nobody wrote down."""
+import sys
+import types
+
+import numpy as np
+import pytest
+from hypothesis import HealthCheck, given, settings
+from hypothesis import strategies as st
+
+from tests._gpu_util import pairs_to_codes, to_device
+
+pytestmark = pytest.mark.gpu
+
+cases = settings(max_examples=100, deadline=None, derandomize=True,
+                 suppress_health_check=[HealthCheck.too_slow])
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ej():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1702_00093_amd as ej
+    ej.lib()  # raises if the library is not built
+    return ej
+
+
+@pytest.fixture(scope="module")
+def ctx(ej):
+    return ej.Context(0)
+
+
+@st.composite
+def families(draw, max_len=60):
+    """Random base strings with copies carrying a few edits, plus empty
+    strings now and then."""
+    letters = draw(st.sampled_from(["ACGT", "ACDEFGHIKLMNPQRSTVWY"]))
+    bases = draw(st.lists(st.text(alphabet=letters, min_size=1, max_size=max_len), min_size=1,
+                          max_size=5))
+    out = []
+    for b in bases:
+        for _ in range(draw(st.integers(1, 4))):
+            s = list(b)
+            for _ in range(draw(st.integers(0, 4))):
+                i = draw(st.integers(0, max(0, len(s) - 1)))
+                op = draw(st.sampled_from("isd"))
+                c = draw(st.sampled_from(letters))
+                if op == "i":
+                    s.insert(i, c)
+                elif op == "s" and s:
+                    s[i] = c
+                elif s:
+                    del s[i]
+            out.append("".join(s).encode())
+    out += [b""] * draw(st.integers(0, 2))
+    order = draw(st.permutations(range(len(out))))
+    return [out[i] for i in order]
+
+
+def _set(strings):
+    chars = np.frombuffer(b"".join(strings), dtype=np.uint8).copy()
+    off = np.zeros(len(strings) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(s) for s in strings])
+    return types.SimpleNamespace(chars=chars, offsets=off)
+
+
+@cases
+@given(families(), st.integers(0, 12), st.integers(1, 6), st.integers(1, 6), st.integers(1, 6),
+       st.integers(0, 2**31))
+def test_join_equals_the_oracle(ej, ctx, oracle_lib, strings, K, r, z, m, seed):
+    col = _set(strings)
+    _say(f"join n={len(strings)} K={K} r={r} z={z} m={m} seed={seed}")
+    ref = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed)
+    res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=seed)
+    assert pairs_to_codes(res.pairs).tolist() == ref.out.tolist()
+    assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
+    assert res.n_candidates == len(ref.cand)
+
+
+@cases
+@given(families(max_len=300), st.integers(0, 400), st.randoms(use_true_random=False))
+def test_verify_equals_the_oracle_in_every_form(ej, ctx, oracle_lib, strings, K, rnd):
+    import torch
+    col = _set(strings)
+    n = len(strings)
+    pairs = [(rnd.randrange(n), rnd.randrange(n)) for _ in range(rnd.randrange(1, 40))]
+    codes = np.array([(a << 32) | b for a, b in pairs], dtype=np.uint64)
+    want = oracle_lib.verify_pairs(col.chars, col.offsets, codes, K).tolist()
+    chars, offs = to_device(col)
+    d_codes = torch.from_numpy(codes.astype(np.int64)).cuda()
+    old = ctx.tune_get("verify_mode")
+    try:
+        for mode in (0, 1, 2, 3):
+            ctx.tune_set("verify_mode", mode)
+            _say(f"verify n={n} pairs={len(pairs)} K={K} mode={mode}")
+            got = ctx.verify(chars, offs, d_codes, K)
+            assert got.cpu().numpy().astype(np.uint32).tolist() == want
+    finally:
+        ctx.tune_set("verify_mode", old)
