@@ -105,3 +105,42 @@ def test_verify_equals_the_oracle_in_every_form(ej, ctx, oracle_lib, strings, K,
             assert got.cpu().numpy().astype(np.uint32).tolist() == want
     finally:
         ctx.tune_set("verify_mode", old)
+
+
+def _assert_same_join(res, ref, shape=True):
+    """Output, distances, candidate and raw counts; L and the alphabet size
+    too, except for the grouped join (each group takes its own)."""
+    assert pairs_to_codes(res.pairs).tolist() == ref.out.tolist()
+    assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
+    assert res.n_candidates == len(ref.cand)
+    assert res.n_raw == ref.n_raw
+    if shape:
+        assert (res.L, res.sigma) == (ref.L, ref.sigma)
+
+
+@cases
+@given(families(), st.integers(1, 12), st.integers(0, 12), st.integers(0, 3), st.integers(1, 5),
+       st.integers(1, 5), st.integers(1, 6), st.integers(0, 2**31))
+def test_plus_equals_the_oracle(ej, ctx, oracle_lib, strings, K, delta, T, r, z, m, seed):
+    col = _set(strings)
+    delta = min(delta, K)
+    # delta = 0 asks the library for the paper's step, floor(sqrt(ceil(average
+    # length))) and at least 1; the oracle takes the step itself
+    n = len(strings)
+    avg = -(-int(col.offsets[-1]) // n)
+    step = delta if delta else max(1, int(np.floor(np.sqrt(avg))))
+    _say(f"plus n={n} K={K} delta={delta} (step {step}) T={T} r={r} z={z} m={m} seed={seed}")
+    ref = oracle_lib.join_plus(col.chars, col.offsets, K, r, z, m, delta=step, T=T, seed=seed)
+    res = ctx.join_plus(col.chars, col.offsets, K, r, z, m, delta=delta, T=T, seed=seed)
+    _assert_same_join(res, ref)
+
+
+@cases
+@given(families(), st.integers(1, 12), st.integers(1, 5), st.integers(1, 5), st.integers(1, 6),
+       st.integers(0, 2**31))
+def test_grouped_equals_the_oracle(ej, ctx, oracle_lib, strings, K, r, z, m, seed):
+    col = _set(strings)
+    _say(f"grouped n={len(strings)} K={K} r={r} z={z} m={m} seed={seed}")
+    ref = oracle_lib.join_grouped(col.chars, col.offsets, K, r, z, m, seed=seed)
+    res = ctx.join_grouped(col.chars, col.offsets, K, r, z, m, seed=seed)
+    _assert_same_join(res, ref, shape=False)
