@@ -144,3 +144,47 @@ def test_grouped_equals_the_oracle(ej, ctx, oracle_lib, strings, K, r, z, m, see
     ref = oracle_lib.join_grouped(col.chars, col.offsets, K, r, z, m, seed=seed)
     res = ctx.join_grouped(col.chars, col.offsets, K, r, z, m, seed=seed)
     _assert_same_join(res, ref, shape=False)
+
+
+@cases
+@given(families(), st.integers(0, 12), st.integers(1, 5), st.integers(1, 5), st.integers(1, 6),
+       st.integers(0, 70), st.integers(0, 2**31))
+def test_short_pass_equals_the_oracle(ej, ctx, oracle_lib, strings, K, r, z, m, S, seed):
+    col = _set(strings)
+    _say(f"short pass n={len(strings)} K={K} S={S} r={r} z={z} m={m} seed={seed}")
+    ref = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, exact_len=S)
+    res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=seed, exact_len=S)
+    assert pairs_to_codes(res.pairs).tolist() == ref.out.tolist()
+    assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
+
+
+@cases
+@given(families(), st.integers(1, 4), st.integers(1, 4), st.integers(1, 5),
+       st.integers(8, 64), st.integers(0, 2**31), st.randoms(use_true_random=False))
+def test_queries_equal_the_oracle(ej, ctx, oracle_lib, strings, r, z, m, L, seed, rnd):
+    col = _set(strings)
+    letters = sorted(set(b"".join(strings))) or [ord("A")]
+    queries = []
+    for _ in range(rnd.randrange(1, 12)):
+        s = bytearray(strings[rnd.randrange(len(strings))])
+        for _ in range(rnd.randrange(0, 4)):
+            i = rnd.randrange(len(s) + 1)
+            c = letters[rnd.randrange(len(letters))]
+            if rnd.random() < 0.5 or not s:
+                s.insert(i, c)
+            else:
+                s[min(i, len(s) - 1)] = c
+        queries.append(bytes(s))
+    q = _set(queries)
+    Kq = np.array([rnd.randrange(0, 13) for _ in queries], dtype=np.uint32)
+    _say(f"queries n={len(strings)} nq={len(queries)} r={r} z={z} m={m} L={L} seed={seed}")
+    ref_off, ref_ids, ref_dist = oracle_lib.query(col.chars, col.offsets, q.chars, q.offsets,
+                                                  Kq, r, z, m, seed=seed, L=L)
+    ix = ej.Index(ctx, col.chars, col.offsets, r, z, m, seed=seed, L=L)
+    try:
+        res = ix.query(q.chars, q.offsets, Kq)
+        assert res.offsets.astype(np.uint64).tolist() == ref_off.tolist()
+        assert res.ids.astype(np.uint32).tolist() == ref_ids.tolist()
+        assert res.dist.astype(np.int64).tolist() == ref_dist.astype(np.int64).tolist()
+    finally:
+        ix.close()
