@@ -188,3 +188,24 @@ def test_queries_equal_the_oracle(ej, ctx, oracle_lib, strings, r, z, m, L, seed
         assert res.dist.astype(np.int64).tolist() == ref_dist.astype(np.int64).tolist()
     finally:
         ix.close()
+
+
+@settings(max_examples=40, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(st.integers(0, 2**31), st.integers(5, 60), st.integers(1, 5), st.integers(40, 400),
+       st.integers(0, 800), st.floats(0.0, 0.1), st.integers(0, 150), st.integers(1, 8),
+       st.integers(1, 8), st.integers(1, 10), st.sampled_from([0, 32, 64, 128]))
+def test_larger_joins_equal_the_oracle(ej, ctx, oracle_lib, seed, n_bases, copies, lo, span,
+                                       rate, K, r, z, m, L):
+    """Sets of up to 300 strings of up to 1,200 letters: many tiles, ragged
+    tails, bands of 1 to 5 words, truncated and untruncated walks."""
+    import synthdata as sd
+    col = sd.clusters(seed, n_bases, lambda rr, b: rr.integers(1, copies + 1),
+                      lambda rr: rr.integers(lo, lo + span + 1),
+                      lambda rr, LL: rr.poisson(rate * LL))
+    _say(f"larger join n={col.n} K={K} r={r} z={z} m={m} L={L} seed={seed}")
+    ref = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
+    res = ctx.join(col.chars, col.offsets, K, r, z, m, seed=seed, L=L)
+    assert pairs_to_codes(res.pairs).tolist() == ref.out.tolist()
+    assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
+    assert res.n_candidates == len(ref.cand)
