@@ -209,3 +209,33 @@ def test_larger_joins_equal_the_oracle(ej, ctx, oracle_lib, seed, n_bases, copie
     assert pairs_to_codes(res.pairs).tolist() == ref.out.tolist()
     assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
     assert res.n_candidates == len(ref.cand)
+
+
+_graph_states = []
+
+
+@settings(max_examples=30, deadline=None, derandomize=True,
+          suppress_health_check=[HealthCheck.too_slow])
+@given(families(), st.integers(0, 12), st.integers(1, 5), st.integers(1, 5), st.integers(1, 6),
+       st.integers(0, 2**31))
+def test_graph_joins_equal_the_oracle(ej, ctx, oracle_lib, strings, K, r, z, m, seed):
+    """Device-resident input with EJ_FLAG_GRAPH: the host-sized join, the
+    device-sized one and the captured graph's replay all give the oracle's
+    result."""
+    col = _set(strings)
+    chars, offs = to_device(col)
+    _say(f"graph join n={len(strings)} K={K} r={r} z={z} m={m} seed={seed}")
+    ref = oracle_lib.join(col.chars, col.offsets, K, r, z, m, seed=seed)
+    for _ in range(3):
+        res = ctx.join(chars, offs, K, r, z, m, seed=seed, flags=ej.FLAG_GRAPH)
+        assert pairs_to_codes(res.pairs).tolist() == ref.out.tolist()
+        assert res.dist.tolist() == ref.out_dist.astype(np.int32).tolist()
+        assert res.n_candidates == len(ref.cand)
+        _graph_states.append(res.graph)
+
+
+def test_graph_joins_were_replayed():
+    """The generated graph joins above reached the replayed graph."""
+    if not _graph_states:
+        pytest.skip("the generated graph joins did not run")
+    assert 2 in _graph_states
