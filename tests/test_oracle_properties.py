@@ -7,7 +7,9 @@ CGK walks on strings that share a prefix, driven by the same random bits,
 emit the same symbols while both are inside it (Algorithm 1: the walk's
 index advances by at most one per step), and emit only padding once past
 the end; the sampled key depends on the sampled positions only; the join's
-output is exactly its candidates within K, with their exact distances."""
+(and EmbedJoin+'s) output is exactly its candidates within K, with their
+exact distances; a serving query returns true matches in index order and
+always finds an identical member."""
 import numpy as np
 from hypothesis import HealthCheck, given, settings
 from hypothesis import strategies as st
@@ -200,3 +202,36 @@ def test_grouped_join_output_is_exact(oracle_lib, strings, K, seed):
     truth = dict(zip(truth_codes.tolist(), truth_d.tolist()))
     for c, d in zip(res.out.tolist(), res.out_dist.tolist()):
         assert truth.get(c) == d
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(families(), st.integers(1, 6), st.integers(1, 6), st.integers(1, 3), st.integers(0, 2**31))
+def test_plus_output_is_exact(oracle_lib, strings, K, delta, T, seed):
+    chars, off = _set(strings)
+    res = oracle_lib.join_plus(chars, off, K, 3, 3, 2, delta=min(delta, K), T=T, seed=seed)
+    truth_codes, truth_d = oracle_lib.brute_join(chars, off, K, full=True)
+    truth = dict(zip(truth_codes.tolist(), truth_d.tolist()))
+    cand = set(res.cand.tolist())
+    out = dict(zip(res.out.tolist(), res.out_dist.tolist()))
+    assert set(out) == cand & set(truth)
+    assert all(out[c] == truth[c] for c in out)
+
+
+@settings(max_examples=30, deadline=None, suppress_health_check=[HealthCheck.too_slow])
+@given(families(), st.lists(st.integers(0, 8), min_size=1, max_size=6), st.integers(0, 2**31))
+def test_query_results_are_true_matches(oracle_lib, strings, kq, seed):
+    """Each query's results are index strings within its threshold, with
+    their exact distances, in increasing index order; a query equal to an
+    index member finds that member at distance 0."""
+    chars, off = _set(strings)
+    queries = [strings[i % len(strings)] for i in range(len(kq))]
+    qc, qo = _set(queries)
+    Kq = np.array(kq, dtype=np.uint32)
+    ro, ids, dist = oracle_lib.query(chars, off, qc, qo, Kq, 4, 4, 2, seed=seed, L=32)
+    for q in range(len(queries)):
+        got = list(zip(ids[ro[q]:ro[q + 1]].tolist(), dist[ro[q]:ro[q + 1]].tolist()))
+        assert [i for i, _ in got] == sorted(i for i, _ in got)
+        for i, d in got:
+            assert d == oracle_lib.ed_full(queries[q], strings[i]) <= Kq[q]
+        assert (q % len(strings), 0) in got or any(
+            strings[i] == queries[q] and d == 0 for i, d in got)
