@@ -129,8 +129,8 @@ typedef struct {
     /* The verification form that ran: 0 two passes over groups of pairs,
      * 1 persistent groups of pairs, 2 one pair per lane, 3 several lanes per
      * pair with several band words each (2 and 3: "verify_mode" 2), 4 grouped
-     * by pattern ("verify_mode" 3), 5 the two-pass form with two band words
-     * per lane ("verify_wpl" 2 or 4). */
+     * by pattern ("verify_mode" 3), 5 the two-pass form with two or four
+     * band words per lane ("verify_wpl" 2 or 4). */
     uint32_t verify_form;
     /* 1 when pairs and dist are device pointers (EJ_FLAG_DEVICE_OUT) */
     uint32_t on_device;

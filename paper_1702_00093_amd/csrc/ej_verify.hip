@@ -137,7 +137,7 @@ __host__ __device__ inline uint32_t tile_words_for(uint32_t sigma, uint32_t stri
 // symbol s of tw selects the symbol's bit array; the lane's two words at
 // `slot` are funnel-shifted by s), which keeps the live registers low.
 // Addresses are LDS byte offsets: symbol c's words start at c * stride4
-// (a 24-bit multiply-add, full rate) and the lane's word at slot4.
+// (a 24-bit multiply of the symbol byte) and the lane's word at slot4.
 template <int MODE, bool FAST>
 __device__ inline void myers_block(const uint8_t *peq, uint32_t stride4, uint32_t slot4,
                                    const uint32_t tw[8], uint32_t &Pv, uint32_t &Mv, uint32_t &Z,
